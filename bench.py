@@ -1,0 +1,184 @@
+"""Benchmark: PNOF7 energy + gradient iterations per second on one MI355X.
+
+One step is the whole hot path on one batch of synthetic input:
+  occupation map gamma -> n, Lagrangian (J, K, energy, Fock vectors, lambda, dE/dC, dE/dn,
+  max asymmetry), ON-map adjoint dE/dgamma, and the orbital step (symmetrised lambda,
+  float64 eigensolver, C_new = C U).
+Default workload: N_bf = 1200, N_aux = 4800 (B in bfloat16, 13.8 GB, generated on the device),
+100 pairs, 11 weak orbitals per pair (1200 active orbitals), bf16-split contractions.
+
+Prints one JSON line (see the repository's measurement notes for the fields).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"bf16": 2.5e15, "f64": 78.6e12}
+GOLDEN_C5 = os.path.join(ROOT, "tests", "golden", "c5_df1200_expected.json")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c5_df1200")
+    ap.add_argument("--precision", default="bf16split", choices=["bf16split", "fp64", "bf16"])
+    ap.add_argument("--fp64-steps", type=int, default=1, help="steps of the float64 path for the speedup (0: skip)")
+    ap.add_argument("--cpu-rows", type=int, default=192, help="rows of B in the oracle's timed sample (0: skip)")
+    ap.add_argument("--pchunk", type=int, default=0)
+    return ap.parse_args()
+
+
+def stage_flops(wl, stage):
+    """Algorithmic flops of one full pass of a contraction stage (one product per contraction)."""
+    nb, na, nx = wl.nbf, wl.nact, wl.naux
+    return {"X": 2.0 * nx * nb * nb * na, "b": 2.0 * nx * na * nb * na, "Y": 2.0 * nx * nb * na * na}[stage]
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported in this build "
+              "(the aux-index sharding across GPUs is a design note, not code).", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2004_06142_amd as P
+    import synth
+    import synth.device as sdev
+
+    dev = torch.device("cuda", 0)
+    wl = synth.WORKLOADS[args.workload]
+    inst = synth.workload(args.workload, with_b=False)
+    prec = {"bf16split": P.BF16_SPLIT, "fp64": P.FP64, "bf16": P.BF16}[args.precision]
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    C0, H, gamma = t(inst.C), t(inst.H), t(inst.gamma)
+    bdt = torch.bfloat16 if wl.b_dtype == "bf16" else torch.float64
+    B = sdev.make_b(inst.key, wl.nbf, wl.naux, dtype=bdt, device=dev)
+    kind = P.INTS_DF_BF16 if wl.b_dtype == "bf16" else P.INTS_DF_F64
+    ctx = P.Context(0)
+    if args.pchunk:
+        ctx.set_pchunk(args.pchunk)
+
+    def step(prob, C):
+        out = P.energy_and_grad(ctx, prob, C, gamma, H, B)
+        Cn, eps = ctx.orbital_step(out["lam"], C)
+        return out, Cn
+
+    def run(prob, warmup, steps, profile):
+        ctx.reserve(prob)
+        out = None
+        for _ in range(warmup):
+            out, _ = step(prob, C0)
+        torch.cuda.synchronize()
+        if profile:
+            ctx.profile_begin()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            out, _ = step(prob, C0)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = ctx.profile_end() if profile else None
+        return out, dt, prof
+
+    prob = P.problem(wl.nbf, wl.naux, wl.npairs, wl.ncwo, P.PNOF7, prec, kind)
+    print(f"[bench] workload {wl.name}: warmup {args.warmup}, timing {args.steps} steps", file=sys.stderr, flush=True)
+    out, dt, prof = run(prob, args.warmup, args.steps, True)
+    ms = 1e3 * dt / args.steps
+    E = out["E"].item()
+    print(f"[bench] {ms:.1f} ms/step, E = {E:.10f}, stages {prof}", file=sys.stderr, flush=True)
+
+    # dominant contraction kernel and its roofline
+    dtype_key = "f64" if prec == P.FP64 else "bf16"
+    stage = max(("X", "b", "Y"), key=lambda s: prof[s][0])
+    st_ms, st_n = prof[stage]
+    flops = stage_flops(wl, stage) * args.steps
+    achieved = flops / (st_ms * 1e-3)
+    terms = {"X": 2, "b": 3, "Y": 3}[stage] if prec == P.BF16_SPLIT else 1
+    roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[dtype_key] / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / PEAK[dtype_key], "traffic": None,
+                "kernel": {"X": "gemm1_kernel", "b": "gemm2_kernel", "Y": "gemm3_kernel"}[stage],
+                "avg_launch_ms": st_ms / st_n, "launches": st_n,
+                "issued_frac": achieved * terms / PEAK[dtype_key]}
+    stages = {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[1] / args.steps} for k, v in prof.items()}
+
+    result = {
+        "metric": "PNOF7 energy+grad iterations/sec", "value": args.steps / dt, "unit": "iters/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {"bf16split": "bf16x3+f32acc+f64", "fp64": "f64", "bf16": "bf16+f32acc"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": wl.name, "nbf": wl.nbf, "naux": wl.naux, "npairs": wl.npairs, "ncwo": wl.ncwo,
+                   "nact": wl.nact, "functional": "PNOF7", "B": wl.b_dtype, "seed": synth.seed_of(wl.name)},
+        "energy_Ha": E, "stages": stages, "roofline": roofline,
+    }
+    if os.path.exists(GOLDEN_C5) and wl.name == "c5_df1200":
+        ref = json.load(open(GOLDEN_C5))
+        result["abs_err_Ha_vs_oracle"] = abs(E - ref["E"])
+
+    if args.fp64_steps > 0 and prec != P.FP64:
+        p64 = P.problem(wl.nbf, wl.naux, wl.npairs, wl.ncwo, P.PNOF7, P.FP64, kind)
+        print("[bench] float64 path for the speedup", file=sys.stderr, flush=True)
+        o64, dt64, prof64 = run(p64, 0, args.fp64_steps, True)
+        result["fp64_path"] = {"ms_per_step": 1e3 * dt64 / args.fp64_steps, "energy_Ha": o64["E"].item(),
+                               "speedup_of_mixed": (dt64 / args.fp64_steps) / (dt / args.steps),
+                               "abs_dE_mixed_vs_fp64": abs(E - o64["E"].item()),
+                               "stages_ms": {k: v[0] / args.fp64_steps for k, v in prof64.items()}}
+    del B
+    torch.cuda.empty_cache()
+
+    if args.cpu_rows > 0:
+        result["cpu_baseline"] = cpu_baseline(wl, inst, args.cpu_rows)
+    print(json.dumps(result), flush=True)
+
+
+def cpu_baseline(wl, inst, rows):
+    """The FP64 oracle (streamed route) timed on a bounded sample of the same workload."""
+    import numpy as np
+    import torch
+
+    import synth.device as sdev
+    from oracle import pnof, stream
+
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("internal_api") == "openblas"] or [1])
+    except Exception:
+        cores = os.cpu_count()
+    rows = min(rows, wl.naux)
+    out = torch.empty((rows, wl.nbf, wl.nbf), dtype=torch.bfloat16 if wl.b_dtype == "bf16" else torch.float64,
+                      device="cuda")
+    sdev.fill_b(out, inst.key, wl.nbf, wl.naux, 0)
+    Bs = out.to(torch.float64).cpu().numpy()
+    del out
+    n = pnof.on_sigmoid(inst.gamma, wl.npairs, wl.ncwo)
+    print(f"[bench] cpu oracle on {rows} of {wl.naux} rows of B", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    stream.lagrangian(inst.C, n, inst.H, Bs[:0], wl.npairs, wl.ncwo, pnof.PNOF7, naux=0)
+    t_fixed = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    r = stream.lagrangian(inst.C, n, inst.H, Bs, wl.npairs, wl.ncwo, pnof.PNOF7, naux=rows)
+    t_rows = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    pnof.orbital_step(r["lam"], inst.C)
+    t_orb = time.perf_counter() - t0
+    per_row = max(0.0, t_rows - t_fixed) / rows
+    s_iter = t_fixed + per_row * wl.naux + t_orb
+    return {"value": 1.0 / s_iter, "unit": "iters/s", "cores": cores, "kind": "oracle",
+            "sample": f"streamed FP64 oracle over {rows} of {wl.naux} B rows ({t_rows:.1f} s), per-row cost scaled "
+                      f"to all rows, plus its fixed part ({t_fixed:.1f} s) and orbital step ({t_orb:.1f} s)",
+            "seconds_per_iter_est": s_iter}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,170 @@
+/*
+ * pnof.h -- C ABI of the MI355X (gfx950) PNOF5 / PNOF7 / PNOF7s orbital-optimisation step.
+ *
+ * The operations follow M. Piris and I. Mitxelena, "DoNOF: an open-source implementation of
+ * natural-orbital-functional-based methods for quantum chemistry", arXiv:2004.06142:
+ *   energy          Section 2, Eqs. EPNOF7, Eg, Efg (PNOF5: Phi = 0; PNOF7s: Eq. Efg_s)
+ *   J, K            Section 3.5, Eqs. JKpq and Gpmn (L = K for real orbitals, Section 2)
+ *   Fock vectors    Section 3.2, Eqs. lowdin, Vee-s, Vee-d
+ *   Lagrangian      Section 3.2, Eqs. lag and gval; symmetry criterion of Section 3.4
+ *   orbital step    Section 3.2, Eq. Fockian, aufbau diagonal and zeta scaling; initial step of
+ *                   Section 3.4 (diagonalisation of the symmetrised Lagrangian)
+ *   ON maps         Section 3.1, Eqs. soo, sum1-h, woo (trigonometric), and a sigmoid map
+ *
+ * Conventions shared by every call
+ *   - All array arguments are DEVICE pointers on the context's device, row-major, float64 unless
+ *     stated.  The caller owns every buffer; the library never frees or retains them.
+ *   - C[mu*nbf + p] = C_{mu p}: column p holds orbital p in the (orthonormal, S = I) AO basis.
+ *   - n[p], p < nbf: per-spin occupation numbers; n[p] = 0 for p >= nact = npairs*(ncwo+1).
+ *   - Orbital layout (fixed by npairs, ncwo): the strong orbital of pair g is orbital g; the ncwo
+ *     weak orbitals of pair g are npairs + ncwo*(npairs-1-g) + k, k = 0..ncwo-1 (consecutive
+ *     blocks in reverse pair order, the coupling of the water tables of Section 5).
+ *   - H: nbf x nbf symmetric one-electron matrix.
+ *   - Two-electron integrals, by pnof_problem.ints:
+ *       PNOF_INTS_ERI4_F64  ERI[((m*nbf + n)*nbf + l)*nbf + s] = (mn|ls), float64, nbf <= 64;
+ *       PNOF_INTS_DF_F64    B[(P*nbf + m)*nbf + n], float64, (mn|ls) = sum_P B_Pmn B_Pls;
+ *       PNOF_INTS_DF_BF16   the same B stored as bfloat16 (the stored values are exact inputs).
+ *     B_P must be symmetric in (m, n).
+ *   - Calls are asynchronous on the context's HIP stream; outputs are valid after that stream is
+ *     synchronised.  Scalar outputs (E, max_asym) are device scalars.
+ *   - Errors: arguments, shapes and enums are validated on the host before anything is enqueued;
+ *     on error nothing is launched and the call returns a status; pnof_last_error() gives the text.
+ *     A failed launch or an earlier asynchronous device error is returned as PNOF_E_DEVICE.
+ *     Nothing throws across the ABI.
+ *   - Workspace: device scratch comes from pnof_set_workspace (caller-owned, e.g. a torch tensor)
+ *     when one of sufficient size has been set; otherwise the context allocates and keeps its own
+ *     (grow-only, freed by pnof_destroy).
+ *   - One context per host thread and stream; calls on one context must not overlap.
+ */
+#ifndef PNOF_H
+#define PNOF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PNOF_ABI_VERSION 1
+
+typedef struct pnof_ctx_s* pnof_ctx;
+
+typedef enum {
+  PNOF_OK = 0,
+  PNOF_E_ARG = 1,          /* NULL pointer, bad context, bad scalar argument          */
+  PNOF_E_SHAPE = 2,        /* inconsistent sizes                                        */
+  PNOF_E_DTYPE = 3,        /* precision / integral kind combination not allowed        */
+  PNOF_E_NOMEM = 4,        /* workspace allocation failed                               */
+  PNOF_E_DEVICE = 5,       /* HIP launch or runtime error (possibly from an earlier call) */
+  PNOF_E_NONFINITE = 6,    /* PNOF_CHECK_FINITE found a NaN / Inf in an input           */
+  PNOF_E_UNSUPPORTED = 7,  /* valid request that this build does not implement         */
+  PNOF_E_EIG = 8           /* the eigensolver did not converge                          */
+} pnof_status;
+
+typedef enum { PNOF5 = 5, PNOF7 = 7, PNOF7S = 8 } pnof_functional;
+
+/* Arithmetic of the three-index contractions (X = B C, b = C^T X, Y = sum_P X W):
+ *   PNOF_FP64        float64 matrix cores;
+ *   PNOF_BF16        one bfloat16 pass per contraction, float32 accumulation (error study only);
+ *   PNOF_BF16_SPLIT  C, X and W carried as bfloat16 hi + lo pairs (2, 3 and 3 products),
+ *                    float32 accumulation, float64 sums over P, and the energy corrected to first
+ *                    order with 4 <Y, C_A - (C_hi + C_lo)> in float64.
+ * Energies, lambda, J = D^T D, the eigensolver and all reductions are float64 in every mode. */
+typedef enum { PNOF_FP64 = 0, PNOF_BF16 = 2, PNOF_BF16_SPLIT = 3 } pnof_precision;
+
+typedef enum { PNOF_INTS_ERI4_F64 = 0, PNOF_INTS_DF_F64 = 1, PNOF_INTS_DF_BF16 = 2 } pnof_ints;
+
+enum { PNOF_CHECK_FINITE = 1 };
+
+typedef struct {
+  int32_t nbf;         /* AO basis size N_B                                   */
+  int32_t naux;        /* density-fitting rank (0 for PNOF_INTS_ERI4_F64)     */
+  int32_t npairs;      /* electron pairs N_II/2 (singlet: N_I = 0)            */
+  int32_t ncwo;        /* weak orbitals per pair N_g (>= 1)                   */
+  int32_t functional;  /* pnof_functional                                     */
+  int32_t precision;   /* pnof_precision                                      */
+  int32_t ints;        /* pnof_ints                                           */
+  int32_t flags;       /* PNOF_CHECK_FINITE                                   */
+} pnof_problem;
+
+/* ---- context ---------------------------------------------------------------------------- */
+/* Create a context on HIP device `device` issuing work on `hip_stream` (NULL = null stream). */
+pnof_status pnof_create(pnof_ctx* out, int device, void* hip_stream);
+void pnof_destroy(pnof_ctx ctx);
+pnof_status pnof_set_stream(pnof_ctx ctx, void* hip_stream);
+/* Text of the last error on this context (ctx may be NULL: the last error of this thread). */
+const char* pnof_last_error(pnof_ctx ctx);
+int pnof_abi_version(void);
+
+/* Host-only validation of a problem description (no device access). */
+pnof_status pnof_check_problem(const pnof_problem* prob);
+/* Bytes of device workspace that the DF calls on `prob` use. */
+pnof_status pnof_workspace_size(pnof_ctx ctx, const pnof_problem* prob, size_t* bytes);
+/* Lend `bytes` of device memory at `dev` (256-byte aligned) to the context; NULL detaches. */
+pnof_status pnof_set_workspace(pnof_ctx ctx, void* dev, size_t bytes);
+/* Rows of B processed per pass (0 = automatic).  Results do not depend on it beyond rounding. */
+pnof_status pnof_set_pchunk(pnof_ctx ctx, int32_t pchunk);
+
+/* Measurement: between pnof_profile_begin and pnof_profile_end every launch of the three-index
+ * contraction kernels (and of the eigensolver) is bracketed by HIP events recorded on the context
+ * stream.  pnof_profile_end synchronises the stream and returns, per stage, the summed event time
+ * in milliseconds and the number of launches (arrays of PNOF_NSTAGES entries). */
+enum { PNOF_STAGE_X = 0, PNOF_STAGE_B = 1, PNOF_STAGE_Y = 2, PNOF_STAGE_EIG = 3, PNOF_NSTAGES = 4 };
+pnof_status pnof_profile_begin(pnof_ctx ctx);
+pnof_status pnof_profile_end(pnof_ctx ctx, double* ms, int64_t* launches);
+
+/* ---- occupation numbers (Section 3.1) ------------------------------------------------------- */
+/* kind 0, sigmoid-normalised: n_p = s(gamma_p) / sum_{r in pair(p)} s(gamma_r), ngamma = nact.
+ * kind 1, trigonometric (Eqs. soo, woo): ngamma = npairs*ncwo; gamma[g] is the strong orbital's
+ *   variable of pair g and gamma[npairs + g*(ncwo-1) + i] the i-th weak one.
+ * n: nact outputs.  dn_dgamma: optional nact x ngamma dense Jacobian (NULL to skip). */
+pnof_status pnof_on_map(pnof_ctx ctx, int32_t kind, int32_t npairs, int32_t ncwo,
+                        const double* gamma, double* n, double* dn_dgamma);
+/* Adjoint of the ON map: dEdgamma[r] = sum_p dEdn[p] dn_p/dgamma_r (ngamma outputs). */
+pnof_status pnof_on_map_vjp(pnof_ctx ctx, int32_t kind, int32_t npairs, int32_t ncwo,
+                            const double* gamma, const double* dEdn, double* dEdgamma);
+
+/* ---- NO integrals (Eqs. JKpq, Gpmn) --------------------------------------------------------- */
+/* J, K: nact x nact, J_pq = (pp|qq), K_pq = (pq|pq).
+ * Jq_ao, Kq_ao (optional, both NULL or both set): nq x nbf x nbf per-orbital AO matrices
+ * J^q, K^q for the orbitals q_idx[0..nq) (device int32, each < nact). */
+pnof_status pnof_jk(pnof_ctx ctx, const pnof_problem* prob, const double* C, const void* ints,
+                    double* J, double* K, double* Jq_ao, double* Kq_ao, const int32_t* q_idx,
+                    int32_t nq);
+
+/* ---- energy (Eqs. EPNOF7, Eg, Efg) ---------------------------------------------------------- */
+pnof_status pnof_energy(pnof_ctx ctx, const pnof_problem* prob, const double* C, const double* n,
+                        const double* H, const void* ints, double* E);
+
+/* ---- generalised Fock (Eqs. lowdin, Vee-s, Vee-d) -------------------------------------------- */
+/* Y: nbf x nact, Y[:, q] = F^q c_q with F^q = n_q H + sum_r (alpha_qr J^r + beta_qr K^r) (the
+ * paper's operator divided by 4).  Fq_ao (optional): nq x nbf x nbf matrices F^q, q in q_idx. */
+pnof_status pnof_fock(pnof_ctx ctx, const pnof_problem* prob, const double* C, const double* n,
+                      const double* H, const void* ints, double* Y, double* Fq_ao,
+                      const int32_t* q_idx, int32_t nq);
+
+/* ---- Lagrangian and gradients (Eqs. lag, gval, lowdin) ---------------------------------------- */
+/* lambda: nbf x nbf, lambda_pq = c_p^T F^q c_q for q < nact, 0 for q >= nact.  E: energy.
+ * Optional (NULL to skip): dEdC (nbf x nbf, = 4 F^q c_q, 0 for inactive columns), dEdn (nact),
+ * max_asym (max |lambda_pq - lambda_qp|), J and K (nact x nact). */
+pnof_status pnof_lagrangian(pnof_ctx ctx, const pnof_problem* prob, const double* C,
+                            const double* n, const double* H, const void* ints, double* lambda,
+                            double* E, double* dEdC, double* dEdn, double* max_asym, double* J,
+                            double* K);
+
+/* ---- orbital step (Eq. Fockian; Section 3.4) ------------------------------------------------ */
+/* diag_prev == NULL: S = (lambda + lambda^T)/2.  Otherwise S_pq = lambda_pq - lambda_qp for p < q
+ * (mirrored), S_pp = diag_prev[p], and when zeta > 0 every off-diagonal |S_pq| > zeta is divided
+ * by ten until it is <= zeta.  (eps, U) = eigh(S) in float64, eps ascending, each column of U
+ * signed so that its largest-magnitude entry (lowest index on ties) is positive;
+ * C_new = C U.  lambda, C, C_new: nbf x nbf; eps: nbf; S_out (optional): the matrix diagonalised.
+ * C_new must not alias C or lambda. */
+pnof_status pnof_orbital_step(pnof_ctx ctx, int32_t nbf, const double* lambda, const double* C,
+                              const double* diag_prev, double zeta, double* C_new, double* eps,
+                              double* S_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PNOF_H */

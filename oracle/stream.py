@@ -37,9 +37,9 @@ def jk(C, B, nact: int, naux: int | None = None, pchunk: int = 64):
     D = np.zeros((naux, nact))
     for p0, p1, Bc in _chunks(B, naux, pchunk):
         X = Bc @ CA                                    # (P, nbf, nact)
-        b = np.einsum("mp,Pmq->Ppq", CA, X)
-        K += np.einsum("Ppq,Ppq->pq", b, b)
-        D[p0:p1] = np.einsum("Ppp->Pp", b)
+        b = CA.T @ X                                   # (P, nact, nact)
+        K += (b * b).sum(axis=0)
+        D[p0:p1] = np.diagonal(b, axis1=1, axis2=2)
     return D.T @ D, K, D
 
 
@@ -62,15 +62,16 @@ def lagrangian(C, n, H, B, npairs: int, ncwo: int, functional: int = pnof.PNOF7,
     D = np.zeros((naux, nact))
     for p0, p1, Bc in _chunks(B, naux, pchunk):
         X = Bc @ CA                                    # (P, nbf, nact)
-        b = np.einsum("mp,Pmq->Ppq", CA, X)
-        K += np.einsum("Ppq,Ppq->pq", b, b)
-        Dc = np.einsum("Ppp->Pp", b)
+        b = CA.T @ X                                   # (P, nact, nact)
+        K += (b * b).sum(axis=0)
+        Dc = np.diagonal(b, axis1=1, axis2=2).copy()
         D[p0:p1] = Dc
         d = Dc @ alpha                                 # (P, nact): sum_r alpha_qr D_Pr
         W = b * beta[None, :, :]
         idx = np.arange(nact)
         W[:, idx, idx] += d
-        Y += np.einsum("Pmr,Prq->mq", X, W)
+        for k in range(X.shape[0]):
+            Y += X[k] @ W[k]
     J = D.T @ D
     E = math.fsum(np.concatenate([2.0 * n * Hpp, (alpha * J).ravel(), (beta * K).ravel()]))
     lam = np.zeros((nbf, nbf))

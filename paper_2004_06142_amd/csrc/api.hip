@@ -1,0 +1,667 @@
+// C ABI of libpnof: context, validation, workspace planning and the per-call drivers.
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "pnof.h"
+
+using namespace pnof;
+
+struct pnof_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  rocblas_handle blas = nullptr;
+  std::string err;
+  char* ext_ws = nullptr;
+  size_t ext_bytes = 0;
+  char* own_ws = nullptr;
+  size_t own_bytes = 0;
+  int pchunk = 0;
+  int* host_info = nullptr;  // pinned
+  // measurement: launches of the contraction kernels bracketed by events on the stream
+  bool profiling = false;
+  struct Ev { int stage; hipEvent_t a, b; };
+  std::vector<Ev> evs;
+  std::vector<hipEvent_t> pool;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+pnof_status fail(pnof_ctx ctx, pnof_status st, const std::string& msg) {
+  g_err = msg;
+  if (ctx) ctx->err = msg;
+  return st;
+}
+
+#define DEV_CHECK(ctx, expr)                                                                  \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      return fail(ctx, PNOF_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+// Bump allocator over a workspace region; with base == nullptr it only measures.
+struct Arena {
+  char* base;
+  size_t off = 0;
+  explicit Arena(char* b) : base(b) {}
+  template <typename T>
+  T* take(long long count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += sizeof(T) * (size_t)(count > 0 ? count : 0);
+    return p;
+  }
+};
+
+hipEvent_t pool_event(pnof_ctx ctx) {
+  if (!ctx->pool.empty()) {
+    hipEvent_t e = ctx->pool.back();
+    ctx->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one launch with events when the context is profiling.
+struct StageTimer {
+  pnof_ctx ctx;
+  int stage;
+  hipEvent_t a = nullptr;
+  StageTimer(pnof_ctx c, int st) : ctx(c), stage(st) {
+    if (ctx->profiling && (a = pool_event(ctx))) hipEventRecord(a, ctx->stream);
+  }
+  ~StageTimer() {
+    if (!a) return;
+    hipEvent_t b = pool_event(ctx);
+    if (!b) return;
+    hipEventRecord(b, ctx->stream);
+    ctx->evs.push_back({stage, a, b});
+  }
+};
+#define TIMED(ctx, stage, expr) [&]() { StageTimer t_(ctx, stage); return (expr); }()
+
+bool is_df(int ints) { return ints == PNOF_INTS_DF_F64 || ints == PNOF_INTS_DF_BF16; }
+
+pnof_status check_problem(pnof_ctx ctx, const pnof_problem* p) {
+  if (!p) return fail(ctx, PNOF_E_ARG, "problem is NULL");
+  if (p->nbf <= 0) return fail(ctx, PNOF_E_SHAPE, "nbf must be positive");
+  if (p->npairs <= 0 || p->ncwo <= 0) return fail(ctx, PNOF_E_SHAPE, "npairs and ncwo must be positive");
+  const long long nact = (long long)p->npairs * (p->ncwo + 1);
+  if (nact > p->nbf) return fail(ctx, PNOF_E_SHAPE, "npairs*(ncwo+1) exceeds nbf");
+  if (p->functional != PNOF5 && p->functional != PNOF7 && p->functional != PNOF7S)
+    return fail(ctx, PNOF_E_ARG, "unknown functional");
+  if (p->precision != PNOF_FP64 && p->precision != PNOF_BF16 && p->precision != PNOF_BF16_SPLIT)
+    return fail(ctx, PNOF_E_ARG, "unknown precision");
+  if (p->ints != PNOF_INTS_ERI4_F64 && !is_df(p->ints)) return fail(ctx, PNOF_E_ARG, "unknown integral kind");
+  if (p->flags & ~PNOF_CHECK_FINITE) return fail(ctx, PNOF_E_ARG, "unknown flag bits");
+  if (p->ints == PNOF_INTS_ERI4_F64) {
+    if (p->naux != 0) return fail(ctx, PNOF_E_SHAPE, "naux must be 0 with explicit four-index integrals");
+    if (p->nbf > 64) return fail(ctx, PNOF_E_SHAPE, "explicit four-index integrals need nbf <= 64");
+    if (p->precision != PNOF_FP64) return fail(ctx, PNOF_E_DTYPE, "explicit integrals are float64 only");
+  } else {
+    if (p->naux <= 0) return fail(ctx, PNOF_E_SHAPE, "naux must be positive for density fitting");
+  }
+  if ((long long)p->nbf * p->nbf > (1LL << 31)) return fail(ctx, PNOF_E_SHAPE, "nbf too large");
+  return PNOF_OK;
+}
+
+// ------------------------------------------------------------------------ planning
+struct Plan {
+  int nbf, nact, naux, npairs, ncwo, functional, prec, ints;
+  int pc, ns2, ns3;
+  int ldk, ldx, ldxx, ldw;
+  bool split;   // bf16 family
+  int terms;    // 1 or 3
+};
+
+Plan make_plan(const pnof_problem* p, int pchunk_override) {
+  Plan pl{};
+  pl.nbf = p->nbf;
+  pl.nact = p->npairs * (p->ncwo + 1);
+  pl.naux = p->naux;
+  pl.npairs = p->npairs;
+  pl.ncwo = p->ncwo;
+  pl.functional = p->functional;
+  pl.prec = p->precision;
+  pl.ints = p->ints;
+  pl.split = (p->precision != PNOF_FP64);
+  pl.terms = p->precision == PNOF_BF16_SPLIT ? 3 : 1;
+  const int tile = pl.split ? 128 : 64;
+  pl.ldk = (int)round_up(pl.nbf, 8);
+  pl.ldx = (int)round_up(pl.nbf, 8);
+  pl.ldxx = (int)round_up(pl.nact, 8);
+  pl.ldw = (int)round_up(pl.nact, 8);
+  if (!is_df(p->ints)) { pl.pc = pl.ns2 = pl.ns3 = 1; return pl; }
+  const long long t1 = (long long)cdiv(pl.nact, tile) * cdiv(pl.nbf, tile);
+  long long pc = pchunk_override > 0 ? pchunk_override : std::max(1LL, (2048 + t1 - 1) / t1);
+  // keep the per-chunk buffers modest
+  const long long per_p = pl.split ? (long long)(2 * pl.nact * pl.ldx + 2 * pl.nbf * pl.ldxx + 2 * pl.nact * pl.ldw) * 2 +
+                                         (p->ints == PNOF_INTS_DF_F64 ? 4LL * pl.nbf * pl.nbf : 0)
+                                   : (long long)(pl.nact * pl.ldx + pl.nact * pl.ldw) * 8 +
+                                         (p->ints == PNOF_INTS_DF_BF16 ? 8LL * pl.nbf * pl.nbf : 0);
+  const long long cap = std::max(1LL, (1LL << 30) / std::max(1LL, per_p));
+  if (pchunk_override <= 0) pc = std::min(pc, cap);
+  pc = std::min<long long>(pc, pl.naux);
+  pl.pc = (int)std::max(1LL, pc);
+  const int tt = cdiv(pl.nact, tile);
+  const long long ntri = (long long)tt * (tt + 1) / 2;
+  pl.ns2 = (int)std::min<long long>(pl.pc, std::max(1LL, (1024 + ntri - 1) / ntri));
+  const long long t3 = (long long)cdiv(pl.nbf, tile) * cdiv(pl.nact, tile);
+  pl.ns3 = (int)std::min<long long>(pl.pc, std::max(1LL, (1024 + t3 - 1) / t3));
+  return pl;
+}
+
+struct Bufs {
+  double *alpha, *beta, *HC, *Hpp, *J, *K, *Y2e, *Y, *D, *Kpart, *partials, *E;
+  float* beta32;
+  double* Ct;           // fp64
+  u16 *cth, *ctl;       // split
+  double *XT, *W, *Ypart64, *Bw;   // fp64 chunk
+  u16 *xth, *xtl, *xh, *xl, *wh, *wl, *bh, *bl;  // split chunk
+  float* Ypart32;
+  double *Jr, *Kr;      // explicit integrals
+  int* flag;
+  size_t bytes;
+};
+
+Bufs carve(const Plan& pl, char* base) {
+  Arena a(base);
+  Bufs b{};
+  const long long n2 = (long long)pl.nact * pl.nact;
+  const long long ny = (long long)pl.nbf * pl.nact;
+  b.alpha = a.take<double>(n2);
+  b.beta = a.take<double>(n2);
+  b.beta32 = a.take<float>(n2);
+  b.HC = a.take<double>(ny);
+  b.Hpp = a.take<double>(pl.nact);
+  b.J = a.take<double>(n2);
+  b.K = a.take<double>(n2);
+  b.Y2e = a.take<double>(ny);
+  b.Y = a.take<double>(ny);
+  b.partials = a.take<double>(512);
+  b.E = a.take<double>(4);
+  b.flag = a.take<int>(4);
+  if (is_df(pl.ints)) {
+    b.D = a.take<double>((long long)pl.naux * pl.nact);
+    b.Kpart = a.take<double>((long long)pl.ns2 * n2);
+    if (!pl.split) {
+      b.Ct = a.take<double>((long long)pl.nact * pl.ldk);
+      b.XT = a.take<double>((long long)pl.pc * pl.nact * pl.ldx);
+      b.W = a.take<double>((long long)pl.pc * pl.nact * pl.ldw);
+      b.Ypart64 = a.take<double>((long long)pl.ns3 * ny);
+      if (pl.ints == PNOF_INTS_DF_BF16) b.Bw = a.take<double>((long long)pl.pc * pl.nbf * pl.nbf);
+    } else {
+      b.cth = a.take<u16>((long long)pl.nact * pl.ldk);
+      b.ctl = a.take<u16>((long long)pl.nact * pl.ldk);
+      b.xth = a.take<u16>((long long)pl.pc * pl.nact * pl.ldx);
+      b.xh = a.take<u16>((long long)pl.pc * pl.nbf * pl.ldxx);
+      b.wh = a.take<u16>((long long)pl.pc * pl.nact * pl.ldw);
+      if (pl.terms > 1) {
+        b.xtl = a.take<u16>((long long)pl.pc * pl.nact * pl.ldx);
+        b.xl = a.take<u16>((long long)pl.pc * pl.nbf * pl.ldxx);
+        b.wl = a.take<u16>((long long)pl.pc * pl.nact * pl.ldw);
+      }
+      b.Ypart32 = a.take<float>((long long)pl.ns3 * ny);
+      if (pl.ints == PNOF_INTS_DF_F64) {
+        b.bh = a.take<u16>((long long)pl.pc * pl.nbf * pl.nbf);
+        b.bl = a.take<u16>((long long)pl.pc * pl.nbf * pl.nbf);
+      }
+    }
+  } else {
+    b.Jr = a.take<double>((long long)pl.nact * pl.nbf * pl.nbf);
+    b.Kr = a.take<double>((long long)pl.nact * pl.nbf * pl.nbf);
+  }
+  b.bytes = a.off + 256;
+  return b;
+}
+
+// Workspace: the caller's if large enough, else the context's own (grow-only).
+pnof_status get_ws(pnof_ctx ctx, size_t bytes, char** out) {
+  if (ctx->ext_ws && ctx->ext_bytes >= bytes) { *out = ctx->ext_ws; return PNOF_OK; }
+  if (ctx->own_bytes < bytes) {
+    if (ctx->own_ws) {
+      hipStreamSynchronize(ctx->stream);
+      hipFree(ctx->own_ws);
+      ctx->own_ws = nullptr;
+      ctx->own_bytes = 0;
+    }
+    if (hipMalloc(&ctx->own_ws, bytes) != hipSuccess) {
+      hipGetLastError();
+      return fail(ctx, PNOF_E_NOMEM, "workspace allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    ctx->own_bytes = bytes;
+  }
+  *out = ctx->own_ws;
+  return PNOF_OK;
+}
+
+pnof_status check_ctx(pnof_ctx ctx) {
+  if (!ctx) return fail(nullptr, PNOF_E_ARG, "context is NULL");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return fail(ctx, PNOF_E_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+  e = hipGetLastError();
+  if (e != hipSuccess) return fail(ctx, PNOF_E_DEVICE, std::string("earlier device error: ") + hipGetErrorString(e));
+  return PNOF_OK;
+}
+
+pnof_status check_finite(pnof_ctx ctx, Bufs& b, const void* p, long long n, int is_bf16, const char* what) {
+  DEV_CHECK(ctx, hipMemsetAsync(b.flag, 0, sizeof(int), ctx->stream));
+  DEV_CHECK(ctx, count_nonfinite(ctx->stream, p, n, is_bf16, b.flag));
+  int h = 0;
+  DEV_CHECK(ctx, hipMemcpyAsync(&h, b.flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  DEV_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+  if (h) return fail(ctx, PNOF_E_NONFINITE, std::string("non-finite value in ") + what);
+  return PNOF_OK;
+}
+
+// ------------------------------------------------------------------------ the step driver
+struct Req {
+  double *J = nullptr, *K = nullptr, *Y = nullptr, *E = nullptr, *lam = nullptr, *dEdC = nullptr,
+         *dEdn = nullptr, *asym = nullptr;
+  double *Jq = nullptr, *Kq = nullptr, *Fq = nullptr;
+  const int32_t* q_idx = nullptr;
+  int nq = 0;
+  bool need_y = false;   // Fock vectors (and everything built from them)
+  bool need_e = false;
+};
+
+pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, const double* n,
+                     const double* H, const void* ints, Req& r) {
+  const Plan pl = make_plan(prob, ctx->pchunk);
+  Bufs b = carve(pl, nullptr);
+  char* ws = nullptr;
+  pnof_status st = get_ws(ctx, b.bytes, &ws);
+  if (st != PNOF_OK) return st;
+  b = carve(pl, ws);
+  hipStream_t s = ctx->stream;
+  const int nbf = pl.nbf, nact = pl.nact;
+  const long long n2 = (long long)nact * nact, ny = (long long)nbf * nact;
+
+  if (prob->flags & PNOF_CHECK_FINITE) {
+    const long long nint = is_df(pl.ints) ? (long long)pl.naux * nbf * nbf : (long long)nbf * nbf * nbf * nbf;
+    if ((st = check_finite(ctx, b, C, (long long)nbf * nbf, 0, "C")) != PNOF_OK) return st;
+    if (n && (st = check_finite(ctx, b, n, nact, 0, "n")) != PNOF_OK) return st;
+    if (H && (st = check_finite(ctx, b, H, (long long)nbf * nbf, 0, "H")) != PNOF_OK) return st;
+    if ((st = check_finite(ctx, b, ints, nint, pl.ints == PNOF_INTS_DF_BF16, "integrals")) != PNOF_OK) return st;
+  }
+
+  double* J = r.J ? r.J : b.J;
+  double* K = r.K ? r.K : b.K;
+  double* Y = r.Y ? r.Y : b.Y;
+  const bool want_y = r.need_y || (pl.split && r.need_e) || r.Fq;
+  const bool want_e = r.need_e;
+  const bool have_n = (n != nullptr);
+
+  if (have_n) DEV_CHECK(ctx, coeffs(s, nact, pl.npairs, pl.ncwo, pl.functional, n, b.alpha, b.beta, b.beta32));
+  if (H) {
+    // HC = H C_A ; Hpp = diag(C_A^T H C_A)
+    DEV_CHECK(ctx, gemm_f64(s, nbf, nact, nbf, 1, 1.0, H, nbf, 1, 0, C, nbf, 1, 0, 0.0, b.HC, nact, 1, 0));
+    DEV_CHECK(ctx, hpp_from_hc(s, nbf, nact, C, b.HC, b.Hpp));
+  }
+  if (r.Jq) DEV_CHECK(ctx, fill_f64(s, r.Jq, (long long)r.nq * nbf * nbf, 0.0));
+  if (r.Kq) DEV_CHECK(ctx, fill_f64(s, r.Kq, (long long)r.nq * nbf * nbf, 0.0));
+  if (r.Fq) DEV_CHECK(ctx, fill_f64(s, r.Fq, (long long)r.nq * nbf * nbf, 0.0));
+
+  int corr_terms = 0;
+  if (!is_df(pl.ints)) {
+    const double* ERI = static_cast<const double*>(ints);
+    DEV_CHECK(ctx, eri_jk_ao(s, nbf, nact, ERI, C, b.Jr, b.Kr));
+    DEV_CHECK(ctx, eri_jk_no(s, nbf, nact, C, b.Jr, b.Kr, J, K));
+    if (want_y) DEV_CHECK(ctx, eri_y(s, nbf, nact, C, n, b.HC, b.alpha, b.beta, b.Jr, b.Kr, b.Y2e));
+    if (r.Jq) DEV_CHECK(ctx, gather_ao(s, nbf, r.nq, r.q_idx, b.Jr, r.Jq));
+    if (r.Kq) DEV_CHECK(ctx, gather_ao(s, nbf, r.nq, r.q_idx, b.Kr, r.Kq));
+    if (r.Fq) DEV_CHECK(ctx, eri_fock_ao(s, nbf, nact, r.nq, r.q_idx, n, H, b.alpha, b.beta, b.Jr, b.Kr, r.Fq));
+  } else {
+    DEV_CHECK(ctx, fill_f64(s, K, n2, 0.0));
+    if (want_y) DEV_CHECK(ctx, fill_f64(s, b.Y2e, ny, 0.0));
+    if (!pl.split) DEV_CHECK(ctx, transpose_ca(s, nbf, nact, C, b.Ct, pl.ldk));
+    else {
+      DEV_CHECK(ctx, split_ca(s, nbf, nact, pl.terms, C, b.cth, b.ctl, pl.ldk));
+      corr_terms = pl.terms > 1 ? 2 : 1;
+    }
+    const long long bsz = (long long)nbf * nbf;
+    for (int p0 = 0; p0 < pl.naux; p0 += pl.pc) {
+      const int np = std::min(pl.pc, pl.naux - p0);
+      const int ns2 = std::min(pl.ns2, np), ns3 = std::min(pl.ns3, np);
+      double* Dc = b.D + (long long)p0 * nact;
+      if (!pl.split) {
+        const double* Bc;
+        if (pl.ints == PNOF_INTS_DF_F64) Bc = static_cast<const double*>(ints) + p0 * bsz;
+        else {
+          DEV_CHECK(ctx, widen_bf16(s, np * bsz, static_cast<const u16*>(ints) + p0 * bsz, b.Bw));
+          Bc = b.Bw;
+        }
+        DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_X, df_f64_gemm1(s, nbf, nact, np, b.Ct, pl.ldk, Bc, b.XT, pl.ldx)));
+        DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_B, df_f64_gemm2(s, nbf, nact, np, ns2, b.Ct, pl.ldk, b.XT, pl.ldx, b.beta, b.Kpart, Dc, b.W, pl.ldw)));
+        DEV_CHECK(ctx, reduce_k(s, nact, ns2, b.Kpart, K));
+        if (want_y) {
+          DEV_CHECK(ctx, add_diag_f64(s, nact, np, Dc, b.alpha, b.W, pl.ldw));
+          DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_Y, df_f64_gemm3(s, nbf, nact, np, ns3, b.XT, pl.ldx, b.W, pl.ldw, b.Ypart64)));
+          DEV_CHECK(ctx, reduce_y_f64(s, ny, ns3, b.Ypart64, b.Y2e));
+        }
+        if (r.Jq || r.Kq || r.Fq)
+          DEV_CHECK(ctx, df_ao_accum(s, nbf, nact, np, r.nq, r.q_idx, Bc, 0, Dc, b.alpha, b.beta, b.XT, nullptr, nullptr,
+                                     pl.ldx, r.Jq, r.Kq, r.Fq));
+      } else {
+        SplitPtr Bp;
+        const void* Bsrc;
+        if (pl.ints == PNOF_INTS_DF_BF16) {
+          Bp.hi = static_cast<const u16*>(ints) + p0 * bsz;
+          Bp.lo = nullptr;
+          Bsrc = Bp.hi;
+        } else {
+          const double* Bf = static_cast<const double*>(ints) + p0 * bsz;
+          DEV_CHECK(ctx, split_b(s, np * bsz, Bf, b.bh, b.bl));
+          Bp.hi = b.bh;
+          Bp.lo = pl.terms > 1 ? b.bl : nullptr;
+          Bsrc = Bf;
+        }
+        SplitPtr Ct{b.cth, pl.terms > 1 ? b.ctl : nullptr};
+        DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_X, df_bf16_gemm1(s, nbf, nact, np, pl.terms, Ct, pl.ldk, Bp, bsz, nbf, b.xth, b.xtl, pl.ldx,
+                                     b.xh, b.xl, pl.ldxx)));
+        SplitPtr XT{b.xth, b.xtl};
+        DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_B, df_bf16_gemm2(s, nbf, nact, np, ns2, pl.terms, Ct, pl.ldk, XT, pl.ldx, b.beta32, b.Kpart, Dc,
+                                     b.wh, b.wl, pl.ldw)));
+        DEV_CHECK(ctx, reduce_k(s, nact, ns2, b.Kpart, K));
+        if (want_y) {
+          DEV_CHECK(ctx, add_diag_bf16(s, nact, np, Dc, b.alpha, b.wh, b.wl, pl.ldw));
+          SplitPtr X{b.xh, b.xl}, W{b.wh, b.wl};
+          DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_Y, df_bf16_gemm3(s, nbf, nact, np, ns3, pl.terms, X, pl.ldxx, W, pl.ldw, b.Ypart32)));
+          DEV_CHECK(ctx, reduce_y_f32(s, ny, ns3, b.Ypart32, b.Y2e));
+        }
+        if (r.Jq || r.Kq || r.Fq)
+          DEV_CHECK(ctx, df_ao_accum(s, nbf, nact, np, r.nq, r.q_idx, Bsrc, pl.ints == PNOF_INTS_DF_BF16, Dc, b.alpha,
+                                     b.beta, nullptr, b.xth, b.xtl, pl.ldx, r.Jq, r.Kq, r.Fq));
+      }
+    }
+    // J = D^T D
+    DEV_CHECK(ctx, gemm_f64(s, nact, nact, pl.naux, 1, 1.0, b.D, 1, nact, 0, b.D, nact, 1, 0, 0.0, J, nact, 1, 0));
+    if (r.Fq) DEV_CHECK(ctx, fock_ao_h(s, nbf, r.nq, r.q_idx, n, H, r.Fq));
+  }
+
+  if (want_e) {
+    double* E = r.E ? r.E : b.E;
+    DEV_CHECK(ctx, energy(s, nbf, nact, n, b.Hpp, b.alpha, b.beta, J, K, b.Y2e, C, b.cth, b.ctl, pl.ldk, corr_terms,
+                          b.partials, E));
+  }
+  if (want_y) DEV_CHECK(ctx, assemble_y(s, nbf, nact, n, b.HC, b.Y2e, Y));
+  if (r.lam) {
+    DEV_CHECK(ctx, gemm_f64(s, nbf, nact, nbf, 1, 1.0, C, 1, nbf, 0, Y, nact, 1, 0, 0.0, r.lam, nbf, 1, 0));
+    DEV_CHECK(ctx, zero_cols(s, nbf, nact, r.lam));
+    if (r.asym) DEV_CHECK(ctx, max_asym(s, nbf, r.lam, b.partials + 256, r.asym));
+  }
+  if (r.dEdC) DEV_CHECK(ctx, grad_c(s, nbf, nact, Y, r.dEdC));
+  if (r.dEdn) DEV_CHECK(ctx, grad_n(s, nact, pl.npairs, pl.ncwo, pl.functional, n, b.Hpp, J, K, r.dEdn));
+  return PNOF_OK;
+}
+
+pnof_status check_ptrs(pnof_ctx ctx, std::initializer_list<const void*> ps, const char* what) {
+  for (const void* p : ps)
+    if (!p) return fail(ctx, PNOF_E_ARG, std::string("required pointer is NULL in ") + what);
+  return PNOF_OK;
+}
+
+pnof_status check_q(pnof_ctx ctx, const void* a, const int32_t* q_idx, int32_t nq) {
+  if (a && (!q_idx || nq <= 0)) return fail(ctx, PNOF_E_ARG, "per-orbital AO output needs q_idx and nq > 0");
+  if (!a && nq < 0) return fail(ctx, PNOF_E_ARG, "nq must not be negative");
+  return PNOF_OK;
+}
+
+}  // namespace
+
+// ============================================================================ ABI
+extern "C" {
+
+int pnof_abi_version(void) { return PNOF_ABI_VERSION; }
+
+const char* pnof_last_error(pnof_ctx ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+
+pnof_status pnof_check_problem(const pnof_problem* prob) { return check_problem(nullptr, prob); }
+
+pnof_status pnof_create(pnof_ctx* out, int device, void* hip_stream) {
+  if (!out) return fail(nullptr, PNOF_E_ARG, "output pointer is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    hipGetLastError();
+    return fail(nullptr, PNOF_E_DEVICE, "no HIP device");
+  }
+  if (device < 0 || device >= ndev) return fail(nullptr, PNOF_E_ARG, "device index out of range");
+  if (hipSetDevice(device) != hipSuccess) return fail(nullptr, PNOF_E_DEVICE, "hipSetDevice failed");
+  pnof_ctx c = new pnof_ctx_s();
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  if (rocblas_create_handle(&c->blas) != rocblas_status_success) {
+    delete c;
+    return fail(nullptr, PNOF_E_DEVICE, "rocblas_create_handle failed");
+  }
+  rocblas_set_stream(c->blas, c->stream);
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->host_info), sizeof(int) * 4, hipHostMallocDefault) != hipSuccess) {
+    rocblas_destroy_handle(c->blas);
+    delete c;
+    return fail(nullptr, PNOF_E_NOMEM, "pinned allocation failed");
+  }
+  *out = c;
+  return PNOF_OK;
+}
+
+void pnof_destroy(pnof_ctx ctx) {
+  if (!ctx) return;
+  hipSetDevice(ctx->device);
+  hipStreamSynchronize(ctx->stream);
+  for (auto& e : ctx->evs) {
+    hipEventDestroy(e.a);
+    hipEventDestroy(e.b);
+  }
+  for (auto e : ctx->pool) hipEventDestroy(e);
+  if (ctx->own_ws) hipFree(ctx->own_ws);
+  if (ctx->host_info) hipHostFree(ctx->host_info);
+  if (ctx->blas) rocblas_destroy_handle(ctx->blas);
+  delete ctx;
+}
+
+pnof_status pnof_set_stream(pnof_ctx ctx, void* hip_stream) {
+  if (!ctx) return fail(nullptr, PNOF_E_ARG, "context is NULL");
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  rocblas_set_stream(ctx->blas, ctx->stream);
+  return PNOF_OK;
+}
+
+pnof_status pnof_workspace_size(pnof_ctx ctx, const pnof_problem* prob, size_t* bytes) {
+  pnof_status st = check_problem(ctx, prob);
+  if (st != PNOF_OK) return st;
+  if (!bytes) return fail(ctx, PNOF_E_ARG, "bytes is NULL");
+  *bytes = carve(make_plan(prob, ctx ? ctx->pchunk : 0), nullptr).bytes;
+  return PNOF_OK;
+}
+
+pnof_status pnof_set_workspace(pnof_ctx ctx, void* dev, size_t bytes) {
+  if (!ctx) return fail(nullptr, PNOF_E_ARG, "context is NULL");
+  if (dev && (reinterpret_cast<uintptr_t>(dev) & 255)) return fail(ctx, PNOF_E_ARG, "workspace must be 256-byte aligned");
+  ctx->ext_ws = static_cast<char*>(dev);
+  ctx->ext_bytes = dev ? bytes : 0;
+  return PNOF_OK;
+}
+
+pnof_status pnof_profile_begin(pnof_ctx ctx) {
+  if (!ctx) return fail(nullptr, PNOF_E_ARG, "context is NULL");
+  for (auto& e : ctx->evs) {
+    ctx->pool.push_back(e.a);
+    ctx->pool.push_back(e.b);
+  }
+  ctx->evs.clear();
+  ctx->profiling = true;
+  return PNOF_OK;
+}
+
+pnof_status pnof_profile_end(pnof_ctx ctx, double* ms, int64_t* launches) {
+  if (!ctx) return fail(nullptr, PNOF_E_ARG, "context is NULL");
+  if (!ms || !launches) return fail(ctx, PNOF_E_ARG, "output arrays are NULL");
+  ctx->profiling = false;
+  for (int i = 0; i < PNOF_NSTAGES; ++i) { ms[i] = 0.0; launches[i] = 0; }
+  DEV_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+  for (auto& e : ctx->evs) {
+    float t = 0.f;
+    DEV_CHECK(ctx, hipEventElapsedTime(&t, e.a, e.b));
+    ms[e.stage] += t;
+    launches[e.stage] += 1;
+    ctx->pool.push_back(e.a);
+    ctx->pool.push_back(e.b);
+  }
+  ctx->evs.clear();
+  return PNOF_OK;
+}
+
+pnof_status pnof_set_pchunk(pnof_ctx ctx, int32_t pchunk) {
+  if (!ctx) return fail(nullptr, PNOF_E_ARG, "context is NULL");
+  if (pchunk < 0) return fail(ctx, PNOF_E_ARG, "pchunk must be >= 0");
+  ctx->pchunk = pchunk;
+  return PNOF_OK;
+}
+
+pnof_status pnof_on_map(pnof_ctx ctx, int32_t kind, int32_t npairs, int32_t ncwo, const double* gamma, double* n,
+                        double* dn_dgamma) {
+  if (!ctx) return fail(nullptr, PNOF_E_ARG, "context is NULL");
+  if (kind != 0 && kind != 1) return fail(ctx, PNOF_E_ARG, "unknown ON map kind");
+  if (npairs <= 0 || ncwo <= 0) return fail(ctx, PNOF_E_SHAPE, "npairs and ncwo must be positive");
+  pnof_status st = check_ptrs(ctx, {gamma, n}, "pnof_on_map");
+  if (st != PNOF_OK) return st;
+  if ((st = check_ctx(ctx)) != PNOF_OK) return st;
+  const long long nact = (long long)npairs * (ncwo + 1);
+  const long long ngam = kind == 0 ? nact : (long long)npairs * ncwo;
+  if (dn_dgamma) DEV_CHECK(ctx, fill_f64(ctx->stream, dn_dgamma, nact * ngam, 0.0));
+  DEV_CHECK(ctx, on_map(ctx->stream, kind, npairs, ncwo, gamma, n, dn_dgamma));
+  return PNOF_OK;
+}
+
+pnof_status pnof_on_map_vjp(pnof_ctx ctx, int32_t kind, int32_t npairs, int32_t ncwo, const double* gamma,
+                            const double* dEdn, double* dEdgamma) {
+  if (!ctx) return fail(nullptr, PNOF_E_ARG, "context is NULL");
+  if (kind != 0 && kind != 1) return fail(ctx, PNOF_E_ARG, "unknown ON map kind");
+  if (npairs <= 0 || ncwo <= 0) return fail(ctx, PNOF_E_SHAPE, "npairs and ncwo must be positive");
+  pnof_status st = check_ptrs(ctx, {gamma, dEdn, dEdgamma}, "pnof_on_map_vjp");
+  if (st != PNOF_OK) return st;
+  if ((st = check_ctx(ctx)) != PNOF_OK) return st;
+  DEV_CHECK(ctx, on_map_vjp(ctx->stream, kind, npairs, ncwo, gamma, dEdn, dEdgamma));
+  return PNOF_OK;
+}
+
+pnof_status pnof_jk(pnof_ctx ctx, const pnof_problem* prob, const double* C, const void* ints, double* J, double* K,
+                    double* Jq_ao, double* Kq_ao, const int32_t* q_idx, int32_t nq) {
+  if (!ctx) return fail(nullptr, PNOF_E_ARG, "context is NULL");
+  pnof_status st = check_problem(ctx, prob);
+  if (st != PNOF_OK) return st;
+  if ((st = check_ptrs(ctx, {C, ints, J, K}, "pnof_jk")) != PNOF_OK) return st;
+  if ((!Jq_ao) != (!Kq_ao)) return fail(ctx, PNOF_E_ARG, "Jq_ao and Kq_ao must both be set or both be NULL");
+  if ((st = check_q(ctx, Jq_ao, q_idx, nq)) != PNOF_OK) return st;
+  if ((st = check_ctx(ctx)) != PNOF_OK) return st;
+  Req r;
+  r.J = J;
+  r.K = K;
+  r.Jq = Jq_ao;
+  r.Kq = Kq_ao;
+  r.q_idx = q_idx;
+  r.nq = Jq_ao ? nq : 0;
+  // the coefficient kernels are not needed; pass no ONs
+  return run_step(ctx, prob, C, nullptr, nullptr, ints, r);
+}
+
+pnof_status pnof_energy(pnof_ctx ctx, const pnof_problem* prob, const double* C, const double* n, const double* H,
+                        const void* ints, double* E) {
+  if (!ctx) return fail(nullptr, PNOF_E_ARG, "context is NULL");
+  pnof_status st = check_problem(ctx, prob);
+  if (st != PNOF_OK) return st;
+  if ((st = check_ptrs(ctx, {C, n, H, ints, E}, "pnof_energy")) != PNOF_OK) return st;
+  if ((st = check_ctx(ctx)) != PNOF_OK) return st;
+  Req r;
+  r.E = E;
+  r.need_e = true;
+  return run_step(ctx, prob, C, n, H, ints, r);
+}
+
+pnof_status pnof_fock(pnof_ctx ctx, const pnof_problem* prob, const double* C, const double* n, const double* H,
+                      const void* ints, double* Y, double* Fq_ao, const int32_t* q_idx, int32_t nq) {
+  if (!ctx) return fail(nullptr, PNOF_E_ARG, "context is NULL");
+  pnof_status st = check_problem(ctx, prob);
+  if (st != PNOF_OK) return st;
+  if ((st = check_ptrs(ctx, {C, n, H, ints, Y}, "pnof_fock")) != PNOF_OK) return st;
+  if ((st = check_q(ctx, Fq_ao, q_idx, nq)) != PNOF_OK) return st;
+  if ((st = check_ctx(ctx)) != PNOF_OK) return st;
+  Req r;
+  r.Y = Y;
+  r.need_y = true;
+  r.Fq = Fq_ao;
+  r.q_idx = q_idx;
+  r.nq = Fq_ao ? nq : 0;
+  return run_step(ctx, prob, C, n, H, ints, r);
+}
+
+pnof_status pnof_lagrangian(pnof_ctx ctx, const pnof_problem* prob, const double* C, const double* n,
+                            const double* H, const void* ints, double* lambda, double* E, double* dEdC,
+                            double* dEdn, double* max_asym_out, double* J, double* K) {
+  if (!ctx) return fail(nullptr, PNOF_E_ARG, "context is NULL");
+  pnof_status st = check_problem(ctx, prob);
+  if (st != PNOF_OK) return st;
+  if ((st = check_ptrs(ctx, {C, n, H, ints, lambda, E}, "pnof_lagrangian")) != PNOF_OK) return st;
+  if ((st = check_ctx(ctx)) != PNOF_OK) return st;
+  Req r;
+  r.lam = lambda;
+  r.E = E;
+  r.dEdC = dEdC;
+  r.dEdn = dEdn;
+  r.asym = max_asym_out;
+  r.J = J;
+  r.K = K;
+  r.need_y = true;
+  r.need_e = true;
+  return run_step(ctx, prob, C, n, H, ints, r);
+}
+
+pnof_status pnof_orbital_step(pnof_ctx ctx, int32_t nbf, const double* lambda, const double* C,
+                              const double* diag_prev, double zeta, double* C_new, double* eps, double* S_out) {
+  if (!ctx) return fail(nullptr, PNOF_E_ARG, "context is NULL");
+  if (nbf <= 0) return fail(ctx, PNOF_E_SHAPE, "nbf must be positive");
+  if (!std::isfinite(zeta)) return fail(ctx, PNOF_E_ARG, "zeta must be finite");
+  pnof_status st = check_ptrs(ctx, {lambda, C, C_new, eps}, "pnof_orbital_step");
+  if (st != PNOF_OK) return st;
+  if (C_new == C || C_new == lambda) return fail(ctx, PNOF_E_ARG, "C_new must not alias C or lambda");
+  if ((st = check_ctx(ctx)) != PNOF_OK) return st;
+  const long long n2 = (long long)nbf * nbf;
+  Arena probe(nullptr);
+  probe.take<double>(n2);
+  probe.take<double>(nbf);
+  probe.take<int>(4);
+  char* ws = nullptr;
+  if ((st = get_ws(ctx, probe.off + 256, &ws)) != PNOF_OK) return st;
+  Arena a(ws);
+  double* A = a.take<double>(n2);
+  double* E = a.take<double>(nbf);
+  int* info = a.take<int>(4);
+  hipStream_t s = ctx->stream;
+  DEV_CHECK(ctx, build_s(s, nbf, lambda, diag_prev, zeta, A));
+  if (S_out) DEV_CHECK(ctx, hipMemcpyAsync(S_out, A, n2 * sizeof(double), hipMemcpyDeviceToDevice, s));
+  rocblas_status rs = TIMED(ctx, PNOF_STAGE_EIG, rocsolver_dsyevd(ctx->blas, rocblas_evect_original,
+                                                                 rocblas_fill_upper, nbf, A, nbf, eps, E, info));
+  if (rs != rocblas_status_success) return fail(ctx, PNOF_E_DEVICE, "rocsolver_dsyevd failed to launch");
+  DEV_CHECK(ctx, sign_fix_cols(s, nbf, A));
+  // C_new[mu][j] = sum_i C[mu][i] U[i][j], U column-major: U[i][j] = A[j*nbf + i]
+  DEV_CHECK(ctx, gemm_f64(s, nbf, nbf, nbf, 1, 1.0, C, nbf, 1, 0, A, 1, nbf, 0, 0.0, C_new, nbf, 1, 0));
+  DEV_CHECK(ctx, hipMemcpyAsync(ctx->host_info, info, sizeof(int), hipMemcpyDeviceToHost, s));
+  DEV_CHECK(ctx, hipStreamSynchronize(s));
+  if (*ctx->host_info != 0)
+    return fail(ctx, PNOF_E_EIG, "eigensolver did not converge (info = " + std::to_string(*ctx->host_info) + ")");
+  return PNOF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,144 @@
+// Internal declarations shared by the libpnof translation units (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+namespace pnof {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint16_t u16;
+
+// ---------------------------------------------------------------- orbital layout
+// Strong orbital of pair g is g; weak k of pair g is npairs + ncwo*(npairs-1-g) + k.
+__host__ __device__ inline int pair_of(int p, int npairs, int ncwo) {
+  if (p < npairs) return p;
+  int w = p - npairs;
+  int blk = w / ncwo;
+  return (blk < npairs) ? (npairs - 1 - blk) : -1;
+}
+__host__ __device__ inline int weak_index(int g, int k, int npairs, int ncwo) {
+  return npairs + ncwo * (npairs - 1 - g) + k;
+}
+
+// ---------------------------------------------------------------- bf16 helpers
+// Round-to-nearest-even float32 -> bfloat16 bits (inputs here are finite).
+__device__ __forceinline__ u16 f32_to_bf16_bits(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (u16)(u >> 16);
+}
+__device__ __forceinline__ float bf16_bits_to_f32(u16 b) { return __uint_as_float(((uint32_t)b) << 16); }
+
+// x ~= hi + lo with hi = bf16(x), lo = bf16(x - hi).
+__device__ __forceinline__ void split_f32(float x, u16& hi, u16& lo) {
+  hi = f32_to_bf16_bits(x);
+  lo = f32_to_bf16_bits(x - bf16_bits_to_f32(hi));
+}
+__device__ __forceinline__ void split_f64(double x, u16& hi, u16& lo) {
+  hi = f32_to_bf16_bits((float)x);
+  lo = f32_to_bf16_bits((float)(x - (double)bf16_bits_to_f32(hi)));
+}
+
+inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
+inline long long round_up(long long a, long long b) { return (a + b - 1) / b * b; }
+
+// ---------------------------------------------------------------- f64 GEMM (k_gemm_f64.hip)
+// C[b] = alpha * A[b] B[b] + beta * C[b] with strided views
+//   A(m,k) = A[b*sab + m*sam + k*sak], B(k,n) = B[b*sbb + k*sbk + n*sbn], C(m,n) = C[b*scb + m*scm + n*scn]
+// Exactly one of sam/sak and one of sbk/sbn must be 1.
+hipError_t gemm_f64(hipStream_t s, int M, int N, int K, int batch, double alpha, const double* A,
+                    long long sam, long long sak, long long sab, const double* B, long long sbk,
+                    long long sbn, long long sbb, double beta, double* C, long long scm, long long scn,
+                    long long scb);
+
+// FP64 three-index contractions of one P-chunk (np rows of B).
+//  gemm1: XT[P][p][mu] = sum_nu Ct[p][nu] B_P[mu][nu]      (Ct: nact x ldk, XT: ld ldx)
+//  gemm2: b_P = Ct XT_P^T on lower tiles; Kpart[s] += b^2; D[P][p] = b_pp; W[P] = b o beta
+//  gemm3: Ypart[s][mu][q] = sum_{P in split s} sum_r XT[P][r][mu] W[P][r][q]
+hipError_t df_f64_gemm1(hipStream_t s, int nbf, int nact, int np, const double* Ct, int ldk,
+                        const double* Bchunk, double* XT, int ldx);
+hipError_t df_f64_gemm2(hipStream_t s, int nbf, int nact, int np, int nsplit, const double* Ct,
+                        int ldk, const double* XT, int ldx, const double* beta, double* Kpart,
+                        double* Dchunk, double* W, int ldw);
+hipError_t df_f64_gemm3(hipStream_t s, int nbf, int nact, int np, int nsplit, const double* XT,
+                        int ldx, const double* W, int ldw, double* Ypart);
+
+// ---------------------------------------------------------------- bf16 split GEMMs (k_gemm_bf16.hip)
+// terms: 1 = hi*hi; 3 = hi*hi + hi*lo + lo*hi.  B_P given as bf16 (exact, 2 products against the
+// split Ct) or as a pre-split hi/lo pair (3 products).
+struct SplitPtr {
+  const u16* hi;
+  const u16* lo;  // may be null when terms == 1 or the operand is exact
+};
+hipError_t df_bf16_gemm1(hipStream_t s, int nbf, int nact, int np, int terms, SplitPtr Ct, int ldk,
+                         SplitPtr Bp, long long bstride, int ldb, u16* XT_hi, u16* XT_lo, int ldx,
+                         u16* X_hi, u16* X_lo, int ldxx);
+hipError_t df_bf16_gemm2(hipStream_t s, int nbf, int nact, int np, int nsplit, int terms,
+                         SplitPtr Ct, int ldk, SplitPtr XT, int ldx, const float* beta32,
+                         double* Kpart, double* Dchunk, u16* W_hi, u16* W_lo, int ldw);
+hipError_t df_bf16_gemm3(hipStream_t s, int nbf, int nact, int np, int nsplit, int terms, SplitPtr X,
+                         int ldxx, SplitPtr W, int ldw, float* Ypart);
+
+// ---------------------------------------------------------------- small kernels (k_small.hip)
+hipError_t fill_f64(hipStream_t s, double* p, long long n, double v);
+hipError_t fill_u16(hipStream_t s, u16* p, long long n, u16 v);
+hipError_t coeffs(hipStream_t s, int nact, int npairs, int ncwo, int functional, const double* n,
+                  double* alpha, double* beta, float* beta32);
+hipError_t transpose_ca(hipStream_t s, int nbf, int nact, const double* C, double* Ct, int ldk);
+hipError_t split_ca(hipStream_t s, int nbf, int nact, int terms, const double* C, u16* Ct_hi,
+                    u16* Ct_lo, int ldk);
+hipError_t split_b(hipStream_t s, long long n, const double* B, u16* hi, u16* lo);
+hipError_t widen_bf16(hipStream_t s, long long n, const u16* src, double* dst);
+hipError_t hpp_from_hc(hipStream_t s, int nbf, int nact, const double* C, const double* HC, double* Hpp);
+hipError_t add_diag_f64(hipStream_t s, int nact, int np, const double* Dchunk, const double* alpha,
+                        double* W, int ldw);
+hipError_t add_diag_bf16(hipStream_t s, int nact, int np, const double* Dchunk, const double* alpha,
+                         u16* W_hi, u16* W_lo, int ldw);
+hipError_t reduce_k(hipStream_t s, int nact, int nsplit, const double* Kpart, double* K);
+hipError_t reduce_y_f64(hipStream_t s, long long n, int nsplit, const double* Ypart, double* Y);
+hipError_t reduce_y_f32(hipStream_t s, long long n, int nsplit, const float* Ypart, double* Y);
+hipError_t energy(hipStream_t s, int nbf, int nact, const double* n, const double* Hpp,
+                  const double* alpha, const double* beta, const double* J, const double* K,
+                  const double* Y2e, const double* C, const u16* Ct_hi, const u16* Ct_lo, int ldk,
+                  int corr_terms, double* partials, double* E);
+hipError_t assemble_y(hipStream_t s, int nbf, int nact, const double* n, const double* HC,
+                      const double* Y2e, double* Y);
+hipError_t grad_c(hipStream_t s, int nbf, int nact, const double* Y, double* dEdC);
+hipError_t zero_cols(hipStream_t s, int nbf, int col0, double* M);
+hipError_t max_asym(hipStream_t s, int nbf, const double* lam, double* partials, double* out);
+hipError_t grad_n(hipStream_t s, int nact, int npairs, int ncwo, int functional, const double* n,
+                  const double* Hpp, const double* J, const double* K, double* dEdn);
+hipError_t on_map(hipStream_t s, int kind, int npairs, int ncwo, const double* gamma, double* n,
+                  double* jac);
+hipError_t on_map_vjp(hipStream_t s, int kind, int npairs, int ncwo, const double* gamma,
+                      const double* dEdn, double* dEdgamma);
+hipError_t build_s(hipStream_t s, int nbf, const double* lam, const double* diag_prev, double zeta,
+                   double* S);
+hipError_t sign_fix_cols(hipStream_t s, int nbf, double* Ucm);
+hipError_t count_nonfinite(hipStream_t s, const void* p, long long n, int is_bf16, int* flag);
+// explicit four-index integrals (nbf <= 64)
+hipError_t eri_jk_ao(hipStream_t s, int nbf, int nact, const double* ERI, const double* C,
+                     double* Jr, double* Kr);
+hipError_t eri_jk_no(hipStream_t s, int nbf, int nact, const double* C, const double* Jr,
+                     const double* Kr, double* J, double* K);
+hipError_t eri_y(hipStream_t s, int nbf, int nact, const double* C, const double* n,
+                 const double* HC, const double* alpha, const double* beta, const double* Jr,
+                 const double* Kr, double* Y2e);
+hipError_t gather_ao(hipStream_t s, int nbf, int nq, const int32_t* q_idx, const double* src,
+                     double* dst);
+hipError_t eri_fock_ao(hipStream_t s, int nbf, int nact, int nq, const int32_t* q_idx,
+                       const double* n, const double* H, const double* alpha, const double* beta,
+                       const double* Jr, const double* Kr, double* Fq);
+// density-fitted per-orbital AO matrices, accumulated one P-chunk at a time
+hipError_t df_ao_accum(hipStream_t s, int nbf, int nact, int np, int nq, const int32_t* q_idx,
+                       const void* Bchunk, int b_is_bf16, const double* Dchunk,
+                       const double* alpha, const double* beta, const double* XT, const u16* XT_hi,
+                       const u16* XT_lo, int ldx, double* Jq, double* Kq, double* Fq);
+hipError_t fock_ao_h(hipStream_t s, int nbf, int nq, const int32_t* q_idx, const double* n,
+                     const double* H, double* Fq);
+
+}  // namespace pnof

@@ -1,0 +1,290 @@
+// Float64 matrix-core (v_mfma_f64_16x16x4) contractions.
+//
+// Block tile 64 x 64 x 16, 256 threads = 4 waves in a 2 x 2 arrangement, each wave owning a
+// 32 x 32 sub-tile = 2 x 2 MFMA blocks of 16 x 16.  Operands are staged through LDS stored
+// k-major ([k][m] and [k][n]), which is the order in which the f64 MFMA consumes them (lane l
+// supplies A[m = l%16][k = l/16] and B[k = l/16][n = l%16]; the result element (4*(l/16)+j, l%16)
+// sits in component j of lane l).  Register prefetch of the next k-slab overlaps global loads
+// with the matrix-core work.
+#include "common.h"
+
+namespace pnof {
+namespace {
+
+constexpr int TM = 64, TN = 64, TK = 16, LPAD = 2;
+
+struct F64Smem {
+  double a[TK][TM + LPAD];
+  double b[TK][TN + LPAD];
+};
+
+// Strided view helper: element (r, k) of an operand, with r the output-side index.
+template <bool RCONTIG>
+__device__ __forceinline__ void load_slab(const double* __restrict__ P, long long sr, long long sk,
+                                          int R, int K, int r0, int k0, double (&reg)[4]) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    int r, k;
+    if (RCONTIG) { r = t & 63; k = (t >> 6) + 4 * i; }
+    else         { r = t >> 2; k = ((t & 3) << 2) + i; }
+    const int gr = r0 + r, gk = k0 + k;
+    reg[i] = (gr < R && gk < K) ? P[(long long)gr * sr + (long long)gk * sk] : 0.0;
+  }
+}
+
+template <bool RCONTIG>
+__device__ __forceinline__ void store_slab(double (*S)[TM + LPAD], const double (&reg)[4]) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    int r, k;
+    if (RCONTIG) { r = t & 63; k = (t >> 6) + 4 * i; }
+    else         { r = t >> 2; k = ((t & 3) << 2) + i; }
+    S[k][r] = reg[i];
+  }
+}
+
+// acc[mi][ni] += A(m0.., :) B(:, n0..) over k in [0, K).
+template <bool AM, bool BN>
+__device__ __forceinline__ void tile_f64(F64Smem& sm, const double* __restrict__ A, long long sam,
+                                         long long sak, const double* __restrict__ B, long long sbk,
+                                         long long sbn, int M, int N, int K, int m0, int n0,
+                                         f64x4 (&acc)[2][2]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  double ra[4], rb[4];
+  load_slab<AM>(A, sam, sak, M, K, m0, 0, ra);
+  load_slab<BN>(B, sbn, sbk, N, K, n0, 0, rb);
+  for (int k0 = 0; k0 < K; k0 += TK) {
+    __syncthreads();
+    store_slab<AM>(sm.a, ra);
+    store_slab<BN>(sm.b, rb);
+    __syncthreads();
+    if (k0 + TK < K) {
+      load_slab<AM>(A, sam, sak, M, K, m0, k0 + TK, ra);
+      load_slab<BN>(B, sbn, sbk, N, K, n0, k0 + TK, rb);
+    }
+#pragma unroll
+    for (int kk = 0; kk < TK; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      double a0 = sm.a[kr][wm + (lane & 15)], a1 = sm.a[kr][wm + 16 + (lane & 15)];
+      double b0 = sm.b[kr][wn + (lane & 15)], b1 = sm.b[kr][wn + 16 + (lane & 15)];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+  }
+}
+
+__device__ __forceinline__ void zero_acc(f64x4 (&acc)[2][2]) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+}
+
+// Row / column of component j of acc[mi][ni] relative to the block tile origin.
+__device__ __forceinline__ int acc_row(int mi, int j) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  return (wave >> 1) * 32 + mi * 16 + 4 * (lane >> 4) + j;
+}
+__device__ __forceinline__ int acc_col(int ni) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  return (wave & 1) * 32 + ni * 16 + (lane & 15);
+}
+
+template <bool AM, bool BN>
+__global__ __launch_bounds__(256) void gemm_f64_kernel(int M, int N, int K, double alpha,
+                                                       const double* __restrict__ A, long long sam,
+                                                       long long sak, long long sab,
+                                                       const double* __restrict__ B, long long sbk,
+                                                       long long sbn, long long sbb, double beta,
+                                                       double* __restrict__ C, long long scm,
+                                                       long long scn, long long scb) {
+  __shared__ F64Smem sm;
+  const int tiles_n = (N + TN - 1) / TN;
+  const int m0 = (blockIdx.x / tiles_n) * TM, n0 = (blockIdx.x % tiles_n) * TN;
+  const long long b = blockIdx.y;
+  f64x4 acc[2][2];
+  zero_acc(acc);
+  tile_f64<AM, BN>(sm, A + b * sab, sam, sak, B + b * sbb, sbk, sbn, M, N, K, m0, n0, acc);
+  double* Cb = C + b * scb;
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int m = m0 + acc_row(mi, j), n = n0 + acc_col(ni);
+        if (m < M && n < N) {
+          double* c = Cb + (long long)m * scm + (long long)n * scn;
+          *c = alpha * acc[mi][ni][j] + (beta != 0.0 ? beta * *c : 0.0);
+        }
+      }
+}
+
+// Lower-triangle tile index t -> (tm, tn) with tn <= tm.
+__device__ __forceinline__ void tri_tile(int t, int& tm, int& tn) {
+  int r = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((r + 1) * (r + 2) / 2 <= t) ++r;
+  while (r * (r + 1) / 2 > t) --r;
+  tm = r;
+  tn = t - r * (r + 1) / 2;
+}
+
+// gemm1: XT[P][p][mu] = sum_nu Ct[p][nu] B_P[nu][mu] (B_P symmetric, row-major).
+__global__ __launch_bounds__(256) void df_gemm1_kernel(int nbf, int nact, const double* __restrict__ Ct,
+                                                       int ldk, const double* __restrict__ Bc,
+                                                       double* __restrict__ XT, int ldx) {
+  __shared__ F64Smem sm;
+  const int tiles_n = (nbf + TN - 1) / TN;
+  const int m0 = (blockIdx.x / tiles_n) * TM, n0 = (blockIdx.x % tiles_n) * TN;
+  const long long P = blockIdx.y;
+  f64x4 acc[2][2];
+  zero_acc(acc);
+  // A(m=p, k=nu) = Ct[p*ldk + nu] (k contiguous); B(k=nu, n=mu) = B_P[nu*nbf + mu] (n contiguous)
+  tile_f64<false, true>(sm, Ct, ldk, 1, Bc + P * nbf * nbf, nbf, 1, nact, nbf, nbf, m0, n0, acc);
+  double* X = XT + P * (long long)nact * ldx;
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int m = m0 + acc_row(mi, j), n = n0 + acc_col(ni);
+        if (m < nact && n < nbf) X[(long long)m * ldx + n] = acc[mi][ni][j];
+      }
+}
+
+// gemm2: b_P = Ct XT_P^T on lower tiles of the nact x nact result, P in the block's split.
+__global__ __launch_bounds__(256) void df_gemm2_kernel(int nbf, int nact, int np, int nsplit,
+                                                       const double* __restrict__ Ct, int ldk,
+                                                       const double* __restrict__ XT, int ldx,
+                                                       const double* __restrict__ beta,
+                                                       double* __restrict__ Kpart,
+                                                       double* __restrict__ Dc,
+                                                       double* __restrict__ W, int ldw) {
+  __shared__ F64Smem sm;
+  int tm, tn;
+  tri_tile(blockIdx.x, tm, tn);
+  const int m0 = tm * TM, n0 = tn * TN;
+  const int s = blockIdx.y;
+  const int pb = (int)((long long)np * s / nsplit), pe = (int)((long long)np * (s + 1) / nsplit);
+  f64x4 kacc[2][2];
+  zero_acc(kacc);
+  for (int P = pb; P < pe; ++P) {
+    f64x4 acc[2][2];
+    zero_acc(acc);
+    // A(m=p, k=mu) = Ct[p*ldk + mu]; B(k=mu, n=q) = XT_P[q*ldx + mu] (k contiguous)
+    tile_f64<false, false>(sm, Ct, ldk, 1, XT + (long long)P * nact * ldx, 1, ldx, nact, nact, nbf,
+                           m0, n0, acc);
+    double* Wp = W + (long long)P * nact * ldw;
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int p = m0 + acc_row(mi, j), q = n0 + acc_col(ni);
+          const double b = acc[mi][ni][j];
+          kacc[mi][ni][j] += b * b;
+          if (p < nact && q <= p) {  // each unordered pair written once: deterministic W
+            const double w = b * beta[(long long)p * nact + q];
+            Wp[(long long)p * ldw + q] = w;
+            Wp[(long long)q * ldw + p] = w;
+            if (p == q) Dc[(long long)P * nact + p] = b;
+          }
+        }
+  }
+  double* Kp = Kpart + (long long)s * nact * nact;
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int p = m0 + acc_row(mi, j), q = n0 + acc_col(ni);
+        if (p < nact && q < nact) Kp[(long long)p * nact + q] = kacc[mi][ni][j];
+      }
+}
+
+// gemm3: Ypart[s][mu][q] = sum_{P in split s} sum_r XT_P[r][mu] W_P[r][q].
+__global__ __launch_bounds__(256) void df_gemm3_kernel(int nbf, int nact, int np, int nsplit,
+                                                       const double* __restrict__ XT, int ldx,
+                                                       const double* __restrict__ W, int ldw,
+                                                       double* __restrict__ Ypart) {
+  __shared__ F64Smem sm;
+  const int tiles_n = (nact + TN - 1) / TN;
+  const int m0 = (blockIdx.x / tiles_n) * TM, n0 = (blockIdx.x % tiles_n) * TN;
+  const int s = blockIdx.y;
+  const int pb = (int)((long long)np * s / nsplit), pe = (int)((long long)np * (s + 1) / nsplit);
+  f64x4 acc[2][2];
+  zero_acc(acc);
+  for (int P = pb; P < pe; ++P) {
+    // A(m=mu, k=r) = XT_P[r*ldx + mu] (m contiguous); B(k=r, n=q) = W_P[r*ldw + q] (n contiguous)
+    tile_f64<true, true>(sm, XT + (long long)P * nact * ldx, 1, ldx, W + (long long)P * nact * ldw,
+                         ldw, 1, nbf, nact, nact, m0, n0, acc);
+  }
+  double* Y = Ypart + (long long)s * nbf * nact;
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int m = m0 + acc_row(mi, j), n = n0 + acc_col(ni);
+        if (m < nbf && n < nact) Y[(long long)m * nact + n] = acc[mi][ni][j];
+      }
+}
+
+}  // namespace
+
+hipError_t gemm_f64(hipStream_t s, int M, int N, int K, int batch, double alpha, const double* A,
+                    long long sam, long long sak, long long sab, const double* B, long long sbk,
+                    long long sbn, long long sbb, double beta, double* C, long long scm, long long scn,
+                    long long scb) {
+  if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  dim3 grid(cdiv(M, TM) * cdiv(N, TN), batch);
+  const bool am = (sam == 1), bn = (sbn == 1);
+  if (am && bn)
+    hipLaunchKernelGGL((gemm_f64_kernel<true, true>), grid, dim3(256), 0, s, M, N, K, alpha, A, sam, sak, sab, B, sbk, sbn, sbb, beta, C, scm, scn, scb);
+  else if (am && !bn)
+    hipLaunchKernelGGL((gemm_f64_kernel<true, false>), grid, dim3(256), 0, s, M, N, K, alpha, A, sam, sak, sab, B, sbk, sbn, sbb, beta, C, scm, scn, scb);
+  else if (!am && bn)
+    hipLaunchKernelGGL((gemm_f64_kernel<false, true>), grid, dim3(256), 0, s, M, N, K, alpha, A, sam, sak, sab, B, sbk, sbn, sbb, beta, C, scm, scn, scb);
+  else
+    hipLaunchKernelGGL((gemm_f64_kernel<false, false>), grid, dim3(256), 0, s, M, N, K, alpha, A, sam, sak, sab, B, sbk, sbn, sbb, beta, C, scm, scn, scb);
+  return hipGetLastError();
+}
+
+hipError_t df_f64_gemm1(hipStream_t s, int nbf, int nact, int np, const double* Ct, int ldk,
+                        const double* Bchunk, double* XT, int ldx) {
+  if (np <= 0) return hipSuccess;
+  dim3 grid(cdiv(nact, TM) * cdiv(nbf, TN), np);
+  hipLaunchKernelGGL(df_gemm1_kernel, grid, dim3(256), 0, s, nbf, nact, Ct, ldk, Bchunk, XT, ldx);
+  return hipGetLastError();
+}
+
+hipError_t df_f64_gemm2(hipStream_t s, int nbf, int nact, int np, int nsplit, const double* Ct,
+                        int ldk, const double* XT, int ldx, const double* beta, double* Kpart,
+                        double* Dchunk, double* W, int ldw) {
+  if (np <= 0) return hipSuccess;
+  const int t = cdiv(nact, TM);
+  dim3 grid(t * (t + 1) / 2, nsplit);
+  hipLaunchKernelGGL(df_gemm2_kernel, grid, dim3(256), 0, s, nbf, nact, np, nsplit, Ct, ldk, XT, ldx,
+                     beta, Kpart, Dchunk, W, ldw);
+  return hipGetLastError();
+}
+
+hipError_t df_f64_gemm3(hipStream_t s, int nbf, int nact, int np, int nsplit, const double* XT,
+                        int ldx, const double* W, int ldw, double* Ypart) {
+  if (np <= 0) return hipSuccess;
+  dim3 grid(cdiv(nbf, TM) * cdiv(nact, TN), nsplit);
+  hipLaunchKernelGGL(df_gemm3_kernel, grid, dim3(256), 0, s, nbf, nact, np, nsplit, XT, ldx, W, ldw,
+                     Ypart);
+  return hipGetLastError();
+}
+
+}  // namespace pnof

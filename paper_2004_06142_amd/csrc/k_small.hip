@@ -1,0 +1,751 @@
+// Element-wise, reduction and small-matrix kernels of the PNOF step (float64 throughout).
+#include "common.h"
+
+namespace pnof {
+namespace {
+
+constexpr int NT = 256;
+
+inline dim3 grid1(long long n, int per = NT) {
+  long long b = (n + per - 1) / per;
+  if (b < 1) b = 1;
+  if (b > 65535LL * 16) b = 65535LL * 16;
+  return dim3((unsigned)b);
+}
+
+#define GRID_STRIDE(i, n) \
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (long long)gridDim.x * blockDim.x)
+
+__global__ void fill_f64_k(double* p, long long n, double v) { GRID_STRIDE(i, n) p[i] = v; }
+__global__ void fill_u16_k(u16* p, long long n, u16 v) { GRID_STRIDE(i, n) p[i] = v; }
+
+// alpha, beta of E_2 = sum_pq alpha_pq J_pq + beta_pq K_pq (Eqs. Eg, Efg, Efg_s).
+__global__ void coeffs_k(int nact, int npairs, int ncwo, int functional, const double* __restrict__ n,
+                         double* __restrict__ alpha, double* __restrict__ beta, float* __restrict__ beta32) {
+  GRID_STRIDE(i, (long long)nact * nact) {
+    const int p = (int)(i / nact), q = (int)(i % nact);
+    const int gp = pair_of(p, npairs, ncwo), gq = pair_of(q, npairs, ncwo);
+    const double np_ = n[p], nq = n[q];
+    double a = 0.0, b;
+    if (gp == gq) {
+      if (p == q) b = np_;
+      else {
+        const double s = sqrt(np_ * nq);
+        b = (p < npairs || q < npairs) ? -s : s;
+      }
+    } else {
+      a = 2.0 * np_ * nq;
+      if (functional == 5) b = -np_ * nq;
+      else if (functional == 8) b = -np_ * nq - 4.0 * (np_ * (1.0 - np_)) * (nq * (1.0 - nq));
+      else b = -np_ * nq - sqrt(np_ * (1.0 - np_)) * sqrt(nq * (1.0 - nq));
+    }
+    alpha[i] = a;
+    beta[i] = b;
+    if (beta32) beta32[i] = (float)b;
+  }
+}
+
+__global__ void transpose_ca_k(int nbf, int nact, const double* __restrict__ C, double* __restrict__ Ct, int ldk) {
+  GRID_STRIDE(i, (long long)nact * nbf) {
+    const int p = (int)(i / nbf), mu = (int)(i % nbf);
+    Ct[(long long)p * ldk + mu] = C[(long long)mu * nbf + p];
+  }
+}
+
+__global__ void split_ca_k(int nbf, int nact, int terms, const double* __restrict__ C, u16* __restrict__ hi,
+                           u16* __restrict__ lo, int ldk) {
+  GRID_STRIDE(i, (long long)nact * nbf) {
+    const int p = (int)(i / nbf), mu = (int)(i % nbf);
+    u16 h, l;
+    split_f64(C[(long long)mu * nbf + p], h, l);
+    hi[(long long)p * ldk + mu] = h;
+    if (terms > 1) lo[(long long)p * ldk + mu] = l;
+  }
+}
+
+__global__ void split_b_k(long long n, const double* __restrict__ B, u16* __restrict__ hi, u16* __restrict__ lo) {
+  GRID_STRIDE(i, n) {
+    u16 h, l;
+    split_f64(B[i], h, l);
+    hi[i] = h;
+    lo[i] = l;
+  }
+}
+
+// Hpp[p] = sum_mu C[mu][p] HC[mu][p]: one wavefront per orbital, fixed reduction order.
+__global__ void hpp_k(int nbf, int nact, const double* __restrict__ C, const double* __restrict__ HC,
+                      double* __restrict__ Hpp) {
+  const int p = blockIdx.x;
+  const int lane = threadIdx.x;
+  double s = 0.0;
+  for (int mu = lane; mu < nbf; mu += 64) s += C[(long long)mu * nbf + p] * HC[(long long)mu * nact + p];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) Hpp[p] = s;
+}
+
+// d_Pp = sum_q D[P][q] alpha[q][p]; W_P[p][p] += d_Pp.
+__global__ void add_diag_f64_k(int nact, int np, const double* __restrict__ Dc, const double* __restrict__ alpha,
+                               double* __restrict__ W, int ldw) {
+  GRID_STRIDE(i, (long long)np * nact) {
+    const long long P = i / nact;
+    const int p = (int)(i % nact);
+    const double* Dp = Dc + P * nact;
+    double d = 0.0;
+    for (int q = 0; q < nact; ++q) d += Dp[q] * alpha[(long long)p * nact + q];
+    W[P * nact * ldw + (long long)p * ldw + p] += d;
+  }
+}
+
+__global__ void add_diag_bf16_k(int nact, int np, const double* __restrict__ Dc, const double* __restrict__ alpha,
+                                u16* __restrict__ Wh, u16* __restrict__ Wl, int ldw) {
+  GRID_STRIDE(i, (long long)np * nact) {
+    const long long P = i / nact;
+    const int p = (int)(i % nact);
+    const double* Dp = Dc + P * nact;
+    double d = 0.0;
+    for (int q = 0; q < nact; ++q) d += Dp[q] * alpha[(long long)p * nact + q];
+    const long long o = P * nact * ldw + (long long)p * ldw + p;
+    double w = (double)bf16_bits_to_f32(Wh[o]) + (Wl ? (double)bf16_bits_to_f32(Wl[o]) : 0.0) + d;
+    u16 h, l;
+    split_f64(w, h, l);
+    Wh[o] = h;
+    if (Wl) Wl[o] = l;
+  }
+}
+
+// K[p][q] += sum_s Kpart[s][max][min], mirrored.
+__global__ void reduce_k_k(int nact, int nsplit, const double* __restrict__ Kpart, double* __restrict__ K) {
+  GRID_STRIDE(i, (long long)nact * nact) {
+    const int p = (int)(i / nact), q = (int)(i % nact);
+    const int a = p > q ? p : q, b = p > q ? q : p;
+    double s = 0.0;
+    for (int k = 0; k < nsplit; ++k) s += Kpart[(long long)k * nact * nact + (long long)a * nact + b];
+    K[i] += s;
+  }
+}
+
+template <typename T>
+__global__ void reduce_y_k(long long n, int nsplit, const T* __restrict__ Yp, double* __restrict__ Y) {
+  GRID_STRIDE(i, n) {
+    double s = 0.0;
+    for (int k = 0; k < nsplit; ++k) s += (double)Yp[(long long)k * n + i];
+    Y[i] += s;
+  }
+}
+
+// Energy (Eqs. EPNOF7, Eg, Efg) and, for split arithmetic, the first-order correction
+// 4 <Y2e, C_A - C~_A>.  Stage 1: fixed-range block partial sums; stage 2: one block.
+__device__ inline double block_sum(double v) {
+  __shared__ double red[NT / 64];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < NT / 64; ++i) s += red[i];
+  return s;
+}
+
+__global__ void energy_stage1_k(int nbf, int nact, const double* __restrict__ n, const double* __restrict__ Hpp,
+                                const double* __restrict__ alpha, const double* __restrict__ beta,
+                                const double* __restrict__ J, const double* __restrict__ K,
+                                const double* __restrict__ Y2e, const double* __restrict__ C,
+                                const u16* __restrict__ cth, const u16* __restrict__ ctl, int ldk,
+                                int corr_terms, double* __restrict__ partials) {
+  const long long n2 = (long long)nact * nact;
+  const long long ncorr = corr_terms > 0 ? (long long)nbf * nact : 0;
+  const long long total = nact + n2 + ncorr;
+  const long long per = (total + gridDim.x - 1) / gridDim.x;
+  const long long b0 = blockIdx.x * per, b1 = min(total, b0 + per);
+  double s = 0.0;
+  for (long long i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
+    if (i < nact) s += 2.0 * n[i] * Hpp[i];
+    else if (i < nact + n2) { const long long k = i - nact; s += alpha[k] * J[k] + beta[k] * K[k]; }
+    else {
+      const long long k = i - nact - n2;
+      const int mu = (int)(k / nact), p = (int)(k % nact);
+      double ct = (double)bf16_bits_to_f32(cth[(long long)p * ldk + mu]);
+      if (corr_terms > 1) ct += (double)bf16_bits_to_f32(ctl[(long long)p * ldk + mu]);
+      s += 4.0 * Y2e[k] * (C[(long long)mu * nbf + p] - ct);
+    }
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ void sum_partials_k(int nparts, const double* __restrict__ partials, double* __restrict__ out) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) s += partials[i];
+  s = block_sum(s);
+  if (threadIdx.x == 0) *out = s;
+}
+
+__global__ void assemble_y_k(int nbf, int nact, const double* __restrict__ n, const double* __restrict__ HC,
+                             const double* __restrict__ Y2e, double* __restrict__ Y) {
+  GRID_STRIDE(i, (long long)nbf * nact) {
+    const int q = (int)(i % nact);
+    Y[i] = n[q] * HC[i] + Y2e[i];
+  }
+}
+
+__global__ void grad_c_k(int nbf, int nact, const double* __restrict__ Y, double* __restrict__ G) {
+  GRID_STRIDE(i, (long long)nbf * nbf) {
+    const int mu = (int)(i / nbf), q = (int)(i % nbf);
+    G[i] = q < nact ? 4.0 * Y[(long long)mu * nact + q] : 0.0;
+  }
+}
+
+__global__ void zero_cols_k(int nbf, int col0, double* __restrict__ M) {
+  const long long w = nbf - col0;
+  GRID_STRIDE(i, (long long)nbf * w) {
+    const long long r = i / w;
+    const int c = col0 + (int)(i % w);
+    M[r * nbf + c] = 0.0;
+  }
+}
+
+__device__ inline double block_max(double v) {
+  __shared__ double red[NT / 64];
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < NT / 64; ++i) s = fmax(s, red[i]);
+  return s;
+}
+
+__global__ void asym_stage1_k(int nbf, const double* __restrict__ lam, double* __restrict__ partials) {
+  double m = 0.0;
+  GRID_STRIDE(i, (long long)nbf * nbf) {
+    const long long p = i / nbf, q = i % nbf;
+    m = fmax(m, fabs(lam[i] - lam[q * nbf + p]));
+  }
+  m = block_max(m);
+  if (threadIdx.x == 0) partials[blockIdx.x] = m;
+}
+
+__global__ void max_partials_k(int nparts, const double* __restrict__ partials, double* __restrict__ out) {
+  double m = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) m = fmax(m, partials[i]);
+  m = block_max(m);
+  if (threadIdx.x == 0) *out = m;
+}
+
+// dE/dn_p (derivative of Eqs. Eg, Efg at fixed J, K, H_pp): one wavefront per orbital.
+__global__ void grad_n_k(int nact, int npairs, int ncwo, int functional, const double* __restrict__ n,
+                         const double* __restrict__ Hpp, const double* __restrict__ J,
+                         const double* __restrict__ K, double* __restrict__ g) {
+  const int p = blockIdx.x, lane = threadIdx.x;
+  const int gp = pair_of(p, npairs, ncwo);
+  const double np_ = n[p];
+  const double php = sqrt(np_ * (1.0 - np_));
+  double s = 0.0;
+  for (int q = lane; q < nact; q += 64) {
+    if (q == p) continue;
+    const double nq = n[q];
+    const double kpq = K[(long long)p * nact + q];
+    if (pair_of(q, npairs, ncwo) == gp) {
+      const double sg = (p < npairs || q < npairs) ? -1.0 : 1.0;
+      s += sg * sqrt(nq / np_) * kpq;
+    } else {
+      s += 4.0 * nq * J[(long long)p * nact + q] - 2.0 * nq * kpq;
+      if (functional == 7) s += -sqrt(nq * (1.0 - nq)) * (1.0 - 2.0 * np_) / php * kpq;
+      else if (functional == 8) s += -8.0 * (1.0 - 2.0 * np_) * nq * (1.0 - nq) * kpq;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) g[p] = 2.0 * Hpp[p] + K[(long long)p * nact + p] + s;
+}
+
+__device__ inline double sigm(double x) { return 1.0 / (1.0 + exp(-x)); }
+
+// ON maps, one thread per pair (Section 3.1).
+__global__ void on_map_k(int kind, int npairs, int ncwo, const double* __restrict__ gamma,
+                         double* __restrict__ n, double* __restrict__ jac) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= npairs) return;
+  const int nact = npairs * (ncwo + 1);
+  const int ngam = kind == 0 ? nact : npairs * ncwo;
+  if (kind == 0) {
+    double S = sigm(gamma[g]);
+    for (int k = 0; k < ncwo; ++k) S += sigm(gamma[weak_index(g, k, npairs, ncwo)]);
+    for (int a = -1; a < ncwo; ++a) {
+      const int p = a < 0 ? g : weak_index(g, a, npairs, ncwo);
+      const double sp = sigm(gamma[p]);
+      n[p] = sp / S;
+      if (jac) {
+        for (int b = -1; b < ncwo; ++b) {
+          const int r = b < 0 ? g : weak_index(g, b, npairs, ncwo);
+          const double sr = sigm(gamma[r]);
+          const double dsr = sr * (1.0 - sr);
+          jac[(long long)p * ngam + r] = ((p == r ? dsr : 0.0) * S - sp * dsr) / (S * S);
+        }
+      }
+    }
+  } else {
+    const double gs = gamma[g];
+    const double cg = cos(gs), sg = sin(gs);
+    n[g] = 0.5 * (1.0 + cg * cg);
+    const double h = 0.5 * sg * sg, dh = sg * cg;
+    if (jac) jac[(long long)g * ngam + g] = -cg * sg;
+    double prod = 1.0;
+    for (int i = 0; i < ncwo; ++i) {
+      const int p = weak_index(g, i, npairs, ncwo);
+      const bool last = (i == ncwo - 1);
+      const double gi = last ? 0.0 : gamma[npairs + g * (ncwo - 1) + i];
+      const double si2 = last ? 1.0 : sin(gi) * sin(gi);
+      n[p] = h * prod * si2;
+      if (jac) {
+        jac[(long long)p * ngam + g] = dh * prod * si2;
+        // derivative w.r.t. the earlier weak variables j < i (cos^2 factors)
+        for (int j = 0; j < i && j < ncwo - 1; ++j) {
+          const double gj = gamma[npairs + g * (ncwo - 1) + j];
+          double other = h * si2;
+          for (int k = 0; k < i && k < ncwo - 1; ++k) {
+            if (k == j) continue;
+            const double gk = gamma[npairs + g * (ncwo - 1) + k];
+            other *= cos(gk) * cos(gk);
+          }
+          jac[(long long)p * ngam + npairs + g * (ncwo - 1) + j] = other * (-2.0 * cos(gj) * sin(gj));
+        }
+        if (!last) jac[(long long)p * ngam + npairs + g * (ncwo - 1) + i] = h * prod * 2.0 * sin(gi) * cos(gi);
+      }
+      if (!last) prod *= cos(gi) * cos(gi);
+    }
+  }
+}
+
+// dE/dgamma = (dn/dgamma)^T dE/dn, pair by pair.
+__global__ void on_map_vjp_k(int kind, int npairs, int ncwo, const double* __restrict__ gamma,
+                             const double* __restrict__ dEdn, double* __restrict__ out) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= npairs) return;
+  if (kind == 0) {
+    double S = sigm(gamma[g]);
+    for (int k = 0; k < ncwo; ++k) S += sigm(gamma[weak_index(g, k, npairs, ncwo)]);
+    // dE/dgamma_r = s'_r / S * (dEdn_r - sum_p n_p dEdn_p)
+    double avg = 0.0;
+    for (int a = -1; a < ncwo; ++a) {
+      const int p = a < 0 ? g : weak_index(g, a, npairs, ncwo);
+      avg += sigm(gamma[p]) / S * dEdn[p];
+    }
+    for (int b = -1; b < ncwo; ++b) {
+      const int r = b < 0 ? g : weak_index(g, b, npairs, ncwo);
+      const double sr = sigm(gamma[r]);
+      out[r] = sr * (1.0 - sr) / S * (dEdn[r] - avg);
+    }
+  } else {
+    // n_i = h * prod_{k<i} c_k^2 * f_i, f_i = s_i^2 (f = 1 for the last weak orbital),
+    // c_k = cos(gamma_k), s_k = sin(gamma_k) of the pair's weak variables; h = sin^2(gamma_g)/2.
+    const double gs = gamma[g];
+    const double cg = cos(gs), sg = sin(gs);
+    const double h = 0.5 * sg * sg, dh = sg * cg;
+    const int base = npairs + g * (ncwo - 1);
+    double acc_g = -cg * sg * dEdn[g];
+    double prod = 1.0;
+    for (int i = 0; i < ncwo; ++i) {
+      const bool last = (i == ncwo - 1);
+      const double si = last ? 0.0 : sin(gamma[base + i]);
+      const double fi = last ? 1.0 : si * si;
+      acc_g += dh * prod * fi * dEdn[weak_index(g, i, npairs, ncwo)];
+      if (!last) { const double ci = cos(gamma[base + i]); prod *= ci * ci; }
+    }
+    out[g] = acc_g;
+    for (int j = 0; j < ncwo - 1; ++j) {
+      const double cj = cos(gamma[base + j]), sj = sin(gamma[base + j]);
+      double sum = 0.0;
+      for (int i = j; i < ncwo; ++i) {
+        const bool last = (i == ncwo - 1);
+        double other = h;                           // prod over k < i, k != j of c_k^2
+        for (int k = 0; k < i; ++k) {
+          if (k == j) continue;
+          const double ck = cos(gamma[base + k]);
+          other *= ck * ck;
+        }
+        double d;
+        if (i == j) d = other * 2.0 * sj * cj;      // d(s_j^2)
+        else {
+          const double si = last ? 0.0 : sin(gamma[base + i]);
+          d = other * (-2.0 * cj * sj) * (last ? 1.0 : si * si);  // d(c_j^2) * f_i
+        }
+        sum += d * dEdn[weak_index(g, i, npairs, ncwo)];
+      }
+      out[base + j] = sum;
+    }
+  }
+}
+
+// Matrix diagonalised by the orbital step.
+__global__ void build_s_k(int nbf, const double* __restrict__ lam, const double* __restrict__ dprev, double zeta,
+                          double* __restrict__ S) {
+  GRID_STRIDE(i, (long long)nbf * nbf) {
+    const long long p = i / nbf, q = i % nbf;
+    const double a = lam[p * nbf + q], b = lam[q * nbf + p];
+    double v;
+    if (!dprev) v = 0.5 * (a + b);
+    else if (p == q) v = dprev[p];
+    else {
+      v = (p < q) ? (a - b) : (b - a);   // S_pq = lambda_pq - lambda_qp for p < q, mirrored
+      if (zeta > 0.0)
+        while (fabs(v) > zeta) v /= 10.0;
+    }
+    S[i] = v;
+  }
+}
+
+// Column j of the column-major eigenvector matrix: make its largest-|.| entry (lowest index on
+// ties) positive.  One block per column.
+__global__ void sign_fix_k(int nbf, double* __restrict__ U) {
+  const int j = blockIdx.x;
+  double* col = U + (long long)j * nbf;
+  __shared__ double bv[NT];
+  __shared__ int bi[NT];
+  double best = -1.0;
+  int idx = 0;
+  for (int i = threadIdx.x; i < nbf; i += blockDim.x) {
+    const double a = fabs(col[i]);
+    if (a > best) { best = a; idx = i; }
+  }
+  bv[threadIdx.x] = best;
+  bi[threadIdx.x] = idx;
+  __syncthreads();
+  for (int off = NT / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      const double o = bv[threadIdx.x + off];
+      const int oi = bi[threadIdx.x + off];
+      if (o > bv[threadIdx.x] || (o == bv[threadIdx.x] && oi < bi[threadIdx.x])) {
+        bv[threadIdx.x] = o;
+        bi[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  const bool neg = col[bi[0]] < 0.0;
+  __syncthreads();
+  if (neg)
+    for (int i = threadIdx.x; i < nbf; i += blockDim.x) col[i] = -col[i];
+}
+
+__global__ void nonfinite_k(const void* p, long long n, int is_bf16, int* flag) {
+  int bad = 0;
+  GRID_STRIDE(i, n) {
+    double v = is_bf16 ? (double)bf16_bits_to_f32(reinterpret_cast<const u16*>(p)[i])
+                       : reinterpret_cast<const double*>(p)[i];
+    if (!isfinite(v)) bad = 1;
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
+// ---- explicit four-index integrals (nbf <= 64) ----
+// Jr[r][m][n] = sum_ls (mn|ls) C_lr C_sr ; Kr[r][m][n] = sum_ls (ml|ns) C_lr C_sr (Eq. Gpmn).
+__global__ void eri_jk_ao_k(int nbf, int nact, const double* __restrict__ ERI, const double* __restrict__ C,
+                            double* __restrict__ Jr, double* __restrict__ Kr) {
+  const long long n2 = (long long)nbf * nbf;
+  GRID_STRIDE(i, (long long)nact * n2) {
+    const int r = (int)(i / n2);
+    const int m = (int)((i % n2) / nbf), n = (int)(i % nbf);
+    double sj = 0.0, sk = 0.0;
+    for (int l = 0; l < nbf; ++l) {
+      const double cl = C[(long long)l * nbf + r];
+      double tj = 0.0, tk = 0.0;
+      for (int s = 0; s < nbf; ++s) {
+        const double cs = C[(long long)s * nbf + r];
+        tj += ERI[(((long long)m * nbf + n) * nbf + l) * nbf + s] * cs;
+        tk += ERI[(((long long)m * nbf + l) * nbf + n) * nbf + s] * cs;
+      }
+      sj += cl * tj;
+      sk += cl * tk;
+    }
+    Jr[i] = sj;
+    Kr[i] = sk;
+  }
+}
+
+// J_pq = c_p^T J^q c_p, K_pq = c_p^T K^q c_p (Eq. JKpq).
+__global__ void eri_jk_no_k(int nbf, int nact, const double* __restrict__ C, const double* __restrict__ Jr,
+                            const double* __restrict__ Kr, double* __restrict__ J, double* __restrict__ K) {
+  GRID_STRIDE(i, (long long)nact * nact) {
+    const int p = (int)(i / nact), q = (int)(i % nact);
+    const double* Jq = Jr + (long long)q * nbf * nbf;
+    const double* Kq = Kr + (long long)q * nbf * nbf;
+    double sj = 0.0, sk = 0.0;
+    for (int m = 0; m < nbf; ++m) {
+      double tj = 0.0, tk = 0.0;
+      for (int n = 0; n < nbf; ++n) {
+        const double cn = C[(long long)n * nbf + p];
+        tj += Jq[(long long)m * nbf + n] * cn;
+        tk += Kq[(long long)m * nbf + n] * cn;
+      }
+      const double cm = C[(long long)m * nbf + p];
+      sj += cm * tj;
+      sk += cm * tk;
+    }
+    J[i] = sj;
+    K[i] = sk;
+  }
+}
+
+// Y2e[m][q] = sum_r (alpha_qr J^r + beta_qr K^r) c_q.
+__global__ void eri_y_k(int nbf, int nact, const double* __restrict__ C, const double* __restrict__ alpha,
+                        const double* __restrict__ beta, const double* __restrict__ Jr,
+                        const double* __restrict__ Kr, double* __restrict__ Y2e) {
+  GRID_STRIDE(i, (long long)nbf * nact) {
+    const int m = (int)(i / nact), q = (int)(i % nact);
+    double s = 0.0;
+    for (int r = 0; r < nact; ++r) {
+      const double a = alpha[(long long)q * nact + r], b = beta[(long long)q * nact + r];
+      const double* Jm = Jr + ((long long)r * nbf + m) * nbf;
+      const double* Km = Kr + ((long long)r * nbf + m) * nbf;
+      double tj = 0.0, tk = 0.0;
+      for (int n = 0; n < nbf; ++n) {
+        const double cn = C[(long long)n * nbf + q];
+        tj += Jm[n] * cn;
+        tk += Km[n] * cn;
+      }
+      s += a * tj + b * tk;
+    }
+    Y2e[i] = s;
+  }
+}
+
+__global__ void gather_ao_k(int nbf, int nq, const int32_t* __restrict__ q_idx, const double* __restrict__ src,
+                            double* __restrict__ dst) {
+  const long long n2 = (long long)nbf * nbf;
+  GRID_STRIDE(i, (long long)nq * n2) {
+    const int k = (int)(i / n2);
+    dst[i] = src[(long long)q_idx[k] * n2 + i % n2];
+  }
+}
+
+__global__ void eri_fock_ao_k(int nbf, int nact, int nq, const int32_t* __restrict__ q_idx,
+                              const double* __restrict__ n, const double* __restrict__ H,
+                              const double* __restrict__ alpha, const double* __restrict__ beta,
+                              const double* __restrict__ Jr, const double* __restrict__ Kr,
+                              double* __restrict__ Fq) {
+  const long long n2 = (long long)nbf * nbf;
+  GRID_STRIDE(i, (long long)nq * n2) {
+    const int k = (int)(i / n2);
+    const long long e = i % n2;
+    const int q = q_idx[k];
+    double s = n[q] * H[e];
+    for (int r = 0; r < nact; ++r)
+      s += alpha[(long long)q * nact + r] * Jr[(long long)r * n2 + e] + beta[(long long)q * nact + r] * Kr[(long long)r * n2 + e];
+    Fq[i] = s;
+  }
+}
+
+__global__ void fock_ao_h_k(int nbf, int nq, const int32_t* __restrict__ q_idx, const double* __restrict__ n,
+                            const double* __restrict__ H, double* __restrict__ Fq) {
+  const long long n2 = (long long)nbf * nbf;
+  GRID_STRIDE(i, (long long)nq * n2) {
+    const int k = (int)(i / n2);
+    Fq[i] += n[q_idx[k]] * H[i % n2];
+  }
+}
+
+// Per-orbital AO matrices from one P-chunk:  J^q += sum_P D_Pq B_P,  K^q += sum_P x_Pq x_Pq^T,
+// F^q += sum_P [d_Pq B_P + sum_r beta_qr x_Pr x_Pr^T]  with x_Pr[mu] = XT[P][r][mu].
+__device__ inline double xt_val(const double* XT, const u16* xh, const u16* xl, long long o) {
+  if (XT) return XT[o];
+  double v = (double)bf16_bits_to_f32(xh[o]);
+  if (xl) v += (double)bf16_bits_to_f32(xl[o]);
+  return v;
+}
+
+__global__ void df_ao_accum_k(int nbf, int nact, int np, int nq, const int32_t* __restrict__ q_idx,
+                              const void* __restrict__ Bc, int b_bf16, const double* __restrict__ Dc,
+                              const double* __restrict__ alpha, const double* __restrict__ beta,
+                              const double* __restrict__ XT, const u16* __restrict__ xh,
+                              const u16* __restrict__ xl, int ldx, double* __restrict__ Jq,
+                              double* __restrict__ Kq, double* __restrict__ Fq) {
+  const long long n2 = (long long)nbf * nbf;
+  GRID_STRIDE(i, (long long)nq * n2) {
+    const int k = (int)(i / n2);
+    const long long e = i % n2;
+    const int m = (int)(e / nbf), nn = (int)(e % nbf);
+    const int q = q_idx[k];
+    double sj = 0.0, sk = 0.0, sf = 0.0;
+    for (int P = 0; P < np; ++P) {
+      const long long bo = (long long)P * n2 + e;
+      const double b = b_bf16 ? (double)bf16_bits_to_f32(reinterpret_cast<const u16*>(Bc)[bo])
+                              : reinterpret_cast<const double*>(Bc)[bo];
+      const double* Dp = Dc + (long long)P * nact;
+      const long long xo = (long long)P * nact * ldx;
+      sj += Dp[q] * b;
+      const double xm = xt_val(XT, xh, xl, xo + (long long)q * ldx + m);
+      const double xn = xt_val(XT, xh, xl, xo + (long long)q * ldx + nn);
+      sk += xm * xn;
+      if (Fq) {
+        double d = 0.0, kk = 0.0;
+        for (int r = 0; r < nact; ++r) {
+          d += alpha[(long long)q * nact + r] * Dp[r];
+          kk += beta[(long long)q * nact + r] * xt_val(XT, xh, xl, xo + (long long)r * ldx + m) *
+                xt_val(XT, xh, xl, xo + (long long)r * ldx + nn);
+        }
+        sf += d * b + kk;
+      }
+    }
+    if (Jq) Jq[i] += sj;
+    if (Kq) Kq[i] += sk;
+    if (Fq) Fq[i] += sf;
+  }
+}
+
+}  // namespace
+
+#define LAUNCH(kern, grid, block, ...)                              \
+  do {                                                              \
+    hipLaunchKernelGGL(kern, grid, block, 0, s, __VA_ARGS__);       \
+    return hipGetLastError();                                       \
+  } while (0)
+
+hipError_t fill_f64(hipStream_t s, double* p, long long n, double v) {
+  if (n <= 0) return hipSuccess;
+  LAUNCH(fill_f64_k, grid1(n), dim3(NT), p, n, v);
+}
+hipError_t fill_u16(hipStream_t s, u16* p, long long n, u16 v) {
+  if (n <= 0) return hipSuccess;
+  LAUNCH(fill_u16_k, grid1(n), dim3(NT), p, n, v);
+}
+hipError_t coeffs(hipStream_t s, int nact, int npairs, int ncwo, int functional, const double* n,
+                  double* alpha, double* beta, float* beta32) {
+  LAUNCH(coeffs_k, grid1((long long)nact * nact), dim3(NT), nact, npairs, ncwo, functional, n, alpha, beta, beta32);
+}
+hipError_t transpose_ca(hipStream_t s, int nbf, int nact, const double* C, double* Ct, int ldk) {
+  LAUNCH(transpose_ca_k, grid1((long long)nbf * nact), dim3(NT), nbf, nact, C, Ct, ldk);
+}
+hipError_t split_ca(hipStream_t s, int nbf, int nact, int terms, const double* C, u16* hi, u16* lo, int ldk) {
+  LAUNCH(split_ca_k, grid1((long long)nbf * nact), dim3(NT), nbf, nact, terms, C, hi, lo, ldk);
+}
+hipError_t split_b(hipStream_t s, long long n, const double* B, u16* hi, u16* lo) {
+  if (n <= 0) return hipSuccess;
+  LAUNCH(split_b_k, grid1(n), dim3(NT), n, B, hi, lo);
+}
+hipError_t hpp_from_hc(hipStream_t s, int nbf, int nact, const double* C, const double* HC, double* Hpp) {
+  LAUNCH(hpp_k, dim3(nact), dim3(64), nbf, nact, C, HC, Hpp);
+}
+hipError_t add_diag_f64(hipStream_t s, int nact, int np, const double* Dc, const double* alpha, double* W, int ldw) {
+  if (np <= 0) return hipSuccess;
+  LAUNCH(add_diag_f64_k, grid1((long long)np * nact), dim3(NT), nact, np, Dc, alpha, W, ldw);
+}
+hipError_t add_diag_bf16(hipStream_t s, int nact, int np, const double* Dc, const double* alpha, u16* Wh,
+                         u16* Wl, int ldw) {
+  if (np <= 0) return hipSuccess;
+  LAUNCH(add_diag_bf16_k, grid1((long long)np * nact), dim3(NT), nact, np, Dc, alpha, Wh, Wl, ldw);
+}
+hipError_t reduce_k(hipStream_t s, int nact, int nsplit, const double* Kpart, double* K) {
+  LAUNCH(reduce_k_k, grid1((long long)nact * nact), dim3(NT), nact, nsplit, Kpart, K);
+}
+hipError_t reduce_y_f64(hipStream_t s, long long n, int nsplit, const double* Yp, double* Y) {
+  LAUNCH(reduce_y_k<double>, grid1(n), dim3(NT), n, nsplit, Yp, Y);
+}
+hipError_t reduce_y_f32(hipStream_t s, long long n, int nsplit, const float* Yp, double* Y) {
+  LAUNCH(reduce_y_k<float>, grid1(n), dim3(NT), n, nsplit, Yp, Y);
+}
+hipError_t energy(hipStream_t s, int nbf, int nact, const double* n, const double* Hpp,
+                  const double* alpha, const double* beta, const double* J, const double* K,
+                  const double* Y2e, const double* C, const u16* cth, const u16* ctl, int ldk,
+                  int corr_terms, double* partials, double* E) {
+  const int nb = 256;
+  hipLaunchKernelGGL(energy_stage1_k, dim3(nb), dim3(NT), 0, s, nbf, nact, n, Hpp, alpha, beta, J, K, Y2e,
+                     C, cth, ctl, ldk, corr_terms, partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  LAUNCH(sum_partials_k, dim3(1), dim3(NT), nb, partials, E);
+}
+hipError_t assemble_y(hipStream_t s, int nbf, int nact, const double* n, const double* HC, const double* Y2e,
+                      double* Y) {
+  LAUNCH(assemble_y_k, grid1((long long)nbf * nact), dim3(NT), nbf, nact, n, HC, Y2e, Y);
+}
+hipError_t grad_c(hipStream_t s, int nbf, int nact, const double* Y, double* G) {
+  LAUNCH(grad_c_k, grid1((long long)nbf * nbf), dim3(NT), nbf, nact, Y, G);
+}
+hipError_t zero_cols(hipStream_t s, int nbf, int col0, double* M) {
+  if (col0 >= nbf) return hipSuccess;
+  LAUNCH(zero_cols_k, grid1((long long)nbf * (nbf - col0)), dim3(NT), nbf, col0, M);
+}
+hipError_t max_asym(hipStream_t s, int nbf, const double* lam, double* partials, double* out) {
+  const int nb = 256;
+  hipLaunchKernelGGL(asym_stage1_k, dim3(nb), dim3(NT), 0, s, nbf, lam, partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  LAUNCH(max_partials_k, dim3(1), dim3(NT), nb, partials, out);
+}
+hipError_t grad_n(hipStream_t s, int nact, int npairs, int ncwo, int functional, const double* n,
+                  const double* Hpp, const double* J, const double* K, double* dEdn) {
+  LAUNCH(grad_n_k, dim3(nact), dim3(64), nact, npairs, ncwo, functional, n, Hpp, J, K, dEdn);
+}
+hipError_t on_map(hipStream_t s, int kind, int npairs, int ncwo, const double* gamma, double* n, double* jac) {
+  LAUNCH(on_map_k, dim3(cdiv(npairs, 64)), dim3(64), kind, npairs, ncwo, gamma, n, jac);
+}
+hipError_t on_map_vjp(hipStream_t s, int kind, int npairs, int ncwo, const double* gamma, const double* dEdn,
+                      double* out) {
+  LAUNCH(on_map_vjp_k, dim3(cdiv(npairs, 64)), dim3(64), kind, npairs, ncwo, gamma, dEdn, out);
+}
+hipError_t build_s(hipStream_t s, int nbf, const double* lam, const double* dprev, double zeta, double* S) {
+  LAUNCH(build_s_k, grid1((long long)nbf * nbf), dim3(NT), nbf, lam, dprev, zeta, S);
+}
+hipError_t sign_fix_cols(hipStream_t s, int nbf, double* U) {
+  LAUNCH(sign_fix_k, dim3(nbf), dim3(NT), nbf, U);
+}
+hipError_t count_nonfinite(hipStream_t s, const void* p, long long n, int is_bf16, int* flag) {
+  if (n <= 0) return hipSuccess;
+  LAUNCH(nonfinite_k, grid1(n), dim3(NT), p, n, is_bf16, flag);
+}
+hipError_t eri_jk_ao(hipStream_t s, int nbf, int nact, const double* ERI, const double* C, double* Jr, double* Kr) {
+  LAUNCH(eri_jk_ao_k, grid1((long long)nact * nbf * nbf), dim3(NT), nbf, nact, ERI, C, Jr, Kr);
+}
+hipError_t eri_jk_no(hipStream_t s, int nbf, int nact, const double* C, const double* Jr, const double* Kr,
+                     double* J, double* K) {
+  LAUNCH(eri_jk_no_k, grid1((long long)nact * nact), dim3(NT), nbf, nact, C, Jr, Kr, J, K);
+}
+hipError_t eri_y(hipStream_t s, int nbf, int nact, const double* C, const double* /*n*/, const double* /*HC*/,
+                 const double* alpha, const double* beta, const double* Jr, const double* Kr, double* Y2e) {
+  LAUNCH(eri_y_k, grid1((long long)nbf * nact), dim3(NT), nbf, nact, C, alpha, beta, Jr, Kr, Y2e);
+}
+hipError_t gather_ao(hipStream_t s, int nbf, int nq, const int32_t* q_idx, const double* src, double* dst) {
+  if (nq <= 0) return hipSuccess;
+  LAUNCH(gather_ao_k, grid1((long long)nq * nbf * nbf), dim3(NT), nbf, nq, q_idx, src, dst);
+}
+hipError_t eri_fock_ao(hipStream_t s, int nbf, int nact, int nq, const int32_t* q_idx, const double* n,
+                       const double* H, const double* alpha, const double* beta, const double* Jr,
+                       const double* Kr, double* Fq) {
+  if (nq <= 0) return hipSuccess;
+  LAUNCH(eri_fock_ao_k, grid1((long long)nq * nbf * nbf), dim3(NT), nbf, nact, nq, q_idx, n, H, alpha, beta, Jr, Kr, Fq);
+}
+hipError_t df_ao_accum(hipStream_t s, int nbf, int nact, int np, int nq, const int32_t* q_idx,
+                       const void* Bchunk, int b_is_bf16, const double* Dchunk, const double* alpha,
+                       const double* beta, const double* XT, const u16* XT_hi, const u16* XT_lo, int ldx,
+                       double* Jq, double* Kq, double* Fq) {
+  if (nq <= 0 || np <= 0) return hipSuccess;
+  LAUNCH(df_ao_accum_k, grid1((long long)nq * nbf * nbf), dim3(NT), nbf, nact, np, nq, q_idx, Bchunk,
+         b_is_bf16, Dchunk, alpha, beta, XT, XT_hi, XT_lo, ldx, Jq, Kq, Fq);
+}
+hipError_t fock_ao_h(hipStream_t s, int nbf, int nq, const int32_t* q_idx, const double* n, const double* H,
+                     double* Fq) {
+  if (nq <= 0) return hipSuccess;
+  LAUNCH(fock_ao_h_k, grid1((long long)nq * nbf * nbf), dim3(NT), nbf, nq, q_idx, n, H, Fq);
+}
+
+}  // namespace pnof
+
+namespace pnof {
+namespace {
+__global__ void widen_bf16_k(long long n, const u16* __restrict__ src, double* __restrict__ dst) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    dst[i] = (double)bf16_bits_to_f32(src[i]);
+}
+}  // namespace
+hipError_t widen_bf16(hipStream_t s, long long n, const u16* src, double* dst) {
+  if (n <= 0) return hipSuccess;
+  long long b = (n + 255) / 256;
+  if (b > 65535LL * 16) b = 65535LL * 16;
+  hipLaunchKernelGGL(widen_bf16_k, dim3((unsigned)b), dim3(256), 0, s, n, src, dst);
+  return hipGetLastError();
+}
+}  // namespace pnof

@@ -1,0 +1,317 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances: float64 path |dE| <= 1e-8 Ha (the paper's global energy threshold) and lambda to
+1e-10; bf16-split path |dE| <= 1e-6 Ha and lambda / J / K well below the symmetry threshold
+delta = 1e-4 of the orbital optimisation (asserted at 2e-5).
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import pnof, stream
+
+P = pytest.importorskip("paper_2004_06142_amd")
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda", 0)
+
+
+def t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def h(x):
+    return x.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return P.Context(0)
+
+
+def _ints(inst, kind):
+    if kind == P.INTS_ERI4_F64:
+        return t(inst.ERI)
+    if kind == P.INTS_DF_F64:
+        return t(inst.B)
+    return t(inst.B).to(torch.bfloat16)      # exact: the values are bf16-rounded already
+
+
+def _case(name, nbf, naux, npairs, ncwo, dtype="f64", seed=1):
+    return synth.make(synth.Workload(name, nbf, naux, npairs, ncwo, dtype), seed)
+
+
+def _ref(inst, func):
+    wl = inst.wl
+    n = pnof.on_sigmoid(inst.gamma, wl.npairs, wl.ncwo)
+    r = stream.lagrangian(inst.C, n, inst.H, inst.B, wl.npairs, wl.ncwo, func)
+    return n, r
+
+
+# ------------------------------------------------------------------------------ explicit integrals
+@pytest.mark.parametrize("func", [P.PNOF5, P.PNOF7, P.PNOF7S])
+def test_eri4_workload_parity(ctx, func):
+    inst = synth.workload("c1_eri24")
+    wl = inst.wl
+    n = pnof.on_sigmoid(inst.gamma, wl.npairs, wl.ncwo)
+    prob = P.problem(wl.nbf, 0, wl.npairs, wl.ncwo, func, P.FP64, P.INTS_ERI4_F64)
+    out = ctx.lagrangian(prob, t(inst.C), t(n), t(inst.H), t(inst.ERI), jk=True)
+    F = pnof.fock_ao(inst.C, n, inst.H, inst.ERI, wl.npairs, wl.ncwo, func, kind="eri")
+    lam = pnof.lagrangian(inst.C, F)
+    J, K = pnof.jk_no(inst.ERI, inst.C, wl.nact, "eri")
+    e = pnof.energy_from_jk(n, pnof.h_no(inst.C, inst.H, wl.nact), J, K, wl.npairs, wl.ncwo, func)
+    assert abs(out["E"].item() - e) < 1e-10
+    assert np.max(np.abs(h(out["lam"]) - lam)) < 1e-11
+    assert np.max(np.abs(h(out["J"]) - J)) < 1e-12 and np.max(np.abs(h(out["K"]) - K)) < 1e-12
+    assert np.max(np.abs(h(out["dEdC"]) - pnof.grad_C(inst.C, F))) < 1e-10
+    hpp = pnof.h_no(inst.C, inst.H, wl.nact)
+    assert np.max(np.abs(h(out["dEdn"]) - pnof.grad_n(n, hpp, J, K, wl.npairs, wl.ncwo, func))) < 1e-10
+    assert abs(out["max_asym"].item() - pnof.max_asym(lam)) < 1e-11
+
+
+def test_eri4_equals_df_route(ctx):
+    inst = synth.workload("c1_eri24")
+    wl = inst.wl
+    n = pnof.on_sigmoid(inst.gamma, wl.npairs, wl.ncwo)
+    pe = P.problem(wl.nbf, 0, wl.npairs, wl.ncwo, P.PNOF7, P.FP64, P.INTS_ERI4_F64)
+    pd = P.problem(wl.nbf, wl.naux, wl.npairs, wl.ncwo, P.PNOF7, P.FP64, P.INTS_DF_F64)
+    a = ctx.lagrangian(pe, t(inst.C), t(n), t(inst.H), t(inst.ERI))
+    b = ctx.lagrangian(pd, t(inst.C), t(n), t(inst.H), t(inst.B))
+    assert abs(a["E"].item() - b["E"].item()) < 1e-11
+    assert np.max(np.abs(h(a["lam"]) - h(b["lam"]))) < 1e-11
+
+
+# ------------------------------------------------------------------------------ density fitting
+SHAPES = [
+    ("c2_df200", 200, 800, 20, 4),
+    ("ragged77", 77, 51, 7, 3),           # nbf not a multiple of 8: unaligned bf16 rows
+    ("all_active", 60, 37, 6, 9),         # nact == nbf
+    ("one_pair", 9, 5, 1, 1),             # smallest pairing problem
+    ("tall_aux", 130, 300, 13, 4),        # several tiles and a ragged tail
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=[s[0] for s in SHAPES])
+@pytest.mark.parametrize("prec", [P.FP64, P.BF16_SPLIT], ids=["fp64", "bf16split"])
+@pytest.mark.parametrize("bdt", ["f64", "bf16"])
+def test_df_parity(ctx, shape, prec, bdt):
+    name, nbf, naux, npairs, ncwo = shape
+    inst = _case(name, nbf, naux, npairs, ncwo, bdt)
+    wl = inst.wl
+    kind = P.INTS_DF_F64 if bdt == "f64" else P.INTS_DF_BF16
+    n, ref = _ref(inst, pnof.PNOF7)
+    prob = P.problem(nbf, naux, npairs, ncwo, P.PNOF7, prec, kind)
+    out = ctx.lagrangian(prob, t(inst.C), t(n), t(inst.H), _ints(inst, kind), jk=True)
+    dE = abs(out["E"].item() - ref["E"])
+    dlam = np.max(np.abs(h(out["lam"]) - ref["lam"]))
+    dJ = np.max(np.abs(h(out["J"]) - ref["J"]))
+    dK = np.max(np.abs(h(out["K"]) - ref["K"]))
+    dG = np.max(np.abs(h(out["dEdC"]) - ref["dEdC"]))
+    print(f"{name} prec={prec} B={bdt}: dE={dE:.2e} dlam={dlam:.2e} dJ={dJ:.2e} dK={dK:.2e} dG={dG:.2e}")
+    if prec == P.FP64:
+        assert dE < 1e-8 and dlam < 1e-10 and dJ < 1e-12 and dK < 1e-12 and dG < 1e-9
+    else:
+        # float64 B is itself carried as a bf16 pair, whose third-slice residual is not corrected
+        assert dE < 1e-6 and dlam < 2e-5 and dJ < 2e-5 and dK < 2e-5
+    hpp = ref["Hpp"]
+    assert np.max(np.abs(h(out["dEdn"]) - pnof.grad_n(n, hpp, ref["J"], ref["K"], npairs, ncwo, pnof.PNOF7))) < (
+        1e-9 if prec == P.FP64 else 1e-4)
+
+
+@pytest.mark.parametrize("func", [P.PNOF5, P.PNOF7S])
+def test_df_functionals(ctx, func):
+    inst = _case("func", 70, 90, 5, 3)
+    n, ref = _ref(inst, func)
+    prob = P.problem(70, 90, 5, 3, func, P.FP64, P.INTS_DF_F64)
+    out = ctx.lagrangian(prob, t(inst.C), t(n), t(inst.H), t(inst.B))
+    assert abs(out["E"].item() - ref["E"]) < 1e-9
+    assert np.max(np.abs(h(out["lam"]) - ref["lam"])) < 1e-10
+
+
+def test_bf16_single_pass_is_coarser(ctx):
+    """The one-pass bf16 mode exists for the error study: it must be markedly worse than split."""
+    inst = _case("c2ish", 200, 800, 20, 4, "bf16")
+    n, ref = _ref(inst, pnof.PNOF7)
+    errs = {}
+    for prec in (P.BF16, P.BF16_SPLIT):
+        prob = P.problem(200, 800, 20, 4, P.PNOF7, prec, P.INTS_DF_BF16)
+        out = ctx.lagrangian(prob, t(inst.C), t(n), t(inst.H), _ints(inst, P.INTS_DF_BF16))
+        errs[prec] = abs(out["E"].item() - ref["E"])
+    print(errs)
+    assert errs[P.BF16_SPLIT] < 1e-6 < errs[P.BF16]
+
+
+@pytest.mark.parametrize("pc", [1, 7, 0])
+def test_pchunk_invariance(ctx, pc):
+    inst = _case("chunks", 64, 45, 4, 3)
+    n, ref = _ref(inst, pnof.PNOF7)
+    prob = P.problem(64, 45, 4, 3, P.PNOF7, P.FP64, P.INTS_DF_F64)
+    ctx.set_pchunk(pc)
+    try:
+        out = ctx.lagrangian(prob, t(inst.C), t(n), t(inst.H), t(inst.B))
+    finally:
+        ctx.set_pchunk(0)
+    assert abs(out["E"].item() - ref["E"]) < 1e-10
+
+
+def test_determinism(ctx):
+    inst = _case("det", 150, 200, 10, 4, "bf16")
+    n, _ = _ref(inst, pnof.PNOF7)
+    prob = P.problem(150, 200, 10, 4, P.PNOF7, P.BF16_SPLIT, P.INTS_DF_BF16)
+    B = _ints(inst, P.INTS_DF_BF16)
+    a = ctx.lagrangian(prob, t(inst.C), t(n), t(inst.H), B)
+    b = ctx.lagrangian(prob, t(inst.C), t(n), t(inst.H), B)
+    for k in ("E", "lam", "dEdC", "dEdn"):
+        assert torch.equal(a[k], b[k]), k
+
+
+def test_energy_and_fock_entry_points(ctx):
+    inst = _case("entry", 50, 60, 4, 2)
+    wl = inst.wl
+    n, ref = _ref(inst, pnof.PNOF7)
+    for prec in (P.FP64, P.BF16_SPLIT):
+        prob = P.problem(50, 60, 4, 2, P.PNOF7, prec, P.INTS_DF_F64)
+        E = ctx.energy(prob, t(inst.C), t(n), t(inst.H), t(inst.B))
+        Y = ctx.fock(prob, t(inst.C), t(n), t(inst.H), t(inst.B))
+        tol = 1e-9 if prec == P.FP64 else 1e-6
+        assert abs(E.item() - ref["E"]) < tol
+        assert np.max(np.abs(h(Y) - ref["Y"])) < (1e-10 if prec == P.FP64 else 2e-5)
+
+
+@pytest.mark.parametrize("prec", [P.FP64, P.BF16_SPLIT])
+def test_per_orbital_ao_matrices(ctx, prec):
+    inst = _case("ao", 20, 30, 3, 2)
+    wl = inst.wl
+    n = pnof.on_sigmoid(inst.gamma, 3, 2)
+    q = [0, 4, 8]
+    prob = P.problem(20, 30, 3, 2, P.PNOF7, prec, P.INTS_DF_F64)
+    J, K, Jq, Kq = ctx.jk(prob, t(inst.C), t(inst.B), q_idx=q)
+    Y, Fq = ctx.fock(prob, t(inst.C), t(n), t(inst.H), t(inst.B), q_idx=q)
+    F = pnof.fock_ao(inst.C, n, inst.H, inst.B, 3, 2, pnof.PNOF7)
+    tol = 1e-12 if prec == P.FP64 else 1e-5
+    for i, qq in enumerate(q):
+        Jr, Kr = pnof.jk_ao_df(inst.B, inst.C, qq)
+        assert np.max(np.abs(h(Jq[i]) - Jr)) < tol
+        assert np.max(np.abs(h(Kq[i]) - Kr)) < tol
+        assert np.max(np.abs(h(Fq[i]) - F[qq])) < tol * 10
+    # the explicit-integral route gives the same matrices
+    ERI = pnof.eri_from_df(inst.B)
+    pe = P.problem(20, 0, 3, 2, P.PNOF7, P.FP64, P.INTS_ERI4_F64)
+    J2, K2, Jq2, Kq2 = ctx.jk(pe, t(inst.C), t(ERI), q_idx=q)
+    _, Fq2 = ctx.fock(pe, t(inst.C), t(n), t(inst.H), t(ERI), q_idx=q)
+    for i, qq in enumerate(q):
+        assert np.max(np.abs(h(Jq2[i]) - pnof.jk_ao_df(inst.B, inst.C, qq)[0])) < 1e-12
+        assert np.max(np.abs(h(Fq2[i]) - F[qq])) < 1e-11
+
+
+# ------------------------------------------------------------------------------ ON maps
+@pytest.mark.parametrize("kind", [P.ON_SIGMOID, P.ON_TRIG])
+def test_on_map_and_adjoint(ctx, kind):
+    npairs, ncwo = 7, 4
+    rng = np.random.default_rng(3)
+    if kind == P.ON_SIGMOID:
+        gam = rng.standard_normal(npairs * (ncwo + 1))
+        nf, jf = pnof.on_sigmoid, pnof.on_sigmoid_jac
+    else:
+        gam = rng.uniform(-2, 2, npairs * ncwo)
+        nf, jf = pnof.on_trig, pnof.on_trig_jac
+    n, jac = ctx.on_map(t(gam), npairs, ncwo, kind, jacobian=True)
+    assert np.max(np.abs(h(n) - nf(gam, npairs, ncwo))) < 1e-15
+    assert np.max(np.abs(h(jac) - jf(gam, npairs, ncwo))) < 1e-14
+    g = rng.standard_normal(npairs * (ncwo + 1))
+    v = ctx.on_map_vjp(t(gam), t(g), npairs, ncwo, kind)
+    assert np.max(np.abs(h(v) - jf(gam, npairs, ncwo).T @ g)) < 1e-13
+
+
+# ------------------------------------------------------------------------------ orbital step
+def _eig_compare(eps, eps_ref, Cn, C, S_ref):
+    assert np.max(np.abs(eps - eps_ref)) < 1e-10
+    U = C.T @ Cn
+    assert np.max(np.abs(U.T @ U - np.eye(len(eps)))) < 1e-12
+    assert np.max(np.abs(S_ref @ U - U * eps[None, :])) < 1e-9
+
+
+def test_orbital_step_symmetrised(ctx):
+    inst = _case("orb", 120, 150, 10, 3)
+    n, ref = _ref(inst, pnof.PNOF7)
+    Cn, eps, S = ctx.orbital_step(t(ref["lam"]), t(inst.C), want_s=True)
+    Cr, eps_r, Sr = pnof.orbital_step(ref["lam"], inst.C)
+    assert np.array_equal(h(S), Sr)
+    _eig_compare(h(eps), eps_r, h(Cn), inst.C, Sr)
+    # eigenvalues of clusters with a gap > 1e-8 identify columns up to sign; the sign is fixed
+    gaps = np.diff(eps_r)
+    iso = [j for j in range(len(eps_r)) if (j == 0 or gaps[j - 1] > 1e-6) and (j == len(eps_r) - 1 or gaps[j] > 1e-6)]
+    assert np.max(np.abs(h(Cn)[:, iso] - Cr[:, iso])) < 1e-8
+
+
+def test_orbital_step_fockian_zeta(ctx):
+    inst = _case("orbF", 40, 60, 4, 3)
+    n, ref = _ref(inst, pnof.PNOF7)
+    diag = np.sort(np.random.default_rng(2).uniform(-3, 1, 40))
+    Cn, eps, S = ctx.orbital_step(t(ref["lam"]), t(inst.C), t(diag), zeta=0.01, want_s=True)
+    Cr, eps_r, Sr = pnof.orbital_step(ref["lam"], inst.C, diag_prev=diag, zeta=0.01)
+    assert np.array_equal(h(S), Sr)        # division by ten is correctly rounded on both sides
+    _eig_compare(h(eps), eps_r, h(Cn), inst.C, Sr)
+
+
+def test_orbital_step_degenerate_eri_workload(ctx):
+    """nbf > 2 nact: the symmetrised Lagrangian has exactly nbf - 2 nact zero eigenvalues."""
+    inst = synth.workload("c1_eri24")
+    wl = inst.wl
+    n = pnof.on_sigmoid(inst.gamma, wl.npairs, wl.ncwo)
+    F = pnof.fock_ao(inst.C, n, inst.H, inst.ERI, wl.npairs, wl.ncwo, pnof.PNOF7, kind="eri")
+    lam = pnof.lagrangian(inst.C, F)
+    Cn, eps = ctx.orbital_step(t(lam), t(inst.C))
+    Cr, eps_r, Sr = pnof.orbital_step(lam, inst.C)
+    assert np.sum(np.abs(eps_r) < 1e-12) == wl.nbf - 2 * wl.nact
+    _eig_compare(h(eps), eps_r, h(Cn), inst.C, Sr)
+    # projector onto the degenerate null cluster agrees
+    z = np.abs(eps_r) < 1e-10
+    Pg = h(Cn)[:, z] @ h(Cn)[:, z].T
+    Pr = Cr[:, z] @ Cr[:, z].T
+    assert np.max(np.abs(Pg - Pr)) < 1e-9
+    # the energy at the new orbitals is the same (sign-invariant quantity)
+    e1 = pnof.energy(h(Cn), n, inst.H, inst.ERI, wl.npairs, wl.ncwo, pnof.PNOF7, kind="eri")
+    e2 = pnof.energy(Cr, n, inst.H, inst.ERI, wl.npairs, wl.ncwo, pnof.PNOF7, kind="eri")
+    assert abs(e1 - e2) < 1e-10
+
+
+# ------------------------------------------------------------------------------ autograd
+def test_autograd_function_gradients(ctx):
+    inst = _case("ag", 40, 50, 3, 3)
+    wl = inst.wl
+    prob = P.problem(40, 50, 3, 3, P.PNOF7, P.FP64, P.INTS_DF_F64)
+    C = t(inst.C).requires_grad_(True)
+    g = t(inst.gamma).requires_grad_(True)
+    E = P.PNOFEnergy.apply(C, g, t(inst.H), t(inst.B), prob, ctx)
+    (2.0 * E).backward()
+    n = pnof.on_sigmoid(inst.gamma, 3, 3)
+    ref = stream.lagrangian(inst.C, n, inst.H, inst.B, 3, 3, pnof.PNOF7)
+    dg = pnof.on_sigmoid_jac(inst.gamma, 3, 3).T @ ref["dEdn"]
+    assert abs(E.item() - ref["E"]) < 1e-10
+    assert np.max(np.abs(h(C.grad) - 2 * ref["dEdC"])) < 1e-10
+    assert np.max(np.abs(h(g.grad) - 2 * dg)) < 1e-10
+
+
+# ------------------------------------------------------------------------------ errors
+def test_error_paths(ctx):
+    inst = _case("err", 30, 20, 2, 2)
+    n = pnof.on_sigmoid(inst.gamma, 2, 2)
+    bad = P.problem(30, 20, 20, 2)                # nact > nbf
+    with pytest.raises(P.PnofError) as e:
+        P.pnof_energy(ctx, bad, t(inst.C), t(n), t(inst.H), t(inst.B), t(np.zeros(1)))
+    assert e.value.status == 2
+    ok = P.problem(30, 20, 2, 2, flags=P.CHECK_FINITE)
+    Bn = inst.B.copy()
+    Bn[3, 1, 2] = np.nan
+    with pytest.raises(P.PnofError) as e:
+        ctx.energy(ok, t(inst.C), t(n), t(inst.H), t(Bn))
+    assert e.value.status == 6
+    with pytest.raises(P.PnofError) as e:
+        ctx.energy(P.problem(30, 20, 2, 2, precision=1), t(inst.C), t(n), t(inst.H), t(inst.B))
+    assert e.value.status == 1
+    # the context still works after errors
+    assert np.isfinite(ctx.energy(P.problem(30, 20, 2, 2), t(inst.C), t(n), t(inst.H), t(inst.B)).item())
