@@ -33,7 +33,7 @@ def parse():
     ap.add_argument("--workload", default="c5_df1200")
     ap.add_argument("--precision", default="bf16split", choices=["bf16split", "fp64", "bf16"])
     ap.add_argument("--fp64-steps", type=int, default=1, help="steps of the float64 path for the speedup (0: skip)")
-    ap.add_argument("--cpu-rows", type=int, default=192, help="rows of B in the oracle's timed sample (0: skip)")
+    ap.add_argument("--cpu-rows", type=int, default=384, help="rows of B in the oracle's timed sample (0: skip)")
     ap.add_argument("--pchunk", type=int, default=0)
     return ap.parse_args()
 

@@ -144,13 +144,15 @@ Plan make_plan(const pnof_problem* p, int pchunk_override) {
   pl.ldw = (int)round_up(pl.nact, 8);
   if (!is_df(p->ints)) { pl.pc = pl.ns2 = pl.ns3 = 1; return pl; }
   const long long t1 = (long long)cdiv(pl.nact, tile) * cdiv(pl.nbf, tile);
-  long long pc = pchunk_override > 0 ? pchunk_override : std::max(1LL, (2048 + t1 - 1) / t1);
+  // enough blocks per launch to fill the chip, and enough rows per chunk that the per-split K
+  // partials (ns2 x nact^2, read-modified-written once per chunk) stay small next to X and W
+  long long pc = pchunk_override > 0 ? pchunk_override : std::max(64LL, (4096 + t1 - 1) / t1);
   // keep the per-chunk buffers modest
   const long long per_p = pl.split ? (long long)(2 * pl.nact * pl.ldx + 2 * pl.nbf * pl.ldxx + 2 * pl.nact * pl.ldw) * 2 +
                                          (p->ints == PNOF_INTS_DF_F64 ? 4LL * pl.nbf * pl.nbf : 0)
                                    : (long long)(pl.nact * pl.ldx + pl.nact * pl.ldw) * 8 +
                                          (p->ints == PNOF_INTS_DF_BF16 ? 8LL * pl.nbf * pl.nbf : 0);
-  const long long cap = std::max(1LL, (1LL << 30) / std::max(1LL, per_p));
+  const long long cap = std::max(1LL, (2LL << 30) / std::max(1LL, per_p));
   if (pchunk_override <= 0) pc = std::min(pc, cap);
   pc = std::min<long long>(pc, pl.naux);
   pl.pc = (int)std::max(1LL, pc);
@@ -324,6 +326,7 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
     if (r.Fq) DEV_CHECK(ctx, eri_fock_ao(s, nbf, nact, r.nq, r.q_idx, n, H, b.alpha, b.beta, b.Jr, b.Kr, r.Fq));
   } else {
     DEV_CHECK(ctx, fill_f64(s, K, n2, 0.0));
+    DEV_CHECK(ctx, fill_f64(s, b.Kpart, (long long)pl.ns2 * n2, 0.0));
     if (want_y) DEV_CHECK(ctx, fill_f64(s, b.Y2e, ny, 0.0));
     if (!pl.split) DEV_CHECK(ctx, transpose_ca(s, nbf, nact, C, b.Ct, pl.ldk));
     else {
@@ -344,7 +347,6 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
         }
         DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_X, df_f64_gemm1(s, nbf, nact, np, b.Ct, pl.ldk, Bc, b.XT, pl.ldx)));
         DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_B, df_f64_gemm2(s, nbf, nact, np, ns2, b.Ct, pl.ldk, b.XT, pl.ldx, b.beta, b.Kpart, Dc, b.W, pl.ldw)));
-        DEV_CHECK(ctx, reduce_k(s, nact, ns2, b.Kpart, K));
         if (want_y) {
           DEV_CHECK(ctx, add_diag_f64(s, nact, np, Dc, b.alpha, b.W, pl.ldw));
           DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_Y, df_f64_gemm3(s, nbf, nact, np, ns3, b.XT, pl.ldx, b.W, pl.ldw, b.Ypart64)));
@@ -373,7 +375,6 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
         SplitPtr XT{b.xth, b.xtl};
         DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_B, df_bf16_gemm2(s, nbf, nact, np, ns2, pl.terms, Ct, pl.ldk, XT, pl.ldx, b.beta32, b.Kpart, Dc,
                                      b.wh, b.wl, pl.ldw)));
-        DEV_CHECK(ctx, reduce_k(s, nact, ns2, b.Kpart, K));
         if (want_y) {
           DEV_CHECK(ctx, add_diag_bf16(s, nact, np, Dc, b.alpha, b.wh, b.wl, pl.ldw));
           SplitPtr X{b.xh, b.xl}, W{b.wh, b.wl};
@@ -385,6 +386,7 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
                                      b.beta, nullptr, b.xth, b.xtl, pl.ldx, r.Jq, r.Kq, r.Fq));
       }
     }
+    DEV_CHECK(ctx, reduce_k(s, nact, pl.ns2, b.Kpart, K));
     // J = D^T D
     DEV_CHECK(ctx, gemm_f64(s, nact, nact, pl.naux, 1, 1.0, b.D, 1, nact, 0, b.D, nact, 1, 0, 0.0, J, nact, 1, 0));
     if (r.Fq) DEV_CHECK(ctx, fock_ao_h(s, nbf, r.nq, r.q_idx, n, H, r.Fq));

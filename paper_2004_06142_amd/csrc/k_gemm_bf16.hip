@@ -222,7 +222,8 @@ __global__ __launch_bounds__(256) void gemm1_kernel(int nbf, int nact, const u16
     }
 }
 
-// gemm2: b_P = Ct XT_P^T on lower tiles; Kpart[s] = sum_{P in s} b^2, D[P][p] = b_pp,
+// gemm2: b_P = Ct XT_P^T on lower tiles; Kpart[s] += sum_{P in s} b^2 (lower triangle, summed over
+// the successive P-chunks of one call), D[P][p] = b_pp,
 // W_P = b o beta (symmetric, each unordered pair written once, split hi/lo).
 template <int TERMS>
 __global__ __launch_bounds__(256) void gemm2_kernel(int nbf, int nact, int np, int nsplit,
@@ -281,7 +282,7 @@ __global__ __launch_bounds__(256) void gemm2_kernel(int nbf, int nact, int np, i
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int p = m0 + row_of(i, j), q = n0 + col_of(jn);
-        if (p < nact && q <= p) Kp[(long long)p * nact + q] = (double)kacc[i][jn][j];
+        if (p < nact && q <= p) Kp[(long long)p * nact + q] += (double)kacc[i][jn][j];
       }
 }
 

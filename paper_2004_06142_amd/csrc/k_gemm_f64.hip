@@ -3,7 +3,7 @@
 // Block tile 64 x 64 x 16, 256 threads = 4 waves in a 2 x 2 arrangement, each wave owning a
 // 32 x 32 sub-tile = 2 x 2 MFMA blocks of 16 x 16.  Operands are staged through LDS stored
 // k-major ([k][m] and [k][n]), which is the order in which the f64 MFMA consumes them (lane l
-// supplies A[m = l%16][k = l/16] and B[k = l/16][n = l%16]; the result element (4*(l/16)+j, l%16)
+// supplies A[m = l%16][k = l/16] and B[k = l/16][n = l%16]; the result element (l/16 + 4*j, l%16)
 // sits in component j of lane l).  Register prefetch of the next k-slab overlaps global loads
 // with the matrix-core work.
 #include "common.h"
@@ -88,7 +88,7 @@ __device__ __forceinline__ void zero_acc(f64x4 (&acc)[2][2]) {
 // Row / column of component j of acc[mi][ni] relative to the block tile origin.
 __device__ __forceinline__ int acc_row(int mi, int j) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  return (wave >> 1) * 32 + mi * 16 + 4 * (lane >> 4) + j;
+  return (wave >> 1) * 32 + mi * 16 + (lane >> 4) + 4 * j;
 }
 __device__ __forceinline__ int acc_col(int ni) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(256) void df_gemm2_kernel(int nbf, int nact, int np
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int p = m0 + acc_row(mi, j), q = n0 + acc_col(ni);
-        if (p < nact && q < nact) Kp[(long long)p * nact + q] = kacc[mi][ni][j];
+        if (p < nact && q <= p) Kp[(long long)p * nact + q] += kacc[mi][ni][j];
       }
 }
 

@@ -91,7 +91,7 @@ __global__ void add_diag_f64_k(int nact, int np, const double* __restrict__ Dc, 
     const int p = (int)(i % nact);
     const double* Dp = Dc + P * nact;
     double d = 0.0;
-    for (int q = 0; q < nact; ++q) d += Dp[q] * alpha[(long long)p * nact + q];
+    for (int q = 0; q < nact; ++q) d += Dp[q] * alpha[(long long)q * nact + p];   // alpha symmetric
     W[P * nact * ldw + (long long)p * ldw + p] += d;
   }
 }
@@ -103,7 +103,7 @@ __global__ void add_diag_bf16_k(int nact, int np, const double* __restrict__ Dc,
     const int p = (int)(i % nact);
     const double* Dp = Dc + P * nact;
     double d = 0.0;
-    for (int q = 0; q < nact; ++q) d += Dp[q] * alpha[(long long)p * nact + q];
+    for (int q = 0; q < nact; ++q) d += Dp[q] * alpha[(long long)q * nact + p];   // alpha symmetric
     const long long o = P * nact * ldw + (long long)p * ldw + p;
     double w = (double)bf16_bits_to_f32(Wh[o]) + (Wl ? (double)bf16_bits_to_f32(Wl[o]) : 0.0) + d;
     u16 h, l;

@@ -120,7 +120,7 @@ def b_factor_table(nbf: int, naux: int) -> np.ndarray:
 def bf16_round(x: np.ndarray) -> np.ndarray:
     """Round float64 to the nearest bfloat16 (ties to even); returns float64 values."""
     x = np.asarray(x, dtype=np.float64)
-    out = np.zeros_like(x)
+    out = x.copy()                        # zeros keep their sign
     nz = x != 0.0
     _, e = np.frexp(x[nz])                # x = m 2^e, 0.5 <= |m| < 1 -> floor(log2|x|) = e-1
     qe = np.maximum(e - 1, -126) - 7

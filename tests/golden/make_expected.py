@@ -1,0 +1,80 @@
+"""Write the oracle's expected values for the full-size workloads (runs on the CPU only).
+
+Usage: python tests/golden/make_expected.py c5_df1200 [c3_df500] ...
+Calls only ``oracle`` (FP64, streamed route) on inputs from ``synth``; B rows are regenerated
+chunk by chunk from the counter-based stream, in worker processes, so that no full float64 copy of B
+ever exists.  Output: tests/golden/<workload>_expected.json with the energy, the orbital-step
+eigenvalues and sampled entries of J, K, lambda, dE/dC and dE/dn (indices stored with the values).
+"""
+from __future__ import annotations
+
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+from oracle import pnof, stream  # noqa: E402
+
+CHUNK = 48
+
+
+def _rows(args):
+    key, nbf, naux, p0, p1, dt = args
+    return p0, synth.b_chunk(key, nbf, naux, p0, p1, dt)
+
+
+def expected(name: str, workers: int = 6) -> dict:
+    inst = synth.workload(name, with_b=False)
+    wl = inst.wl
+    n = pnof.on_sigmoid(inst.gamma, wl.npairs, wl.ncwo)
+    ranges = [(inst.key, wl.nbf, wl.naux, p0, min(wl.naux, p0 + CHUNK), wl.b_dtype)
+              for p0 in range(0, wl.naux, CHUNK)]
+    t0 = time.time()
+    with mp.get_context("fork").Pool(workers) as pool:
+        it = pool.imap(_rows, ranges)
+        pending = {}
+
+        def chunk(p0, p1):
+            while p0 not in pending:
+                q0, rows = next(it)
+                pending[q0] = rows
+            rows = pending.pop(p0)
+            assert rows.shape[0] == p1 - p0
+            print(f"  rows {p0}..{p1} ({time.time() - t0:.0f} s)", flush=True)
+            return rows
+
+        r = stream.lagrangian(inst.C, n, inst.H, chunk, wl.npairs, wl.ncwo, pnof.PNOF7, naux=wl.naux,
+                              pchunk=CHUNK)
+    _, eps, _ = pnof.orbital_step(r["lam"], inst.C)
+    rng = np.random.default_rng(17)
+    pq = rng.integers(0, wl.nact, size=(64, 2))
+    lam_pq = np.stack([rng.integers(0, wl.nbf, 64), rng.integers(0, wl.nact, 64)], axis=1)
+    mq = np.stack([rng.integers(0, wl.nbf, 32), rng.integers(0, wl.nact, 32)], axis=1)
+    pn = rng.integers(0, wl.nact, 32)
+    return {
+        "workload": name, "seed": synth.seed_of(name), "functional": "PNOF7", "on_map": "sigmoid",
+        "E": r["E"], "max_asym": pnof.max_asym(r["lam"]),
+        "eps": eps.tolist(),
+        "J": {"idx": pq.tolist(), "val": [r["J"][p, q] for p, q in pq]},
+        "K": {"idx": pq.tolist(), "val": [r["K"][p, q] for p, q in pq]},
+        "lam": {"idx": lam_pq.tolist(), "val": [r["lam"][p, q] for p, q in lam_pq]},
+        "dEdC": {"idx": mq.tolist(), "val": [r["dEdC"][m, q] for m, q in mq]},
+        "dEdn": {"idx": pn.tolist(), "val": [r["dEdn"][p] for p in pn]},
+        "seconds": time.time() - t0,
+    }
+
+
+if __name__ == "__main__":
+    for name in sys.argv[1:]:
+        out = expected(name)
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{name}_expected.json")
+        with open(path, "w") as f:
+            json.dump(out, f)
+        print(f"wrote {path}: E = {out['E']:.12f} ({out['seconds']:.0f} s)")
