@@ -35,6 +35,9 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=1, help="steps of the float64 path for the speedup (0: skip)")
     ap.add_argument("--cpu-rows", type=int, default=384, help="rows of B in the oracle's timed sample (0: skip)")
     ap.add_argument("--pchunk", type=int, default=0)
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch-parameter autotuner")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run a plain device-to-device copy of this many MiB (reference for traffic counters)")
     return ap.parse_args()
 
 
@@ -58,6 +61,12 @@ def main():
     import synth.device as sdev
 
     dev = torch.device("cuda", 0)
+    if args.copy_calibration:
+        src = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     wl = synth.WORKLOADS[args.workload]
     inst = synth.workload(args.workload, with_b=False)
     prec = {"bf16split": P.BF16_SPLIT, "fp64": P.FP64, "bf16": P.BF16}[args.precision]
@@ -77,6 +86,12 @@ def main():
 
     def run(prob, warmup, steps, profile):
         ctx.reserve(prob)
+        if not args.no_tune and not args.pchunk:
+            from paper_2004_06142_amd import autotune
+            n0 = ctx.on_map(gamma, prob.npairs, prob.ncwo)
+            ent = autotune.tune(ctx, prob, lambda: ctx.lagrangian(prob, C0, n0, H, B), verbose=False)
+            print(f"[bench] tuning {ent['tuning']}", file=sys.stderr, flush=True)
+            ctx.reserve(prob)
         out = None
         for _ in range(warmup):
             out, _ = step(prob, C0)
@@ -120,7 +135,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "nbf": wl.nbf, "naux": wl.naux, "npairs": wl.npairs, "ncwo": wl.ncwo,
                    "nact": wl.nact, "functional": "PNOF7", "B": wl.b_dtype, "seed": synth.seed_of(wl.name)},
-        "energy_Ha": E, "stages": stages, "roofline": roofline,
+        "energy_Ha": E, "stages": stages, "roofline": roofline, "launch": ctx.plan(prob),
     }
     if os.path.exists(GOLDEN_C5) and wl.name == "c5_df1200":
         ref = json.load(open(GOLDEN_C5))

@@ -103,7 +103,20 @@ pnof_status pnof_check_problem(const pnof_problem* prob);
 pnof_status pnof_workspace_size(pnof_ctx ctx, const pnof_problem* prob, size_t* bytes);
 /* Lend `bytes` of device memory at `dev` (256-byte aligned) to the context; NULL detaches. */
 pnof_status pnof_set_workspace(pnof_ctx ctx, void* dev, size_t bytes);
-/* Rows of B processed per pass (0 = automatic).  Results do not depend on it beyond rounding. */
+/* Launch parameters of the density-fitted path (0 = automatic for every field):
+ *   pchunk     rows of B processed per pass;
+ *   nsplit_b   P-groups of the b / K contraction (each group keeps its own K partial sums);
+ *   nsplit_y   P-groups of the Y contraction (each group keeps its own Y partial sums);
+ *   x_variant, y_variant  block-tile shape of the bf16 X and Y contractions: 0 = 128 x 128 (two
+ *              blocks per compute unit), 1 = 128 x 256 / 256 x 128 (one block per compute unit).
+ * Results do not depend on them beyond floating-point rounding order.  pnof_get_plan returns the
+ * values a call on `prob` would use. */
+typedef struct {
+  int32_t pchunk, nsplit_b, nsplit_y, x_variant, y_variant;
+} pnof_tuning;
+pnof_status pnof_set_tuning(pnof_ctx ctx, const pnof_tuning* tuning);   /* NULL: all automatic */
+pnof_status pnof_get_plan(pnof_ctx ctx, const pnof_problem* prob, pnof_tuning* out);
+/* Shorthand for setting only pnof_tuning.pchunk. */
 pnof_status pnof_set_pchunk(pnof_ctx ctx, int32_t pchunk);
 
 /* Measurement: between pnof_profile_begin and pnof_profile_end every launch of the three-index

@@ -31,7 +31,7 @@ STATUS = {0: "PNOF_OK", 1: "PNOF_E_ARG", 2: "PNOF_E_SHAPE", 3: "PNOF_E_DTYPE", 4
 EXPORTS = ["pnof_abi_version", "pnof_last_error", "pnof_check_problem", "pnof_create", "pnof_destroy",
            "pnof_set_stream", "pnof_workspace_size", "pnof_set_workspace", "pnof_set_pchunk", "pnof_on_map",
            "pnof_on_map_vjp", "pnof_jk", "pnof_energy", "pnof_fock", "pnof_lagrangian", "pnof_orbital_step",
-           "pnof_profile_begin", "pnof_profile_end"]
+           "pnof_profile_begin", "pnof_profile_end", "pnof_set_tuning", "pnof_get_plan"]
 STAGES = ("X", "b", "Y", "eig")
 
 
@@ -39,6 +39,13 @@ class PnofError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
         self.status = status
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("pchunk", "nsplit_b", "nsplit_y", "x_variant", "y_variant")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
 
 
 class Problem(ctypes.Structure):
@@ -83,6 +90,8 @@ def lib():
             "pnof_fock": ([P, PP, P, P, P, P, P, P, P, I], S),
             "pnof_lagrangian": ([P, PP, P, P, P, P, P, P, P, P, P, P, P], S),
             "pnof_orbital_step": ([P, I, P, P, P, D, P, P, P], S),
+            "pnof_set_tuning": ([P, ctypes.POINTER(Tuning)], S),
+            "pnof_get_plan": ([P, PP, ctypes.POINTER(Tuning)], S),
             "pnof_profile_begin": ([P], S),
             "pnof_profile_end": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], S),
         }
@@ -167,6 +176,19 @@ class Context:
         cnt = (ctypes.c_int64 * 4)()
         _raise(self, lib().pnof_profile_end(self.handle, ms, cnt))
         return {k: (ms[i], cnt[i]) for i, k in enumerate(STAGES)}
+
+    def set_tuning(self, tuning=None, **kw):
+        """Set launch parameters (a Tuning, a dict, or keywords); None resets to automatic."""
+        if tuning is None and not kw:
+            _raise(self, lib().pnof_set_tuning(self.handle, None))
+            return
+        t = tuning if isinstance(tuning, Tuning) else Tuning(**{**(tuning or {}), **kw})
+        _raise(self, lib().pnof_set_tuning(self.handle, ctypes.byref(t)))
+
+    def plan(self, prob) -> dict:
+        t = Tuning()
+        _raise(self, lib().pnof_get_plan(self.handle, ctypes.byref(prob), ctypes.byref(t)))
+        return t.as_dict()
 
     def set_pchunk(self, pc: int):
         _raise(self, lib().pnof_set_pchunk(self.handle, pc))

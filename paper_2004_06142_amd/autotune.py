@@ -1,0 +1,117 @@
+"""Launch-parameter autotuner for the density-fitted contractions.
+
+For a problem shape it times candidate launch parameters (rows per chunk, P-splits of the b and Y
+contractions, block-tile variants of X and Y) on the device with the library's own stage timers,
+one stage at a time (coordinate search), and keeps the fastest.  Results are cached in a JSON file
+keyed by GPU architecture, precision and a size bucket of (nbf, nact, naux); the path comes from
+PNOF_AUTOTUNE_CACHE (default: autotune_cache.json next to this file).
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+
+import torch
+
+from . import Context, Tuning
+
+CACHE = os.environ.get("PNOF_AUTOTUNE_CACHE",
+                       os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json"))
+
+
+def _bucket(x: int) -> int:
+    """Size bucket: powers of two split in quarters."""
+    if x <= 0:
+        return 0
+    e = math.floor(math.log2(x))
+    return int(2 ** e * (1 + math.floor(4 * (x / 2 ** e - 1)) / 4))
+
+
+def key(prob, arch: str) -> str:
+    return f"{arch}:p{prob.precision}:i{prob.ints}:nbf{_bucket(prob.nbf)}:nact{_bucket(prob.nact)}:naux{_bucket(prob.naux)}"
+
+
+def _arch(device) -> str:
+    try:
+        return torch.cuda.get_device_properties(device).gcnArchName.split(":")[0]
+    except Exception:
+        return "unknown"
+
+
+def load_cache() -> dict:
+    try:
+        with open(CACHE) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def save_cache(c: dict):
+    tmp = CACHE + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(c, f, indent=1, sort_keys=True)
+    os.replace(tmp, CACHE)
+
+
+def _time(ctx: Context, prob, run, reps: int) -> dict:
+    run()                                    # warm (and size the workspace)
+    torch.cuda.synchronize()
+    ctx.profile_begin()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        run()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    st = ctx.profile_end()
+    return {"wall": wall, **{k: v[0] / reps for k, v in st.items()}}
+
+
+def tune(ctx: Context, prob, run, reps: int = 2, use_cache: bool = True, verbose: bool = False) -> dict:
+    """Pick launch parameters for `prob`; `run()` performs one library call on that problem."""
+    arch = _arch(ctx.device)
+    k = key(prob, arch)
+    cache = load_cache() if use_cache else {}
+    if k in cache:
+        ctx.set_tuning(cache[k]["tuning"])
+        return cache[k]
+    ctx.set_tuning(None)
+    base = ctx.plan(prob)
+    best = dict(base)
+
+    def measure(t):
+        ctx.set_tuning(Tuning(**t))
+        r = _time(ctx, prob, run, reps)
+        if verbose:
+            print("  tune", t, {a: round(b, 3) for a, b in r.items()}, flush=True)
+        return r
+
+    cur = measure(best)
+    # chunk size first (it sets the scale of the other two splits)
+    for pc in sorted({max(1, base["pchunk"] // 2), base["pchunk"], base["pchunk"] * 2}):
+        if pc == best["pchunk"] or pc > prob.naux:
+            continue
+        t = dict(best, pchunk=pc, nsplit_b=0, nsplit_y=0)
+        r = measure(t)
+        if r["wall"] < cur["wall"]:
+            best, cur = ctx.plan(prob), r
+    ctx.set_tuning(Tuning(**best))
+    # per-stage parameters, each judged on its own stage time
+    for field, stage, cands in (("x_variant", "X", [0, 1]), ("y_variant", "Y", [0, 1]),
+                                ("nsplit_b", "b", [best["nsplit_b"] // 2, best["nsplit_b"] * 2]),
+                                ("nsplit_y", "Y", [best["nsplit_y"] // 2, best["nsplit_y"] * 2])):
+        for v in cands:
+            if v == best[field] or v < 0 or (field.startswith("nsplit") and (v < 1 or v > best["pchunk"])):
+                continue
+            r = measure(dict(best, **{field: v}))
+            if r[stage] < cur[stage] * 0.98:
+                best, cur = dict(best, **{field: v}), r
+    ctx.set_tuning(Tuning(**best))
+    entry = {"tuning": best, "ms": {a: 1e3 * b if a == "wall" else b for a, b in cur.items()}, "arch": arch,
+             "shape": [prob.nbf, prob.nact, prob.naux]}
+    if use_cache:
+        cache = load_cache()
+        cache[k] = entry
+        save_cache(cache)
+    return entry

@@ -22,7 +22,7 @@ struct pnof_ctx_s {
   size_t ext_bytes = 0;
   char* own_ws = nullptr;
   size_t own_bytes = 0;
-  int pchunk = 0;
+  pnof_tuning tune{0, 0, 0, 0, 0};
   int* host_info = nullptr;  // pinned
   // measurement: launches of the contraction kernels bracketed by events on the stream
   bool profiling = false;
@@ -119,13 +119,13 @@ pnof_status check_problem(pnof_ctx ctx, const pnof_problem* p) {
 // ------------------------------------------------------------------------ planning
 struct Plan {
   int nbf, nact, naux, npairs, ncwo, functional, prec, ints;
-  int pc, ns2, ns3;
-  int ldk, ldx, ldxx, ldw;
+  int pc, ns2, ns3, xv, yv;
+  int ldk, ldx, ldxx, ldw, nact32;
   bool split;   // bf16 family
   int terms;    // 1 or 3
 };
 
-Plan make_plan(const pnof_problem* p, int pchunk_override) {
+Plan make_plan(const pnof_problem* p, const pnof_tuning& tu) {
   Plan pl{};
   pl.nbf = p->nbf;
   pl.nact = p->npairs * (p->ncwo + 1);
@@ -137,30 +137,35 @@ Plan make_plan(const pnof_problem* p, int pchunk_override) {
   pl.ints = p->ints;
   pl.split = (p->precision != PNOF_FP64);
   pl.terms = p->precision == PNOF_BF16_SPLIT ? 3 : 1;
+  pl.xv = pl.split ? (tu.x_variant == 1) : 0;
+  pl.yv = pl.split ? (tu.y_variant == 1) : 0;
   const int tile = pl.split ? 128 : 64;
-  pl.ldk = (int)round_up(pl.nbf, 8);
-  pl.ldx = (int)round_up(pl.nbf, 8);
-  pl.ldxx = (int)round_up(pl.nact, 8);
-  pl.ldw = (int)round_up(pl.nact, 8);
+  // workspace rows padded to multiples of 32 (zero pads): whole k-tiles never need masking
+  pl.ldk = (int)round_up(pl.nbf, 32);
+  pl.ldx = (int)round_up(pl.nbf, 32);
+  pl.ldxx = (int)round_up(pl.nact, 32);
+  pl.ldw = (int)round_up(pl.nact, 32);
+  pl.nact32 = (int)round_up(pl.nact, 32);
   if (!is_df(p->ints)) { pl.pc = pl.ns2 = pl.ns3 = 1; return pl; }
-  const long long t1 = (long long)cdiv(pl.nact, tile) * cdiv(pl.nbf, tile);
+  const long long t1 = (long long)cdiv(pl.nact, tile) * cdiv(pl.nbf, pl.xv ? 256 : tile);
   // enough blocks per launch to fill the chip, and enough rows per chunk that the per-split K
   // partials (ns2 x nact^2, read-modified-written once per chunk) stay small next to X and W
-  long long pc = pchunk_override > 0 ? pchunk_override : std::max(64LL, (4096 + t1 - 1) / t1);
-  // keep the per-chunk buffers modest
-  const long long per_p = pl.split ? (long long)(2 * pl.nact * pl.ldx + 2 * pl.nbf * pl.ldxx + 2 * pl.nact * pl.ldw) * 2 +
+  long long pc = tu.pchunk > 0 ? tu.pchunk : std::max(64LL, (4096 + t1 - 1) / t1);
+  const long long per_p = pl.split ? (long long)(2LL * pl.nact32 * pl.ldx + 2LL * pl.nact32 * pl.ldw) * 2 +
                                          (p->ints == PNOF_INTS_DF_F64 ? 4LL * pl.nbf * pl.nbf : 0)
                                    : (long long)(pl.nact * pl.ldx + pl.nact * pl.ldw) * 8 +
                                          (p->ints == PNOF_INTS_DF_BF16 ? 8LL * pl.nbf * pl.nbf : 0);
   const long long cap = std::max(1LL, (2LL << 30) / std::max(1LL, per_p));
-  if (pchunk_override <= 0) pc = std::min(pc, cap);
+  if (tu.pchunk <= 0) pc = std::min(pc, cap);
   pc = std::min<long long>(pc, pl.naux);
   pl.pc = (int)std::max(1LL, pc);
   const int tt = cdiv(pl.nact, tile);
   const long long ntri = (long long)tt * (tt + 1) / 2;
-  pl.ns2 = (int)std::min<long long>(pl.pc, std::max(1LL, (1024 + ntri - 1) / ntri));
-  const long long t3 = (long long)cdiv(pl.nbf, tile) * cdiv(pl.nact, tile);
-  pl.ns3 = (int)std::min<long long>(pl.pc, std::max(1LL, (1024 + t3 - 1) / t3));
+  pl.ns2 = tu.nsplit_b > 0 ? tu.nsplit_b : (int)std::max(1LL, (1024 + ntri - 1) / ntri);
+  pl.ns2 = std::min(pl.ns2, pl.pc);
+  const long long t3 = (long long)cdiv(pl.nbf, pl.yv ? 256 : tile) * cdiv(pl.nact, tile);
+  pl.ns3 = tu.nsplit_y > 0 ? tu.nsplit_y : (int)std::max(1LL, (1024 + t3 - 1) / t3);
+  pl.ns3 = std::min(pl.ns3, pl.pc);
   return pl;
 }
 
@@ -170,7 +175,7 @@ struct Bufs {
   double* Ct;           // fp64
   u16 *cth, *ctl;       // split
   double *XT, *W, *Ypart64, *Bw;   // fp64 chunk
-  u16 *xth, *xtl, *xh, *xl, *wh, *wl, *bh, *bl;  // split chunk
+  u16 *xth, *xtl, *wh, *wl, *bh, *bl;  // split chunk
   float* Ypart32;
   double *Jr, *Kr;      // explicit integrals
   int* flag;
@@ -204,15 +209,13 @@ Bufs carve(const Plan& pl, char* base) {
       b.Ypart64 = a.take<double>((long long)pl.ns3 * ny);
       if (pl.ints == PNOF_INTS_DF_BF16) b.Bw = a.take<double>((long long)pl.pc * pl.nbf * pl.nbf);
     } else {
-      b.cth = a.take<u16>((long long)pl.nact * pl.ldk);
-      b.ctl = a.take<u16>((long long)pl.nact * pl.ldk);
-      b.xth = a.take<u16>((long long)pl.pc * pl.nact * pl.ldx);
-      b.xh = a.take<u16>((long long)pl.pc * pl.nbf * pl.ldxx);
-      b.wh = a.take<u16>((long long)pl.pc * pl.nact * pl.ldw);
+      b.cth = a.take<u16>((long long)pl.nact32 * pl.ldk);
+      b.ctl = a.take<u16>((long long)pl.nact32 * pl.ldk);
+      b.xth = a.take<u16>((long long)pl.pc * pl.nact32 * pl.ldx);
+      b.wh = a.take<u16>((long long)pl.pc * pl.nact32 * pl.ldw);
       if (pl.terms > 1) {
-        b.xtl = a.take<u16>((long long)pl.pc * pl.nact * pl.ldx);
-        b.xl = a.take<u16>((long long)pl.pc * pl.nbf * pl.ldxx);
-        b.wl = a.take<u16>((long long)pl.pc * pl.nact * pl.ldw);
+        b.xtl = a.take<u16>((long long)pl.pc * pl.nact32 * pl.ldx);
+        b.wl = a.take<u16>((long long)pl.pc * pl.nact32 * pl.ldw);
       }
       b.Ypart32 = a.take<float>((long long)pl.ns3 * ny);
       if (pl.ints == PNOF_INTS_DF_F64) {
@@ -280,7 +283,7 @@ struct Req {
 
 pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, const double* n,
                      const double* H, const void* ints, Req& r) {
-  const Plan pl = make_plan(prob, ctx->pchunk);
+  const Plan pl = make_plan(prob, ctx->tune);
   Bufs b = carve(pl, nullptr);
   char* ws = nullptr;
   pnof_status st = get_ws(ctx, b.bytes, &ws);
@@ -328,8 +331,21 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
     DEV_CHECK(ctx, fill_f64(s, K, n2, 0.0));
     DEV_CHECK(ctx, fill_f64(s, b.Kpart, (long long)pl.ns2 * n2, 0.0));
     if (want_y) DEV_CHECK(ctx, fill_f64(s, b.Y2e, ny, 0.0));
+    WsDims wd{pl.nact32, 0, 0, 0};
     if (!pl.split) DEV_CHECK(ctx, transpose_ca(s, nbf, nact, C, b.Ct, pl.ldk));
     else {
+      const long long nct = (long long)pl.nact32 * pl.ldk, nxt = (long long)pl.pc * pl.nact32 * pl.ldx,
+                      nw = (long long)pl.pc * pl.nact32 * pl.ldw;
+      wd = WsDims{pl.nact32, 2 * nct, 2 * nxt, 2 * nw};
+      // the zero pads of the tiles are part of the contract of the contraction kernels
+      DEV_CHECK(ctx, fill_u16(s, b.cth, nct, 0));
+      DEV_CHECK(ctx, fill_u16(s, b.xth, nxt, 0));
+      DEV_CHECK(ctx, fill_u16(s, b.wh, nw, 0));
+      if (pl.terms > 1) {
+        DEV_CHECK(ctx, fill_u16(s, b.ctl, nct, 0));
+        DEV_CHECK(ctx, fill_u16(s, b.xtl, nxt, 0));
+        DEV_CHECK(ctx, fill_u16(s, b.wl, nw, 0));
+      }
       DEV_CHECK(ctx, split_ca(s, nbf, nact, pl.terms, C, b.cth, b.ctl, pl.ldk));
       corr_terms = pl.terms > 1 ? 2 : 1;
     }
@@ -354,15 +370,18 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
         }
         if (r.Jq || r.Kq || r.Fq)
           DEV_CHECK(ctx, df_ao_accum(s, nbf, nact, np, r.nq, r.q_idx, Bc, 0, Dc, b.alpha, b.beta, b.XT, nullptr, nullptr,
-                                     pl.ldx, r.Jq, r.Kq, r.Fq));
+                                     pl.ldx, (long long)nact * pl.ldx, r.Jq, r.Kq, r.Fq));
       } else {
         SplitPtr Bp;
         const void* Bsrc;
+        long long b_bytes;
         if (pl.ints == PNOF_INTS_DF_BF16) {
           Bp.hi = static_cast<const u16*>(ints) + p0 * bsz;
           Bp.lo = nullptr;
           Bsrc = Bp.hi;
+          b_bytes = 2LL * (pl.naux - p0) * bsz;
         } else {
+          b_bytes = 2LL * np * bsz;
           const double* Bf = static_cast<const double*>(ints) + p0 * bsz;
           DEV_CHECK(ctx, split_b(s, np * bsz, Bf, b.bh, b.bl));
           Bp.hi = b.bh;
@@ -370,20 +389,21 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
           Bsrc = Bf;
         }
         SplitPtr Ct{b.cth, pl.terms > 1 ? b.ctl : nullptr};
-        DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_X, df_bf16_gemm1(s, nbf, nact, np, pl.terms, Ct, pl.ldk, Bp, bsz, nbf, b.xth, b.xtl, pl.ldx,
-                                     b.xh, b.xl, pl.ldxx)));
+        DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_X, df_bf16_gemm1(s, nbf, nact, np, pl.terms, Ct, pl.ldk, Bp, bsz, nbf, b_bytes, b.xth,
+                                                               b.xtl, pl.ldx, pl.xv, wd)));
         SplitPtr XT{b.xth, b.xtl};
         DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_B, df_bf16_gemm2(s, nbf, nact, np, ns2, pl.terms, Ct, pl.ldk, XT, pl.ldx, b.beta32, b.Kpart, Dc,
-                                     b.wh, b.wl, pl.ldw)));
+                                     b.wh, b.wl, pl.ldw, wd)));
         if (want_y) {
-          DEV_CHECK(ctx, add_diag_bf16(s, nact, np, Dc, b.alpha, b.wh, b.wl, pl.ldw));
-          SplitPtr X{b.xh, b.xl}, W{b.wh, b.wl};
-          DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_Y, df_bf16_gemm3(s, nbf, nact, np, ns3, pl.terms, X, pl.ldxx, W, pl.ldw, b.Ypart32)));
+          DEV_CHECK(ctx, add_diag_bf16(s, nact, np, Dc, b.alpha, b.wh, b.wl, pl.ldw, (long long)pl.nact32 * pl.ldw));
+          SplitPtr W{b.wh, b.wl};
+          DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_Y, df_bf16_gemm3(s, nbf, nact, np, ns3, pl.terms, XT, pl.ldx, W, pl.ldw, b.Ypart32, pl.yv, wd)));
           DEV_CHECK(ctx, reduce_y_f32(s, ny, ns3, b.Ypart32, b.Y2e));
         }
         if (r.Jq || r.Kq || r.Fq)
           DEV_CHECK(ctx, df_ao_accum(s, nbf, nact, np, r.nq, r.q_idx, Bsrc, pl.ints == PNOF_INTS_DF_BF16, Dc, b.alpha,
-                                     b.beta, nullptr, b.xth, b.xtl, pl.ldx, r.Jq, r.Kq, r.Fq));
+                                     b.beta, nullptr, b.xth, b.xtl, pl.ldx, (long long)pl.nact32 * pl.ldx, r.Jq, r.Kq,
+                                     r.Fq));
       }
     }
     DEV_CHECK(ctx, reduce_k(s, nact, pl.ns2, b.Kpart, K));
@@ -484,7 +504,7 @@ pnof_status pnof_workspace_size(pnof_ctx ctx, const pnof_problem* prob, size_t* 
   pnof_status st = check_problem(ctx, prob);
   if (st != PNOF_OK) return st;
   if (!bytes) return fail(ctx, PNOF_E_ARG, "bytes is NULL");
-  *bytes = carve(make_plan(prob, ctx ? ctx->pchunk : 0), nullptr).bytes;
+  *bytes = carve(make_plan(prob, ctx ? ctx->tune : pnof_tuning{0, 0, 0, 0, 0}), nullptr).bytes;
   return PNOF_OK;
 }
 
@@ -528,7 +548,30 @@ pnof_status pnof_profile_end(pnof_ctx ctx, double* ms, int64_t* launches) {
 pnof_status pnof_set_pchunk(pnof_ctx ctx, int32_t pchunk) {
   if (!ctx) return fail(nullptr, PNOF_E_ARG, "context is NULL");
   if (pchunk < 0) return fail(ctx, PNOF_E_ARG, "pchunk must be >= 0");
-  ctx->pchunk = pchunk;
+  ctx->tune.pchunk = pchunk;
+  return PNOF_OK;
+}
+
+pnof_status pnof_set_tuning(pnof_ctx ctx, const pnof_tuning* t) {
+  if (!ctx) return fail(nullptr, PNOF_E_ARG, "context is NULL");
+  if (!t) {
+    ctx->tune = pnof_tuning{0, 0, 0, 0, 0};
+    return PNOF_OK;
+  }
+  if (t->pchunk < 0 || t->nsplit_b < 0 || t->nsplit_y < 0 || t->x_variant < 0 || t->x_variant > 1 ||
+      t->y_variant < 0 || t->y_variant > 1)
+    return fail(ctx, PNOF_E_ARG, "tuning values out of range");
+  ctx->tune = *t;
+  return PNOF_OK;
+}
+
+pnof_status pnof_get_plan(pnof_ctx ctx, const pnof_problem* prob, pnof_tuning* out) {
+  if (!ctx) return fail(nullptr, PNOF_E_ARG, "context is NULL");
+  pnof_status st = check_problem(ctx, prob);
+  if (st != PNOF_OK) return st;
+  if (!out) return fail(ctx, PNOF_E_ARG, "output is NULL");
+  const Plan pl = make_plan(prob, ctx->tune);
+  *out = pnof_tuning{pl.pc, pl.ns2, pl.ns3, pl.xv, pl.yv};
   return PNOF_OK;
 }
 

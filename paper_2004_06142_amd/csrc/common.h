@@ -68,20 +68,26 @@ hipError_t df_f64_gemm3(hipStream_t s, int nbf, int nact, int np, int nsplit, co
                         int ldx, const double* W, int ldw, double* Ypart);
 
 // ---------------------------------------------------------------- bf16 split GEMMs (k_gemm_bf16.hip)
-// terms: 1 = hi*hi; 3 = hi*hi + hi*lo + lo*hi.  B_P given as bf16 (exact, 2 products against the
+// terms: 1 = hi*hi; 3 = hi*hi + hi*lo + lo*hi.  variant: 0 = 128 x 128 block tiles (two blocks per
+// CU), 1 = 128 x 256 (X) or 256 x 128 (Y) block tiles (one block per CU).  B_P given as bf16 (exact, 2 products against the
 // split Ct) or as a pre-split hi/lo pair (3 products).
 struct SplitPtr {
   const u16* hi;
   const u16* lo;  // may be null when terms == 1 or the operand is exact
 };
-hipError_t df_bf16_gemm1(hipStream_t s, int nbf, int nact, int np, int terms, SplitPtr Ct, int ldk,
-                         SplitPtr Bp, long long bstride, int ldb, u16* XT_hi, u16* XT_lo, int ldx,
-                         u16* X_hi, u16* X_lo, int ldxx);
+// Geometry of the split-path workspace operands (see k_gemm_bf16.hip).
+struct WsDims {
+  int nact32;
+  long long ct_bytes, xt_bytes, w_bytes;
+};
+hipError_t df_bf16_gemm1(hipStream_t s, int nbf, int nact, int np, int terms, SplitPtr Ct, int ldk, SplitPtr Bp,
+                         long long bstride, int ldb, long long b_bytes, u16* XT_hi, u16* XT_lo, int ldx, int variant,
+                         const WsDims& d);
 hipError_t df_bf16_gemm2(hipStream_t s, int nbf, int nact, int np, int nsplit, int terms,
                          SplitPtr Ct, int ldk, SplitPtr XT, int ldx, const float* beta32,
-                         double* Kpart, double* Dchunk, u16* W_hi, u16* W_lo, int ldw);
-hipError_t df_bf16_gemm3(hipStream_t s, int nbf, int nact, int np, int nsplit, int terms, SplitPtr X,
-                         int ldxx, SplitPtr W, int ldw, float* Ypart);
+                         double* Kpart, double* Dchunk, u16* W_hi, u16* W_lo, int ldw, const WsDims& d);
+hipError_t df_bf16_gemm3(hipStream_t s, int nbf, int nact, int np, int nsplit, int terms, SplitPtr XT,
+                         int ldx, SplitPtr W, int ldw, float* Ypart, int variant, const WsDims& d);
 
 // ---------------------------------------------------------------- small kernels (k_small.hip)
 hipError_t fill_f64(hipStream_t s, double* p, long long n, double v);
@@ -97,7 +103,7 @@ hipError_t hpp_from_hc(hipStream_t s, int nbf, int nact, const double* C, const 
 hipError_t add_diag_f64(hipStream_t s, int nact, int np, const double* Dchunk, const double* alpha,
                         double* W, int ldw);
 hipError_t add_diag_bf16(hipStream_t s, int nact, int np, const double* Dchunk, const double* alpha,
-                         u16* W_hi, u16* W_lo, int ldw);
+                         u16* W_hi, u16* W_lo, int ldw, long long pstride);
 hipError_t reduce_k(hipStream_t s, int nact, int nsplit, const double* Kpart, double* K);
 hipError_t reduce_y_f64(hipStream_t s, long long n, int nsplit, const double* Ypart, double* Y);
 hipError_t reduce_y_f32(hipStream_t s, long long n, int nsplit, const float* Ypart, double* Y);
@@ -137,7 +143,7 @@ hipError_t eri_fock_ao(hipStream_t s, int nbf, int nact, int nq, const int32_t* 
 hipError_t df_ao_accum(hipStream_t s, int nbf, int nact, int np, int nq, const int32_t* q_idx,
                        const void* Bchunk, int b_is_bf16, const double* Dchunk,
                        const double* alpha, const double* beta, const double* XT, const u16* XT_hi,
-                       const u16* XT_lo, int ldx, double* Jq, double* Kq, double* Fq);
+                       const u16* XT_lo, int ldx, long long xps, double* Jq, double* Kq, double* Fq);
 hipError_t fock_ao_h(hipStream_t s, int nbf, int nq, const int32_t* q_idx, const double* n,
                      const double* H, double* Fq);
 

@@ -1,155 +1,419 @@
 // bfloat16 matrix-core (v_mfma_f32_16x16x32_bf16) contractions with float32 accumulation.
 //
-// Every product here is "NT": both operands are stored with the contraction index k contiguous
-// (A row m = A[m*lda + k], B row n = B[n*ldb + k]), which is the order in which one MFMA lane
-// consumes eight consecutive k values.  An operand may be carried as a hi + lo pair of bf16
-// values (x ~= hi + lo to about 16 significant bits); the accumulator then receives
+// Operands may be carried as a hi + lo pair of bf16 values (x ~= hi + lo to about 16 significant
+// bits); the accumulator then receives
 //   terms = 1: hi*hi
 //   terms = 2: Ahi*Bhi + Alo*Bhi                  (B exact in bf16)
 //   terms = 3: Ahi*Bhi + Ahi*Blo + Alo*Bhi        (the lo*lo product is below float32 rounding)
-// Block tile 128 x 128 x 32, 256 threads = 4 waves in a 2 x 2 arrangement, each wave owning
-// 64 x 64 = 4 x 4 MFMA blocks; operands are staged through LDS rows padded by 16 bytes, with
-// register prefetch of the next k-slab.  MFMA lane layout: lane l supplies row l%16 and the
-// eight k values 8*(l/16)..8*(l/16)+7; result element (4*(l/16)+j, l%16) is component j.
+//
+// Block tiles BM x BN x 32 (128 x 256 for X, 128 x 128 for the symmetric b, 256 x 128 for Y),
+// 256 threads = 4 waves (2 x 2), each wave owning (BM/2) x (BN/2) in 16 x 16 MFMA blocks.  Operand
+// k-tiles go global -> registers (one tile ahead) -> LDS (two buffers), one barrier per k-tile.  MFMA lane layout (16x16x32 bf16): lane l supplies row l%16 and the eight k
+// values 8*(l/16)..+7 of each operand; result element (4*(l/16)+j, l%16) is component j.
+//
+// Operand storage in global memory:
+//   "row" operand: row r (an output index) is contiguous in k  -> LDS [r][k] (16-byte chunks
+//     XOR-swizzled within the row), 16-byte reads;
+//   "col" operand: row k is contiguous in the output index    -> LDS [k][r], read with the
+//     transposing LDS load (ds_read_b64_tr_b16), which within each 16-lane group hands lane i
+//     element i%4 of the 8-byte chunks fetched by lanes 4j + i/4 (j = 0..3), i.e. four consecutive
+//     k of one row when lane 4j+q fetched rows 4q..4q+3 of k-row j.
+// Blocks are numbered so that the eight XCDs each receive one contiguous range of work items:
+// items sharing an operand (same P, or same split of P) run on the same XCD and share its L2.
 #include "common.h"
 
 namespace pnof {
 namespace {
 
-constexpr int BM = 128, BN = 128, BK = 32, KP = BK + 8;  // LDS row pitch in bf16 elements
-
-struct Operand {
-  const u16* hi;
-  const u16* lo;
-  long long ld;     // elements between rows
-  int rows;         // valid rows
-  int K;            // valid k
-};
+constexpr int BK = 32;
+constexpr int RP = BK;              // row-layout LDS pitch (bf16 elements): 64 bytes, chunks swizzled
+constexpr int NXCD = 8;
+constexpr int T2 = 128;             // tile of the symmetric nact x nact products
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef short v4s __attribute__((ext_vector_type(4)));
 
-// One 16-byte chunk (8 bf16) of row r, k in [k, k+8); zeros outside the valid region.
-__device__ __forceinline__ u32x4 load_chunk(const u16* __restrict__ p, long long ld, int rows, int K,
-                                            int r, int k) {
-  u32x4 v = {0u, 0u, 0u, 0u};
-  if (r >= rows) return v;
-  const u16* src = p + (long long)r * ld + k;
-  if (k + 8 <= K && ((ld & 7) == 0) && ((((uintptr_t)p) & 15) == 0)) {
-    v = *reinterpret_cast<const u32x4*>(src);
-  } else {
-    uint32_t w[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-    for (int i = 0; i < 8; ++i)
-      if (k + i < K) w[i >> 1] |= ((uint32_t)src[i]) << (16 * (i & 1));
-    v = u32x4{w[0], w[1], w[2], w[3]};
-  }
-  return v;
-}
-
-struct Smem {
-  u16 a[2][BM][KP];
-  u16 b[2][BN][KP];
+struct Opnd {
+  const u16* hi;
+  const u16* lo;
+  long long ld;   // elements between consecutive storage rows
+  int R;          // valid output-index extent (rows of a row operand, columns of a col operand)
+  int K;          // valid k extent
+  bool col;       // storage rows run along k (read through the transposing LDS load)
 };
 
-template <int TERMS, bool ALO, bool BLO>
-struct Tile {
-  u32x4 ra[2][2], rb[2][2];  // [hi/lo][chunk]
+__device__ __forceinline__ bool aligned16(const void* p, long long ld) {
+  return ((ld & 7) == 0) && ((reinterpret_cast<uintptr_t>(p) & 15) == 0);
+}
 
-  __device__ __forceinline__ void load(const Operand& A, const Operand& B, int m0, int n0, int k0) {
-    const int t = threadIdx.x;
+// 8 consecutive elements src[0..7] of a storage row, zero beyond `valid` elements.
+__device__ __forceinline__ u32x4 ld8(const u16* __restrict__ src, int valid, bool vec) {
+  if (valid >= 8 && vec) return *reinterpret_cast<const u32x4*>(src);
+  uint32_t w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      const int idx = t + 256 * c;          // 512 chunks = 128 rows x 4 chunks
-      const int r = idx >> 2, kc = (idx & 3) * 8;
-      ra[0][c] = load_chunk(A.hi, A.ld, A.rows, A.K, m0 + r, k0 + kc);
-      if (ALO) ra[1][c] = load_chunk(A.lo, A.ld, A.rows, A.K, m0 + r, k0 + kc);
-      rb[0][c] = load_chunk(B.hi, B.ld, B.rows, B.K, n0 + r, k0 + kc);
-      if (BLO) rb[1][c] = load_chunk(B.lo, B.ld, B.rows, B.K, n0 + r, k0 + kc);
-    }
-  }
-  __device__ __forceinline__ void store(Smem& sm) {
-    const int t = threadIdx.x;
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      const int idx = t + 256 * c;
-      const int r = idx >> 2, kc = (idx & 3) * 8;
-      *reinterpret_cast<u32x4*>(&sm.a[0][r][kc]) = ra[0][c];
-      if (ALO) *reinterpret_cast<u32x4*>(&sm.a[1][r][kc]) = ra[1][c];
-      *reinterpret_cast<u32x4*>(&sm.b[0][r][kc]) = rb[0][c];
-      if (BLO) *reinterpret_cast<u32x4*>(&sm.b[1][r][kc]) = rb[1][c];
-    }
-  }
+  for (int i = 0; i < 8; ++i)
+    if (i < valid) w[i >> 1] |= ((uint32_t)src[i]) << (16 * (i & 1));
+  return u32x4{w[0], w[1], w[2], w[3]};
+}
+
+__device__ __forceinline__ int swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
+
+// LDS geometry of one operand slice with D output-index rows.
+template <int D>
+struct Geo {
+  static constexpr int CP = D + 16;                          // col-layout pitch (bf16)
+  static constexpr int SLOT = (D * RP > BK * CP) ? D * RP : BK * CP;
+  static constexpr int NCH = D * BK / 8 / 256;               // 16-byte chunks per thread
 };
 
-__device__ __forceinline__ bf16x8 frag(const u16* p) {
-  return *reinterpret_cast<const bf16x8*>(p);
-}
+// Global -> registers: one BK-deep k-tile of one operand slice (D x BK elements), as raw 16-byte
+// chunks plus the number of valid elements of each.  VEC: every storage row starts 16-byte aligned
+// and may be read in whole chunks up to the next multiple of 8 past K (or R); the load is issued
+// unconditionally from a clamped address, and the invalid elements are cleared only when the chunk
+// is written to LDS, so nothing waits on the load before the matrix-core work of the k-tile.
+template <int D>
+struct Chunks {
+  u32x4 v[Geo<D>::NCH];
+  int valid[Geo<D>::NCH];
+};
 
-// acc += A(m0.., :) B(n0.., :)^T over k in [0, K).
-template <int TERMS, bool ALO, bool BLO>
-__device__ __forceinline__ void tile_bf16(Smem& sm, const Operand& A, const Operand& B, int m0,
-                                          int n0, f32x4 (&acc)[4][4]) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
-  const int K = A.K;
-  Tile<TERMS, ALO, BLO> tl;
-  tl.load(A, B, m0, n0, 0);
-  const int fr = lane & 15, fk = (lane >> 4) * 8;
-  for (int k0 = 0; k0 < K; k0 += BK) {
-    __syncthreads();
-    tl.store(sm);
-    __syncthreads();
-    if (k0 + BK < K) tl.load(A, B, m0, n0, k0 + BK);
-    bf16x8 ah[4], bh[4];
+template <int D, bool VEC>
+__device__ __forceinline__ void fetch(const u16* __restrict__ base, const Opnd& o, int r0, int k0, Chunks<D>& ch) {
+  const int t = threadIdx.x;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      ah[i] = frag(&sm.a[0][wm + i * 16 + fr][fk]);
-      bh[i] = frag(&sm.b[0][wn + i * 16 + fr][fk]);
+  for (int c = 0; c < Geo<D>::NCH; ++c) {
+    const int idx = t + 256 * c;
+    int gr, gk, valid;
+    long long off;
+    if (!o.col) {  // D rows x 4 chunks along k
+      gr = r0 + (idx >> 2);
+      gk = k0 + (idx & 3) * 8;
+      off = (long long)gr * o.ld + gk;
+      valid = o.K - gk;
+    } else {       // BK k-rows x D/8 chunks along the output index
+      gk = k0 + idx / (D / 8);
+      gr = r0 + (idx % (D / 8)) * 8;
+      off = (long long)gk * o.ld + gr;
+      valid = o.R - gr;
     }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-    if (TERMS >= 2) {
-      if (BLO) {
-        bf16x8 bl[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) bl[j] = frag(&sm.b[1][wn + j * 16 + fr][fk]);
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-      }
-      if (ALO) {
-        bf16x8 al[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) al[i] = frag(&sm.a[1][wm + i * 16 + fr][fk]);
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-      }
-    }
+    const bool ok = gr < o.R && gk < o.K;
+    ch.valid[c] = ok ? (valid < 8 ? valid : 8) : 0;
+    if (VEC) ch.v[c] = *reinterpret_cast<const u32x4*>(base + (ok ? off : 0));
+    else ch.v[c] = ok ? ld8(base + off, valid, false) : u32x4{0u, 0u, 0u, 0u};
   }
 }
 
-__device__ __forceinline__ void zero4(f32x4 (&acc)[4][4]) {
+__device__ __forceinline__ u32x4 mask8(u32x4 v, int valid) {
+  uint32_t w[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    w[i] = (2 * i < valid ? (v[i] & 0xFFFFu) : 0u) | (2 * i + 1 < valid ? (v[i] & 0xFFFF0000u) : 0u);
+  return u32x4{w[0], w[1], w[2], w[3]};
 }
 
+// Row layout: the four 16-byte chunks of row r are stored permuted, chunk c at c ^ swz(r).  Reads
+// of one chunk by 16 consecutive rows and writes of whole rows by consecutive lanes then touch
+// distinct banks whether the LDS is organised as 32 or as 64 four-byte banks.
+template <int D>
+__device__ __forceinline__ void stash(u16* __restrict__ s, bool col, const Chunks<D>& ch) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int c = 0; c < Geo<D>::NCH; ++c) {
+    const int idx = t + 256 * c;
+    u16* dst = !col ? s + (idx >> 2) * RP + (((idx & 3) ^ swz(idx >> 2)) * 8)
+                    : s + (idx / (D / 8)) * Geo<D>::CP + (idx % (D / 8)) * 8;
+    *reinterpret_cast<u32x4*>(dst) = mask8(ch.v[c], ch.valid[c]);
+  }
+}
+
+// MFMA operand fragment for the 16 output rows starting at r: lane l gets row r + l%16 and the
+// eight k values 8*(l/16)..+7 of the current k-tile.
+template <int D>
+__device__ __forceinline__ bf16x8 frag(const u16* __restrict__ s, bool col, int r) {
+  const int lane = threadIdx.x & 63;
+  if (!col) {
+    const int rr = r + (lane & 15);
+    return *reinterpret_cast<const bf16x8*>(s + rr * RP + (((lane >> 4) ^ swz(rr)) * 8));
+  }
+  const int g = lane >> 4, L = lane & 15, j = L >> 2, q = L & 3;
+  typedef __attribute__((address_space(3))) v4s* lds_v4s;
+  const u16* p0 = s + (8 * g + j) * Geo<D>::CP + r + 4 * q;
+  const u16* p1 = s + (8 * g + 4 + j) * Geo<D>::CP + r + 4 * q;
+  union { v4s h[2]; bf16x8 v; } u;
+  u.h[0] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s)(p0));
+  u.h[1] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s)(p1));
+  return u.v;
+}
+
+template <int BM, int BN, bool ALO, bool BLO>
+struct Stage {
+  u16 a[2][ALO ? 2 : 1][Geo<BM>::SLOT];
+  u16 b[2][BLO ? 2 : 1][Geo<BN>::SLOT];
+};
+
+template <int MI, int NI>
+__device__ __forceinline__ void zero(f32x4 (&acc)[MI][NI]) {
+#pragma unroll
+  for (int i = 0; i < MI; ++i)
+#pragma unroll
+    for (int j = 0; j < NI; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+}
+
+// Main loop over a sequence of segments (one per P), each a contraction over k in [0, K), for a
+// BM x BN block tile; 4 waves in 2 x 2, each owning (BM/2) x (BN/2).  acc is reset at the start of
+// each segment when RESET; epi(seg, acc) runs at the end of each.  A(seg, k0) / B(seg, k0) give
+// the operand descriptors of a k-tile (the storage order may change from one k-tile to the next).
+template <int BM, int BN, bool ALO, bool BLO, bool ACOL, bool BCOL, bool RESET, typename FA, typename FB, typename EPI>
+__device__ __forceinline__ void mainloop(Stage<BM, BN, ALO, BLO>& sm, int nseg, int kb, int ke, int m0, int n0, FA A,
+                                         FB B, f32x4 (&acc)[BM / 32][BN / 32], EPI epi) {
+  constexpr int MI = BM / 32, NI = BN / 32;
+  const int wave = threadIdx.x >> 6;
+  const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
+  const int KT = (ke - kb + BK - 1) / BK;
+  const int total = nseg * KT;
+  if (total <= 0) return;
+  Chunks<BM> ra[ALO ? 2 : 1];
+  Chunks<BN> rb[BLO ? 2 : 1];
+  int lseg = 0, lk = kb;
+  auto load = [&]() {
+    Opnd a = A(lseg), b = B(lseg);
+    a.col = ACOL;
+    b.col = BCOL;
+    fetch<BM, false>(a.hi, a, m0, lk, ra[0]);
+    if (ALO) fetch<BM, false>(a.lo, a, m0, lk, ra[ALO ? 1 : 0]);
+    fetch<BN, false>(b.hi, b, n0, lk, rb[0]);
+    if (BLO) fetch<BN, false>(b.lo, b, n0, lk, rb[BLO ? 1 : 0]);
+    lk += BK;
+    if (lk >= ke) { lk = kb; ++lseg; }
+  };
+  auto store = [&](int buf) {
+    stash<BM>(sm.a[buf][0], ACOL, ra[0]);
+    if (ALO) stash<BM>(sm.a[buf][ALO ? 1 : 0], ACOL, ra[ALO ? 1 : 0]);
+    stash<BN>(sm.b[buf][0], BCOL, rb[0]);
+    if (BLO) stash<BN>(sm.b[buf][BLO ? 1 : 0], BCOL, rb[BLO ? 1 : 0]);
+  };
+  load();
+  store(0);
+  __syncthreads();
+  if (RESET) zero(acc);
+  int seg = 0, kt = 0;
+  for (int it = 0; it < total; ++it) {
+    const int buf = it & 1;
+    const bool more = it + 1 < total;
+    if (more) load();
+    bf16x8 ah[MI], bh[NI];
+#pragma unroll
+    for (int i = 0; i < MI; ++i) ah[i] = frag<BM>(sm.a[buf][0], ACOL, wm + 16 * i);
+#pragma unroll
+    for (int j = 0; j < NI; ++j) bh[j] = frag<BN>(sm.b[buf][0], BCOL, wn + 16 * j);
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+      for (int j = 0; j < NI; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+    if (BLO) {
+      bf16x8 bl[NI];
+#pragma unroll
+      for (int j = 0; j < NI; ++j) bl[j] = frag<BN>(sm.b[buf][BLO ? 1 : 0], BCOL, wn + 16 * j);
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < NI; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+    }
+    if (ALO) {
+#pragma unroll
+      for (int i = 0; i < MI; ++i) {
+        const bf16x8 al = frag<BM>(sm.a[buf][ALO ? 1 : 0], ACOL, wm + 16 * i);
+#pragma unroll
+        for (int j = 0; j < NI; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+      }
+    }
+    if (more) store(buf ^ 1);
+    if (++kt == KT) {
+      epi(seg, acc);
+      if (RESET) zero(acc);
+      kt = 0;
+      ++seg;
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Direct-to-LDS pipeline (aligned operands).  Each k-tile slice is fetched by buffer loads that
+// write LDS directly (16 bytes per lane, a wave filling one contiguous 1 KB block), S stages deep,
+// so S-1 k-tiles are in flight while the matrix cores work on the oldest one; no registers are
+// spent on staging.  Loads past the buffer's record limit return zeros.  Requirements: every
+// storage row starts 16-byte aligned; rows of the workspace operands are zero-padded to a
+// multiple of 32 in k, so the k-tail of the last tile contributes nothing.
+// Slice layouts (no padding): row mode element (r, k) at r*BK + ((k/8) ^ swz(r))*8 + k%8;
+// col mode element (kr, r) at kr*D + ((r/8) ^ cswz(kr))*8 + r%8.
+__device__ __forceinline__ int cswz(int kr) { return 2 * (kr & 3); }
+
+constexpr int waitcnt_vm(int n) {
+  // gfx9 s_waitcnt immediate: vmcnt[3:0] bits 3:0, vmcnt[5:4] bits 15:14; expcnt and lgkmcnt maxed
+  return (n & 0xF) | ((n >> 4) << 14) | (0x7 << 4) | (0xF << 8);
+}
+
+struct Rsrc {
+  __amdgpu_buffer_rsrc_t r;
+};
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, long long bytes) {
+  const int nrec = bytes > 0x7FFFFFFFLL ? 0x7FFFFFFF : (int)bytes;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, nrec, 0x00020000);
+}
+
+// Operand of one k-tile for the direct path: slice base, its record limit, storage layout.
+struct DOpnd {
+  const u16* hi;
+  const u16* lo;
+  long long ld;
+  long long bytes;   // readable bytes from hi (and from lo) onwards
+};
+
+template <int D>
+__device__ __forceinline__ void dl_issue(u16* lds_slice, const u16* base, long long bytes, long long ld, const bool col,
+                                         int r0, int k0) {
+  constexpr int PER_WAVE = D / 64;   // (D * BK / 8 chunks) / 64 lanes / 4 waves
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(base, bytes);
+#pragma unroll
+  for (int i = 0; i < PER_WAVE; ++i) {
+    const int blk = wave * PER_WAVE + i;
+    const int q = blk * 64 + lane;
+    long long off;
+    if (!col) {
+      const int row = q >> 2, c = (q & 3) ^ swz(q >> 2);
+      off = (long long)(r0 + row) * ld + k0 + c * 8;
+    } else {
+      const int kr = q / (D / 8), c = (q % (D / 8)) ^ cswz(q / (D / 8));
+      off = (long long)(k0 + kr) * ld + r0 + c * 8;
+    }
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(lds_slice + blk * 512),
+                                             16, (unsigned)(off * 2), 0, 0, 0);
+  }
+}
+
+template <int D, bool COL>
+__device__ __forceinline__ bf16x8 dl_frag(const u16* __restrict__ s, int r) {
+  const int lane = threadIdx.x & 63;
+  if constexpr (!COL) {
+    const int rr = r + (lane & 15);
+    return *reinterpret_cast<const bf16x8*>(s + rr * BK + (((lane >> 4) ^ swz(rr)) * 8));
+  }
+  const int g = lane >> 4, L = lane & 15, j = L >> 2, q = L & 3;
+  typedef __attribute__((address_space(3))) v4s* lds_v4s;
+  const int m = r + 4 * q;
+  const int k0 = 8 * g + j, k1 = 8 * g + 4 + j;
+  const u16* p0 = s + k0 * D + (((m >> 3) ^ cswz(k0)) << 3) + (m & 7);
+  const u16* p1 = s + k1 * D + (((m >> 3) ^ cswz(k1)) << 3) + (m & 7);
+  union { v4s h[2]; bf16x8 v; } u;
+  u.h[0] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s)(p0));
+  u.h[1] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s)(p1));
+  return u.v;
+}
+
+// Pipeline depth that fits `budget` bytes of LDS (at most 4 stages).
+constexpr int ring_depth(int BM, int BN, bool ALO, bool BLO, int budget) {
+  const int stage = 2 * BK * (BM * (ALO ? 2 : 1) + BN * (BLO ? 2 : 1));
+  const int s = budget / stage;
+  return s > 4 ? 4 : s;
+}
+
+template <int BM, int BN, bool ALO, bool BLO, int S>
+struct Ring {
+  u16 a[S][ALO ? 2 : 1][BM * BK];
+  u16 b[S][BLO ? 2 : 1][BN * BK];
+};
+
+// Contraction over segments seg = 0..nseg-1 and k in [kb, ke) of each; ACOL / BCOL fix the storage
+// order of the operands at compile time.
+template <int BM, int BN, bool ALO, bool BLO, int S, bool ACOL, bool BCOL, bool RESET, typename FA, typename FB,
+          typename EPI>
+__device__ __forceinline__ void mainloop_dl(Ring<BM, BN, ALO, BLO, S>& sm, int nseg, int kb, int ke, int m0, int n0,
+                                            FA A, FB B, f32x4 (&acc)[BM / 32][BN / 32], EPI epi) {
+  constexpr int MI = BM / 32, NI = BN / 32;
+  constexpr int L = (ALO ? 2 : 1) * (BM / 64) + (BLO ? 2 : 1) * (BN / 64);   // loads per wave per tile
+  static_assert(L * (S - 2) < 64, "vmcnt range");
+  const int wave = threadIdx.x >> 6;
+  const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
+  const int KT = (ke - kb + BK - 1) / BK;
+  const int total = nseg * KT;
+  if (total <= 0) return;
+  int lseg = 0, lk = kb;
+  auto issue = [&](int stage) {
+    const DOpnd a = A(lseg), b = B(lseg);
+    dl_issue<BM>(sm.a[stage][0], a.hi, a.bytes, a.ld, ACOL, m0, lk);
+    if (ALO) dl_issue<BM>(sm.a[stage][ALO ? 1 : 0], a.lo, a.bytes, a.ld, ACOL, m0, lk);
+    dl_issue<BN>(sm.b[stage][0], b.hi, b.bytes, b.ld, BCOL, n0, lk);
+    if (BLO) dl_issue<BN>(sm.b[stage][BLO ? 1 : 0], b.lo, b.bytes, b.ld, BCOL, n0, lk);
+    lk += BK;
+    if (lk >= ke) { lk = kb; ++lseg; }
+  };
+#pragma unroll
+  for (int t = 0; t < S - 1; ++t)
+    if (t < total) issue(t);
+  if (RESET) zero(acc);
+  int seg = 0, kt = 0, stage = 0;
+  for (int it = 0; it < total; ++it) {
+    if (it + S - 2 < total) __builtin_amdgcn_s_waitcnt(waitcnt_vm(L * (S - 2)));
+    else __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+    __builtin_amdgcn_s_barrier();
+    if (it + S - 1 < total) issue((stage + S - 1) % S);
+    bf16x8 ah[MI], bh[NI];
+#pragma unroll
+    for (int i = 0; i < MI; ++i) ah[i] = dl_frag<BM, ACOL>(sm.a[stage][0], wm + 16 * i);
+#pragma unroll
+    for (int j = 0; j < NI; ++j) bh[j] = dl_frag<BN, BCOL>(sm.b[stage][0], wn + 16 * j);
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+      for (int j = 0; j < NI; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+    if (BLO) {
+      bf16x8 bl[NI];
+#pragma unroll
+      for (int j = 0; j < NI; ++j) bl[j] = dl_frag<BN, BCOL>(sm.b[stage][BLO ? 1 : 0], wn + 16 * j);
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < NI; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+    }
+    if (ALO) {
+#pragma unroll
+      for (int i = 0; i < MI; ++i) {
+        const bf16x8 al = dl_frag<BM, ACOL>(sm.a[stage][ALO ? 1 : 0], wm + 16 * i);
+#pragma unroll
+        for (int j = 0; j < NI; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+      }
+    }
+    if (++kt == KT) {
+      epi(seg, acc);
+      if (RESET) zero(acc);
+      kt = 0;
+      ++seg;
+    }
+    stage = (stage + 1 == S) ? 0 : stage + 1;
+  }
+  __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+  __builtin_amdgcn_s_barrier();
+}
+
+// Output row / column of component j of acc[i][jn] relative to the block tile origin.
+template <int BM>
 __device__ __forceinline__ int row_of(int i, int j) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  return (wave >> 1) * 64 + i * 16 + 4 * (lane >> 4) + j;
+  return (wave >> 1) * (BM / 2) + i * 16 + 4 * (lane >> 4) + j;
 }
+template <int BN>
 __device__ __forceinline__ int col_of(int jn) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  return (wave & 1) * 64 + jn * 16 + (lane & 15);
+  return (wave & 1) * (BN / 2) + jn * 16 + (lane & 15);
 }
 
 __device__ __forceinline__ void tri_tile(int t, int& tm, int& tn) {
@@ -160,119 +424,152 @@ __device__ __forceinline__ void tri_tile(int t, int& tm, int& tn) {
   tn = t - r * (r + 1) / 2;
 }
 
-// gemm1: XT_P[p][mu] = sum_nu Ct[p][nu] B_P[mu][nu]; written split as XT (p-major) and X (mu-major).
-template <int TERMS, bool BLO>
-__global__ __launch_bounds__(256) void gemm1_kernel(int nbf, int nact, const u16* __restrict__ ct_hi,
-                                                    const u16* __restrict__ ct_lo, int ldk,
-                                                    const u16* __restrict__ b_hi,
-                                                    const u16* __restrict__ b_lo, long long bstride,
-                                                    int ldb, u16* __restrict__ xt_hi,
-                                                    u16* __restrict__ xt_lo, int ldx,
-                                                    u16* __restrict__ x_hi, u16* __restrict__ x_lo,
-                                                    int ldxx) {
-  __shared__ Smem sm;
-  const int tiles_n = (nbf + BN - 1) / BN;
-  const int m0 = (blockIdx.x / tiles_n) * BM, n0 = (blockIdx.x % tiles_n) * BN;
-  const long long P = blockIdx.y;
-  Operand A{ct_hi, ct_lo, ldk, nact, nbf};
-  Operand B{b_hi + P * bstride, BLO ? b_lo + P * bstride : nullptr, ldb, nbf, nbf};
-  f32x4 acc[4][4];
-  zero4(acc);
-  tile_bf16<TERMS, (TERMS >= 2), BLO>(sm, A, B, m0, n0, acc);
-  u16* XTh = xt_hi + P * (long long)nact * ldx;
-  u16* XTl = xt_lo ? xt_lo + P * (long long)nact * ldx : nullptr;
-  u16* Xh = x_hi + P * (long long)nbf * ldxx;
-  u16* Xl = x_lo ? x_lo + P * (long long)nbf * ldxx : nullptr;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int jn = 0; jn < 4; ++jn) {
-      const int mu = n0 + col_of(jn);
-      const int pb = m0 + row_of(i, 0);
-      if (mu >= nbf) continue;
-      u16 h[4], l[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (TERMS == 1) { h[j] = f32_to_bf16_bits(acc[i][jn][j]); l[j] = 0; }
-        else split_f32(acc[i][jn][j], h[j], l[j]);
-      }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int p = pb + j;
-        if (p < nact) {
-          XTh[(long long)p * ldx + mu] = h[j];
-          if (XTl) XTl[(long long)p * ldx + mu] = l[j];
-        }
-      }
-      if (pb + 3 < nact) {  // four consecutive p of row mu: one 8-byte store per array
-        uint2 vh = {(uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16)};
-        *reinterpret_cast<uint2*>(&Xh[(long long)mu * ldxx + pb]) = vh;
-        if (Xl) {
-          uint2 vl = {(uint32_t)l[0] | ((uint32_t)l[1] << 16), (uint32_t)l[2] | ((uint32_t)l[3] << 16)};
-          *reinterpret_cast<uint2*>(&Xl[(long long)mu * ldxx + pb]) = vl;
-        }
-      } else {
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          if (pb + j < nact) {
-            Xh[(long long)mu * ldxx + pb + j] = h[j];
-            if (Xl) Xl[(long long)mu * ldxx + pb + j] = l[j];
-          }
-      }
-    }
+// Block id -> work item, each XCD taking one contiguous range of items (-1: padding block).
+__device__ __forceinline__ int xcd_item(int total) {
+  const int per = (total + NXCD - 1) / NXCD;
+  const int w = (int)(blockIdx.x % NXCD) * per + (int)(blockIdx.x / NXCD);
+  return w < total ? w : -1;
 }
 
-// gemm2: b_P = Ct XT_P^T on lower tiles; Kpart[s] += sum_{P in s} b^2 (lower triangle, summed over
-// the successive P-chunks of one call), D[P][p] = b_pp,
-// W_P = b o beta (symmetric, each unordered pair written once, split hi/lo).
-template <int TERMS>
-__global__ __launch_bounds__(256) void gemm2_kernel(int nbf, int nact, int np, int nsplit,
-                                                    const u16* __restrict__ ct_hi,
-                                                    const u16* __restrict__ ct_lo, int ldk,
-                                                    const u16* __restrict__ xt_hi,
-                                                    const u16* __restrict__ xt_lo, int ldx,
-                                                    const float* __restrict__ beta32,
-                                                    double* __restrict__ Kpart,
-                                                    double* __restrict__ Dc,
-                                                    u16* __restrict__ w_hi, u16* __restrict__ w_lo,
-                                                    int ldw) {
-  __shared__ Smem sm;
+// Shapes of the workspace operands: Ct is nact32 x ldk, each XT_P is nact32 x ldx and each W_P is
+// nact32 x ldw (nact32 = nact rounded up to 32), row-major, zero outside the valid block.
+struct WS {
+  int nact32;
+  long long ct_bytes;   // bytes of one Ct array (hi or lo)
+  long long xt_bytes;   // bytes of one XT array (all P of the chunk)
+  long long w_bytes;    // bytes of one W array
+};
+
+// gemm1: XT_P[p][mu] = sum_nu Ct[p][nu] B_P[mu][nu], written as a hi/lo pair.  Tile 128 (p) x G1N (mu).
+template <int TERMS, bool BLO, int G1N, int MINB, bool VEC>
+__global__ __launch_bounds__(256, MINB) void gemm1_kernel(int nbf, int nact, int np, const u16* __restrict__ ct_hi,
+                                                       const u16* __restrict__ ct_lo, int ldk,
+                                                       const u16* __restrict__ b_hi, const u16* __restrict__ b_lo,
+                                                       long long bstride, int ldb, long long b_bytes,
+                                                       u16* __restrict__ xt_hi, u16* __restrict__ xt_lo, int ldx,
+                                                       WS ws) {
+  constexpr bool ALO = TERMS >= 2;
+  constexpr int G1M = 128;
+  const int tm_n = (nact + G1M - 1) / G1M, tn_n = (nbf + G1N - 1) / G1N;
+  const int w = xcd_item(np * tm_n * tn_n);
+  if (w < 0) return;
+  const int P = w / (tm_n * tn_n), tile = w % (tm_n * tn_n);
+  const int m0 = (tile / tn_n) * G1M, n0 = (tile % tn_n) * G1N;
+  const long long xoff = (long long)P * ws.nact32 * ldx;
+  u16* XTh = xt_hi + xoff;
+  u16* XTl = xt_lo ? xt_lo + xoff : nullptr;
+  f32x4 acc[G1M / 32][G1N / 32];
+  auto epi = [&](int, f32x4(&a)[G1M / 32][G1N / 32]) {
+#pragma unroll
+    for (int i = 0; i < G1M / 32; ++i)
+#pragma unroll
+      for (int jn = 0; jn < G1N / 32; ++jn) {
+        const int mu = n0 + col_of<G1N>(jn);
+        if (mu >= nbf) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int p = m0 + row_of<G1M>(i, j);
+          if (p >= nact) continue;
+          u16 h, l;
+          if (TERMS == 1) { h = f32_to_bf16_bits(a[i][jn][j]); l = 0; }
+          else split_f32(a[i][jn][j], h, l);
+          XTh[(long long)p * ldx + mu] = h;
+          if (XTl) XTl[(long long)p * ldx + mu] = l;
+        }
+      }
+  };
+  if constexpr (VEC) {
+    // two blocks per compute unit for the 128 x 128 tile, one for the wide tile
+    constexpr int S = ring_depth(G1M, G1N, ALO, BLO, G1N == 128 ? 81920 : 163840);
+    __shared__ Ring<G1M, G1N, ALO, BLO, S> sm;
+    auto A = [&](int) { return DOpnd{ct_hi, ct_lo, ldk, ws.ct_bytes}; };
+    auto B = [&](int) {
+      const long long o = (long long)P * bstride;
+      return DOpnd{b_hi + o, BLO ? b_lo + o : nullptr, ldb, b_bytes - 2 * o};
+    };
+    mainloop_dl<G1M, G1N, ALO, BLO, S, false, false, true>(sm, 1, 0, nbf, m0, n0, A, B, acc, epi);
+  } else {
+    __shared__ Stage<G1M, G1N, ALO, BLO> sm;
+    auto A = [&](int) { return Opnd{ct_hi, ct_lo, ldk, nact, nbf, false}; };
+    auto B = [&](int) {
+      return Opnd{b_hi + (long long)P * bstride, BLO ? b_lo + (long long)P * bstride : nullptr, ldb, nbf, nbf, false};
+    };
+    mainloop<G1M, G1N, ALO, BLO, false, false, true>(sm, 1, 0, nbf, m0, n0, A, B, acc, epi);
+  }
+}
+
+// gemm2: b_P = Ct XT_P^T on lower 128-tiles; Kpart[s] += sum_{P in s} b^2 (lower triangle, summed
+// over the successive P-chunks of one call), D[P][p] = b_pp, W_P = b o beta as a hi/lo pair,
+// stored only for the lower tiles (diagonal tiles in full): the upper blocks are read transposed.
+template <int TERMS, bool VEC>
+__global__ __launch_bounds__(256, 1) void gemm2_kernel(int nbf, int nact, int np, int nsplit,
+                                                       const u16* __restrict__ ct_hi, const u16* __restrict__ ct_lo,
+                                                       int ldk, const u16* __restrict__ xt_hi,
+                                                       const u16* __restrict__ xt_lo, int ldx,
+                                                       const float* __restrict__ beta32, double* __restrict__ Kpart,
+                                                       double* __restrict__ Dc, u16* __restrict__ w_hi,
+                                                       u16* __restrict__ w_lo, int ldw, WS ws) {
+  constexpr bool LO = TERMS >= 3;
+  __shared__ float sbeta[T2][T2];
+  const int tt = (nact + T2 - 1) / T2;
+  const int ntri = tt * (tt + 1) / 2;
+  const int w = xcd_item(nsplit * ntri);
+  if (w < 0) return;
+  const int s = w / ntri;
   int tm, tn;
-  tri_tile(blockIdx.x, tm, tn);
-  const int m0 = tm * BM, n0 = tn * BN;
-  const int s = blockIdx.y;
+  tri_tile(w % ntri, tm, tn);
+  const int m0 = tm * T2, n0 = tn * T2;
   const int pb = (int)((long long)np * s / nsplit), pe = (int)((long long)np * (s + 1) / nsplit);
-  f32x4 kacc[4][4];
-  zero4(kacc);
-  Operand A{ct_hi, ct_lo, ldk, nact, nbf};
-  for (int P = pb; P < pe; ++P) {
-    const long long off = (long long)P * nact * ldx;
-    Operand B{xt_hi + off, xt_lo ? xt_lo + off : nullptr, ldx, nact, nbf};
-    f32x4 acc[4][4];
-    zero4(acc);
-    tile_bf16<TERMS, (TERMS >= 2), (TERMS >= 3)>(sm, A, B, m0, n0, acc);
-    u16* Wh = w_hi + (long long)P * nact * ldw;
-    u16* Wl = w_lo ? w_lo + (long long)P * nact * ldw : nullptr;
+  for (int e = threadIdx.x; e < T2 * T2; e += 256) {
+    const int r = e / T2, c = e % T2;
+    const int p = m0 + r, q = n0 + c;
+    sbeta[r][c] = (p < nact && q < nact) ? beta32[(long long)p * nact + q] : 0.f;
+  }
+  __syncthreads();
+  f32x4 kacc[4][4], acc[4][4];
+  zero(kacc);
+  const bool diag = (tm == tn);
+  auto epi = [&](int seg, f32x4(&a)[4][4]) {
+    const int P = pb + seg;
+    u16* Wh = w_hi + (long long)P * ws.nact32 * ldw;
+    u16* Wl = LO ? w_lo + (long long)P * ws.nact32 * ldw : nullptr;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int jn = 0; jn < 4; ++jn)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int p = m0 + row_of(i, j), q = n0 + col_of(jn);
-          const float b = acc[i][jn][j];
+          const int r = row_of<T2>(i, j), c = col_of<T2>(jn);
+          const int p = m0 + r, q = n0 + c;
+          const float b = a[i][jn][j];
           kacc[i][jn][j] += b * b;
-          if (p < nact && q <= p) {
-            const float w = b * beta32[(long long)p * nact + q];
+          if (p < nact && q < nact) {
+            const float wv = b * sbeta[r][c];
             u16 h, l;
-            if (TERMS == 1) { h = f32_to_bf16_bits(w); l = 0; }
-            else split_f32(w, h, l);
+            if (!LO) { h = f32_to_bf16_bits(wv); l = 0; }
+            else split_f32(wv, h, l);
             Wh[(long long)p * ldw + q] = h;
-            Wh[(long long)q * ldw + p] = h;
-            if (Wl) { Wl[(long long)p * ldw + q] = l; Wl[(long long)q * ldw + p] = l; }
-            if (p == q) Dc[(long long)P * nact + p] = (double)b;
+            if (LO) Wl[(long long)p * ldw + q] = l;
+            if (diag && p == q) Dc[(long long)P * nact + p] = (double)b;
           }
         }
+  };
+  if constexpr (VEC) {
+    __shared__ Ring<T2, T2, LO, LO, 3> sm;
+    auto A = [&](int) { return DOpnd{ct_hi, ct_lo, ldk, ws.ct_bytes}; };
+    auto B = [&](int seg) {
+      const long long off = (long long)(pb + seg) * ws.nact32 * ldx;
+      return DOpnd{xt_hi + off, LO ? xt_lo + off : nullptr, ldx, ws.xt_bytes - 2 * off};
+    };
+    mainloop_dl<T2, T2, LO, LO, 3, false, false, true>(sm, pe - pb, 0, nbf, m0, n0, A, B, acc, epi);
+  } else {
+    __shared__ Stage<T2, T2, LO, LO> sm;
+    auto A = [&](int) { return Opnd{ct_hi, ct_lo, ldk, nact, nbf, false}; };
+    auto B = [&](int seg) {
+      const long long off = (long long)(pb + seg) * ws.nact32 * ldx;
+      return Opnd{xt_hi + off, LO ? xt_lo + off : nullptr, ldx, nact, nbf, false};
+    };
+    mainloop<T2, T2, LO, LO, false, false, true>(sm, pe - pb, 0, nbf, m0, n0, A, B, acc, epi);
   }
   double* Kp = Kpart + (long long)s * nact * nact;
 #pragma unroll
@@ -281,81 +578,159 @@ __global__ __launch_bounds__(256) void gemm2_kernel(int nbf, int nact, int np, i
     for (int jn = 0; jn < 4; ++jn)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int p = m0 + row_of(i, j), q = n0 + col_of(jn);
+        const int p = m0 + row_of<T2>(i, j), q = n0 + col_of<T2>(jn);
         if (p < nact && q <= p) Kp[(long long)p * nact + q] += (double)kacc[i][jn][j];
       }
 }
 
-// gemm3: Ypart[s][mu][q] = sum_{P in s} sum_r X_P[mu][r] W_P[q][r]  (W symmetric).
-template <int TERMS>
-__global__ __launch_bounds__(256) void gemm3_kernel(int nbf, int nact, int np, int nsplit,
-                                                    const u16* __restrict__ x_hi,
-                                                    const u16* __restrict__ x_lo, int ldxx,
-                                                    const u16* __restrict__ w_hi,
-                                                    const u16* __restrict__ w_lo, int ldw,
-                                                    float* __restrict__ Ypart) {
-  __shared__ Smem sm;
-  const int tiles_n = (nact + BN - 1) / BN;
-  const int m0 = (blockIdx.x / tiles_n) * BM, n0 = (blockIdx.x % tiles_n) * BN;
-  const int s = blockIdx.y;
+// gemm3: Ypart[s][mu][q] = sum_{P in s} sum_r XT_P[r][mu] W_P[q][r].  XT is read as a col operand;
+// W[q][r] is read from row q for r-tiles up to q's 128-tile and from row r (transposed) beyond it.
+// Tile G3M (mu) x 128 (q).
+template <int TERMS, int G3M, int MINB, bool VEC>
+__global__ __launch_bounds__(256, MINB) void gemm3_kernel(int nbf, int nact, int np, int nsplit,
+                                                       const u16* __restrict__ xt_hi, const u16* __restrict__ xt_lo,
+                                                       int ldx, const u16* __restrict__ w_hi,
+                                                       const u16* __restrict__ w_lo, int ldw,
+                                                       float* __restrict__ Ypart, WS ws) {
+  constexpr bool LO = TERMS >= 3;
+  constexpr int G3N = T2;
+  const int tm_n = (nbf + G3M - 1) / G3M, tn_n = (nact + G3N - 1) / G3N;
+  const int w = xcd_item(nsplit * tm_n * tn_n);
+  if (w < 0) return;
+  const int s = w / (tm_n * tn_n), tile = w % (tm_n * tn_n);
+  const int m0 = (tile / tn_n) * G3M, n0 = (tile % tn_n) * G3N;
   const int pb = (int)((long long)np * s / nsplit), pe = (int)((long long)np * (s + 1) / nsplit);
-  f32x4 acc[4][4];
-  zero4(acc);
-  for (int P = pb; P < pe; ++P) {
-    const long long ox = (long long)P * nbf * ldxx, ow = (long long)P * nact * ldw;
-    Operand A{x_hi + ox, x_lo ? x_lo + ox : nullptr, ldxx, nbf, nact};
-    Operand B{w_hi + ow, w_lo ? w_lo + ow : nullptr, ldw, nact, nact};
-    tile_bf16<TERMS, (TERMS >= 2), (TERMS >= 3)>(sm, A, B, m0, n0, acc);
+  f32x4 acc[G3M / 32][G3N / 32];
+  zero(acc);
+  auto none = [&](int, f32x4(&)[G3M / 32][G3N / 32]) {};
+  // W[q][r] comes from row q while r < n0 + 128 (lower and diagonal tiles) and from row r
+  // (transposed) beyond: two passes over the P-range, one per storage order
+  const int ksplit = min(nact, n0 + T2);
+  if constexpr (VEC) {
+    constexpr int S = ring_depth(G3M, G3N, LO, LO, 163840);
+    __shared__ Ring<G3M, G3N, LO, LO, S> sm;
+    auto A = [&](int seg) {
+      const long long off = (long long)(pb + seg) * ws.nact32 * ldx;
+      return DOpnd{xt_hi + off, LO ? xt_lo + off : nullptr, ldx, ws.xt_bytes - 2 * off};
+    };
+    auto B = [&](int seg) {
+      const long long off = (long long)(pb + seg) * ws.nact32 * ldw;
+      return DOpnd{w_hi + off, LO ? w_lo + off : nullptr, ldw, ws.w_bytes - 2 * off};
+    };
+    mainloop_dl<G3M, G3N, LO, LO, S, true, false, false>(sm, pe - pb, 0, ksplit, m0, n0, A, B, acc, none);
+    if (ksplit < nact)
+      mainloop_dl<G3M, G3N, LO, LO, S, true, true, false>(sm, pe - pb, ksplit, nact, m0, n0, A, B, acc, none);
+  } else {
+    __shared__ Stage<G3M, G3N, LO, LO> sm;
+    auto A = [&](int seg) {
+      const long long off = (long long)(pb + seg) * ws.nact32 * ldx;
+      return Opnd{xt_hi + off, LO ? xt_lo + off : nullptr, ldx, nbf, nact, true};
+    };
+    auto B = [&](int seg) {
+      const long long off = (long long)(pb + seg) * ws.nact32 * ldw;
+      return Opnd{w_hi + off, LO ? w_lo + off : nullptr, ldw, nact, nact, false};
+    };
+    mainloop<G3M, G3N, LO, LO, true, false, false>(sm, pe - pb, 0, ksplit, m0, n0, A, B, acc, none);
+    if (ksplit < nact)
+      mainloop<G3M, G3N, LO, LO, true, true, false>(sm, pe - pb, ksplit, nact, m0, n0, A, B, acc, none);
   }
   float* Y = Ypart + (long long)s * nbf * nact;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < G3M / 32; ++i)
 #pragma unroll
-    for (int jn = 0; jn < 4; ++jn)
+    for (int jn = 0; jn < G3N / 32; ++jn)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int m = m0 + row_of(i, j), n = n0 + col_of(jn);
+        const int m = m0 + row_of<G3M>(i, j), n = n0 + col_of<G3N>(jn);
         if (m < nbf && n < nact) Y[(long long)m * nact + n] = acc[i][jn][j];
       }
 }
 
+inline dim3 xcd_grid(long long items) { return dim3((unsigned)(cdiv(items, NXCD) * NXCD)); }
+
 }  // namespace
 
-hipError_t df_bf16_gemm1(hipStream_t s, int nbf, int nact, int np, int terms, SplitPtr Ct, int ldk,
-                         SplitPtr Bp, long long bstride, int ldb, u16* XT_hi, u16* XT_lo, int ldx,
-                         u16* X_hi, u16* X_lo, int ldxx) {
-  if (np <= 0) return hipSuccess;
-  dim3 grid(cdiv(nact, BM) * cdiv(nbf, BN), np);
-  if (terms == 1)
-    hipLaunchKernelGGL((gemm1_kernel<1, false>), grid, dim3(256), 0, s, nbf, nact, Ct.hi, Ct.lo, ldk, Bp.hi, Bp.lo, bstride, ldb, XT_hi, XT_lo, ldx, X_hi, X_lo, ldxx);
-  else if (Bp.lo == nullptr)
-    hipLaunchKernelGGL((gemm1_kernel<2, false>), grid, dim3(256), 0, s, nbf, nact, Ct.hi, Ct.lo, ldk, Bp.hi, Bp.lo, bstride, ldb, XT_hi, XT_lo, ldx, X_hi, X_lo, ldxx);
+inline bool al16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+inline WS make_ws(const WsDims& d) { return WS{d.nact32, d.ct_bytes, d.xt_bytes, d.w_bytes}; }
+
+template <int TERMS, bool BLO, int G1N, int MINB>
+static void launch_g1(hipStream_t s, int nbf, int nact, int np, SplitPtr Ct, int ldk, SplitPtr Bp, long long bstride,
+                      int ldb, long long b_bytes, u16* XT_hi, u16* XT_lo, int ldx, const WsDims& d) {
+  const dim3 grid = xcd_grid((long long)np * cdiv(nact, 128) * cdiv(nbf, G1N));
+  // direct-to-LDS needs 16-byte aligned rows of the caller's B (nbf % 8 == 0)
+  const bool vec = (ldb % 8 == 0) && (nbf % 8 == 0) && (bstride % 8 == 0) && al16(Bp.hi) && (!Bp.lo || al16(Bp.lo)) &&
+                   al16(Ct.hi) && (!Ct.lo || al16(Ct.lo)) && (ldk % 32 == 0) && (ldx % 32 == 0);
+  if (vec)
+    hipLaunchKernelGGL((gemm1_kernel<TERMS, BLO, G1N, MINB, true>), grid, dim3(256), 0, s, nbf, nact, np, Ct.hi, Ct.lo,
+                       ldk, Bp.hi, Bp.lo, bstride, ldb, b_bytes, XT_hi, XT_lo, ldx, make_ws(d));
   else
-    hipLaunchKernelGGL((gemm1_kernel<3, true>), grid, dim3(256), 0, s, nbf, nact, Ct.hi, Ct.lo, ldk, Bp.hi, Bp.lo, bstride, ldb, XT_hi, XT_lo, ldx, X_hi, X_lo, ldxx);
+    hipLaunchKernelGGL((gemm1_kernel<TERMS, BLO, G1N, MINB, false>), grid, dim3(256), 0, s, nbf, nact, np, Ct.hi, Ct.lo,
+                       ldk, Bp.hi, Bp.lo, bstride, ldb, b_bytes, XT_hi, XT_lo, ldx, make_ws(d));
+}
+
+hipError_t df_bf16_gemm1(hipStream_t s, int nbf, int nact, int np, int terms, SplitPtr Ct, int ldk, SplitPtr Bp,
+                         long long bstride, int ldb, long long b_bytes, u16* XT_hi, u16* XT_lo, int ldx, int variant,
+                         const WsDims& d) {
+  if (np <= 0) return hipSuccess;
+  const bool wide = (variant == 1);
+  if (terms == 1) {
+    if (wide) launch_g1<1, false, 256, 1>(s, nbf, nact, np, Ct, ldk, Bp, bstride, ldb, b_bytes, XT_hi, XT_lo, ldx, d);
+    else launch_g1<1, false, 128, 2>(s, nbf, nact, np, Ct, ldk, Bp, bstride, ldb, b_bytes, XT_hi, XT_lo, ldx, d);
+  } else if (Bp.lo == nullptr) {
+    if (wide) launch_g1<2, false, 256, 1>(s, nbf, nact, np, Ct, ldk, Bp, bstride, ldb, b_bytes, XT_hi, XT_lo, ldx, d);
+    else launch_g1<2, false, 128, 2>(s, nbf, nact, np, Ct, ldk, Bp, bstride, ldb, b_bytes, XT_hi, XT_lo, ldx, d);
+  } else {
+    if (wide) launch_g1<3, true, 256, 1>(s, nbf, nact, np, Ct, ldk, Bp, bstride, ldb, b_bytes, XT_hi, XT_lo, ldx, d);
+    else launch_g1<3, true, 128, 2>(s, nbf, nact, np, Ct, ldk, Bp, bstride, ldb, b_bytes, XT_hi, XT_lo, ldx, d);
+  }
   return hipGetLastError();
 }
 
-hipError_t df_bf16_gemm2(hipStream_t s, int nbf, int nact, int np, int nsplit, int terms,
-                         SplitPtr Ct, int ldk, SplitPtr XT, int ldx, const float* beta32,
-                         double* Kpart, double* Dchunk, u16* W_hi, u16* W_lo, int ldw) {
+hipError_t df_bf16_gemm2(hipStream_t s, int nbf, int nact, int np, int nsplit, int terms, SplitPtr Ct, int ldk,
+                         SplitPtr XT, int ldx, const float* beta32, double* Kpart, double* Dchunk, u16* W_hi,
+                         u16* W_lo, int ldw, const WsDims& d) {
   if (np <= 0) return hipSuccess;
-  const int t = cdiv(nact, BM);
-  dim3 grid(t * (t + 1) / 2, nsplit);
-  if (terms == 1)
-    hipLaunchKernelGGL((gemm2_kernel<1>), grid, dim3(256), 0, s, nbf, nact, np, nsplit, Ct.hi, Ct.lo, ldk, XT.hi, XT.lo, ldx, beta32, Kpart, Dchunk, W_hi, W_lo, ldw);
-  else
-    hipLaunchKernelGGL((gemm2_kernel<3>), grid, dim3(256), 0, s, nbf, nact, np, nsplit, Ct.hi, Ct.lo, ldk, XT.hi, XT.lo, ldx, beta32, Kpart, Dchunk, W_hi, W_lo, ldw);
+  const int t = cdiv(nact, T2);
+  const dim3 grid = xcd_grid((long long)nsplit * t * (t + 1) / 2);
+  const bool vec = (ldk % 32 == 0) && (ldx % 32 == 0) && al16(Ct.hi) && (!Ct.lo || al16(Ct.lo)) && al16(XT.hi) &&
+                   (!XT.lo || al16(XT.lo));
+  const WS ws = make_ws(d);
+  if (terms == 1) {
+    if (vec) hipLaunchKernelGGL((gemm2_kernel<1, true>), grid, dim3(256), 0, s, nbf, nact, np, nsplit, Ct.hi, Ct.lo, ldk, XT.hi, XT.lo, ldx, beta32, Kpart, Dchunk, W_hi, W_lo, ldw, ws);
+    else hipLaunchKernelGGL((gemm2_kernel<1, false>), grid, dim3(256), 0, s, nbf, nact, np, nsplit, Ct.hi, Ct.lo, ldk, XT.hi, XT.lo, ldx, beta32, Kpart, Dchunk, W_hi, W_lo, ldw, ws);
+  } else {
+    if (vec) hipLaunchKernelGGL((gemm2_kernel<3, true>), grid, dim3(256), 0, s, nbf, nact, np, nsplit, Ct.hi, Ct.lo, ldk, XT.hi, XT.lo, ldx, beta32, Kpart, Dchunk, W_hi, W_lo, ldw, ws);
+    else hipLaunchKernelGGL((gemm2_kernel<3, false>), grid, dim3(256), 0, s, nbf, nact, np, nsplit, Ct.hi, Ct.lo, ldk, XT.hi, XT.lo, ldx, beta32, Kpart, Dchunk, W_hi, W_lo, ldw, ws);
+  }
   return hipGetLastError();
 }
 
-hipError_t df_bf16_gemm3(hipStream_t s, int nbf, int nact, int np, int nsplit, int terms, SplitPtr X,
-                         int ldxx, SplitPtr W, int ldw, float* Ypart) {
-  if (np <= 0) return hipSuccess;
-  dim3 grid(cdiv(nbf, BM) * cdiv(nact, BN), nsplit);
-  if (terms == 1)
-    hipLaunchKernelGGL((gemm3_kernel<1>), grid, dim3(256), 0, s, nbf, nact, np, nsplit, X.hi, X.lo, ldxx, W.hi, W.lo, ldw, Ypart);
+template <int TERMS, int G3M, int MINB>
+static void launch_g3(hipStream_t s, int nbf, int nact, int np, int nsplit, SplitPtr XT, int ldx, SplitPtr W, int ldw,
+                      float* Ypart, const WsDims& d) {
+  const dim3 grid = xcd_grid((long long)nsplit * cdiv(nbf, G3M) * cdiv(nact, T2));
+  const bool vec = (ldx % 32 == 0) && (ldw % 32 == 0) && al16(XT.hi) && (!XT.lo || al16(XT.lo)) && al16(W.hi) &&
+                   (!W.lo || al16(W.lo));
+  if (vec)
+    hipLaunchKernelGGL((gemm3_kernel<TERMS, G3M, MINB, true>), grid, dim3(256), 0, s, nbf, nact, np, nsplit, XT.hi,
+                       XT.lo, ldx, W.hi, W.lo, ldw, Ypart, make_ws(d));
   else
-    hipLaunchKernelGGL((gemm3_kernel<3>), grid, dim3(256), 0, s, nbf, nact, np, nsplit, X.hi, X.lo, ldxx, W.hi, W.lo, ldw, Ypart);
+    hipLaunchKernelGGL((gemm3_kernel<TERMS, G3M, MINB, false>), grid, dim3(256), 0, s, nbf, nact, np, nsplit, XT.hi,
+                       XT.lo, ldx, W.hi, W.lo, ldw, Ypart, make_ws(d));
+}
+
+hipError_t df_bf16_gemm3(hipStream_t s, int nbf, int nact, int np, int nsplit, int terms, SplitPtr XT, int ldx,
+                         SplitPtr W, int ldw, float* Ypart, int variant, const WsDims& d) {
+  if (np <= 0) return hipSuccess;
+  const bool wide = (variant == 1);
+  if (terms == 1) {
+    if (wide) launch_g3<1, 256, 1>(s, nbf, nact, np, nsplit, XT, ldx, W, ldw, Ypart, d);
+    else launch_g3<1, 128, 1>(s, nbf, nact, np, nsplit, XT, ldx, W, ldw, Ypart, d);
+  } else {
+    if (wide) launch_g3<3, 256, 1>(s, nbf, nact, np, nsplit, XT, ldx, W, ldw, Ypart, d);
+    else launch_g3<3, 128, 1>(s, nbf, nact, np, nsplit, XT, ldx, W, ldw, Ypart, d);
+  }
   return hipGetLastError();
 }
 

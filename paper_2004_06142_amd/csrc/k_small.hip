@@ -97,14 +97,14 @@ __global__ void add_diag_f64_k(int nact, int np, const double* __restrict__ Dc, 
 }
 
 __global__ void add_diag_bf16_k(int nact, int np, const double* __restrict__ Dc, const double* __restrict__ alpha,
-                                u16* __restrict__ Wh, u16* __restrict__ Wl, int ldw) {
+                                u16* __restrict__ Wh, u16* __restrict__ Wl, int ldw, long long pstride) {
   GRID_STRIDE(i, (long long)np * nact) {
     const long long P = i / nact;
     const int p = (int)(i % nact);
     const double* Dp = Dc + P * nact;
     double d = 0.0;
     for (int q = 0; q < nact; ++q) d += Dp[q] * alpha[(long long)q * nact + p];   // alpha symmetric
-    const long long o = P * nact * ldw + (long long)p * ldw + p;
+    const long long o = P * pstride + (long long)p * ldw + p;
     double w = (double)bf16_bits_to_f32(Wh[o]) + (Wl ? (double)bf16_bits_to_f32(Wl[o]) : 0.0) + d;
     u16 h, l;
     split_f64(w, h, l);
@@ -561,7 +561,7 @@ __global__ void df_ao_accum_k(int nbf, int nact, int np, int nq, const int32_t* 
                               const void* __restrict__ Bc, int b_bf16, const double* __restrict__ Dc,
                               const double* __restrict__ alpha, const double* __restrict__ beta,
                               const double* __restrict__ XT, const u16* __restrict__ xh,
-                              const u16* __restrict__ xl, int ldx, double* __restrict__ Jq,
+                              const u16* __restrict__ xl, int ldx, long long xps, double* __restrict__ Jq,
                               double* __restrict__ Kq, double* __restrict__ Fq) {
   const long long n2 = (long long)nbf * nbf;
   GRID_STRIDE(i, (long long)nq * n2) {
@@ -575,7 +575,7 @@ __global__ void df_ao_accum_k(int nbf, int nact, int np, int nq, const int32_t* 
       const double b = b_bf16 ? (double)bf16_bits_to_f32(reinterpret_cast<const u16*>(Bc)[bo])
                               : reinterpret_cast<const double*>(Bc)[bo];
       const double* Dp = Dc + (long long)P * nact;
-      const long long xo = (long long)P * nact * ldx;
+      const long long xo = (long long)P * xps;
       sj += Dp[q] * b;
       const double xm = xt_val(XT, xh, xl, xo + (long long)q * ldx + m);
       const double xn = xt_val(XT, xh, xl, xo + (long long)q * ldx + nn);
@@ -634,9 +634,9 @@ hipError_t add_diag_f64(hipStream_t s, int nact, int np, const double* Dc, const
   LAUNCH(add_diag_f64_k, grid1((long long)np * nact), dim3(NT), nact, np, Dc, alpha, W, ldw);
 }
 hipError_t add_diag_bf16(hipStream_t s, int nact, int np, const double* Dc, const double* alpha, u16* Wh,
-                         u16* Wl, int ldw) {
+                         u16* Wl, int ldw, long long pstride) {
   if (np <= 0) return hipSuccess;
-  LAUNCH(add_diag_bf16_k, grid1((long long)np * nact), dim3(NT), nact, np, Dc, alpha, Wh, Wl, ldw);
+  LAUNCH(add_diag_bf16_k, grid1((long long)np * nact), dim3(NT), nact, np, Dc, alpha, Wh, Wl, ldw, pstride);
 }
 hipError_t reduce_k(hipStream_t s, int nact, int nsplit, const double* Kpart, double* K) {
   LAUNCH(reduce_k_k, grid1((long long)nact * nact), dim3(NT), nact, nsplit, Kpart, K);
@@ -721,10 +721,10 @@ hipError_t eri_fock_ao(hipStream_t s, int nbf, int nact, int nq, const int32_t* 
 hipError_t df_ao_accum(hipStream_t s, int nbf, int nact, int np, int nq, const int32_t* q_idx,
                        const void* Bchunk, int b_is_bf16, const double* Dchunk, const double* alpha,
                        const double* beta, const double* XT, const u16* XT_hi, const u16* XT_lo, int ldx,
-                       double* Jq, double* Kq, double* Fq) {
+                       long long xps, double* Jq, double* Kq, double* Fq) {
   if (nq <= 0 || np <= 0) return hipSuccess;
   LAUNCH(df_ao_accum_k, grid1((long long)nq * nbf * nbf), dim3(NT), nbf, nact, np, nq, q_idx, Bchunk,
-         b_is_bf16, Dchunk, alpha, beta, XT, XT_hi, XT_lo, ldx, Jq, Kq, Fq);
+         b_is_bf16, Dchunk, alpha, beta, XT, XT_hi, XT_lo, ldx, xps, Jq, Kq, Fq);
 }
 hipError_t fock_ao_h(hipStream_t s, int nbf, int nq, const int32_t* q_idx, const double* n, const double* H,
                      double* Fq) {
