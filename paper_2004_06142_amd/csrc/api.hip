@@ -170,7 +170,7 @@ Plan make_plan(const pnof_problem* p, const pnof_tuning& tu) {
 }
 
 struct Bufs {
-  double *alpha, *beta, *HC, *Hpp, *J, *K, *Y2e, *Y, *D, *Kpart, *partials, *E;
+  double *alpha, *beta, *HC, *Hpp, *J, *K, *Y2e, *Y, *D, *Kpart, *partials, *E, *dbuf;
   float* beta32;
   double* Ct;           // fp64
   u16 *cth, *ctl;       // split
@@ -201,6 +201,7 @@ Bufs carve(const Plan& pl, char* base) {
   b.flag = a.take<int>(4);
   if (is_df(pl.ints)) {
     b.D = a.take<double>((long long)pl.naux * pl.nact);
+    b.dbuf = a.take<double>((long long)pl.pc * pl.nact);
     b.Kpart = a.take<double>((long long)pl.ns2 * n2);
     if (!pl.split) {
       b.Ct = a.take<double>((long long)pl.nact * pl.ldk);
@@ -364,7 +365,7 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
         DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_X, df_f64_gemm1(s, nbf, nact, np, b.Ct, pl.ldk, Bc, b.XT, pl.ldx)));
         DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_B, df_f64_gemm2(s, nbf, nact, np, ns2, b.Ct, pl.ldk, b.XT, pl.ldx, b.beta, b.Kpart, Dc, b.W, pl.ldw)));
         if (want_y) {
-          DEV_CHECK(ctx, add_diag_f64(s, nact, np, Dc, b.alpha, b.W, pl.ldw));
+          DEV_CHECK(ctx, add_diag_f64(s, nact, np, Dc, b.alpha, b.dbuf, b.W, pl.ldw));
           DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_Y, df_f64_gemm3(s, nbf, nact, np, ns3, b.XT, pl.ldx, b.W, pl.ldw, b.Ypart64)));
           DEV_CHECK(ctx, reduce_y_f64(s, ny, ns3, b.Ypart64, b.Y2e));
         }
@@ -395,7 +396,7 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
         DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_B, df_bf16_gemm2(s, nbf, nact, np, ns2, pl.terms, Ct, pl.ldk, XT, pl.ldx, b.beta32, b.Kpart, Dc,
                                      b.wh, b.wl, pl.ldw, wd)));
         if (want_y) {
-          DEV_CHECK(ctx, add_diag_bf16(s, nact, np, Dc, b.alpha, b.wh, b.wl, pl.ldw, (long long)pl.nact32 * pl.ldw));
+          DEV_CHECK(ctx, add_diag_bf16(s, nact, np, Dc, b.alpha, b.dbuf, b.wh, b.wl, pl.ldw, (long long)pl.nact32 * pl.ldw));
           SplitPtr W{b.wh, b.wl};
           DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_Y, df_bf16_gemm3(s, nbf, nact, np, ns3, pl.terms, XT, pl.ldx, W, pl.ldw, b.Ypart32, pl.yv, wd)));
           DEV_CHECK(ctx, reduce_y_f32(s, ny, ns3, b.Ypart32, b.Y2e));

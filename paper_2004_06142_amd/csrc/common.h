@@ -100,10 +100,11 @@ hipError_t split_ca(hipStream_t s, int nbf, int nact, int terms, const double* C
 hipError_t split_b(hipStream_t s, long long n, const double* B, u16* hi, u16* lo);
 hipError_t widen_bf16(hipStream_t s, long long n, const u16* src, double* dst);
 hipError_t hpp_from_hc(hipStream_t s, int nbf, int nact, const double* C, const double* HC, double* Hpp);
+// d = Dchunk alpha (float64 matrix cores) into dbuf (np x nact), then W_P[p][p] += d[P][p].
 hipError_t add_diag_f64(hipStream_t s, int nact, int np, const double* Dchunk, const double* alpha,
-                        double* W, int ldw);
+                        double* dbuf, double* W, int ldw);
 hipError_t add_diag_bf16(hipStream_t s, int nact, int np, const double* Dchunk, const double* alpha,
-                         u16* W_hi, u16* W_lo, int ldw, long long pstride);
+                         double* dbuf, u16* W_hi, u16* W_lo, int ldw, long long pstride);
 hipError_t reduce_k(hipStream_t s, int nact, int nsplit, const double* Kpart, double* K);
 hipError_t reduce_y_f64(hipStream_t s, long long n, int nsplit, const double* Ypart, double* Y);
 hipError_t reduce_y_f32(hipStream_t s, long long n, int nsplit, const float* Ypart, double* Y);

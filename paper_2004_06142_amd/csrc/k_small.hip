@@ -83,29 +83,22 @@ __global__ void hpp_k(int nbf, int nact, const double* __restrict__ C, const dou
   if (lane == 0) Hpp[p] = s;
 }
 
-// d_Pp = sum_q D[P][q] alpha[q][p]; W_P[p][p] += d_Pp.
-__global__ void add_diag_f64_k(int nact, int np, const double* __restrict__ Dc, const double* __restrict__ alpha,
-                               double* __restrict__ W, int ldw) {
+// W_P[p][p] += d[P][p], with d = D alpha (d_Pp = sum_q D_Pq alpha_qp) computed beforehand.
+__global__ void add_diag_f64_k(int nact, int np, const double* __restrict__ d, double* __restrict__ W, int ldw) {
   GRID_STRIDE(i, (long long)np * nact) {
     const long long P = i / nact;
     const int p = (int)(i % nact);
-    const double* Dp = Dc + P * nact;
-    double d = 0.0;
-    for (int q = 0; q < nact; ++q) d += Dp[q] * alpha[(long long)q * nact + p];   // alpha symmetric
-    W[P * nact * ldw + (long long)p * ldw + p] += d;
+    W[P * nact * ldw + (long long)p * ldw + p] += d[i];
   }
 }
 
-__global__ void add_diag_bf16_k(int nact, int np, const double* __restrict__ Dc, const double* __restrict__ alpha,
-                                u16* __restrict__ Wh, u16* __restrict__ Wl, int ldw, long long pstride) {
+__global__ void add_diag_bf16_k(int nact, int np, const double* __restrict__ d, u16* __restrict__ Wh,
+                                u16* __restrict__ Wl, int ldw, long long pstride) {
   GRID_STRIDE(i, (long long)np * nact) {
     const long long P = i / nact;
     const int p = (int)(i % nact);
-    const double* Dp = Dc + P * nact;
-    double d = 0.0;
-    for (int q = 0; q < nact; ++q) d += Dp[q] * alpha[(long long)q * nact + p];   // alpha symmetric
     const long long o = P * pstride + (long long)p * ldw + p;
-    double w = (double)bf16_bits_to_f32(Wh[o]) + (Wl ? (double)bf16_bits_to_f32(Wl[o]) : 0.0) + d;
+    double w = (double)bf16_bits_to_f32(Wh[o]) + (Wl ? (double)bf16_bits_to_f32(Wl[o]) : 0.0) + d[i];
     u16 h, l;
     split_f64(w, h, l);
     Wh[o] = h;
@@ -629,14 +622,19 @@ hipError_t split_b(hipStream_t s, long long n, const double* B, u16* hi, u16* lo
 hipError_t hpp_from_hc(hipStream_t s, int nbf, int nact, const double* C, const double* HC, double* Hpp) {
   LAUNCH(hpp_k, dim3(nact), dim3(64), nbf, nact, C, HC, Hpp);
 }
-hipError_t add_diag_f64(hipStream_t s, int nact, int np, const double* Dc, const double* alpha, double* W, int ldw) {
+hipError_t add_diag_f64(hipStream_t s, int nact, int np, const double* Dc, const double* alpha, double* dbuf,
+                        double* W, int ldw) {
   if (np <= 0) return hipSuccess;
-  LAUNCH(add_diag_f64_k, grid1((long long)np * nact), dim3(NT), nact, np, Dc, alpha, W, ldw);
+  hipError_t e = gemm_f64(s, np, nact, nact, 1, 1.0, Dc, nact, 1, 0, alpha, nact, 1, 0, 0.0, dbuf, nact, 1, 0);
+  if (e != hipSuccess) return e;
+  LAUNCH(add_diag_f64_k, grid1((long long)np * nact), dim3(NT), nact, np, dbuf, W, ldw);
 }
-hipError_t add_diag_bf16(hipStream_t s, int nact, int np, const double* Dc, const double* alpha, u16* Wh,
-                         u16* Wl, int ldw, long long pstride) {
+hipError_t add_diag_bf16(hipStream_t s, int nact, int np, const double* Dc, const double* alpha, double* dbuf,
+                         u16* Wh, u16* Wl, int ldw, long long pstride) {
   if (np <= 0) return hipSuccess;
-  LAUNCH(add_diag_bf16_k, grid1((long long)np * nact), dim3(NT), nact, np, Dc, alpha, Wh, Wl, ldw, pstride);
+  hipError_t e = gemm_f64(s, np, nact, nact, 1, 1.0, Dc, nact, 1, 0, alpha, nact, 1, 0, 0.0, dbuf, nact, 1, 0);
+  if (e != hipSuccess) return e;
+  LAUNCH(add_diag_bf16_k, grid1((long long)np * nact), dim3(NT), nact, np, dbuf, Wh, Wl, ldw, pstride);
 }
 hipError_t reduce_k(hipStream_t s, int nact, int nsplit, const double* Kpart, double* K) {
   LAUNCH(reduce_k_k, grid1((long long)nact * nact), dim3(NT), nact, nsplit, Kpart, K);
