@@ -22,6 +22,22 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"bf16": 2.5e15, "f64": 78.6e12}
+KSRC = os.path.join(ROOT, "paper_2004_06142_amd", "csrc")
+# HBM bytes per launch from the FETCH_SIZE and WRITE_SIZE counter runs (profiles/), each scaled by the
+# factor a plain 1 GiB elementwise copy gives, and the SHA-256 of the kernel source they were taken on:
+# once the source changes the figure no longer applies and traffic is reported as null.
+TRAFFIC = {
+    # profiles/c5_df1200_hbm_traffic.md: C5, bf16 split, 128-row chunks
+    ("gemm2_kernel", 3): {"bytes": 2543166977 + 454880178,
+                          "plan": {"pchunk": 128, "nsplit_b": 9},
+                          "sha256": {"k_gemm_bf16.hip": "6083e05454aa697560cffeae88d9bb0985521046df8dc821542933632fd94645"}},
+    ("gemm3_kernel", 3): {"bytes": 10764047431 + 29086124,
+                          "plan": {"pchunk": 128, "nsplit_y": 5, "y_variant": 0},
+                          "sha256": {"k_gemm_bf16.hip": "6083e05454aa697560cffeae88d9bb0985521046df8dc821542933632fd94645"}},
+    ("gemm1_kernel", 3): {"bytes": 2401680835 + 742275833,
+                          "plan": {"pchunk": 128, "x_variant": 0},
+                          "sha256": {"k_gemm_bf16.hip": "6083e05454aa697560cffeae88d9bb0985521046df8dc821542933632fd94645"}},
+}
 GOLDEN_C5 = os.path.join(ROOT, "tests", "golden", "c5_df1200_expected.json")
 
 
@@ -33,7 +49,7 @@ def parse():
     ap.add_argument("--workload", default="c5_df1200")
     ap.add_argument("--precision", default="bf16split", choices=["bf16split", "fp64", "bf16"])
     ap.add_argument("--fp64-steps", type=int, default=1, help="steps of the float64 path for the speedup (0: skip)")
-    ap.add_argument("--cpu-rows", type=int, default=384, help="rows of B in the oracle's timed sample (0: skip)")
+    ap.add_argument("--cpu-rows", type=int, default=1024, help="rows of B in the oracle's timed sample (0: skip)")
     ap.add_argument("--pchunk", type=int, default=0)
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-parameter autotuner")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -45,6 +61,22 @@ def stage_flops(wl, stage):
     """Algorithmic flops of one full pass of a contraction stage (one product per contraction)."""
     nb, na, nx = wl.nbf, wl.nact, wl.naux
     return {"X": 2.0 * nx * nb * nb * na, "b": 2.0 * nx * na * nb * na, "Y": 2.0 * nx * nb * na * na}[stage]
+
+
+def _sha(path):
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def traffic(kname, prec, plan):
+    """Measured HBM bytes per launch of the dominant kernel, or None when no valid measurement exists."""
+    ent = TRAFFIC.get((kname, prec))
+    if not ent or ent["plan"] != {k: plan[k] for k in ent["plan"]}:
+        return None
+    if any(_sha(os.path.join(KSRC, f)) != h for f, h in ent["sha256"].items()):
+        return None
+    return ent["bytes"]
 
 
 def main():
@@ -62,9 +94,11 @@ def main():
 
     dev = torch.device("cuda", 0)
     if args.copy_calibration:
+        # one elementwise kernel that reads and writes exactly MIB MiB each (calibrates the HBM counters)
         src = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.cuda.synchronize()
+        torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
     wl = synth.WORKLOADS[args.workload]
@@ -120,9 +154,10 @@ def main():
     flops = stage_flops(wl, stage) * args.steps
     achieved = flops / (st_ms * 1e-3)
     terms = {"X": 2, "b": 3, "Y": 3}[stage] if prec == P.BF16_SPLIT else 1
+    kname = {"X": "gemm1_kernel", "b": "gemm2_kernel", "Y": "gemm3_kernel"}[stage]
     roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[dtype_key] / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK[dtype_key], "traffic": None,
-                "kernel": {"X": "gemm1_kernel", "b": "gemm2_kernel", "Y": "gemm3_kernel"}[stage],
+                "frac": achieved / PEAK[dtype_key], "traffic": traffic(kname, prec, ctx.plan(prob)),
+                "kernel": kname,
                 "avg_launch_ms": st_ms / st_n, "launches": st_n,
                 "issued_frac": achieved * terms / PEAK[dtype_key]}
     stages = {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[1] / args.steps} for k, v in prof.items()}

@@ -115,3 +115,43 @@ def tune(ctx: Context, prob, run, reps: int = 2, use_cache: bool = True, verbose
         cache[k] = entry
         save_cache(cache)
     return entry
+
+
+def main():
+    """Tune one synthetic workload on device 0 and store the entry in the cache file."""
+    import argparse
+
+    import numpy as np
+
+    import synth
+    import synth.device as sdev
+
+    from . import INTS_DF_BF16, INTS_DF_F64, PNOF7, BF16_SPLIT, FP64, problem
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="c5_df1200")
+    ap.add_argument("--precision", default="bf16split", choices=["bf16split", "fp64"])
+    ap.add_argument("--reps", type=int, default=2)
+    args = ap.parse_args()
+    dev = torch.device("cuda", 0)
+    inst = synth.workload(args.workload, with_b=False)
+    wl = inst.wl
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    C, H, gamma = t(inst.C), t(inst.H), t(inst.gamma)
+    B = sdev.make_b(inst.key, wl.nbf, wl.naux, dtype=torch.bfloat16 if wl.b_dtype == "bf16" else torch.float64,
+                    device=dev)
+    kind = INTS_DF_BF16 if wl.b_dtype == "bf16" else INTS_DF_F64
+    prec = BF16_SPLIT if args.precision == "bf16split" else FP64
+    prob = problem(wl.nbf, wl.naux, wl.npairs, wl.ncwo, PNOF7, prec, kind)
+    ctx = Context(0)
+    ctx.reserve(prob)
+    n = ctx.on_map(gamma, wl.npairs, wl.ncwo)
+    ent = tune(ctx, prob, lambda: ctx.lagrangian(prob, C, n, H, B), reps=args.reps, use_cache=False, verbose=True)
+    cache = load_cache()
+    cache[key(prob, _arch(0))] = ent
+    save_cache(cache)
+    print(json.dumps(ent), flush=True)
+
+
+if __name__ == "__main__":
+    main()
