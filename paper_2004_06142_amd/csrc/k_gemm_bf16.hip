@@ -316,11 +316,12 @@ __device__ __forceinline__ bf16x8 dl_frag(const u16* __restrict__ s, int r) {
   return u.v;
 }
 
-// Pipeline depth that fits `budget` bytes of LDS (at most 4 stages).
+// Pipeline depth that fits `budget` bytes of LDS (at most 5 stages: up to four k-tiles in flight
+// while one is consumed, which is what covers the latency of operands streamed from HBM).
 constexpr int ring_depth(int BM, int BN, bool ALO, bool BLO, int budget) {
   const int stage = 2 * BK * (BM * (ALO ? 2 : 1) + BN * (BLO ? 2 : 1));
   const int s = budget / stage;
-  return s > 4 ? 4 : s;
+  return s > 5 ? 5 : s;
 }
 
 template <int BM, int BN, bool ALO, bool BLO, int S>
@@ -416,12 +417,25 @@ __device__ __forceinline__ int col_of(int jn) {
   return (wave & 1) * (BN / 2) + jn * 16 + (lane & 15);
 }
 
-__device__ __forceinline__ void tri_tile(int t, int& tm, int& tn) {
+// Lower-triangle tile t of a tt x tt tiling, ordered by column (tiles sharing tn are consecutive,
+// so the blocks an XCD holds at once read few distinct column panels).
+__device__ __forceinline__ void tri_tile(int t, int tt, int& tm, int& tn) {
   int r = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
   while ((r + 1) * (r + 2) / 2 <= t) ++r;
   while (r * (r + 1) / 2 > t) --r;
-  tm = r;
-  tn = t - r * (r + 1) / 2;
+  tn = tt - 1 - r;
+  tm = tt - 1 - (t - r * (r + 1) / 2);
+}
+
+// Tile t of a tm_n x tn_n grid in groups of G rows: consecutive tiles sweep G rows of one column,
+// then the next column, so a run of consecutive tiles covers a compact G x (run / G) patch.
+template <int G>
+__device__ __forceinline__ void grouped_tile(int t, int tm_n, int tn_n, int& tm, int& tn) {
+  const int per_group = G * tn_n;
+  const int g = t / per_group, r = t % per_group;
+  const int rows = min(G, tm_n - g * G);
+  tm = g * G + r % rows;
+  tn = r / rows;
 }
 
 // Block id -> work item, each XCD taking one contiguous range of items (-1: padding block).
@@ -499,8 +513,8 @@ __global__ __launch_bounds__(256, MINB) void gemm1_kernel(int nbf, int nact, int
 }
 
 // gemm2: b_P = Ct XT_P^T on lower 128-tiles; Kpart[s] += sum_{P in s} b^2 (lower triangle, summed
-// over the successive P-chunks of one call), D[P][p] = b_pp, W_P = b o beta as a hi/lo pair,
-// stored only for the lower tiles (diagonal tiles in full): the upper blocks are read transposed.
+// over the successive P-chunks of one call), D[P][p] = b_pp, W_P = b o beta as a hi/lo pair, written
+// in full (off-diagonal tiles store their mirror image as well).
 template <int TERMS, bool VEC>
 __global__ __launch_bounds__(256, 1) void gemm2_kernel(int nbf, int nact, int np, int nsplit,
                                                        const u16* __restrict__ ct_hi, const u16* __restrict__ ct_lo,
@@ -510,22 +524,26 @@ __global__ __launch_bounds__(256, 1) void gemm2_kernel(int nbf, int nact, int np
                                                        double* __restrict__ Dc, u16* __restrict__ w_hi,
                                                        u16* __restrict__ w_lo, int ldw, WS ws) {
   constexpr bool LO = TERMS >= 3;
-  __shared__ float sbeta[T2][T2];
   const int tt = (nact + T2 - 1) / T2;
   const int ntri = tt * (tt + 1) / 2;
   const int w = xcd_item(nsplit * ntri);
   if (w < 0) return;
   const int s = w / ntri;
   int tm, tn;
-  tri_tile(w % ntri, tm, tn);
+  tri_tile(w % ntri, tt, tm, tn);
   const int m0 = tm * T2, n0 = tn * T2;
   const int pb = (int)((long long)np * s / nsplit), pe = (int)((long long)np * (s + 1) / nsplit);
-  for (int e = threadIdx.x; e < T2 * T2; e += 256) {
-    const int r = e / T2, c = e % T2;
-    const int p = m0 + r, q = n0 + c;
-    sbeta[r][c] = (p < nact && q < nact) ? beta32[(long long)p * nact + q] : 0.f;
-  }
-  __syncthreads();
+  // beta of this lane's accumulator positions, kept in registers for the whole P-range
+  f32x4 bet[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int jn = 0; jn < 4; ++jn)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int p = m0 + row_of<T2>(i, j), q = n0 + col_of<T2>(jn);
+        bet[i][jn][j] = (p < nact && q < nact) ? beta32[(long long)p * nact + q] : 0.f;
+      }
   f32x4 kacc[4][4], acc[4][4];
   zero(kacc);
   const bool diag = (tm == tn);
@@ -539,12 +557,11 @@ __global__ __launch_bounds__(256, 1) void gemm2_kernel(int nbf, int nact, int np
       for (int jn = 0; jn < 4; ++jn)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int r = row_of<T2>(i, j), c = col_of<T2>(jn);
-          const int p = m0 + r, q = n0 + c;
+          const int p = m0 + row_of<T2>(i, j), q = n0 + col_of<T2>(jn);
           const float b = a[i][jn][j];
           kacc[i][jn][j] += b * b;
           if (p < nact && q < nact) {
-            const float wv = b * sbeta[r][c];
+            const float wv = b * bet[i][jn][j];
             u16 h, l;
             if (!LO) { h = f32_to_bf16_bits(wv); l = 0; }
             else split_f32(wv, h, l);
@@ -553,15 +570,47 @@ __global__ __launch_bounds__(256, 1) void gemm2_kernel(int nbf, int nact, int np
             if (diag && p == q) Dc[(long long)P * nact + p] = (double)b;
           }
         }
+    if (!diag) {
+      // mirror W_qp = W_pq: the four components of acc[i][jn] are consecutive p of one q
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int jn = 0; jn < 4; ++jn) {
+          const int p = m0 + row_of<T2>(i, 0), q = n0 + col_of<T2>(jn);
+          if (q >= nact || p >= nact) continue;
+          u16 h[4], l[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const float wv = p + j < nact ? a[i][jn][j] * bet[i][jn][j] : 0.f;
+            if (!LO) { h[j] = f32_to_bf16_bits(wv); l[j] = 0; }
+            else split_f32(wv, h[j], l[j]);
+          }
+          // p % 4 == 0 and ldw % 4 == 0: the four entries W[q][p..p+3] (p + 3 < ldw) are one 8-byte word
+          const long long o = (long long)q * ldw + p;
+          if ((ldw & 3) == 0) {
+            *reinterpret_cast<uint2*>(Wh + o) = uint2{h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16)};
+            if (LO)
+              *reinterpret_cast<uint2*>(Wl + o) = uint2{l[0] | ((uint32_t)l[1] << 16), l[2] | ((uint32_t)l[3] << 16)};
+          } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              if (p + j < nact) {
+                Wh[o + j] = h[j];
+                if (LO) Wl[o + j] = l[j];
+              }
+          }
+        }
+    }
   };
   if constexpr (VEC) {
-    __shared__ Ring<T2, T2, LO, LO, 3> sm;
+    constexpr int S = ring_depth(T2, T2, LO, LO, 163840);
+    __shared__ Ring<T2, T2, LO, LO, S> sm;
     auto A = [&](int) { return DOpnd{ct_hi, ct_lo, ldk, ws.ct_bytes}; };
     auto B = [&](int seg) {
       const long long off = (long long)(pb + seg) * ws.nact32 * ldx;
       return DOpnd{xt_hi + off, LO ? xt_lo + off : nullptr, ldx, ws.xt_bytes - 2 * off};
     };
-    mainloop_dl<T2, T2, LO, LO, 3, false, false, true>(sm, pe - pb, 0, nbf, m0, n0, A, B, acc, epi);
+    mainloop_dl<T2, T2, LO, LO, S, false, false, true>(sm, pe - pb, 0, nbf, m0, n0, A, B, acc, epi);
   } else {
     __shared__ Stage<T2, T2, LO, LO> sm;
     auto A = [&](int) { return Opnd{ct_hi, ct_lo, ldk, nact, nbf, false}; };
@@ -583,8 +632,9 @@ __global__ __launch_bounds__(256, 1) void gemm2_kernel(int nbf, int nact, int np
       }
 }
 
-// gemm3: Ypart[s][mu][q] = sum_{P in s} sum_r XT_P[r][mu] W_P[q][r].  XT is read as a col operand;
-// W[q][r] is read from row q for r-tiles up to q's 128-tile and from row r (transposed) beyond it.
+// gemm3: Ypart[s][mu][q] = sum_{P in s} sum_r XT_P[r][mu] W_P[q][r].  XT is read as a col operand,
+// W (stored in full) as a row operand; every block walks (P, r) in the same order, so blocks of one
+// split that share an operand panel read it at about the same time.
 // Tile G3M (mu) x 128 (q).
 template <int TERMS, int G3M, int MINB, bool VEC>
 __global__ __launch_bounds__(256, MINB) void gemm3_kernel(int nbf, int nact, int np, int nsplit,
@@ -597,15 +647,14 @@ __global__ __launch_bounds__(256, MINB) void gemm3_kernel(int nbf, int nact, int
   const int tm_n = (nbf + G3M - 1) / G3M, tn_n = (nact + G3N - 1) / G3N;
   const int w = xcd_item(nsplit * tm_n * tn_n);
   if (w < 0) return;
-  const int s = w / (tm_n * tn_n), tile = w % (tm_n * tn_n);
-  const int m0 = (tile / tn_n) * G3M, n0 = (tile % tn_n) * G3N;
+  const int s = w / (tm_n * tn_n);
+  int tm, tn;
+  grouped_tile<4>(w % (tm_n * tn_n), tm_n, tn_n, tm, tn);
+  const int m0 = tm * G3M, n0 = tn * G3N;
   const int pb = (int)((long long)np * s / nsplit), pe = (int)((long long)np * (s + 1) / nsplit);
   f32x4 acc[G3M / 32][G3N / 32];
   zero(acc);
   auto none = [&](int, f32x4(&)[G3M / 32][G3N / 32]) {};
-  // W[q][r] comes from row q while r < n0 + 128 (lower and diagonal tiles) and from row r
-  // (transposed) beyond: two passes over the P-range, one per storage order
-  const int ksplit = min(nact, n0 + T2);
   if constexpr (VEC) {
     constexpr int S = ring_depth(G3M, G3N, LO, LO, 163840);
     __shared__ Ring<G3M, G3N, LO, LO, S> sm;
@@ -617,9 +666,7 @@ __global__ __launch_bounds__(256, MINB) void gemm3_kernel(int nbf, int nact, int
       const long long off = (long long)(pb + seg) * ws.nact32 * ldw;
       return DOpnd{w_hi + off, LO ? w_lo + off : nullptr, ldw, ws.w_bytes - 2 * off};
     };
-    mainloop_dl<G3M, G3N, LO, LO, S, true, false, false>(sm, pe - pb, 0, ksplit, m0, n0, A, B, acc, none);
-    if (ksplit < nact)
-      mainloop_dl<G3M, G3N, LO, LO, S, true, true, false>(sm, pe - pb, ksplit, nact, m0, n0, A, B, acc, none);
+    mainloop_dl<G3M, G3N, LO, LO, S, true, false, false>(sm, pe - pb, 0, nact, m0, n0, A, B, acc, none);
   } else {
     __shared__ Stage<G3M, G3N, LO, LO> sm;
     auto A = [&](int seg) {
@@ -630,9 +677,7 @@ __global__ __launch_bounds__(256, MINB) void gemm3_kernel(int nbf, int nact, int
       const long long off = (long long)(pb + seg) * ws.nact32 * ldw;
       return Opnd{w_hi + off, LO ? w_lo + off : nullptr, ldw, nact, nact, false};
     };
-    mainloop<G3M, G3N, LO, LO, true, false, false>(sm, pe - pb, 0, ksplit, m0, n0, A, B, acc, none);
-    if (ksplit < nact)
-      mainloop<G3M, G3N, LO, LO, true, true, false>(sm, pe - pb, ksplit, nact, m0, n0, A, B, acc, none);
+    mainloop<G3M, G3N, LO, LO, true, false, false>(sm, pe - pb, 0, nact, m0, n0, A, B, acc, none);
   }
   float* Y = Ypart + (long long)s * nbf * nact;
 #pragma unroll
