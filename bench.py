@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=1024, help="rows of B in the oracle's timed sample (0: skip)")
     ap.add_argument("--pchunk", type=int, default=0)
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-parameter autotuner")
+    ap.add_argument("--pes-reps", type=int, default=20,
+                    help="timed replays of the 64-instance PES-scan batch (0: skip that measurement)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a plain device-to-device copy of this many MiB (reference for traffic counters)")
     return ap.parse_args()
@@ -187,9 +189,62 @@ def main():
     del B
     torch.cuda.empty_cache()
 
+    if args.pes_reps > 0:
+        result["pes_batch"] = pes_batch(P, ctx, args.pes_reps)
+        torch.cuda.empty_cache()
+
     if args.cpu_rows > 0:
         result["cpu_baseline"] = cpu_baseline(wl, inst, args.cpu_rows)
     print(json.dumps(result), flush=True)
+
+
+GOLDEN_PES = os.path.join(ROOT, "tests", "golden", "pes64_expected.json")
+
+
+def pes_batch(P, ctx, reps):
+    """The 64-instance PES scan (N_bf in [40, 300], bf16 split) as one graph-replayed batch."""
+    import numpy as np
+    import torch
+
+    import synth
+    import synth.device as sdev
+
+    dev = ctx.device
+    insts = synth.pes_scan(64, with_b=False)
+    probs, ins = [], []
+    for inst in insts:
+        wl = inst.wl
+        probs.append(P.problem(wl.nbf, wl.naux, wl.npairs, wl.ncwo, P.PNOF7, P.BF16_SPLIT, P.INTS_DF_BF16))
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        ins.append({"C": t(inst.C), "H": t(inst.H), "n": ctx.on_map(t(inst.gamma), wl.npairs, wl.ncwo),
+                    "B": sdev.make_b(inst.key, wl.nbf, wl.naux, dtype=torch.bfloat16, device=dev)})
+    batch = P.Batch(ctx, probs)
+    outs = batch.bind(ins)
+    for _ in range(3):
+        batch.run(graph=True)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        batch.run(graph=True)
+        b.record()
+        b.synchronize()
+        times.append(a.elapsed_time(b))
+    times = np.array(times)
+    flops = sum(2.0 * p.naux * p.nbf * p.nact * (p.nbf + 2 * p.nact) for p in probs)
+    med = float(np.median(times))
+    res = {"instances": len(probs), "nbf_range": [min(p.nbf for p in probs), max(p.nbf for p in probs)],
+           "ms_per_batch_p50": med, "ms_p90": float(np.percentile(times, 90)), "ms_p99": float(np.percentile(times, 99)),
+           "instances_per_s": len(probs) / (med * 1e-3), "launches_per_batch": batch.info()["launches"],
+           "graph": True, "algorithmic_tflops": flops / (med * 1e-3) / 1e12,
+           "note": "every instance completes with the batch's last grouped launch, so per-instance latency "
+                   "equals the batch latency"}
+    if os.path.exists(GOLDEN_PES):
+        ref = json.load(open(GOLDEN_PES))
+        res["max_abs_dE_vs_oracle"] = max(abs(o["E"].item() - r["E"]) for o, r in zip(outs, ref["instances"]))
+    batch.close()
+    return res
 
 
 def cpu_baseline(wl, inst, rows):

@@ -177,6 +177,44 @@ pnof_status pnof_orbital_step(pnof_ctx ctx, int32_t nbf, const double* lambda, c
                               const double* diag_prev, double zeta, double* C_new, double* eps,
                               double* S_out);
 
+/* ---- batches of independent problems (a potential-energy-surface scan) ---------------------- */
+/* A batch runs the Lagrangian step (as pnof_lagrangian: E, lambda, optional dE/dC, dE/dn and
+ * max asymmetry) for ninst independent problems of different sizes in one fixed sequence of
+ * grouped launches: every launch covers all instances, so small instances share the chip instead of
+ * each leaving it mostly idle.  Restrictions: every problem uses PNOF_INTS_DF_BF16 and the same
+ * precision (PNOF_BF16_SPLIT or PNOF_BF16), flags == 0, and each instance's packed B and tile
+ * buffers stay below 2 GiB (roughly nbf <= 600 at naux = 4 nbf); the functional may differ.
+ *
+ * pnof_batch_plan: validates the problems and allocates the batch's device workspace (owned by the
+ *   batch, freed by pnof_batch_destroy; the only allocation of a batch).  Uses the context's device
+ *   and stream; the context must outlive the batch.
+ * pnof_batch_bind: io[i] gives instance i's device buffers (the pnof_lagrangian conventions:
+ *   C, H, lambda, dEdC nbf x nbf; n, dEdn nbf; E and max_asym one double each).  Binding copies
+ *   every instance's B into the batch's padded layout (rows padded to a multiple of 32) and
+ *   clears the tile workspace, on the context stream; later runs read that copy, so bind again
+ *   after B changes.  C, n and H are read by every run at the bound addresses.
+ * pnof_batch_run: enqueues one step of every instance on the context stream.  use_graph != 0
+ *   captures the sequence into a HIP graph on its first use (on a private stream) and replays it
+ *   afterwards; rebinding discards the graph.  Runs on one batch must not overlap. */
+typedef struct pnof_batch_s* pnof_batch;
+typedef struct {
+  const double* C;
+  const double* n;
+  const double* H;
+  const void* ints;     /* B: naux x nbf x nbf bfloat16 */
+  double* lambda;       /* required */
+  double* E;            /* required: one device double */
+  double* dEdC;         /* optional */
+  double* dEdn;         /* optional (entries >= nact untouched) */
+  double* max_asym;     /* optional: one device double */
+} pnof_batch_io;
+pnof_status pnof_batch_plan(pnof_ctx ctx, int32_t ninst, const pnof_problem* probs, pnof_batch* out);
+pnof_status pnof_batch_bind(pnof_batch batch, const pnof_batch_io* io);
+pnof_status pnof_batch_run(pnof_batch batch, int32_t use_graph);
+/* Device bytes held by the batch, and the number of launches one run enqueues. */
+pnof_status pnof_batch_info(pnof_batch batch, size_t* bytes, int32_t* launches);
+void pnof_batch_destroy(pnof_batch batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -31,7 +31,8 @@ STATUS = {0: "PNOF_OK", 1: "PNOF_E_ARG", 2: "PNOF_E_SHAPE", 3: "PNOF_E_DTYPE", 4
 EXPORTS = ["pnof_abi_version", "pnof_last_error", "pnof_check_problem", "pnof_create", "pnof_destroy",
            "pnof_set_stream", "pnof_workspace_size", "pnof_set_workspace", "pnof_set_pchunk", "pnof_on_map",
            "pnof_on_map_vjp", "pnof_jk", "pnof_energy", "pnof_fock", "pnof_lagrangian", "pnof_orbital_step",
-           "pnof_profile_begin", "pnof_profile_end", "pnof_set_tuning", "pnof_get_plan"]
+           "pnof_profile_begin", "pnof_profile_end", "pnof_set_tuning", "pnof_get_plan", "pnof_batch_plan",
+           "pnof_batch_bind", "pnof_batch_run", "pnof_batch_info", "pnof_batch_destroy"]
 STAGES = ("X", "b", "Y", "eig")
 
 
@@ -46,6 +47,10 @@ class Tuning(ctypes.Structure):
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class BatchIO(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("C", "n", "H", "ints", "lambda_", "E", "dEdC", "dEdn", "max_asym")]
 
 
 class Problem(ctypes.Structure):
@@ -94,6 +99,11 @@ def lib():
             "pnof_get_plan": ([P, PP, ctypes.POINTER(Tuning)], S),
             "pnof_profile_begin": ([P], S),
             "pnof_profile_end": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], S),
+            "pnof_batch_plan": ([P, I, PP, ctypes.POINTER(ctypes.c_void_p)], S),
+            "pnof_batch_bind": ([P, ctypes.POINTER(BatchIO)], S),
+            "pnof_batch_run": ([P, I], S),
+            "pnof_batch_info": ([P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_int32)], S),
+            "pnof_batch_destroy": ([P], None),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -383,3 +393,75 @@ def energy_and_grad(ctx, prob, C, gamma, H, ints, kind=ON_SIGMOID):
     out["dEdgamma"] = ctx.on_map_vjp(gamma, out["dEdn"], prob.npairs, prob.ncwo, kind)
     out["n"] = n
     return out
+
+
+# ----------------------------------------------------------------------------- batches
+class Batch:
+    """A batch of independent problems run by one fixed sequence of grouped launches.
+
+    ``problems``: list of Problem (DF_BF16, one precision).  ``bind(inputs)`` takes, per instance, a
+    dict with device tensors C, n, H, B (and optionally dEdC / dEdn / max_asym flags via
+    ``grads=True``) and allocates the outputs; ``run(graph=True)`` enqueues one step of every
+    instance (captured into a HIP graph on the first call) and returns the output dicts.
+    """
+
+    def __init__(self, ctx: Context, problems):
+        self.ctx = ctx
+        self.problems = list(problems)
+        arr = (Problem * len(self.problems))(*self.problems)
+        h = ctypes.c_void_p()
+        _raise(ctx, lib().pnof_batch_plan(ctx.handle, len(self.problems), arr, ctypes.byref(h)))
+        self.handle = h
+        self.inputs = None
+        self.outputs = None
+
+    def info(self):
+        nb, nl = ctypes.c_size_t(), ctypes.c_int32()
+        _raise(self.ctx, lib().pnof_batch_info(self.handle, ctypes.byref(nb), ctypes.byref(nl)))
+        return {"bytes": nb.value, "launches": nl.value}
+
+    def bind(self, inputs, grads: bool = True):
+        if len(inputs) != len(self.problems):
+            raise ValueError("one input dict per instance is required")
+        d = self.ctx.device
+        ios = (BatchIO * len(inputs))()
+        outs = []
+        for i, (prob, x) in enumerate(zip(self.problems, inputs)):
+            nbf = prob.nbf
+            _check(x["C"], nbf * nbf, torch.float64, d, f"C[{i}]")
+            _check(x["H"], nbf * nbf, torch.float64, d, f"H[{i}]")
+            if x["n"].numel() not in (prob.nact, nbf):
+                raise ValueError(f"n[{i}]: expected nact or nbf entries")
+            _check(x["n"], x["n"].numel(), torch.float64, d, f"n[{i}]")
+            _ints_check(prob, x["B"], d)
+            o = {"E": torch.zeros(1, dtype=torch.float64, device=d),
+                 "lam": torch.zeros(nbf, nbf, dtype=torch.float64, device=d)}
+            if grads:
+                o["dEdC"] = torch.zeros(nbf, nbf, dtype=torch.float64, device=d)
+                o["dEdn"] = torch.zeros(prob.nact, dtype=torch.float64, device=d)
+                o["max_asym"] = torch.zeros(1, dtype=torch.float64, device=d)
+            io = ios[i]
+            io.C, io.n, io.H, io.ints = (x["C"].data_ptr(), x["n"].data_ptr(), x["H"].data_ptr(), x["B"].data_ptr())
+            io.lambda_, io.E = o["lam"].data_ptr(), o["E"].data_ptr()
+            io.dEdC = o["dEdC"].data_ptr() if grads else None
+            io.dEdn = o["dEdn"].data_ptr() if grads else None
+            io.max_asym = o["max_asym"].data_ptr() if grads else None
+            outs.append(o)
+        _raise(self.ctx, lib().pnof_batch_bind(self.handle, ios))
+        self.inputs, self.outputs = list(inputs), outs   # keep the bound tensors alive
+        return outs
+
+    def run(self, graph: bool = True):
+        _raise(self.ctx, lib().pnof_batch_run(self.handle, 1 if graph else 0))
+        return self.outputs
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().pnof_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

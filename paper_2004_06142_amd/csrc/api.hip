@@ -2,6 +2,7 @@
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -443,6 +444,90 @@ pnof_status check_q(pnof_ctx ctx, const void* a, const int32_t* q_idx, int32_t n
 
 }  // namespace
 
+// ------------------------------------------------------------------------ batches
+namespace {
+
+// Geometry of one batch instance: sizes, leading dimensions and P-splits of the grouped launches.
+struct BatchGeom {
+  int nbf, nact, naux, ldk, ldw, nact32, ns2, ns3;
+};
+
+BatchGeom batch_geom(const pnof_problem& p) {
+  BatchGeom g{};
+  g.nbf = p.nbf;
+  g.nact = p.npairs * (p.ncwo + 1);
+  g.naux = p.naux;
+  g.ldk = (int)round_up(g.nbf, 32);
+  g.nact32 = g.ldw = (int)round_up(g.nact, 32);
+  // P-splits sized so that one work item of the b and Y contractions is about 64 k-tiles long
+  const int pps2 = std::max(1, 64 / cdiv(g.nbf, 32)), pps3 = std::max(1, 64 / cdiv(g.nact, 32));
+  g.ns2 = cdiv(g.naux, pps2);
+  g.ns3 = cdiv(g.naux, pps3);
+  return g;
+}
+
+}  // namespace
+
+struct pnof_batch_s {
+  pnof_ctx ctx = nullptr;
+  int ninst = 0, terms = 3;
+  std::vector<pnof_problem> probs;
+  std::vector<BatchGeom> geo;
+  std::vector<BInst> inst;            // host copies (pointers filled at plan and bind)
+  char* ws = nullptr;
+  size_t bytes = 0;
+  BInst* d_inst = nullptr;
+  G1Args* d_g1 = nullptr;
+  G2Args* d_g2 = nullptr;
+  G3Args* d_g3 = nullptr;
+  int* d_off = nullptr;               // 3 x (ninst + 1)
+  F64Gemm* d_f64 = nullptr;           // 4 x ninst: H C_A, D alpha, D^T D, C^T Y
+  int tot1 = 0, tot2 = 0, tot3 = 0;
+  BMax mx{};
+  int maxM[4] = {0, 0, 0, 0}, maxN[4] = {0, 0, 0, 0};
+  bool bound = false;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int launches = 13;
+};
+
+namespace {
+
+void batch_drop_graph(pnof_batch b) {
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+// The fixed launch sequence of one batch step.
+hipError_t batch_enqueue(pnof_batch b, hipStream_t s) {
+  const int n = b->ninst;
+  hipError_t e;
+#define BSTEP(expr) \
+  if ((e = (expr)) != hipSuccess) return e
+  BSTEP(batch_prep(s, n, b->d_inst, b->mx));
+  BSTEP(gemm_f64_grouped(s, n, b->maxM[0], b->maxN[0], false, true, b->d_f64));
+  BSTEP(batch_hpp(s, n, b->d_inst, b->mx));
+  BSTEP(df_bf16_gemm1_grouped(s, n, b->tot1, b->terms, b->d_g1, b->d_off));
+  BSTEP(df_bf16_gemm2_grouped(s, n, b->tot2, b->terms, b->d_g2, b->d_off + (n + 1)));
+  BSTEP(gemm_f64_grouped(s, n, b->maxM[1], b->maxN[1], false, true, b->d_f64 + n));
+  BSTEP(batch_add_diag(s, n, b->d_inst, b->mx));
+  BSTEP(df_bf16_gemm3_grouped(s, n, b->tot3, b->terms, b->d_g3, b->d_off + 2 * (n + 1)));
+  BSTEP(batch_reduce(s, n, b->d_inst, b->mx));
+  BSTEP(gemm_f64_grouped(s, n, b->maxM[2], b->maxN[2], true, true, b->d_f64 + 2 * n));
+  BSTEP(batch_energy_y(s, n, b->d_inst, b->mx));
+  BSTEP(gemm_f64_grouped(s, n, b->maxM[3], b->maxN[3], true, true, b->d_f64 + 3 * n));
+  BSTEP(batch_finish(s, n, b->d_inst, b->mx));
+#undef BSTEP
+  return hipSuccess;
+}
+
+pnof_status batch_fail(pnof_batch b, pnof_status st, const std::string& msg) { return fail(b ? b->ctx : nullptr, st, msg); }
+
+}  // namespace
+
 // ============================================================================ ABI
 extern "C" {
 
@@ -708,6 +793,211 @@ pnof_status pnof_orbital_step(pnof_ctx ctx, int32_t nbf, const double* lambda, c
   if (*ctx->host_info != 0)
     return fail(ctx, PNOF_E_EIG, "eigensolver did not converge (info = " + std::to_string(*ctx->host_info) + ")");
   return PNOF_OK;
+}
+
+pnof_status pnof_batch_plan(pnof_ctx ctx, int32_t ninst, const pnof_problem* probs, pnof_batch* out) {
+  if (!out) return fail(ctx, PNOF_E_ARG, "output pointer is NULL");
+  *out = nullptr;
+  pnof_status st = check_ctx(ctx);
+  if (st != PNOF_OK) return st;
+  if (ninst <= 0 || !probs) return fail(ctx, PNOF_E_ARG, "a batch needs ninst > 0 problems");
+  const int prec = probs[0].precision;
+  for (int i = 0; i < ninst; ++i) {
+    if ((st = check_problem(ctx, &probs[i])) != PNOF_OK)
+      return fail(ctx, st, "instance " + std::to_string(i) + ": " + ctx->err);
+    if (probs[i].ints != PNOF_INTS_DF_BF16)
+      return fail(ctx, PNOF_E_UNSUPPORTED, "batches take bfloat16 density-fitting factors (PNOF_INTS_DF_BF16)");
+    if (probs[i].precision != PNOF_BF16_SPLIT && probs[i].precision != PNOF_BF16)
+      return fail(ctx, PNOF_E_UNSUPPORTED, "batches run the bf16 contractions (PNOF_BF16_SPLIT or PNOF_BF16)");
+    if (probs[i].precision != prec) return fail(ctx, PNOF_E_ARG, "all instances of a batch share one precision");
+    if (probs[i].flags != 0) return fail(ctx, PNOF_E_UNSUPPORTED, "batches take no flags");
+  }
+  pnof_batch b = new pnof_batch_s();
+  b->ctx = ctx;
+  b->ninst = ninst;
+  b->terms = prec == PNOF_BF16_SPLIT ? 3 : 1;
+  b->probs.assign(probs, probs + ninst);
+  b->inst.resize(ninst);
+  // carve (measure, then allocate and carve again)
+  auto carve_all = [&](char* base) -> size_t {
+    Arena a(base);
+    b->geo.clear();
+    for (int i = 0; i < ninst; ++i) {
+      const pnof_problem& p = probs[i];
+      const BatchGeom g = batch_geom(p);
+      b->geo.push_back(g);
+      BInst& d = b->inst[i];
+      d = BInst{};
+      d.nbf = g.nbf; d.nact = g.nact; d.naux = g.naux; d.npairs = p.npairs; d.ncwo = p.ncwo;
+      d.functional = p.functional; d.terms = b->terms;
+      d.ldk = g.ldk; d.ldw = g.ldw; d.nact32 = g.nact32; d.ns2 = g.ns2; d.ns3 = g.ns3;
+      const long long n2 = (long long)g.nact * g.nact, ny = (long long)g.nbf * g.nact;
+      d.Bp = a.take<u16>((long long)g.naux * g.nbf * g.ldk);
+      d.cth = a.take<u16>((long long)g.nact32 * g.ldk);
+      d.xth = a.take<u16>((long long)g.naux * g.nact32 * g.ldk);
+      d.wh = a.take<u16>((long long)g.naux * g.nact32 * g.ldw);
+      if (b->terms > 1) {
+        d.ctl = a.take<u16>((long long)g.nact32 * g.ldk);
+        d.xtl = a.take<u16>((long long)g.naux * g.nact32 * g.ldk);
+        d.wl = a.take<u16>((long long)g.naux * g.nact32 * g.ldw);
+      }
+      d.alpha = a.take<double>(n2);
+      d.beta = a.take<double>(n2);
+      d.beta32 = a.take<float>(n2);
+      d.J = a.take<double>(n2);
+      d.K = a.take<double>(n2);
+      d.Kpart = a.take<double>((long long)g.ns2 * n2);
+      d.HC = a.take<double>(ny);
+      d.Y2e = a.take<double>(ny);
+      d.Y = a.take<double>(ny);
+      d.Ypart = a.take<float>((long long)g.ns3 * ny);
+      d.Hpp = a.take<double>(g.nact);
+      d.D = a.take<double>((long long)g.naux * g.nact);
+      d.dbuf = a.take<double>((long long)g.naux * g.nact);
+    }
+    b->d_inst = a.take<BInst>(ninst);
+    b->d_g1 = a.take<G1Args>(ninst);
+    b->d_g2 = a.take<G2Args>(ninst);
+    b->d_g3 = a.take<G3Args>(ninst);
+    b->d_off = a.take<int>(3LL * (ninst + 1));
+    b->d_f64 = a.take<F64Gemm>(4LL * ninst);
+    return a.off + 256;
+  };
+  for (int i = 0; i < ninst; ++i) {
+    const BatchGeom g = batch_geom(probs[i]);
+    const long long lim = (1LL << 31) - 1;
+    if (2LL * g.naux * g.nbf * g.ldk > lim || 2LL * g.naux * g.nact32 * g.ldk > lim || 2LL * g.naux * g.nact32 * g.ldw > lim) {
+      delete b;
+      return fail(ctx, PNOF_E_UNSUPPORTED, "instance " + std::to_string(i) + " is too large for a batch (2 GiB per buffer)");
+    }
+  }
+  b->bytes = carve_all(nullptr);
+  if (hipMalloc(&b->ws, b->bytes) != hipSuccess) {
+    hipGetLastError();
+    delete b;
+    return fail(ctx, PNOF_E_NOMEM, "batch workspace allocation failed");
+  }
+  carve_all(b->ws);
+  // grid maxima and work-item offsets
+  std::vector<int> off(3 * (ninst + 1), 0);
+  BMax mx{};
+  for (int i = 0; i < ninst; ++i) {
+    const BatchGeom& g = b->geo[i];
+    const long long n2 = (long long)g.nact * g.nact, ny = (long long)g.nbf * g.nact;
+    mx.nbf = std::max(mx.nbf, g.nbf);
+    mx.nact = std::max(mx.nact, g.nact);
+    mx.pack = std::max(mx.pack, (long long)g.naux * g.nact32 * g.ldk + (long long)g.naux * g.nbf * g.ldk);
+    mx.prep = std::max(mx.prep, std::max((long long)g.ns2 * n2, (long long)g.nact * g.nbf));
+    mx.y = std::max(mx.y, ny);
+    mx.k = std::max(mx.k, n2);
+    mx.diag = std::max(mx.diag, (long long)g.naux * g.nact);
+    b->maxM[0] = std::max(b->maxM[0], g.nbf);  b->maxN[0] = std::max(b->maxN[0], g.nact);   // H C_A
+    b->maxM[1] = std::max(b->maxM[1], g.naux); b->maxN[1] = std::max(b->maxN[1], g.nact);   // D alpha
+    b->maxM[2] = std::max(b->maxM[2], g.nact); b->maxN[2] = std::max(b->maxN[2], g.nact);   // D^T D
+    b->maxM[3] = std::max(b->maxM[3], g.nbf);  b->maxN[3] = std::max(b->maxN[3], g.nact);   // C^T Y
+  }
+  b->mx = mx;
+  *out = b;
+  return PNOF_OK;
+}
+
+pnof_status pnof_batch_bind(pnof_batch b, const pnof_batch_io* io) {
+  if (!b) return fail(nullptr, PNOF_E_ARG, "batch is NULL");
+  pnof_ctx ctx = b->ctx;
+  pnof_status st = check_ctx(ctx);
+  if (st != PNOF_OK) return st;
+  if (!io) return fail(ctx, PNOF_E_ARG, "io is NULL");
+  const int n = b->ninst;
+  for (int i = 0; i < n; ++i)
+    if (!io[i].C || !io[i].n || !io[i].H || !io[i].ints || !io[i].lambda || !io[i].E)
+      return fail(ctx, PNOF_E_ARG, "instance " + std::to_string(i) + ": C, n, H, ints, lambda and E are required");
+  batch_drop_graph(b);
+  std::vector<G1Args> g1(n);
+  std::vector<G2Args> g2(n);
+  std::vector<G3Args> g3(n);
+  std::vector<F64Gemm> f(4 * n);
+  std::vector<int> off(3 * (n + 1), 0);
+  for (int i = 0; i < n; ++i) {
+    BInst& d = b->inst[i];
+    const BatchGeom& g = b->geo[i];
+    d.C = io[i].C; d.n = io[i].n; d.H = io[i].H; d.B = static_cast<const u16*>(io[i].ints);
+    d.lam = io[i].lambda; d.E = io[i].E; d.dEdC = io[i].dEdC; d.dEdn = io[i].dEdn; d.asym = io[i].max_asym;
+    const long long nct = (long long)g.nact32 * g.ldk, nxt = (long long)g.naux * g.nact32 * g.ldk,
+                    nw = (long long)g.naux * g.nact32 * g.ldw;
+    const WsDims wd{g.nact32, 2 * nct, 2 * nxt, 2 * nw};
+    g1[i] = G1Args{g.nbf, g.nact, g.naux, d.cth, d.ctl, g.ldk, d.Bp, nullptr, (long long)g.nbf * g.ldk, g.ldk,
+                   2LL * g.naux * g.nbf * g.ldk, d.xth, d.xtl, g.ldk, wd};
+    g2[i] = G2Args{g.nbf, g.nact, g.naux, g.ns2, d.cth, d.ctl, g.ldk, d.xth, d.xtl, g.ldk, d.beta32, d.Kpart, d.D,
+                   d.wh, d.wl, g.ldw, wd};
+    g3[i] = G3Args{g.nbf, g.nact, g.naux, g.ns3, d.xth, d.xtl, g.ldk, d.wh, d.wl, g.ldw, d.Ypart, wd};
+    off[i + 1] = off[i] + g1_items(g1[i], 128, true);
+    off[(n + 1) + i + 1] = off[(n + 1) + i] + g2_items(g2[i]);
+    off[2 * (n + 1) + i + 1] = off[2 * (n + 1) + i] + g3_items(g3[i]);
+    f[i] = F64Gemm{g.nbf, g.nact, g.nbf, 1.0, d.H, g.nbf, 1, d.C, g.nbf, 1, 0.0, d.HC, g.nact, 1};
+    f[n + i] = F64Gemm{g.naux, g.nact, g.nact, 1.0, d.D, g.nact, 1, d.alpha, g.nact, 1, 0.0, d.dbuf, g.nact, 1};
+    f[2 * n + i] = F64Gemm{g.nact, g.nact, g.naux, 1.0, d.D, 1, g.nact, d.D, g.nact, 1, 0.0, d.J, g.nact, 1};
+    f[3 * n + i] = F64Gemm{g.nbf, g.nact, g.nbf, 1.0, d.C, 1, g.nbf, d.Y, g.nact, 1, 0.0, d.lam, g.nbf, 1};
+  }
+  b->tot1 = off[n];
+  b->tot2 = off[2 * (n + 1) - 1];
+  b->tot3 = off[3 * (n + 1) - 1];
+  hipStream_t s = ctx->stream;
+  DEV_CHECK(ctx, hipMemcpyAsync(b->d_inst, b->inst.data(), sizeof(BInst) * n, hipMemcpyHostToDevice, s));
+  DEV_CHECK(ctx, hipMemcpyAsync(b->d_g1, g1.data(), sizeof(G1Args) * n, hipMemcpyHostToDevice, s));
+  DEV_CHECK(ctx, hipMemcpyAsync(b->d_g2, g2.data(), sizeof(G2Args) * n, hipMemcpyHostToDevice, s));
+  DEV_CHECK(ctx, hipMemcpyAsync(b->d_g3, g3.data(), sizeof(G3Args) * n, hipMemcpyHostToDevice, s));
+  DEV_CHECK(ctx, hipMemcpyAsync(b->d_off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice, s));
+  DEV_CHECK(ctx, hipMemcpyAsync(b->d_f64, f.data(), sizeof(F64Gemm) * f.size(), hipMemcpyHostToDevice, s));
+  DEV_CHECK(ctx, batch_pack(s, n, b->d_inst, b->mx));
+  // the host staging vectors go out of scope: wait for the copies
+  DEV_CHECK(ctx, hipStreamSynchronize(s));
+  b->bound = true;
+  return PNOF_OK;
+}
+
+pnof_status pnof_batch_run(pnof_batch b, int32_t use_graph) {
+  if (!b) return fail(nullptr, PNOF_E_ARG, "batch is NULL");
+  pnof_ctx ctx = b->ctx;
+  pnof_status st = check_ctx(ctx);
+  if (st != PNOF_OK) return st;
+  if (!b->bound) return fail(ctx, PNOF_E_ARG, "pnof_batch_bind must be called before pnof_batch_run");
+  if (!use_graph) {
+    DEV_CHECK(ctx, batch_enqueue(b, ctx->stream));
+    return PNOF_OK;
+  }
+  if (!b->exec) {
+    if (!b->cap) DEV_CHECK(ctx, hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    DEV_CHECK(ctx, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    hipError_t e = batch_enqueue(b, b->cap);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(b->cap, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (g) hipGraphDestroy(g);
+      hipGetLastError();
+      return fail(ctx, PNOF_E_DEVICE, std::string("graph capture failed: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    b->graph = g;
+    DEV_CHECK(ctx, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  }
+  DEV_CHECK(ctx, hipGraphLaunch(b->exec, ctx->stream));
+  return PNOF_OK;
+}
+
+pnof_status pnof_batch_info(pnof_batch b, size_t* bytes, int32_t* launches) {
+  if (!b) return fail(nullptr, PNOF_E_ARG, "batch is NULL");
+  if (bytes) *bytes = b->bytes;
+  if (launches) *launches = b->launches;
+  return PNOF_OK;
+}
+
+void pnof_batch_destroy(pnof_batch b) {
+  if (!b) return;
+  hipSetDevice(b->ctx->device);
+  hipStreamSynchronize(b->ctx->stream);
+  batch_drop_graph(b);
+  if (b->cap) hipStreamDestroy(b->cap);
+  if (b->ws) hipFree(b->ws);
+  delete b;
 }
 
 }  // extern "C"

@@ -24,6 +24,38 @@ __host__ __device__ inline int weak_index(int g, int k, int npairs, int ncwo) {
   return npairs + ncwo * (npairs - 1 - g) + k;
 }
 
+// ---------------------------------------------------------------- PNOF coefficients
+// alpha_pq, beta_pq of E_2 = sum_pq alpha_pq J_pq + beta_pq K_pq (Eqs. Eg, Efg, Efg_s).
+__device__ inline void pnof_coeff(int p, int q, double np_, double nq, int npairs, int ncwo, int functional,
+                                  double& a, double& b) {
+  a = 0.0;
+  if (pair_of(p, npairs, ncwo) == pair_of(q, npairs, ncwo)) {
+    if (p == q) b = np_;
+    else {
+      const double s = sqrt(np_ * nq);
+      b = (p < npairs || q < npairs) ? -s : s;
+    }
+  } else {
+    a = 2.0 * np_ * nq;
+    if (functional == 5) b = -np_ * nq;
+    else if (functional == 8) b = -np_ * nq - 4.0 * (np_ * (1.0 - np_)) * (nq * (1.0 - nq));
+    else b = -np_ * nq - sqrt(np_ * (1.0 - np_)) * sqrt(nq * (1.0 - nq));
+  }
+}
+
+// Term q != p of dE/dn_p at fixed J, K (derivative of Eqs. Eg, Efg); php = sqrt(n_p (1 - n_p)).
+__device__ inline double grad_n_term(int p, int q, double np_, double nq, double php, double jpq, double kpq,
+                                     int npairs, int ncwo, int functional) {
+  if (pair_of(q, npairs, ncwo) == pair_of(p, npairs, ncwo)) {
+    const double sg = (p < npairs || q < npairs) ? -1.0 : 1.0;
+    return sg * sqrt(nq / np_) * kpq;
+  }
+  double s = 4.0 * nq * jpq - 2.0 * nq * kpq;
+  if (functional == 7) s += -sqrt(nq * (1.0 - nq)) * (1.0 - 2.0 * np_) / php * kpq;
+  else if (functional == 8) s += -8.0 * (1.0 - 2.0 * np_) * nq * (1.0 - nq) * kpq;
+  return s;
+}
+
 // ---------------------------------------------------------------- bf16 helpers
 // Round-to-nearest-even float32 -> bfloat16 bits (inputs here are finite).
 __device__ __forceinline__ u16 f32_to_bf16_bits(float x) {
@@ -43,8 +75,8 @@ __device__ __forceinline__ void split_f64(double x, u16& hi, u16& lo) {
   lo = f32_to_bf16_bits((float)(x - (double)bf16_bits_to_f32(hi)));
 }
 
-inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
-inline long long round_up(long long a, long long b) { return (a + b - 1) / b * b; }
+__host__ __device__ inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
+__host__ __device__ inline long long round_up(long long a, long long b) { return (a + b - 1) / b * b; }
 
 // ---------------------------------------------------------------- f64 GEMM (k_gemm_f64.hip)
 // C[b] = alpha * A[b] B[b] + beta * C[b] with strided views
@@ -54,6 +86,22 @@ hipError_t gemm_f64(hipStream_t s, int M, int N, int K, int batch, double alpha,
                     long long sam, long long sak, long long sab, const double* B, long long sbk,
                     long long sbn, long long sbb, double beta, double* C, long long scm, long long scn,
                     long long scb);
+
+// Grouped form: product g of tab (device memory) is C = alpha A B + beta C with its own sizes and
+// pointers; all products share the unit-stride pattern (a_unit_m: sam == 1, b_unit_n: sbn == 1).
+struct F64Gemm {
+  int M, N, K;
+  double alpha;
+  const double* A;
+  long long sam, sak;
+  const double* B;
+  long long sbk, sbn;
+  double beta;
+  double* C;
+  long long scm, scn;
+};
+hipError_t gemm_f64_grouped(hipStream_t s, int ngemm, int maxM, int maxN, bool a_unit_m, bool b_unit_n,
+                            const F64Gemm* tab);
 
 // FP64 three-index contractions of one P-chunk (np rows of B).
 //  gemm1: XT[P][p][mu] = sum_nu Ct[p][nu] B_P[mu][nu]      (Ct: nact x ldk, XT: ld ldx)
@@ -80,6 +128,67 @@ struct WsDims {
   int nact32;
   long long ct_bytes, xt_bytes, w_bytes;
 };
+// Arguments of one launch of each contraction, for one problem (or one instance of a batch).
+struct G1Args {   // XT_P[p][mu] = sum_nu Ct[p][nu] B_P[mu][nu]
+  int nbf, nact, np;
+  const u16* ct_hi;
+  const u16* ct_lo;
+  int ldk;
+  const u16* b_hi;
+  const u16* b_lo;
+  long long bstride;   // elements between B_P and B_{P+1}
+  int ldb;
+  long long b_bytes;   // readable bytes from b_hi (and b_lo) onwards
+  u16* xt_hi;
+  u16* xt_lo;
+  int ldx;
+  WsDims ws;
+};
+struct G2Args {   // b_P = Ct XT_P^T; K partials, D, W
+  int nbf, nact, np, nsplit;
+  const u16* ct_hi;
+  const u16* ct_lo;
+  int ldk;
+  const u16* xt_hi;
+  const u16* xt_lo;
+  int ldx;
+  const float* beta32;
+  double* Kpart;
+  double* Dc;
+  u16* w_hi;
+  u16* w_lo;
+  int ldw;
+  WsDims ws;
+};
+struct G3Args {   // Ypart[s] = sum_{P in s} X_P W_P
+  int nbf, nact, np, nsplit;
+  const u16* xt_hi;
+  const u16* xt_lo;
+  int ldx;
+  const u16* w_hi;
+  const u16* w_lo;
+  int ldw;
+  float* Ypart;
+  WsDims ws;
+};
+// Work items of one launch.  The stacked form of X treats the rows (P, mu) of np consecutive B_P
+// as one matrix (B_P rows padded to ldb, bstride == nbf * ldb), so short rows do not waste tiles.
+__host__ __device__ inline int g1_items(const G1Args& a, int g1n, bool stacked) {
+  return cdiv(a.nact, 128) * (stacked ? cdiv((long long)a.np * a.nbf, g1n) : a.np * cdiv(a.nbf, g1n));
+}
+__host__ __device__ inline int g2_items(const G2Args& a) {
+  const int t = cdiv(a.nact, 128);
+  return a.nsplit * t * (t + 1) / 2;
+}
+__host__ __device__ inline int g3_items(const G3Args& a) { return a.nsplit * cdiv(a.nbf, 128) * cdiv(a.nact, 128); }
+
+// Grouped launches over the instances of a batch: tab[i] are the arguments of instance i (device
+// memory), off[i] the first work item of instance i (off[ninst] = total).  terms as above;
+// B must be bf16 (exact) with padded rows, and every leading dimension a multiple of 32.
+hipError_t df_bf16_gemm1_grouped(hipStream_t s, int ninst, int total, int terms, const G1Args* tab, const int* off);
+hipError_t df_bf16_gemm2_grouped(hipStream_t s, int ninst, int total, int terms, const G2Args* tab, const int* off);
+hipError_t df_bf16_gemm3_grouped(hipStream_t s, int ninst, int total, int terms, const G3Args* tab, const int* off);
+
 hipError_t df_bf16_gemm1(hipStream_t s, int nbf, int nact, int np, int terms, SplitPtr Ct, int ldk, SplitPtr Bp,
                          long long bstride, int ldb, long long b_bytes, u16* XT_hi, u16* XT_lo, int ldx, int variant,
                          const WsDims& d);
@@ -88,6 +197,40 @@ hipError_t df_bf16_gemm2(hipStream_t s, int nbf, int nact, int np, int nsplit, i
                          double* Kpart, double* Dchunk, u16* W_hi, u16* W_lo, int ldw, const WsDims& d);
 hipError_t df_bf16_gemm3(hipStream_t s, int nbf, int nact, int np, int nsplit, int terms, SplitPtr XT,
                          int ldx, SplitPtr W, int ldw, float* Ypart, int variant, const WsDims& d);
+
+// ---------------------------------------------------------------- batches (k_batch.hip)
+// One instance of a batch: sizes, the caller's inputs and outputs, and its slices of the batch
+// workspace.  Leading dimensions: ldk = ldx = round_up(nbf, 32), ldw = nact32 = round_up(nact, 32).
+struct BInst {
+  int nbf, nact, naux, npairs, ncwo, functional, terms;
+  int ldk, ldw, nact32, ns2, ns3;
+  const double* C;
+  const double* n;
+  const double* H;
+  const u16* B;         // caller's bf16 B, naux x nbf x nbf
+  double* lam;          // caller's outputs (dEdC, dEdn, asym may be null)
+  double* E;
+  double* dEdC;
+  double* dEdn;
+  double* asym;
+  u16* Bp;              // packed B: naux x nbf x ldk, zero pads
+  double *alpha, *beta, *HC, *Hpp, *J, *K, *Kpart, *D, *dbuf, *Y2e, *Y;
+  float* beta32;
+  float* Ypart;
+  u16 *cth, *ctl, *xth, *xtl, *wh, *wl;
+};
+// Each launch covers every instance (blockIdx.y = instance); maxima size the grids.
+struct BMax {
+  int nbf, nact;
+  long long pack, zero, prep, y, k, diag;
+};
+hipError_t batch_pack(hipStream_t s, int ninst, const BInst* tab, const BMax& mx);   // B -> Bp, zero workspace
+hipError_t batch_prep(hipStream_t s, int ninst, const BInst* tab, const BMax& mx);   // coeffs, split C_A, zero K partials
+hipError_t batch_hpp(hipStream_t s, int ninst, const BInst* tab, const BMax& mx);
+hipError_t batch_add_diag(hipStream_t s, int ninst, const BInst* tab, const BMax& mx);
+hipError_t batch_reduce(hipStream_t s, int ninst, const BInst* tab, const BMax& mx);  // Y2e, K
+hipError_t batch_energy_y(hipStream_t s, int ninst, const BInst* tab, const BMax& mx);
+hipError_t batch_finish(hipStream_t s, int ninst, const BInst* tab, const BMax& mx);  // lambda cols, dE/dC, dE/dn, asym
 
 // ---------------------------------------------------------------- small kernels (k_small.hip)
 hipError_t fill_f64(hipStream_t s, double* p, long long n, double v);

@@ -445,41 +445,60 @@ __device__ __forceinline__ int xcd_item(int total) {
   return w < total ? w : -1;
 }
 
-// Shapes of the workspace operands: Ct is nact32 x ldk, each XT_P is nact32 x ldx and each W_P is
-// nact32 x ldw (nact32 = nact rounded up to 32), row-major, zero outside the valid block.
-struct WS {
-  int nact32;
-  long long ct_bytes;   // bytes of one Ct array (hi or lo)
-  long long xt_bytes;   // bytes of one XT array (all P of the chunk)
-  long long w_bytes;    // bytes of one W array
-};
+// Shapes of the workspace operands (WsDims): Ct is nact32 x ldk, each XT_P is nact32 x ldx and each
+// W_P is nact32 x ldw (nact32 = nact rounded up to 32), row-major, zero outside the valid block.
+
+// Instance of a grouped launch that owns work item w: off[i] <= w < off[i+1].
+__device__ __forceinline__ int find_instance(const int* __restrict__ off, int ninst, int w) {
+  int lo = 0, hi = ninst - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= w) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
 
 // gemm1: XT_P[p][mu] = sum_nu Ct[p][nu] B_P[mu][nu], written as a hi/lo pair.  Tile 128 (p) x G1N (mu).
-template <int TERMS, bool BLO, int G1N, int MINB, bool VEC>
-__global__ __launch_bounds__(256, MINB) void gemm1_kernel(int nbf, int nact, int np, const u16* __restrict__ ct_hi,
-                                                       const u16* __restrict__ ct_lo, int ldk,
-                                                       const u16* __restrict__ b_hi, const u16* __restrict__ b_lo,
-                                                       long long bstride, int ldb, long long b_bytes,
-                                                       u16* __restrict__ xt_hi, u16* __restrict__ xt_lo, int ldx,
-                                                       WS ws) {
+// STACK: the n-tiles run over the stacked rows (P, mu) of all np rows of B.
+template <int TERMS, bool BLO, int G1N, int MINB, bool VEC, bool STACK>
+__device__ __forceinline__ void gemm1_body(int w, const G1Args& g) {
   constexpr bool ALO = TERMS >= 2;
   constexpr int G1M = 128;
-  const int tm_n = (nact + G1M - 1) / G1M, tn_n = (nbf + G1N - 1) / G1N;
-  const int w = xcd_item(np * tm_n * tn_n);
-  if (w < 0) return;
-  const int P = w / (tm_n * tn_n), tile = w % (tm_n * tn_n);
-  const int m0 = (tile / tn_n) * G1M, n0 = (tile % tn_n) * G1N;
-  const long long xoff = (long long)P * ws.nact32 * ldx;
-  u16* XTh = xt_hi + xoff;
-  u16* XTl = xt_lo ? xt_lo + xoff : nullptr;
+  const int nbf = g.nbf, nact = g.nact, ldx = g.ldx;
+  const int tm_n = (nact + G1M - 1) / G1M;
+  int P = 0, m0, n0;
+  if constexpr (STACK) {
+    m0 = (w % tm_n) * G1M;
+    n0 = (w / tm_n) * G1N;
+  } else {
+    const int tn_n = (nbf + G1N - 1) / G1N;
+    P = w / (tm_n * tn_n);
+    const int tile = w % (tm_n * tn_n);
+    m0 = (tile / tn_n) * G1M;
+    n0 = (tile % tn_n) * G1N;
+  }
+  const long long pstride = (long long)g.ws.nact32 * ldx;
+  u16* XTh = g.xt_hi + (STACK ? 0 : P * pstride);
+  u16* XTl = g.xt_lo ? g.xt_lo + (STACK ? 0 : P * pstride) : nullptr;
+  const long long nrows = (long long)g.np * nbf;
   f32x4 acc[G1M / 32][G1N / 32];
   auto epi = [&](int, f32x4(&a)[G1M / 32][G1N / 32]) {
 #pragma unroll
     for (int i = 0; i < G1M / 32; ++i)
 #pragma unroll
       for (int jn = 0; jn < G1N / 32; ++jn) {
-        const int mu = n0 + col_of<G1N>(jn);
-        if (mu >= nbf) continue;
+        long long xo;
+        if constexpr (STACK) {
+          const int c = n0 + col_of<G1N>(jn);
+          if (c >= nrows) continue;
+          const int Pc = c / nbf;
+          xo = Pc * pstride + (c - Pc * nbf);
+        } else {
+          const int mu = n0 + col_of<G1N>(jn);
+          if (mu >= nbf) continue;
+          xo = mu;
+        }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int p = m0 + row_of<G1M>(i, j);
@@ -487,26 +506,27 @@ __global__ __launch_bounds__(256, MINB) void gemm1_kernel(int nbf, int nact, int
           u16 h, l;
           if (TERMS == 1) { h = f32_to_bf16_bits(a[i][jn][j]); l = 0; }
           else split_f32(a[i][jn][j], h, l);
-          XTh[(long long)p * ldx + mu] = h;
-          if (XTl) XTl[(long long)p * ldx + mu] = l;
+          XTh[(long long)p * ldx + xo] = h;
+          if (XTl) XTl[(long long)p * ldx + xo] = l;
         }
       }
   };
   if constexpr (VEC) {
-    // two blocks per compute unit for the 128 x 128 tile, one for the wide tile
-    constexpr int S = ring_depth(G1M, G1N, ALO, BLO, G1N == 128 ? 81920 : 163840);
+    // the LDS of one compute unit is shared by MINB blocks
+    constexpr int S = ring_depth(G1M, G1N, ALO, BLO, MINB == 2 ? 81920 : 163840);
     __shared__ Ring<G1M, G1N, ALO, BLO, S> sm;
-    auto A = [&](int) { return DOpnd{ct_hi, ct_lo, ldk, ws.ct_bytes}; };
+    auto A = [&](int) { return DOpnd{g.ct_hi, g.ct_lo, g.ldk, g.ws.ct_bytes}; };
     auto B = [&](int) {
-      const long long o = (long long)P * bstride;
-      return DOpnd{b_hi + o, BLO ? b_lo + o : nullptr, ldb, b_bytes - 2 * o};
+      const long long o = (long long)P * g.bstride;
+      return DOpnd{g.b_hi + o, BLO ? g.b_lo + o : nullptr, g.ldb, g.b_bytes - 2 * o};
     };
     mainloop_dl<G1M, G1N, ALO, BLO, S, false, false, true>(sm, 1, 0, nbf, m0, n0, A, B, acc, epi);
   } else {
     __shared__ Stage<G1M, G1N, ALO, BLO> sm;
-    auto A = [&](int) { return Opnd{ct_hi, ct_lo, ldk, nact, nbf, false}; };
+    auto A = [&](int) { return Opnd{g.ct_hi, g.ct_lo, g.ldk, nact, nbf, false}; };
     auto B = [&](int) {
-      return Opnd{b_hi + (long long)P * bstride, BLO ? b_lo + (long long)P * bstride : nullptr, ldb, nbf, nbf, false};
+      const long long o = (long long)P * g.bstride;
+      return Opnd{g.b_hi + o, BLO ? g.b_lo + o : nullptr, g.ldb, STACK ? (int)nrows : nbf, nbf, false};
     };
     mainloop<G1M, G1N, ALO, BLO, false, false, true>(sm, 1, 0, nbf, m0, n0, A, B, acc, epi);
   }
@@ -516,18 +536,11 @@ __global__ __launch_bounds__(256, MINB) void gemm1_kernel(int nbf, int nact, int
 // over the successive P-chunks of one call), D[P][p] = b_pp, W_P = b o beta as a hi/lo pair, written
 // in full (off-diagonal tiles store their mirror image as well).
 template <int TERMS, bool VEC>
-__global__ __launch_bounds__(256, 1) void gemm2_kernel(int nbf, int nact, int np, int nsplit,
-                                                       const u16* __restrict__ ct_hi, const u16* __restrict__ ct_lo,
-                                                       int ldk, const u16* __restrict__ xt_hi,
-                                                       const u16* __restrict__ xt_lo, int ldx,
-                                                       const float* __restrict__ beta32, double* __restrict__ Kpart,
-                                                       double* __restrict__ Dc, u16* __restrict__ w_hi,
-                                                       u16* __restrict__ w_lo, int ldw, WS ws) {
+__device__ __forceinline__ void gemm2_body(int w, const G2Args& g) {
   constexpr bool LO = TERMS >= 3;
+  const int nbf = g.nbf, nact = g.nact, np = g.np, nsplit = g.nsplit, ldw = g.ldw, ldx = g.ldx;
   const int tt = (nact + T2 - 1) / T2;
   const int ntri = tt * (tt + 1) / 2;
-  const int w = xcd_item(nsplit * ntri);
-  if (w < 0) return;
   const int s = w / ntri;
   int tm, tn;
   tri_tile(w % ntri, tt, tm, tn);
@@ -542,15 +555,15 @@ __global__ __launch_bounds__(256, 1) void gemm2_kernel(int nbf, int nact, int np
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int p = m0 + row_of<T2>(i, j), q = n0 + col_of<T2>(jn);
-        bet[i][jn][j] = (p < nact && q < nact) ? beta32[(long long)p * nact + q] : 0.f;
+        bet[i][jn][j] = (p < nact && q < nact) ? g.beta32[(long long)p * nact + q] : 0.f;
       }
   f32x4 kacc[4][4], acc[4][4];
   zero(kacc);
   const bool diag = (tm == tn);
   auto epi = [&](int seg, f32x4(&a)[4][4]) {
     const int P = pb + seg;
-    u16* Wh = w_hi + (long long)P * ws.nact32 * ldw;
-    u16* Wl = LO ? w_lo + (long long)P * ws.nact32 * ldw : nullptr;
+    u16* Wh = g.w_hi + (long long)P * g.ws.nact32 * ldw;
+    u16* Wl = LO ? g.w_lo + (long long)P * g.ws.nact32 * ldw : nullptr;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -567,7 +580,7 @@ __global__ __launch_bounds__(256, 1) void gemm2_kernel(int nbf, int nact, int np
             else split_f32(wv, h, l);
             Wh[(long long)p * ldw + q] = h;
             if (LO) Wl[(long long)p * ldw + q] = l;
-            if (diag && p == q) Dc[(long long)P * nact + p] = (double)b;
+            if (diag && p == q) g.Dc[(long long)P * nact + p] = (double)b;
           }
         }
     if (!diag) {
@@ -605,22 +618,22 @@ __global__ __launch_bounds__(256, 1) void gemm2_kernel(int nbf, int nact, int np
   if constexpr (VEC) {
     constexpr int S = ring_depth(T2, T2, LO, LO, 163840);
     __shared__ Ring<T2, T2, LO, LO, S> sm;
-    auto A = [&](int) { return DOpnd{ct_hi, ct_lo, ldk, ws.ct_bytes}; };
+    auto A = [&](int) { return DOpnd{g.ct_hi, g.ct_lo, g.ldk, g.ws.ct_bytes}; };
     auto B = [&](int seg) {
-      const long long off = (long long)(pb + seg) * ws.nact32 * ldx;
-      return DOpnd{xt_hi + off, LO ? xt_lo + off : nullptr, ldx, ws.xt_bytes - 2 * off};
+      const long long off = (long long)(pb + seg) * g.ws.nact32 * ldx;
+      return DOpnd{g.xt_hi + off, LO ? g.xt_lo + off : nullptr, ldx, g.ws.xt_bytes - 2 * off};
     };
     mainloop_dl<T2, T2, LO, LO, S, false, false, true>(sm, pe - pb, 0, nbf, m0, n0, A, B, acc, epi);
   } else {
     __shared__ Stage<T2, T2, LO, LO> sm;
-    auto A = [&](int) { return Opnd{ct_hi, ct_lo, ldk, nact, nbf, false}; };
+    auto A = [&](int) { return Opnd{g.ct_hi, g.ct_lo, g.ldk, nact, nbf, false}; };
     auto B = [&](int seg) {
-      const long long off = (long long)(pb + seg) * ws.nact32 * ldx;
-      return Opnd{xt_hi + off, LO ? xt_lo + off : nullptr, ldx, nact, nbf, false};
+      const long long off = (long long)(pb + seg) * g.ws.nact32 * ldx;
+      return Opnd{g.xt_hi + off, LO ? g.xt_lo + off : nullptr, ldx, nact, nbf, false};
     };
     mainloop<T2, T2, LO, LO, false, false, true>(sm, pe - pb, 0, nbf, m0, n0, A, B, acc, epi);
   }
-  double* Kp = Kpart + (long long)s * nact * nact;
+  double* Kp = g.Kpart + (long long)s * nact * nact;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -636,17 +649,12 @@ __global__ __launch_bounds__(256, 1) void gemm2_kernel(int nbf, int nact, int np
 // W (stored in full) as a row operand; every block walks (P, r) in the same order, so blocks of one
 // split that share an operand panel read it at about the same time.
 // Tile G3M (mu) x 128 (q).
-template <int TERMS, int G3M, int MINB, bool VEC>
-__global__ __launch_bounds__(256, MINB) void gemm3_kernel(int nbf, int nact, int np, int nsplit,
-                                                       const u16* __restrict__ xt_hi, const u16* __restrict__ xt_lo,
-                                                       int ldx, const u16* __restrict__ w_hi,
-                                                       const u16* __restrict__ w_lo, int ldw,
-                                                       float* __restrict__ Ypart, WS ws) {
+template <int TERMS, int G3M, bool VEC>
+__device__ __forceinline__ void gemm3_body(int w, const G3Args& g) {
   constexpr bool LO = TERMS >= 3;
   constexpr int G3N = T2;
+  const int nbf = g.nbf, nact = g.nact, np = g.np, nsplit = g.nsplit, ldx = g.ldx, ldw = g.ldw;
   const int tm_n = (nbf + G3M - 1) / G3M, tn_n = (nact + G3N - 1) / G3N;
-  const int w = xcd_item(nsplit * tm_n * tn_n);
-  if (w < 0) return;
   const int s = w / (tm_n * tn_n);
   int tm, tn;
   grouped_tile<4>(w % (tm_n * tn_n), tm_n, tn_n, tm, tn);
@@ -659,27 +667,27 @@ __global__ __launch_bounds__(256, MINB) void gemm3_kernel(int nbf, int nact, int
     constexpr int S = ring_depth(G3M, G3N, LO, LO, 163840);
     __shared__ Ring<G3M, G3N, LO, LO, S> sm;
     auto A = [&](int seg) {
-      const long long off = (long long)(pb + seg) * ws.nact32 * ldx;
-      return DOpnd{xt_hi + off, LO ? xt_lo + off : nullptr, ldx, ws.xt_bytes - 2 * off};
+      const long long off = (long long)(pb + seg) * g.ws.nact32 * ldx;
+      return DOpnd{g.xt_hi + off, LO ? g.xt_lo + off : nullptr, ldx, g.ws.xt_bytes - 2 * off};
     };
     auto B = [&](int seg) {
-      const long long off = (long long)(pb + seg) * ws.nact32 * ldw;
-      return DOpnd{w_hi + off, LO ? w_lo + off : nullptr, ldw, ws.w_bytes - 2 * off};
+      const long long off = (long long)(pb + seg) * g.ws.nact32 * ldw;
+      return DOpnd{g.w_hi + off, LO ? g.w_lo + off : nullptr, ldw, g.ws.w_bytes - 2 * off};
     };
     mainloop_dl<G3M, G3N, LO, LO, S, true, false, false>(sm, pe - pb, 0, nact, m0, n0, A, B, acc, none);
   } else {
     __shared__ Stage<G3M, G3N, LO, LO> sm;
     auto A = [&](int seg) {
-      const long long off = (long long)(pb + seg) * ws.nact32 * ldx;
-      return Opnd{xt_hi + off, LO ? xt_lo + off : nullptr, ldx, nbf, nact, true};
+      const long long off = (long long)(pb + seg) * g.ws.nact32 * ldx;
+      return Opnd{g.xt_hi + off, LO ? g.xt_lo + off : nullptr, ldx, nbf, nact, true};
     };
     auto B = [&](int seg) {
-      const long long off = (long long)(pb + seg) * ws.nact32 * ldw;
-      return Opnd{w_hi + off, LO ? w_lo + off : nullptr, ldw, nact, nact, false};
+      const long long off = (long long)(pb + seg) * g.ws.nact32 * ldw;
+      return Opnd{g.w_hi + off, LO ? g.w_lo + off : nullptr, ldw, nact, nact, false};
     };
     mainloop<G3M, G3N, LO, LO, true, false, false>(sm, pe - pb, 0, nact, m0, n0, A, B, acc, none);
   }
-  float* Y = Ypart + (long long)s * nbf * nact;
+  float* Y = g.Ypart + (long long)s * nbf * nact;
 #pragma unroll
   for (int i = 0; i < G3M / 32; ++i)
 #pragma unroll
@@ -691,43 +699,85 @@ __global__ __launch_bounds__(256, MINB) void gemm3_kernel(int nbf, int nact, int
       }
 }
 
+template <int TERMS, bool BLO, int G1N, int MINB, bool VEC>
+__global__ __launch_bounds__(256, MINB) void gemm1_kernel(G1Args g) {
+  const int w = xcd_item(g1_items(g, G1N, false));
+  if (w < 0) return;
+  gemm1_body<TERMS, BLO, G1N, MINB, VEC, false>(w, g);
+}
+template <int TERMS, bool VEC>
+__global__ __launch_bounds__(256, 1) void gemm2_kernel(G2Args g) {
+  const int w = xcd_item(g2_items(g));
+  if (w < 0) return;
+  gemm2_body<TERMS, VEC>(w, g);
+}
+template <int TERMS, int G3M, int MINB, bool VEC>
+__global__ __launch_bounds__(256, MINB) void gemm3_kernel(G3Args g) {
+  const int w = xcd_item(g3_items(g));
+  if (w < 0) return;
+  gemm3_body<TERMS, G3M, VEC>(w, g);
+}
+
+// Grouped forms: one launch over the work items of every instance of a batch.
+template <int TERMS>
+__global__ __launch_bounds__(256, 1) void gemm1_grouped(const G1Args* __restrict__ tab, const int* __restrict__ off,
+                                                        int ninst, int total) {
+  const int w = xcd_item(total);
+  if (w < 0) return;
+  const int i = find_instance(off, ninst, w);
+  const G1Args g = tab[i];
+  gemm1_body<TERMS, false, 128, 1, true, true>(w - off[i], g);
+}
+template <int TERMS>
+__global__ __launch_bounds__(256, 1) void gemm2_grouped(const G2Args* __restrict__ tab, const int* __restrict__ off,
+                                                        int ninst, int total) {
+  const int w = xcd_item(total);
+  if (w < 0) return;
+  const int i = find_instance(off, ninst, w);
+  const G2Args g = tab[i];
+  gemm2_body<TERMS, true>(w - off[i], g);
+}
+template <int TERMS>
+__global__ __launch_bounds__(256, 1) void gemm3_grouped(const G3Args* __restrict__ tab, const int* __restrict__ off,
+                                                        int ninst, int total) {
+  const int w = xcd_item(total);
+  if (w < 0) return;
+  const int i = find_instance(off, ninst, w);
+  const G3Args g = tab[i];
+  gemm3_body<TERMS, 128, true>(w - off[i], g);
+}
+
 inline dim3 xcd_grid(long long items) { return dim3((unsigned)(cdiv(items, NXCD) * NXCD)); }
 
 }  // namespace
 
 inline bool al16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
-
-inline WS make_ws(const WsDims& d) { return WS{d.nact32, d.ct_bytes, d.xt_bytes, d.w_bytes}; }
-
 template <int TERMS, bool BLO, int G1N, int MINB>
-static void launch_g1(hipStream_t s, int nbf, int nact, int np, SplitPtr Ct, int ldk, SplitPtr Bp, long long bstride,
-                      int ldb, long long b_bytes, u16* XT_hi, u16* XT_lo, int ldx, const WsDims& d) {
-  const dim3 grid = xcd_grid((long long)np * cdiv(nact, 128) * cdiv(nbf, G1N));
+static void launch_g1(hipStream_t s, const G1Args& g) {
+  const dim3 grid = xcd_grid(g1_items(g, G1N, false));
   // direct-to-LDS needs 16-byte aligned rows of the caller's B (nbf % 8 == 0)
-  const bool vec = (ldb % 8 == 0) && (nbf % 8 == 0) && (bstride % 8 == 0) && al16(Bp.hi) && (!Bp.lo || al16(Bp.lo)) &&
-                   al16(Ct.hi) && (!Ct.lo || al16(Ct.lo)) && (ldk % 32 == 0) && (ldx % 32 == 0);
-  if (vec)
-    hipLaunchKernelGGL((gemm1_kernel<TERMS, BLO, G1N, MINB, true>), grid, dim3(256), 0, s, nbf, nact, np, Ct.hi, Ct.lo,
-                       ldk, Bp.hi, Bp.lo, bstride, ldb, b_bytes, XT_hi, XT_lo, ldx, make_ws(d));
-  else
-    hipLaunchKernelGGL((gemm1_kernel<TERMS, BLO, G1N, MINB, false>), grid, dim3(256), 0, s, nbf, nact, np, Ct.hi, Ct.lo,
-                       ldk, Bp.hi, Bp.lo, bstride, ldb, b_bytes, XT_hi, XT_lo, ldx, make_ws(d));
+  const bool vec = (g.ldb % 8 == 0) && (g.nbf % 8 == 0) && (g.bstride % 8 == 0) && al16(g.b_hi) &&
+                   (!g.b_lo || al16(g.b_lo)) && al16(g.ct_hi) && (!g.ct_lo || al16(g.ct_lo)) && (g.ldk % 32 == 0) &&
+                   (g.ldx % 32 == 0);
+  if (vec) hipLaunchKernelGGL((gemm1_kernel<TERMS, BLO, G1N, MINB, true>), grid, dim3(256), 0, s, g);
+  else hipLaunchKernelGGL((gemm1_kernel<TERMS, BLO, G1N, MINB, false>), grid, dim3(256), 0, s, g);
 }
 
 hipError_t df_bf16_gemm1(hipStream_t s, int nbf, int nact, int np, int terms, SplitPtr Ct, int ldk, SplitPtr Bp,
                          long long bstride, int ldb, long long b_bytes, u16* XT_hi, u16* XT_lo, int ldx, int variant,
                          const WsDims& d) {
   if (np <= 0) return hipSuccess;
+  const G1Args g{nbf, nact, np, Ct.hi, Ct.lo, ldk, Bp.hi, Bp.lo, bstride, ldb, b_bytes, XT_hi, XT_lo, ldx, d};
   const bool wide = (variant == 1);
   if (terms == 1) {
-    if (wide) launch_g1<1, false, 256, 1>(s, nbf, nact, np, Ct, ldk, Bp, bstride, ldb, b_bytes, XT_hi, XT_lo, ldx, d);
-    else launch_g1<1, false, 128, 2>(s, nbf, nact, np, Ct, ldk, Bp, bstride, ldb, b_bytes, XT_hi, XT_lo, ldx, d);
+    if (wide) launch_g1<1, false, 256, 1>(s, g);
+    else launch_g1<1, false, 128, 2>(s, g);
   } else if (Bp.lo == nullptr) {
-    if (wide) launch_g1<2, false, 256, 1>(s, nbf, nact, np, Ct, ldk, Bp, bstride, ldb, b_bytes, XT_hi, XT_lo, ldx, d);
-    else launch_g1<2, false, 128, 2>(s, nbf, nact, np, Ct, ldk, Bp, bstride, ldb, b_bytes, XT_hi, XT_lo, ldx, d);
+    if (wide) launch_g1<2, false, 256, 1>(s, g);
+    else launch_g1<2, false, 128, 2>(s, g);
   } else {
-    if (wide) launch_g1<3, true, 256, 1>(s, nbf, nact, np, Ct, ldk, Bp, bstride, ldb, b_bytes, XT_hi, XT_lo, ldx, d);
-    else launch_g1<3, true, 128, 2>(s, nbf, nact, np, Ct, ldk, Bp, bstride, ldb, b_bytes, XT_hi, XT_lo, ldx, d);
+    if (wide) launch_g1<3, true, 256, 1>(s, g);
+    else launch_g1<3, true, 128, 2>(s, g);
   }
   return hipGetLastError();
 }
@@ -736,46 +786,60 @@ hipError_t df_bf16_gemm2(hipStream_t s, int nbf, int nact, int np, int nsplit, i
                          SplitPtr XT, int ldx, const float* beta32, double* Kpart, double* Dchunk, u16* W_hi,
                          u16* W_lo, int ldw, const WsDims& d) {
   if (np <= 0) return hipSuccess;
-  const int t = cdiv(nact, T2);
-  const dim3 grid = xcd_grid((long long)nsplit * t * (t + 1) / 2);
+  const G2Args g{nbf, nact, np, nsplit, Ct.hi, Ct.lo, ldk, XT.hi, XT.lo, ldx, beta32, Kpart, Dchunk, W_hi, W_lo, ldw, d};
+  const dim3 grid = xcd_grid(g2_items(g));
   const bool vec = (ldk % 32 == 0) && (ldx % 32 == 0) && al16(Ct.hi) && (!Ct.lo || al16(Ct.lo)) && al16(XT.hi) &&
                    (!XT.lo || al16(XT.lo));
-  const WS ws = make_ws(d);
   if (terms == 1) {
-    if (vec) hipLaunchKernelGGL((gemm2_kernel<1, true>), grid, dim3(256), 0, s, nbf, nact, np, nsplit, Ct.hi, Ct.lo, ldk, XT.hi, XT.lo, ldx, beta32, Kpart, Dchunk, W_hi, W_lo, ldw, ws);
-    else hipLaunchKernelGGL((gemm2_kernel<1, false>), grid, dim3(256), 0, s, nbf, nact, np, nsplit, Ct.hi, Ct.lo, ldk, XT.hi, XT.lo, ldx, beta32, Kpart, Dchunk, W_hi, W_lo, ldw, ws);
+    if (vec) hipLaunchKernelGGL((gemm2_kernel<1, true>), grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL((gemm2_kernel<1, false>), grid, dim3(256), 0, s, g);
   } else {
-    if (vec) hipLaunchKernelGGL((gemm2_kernel<3, true>), grid, dim3(256), 0, s, nbf, nact, np, nsplit, Ct.hi, Ct.lo, ldk, XT.hi, XT.lo, ldx, beta32, Kpart, Dchunk, W_hi, W_lo, ldw, ws);
-    else hipLaunchKernelGGL((gemm2_kernel<3, false>), grid, dim3(256), 0, s, nbf, nact, np, nsplit, Ct.hi, Ct.lo, ldk, XT.hi, XT.lo, ldx, beta32, Kpart, Dchunk, W_hi, W_lo, ldw, ws);
+    if (vec) hipLaunchKernelGGL((gemm2_kernel<3, true>), grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL((gemm2_kernel<3, false>), grid, dim3(256), 0, s, g);
   }
   return hipGetLastError();
 }
 
 template <int TERMS, int G3M, int MINB>
-static void launch_g3(hipStream_t s, int nbf, int nact, int np, int nsplit, SplitPtr XT, int ldx, SplitPtr W, int ldw,
-                      float* Ypart, const WsDims& d) {
-  const dim3 grid = xcd_grid((long long)nsplit * cdiv(nbf, G3M) * cdiv(nact, T2));
-  const bool vec = (ldx % 32 == 0) && (ldw % 32 == 0) && al16(XT.hi) && (!XT.lo || al16(XT.lo)) && al16(W.hi) &&
-                   (!W.lo || al16(W.lo));
-  if (vec)
-    hipLaunchKernelGGL((gemm3_kernel<TERMS, G3M, MINB, true>), grid, dim3(256), 0, s, nbf, nact, np, nsplit, XT.hi,
-                       XT.lo, ldx, W.hi, W.lo, ldw, Ypart, make_ws(d));
-  else
-    hipLaunchKernelGGL((gemm3_kernel<TERMS, G3M, MINB, false>), grid, dim3(256), 0, s, nbf, nact, np, nsplit, XT.hi,
-                       XT.lo, ldx, W.hi, W.lo, ldw, Ypart, make_ws(d));
+static void launch_g3(hipStream_t s, const G3Args& g) {
+  const dim3 grid = xcd_grid((long long)g.nsplit * cdiv(g.nbf, G3M) * cdiv(g.nact, T2));
+  const bool vec = (g.ldx % 32 == 0) && (g.ldw % 32 == 0) && al16(g.xt_hi) && (!g.xt_lo || al16(g.xt_lo)) &&
+                   al16(g.w_hi) && (!g.w_lo || al16(g.w_lo));
+  if (vec) hipLaunchKernelGGL((gemm3_kernel<TERMS, G3M, MINB, true>), grid, dim3(256), 0, s, g);
+  else hipLaunchKernelGGL((gemm3_kernel<TERMS, G3M, MINB, false>), grid, dim3(256), 0, s, g);
 }
 
 hipError_t df_bf16_gemm3(hipStream_t s, int nbf, int nact, int np, int nsplit, int terms, SplitPtr XT, int ldx,
                          SplitPtr W, int ldw, float* Ypart, int variant, const WsDims& d) {
   if (np <= 0) return hipSuccess;
+  const G3Args g{nbf, nact, np, nsplit, XT.hi, XT.lo, ldx, W.hi, W.lo, ldw, Ypart, d};
   const bool wide = (variant == 1);
   if (terms == 1) {
-    if (wide) launch_g3<1, 256, 1>(s, nbf, nact, np, nsplit, XT, ldx, W, ldw, Ypart, d);
-    else launch_g3<1, 128, 1>(s, nbf, nact, np, nsplit, XT, ldx, W, ldw, Ypart, d);
+    if (wide) launch_g3<1, 256, 1>(s, g);
+    else launch_g3<1, 128, 1>(s, g);
   } else {
-    if (wide) launch_g3<3, 256, 1>(s, nbf, nact, np, nsplit, XT, ldx, W, ldw, Ypart, d);
-    else launch_g3<3, 128, 1>(s, nbf, nact, np, nsplit, XT, ldx, W, ldw, Ypart, d);
+    if (wide) launch_g3<3, 256, 1>(s, g);
+    else launch_g3<3, 128, 1>(s, g);
   }
+  return hipGetLastError();
+}
+
+hipError_t df_bf16_gemm1_grouped(hipStream_t s, int ninst, int total, int terms, const G1Args* tab, const int* off) {
+  if (total <= 0) return hipSuccess;
+  if (terms == 1) hipLaunchKernelGGL((gemm1_grouped<1>), xcd_grid(total), dim3(256), 0, s, tab, off, ninst, total);
+  else hipLaunchKernelGGL((gemm1_grouped<2>), xcd_grid(total), dim3(256), 0, s, tab, off, ninst, total);
+  return hipGetLastError();
+}
+hipError_t df_bf16_gemm2_grouped(hipStream_t s, int ninst, int total, int terms, const G2Args* tab, const int* off) {
+  if (total <= 0) return hipSuccess;
+  if (terms == 1) hipLaunchKernelGGL((gemm2_grouped<1>), xcd_grid(total), dim3(256), 0, s, tab, off, ninst, total);
+  else hipLaunchKernelGGL((gemm2_grouped<3>), xcd_grid(total), dim3(256), 0, s, tab, off, ninst, total);
+  return hipGetLastError();
+}
+hipError_t df_bf16_gemm3_grouped(hipStream_t s, int ninst, int total, int terms, const G3Args* tab, const int* off) {
+  if (total <= 0) return hipSuccess;
+  if (terms == 1) hipLaunchKernelGGL((gemm3_grouped<1>), xcd_grid(total), dim3(256), 0, s, tab, off, ninst, total);
+  else hipLaunchKernelGGL((gemm3_grouped<3>), xcd_grid(total), dim3(256), 0, s, tab, off, ninst, total);
   return hipGetLastError();
 }
 

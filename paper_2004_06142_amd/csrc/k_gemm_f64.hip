@@ -125,6 +125,31 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(int M, int N, int K, doub
       }
 }
 
+// One product of a grouped launch per blockIdx.y; blocks beyond that product's tiles exit.
+template <bool AM, bool BN>
+__global__ __launch_bounds__(256) void gemm_f64_grouped_kernel(const F64Gemm* __restrict__ tab) {
+  __shared__ F64Smem sm;
+  const F64Gemm g = tab[blockIdx.y];
+  const int tiles_n = (g.N + TN - 1) / TN;
+  if ((int)blockIdx.x >= tiles_n * ((g.M + TM - 1) / TM)) return;
+  const int m0 = (blockIdx.x / tiles_n) * TM, n0 = (blockIdx.x % tiles_n) * TN;
+  f64x4 acc[2][2];
+  zero_acc(acc);
+  tile_f64<AM, BN>(sm, g.A, g.sam, g.sak, g.B, g.sbk, g.sbn, g.M, g.N, g.K, m0, n0, acc);
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int m = m0 + acc_row(mi, j), n = n0 + acc_col(ni);
+        if (m < g.M && n < g.N) {
+          double* c = g.C + (long long)m * g.scm + (long long)n * g.scn;
+          *c = g.alpha * acc[mi][ni][j] + (g.beta != 0.0 ? g.beta * *c : 0.0);
+        }
+      }
+}
+
 // Lower-triangle tile index t -> (tm, tn) with tn <= tm.
 __device__ __forceinline__ void tri_tile(int t, int& tm, int& tn) {
   int r = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
@@ -256,6 +281,17 @@ hipError_t gemm_f64(hipStream_t s, int M, int N, int K, int batch, double alpha,
     hipLaunchKernelGGL((gemm_f64_kernel<false, true>), grid, dim3(256), 0, s, M, N, K, alpha, A, sam, sak, sab, B, sbk, sbn, sbb, beta, C, scm, scn, scb);
   else
     hipLaunchKernelGGL((gemm_f64_kernel<false, false>), grid, dim3(256), 0, s, M, N, K, alpha, A, sam, sak, sab, B, sbk, sbn, sbb, beta, C, scm, scn, scb);
+  return hipGetLastError();
+}
+
+hipError_t gemm_f64_grouped(hipStream_t s, int ngemm, int maxM, int maxN, bool a_unit_m, bool b_unit_n,
+                            const F64Gemm* tab) {
+  if (ngemm <= 0 || maxM <= 0 || maxN <= 0) return hipSuccess;
+  dim3 grid(cdiv(maxM, TM) * cdiv(maxN, TN), ngemm);
+  if (a_unit_m && b_unit_n) hipLaunchKernelGGL((gemm_f64_grouped_kernel<true, true>), grid, dim3(256), 0, s, tab);
+  else if (a_unit_m) hipLaunchKernelGGL((gemm_f64_grouped_kernel<true, false>), grid, dim3(256), 0, s, tab);
+  else if (b_unit_n) hipLaunchKernelGGL((gemm_f64_grouped_kernel<false, true>), grid, dim3(256), 0, s, tab);
+  else hipLaunchKernelGGL((gemm_f64_grouped_kernel<false, false>), grid, dim3(256), 0, s, tab);
   return hipGetLastError();
 }
 

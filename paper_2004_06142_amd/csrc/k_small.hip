@@ -24,21 +24,8 @@ __global__ void coeffs_k(int nact, int npairs, int ncwo, int functional, const d
                          double* __restrict__ alpha, double* __restrict__ beta, float* __restrict__ beta32) {
   GRID_STRIDE(i, (long long)nact * nact) {
     const int p = (int)(i / nact), q = (int)(i % nact);
-    const int gp = pair_of(p, npairs, ncwo), gq = pair_of(q, npairs, ncwo);
-    const double np_ = n[p], nq = n[q];
-    double a = 0.0, b;
-    if (gp == gq) {
-      if (p == q) b = np_;
-      else {
-        const double s = sqrt(np_ * nq);
-        b = (p < npairs || q < npairs) ? -s : s;
-      }
-    } else {
-      a = 2.0 * np_ * nq;
-      if (functional == 5) b = -np_ * nq;
-      else if (functional == 8) b = -np_ * nq - 4.0 * (np_ * (1.0 - np_)) * (nq * (1.0 - nq));
-      else b = -np_ * nq - sqrt(np_ * (1.0 - np_)) * sqrt(nq * (1.0 - nq));
-    }
+    double a, b;
+    pnof_coeff(p, q, n[p], n[q], npairs, ncwo, functional, a, b);
     alpha[i] = a;
     beta[i] = b;
     if (beta32) beta32[i] = (float)b;
@@ -234,22 +221,13 @@ __global__ void grad_n_k(int nact, int npairs, int ncwo, int functional, const d
                          const double* __restrict__ Hpp, const double* __restrict__ J,
                          const double* __restrict__ K, double* __restrict__ g) {
   const int p = blockIdx.x, lane = threadIdx.x;
-  const int gp = pair_of(p, npairs, ncwo);
   const double np_ = n[p];
   const double php = sqrt(np_ * (1.0 - np_));
   double s = 0.0;
   for (int q = lane; q < nact; q += 64) {
     if (q == p) continue;
-    const double nq = n[q];
-    const double kpq = K[(long long)p * nact + q];
-    if (pair_of(q, npairs, ncwo) == gp) {
-      const double sg = (p < npairs || q < npairs) ? -1.0 : 1.0;
-      s += sg * sqrt(nq / np_) * kpq;
-    } else {
-      s += 4.0 * nq * J[(long long)p * nact + q] - 2.0 * nq * kpq;
-      if (functional == 7) s += -sqrt(nq * (1.0 - nq)) * (1.0 - 2.0 * np_) / php * kpq;
-      else if (functional == 8) s += -8.0 * (1.0 - 2.0 * np_) * nq * (1.0 - nq) * kpq;
-    }
+    s += grad_n_term(p, q, np_, n[q], php, J[(long long)p * nact + q], K[(long long)p * nact + q], npairs, ncwo,
+                     functional);
   }
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
   if (lane == 0) g[p] = 2.0 * Hpp[p] + K[(long long)p * nact + p] + s;

@@ -1,6 +1,6 @@
 """Write the oracle's expected values for the full-size workloads (runs on the CPU only).
 
-Usage: python tests/golden/make_expected.py c5_df1200 [c3_df500] ...
+Usage: python tests/golden/make_expected.py c5_df1200 [c3_df500] [pes64] ...
 Calls only ``oracle`` (FP64, streamed route) on inputs from ``synth``; B rows are regenerated
 chunk by chunk from the counter-based stream, in worker processes, so that no full float64 copy of B
 ever exists.  Output: tests/golden/<workload>_expected.json with the energy, the orbital-step
@@ -71,10 +71,45 @@ def expected(name: str, workers: int = 6) -> dict:
     }
 
 
+def _energy_term_scale(n, r, wl):
+    """sqrt(sum (alpha J)^2 + (beta K)^2): the size of the two-electron energy terms."""
+    alpha, beta = pnof.coefficients(n, wl.npairs, wl.ncwo, pnof.PNOF7)
+    return float(np.sqrt(np.sum((alpha * r["J"]) ** 2) + np.sum((beta * r["K"]) ** 2)))
+
+
+def expected_pes(ninst: int = 64) -> dict:
+    """Every instance of the PES-scan batch (PNOF7, sigmoid ON map): E, max asymmetry and sampled
+    lambda, dE/dC and dE/dn entries."""
+    t0 = time.time()
+    out = {"workload": "pes64", "seed": synth.seed_of("pes64"), "functional": "PNOF7", "on_map": "sigmoid",
+           "instances": []}
+    rng = np.random.default_rng(19)
+    for i, inst in enumerate(synth.pes_scan(ninst, with_b=False)):
+        wl = inst.wl
+        B = synth.b_chunk(inst.key, wl.nbf, wl.naux, 0, wl.naux, wl.b_dtype)
+        n = pnof.on_sigmoid(inst.gamma, wl.npairs, wl.ncwo)
+        r = stream.lagrangian(inst.C, n, inst.H, B, wl.npairs, wl.ncwo, pnof.PNOF7)
+        del B
+        lam_pq = np.stack([rng.integers(0, wl.nbf, 16), rng.integers(0, wl.nact, 16)], axis=1)
+        mq = np.stack([rng.integers(0, wl.nbf, 8), rng.integers(0, wl.nact, 8)], axis=1)
+        pn = rng.integers(0, wl.nact, 8)
+        out["instances"].append({
+            "nbf": wl.nbf, "naux": wl.naux, "npairs": wl.npairs, "ncwo": wl.ncwo, "E": r["E"],
+            "max_asym": pnof.max_asym(r["lam"]),
+            "lam": {"idx": lam_pq.tolist(), "val": [r["lam"][p, q] for p, q in lam_pq]},
+            "dEdC": {"idx": mq.tolist(), "val": [r["dEdC"][m, q] for m, q in mq]},
+            "dEdn": {"idx": pn.tolist(), "val": [r["dEdn"][p] for p in pn]},
+            "T": _energy_term_scale(n, r, wl),
+        })
+        print(f"  instance {i}: nbf {wl.nbf} E {r['E']:.10f} ({time.time() - t0:.0f} s)", flush=True)
+    out["seconds"] = time.time() - t0
+    return out
+
+
 if __name__ == "__main__":
     for name in sys.argv[1:]:
-        out = expected(name)
+        out = expected_pes() if name == "pes64" else expected(name)
         path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{name}_expected.json")
         with open(path, "w") as f:
             json.dump(out, f)
-        print(f"wrote {path}: E = {out['E']:.12f} ({out['seconds']:.0f} s)")
+        print(f"wrote {path} ({out['seconds']:.0f} s)")
