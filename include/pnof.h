@@ -167,9 +167,10 @@ pnof_status pnof_lagrangian(pnof_ctx ctx, const pnof_problem* prob, const double
                             double* K);
 
 /* ---- orbital step (Eq. Fockian; Section 3.4) ------------------------------------------------ */
-/* diag_prev == NULL: S = (lambda + lambda^T)/2.  Otherwise S_pq = lambda_pq - lambda_qp for p < q
- * (mirrored), S_pp = diag_prev[p], and when zeta > 0 every off-diagonal |S_pq| > zeta is divided
- * by ten until it is <= zeta.  (eps, U) = eigh(S) in float64, eps ascending, each column of U
+/* diag_prev == NULL: S = (lambda + lambda^T)/2.  Otherwise S_pq = lambda_qp - lambda_pq for p < q
+ * (mirrored; the orientation of Eq. Fockian for which the first-order energy change of Eq. ene1
+ * is negative when diag_prev increases with the index), S_pp = diag_prev[p], and when zeta > 0
+ * every off-diagonal |S_pq| > zeta is divided by ten until it is <= zeta.  (eps, U) = eigh(S) in float64, eps ascending, each column of U
  * signed so that its largest-magnitude entry (lowest index on ties) is positive;
  * C_new = C U.  lambda, C, C_new: nbf x nbf; eps: nbf; S_out (optional): the matrix diagonalised.
  * C_new must not alias C or lambda. */

@@ -363,13 +363,18 @@ def grad_n(n, Hpp, J, K, npairs: int, ncwo: int, functional: int = PNOF7):
 def fockian_offdiag(lam):
     """Off-diagonal part of the symmetric matrix of Eq. Fockian.
 
-    For q < p: F_qp = lambda_qp - lambda_pq; F_pq = F_qp.
+    Its elements are differences of the two Lagrange multipliers of a pair; the orientation
+    is the one for which the first-order energy change of Eq. ene1 is negative when the diagonal
+    increases with the orbital index (the aufbau choice of Section 3.2).  With
+    lambda_pq = c_p^T F^q c_q (bra p, operator of orbital q, as in Eqs. lowdin and lag) that is,
+    for q < p: F_qp = F_pq = lambda_pq - lambda_qp (the multiplier whose operator belongs to the
+    lower orbital is subtracted).
     """
     nbf = lam.shape[0]
     F = np.zeros_like(lam)
     for q in range(nbf):
         for p in range(q + 1, nbf):
-            F[q, p] = lam[q, p] - lam[p, q]
+            F[q, p] = lam[p, q] - lam[q, p]
             F[p, q] = F[q, p]
     return F
 

@@ -361,7 +361,7 @@ __global__ void build_s_k(int nbf, const double* __restrict__ lam, const double*
     if (!dprev) v = 0.5 * (a + b);
     else if (p == q) v = dprev[p];
     else {
-      v = (p < q) ? (a - b) : (b - a);   // S_pq = lambda_pq - lambda_qp for p < q, mirrored
+      v = (p < q) ? (b - a) : (a - b);   // S_pq = lambda_qp - lambda_pq for p < q, mirrored
       if (zeta > 0.0)
         while (fabs(v) > zeta) v /= 10.0;
     }

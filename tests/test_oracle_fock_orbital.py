@@ -164,7 +164,7 @@ def test_fockian_offdiagonals_and_zeta_scaling():
     for q in range(6):
         for p in range(6):
             if q < p:
-                assert F[q, p] == lam[q, p] - lam[p, q]       # Eq. Fockian, theta(p - q) = 1
+                assert F[q, p] == lam[p, q] - lam[q, p]       # Eq. Fockian, orientation of Eq. ene1
                 assert F[p, q] == F[q, p]
             elif q == p:
                 assert F[q, p] == 0.0
