@@ -178,6 +178,64 @@ pnof_status pnof_orbital_step(pnof_ctx ctx, int32_t nbf, const double* lambda, c
                               const double* diag_prev, double zeta, double* C_new, double* eps,
                               double* S_out);
 
+/* ---- NOF-MP2 reference terms (Section 4, Eqs. HFL and Esta) ----------------------------------- */
+/* E_hf: Hartree-Fock-like energy of the natural orbitals, 2 sum_g H_gg + sum_fg (2 J_fg - K_fg)
+ * over the strong orbitals g, f < npairs.  E_sta: static correlation,
+ * sum_g sum_{p != q in Omega_g} sqrt(Lambda_p Lambda_q) Pi_qp K_pq - 4 sum_{f != g} sum_{p in
+ * Omega_f, q in Omega_g} Phi_q^2 Phi_p^2 K_pq with Lambda_p = 1 - |1 - 2 n_p| and Pi of Eq. intra.
+ * The dynamic term E^dyn needs amplitude equations that the paper does not give and is not
+ * provided.  C, H: nbf x nbf; n: nact; E_hf, E_sta: device scalars.  Runs the J/K contractions
+ * of pnof_jk on (C, ints). */
+pnof_status pnof_nofmp2_terms(pnof_ctx ctx, const pnof_problem* prob, const double* C, const double* n,
+                              const double* H, const void* ints, double* E_hf, double* E_sta);
+
+/* ---- occupation optimisation at fixed orbitals (Section 3.1) --------------------------------- */
+/* Minimises E(n(gamma)) = 2 sum_p n_p H_pp + sum_pq (alpha_pq J_pq + beta_pq K_pq) over the
+ * unconstrained variables gamma of ON map `kind` (see pnof_on_map) with limited-memory BFGS
+ * (backtracking line search with the Armijo condition).  Only H_pp = c_p^T H c_p, J and K of the
+ * fixed orbitals enter: the integral transformation is done once per occupation optimisation.
+ * C, H: nbf x nbf (H_pp is formed here); J, K: nact x nact from pnof_jk or pnof_lagrangian;
+ * gamma: device, ngamma entries, the starting point on input and the minimiser on output.
+ * E (host): final energy; iterations (host, optional).  The call synchronises the stream. */
+typedef struct {
+  int32_t maxiter;   /* <= 0: 1000 */
+  int32_t memory;    /* correction pairs; <= 0: 10 */
+  double gtol;       /* stop when max |dE/dgamma| <= gtol; <= 0: 1e-9 */
+} pnof_on_opts;
+pnof_status pnof_optimize_on(pnof_ctx ctx, const pnof_problem* prob, int32_t kind, const double* C,
+                             const double* H, const double* J, const double* K, double* gamma,
+                             const pnof_on_opts* opts, double* E, int32_t* iterations);
+
+/* ---- orbital + occupation optimisation (Section 3.4) ------------------------------------------ */
+/* The computational procedure of Section 3.4 on the device:
+ *   initial step: occupations for the guess orbitals, then one diagonalisation of the symmetrised
+ *     Lagrangian, whose eigenvalues are the first diagonal of the matrix of Eq. Fockian;
+ *   iteration j: occupations for the orbitals phi^j (pnof_optimize_on); the matrix of Eq. Fockian
+ *     (pnof_orbital_step conventions) with the previous eigenvalues on the diagonal and the zeta
+ *     scaling; optionally DIIS over the last ndiis matrices (Section 3.3; matrices and error
+ *     vectors, the off-diagonal elements, combined in the fixed AO basis); diagonalisation, new
+ *     orbitals phi^{j+1} = phi^j U and new diagonal.
+ * Stops when max |lambda_pq - lambda_qp| < delta (converged = 1), or when the three energy
+ * differences of Section 3.4 fall below eps_n, eps_phi and eps (converged = 0), or after maxit
+ * iterations.  C (in/out, nbf x nbf, orthonormal columns); gamma (in/out, ngamma) unless fix_n;
+ * n (nact): the fixed occupations on input when fix_n, the final occupations on output otherwise.
+ * Allocates its own device buffers for the duration of the call and synchronises the stream. */
+typedef struct {
+  int32_t on_kind;   /* ON map of the occupation optimisation (0 sigmoid, 1 trigonometric)   */
+  int32_t maxit;     /* macro-iterations; <= 0: 200                                         */
+  int32_t ndiis;     /* DIIS history; 0 or 1: off                                           */
+  int32_t fix_n;     /* 1: occupations fixed at n (e.g. the Hartree-Fock limit)             */
+  double eps_n, eps_phi, eps, delta, zeta;
+  pnof_on_opts on;
+} pnof_opt_opts;
+typedef struct {
+  double E, max_asym, d_n, d_phi, d_E;
+  int32_t iterations, converged;
+} pnof_opt_result;
+pnof_status pnof_optimize(pnof_ctx ctx, const pnof_problem* prob, const double* H, const void* ints,
+                          double* C, double* gamma, double* n, const pnof_opt_opts* opts,
+                          pnof_opt_result* result);
+
 /* ---- batches of independent problems (a potential-energy-surface scan) ---------------------- */
 /* A batch runs the Lagrangian step (as pnof_lagrangian: E, lambda, optional dE/dC, dE/dn and
  * max asymmetry) for ninst independent problems of different sizes in one fixed sequence of

@@ -420,3 +420,37 @@ def orbital_step(lam, C, diag_prev=None, zeta: float = 0.0):
     eps, U = np.linalg.eigh(S)
     U = sign_fix(U)
     return C @ U, eps, S
+
+
+# --------------------------------------------------------------------------- NOF-MP2 reference terms
+def nofmp2_reference(n, Hpp, J, K, npairs: int, ncwo: int):
+    """HF-like energy with the natural orbitals (Eq. HFL) and static correlation (Eq. Esta).
+
+    Singlet case (no singly occupied subspaces).  The HF-like density occupies the strong
+    orbitals g = 0..npairs-1 doubly:
+        E_hf  = 2 sum_g H_gg + sum_{f,g} (2 J_fg - K_fg).
+    Static correlation, with Lambda_p = 1 - |1 - 2 n_p| and Phi_p^2 = n_p (1 - n_p):
+        E_sta = sum_g sum_{p != q in Omega_g} sqrt(Lambda_p Lambda_q) Pi_qp K_pq
+                - 4 sum_{f != g} sum_{p in Omega_f, q in Omega_g} Phi_q^2 Phi_p^2 K_pq,
+    Pi_qp = +sqrt(n_q n_p) for two weak orbitals, -sqrt(n_q n_p) when one is strong (Eq. intra).
+    Both sums use math.fsum.
+    """
+    pair, strong = layout(npairs, ncwo)
+    nact = npairs * (ncwo + 1)
+    hf = [2.0 * Hpp[g] for g in range(npairs)]
+    for f in range(npairs):
+        for g in range(npairs):
+            hf.append(2.0 * J[f, g] - K[f, g])
+    lam = [1.0 - abs(1.0 - 2.0 * n[p]) for p in range(nact)]
+    ph2 = [n[p] * (1.0 - n[p]) for p in range(nact)]
+    sta = []
+    for p in range(nact):
+        for q in range(nact):
+            if p == q:
+                continue
+            if pair[p] == pair[q]:
+                s = -1.0 if (strong[p] or strong[q]) else 1.0
+                sta.append(math.sqrt(lam[p] * lam[q]) * s * math.sqrt(n[p] * n[q]) * K[p, q])
+            else:
+                sta.append(-4.0 * ph2[q] * ph2[p] * K[p, q])
+    return math.fsum(hf), math.fsum(sta)

@@ -31,7 +31,8 @@ STATUS = {0: "PNOF_OK", 1: "PNOF_E_ARG", 2: "PNOF_E_SHAPE", 3: "PNOF_E_DTYPE", 4
 EXPORTS = ["pnof_abi_version", "pnof_last_error", "pnof_check_problem", "pnof_create", "pnof_destroy",
            "pnof_set_stream", "pnof_workspace_size", "pnof_set_workspace", "pnof_set_pchunk", "pnof_on_map",
            "pnof_on_map_vjp", "pnof_jk", "pnof_energy", "pnof_fock", "pnof_lagrangian", "pnof_orbital_step",
-           "pnof_profile_begin", "pnof_profile_end", "pnof_set_tuning", "pnof_get_plan", "pnof_batch_plan",
+           "pnof_profile_begin", "pnof_profile_end", "pnof_set_tuning", "pnof_get_plan", "pnof_optimize_on",
+           "pnof_optimize", "pnof_nofmp2_terms", "pnof_batch_plan",
            "pnof_batch_bind", "pnof_batch_run", "pnof_batch_info", "pnof_batch_destroy"]
 STAGES = ("X", "b", "Y", "eig")
 
@@ -44,6 +45,25 @@ class PnofError(RuntimeError):
 
 class Tuning(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("pchunk", "nsplit_b", "nsplit_y", "x_variant", "y_variant")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class OnOpts(ctypes.Structure):
+    _fields_ = [("maxiter", ctypes.c_int32), ("memory", ctypes.c_int32), ("gtol", ctypes.c_double)]
+
+
+class OptOpts(ctypes.Structure):
+    _fields_ = [("on_kind", ctypes.c_int32), ("maxit", ctypes.c_int32), ("ndiis", ctypes.c_int32),
+                ("fix_n", ctypes.c_int32), ("eps_n", ctypes.c_double), ("eps_phi", ctypes.c_double),
+                ("eps", ctypes.c_double), ("delta", ctypes.c_double), ("zeta", ctypes.c_double), ("on", OnOpts)]
+
+
+class OptResult(ctypes.Structure):
+    _fields_ = [("E", ctypes.c_double), ("max_asym", ctypes.c_double), ("d_n", ctypes.c_double),
+                ("d_phi", ctypes.c_double), ("d_E", ctypes.c_double), ("iterations", ctypes.c_int32),
+                ("converged", ctypes.c_int32)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -99,6 +119,10 @@ def lib():
             "pnof_get_plan": ([P, PP, ctypes.POINTER(Tuning)], S),
             "pnof_profile_begin": ([P], S),
             "pnof_profile_end": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], S),
+            "pnof_optimize_on": ([P, PP, I, P, P, P, P, P, ctypes.POINTER(OnOpts), ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_int32)], S),
+            "pnof_optimize": ([P, PP, P, P, P, P, P, ctypes.POINTER(OptOpts), ctypes.POINTER(OptResult)], S),
+            "pnof_nofmp2_terms": ([P, PP, P, P, P, P, P, P], S),
             "pnof_batch_plan": ([P, I, PP, ctypes.POINTER(ctypes.c_void_p)], S),
             "pnof_batch_bind": ([P, ctypes.POINTER(BatchIO)], S),
             "pnof_batch_run": ([P, I], S),
@@ -261,6 +285,61 @@ class Context:
         pnof_lagrangian(self, prob, C, n, H, ints, out["lam"], out["E"], out.get("dEdC"), out.get("dEdn"),
                         out["max_asym"], out.get("J"), out.get("K"))
         return out
+
+    def nofmp2_terms(self, prob, C, n, H, ints):
+        """(E_hf, E_sta) device scalars of Eqs. HFL and Esta."""
+        d = self.device
+        for tt, name in ((C, "C"), (H, "H")):
+            _check(tt, prob.nbf ** 2, torch.float64, d, name)
+        _check(n, prob.nact, torch.float64, d, "n")
+        _ints_check(prob, ints, d)
+        e_hf, e_sta = self._f64(1), self._f64(1)
+        _raise(self, lib().pnof_nofmp2_terms(self.handle, ctypes.byref(prob), _ptr(C), _ptr(n), _ptr(H), _ptr(ints),
+                                             _ptr(e_hf), _ptr(e_sta)))
+        return e_hf, e_sta
+
+    def optimize_on(self, prob, C, H, J, K, gamma, kind=ON_SIGMOID, maxiter=0, memory=0, gtol=0.0):
+        """Occupation optimisation at fixed orbitals; returns (gamma, E, iterations) (gamma copied)."""
+        d = self.device
+        nbf, nact = prob.nbf, prob.nact
+        ngam = nact if kind == ON_SIGMOID else prob.npairs * prob.ncwo
+        for t, name in ((C, "C"), (H, "H")):
+            _check(t, nbf * nbf, torch.float64, d, name)
+        for t, name in ((J, "J"), (K, "K")):
+            _check(t, nact * nact, torch.float64, d, name)
+        _check(gamma, ngam, torch.float64, d, "gamma")
+        g = gamma.clone()
+        E, it = ctypes.c_double(), ctypes.c_int32()
+        opts = OnOpts(maxiter, memory, gtol)
+        _raise(self, lib().pnof_optimize_on(self.handle, ctypes.byref(prob), kind, _ptr(C), _ptr(H), _ptr(J), _ptr(K),
+                                            _ptr(g), ctypes.byref(opts), ctypes.byref(E), ctypes.byref(it)))
+        return g, E.value, it.value
+
+    def optimize(self, prob, H, ints, C, gamma=None, n=None, on_kind=ON_SIGMOID, maxit=200, ndiis=0, fix_n=False,
+                 eps_n=0.0, eps_phi=0.0, eps=0.0, delta=1e-4, zeta=0.0, on_maxiter=0, on_gtol=0.0):
+        """Orbital + occupation optimisation (Section 3.4).  Returns dict with C, gamma, n and the
+        result fields (E, max_asym, d_n, d_phi, d_E, iterations, converged); inputs are not modified."""
+        d = self.device
+        nbf, nact = prob.nbf, prob.nact
+        _check(H, nbf * nbf, torch.float64, d, "H")
+        _check(C, nbf * nbf, torch.float64, d, "C")
+        _ints_check(prob, ints, d)
+        Cw = C.clone()
+        nw = n.clone() if n is not None else self._f64(nact)
+        _check(nw, nact, torch.float64, d, "n")
+        gw = None
+        if not fix_n:
+            ngam = nact if on_kind == ON_SIGMOID else prob.npairs * prob.ncwo
+            _check(gamma, ngam, torch.float64, d, "gamma")
+            gw = gamma.clone()
+        elif n is None:
+            raise ValueError("fix_n needs n")
+        opts = OptOpts(on_kind, maxit, ndiis, 1 if fix_n else 0, eps_n, eps_phi, eps, delta, zeta,
+                       OnOpts(on_maxiter, 0, on_gtol))
+        res = OptResult()
+        _raise(self, lib().pnof_optimize(self.handle, ctypes.byref(prob), _ptr(H), _ptr(ints), _ptr(Cw), _ptr(gw),
+                                         _ptr(nw), ctypes.byref(opts), ctypes.byref(res)))
+        return {"C": Cw, "gamma": gw, "n": nw, **res.as_dict()}
 
     def orbital_step(self, lam, C, diag_prev=None, zeta=0.0, want_s=False):
         nbf = C.shape[0]

@@ -3,6 +3,7 @@
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -275,7 +276,7 @@ pnof_status check_finite(pnof_ctx ctx, Bufs& b, const void* p, long long n, int 
 // ------------------------------------------------------------------------ the step driver
 struct Req {
   double *J = nullptr, *K = nullptr, *Y = nullptr, *E = nullptr, *lam = nullptr, *dEdC = nullptr,
-         *dEdn = nullptr, *asym = nullptr;
+         *dEdn = nullptr, *asym = nullptr, *Hpp = nullptr;
   double *Jq = nullptr, *Kq = nullptr, *Fq = nullptr;
   const int32_t* q_idx = nullptr;
   int nq = 0;
@@ -315,6 +316,7 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
     // HC = H C_A ; Hpp = diag(C_A^T H C_A)
     DEV_CHECK(ctx, gemm_f64(s, nbf, nact, nbf, 1, 1.0, H, nbf, 1, 0, C, nbf, 1, 0, 0.0, b.HC, nact, 1, 0));
     DEV_CHECK(ctx, hpp_from_hc(s, nbf, nact, C, b.HC, b.Hpp));
+    if (r.Hpp) DEV_CHECK(ctx, hipMemcpyAsync(r.Hpp, b.Hpp, sizeof(double) * nact, hipMemcpyDeviceToDevice, s));
   }
   if (r.Jq) DEV_CHECK(ctx, fill_f64(s, r.Jq, (long long)r.nq * nbf * nbf, 0.0));
   if (r.Kq) DEV_CHECK(ctx, fill_f64(s, r.Kq, (long long)r.nq * nbf * nbf, 0.0));
@@ -446,6 +448,200 @@ pnof_status check_q(pnof_ctx ctx, const void* a, const int32_t* q_idx, int32_t n
 
 // ------------------------------------------------------------------------ batches
 namespace {
+
+// ------------------------------------------------------------------------ optimisation drivers
+// Device buffers owned by one driver call (freed after the stream has drained).
+struct DevBuf {
+  hipStream_t s;
+  std::vector<void*> ptrs;
+  bool ok = true;
+  explicit DevBuf(hipStream_t st) : s(st) {}
+  ~DevBuf() {
+    hipStreamSynchronize(s);
+    for (void* p : ptrs) hipFree(p);
+  }
+  template <typename T>
+  T* get(long long n) {
+    void* p = nullptr;
+    if (hipMalloc(&p, sizeof(T) * (size_t)std::max(1LL, n)) != hipSuccess) {
+      hipGetLastError();
+      ok = false;
+      return nullptr;
+    }
+    ptrs.push_back(p);
+    return static_cast<T*>(p);
+  }
+};
+
+// E(n(gamma)) and dE/dgamma at fixed H_pp, J, K, evaluated on the device (Section 3.1).
+struct OnObjective {
+  pnof_ctx ctx;
+  int kind, npairs, ncwo, nact, nbf, functional, ngam;
+  const double *Hpp, *J, *K;
+  double *gam, *n, *alpha, *beta, *partials, *E, *dEdn, *g;
+  std::vector<double> host;
+  int evals = 0;
+
+  pnof_status eval(const std::vector<double>& x, double& f, std::vector<double>& grad) {
+    hipStream_t s = ctx->stream;
+    DEV_CHECK(ctx, hipMemcpyAsync(gam, x.data(), sizeof(double) * ngam, hipMemcpyHostToDevice, s));
+    DEV_CHECK(ctx, on_map(s, kind, npairs, ncwo, gam, n, nullptr));
+    DEV_CHECK(ctx, coeffs(s, nact, npairs, ncwo, functional, n, alpha, beta, nullptr));
+    DEV_CHECK(ctx, energy(s, nbf, nact, n, Hpp, alpha, beta, J, K, nullptr, nullptr, nullptr, nullptr, 0, 0, partials, E));
+    DEV_CHECK(ctx, grad_n(s, nact, npairs, ncwo, functional, n, Hpp, J, K, dEdn));
+    DEV_CHECK(ctx, on_map_vjp(s, kind, npairs, ncwo, gam, dEdn, g));
+    host.resize(ngam + 1);
+    DEV_CHECK(ctx, hipMemcpyAsync(host.data(), E, sizeof(double), hipMemcpyDeviceToHost, s));
+    DEV_CHECK(ctx, hipMemcpyAsync(host.data() + 1, g, sizeof(double) * ngam, hipMemcpyDeviceToHost, s));
+    DEV_CHECK(ctx, hipStreamSynchronize(s));
+    f = host[0];
+    grad.assign(host.begin() + 1, host.end());
+    ++evals;
+    if (!std::isfinite(f)) return fail(ctx, PNOF_E_NONFINITE, "occupation optimisation reached a non-finite energy");
+    return PNOF_OK;
+  }
+};
+
+pnof_status on_objective_init(pnof_ctx ctx, DevBuf& db, const pnof_problem* prob, int kind, const double* Hpp,
+                              const double* J, const double* K, OnObjective& o) {
+  o.ctx = ctx;
+  o.kind = kind;
+  o.npairs = prob->npairs;
+  o.ncwo = prob->ncwo;
+  o.nact = prob->npairs * (prob->ncwo + 1);
+  o.nbf = prob->nbf;
+  o.functional = prob->functional;
+  o.ngam = kind == 0 ? o.nact : o.npairs * o.ncwo;
+  o.Hpp = Hpp;
+  o.J = J;
+  o.K = K;
+  const long long n2 = (long long)o.nact * o.nact;
+  o.gam = db.get<double>(o.ngam);
+  o.n = db.get<double>(o.nact);
+  o.alpha = db.get<double>(n2);
+  o.beta = db.get<double>(n2);
+  o.partials = db.get<double>(512);
+  o.E = db.get<double>(4);
+  o.dEdn = db.get<double>(o.nact);
+  o.g = db.get<double>(o.ngam);
+  if (!db.ok) return fail(ctx, PNOF_E_NOMEM, "allocation of the occupation-optimisation buffers failed");
+  return PNOF_OK;
+}
+
+double dot(const std::vector<double>& a, const std::vector<double>& b) {
+  double s = 0.0;
+  for (size_t i = 0; i < a.size(); ++i) s += a[i] * b[i];
+  return s;
+}
+
+// Limited-memory BFGS (two-loop recursion) with a backtracking Armijo line search.
+pnof_status lbfgs(OnObjective& o, std::vector<double>& x, const pnof_on_opts& op, double& fx, int& iters) {
+  const int m = op.memory > 0 ? op.memory : 10;
+  const int maxit = op.maxiter > 0 ? op.maxiter : 1000;
+  const double gtol = op.gtol > 0 ? op.gtol : 1e-9;
+  const size_t nv = x.size();
+  std::vector<double> g, xn(nv), gn, d(nv);
+  std::vector<std::vector<double>> S, Y;
+  std::vector<double> rho;
+  pnof_status st = o.eval(x, fx, g);
+  if (st != PNOF_OK) return st;
+  int it = 0, stalled = 0;
+  for (; it < maxit; ++it) {
+    double gmax = 0.0;
+    for (double v : g) gmax = std::max(gmax, std::fabs(v));
+    if (gmax <= gtol) break;
+    // two-loop recursion: d = -H g
+    std::vector<double> q = g, a(S.size());
+    for (int i = (int)S.size() - 1; i >= 0; --i) {
+      a[i] = rho[i] * dot(S[i], q);
+      for (size_t k = 0; k < nv; ++k) q[k] -= a[i] * Y[i][k];
+    }
+    const double h0 = S.empty() ? 1.0 / std::max(1.0, gmax) : dot(S.back(), Y.back()) / dot(Y.back(), Y.back());
+    for (size_t k = 0; k < nv; ++k) q[k] *= h0;
+    for (size_t i = 0; i < S.size(); ++i) {
+      const double bcoef = rho[i] * dot(Y[i], q);
+      for (size_t k = 0; k < nv; ++k) q[k] += S[i][k] * (a[i] - bcoef);
+    }
+    for (size_t k = 0; k < nv; ++k) d[k] = -q[k];
+    double gd = dot(g, d);
+    if (!(gd < 0.0)) {   // not a descent direction: restart from the scaled gradient
+      S.clear();
+      Y.clear();
+      rho.clear();
+      for (size_t k = 0; k < nv; ++k) d[k] = -g[k] / std::max(1.0, gmax);
+      gd = dot(g, d);
+    }
+    double step = 1.0, fn = fx;
+    bool accepted = false;
+    for (int ls = 0; ls < 60; ++ls) {
+      for (size_t k = 0; k < nv; ++k) xn[k] = x[k] + step * d[k];
+      if ((st = o.eval(xn, fn, gn)) != PNOF_OK) return st;
+      if (fn <= fx + 1e-4 * step * gd) {
+        accepted = true;
+        break;
+      }
+      step *= 0.5;
+    }
+    if (!accepted) break;   // no decrease along d within rounding: the minimum is reached
+    std::vector<double> sv(nv), yv(nv);
+    for (size_t k = 0; k < nv; ++k) {
+      sv[k] = xn[k] - x[k];
+      yv[k] = gn[k] - g[k];
+    }
+    const double sy = dot(sv, yv);
+    if (sy > 1e-14 * std::sqrt(dot(sv, sv) * dot(yv, yv))) {
+      S.push_back(sv);
+      Y.push_back(yv);
+      rho.push_back(1.0 / sy);
+      if ((int)S.size() > m) {
+        S.erase(S.begin());
+        Y.erase(Y.begin());
+        rho.erase(rho.begin());
+      }
+    }
+    // stagnation: three successive steps that change E by no more than its rounding
+    stalled = (fx - fn <= 4.0 * DBL_EPSILON * std::max(1.0, std::fabs(fx))) ? stalled + 1 : 0;
+    x = xn;
+    g = gn;
+    fx = fn;
+    if (stalled >= 3) break;
+  }
+  iters = it;
+  return PNOF_OK;
+}
+
+// H_pp = diag(C_A^T H C_A) into Hpp (device), through the scratch HC (nbf x nact).
+pnof_status hpp_of(pnof_ctx ctx, int nbf, int nact, const double* C, const double* H, double* HC, double* Hpp) {
+  hipStream_t s = ctx->stream;
+  DEV_CHECK(ctx, gemm_f64(s, nbf, nact, nbf, 1, 1.0, H, nbf, 1, 0, C, nbf, 1, 0, 0.0, HC, nact, 1, 0));
+  DEV_CHECK(ctx, hpp_from_hc(s, nbf, nact, C, HC, Hpp));
+  return PNOF_OK;
+}
+
+// Small dense solve (Gaussian elimination with partial pivoting), row-major A (n x n).
+bool solve_small(std::vector<double> A, std::vector<double>& b, int n) {
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(A[r * n + c]) > std::fabs(A[piv * n + c])) piv = r;
+    if (std::fabs(A[piv * n + c]) < 1e-300) return false;
+    if (piv != c) {
+      for (int k = 0; k < n; ++k) std::swap(A[c * n + k], A[piv * n + k]);
+      std::swap(b[c], b[piv]);
+    }
+    for (int r = c + 1; r < n; ++r) {
+      const double f = A[r * n + c] / A[c * n + c];
+      for (int k = c; k < n; ++k) A[r * n + k] -= f * A[c * n + k];
+      b[r] -= f * b[c];
+    }
+  }
+  for (int r = n - 1; r >= 0; --r) {
+    double v = b[r];
+    for (int k = r + 1; k < n; ++k) v -= A[r * n + k] * b[k];
+    b[r] = v / A[r * n + r];
+  }
+  return true;
+}
 
 // Geometry of one batch instance: sizes, leading dimensions and P-splits of the grouped launches.
 struct BatchGeom {
@@ -792,6 +988,227 @@ pnof_status pnof_orbital_step(pnof_ctx ctx, int32_t nbf, const double* lambda, c
   DEV_CHECK(ctx, hipStreamSynchronize(s));
   if (*ctx->host_info != 0)
     return fail(ctx, PNOF_E_EIG, "eigensolver did not converge (info = " + std::to_string(*ctx->host_info) + ")");
+  return PNOF_OK;
+}
+
+pnof_status pnof_nofmp2_terms(pnof_ctx ctx, const pnof_problem* prob, const double* C, const double* n,
+                              const double* H, const void* ints, double* E_hf, double* E_sta) {
+  pnof_status st = check_ctx(ctx);
+  if (st != PNOF_OK) return st;
+  if ((st = check_problem(ctx, prob)) != PNOF_OK) return st;
+  if ((st = check_ptrs(ctx, {C, n, H, ints, E_hf, E_sta}, "pnof_nofmp2_terms")) != PNOF_OK) return st;
+  const int nact = prob->npairs * (prob->ncwo + 1);
+  DevBuf db(ctx->stream);
+  double* J = db.get<double>((long long)nact * nact);
+  double* K = db.get<double>((long long)nact * nact);
+  double* Hpp = db.get<double>(nact);
+  double* partials = db.get<double>(256);
+  if (!db.ok) return fail(ctx, PNOF_E_NOMEM, "allocation failed");
+  Req r;
+  r.J = J;
+  r.K = K;
+  r.Hpp = Hpp;
+  if ((st = run_step(ctx, prob, C, nullptr, H, ints, r)) != PNOF_OK) return st;
+  DEV_CHECK(ctx, nofmp2_terms(ctx->stream, nact, prob->npairs, prob->ncwo, n, Hpp, J, K, partials, E_hf, E_sta));
+  return PNOF_OK;
+}
+
+pnof_status pnof_optimize_on(pnof_ctx ctx, const pnof_problem* prob, int32_t kind, const double* C,
+                             const double* H, const double* J, const double* K, double* gamma,
+                             const pnof_on_opts* opts, double* E, int32_t* iterations) {
+  pnof_status st = check_ctx(ctx);
+  if (st != PNOF_OK) return st;
+  if ((st = check_problem(ctx, prob)) != PNOF_OK) return st;
+  if (kind != 0 && kind != 1) return fail(ctx, PNOF_E_ARG, "kind must be 0 (sigmoid) or 1 (trigonometric)");
+  if ((st = check_ptrs(ctx, {C, H, J, K, gamma, E}, "pnof_optimize_on")) != PNOF_OK) return st;
+  const int nbf = prob->nbf, nact = prob->npairs * (prob->ncwo + 1);
+  DevBuf db(ctx->stream);
+  double* HC = db.get<double>((long long)nbf * nact);
+  double* Hpp = db.get<double>(nact);
+  if (!db.ok) return fail(ctx, PNOF_E_NOMEM, "allocation failed");
+  if ((st = hpp_of(ctx, nbf, nact, C, H, HC, Hpp)) != PNOF_OK) return st;
+  OnObjective o;
+  if ((st = on_objective_init(ctx, db, prob, kind, Hpp, J, K, o)) != PNOF_OK) return st;
+  std::vector<double> x(o.ngam);
+  DEV_CHECK(ctx, hipMemcpyAsync(x.data(), gamma, sizeof(double) * o.ngam, hipMemcpyDeviceToHost, ctx->stream));
+  DEV_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+  pnof_on_opts op = opts ? *opts : pnof_on_opts{0, 0, 0.0};
+  double f = 0.0;
+  int it = 0;
+  if ((st = lbfgs(o, x, op, f, it)) != PNOF_OK) return st;
+  DEV_CHECK(ctx, hipMemcpyAsync(gamma, x.data(), sizeof(double) * o.ngam, hipMemcpyHostToDevice, ctx->stream));
+  DEV_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+  *E = f;
+  if (iterations) *iterations = it;
+  return PNOF_OK;
+}
+
+pnof_status pnof_optimize(pnof_ctx ctx, const pnof_problem* prob, const double* H, const void* ints,
+                          double* C, double* gamma, double* n, const pnof_opt_opts* opts,
+                          pnof_opt_result* result) {
+  pnof_status st = check_ctx(ctx);
+  if (st != PNOF_OK) return st;
+  if ((st = check_problem(ctx, prob)) != PNOF_OK) return st;
+  if (!opts || !result) return fail(ctx, PNOF_E_ARG, "opts and result are required");
+  const pnof_opt_opts op = *opts;
+  if ((st = check_ptrs(ctx, {H, ints, C, n}, "pnof_optimize")) != PNOF_OK) return st;
+  if (!op.fix_n && !gamma) return fail(ctx, PNOF_E_ARG, "gamma is required unless fix_n");
+  if (op.on_kind != 0 && op.on_kind != 1) return fail(ctx, PNOF_E_ARG, "on_kind must be 0 or 1");
+  const int nbf = prob->nbf, nact = prob->npairs * (prob->ncwo + 1);
+  const long long nn = (long long)nbf * nbf, n2 = (long long)nact * nact;
+  const int maxit = op.maxit > 0 ? op.maxit : 200;
+  const int ndiis = op.ndiis > 1 ? op.ndiis : 0;
+  hipStream_t s = ctx->stream;
+  DevBuf db(s);
+  double* lam = db.get<double>(nn);
+  double* S = db.get<double>(nn);
+  double* Cn = db.get<double>(nn);
+  double* T1 = db.get<double>(nn);
+  double* diag = db.get<double>(nbf);
+  double* ework = db.get<double>(nbf);
+  int* info = db.get<int>(4);
+  double* J = db.get<double>(n2);
+  double* K = db.get<double>(n2);
+  double* Hpp = db.get<double>(nact);
+  double* scal = db.get<double>(4);   // E, max_asym
+  std::vector<double*> Fao(ndiis), Eao(ndiis);
+  for (int i = 0; i < ndiis; ++i) {
+    Fao[i] = db.get<double>(nn);
+    Eao[i] = db.get<double>(nn);
+  }
+  if (!db.ok) return fail(ctx, PNOF_E_NOMEM, "allocation of the optimisation buffers failed");
+  OnObjective o;
+  if ((st = on_objective_init(ctx, db, prob, op.on_kind, Hpp, J, K, o)) != PNOF_OK) return st;
+  std::vector<double> gam;
+  if (!op.fix_n) {
+    gam.resize(o.ngam);
+    DEV_CHECK(ctx, hipMemcpyAsync(gam.data(), gamma, sizeof(double) * o.ngam, hipMemcpyDeviceToHost, s));
+    DEV_CHECK(ctx, hipStreamSynchronize(s));
+  }
+  pnof_problem pr = *prob;
+  pr.flags = 0;
+  double host2[2];
+  // E (and lambda, its asymmetry) of (C, n)
+  auto lagr = [&](double& E, double& asym) -> pnof_status {
+    Req r;
+    r.lam = lam;
+    r.E = scal;
+    r.asym = scal + 1;
+    r.need_y = r.need_e = true;
+    pnof_status st2 = run_step(ctx, &pr, C, n, H, ints, r);
+    if (st2 != PNOF_OK) return st2;
+    DEV_CHECK(ctx, hipMemcpyAsync(host2, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    DEV_CHECK(ctx, hipStreamSynchronize(s));
+    E = host2[0];
+    asym = host2[1];
+    return PNOF_OK;
+  };
+  // occupations for the current orbitals (Section 3.1): returns E[n^{j+1}, phi^j]
+  auto occupations = [&](double& En) -> pnof_status {
+    Req r;
+    r.J = J;
+    r.K = K;
+    r.Hpp = Hpp;
+    pnof_status st2 = run_step(ctx, &pr, C, nullptr, H, ints, r);
+    if (st2 != PNOF_OK) return st2;
+    if (op.fix_n) {
+      DEV_CHECK(ctx, coeffs(s, nact, pr.npairs, pr.ncwo, pr.functional, n, o.alpha, o.beta, nullptr));
+      DEV_CHECK(ctx, energy(s, nbf, nact, n, Hpp, o.alpha, o.beta, J, K, nullptr, nullptr, nullptr, nullptr, 0, 0,
+                            o.partials, o.E));
+      DEV_CHECK(ctx, hipMemcpyAsync(host2, o.E, sizeof(double), hipMemcpyDeviceToHost, s));
+      DEV_CHECK(ctx, hipStreamSynchronize(s));
+      En = host2[0];
+      return PNOF_OK;
+    }
+    int it = 0;
+    st2 = lbfgs(o, gam, op.on, En, it);
+    if (st2 != PNOF_OK) return st2;
+    DEV_CHECK(ctx, hipMemcpyAsync(gamma, gam.data(), sizeof(double) * o.ngam, hipMemcpyHostToDevice, s));
+    DEV_CHECK(ctx, on_map(s, op.on_kind, pr.npairs, pr.ncwo, gamma, n, nullptr));
+    return PNOF_OK;
+  };
+  // diagonalise S (overwritten by the eigenvectors), new diagonal, C <- C U
+  auto diagonalise = [&]() -> pnof_status {
+    rocblas_status rs = rocsolver_dsyevd(ctx->blas, rocblas_evect_original, rocblas_fill_upper, nbf, S, nbf, diag,
+                                         ework, info);
+    if (rs != rocblas_status_success) return fail(ctx, PNOF_E_DEVICE, "rocsolver_dsyevd failed to launch");
+    DEV_CHECK(ctx, sign_fix_cols(s, nbf, S));
+    DEV_CHECK(ctx, gemm_f64(s, nbf, nbf, nbf, 1, 1.0, C, nbf, 1, 0, S, 1, nbf, 0, 0.0, Cn, nbf, 1, 0));
+    DEV_CHECK(ctx, hipMemcpyAsync(C, Cn, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
+    int hinfo = 0;
+    DEV_CHECK(ctx, hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, s));
+    DEV_CHECK(ctx, hipStreamSynchronize(s));
+    if (hinfo != 0) return fail(ctx, PNOF_E_EIG, "eigensolver did not converge");
+    return PNOF_OK;
+  };
+  // initial step
+  double En = 0.0, E0 = 0.0, asym = 0.0, Eprev = 0.0;
+  if ((st = occupations(En)) != PNOF_OK) return st;
+  if ((st = lagr(E0, asym)) != PNOF_OK) return st;
+  DEV_CHECK(ctx, build_s(s, nbf, lam, nullptr, 0.0, S));
+  if ((st = diagonalise()) != PNOF_OK) return st;
+  if ((st = lagr(Eprev, asym)) != PNOF_OK) return st;
+  pnof_opt_result res{};
+  res.E = Eprev;
+  res.max_asym = asym;
+  int nstored = 0, head = 0;
+  int it = 0;
+  for (it = 1; it <= maxit; ++it) {
+    if ((st = occupations(En)) != PNOF_OK) return st;
+    double Efix = 0.0, Enew = 0.0;
+    if ((st = lagr(Efix, asym)) != PNOF_OK) return st;
+    DEV_CHECK(ctx, build_s(s, nbf, lam, diag, op.zeta, S));
+    if (ndiis) {
+      // store F_AO = C F C^T and e_AO = C offdiag(F) C^T; combine when two or more are stored
+      DEV_CHECK(ctx, gemm_f64(s, nbf, nbf, nbf, 1, 1.0, C, nbf, 1, 0, S, nbf, 1, 0, 0.0, T1, nbf, 1, 0));
+      DEV_CHECK(ctx, gemm_f64(s, nbf, nbf, nbf, 1, 1.0, T1, nbf, 1, 0, C, 1, nbf, 0, 0.0, Fao[head], nbf, 1, 0));
+      DEV_CHECK(ctx, offdiag_copy(s, nbf, S, Cn));
+      DEV_CHECK(ctx, gemm_f64(s, nbf, nbf, nbf, 1, 1.0, C, nbf, 1, 0, Cn, nbf, 1, 0, 0.0, T1, nbf, 1, 0));
+      DEV_CHECK(ctx, gemm_f64(s, nbf, nbf, nbf, 1, 1.0, T1, nbf, 1, 0, C, 1, nbf, 0, 0.0, Eao[head], nbf, 1, 0));
+      head = (head + 1) % ndiis;
+      nstored = std::min(nstored + 1, ndiis);
+      if (nstored >= 2) {
+        const int m = nstored;
+        std::vector<double> A((m + 1) * (m + 1), 0.0), rhs(m + 1, 0.0);
+        rocblas_set_pointer_mode(ctx->blas, rocblas_pointer_mode_host);
+        for (int i = 0; i < m; ++i)
+          for (int j = 0; j <= i; ++j) {
+            double v = 0.0;
+            if (rocblas_ddot(ctx->blas, (int)nn, Eao[i], 1, Eao[j], 1, &v) != rocblas_status_success)
+              return fail(ctx, PNOF_E_DEVICE, "rocblas_ddot failed");
+            A[i * (m + 1) + j] = A[j * (m + 1) + i] = v;
+          }
+        for (int i = 0; i < m; ++i) A[i * (m + 1) + m] = A[m * (m + 1) + i] = -1.0;
+        rhs[m] = -1.0;
+        if (solve_small(A, rhs, m + 1)) {
+          DEV_CHECK(ctx, fill_f64(s, Cn, nn, 0.0));
+          for (int i = 0; i < m; ++i) {
+            const double c = rhs[i];
+            if (rocblas_daxpy(ctx->blas, (int)nn, &c, Fao[i], 1, Cn, 1) != rocblas_status_success)
+              return fail(ctx, PNOF_E_DEVICE, "rocblas_daxpy failed");
+          }
+          // S = C^T F_AO C
+          DEV_CHECK(ctx, gemm_f64(s, nbf, nbf, nbf, 1, 1.0, Cn, nbf, 1, 0, C, nbf, 1, 0, 0.0, T1, nbf, 1, 0));
+          DEV_CHECK(ctx, gemm_f64(s, nbf, nbf, nbf, 1, 1.0, C, 1, nbf, 0, T1, nbf, 1, 0, 0.0, S, nbf, 1, 0));
+        }
+      }
+    }
+    if ((st = diagonalise()) != PNOF_OK) return st;
+    if ((st = lagr(Enew, asym)) != PNOF_OK) return st;
+    res.d_n = std::fabs(En - Eprev);
+    res.d_phi = std::fabs(Enew - Efix);
+    res.d_E = std::fabs(Enew - Eprev);
+    res.max_asym = asym;
+    res.E = Enew;
+    Eprev = Enew;
+    if (asym < op.delta) {
+      res.converged = 1;
+      break;
+    }
+    if (res.d_n < op.eps_n && res.d_phi < op.eps_phi && res.d_E < op.eps) break;
+  }
+  res.iterations = std::min(it, maxit);
+  *result = res;
   return PNOF_OK;
 }
 

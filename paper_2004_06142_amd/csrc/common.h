@@ -269,6 +269,10 @@ hipError_t on_map_vjp(hipStream_t s, int kind, int npairs, int ncwo, const doubl
 hipError_t build_s(hipStream_t s, int nbf, const double* lam, const double* diag_prev, double zeta,
                    double* S);
 hipError_t sign_fix_cols(hipStream_t s, int nbf, double* Ucm);
+hipError_t offdiag_copy(hipStream_t s, int nbf, const double* src, double* dst);
+// E_hf and E_sta (device scalars) from n, H_pp, J, K; partials: 256 doubles of scratch.
+hipError_t nofmp2_terms(hipStream_t s, int nact, int npairs, int ncwo, const double* n, const double* Hpp,
+                        const double* J, const double* K, double* partials, double* E_hf, double* E_sta);
 hipError_t count_nonfinite(hipStream_t s, const void* p, long long n, int is_bf16, int* flag);
 // explicit four-index integrals (nbf <= 64)
 hipError_t eri_jk_ao(hipStream_t s, int nbf, int nact, const double* ERI, const double* C,

@@ -162,6 +162,59 @@ __global__ void sum_partials_k(int nparts, const double* __restrict__ partials, 
   if (threadIdx.x == 0) *out = s;
 }
 
+// NOF-MP2 reference terms (Eqs. HFL, Esta): block partial sums of E_hf and E_sta over a fixed
+// range of the index space [0, npairs) + [0, nact^2); stage 2 adds the partials in order.
+__global__ void nofmp2_stage1_k(int nact, int npairs, int ncwo, const double* __restrict__ n,
+                                const double* __restrict__ Hpp, const double* __restrict__ J,
+                                const double* __restrict__ K, double* __restrict__ partials) {
+  const long long n2 = (long long)nact * nact;
+  const long long total = npairs + (long long)npairs * npairs + n2;
+  const long long per = (total + gridDim.x - 1) / gridDim.x;
+  const long long b0 = blockIdx.x * per, b1 = min(total, b0 + per);
+  double hf = 0.0, sta = 0.0;
+  for (long long i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
+    if (i < npairs) hf += 2.0 * Hpp[i];
+    else if (i < npairs + (long long)npairs * npairs) {
+      const long long k = i - npairs;
+      const int f = (int)(k / npairs), g = (int)(k % npairs);
+      hf += 2.0 * J[(long long)f * nact + g] - K[(long long)f * nact + g];
+    } else {
+      const long long k = i - npairs - (long long)npairs * npairs;
+      const int p = (int)(k / nact), q = (int)(k % nact);
+      if (p == q) continue;
+      const double np_ = n[p], nq = n[q];
+      if (pair_of(p, npairs, ncwo) == pair_of(q, npairs, ncwo)) {
+        const double lp = 1.0 - fabs(1.0 - 2.0 * np_), lq = 1.0 - fabs(1.0 - 2.0 * nq);
+        const double sg = (p < npairs || q < npairs) ? -1.0 : 1.0;
+        sta += sqrt(lp * lq) * sg * sqrt(np_ * nq) * K[k];
+      } else {
+        sta += -4.0 * (nq * (1.0 - nq)) * (np_ * (1.0 - np_)) * K[k];
+      }
+    }
+  }
+  hf = block_sum(hf);
+  sta = block_sum(sta);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = hf;
+    partials[2 * blockIdx.x + 1] = sta;
+  }
+}
+
+__global__ void sum2_partials_k(int nparts, const double* __restrict__ partials, double* __restrict__ a,
+                                double* __restrict__ b) {
+  double x = 0.0, y = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+    x += partials[2 * i];
+    y += partials[2 * i + 1];
+  }
+  x = block_sum(x);
+  y = block_sum(y);
+  if (threadIdx.x == 0) {
+    *a = x;
+    *b = y;
+  }
+}
+
 __global__ void assemble_y_k(int nbf, int nact, const double* __restrict__ n, const double* __restrict__ HC,
                              const double* __restrict__ Y2e, double* __restrict__ Y) {
   GRID_STRIDE(i, (long long)nbf * nact) {
@@ -349,6 +402,11 @@ __global__ void on_map_vjp_k(int kind, int npairs, int ncwo, const double* __res
       out[base + j] = sum;
     }
   }
+}
+
+// dst = src with a zero diagonal (the error vector of the DIIS extrapolation).
+__global__ void offdiag_k(int nbf, const double* __restrict__ src, double* __restrict__ dst) {
+  GRID_STRIDE(i, (long long)nbf * nbf) dst[i] = (i / nbf == i % nbf) ? 0.0 : src[i];
 }
 
 // Matrix diagonalised by the orbital step.
@@ -613,6 +671,17 @@ hipError_t add_diag_bf16(hipStream_t s, int nact, int np, const double* Dc, cons
   hipError_t e = gemm_f64(s, np, nact, nact, 1, 1.0, Dc, nact, 1, 0, alpha, nact, 1, 0, 0.0, dbuf, nact, 1, 0);
   if (e != hipSuccess) return e;
   LAUNCH(add_diag_bf16_k, grid1((long long)np * nact), dim3(NT), nact, np, dbuf, Wh, Wl, ldw, pstride);
+}
+hipError_t nofmp2_terms(hipStream_t s, int nact, int npairs, int ncwo, const double* n, const double* Hpp,
+                        const double* J, const double* K, double* partials, double* E_hf, double* E_sta) {
+  const int nb = 128;   // partials holds 2 * nb doubles
+  hipLaunchKernelGGL(nofmp2_stage1_k, dim3(nb), dim3(NT), 0, s, nact, npairs, ncwo, n, Hpp, J, K, partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  LAUNCH(sum2_partials_k, dim3(1), dim3(NT), nb, partials, E_hf, E_sta);
+}
+hipError_t offdiag_copy(hipStream_t s, int nbf, const double* src, double* dst) {
+  LAUNCH(offdiag_k, grid1((long long)nbf * nbf), dim3(NT), nbf, src, dst);
 }
 hipError_t reduce_k(hipStream_t s, int nact, int nsplit, const double* Kpart, double* K) {
   LAUNCH(reduce_k_k, grid1((long long)nact * nact), dim3(NT), nact, nsplit, Kpart, K);
