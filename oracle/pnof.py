@@ -5,10 +5,12 @@ Notation (arXiv:2004.06142):
   C[mu, p]   NO coefficients, phi_p = sum_mu C[mu,p] zeta_mu (Eq. lcao); S = I
   n[p]       per-spin occupation numbers, 0 <= n <= 1 (Section 2)
   npairs     number of electron pairs N_II/2; ncwo = N_g, weak orbitals per pair
-  nact       npairs * (ncwo + 1) active orbitals; orbitals >= nact have n = 0
+  nsingle    N_I singly occupied orbitals (Omega_I, n = 1/2 each); 0 for singlets
+  nact       npairs * (ncwo + 1) + nsingle active orbitals; orbitals >= nact have n = 0
   ERI[m,n,l,s] = (mn|ls) in chemists' notation; the paper's <mu eta|nu delta> = (mu nu|eta delta)
   B[P,m,n]   density-fitting factor, (mn|ls) = sum_P B[P,m,n] B[P,l,s]
-Only singlets (N_I = 0) are treated, so the Omega_I term of Eq. EPNOF7 is absent.
+Multiplets of highest multiplicity (Section 2, S = N_I / 2) add N_I singly occupied orbitals;
+every function takes nsingle (default 0, the singlet case).
 """
 from __future__ import annotations
 
@@ -20,17 +22,21 @@ PNOF5, PNOF7, PNOF7S = 5, 7, 8
 
 
 # --------------------------------------------------------------------------- layout
-def layout(npairs: int, ncwo: int, nbf: int | None = None):
+def layout(npairs: int, ncwo: int, nbf: int | None = None, nsingle: int = 0):
     """Subspace membership of every orbital (Section 2, Eqs. OmegaG and sum1).
 
-    Strong orbital of pair g (0-based) is orbital g.  Its ncwo weak orbitals form one
-    consecutive block, the blocks taken in reverse pair order: weak k of pair g is
-    npairs + ncwo*(npairs-1-g) + k.  This is the coupling that makes every subspace of
-    the water occupation tables (Tables 1 and 2) sum to two electrons.
+    Strong orbital of pair g (0-based) is orbital g.  The nsingle singly occupied orbitals of
+    Omega_I (each its own subspace, n = 1/2) follow: orbitals npairs .. npairs+nsingle-1, so
+    that the N_Omega = npairs + nsingle subspace-defining orbitals come first, as in the sums of
+    Eqs. EPNOF7 and HFL.  The ncwo weak orbitals of pair g form one consecutive block, the
+    blocks taken in reverse pair order: weak k of pair g is npairs + nsingle + ncwo*(npairs-1-g) + k.
+    This is the coupling that makes every subspace of the water occupation tables (Tables 1 and
+    2) sum to two electrons.
 
-    Returns (pair, strong): pair[p] = g or -1 for inactive p; strong[p] bool.
+    Returns (pair, strong): pair[p] = subspace id (g for pair g, npairs + t for the t-th single
+    orbital) or -1 for inactive p; strong[p] bool.
     """
-    nact = npairs * (ncwo + 1)
+    nact = npairs * (ncwo + 1) + nsingle
     nbf = nact if nbf is None else nbf
     pair = np.full(nbf, -1, dtype=np.int64)
     strong = np.zeros(nbf, dtype=bool)
@@ -38,12 +44,19 @@ def layout(npairs: int, ncwo: int, nbf: int | None = None):
         pair[g] = g
         strong[g] = True
         for k in range(ncwo):
-            pair[npairs + ncwo * (npairs - 1 - g) + k] = g
+            pair[npairs + nsingle + ncwo * (npairs - 1 - g) + k] = g
+    for t in range(nsingle):
+        pair[npairs + t] = npairs + t
     return pair, strong
 
 
-def weak_orbitals(g: int, npairs: int, ncwo: int):
-    return [npairs + ncwo * (npairs - 1 - g) + k for k in range(ncwo)]
+def single_orbitals(npairs: int, nsingle: int):
+    """Orbitals of Omega_I (one electron each, n = 1/2)."""
+    return list(range(npairs, npairs + nsingle))
+
+
+def weak_orbitals(g: int, npairs: int, ncwo: int, nsingle: int = 0):
+    return [npairs + nsingle + ncwo * (npairs - 1 - g) + k for k in range(ncwo)]
 
 
 # --------------------------------------------------------------------------- ON maps
@@ -51,30 +64,35 @@ def _sigmoid(x):
     return 1.0 / (1.0 + np.exp(-x))
 
 
-def on_sigmoid(gamma, npairs: int, ncwo: int):
+def on_sigmoid(gamma, npairs: int, ncwo: int, nsingle: int = 0):
     """n_p = s(gamma_p) / sum_{r in Omega(p)} s(gamma_r): one gamma per active orbital.
 
-    Satisfies 0 < n < 1 and the pairing sum rule (Eq. sum1) by construction.
+    Satisfies 0 < n < 1 and the pairing sum rule (Eq. sum1) by construction.  Orbitals of
+    Omega_I have n = 1/2 whatever their gamma.
     """
-    pair, _ = layout(npairs, ncwo)
+    pair, _ = layout(npairs, ncwo, nsingle=nsingle)
     s = _sigmoid(np.asarray(gamma, dtype=np.float64))
-    tot = np.zeros(npairs)
+    tot = np.zeros(npairs + nsingle)
     for p in range(len(s)):
         tot[pair[p]] += s[p]
-    return np.array([s[p] / tot[pair[p]] for p in range(len(s))])
+    singles = set(single_orbitals(npairs, nsingle))
+    return np.array([0.5 if p in singles else s[p] / tot[pair[p]] for p in range(len(s))])
 
 
-def on_sigmoid_jac(gamma, npairs: int, ncwo: int):
+def on_sigmoid_jac(gamma, npairs: int, ncwo: int, nsingle: int = 0):
     """dn_p/dgamma_r for the sigmoid-normalised map (quotient rule, block-diagonal)."""
-    pair, _ = layout(npairs, ncwo)
+    pair, _ = layout(npairs, ncwo, nsingle=nsingle)
     s = _sigmoid(np.asarray(gamma, dtype=np.float64))
     ds = s * (1.0 - s)
-    tot = np.zeros(npairs)
+    tot = np.zeros(npairs + nsingle)
     for p in range(len(s)):
         tot[pair[p]] += s[p]
     nact = len(s)
+    singles = set(single_orbitals(npairs, nsingle))
     jac = np.zeros((nact, nact))
     for p in range(nact):
+        if p in singles:
+            continue
         for r in range(nact):
             if pair[p] != pair[r]:
                 continue
@@ -93,22 +111,24 @@ def _trig_gammas(gamma, npairs: int, ncwo: int, g: int):
     return gs, gw
 
 
-def on_trig(gamma, npairs: int, ncwo: int):
+def on_trig(gamma, npairs: int, ncwo: int, nsingle: int = 0):
     """Trigonometric ON map of Section 3.1 (Eqs. soo, sum1-h, woo).
 
     n_g = (1 + cos^2 gamma_g)/2, hole h_g = sin^2(gamma_g)/2; the i-th weak orbital
     (i = 1..N_g) gets h_g * prod_{j<i} cos^2 gamma_{p_j} * sin^2 gamma_{p_i}, the last one
-    h_g * prod_{j<N_g} cos^2 gamma_{p_j}.
+    h_g * prod_{j<N_g} cos^2 gamma_{p_j}.  Orbitals of Omega_I have n = 1/2 (no variable).
     """
     gamma = np.asarray(gamma, dtype=np.float64)
-    nact = npairs * (ncwo + 1)
+    nact = npairs * (ncwo + 1) + nsingle
     n = np.zeros(nact)
+    for t in single_orbitals(npairs, nsingle):
+        n[t] = 0.5
     for g in range(npairs):
         gs, gw = _trig_gammas(gamma, npairs, ncwo, g)
         n[g] = 0.5 * (1.0 + math.cos(gs) ** 2)
         h = 0.5 * math.sin(gs) ** 2
         prod = 1.0
-        for i, p in enumerate(weak_orbitals(g, npairs, ncwo)):
+        for i, p in enumerate(weak_orbitals(g, npairs, ncwo, nsingle)):
             if i < ncwo - 1:
                 n[p] = h * prod * math.sin(gw[i]) ** 2
                 prod *= math.cos(gw[i]) ** 2
@@ -117,10 +137,10 @@ def on_trig(gamma, npairs: int, ncwo: int):
     return n
 
 
-def on_trig_jac(gamma, npairs: int, ncwo: int):
+def on_trig_jac(gamma, npairs: int, ncwo: int, nsingle: int = 0):
     """dn/dgamma of the trigonometric map (nact x npairs*ncwo), by the product rule."""
     gamma = np.asarray(gamma, dtype=np.float64)
-    nact = npairs * (ncwo + 1)
+    nact = npairs * (ncwo + 1) + nsingle
     jac = np.zeros((nact, npairs * ncwo))
     for g in range(npairs):
         gs, gw = _trig_gammas(gamma, npairs, ncwo, g)
@@ -129,7 +149,7 @@ def on_trig_jac(gamma, npairs: int, ncwo: int):
         jac[g, col_g] = -math.cos(gs) * math.sin(gs)          # d/dx (1+cos^2 x)/2
         h = 0.5 * math.sin(gs) ** 2
         dh = math.sin(gs) * math.cos(gs)
-        weak = weak_orbitals(g, npairs, ncwo)
+        weak = weak_orbitals(g, npairs, ncwo, nsingle)
         for i, p in enumerate(weak):
             # factors f_j of n_p = h * prod_j f_j, and their derivatives
             factors = [math.cos(gw[j]) ** 2 for j in range(min(i, ncwo - 1))]
@@ -159,7 +179,7 @@ def phi(n):
     return np.sqrt(n * (1.0 - n))
 
 
-def coefficients(n, npairs: int, ncwo: int, functional: int = PNOF7):
+def coefficients(n, npairs: int, ncwo: int, functional: int = PNOF7, nsingle: int = 0):
     """alpha, beta with E_2 = sum_{p,q in A} (alpha_pq J_pq + beta_pq K_pq).
 
     Same subspace (Eq. Eg with Pi of Eq. intra): alpha = 0, beta_pp = n_p,
@@ -167,8 +187,12 @@ def coefficients(n, npairs: int, ncwo: int, functional: int = PNOF7):
     Different subspaces (Eq. Efg, counted once per ordered pair (f, g), f != g):
     alpha = 2 n_p n_q; beta = -n_p n_q - Phi_p Phi_q (PNOF7), -n_p n_q (PNOF5, Phi = 0),
     -n_p n_q - 4 Phi_p^2 Phi_q^2 (PNOF7s, Eq. Efg_s).
+    A singly occupied orbital has no intra-subspace term (no opposite-spin partner in its own
+    orbital, Eq. intra): beta_pp = 0; its interactions with other subspaces follow Eq. Efg with
+    n = 1/2 (Eq. interab takes K for real orbitals in both of its cases).
     """
-    pair, strong = layout(npairs, ncwo)
+    pair, strong = layout(npairs, ncwo, nsingle=nsingle)
+    singles = set(single_orbitals(npairs, nsingle))
     n = np.asarray(n, dtype=np.float64)
     nact = len(pair)
     ph = phi(n)
@@ -178,7 +202,7 @@ def coefficients(n, npairs: int, ncwo: int, functional: int = PNOF7):
         for q in range(nact):
             if pair[p] == pair[q]:
                 if p == q:
-                    beta[p, q] = n[p]
+                    beta[p, q] = 0.0 if p in singles else n[p]
                 elif strong[p] or strong[q]:
                     beta[p, q] = -math.sqrt(n[p] * n[q])
                 else:
@@ -254,12 +278,13 @@ def h_no(C, H, nact: int):
 
 
 # --------------------------------------------------------------------------- energy
-def energy_from_jk(n, Hpp, J, K, npairs: int, ncwo: int, functional: int = PNOF7):
+def energy_from_jk(n, Hpp, J, K, npairs: int, ncwo: int, functional: int = PNOF7, nsingle: int = 0):
     """Singlet PNOF energy, Eqs. EPNOF7, Eg, Efg (and Efg_s / PNOF5 variants).
 
     E = 2 sum_p n_p H_pp + sum_{p,q in A} (alpha_pq J_pq + beta_pq K_pq); summed with fsum.
+    For multiplets the singly occupied orbitals contribute 2 (1/2) H_gg = H_gg (Eq. EPNOF7).
     """
-    alpha, beta = coefficients(n, npairs, ncwo, functional)
+    alpha, beta = coefficients(n, npairs, ncwo, functional, nsingle)
     nact = len(n)
     terms = [2.0 * n[p] * Hpp[p] for p in range(nact)]
     for p in range(nact):
@@ -269,22 +294,22 @@ def energy_from_jk(n, Hpp, J, K, npairs: int, ncwo: int, functional: int = PNOF7
     return math.fsum(terms)
 
 
-def energy(C, n, H, ints, npairs: int, ncwo: int, functional: int = PNOF7, kind: str = "df"):
-    nact = npairs * (ncwo + 1)
+def energy(C, n, H, ints, npairs: int, ncwo: int, functional: int = PNOF7, kind: str = "df", nsingle: int = 0):
+    nact = npairs * (ncwo + 1) + nsingle
     J, K = jk_no(ints, C, nact, kind)
-    return energy_from_jk(n, h_no(C, H, nact), J, K, npairs, ncwo, functional)
+    return energy_from_jk(n, h_no(C, H, nact), J, K, npairs, ncwo, functional, nsingle)
 
 
 # --------------------------------------------------------------------------- Fock / Lagrangian
-def fock_ao(C, n, H, ints, npairs: int, ncwo: int, functional: int = PNOF7, kind: str = "df"):
+def fock_ao(C, n, H, ints, npairs: int, ncwo: int, functional: int = PNOF7, kind: str = "df", nsingle: int = 0):
     """F^q = n_q H + sum_{r in A} (alpha_qr J^r + beta_qr K^r), q in A.
 
     This is Eq. lowdin divided by 4: the one-particle part 4 n_p H and the
     Coulomb/exchange operators of Eqs. Vee-s and Vee-d, whose weights are the
     derivative of Eqs. Eg/Efg with respect to the orbital.
     """
-    nact = npairs * (ncwo + 1)
-    alpha, beta = coefficients(n, npairs, ncwo, functional)
+    nact = npairs * (ncwo + 1) + nsingle
+    alpha, beta = coefficients(n, npairs, ncwo, functional, nsingle)
     Jr, Kr = [], []
     for r in range(nact):
         a, b = jk_ao(ints, C, r, kind)
@@ -327,7 +352,7 @@ def grad_C(C, F):
     return g
 
 
-def grad_n(n, Hpp, J, K, npairs: int, ncwo: int, functional: int = PNOF7):
+def grad_n(n, Hpp, J, K, npairs: int, ncwo: int, functional: int = PNOF7, nsingle: int = 0):
     """dE/dn_p: the derivative of Eqs. EPNOF7/Eg/Efg with J, K, H_pp held fixed.
 
     Same subspace:   2 H_pp + K_pp + sum_{q != p} s_pq sqrt(n_q / n_p) K_pq,
@@ -335,14 +360,17 @@ def grad_n(n, Hpp, J, K, npairs: int, ncwo: int, functional: int = PNOF7):
     Other subspaces: sum_q [4 n_q J_pq - 2 n_q K_pq + kappa_pq K_pq],
                      kappa = -Phi_q (1-2n_p)/Phi_p (PNOF7), 0 (PNOF5),
                      -8 (1-2n_p) n_q (1-n_q) (PNOF7s).
+    A singly occupied orbital has no K_pp term (beta_pp = 0); its occupation is fixed at 1/2,
+    so its entry is the partial derivative only.
     """
-    pair, strong = layout(npairs, ncwo)
+    pair, strong = layout(npairs, ncwo, nsingle=nsingle)
+    singles = set(single_orbitals(npairs, nsingle))
     n = np.asarray(n, dtype=np.float64)
     nact = len(n)
     ph = phi(n)
     g = np.zeros(nact)
     for p in range(nact):
-        terms = [2.0 * Hpp[p], K[p, p]]
+        terms = [2.0 * Hpp[p], 0.0 if p in singles else K[p, p]]
         for q in range(nact):
             if q == p:
                 continue
@@ -423,24 +451,29 @@ def orbital_step(lam, C, diag_prev=None, zeta: float = 0.0):
 
 
 # --------------------------------------------------------------------------- NOF-MP2 reference terms
-def nofmp2_reference(n, Hpp, J, K, npairs: int, ncwo: int):
+def nofmp2_reference(n, Hpp, J, K, npairs: int, ncwo: int, nsingle: int = 0):
     """HF-like energy with the natural orbitals (Eq. HFL) and static correlation (Eq. Esta).
 
-    Singlet case (no singly occupied subspaces).  The HF-like density occupies the strong
-    orbitals g = 0..npairs-1 doubly:
-        E_hf  = 2 sum_g H_gg + sum_{f,g} (2 J_fg - K_fg).
+    The HF-like density occupies the N_Omega = npairs + nsingle subspace-defining orbitals, the
+    strong ones doubly (A_g = 1) and those of Omega_I singly (A_g = 1/2); the term J_gg/4 of
+    Eq. HFL removes the self-interaction A_g^2 (2 J_gg - K_gg) = J_gg/4 of a singly occupied orbital:
+        E_hf  = sum_g 2 A_g H_gg + sum_{f,g} A_f A_g (2 J_fg - K_fg) - sum_{g in Omega_I} J_gg / 4.
     Static correlation, with Lambda_p = 1 - |1 - 2 n_p| and Phi_p^2 = n_p (1 - n_p):
         E_sta = sum_g sum_{p != q in Omega_g} sqrt(Lambda_p Lambda_q) Pi_qp K_pq
                 - 4 sum_{f != g} sum_{p in Omega_f, q in Omega_g} Phi_q^2 Phi_p^2 K_pq,
     Pi_qp = +sqrt(n_q n_p) for two weak orbitals, -sqrt(n_q n_p) when one is strong (Eq. intra).
     Both sums use math.fsum.
     """
-    pair, strong = layout(npairs, ncwo)
-    nact = npairs * (ncwo + 1)
-    hf = [2.0 * Hpp[g] for g in range(npairs)]
-    for f in range(npairs):
-        for g in range(npairs):
-            hf.append(2.0 * J[f, g] - K[f, g])
+    pair, strong = layout(npairs, ncwo, nsingle=nsingle)
+    nact = npairs * (ncwo + 1) + nsingle
+    nom = npairs + nsingle
+    A = [1.0 if g < npairs else 0.5 for g in range(nom)]
+    hf = [2.0 * A[g] * Hpp[g] for g in range(nom)]
+    for f in range(nom):
+        for g in range(nom):
+            hf.append(A[f] * A[g] * (2.0 * J[f, g] - K[f, g]))
+    for g in range(npairs, nom):
+        hf.append(-0.25 * J[g, g])
     lam = [1.0 - abs(1.0 - 2.0 * n[p]) for p in range(nact)]
     ph2 = [n[p] * (1.0 - n[p]) for p in range(nact)]
     sta = []

@@ -44,17 +44,17 @@ def jk(C, B, nact: int, naux: int | None = None, pchunk: int = 64):
 
 
 def lagrangian(C, n, H, B, npairs: int, ncwo: int, functional: int = pnof.PNOF7,
-               naux: int | None = None, pchunk: int = 64):
+               naux: int | None = None, pchunk: int = 64, nsingle: int = 0):
     """E, lambda (nbf x nbf), Y (nbf x nact), J, K, dE/dn in one pass over B.
 
     Returns a dict with keys E, lam, Y, J, K, Hpp, dEdn, dEdC.
     """
     naux = B.shape[0] if naux is None else naux
     nbf = C.shape[0]
-    nact = npairs * (ncwo + 1)
+    nact = npairs * (ncwo + 1) + nsingle
     n = np.asarray(n, dtype=np.float64)[:nact]
     CA = C[:, :nact]
-    alpha, beta = pnof.coefficients(n, npairs, ncwo, functional)
+    alpha, beta = pnof.coefficients(n, npairs, ncwo, functional, nsingle)
     HC = H @ CA
     Hpp = np.einsum("mp,mp->p", CA, HC)
     Y = HC * n[None, :]
@@ -80,5 +80,5 @@ def lagrangian(C, n, H, B, npairs: int, ncwo: int, functional: int = pnof.PNOF7,
     dEdC[:, :nact] = 4.0 * Y
     return {
         "E": E, "lam": lam, "Y": Y, "J": J, "K": K, "Hpp": Hpp, "D": D,
-        "dEdn": pnof.grad_n(n, Hpp, J, K, npairs, ncwo, functional), "dEdC": dEdC,
+        "dEdn": pnof.grad_n(n, Hpp, J, K, npairs, ncwo, functional, nsingle), "dEdC": dEdC,
     }
