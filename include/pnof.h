@@ -3,7 +3,8 @@
  *
  * The operations follow M. Piris and I. Mitxelena, "DoNOF: an open-source implementation of
  * natural-orbital-functional-based methods for quantum chemistry", arXiv:2004.06142:
- *   energy          Section 2, Eqs. EPNOF7, Eg, Efg (PNOF5: Phi = 0; PNOF7s: Eq. Efg_s)
+ *   energy          Section 2, Eqs. EPNOF7, Eg, Efg (PNOF5: Phi = 0; PNOF7s: Eq. Efg_s); multiplets of
+ *                   highest multiplicity through N_I singly occupied orbitals (Eqs. intra, interab)
  *   J, K            Section 3.5, Eqs. JKpq and Gpmn (L = K for real orbitals, Section 2)
  *   Fock vectors    Section 3.2, Eqs. lowdin, Vee-s, Vee-d
  *   Lagrangian      Section 3.2, Eqs. lag and gval; symmetry criterion of Section 3.4
@@ -15,10 +16,12 @@
  *   - All array arguments are DEVICE pointers on the context's device, row-major, float64 unless
  *     stated.  The caller owns every buffer; the library never frees or retains them.
  *   - C[mu*nbf + p] = C_{mu p}: column p holds orbital p in the (orthonormal, S = I) AO basis.
- *   - n[p], p < nbf: per-spin occupation numbers; n[p] = 0 for p >= nact = npairs*(ncwo+1).
- *   - Orbital layout (fixed by npairs, ncwo): the strong orbital of pair g is orbital g; the ncwo
- *     weak orbitals of pair g are npairs + ncwo*(npairs-1-g) + k, k = 0..ncwo-1 (consecutive
- *     blocks in reverse pair order, the coupling of the water tables of Section 5).
+ *   - n[p], p < nbf: per-spin occupation numbers; n[p] = 0 for p >= nact = npairs*(ncwo+1) + nsingle.
+ *   - Orbital layout (fixed by npairs, ncwo, nsingle): the strong orbital of pair g is orbital g;
+ *     the nsingle singly occupied orbitals of Omega_I (n = 1/2, each its own subspace, no
+ *     intra-subspace term) are npairs .. npairs+nsingle-1; the ncwo weak orbitals of pair g are
+ *     npairs + nsingle + ncwo*(npairs-1-g) + k, k = 0..ncwo-1 (consecutive blocks in reverse pair
+ *     order, the coupling of the water tables of Section 5).
  *   - H: nbf x nbf symmetric one-electron matrix.
  *   - Two-electron integrals, by pnof_problem.ints:
  *       PNOF_INTS_ERI4_F64  ERI[((m*nbf + n)*nbf + l)*nbf + s] = (mn|ls), float64, nbf <= 64;
@@ -46,7 +49,7 @@
 extern "C" {
 #endif
 
-#define PNOF_ABI_VERSION 1
+#define PNOF_ABI_VERSION 2
 
 typedef struct pnof_ctx_s* pnof_ctx;
 
@@ -86,6 +89,7 @@ typedef struct {
   int32_t precision;   /* pnof_precision                                      */
   int32_t ints;        /* pnof_ints                                           */
   int32_t flags;       /* PNOF_CHECK_FINITE                                   */
+  int32_t nsingle;     /* N_I singly occupied orbitals (multiplet S = N_I/2); 0: singlet */
 } pnof_problem;
 
 /* ---- context ---------------------------------------------------------------------------- */
@@ -128,14 +132,16 @@ pnof_status pnof_profile_begin(pnof_ctx ctx);
 pnof_status pnof_profile_end(pnof_ctx ctx, double* ms, int64_t* launches);
 
 /* ---- occupation numbers (Section 3.1) ------------------------------------------------------- */
-/* kind 0, sigmoid-normalised: n_p = s(gamma_p) / sum_{r in pair(p)} s(gamma_r), ngamma = nact.
+/* kind 0, sigmoid-normalised: n_p = s(gamma_p) / sum_{r in pair(p)} s(gamma_r), ngamma = nact
+ *   (the entries of singly occupied orbitals are not used).
  * kind 1, trigonometric (Eqs. soo, woo): ngamma = npairs*ncwo; gamma[g] is the strong orbital's
  *   variable of pair g and gamma[npairs + g*(ncwo-1) + i] the i-th weak one.
- * n: nact outputs.  dn_dgamma: optional nact x ngamma dense Jacobian (NULL to skip). */
-pnof_status pnof_on_map(pnof_ctx ctx, int32_t kind, int32_t npairs, int32_t ncwo,
+ * Singly occupied orbitals get n = 1/2.  n: nact outputs.  dn_dgamma: optional nact x ngamma
+ * dense Jacobian (NULL to skip). */
+pnof_status pnof_on_map(pnof_ctx ctx, int32_t kind, int32_t npairs, int32_t ncwo, int32_t nsingle,
                         const double* gamma, double* n, double* dn_dgamma);
 /* Adjoint of the ON map: dEdgamma[r] = sum_p dEdn[p] dn_p/dgamma_r (ngamma outputs). */
-pnof_status pnof_on_map_vjp(pnof_ctx ctx, int32_t kind, int32_t npairs, int32_t ncwo,
+pnof_status pnof_on_map_vjp(pnof_ctx ctx, int32_t kind, int32_t npairs, int32_t ncwo, int32_t nsingle,
                             const double* gamma, const double* dEdn, double* dEdgamma);
 
 /* ---- NO integrals (Eqs. JKpq, Gpmn) --------------------------------------------------------- */
@@ -179,8 +185,9 @@ pnof_status pnof_orbital_step(pnof_ctx ctx, int32_t nbf, const double* lambda, c
                               double* S_out);
 
 /* ---- NOF-MP2 reference terms (Section 4, Eqs. HFL and Esta) ----------------------------------- */
-/* E_hf: Hartree-Fock-like energy of the natural orbitals, 2 sum_g H_gg + sum_fg (2 J_fg - K_fg)
- * over the strong orbitals g, f < npairs.  E_sta: static correlation,
+/* E_hf: Hartree-Fock-like energy of the natural orbitals, sum_g 2 A_g H_gg + sum_fg A_f A_g
+ * (2 J_fg - K_fg) - sum_{g single} J_gg / 4 over the N_Omega = npairs + nsingle subspace-defining
+ * orbitals (A = 1 strong, 1/2 single).  E_sta: static correlation,
  * sum_g sum_{p != q in Omega_g} sqrt(Lambda_p Lambda_q) Pi_qp K_pq - 4 sum_{f != g} sum_{p in
  * Omega_f, q in Omega_g} Phi_q^2 Phi_p^2 K_pq with Lambda_p = 1 - |1 - 2 n_p| and Pi of Eq. intra.
  * The dynamic term E^dyn needs amplitude equations that the paper does not give and is not

@@ -26,29 +26,33 @@ import numpy as np
 from . import pnof, stream
 
 
-def on_map(gamma, npairs, ncwo, kind="sigmoid"):
-    return pnof.on_sigmoid(gamma, npairs, ncwo) if kind == "sigmoid" else pnof.on_trig(gamma, npairs, ncwo)
+def on_map(gamma, npairs, ncwo, kind="sigmoid", nsingle=0):
+    if kind == "sigmoid":
+        return pnof.on_sigmoid(gamma, npairs, ncwo, nsingle)
+    return pnof.on_trig(gamma, npairs, ncwo, nsingle)
 
 
-def on_jac(gamma, npairs, ncwo, kind="sigmoid"):
-    return pnof.on_sigmoid_jac(gamma, npairs, ncwo) if kind == "sigmoid" else pnof.on_trig_jac(gamma, npairs, ncwo)
+def on_jac(gamma, npairs, ncwo, kind="sigmoid", nsingle=0):
+    if kind == "sigmoid":
+        return pnof.on_sigmoid_jac(gamma, npairs, ncwo, nsingle)
+    return pnof.on_trig_jac(gamma, npairs, ncwo, nsingle)
 
 
-def on_energy_grad(gamma, Hpp, J, K, npairs, ncwo, functional=pnof.PNOF7, kind="sigmoid"):
+def on_energy_grad(gamma, Hpp, J, K, npairs, ncwo, functional=pnof.PNOF7, kind="sigmoid", nsingle=0):
     """E(n(gamma)) at fixed J, K, H_pp and its gradient (dn/dgamma)^T dE/dn."""
-    n = on_map(gamma, npairs, ncwo, kind)
-    E = pnof.energy_from_jk(n, Hpp, J, K, npairs, ncwo, functional)
-    g = on_jac(gamma, npairs, ncwo, kind).T @ pnof.grad_n(n, Hpp, J, K, npairs, ncwo, functional)
+    n = on_map(gamma, npairs, ncwo, kind, nsingle)
+    E = pnof.energy_from_jk(n, Hpp, J, K, npairs, ncwo, functional, nsingle)
+    g = on_jac(gamma, npairs, ncwo, kind, nsingle).T @ pnof.grad_n(n, Hpp, J, K, npairs, ncwo, functional, nsingle)
     return E, g
 
 
 def optimize_on(gamma0, Hpp, J, K, npairs, ncwo, functional=pnof.PNOF7, kind="sigmoid", gtol=1e-10,
-                maxiter=1000):
+                maxiter=1000, nsingle=0):
     """Minimise E over gamma at fixed orbitals; returns (gamma, E, iterations)."""
     from scipy.optimize import minimize
 
     res = minimize(on_energy_grad, np.asarray(gamma0, dtype=np.float64), jac=True, method="L-BFGS-B",
-                   args=(Hpp, J, K, npairs, ncwo, functional, kind),
+                   args=(Hpp, J, K, npairs, ncwo, functional, kind, nsingle),
                    options={"gtol": gtol, "ftol": 1e-15, "maxiter": maxiter, "maxcor": 10})
     return res.x, float(res.fun), int(res.nit)
 
@@ -58,13 +62,13 @@ def _jk_hpp(C, H, ints, nact, kind):
     return pnof.h_no(C, H, nact), J, K
 
 
-def _lagrangian(C, n, H, ints, npairs, ncwo, functional, kind):
+def _lagrangian(C, n, H, ints, npairs, ncwo, functional, kind, nsingle=0):
     if kind == "df":
-        r = stream.lagrangian(C, n, H, ints, npairs, ncwo, functional)
+        r = stream.lagrangian(C, n, H, ints, npairs, ncwo, functional, nsingle=nsingle)
         return r["E"], r["lam"]
-    F = pnof.fock_ao(C, n, H, ints, npairs, ncwo, functional, kind)
+    F = pnof.fock_ao(C, n, H, ints, npairs, ncwo, functional, kind, nsingle)
     lam = pnof.lagrangian(C, F)
-    return pnof.energy(C, n, H, ints, npairs, ncwo, functional, kind), lam
+    return pnof.energy(C, n, H, ints, npairs, ncwo, functional, kind, nsingle), lam
 
 
 def diis_extrapolate(mats, errs):
@@ -83,13 +87,14 @@ def diis_extrapolate(mats, errs):
 
 
 def optimize(C0, gamma0, H, ints, npairs, ncwo, functional=pnof.PNOF7, kind="df", on_kind="sigmoid",
-             maxit=200, eps_n=1e-10, eps_phi=1e-10, eps=1e-10, delta=1e-4, zeta=0.0, ndiis=0, fixed_n=None):
+             maxit=200, eps_n=1e-10, eps_phi=1e-10, eps=1e-10, delta=1e-4, zeta=0.0, ndiis=0, fixed_n=None,
+             nsingle=0):
     """Orbital + occupation optimisation of Section 3.4.
 
     fixed_n: occupations held fixed (no occupation optimisation), e.g. the Hartree-Fock limit.
     Returns dict(C, gamma, n, E, max_asym, iterations, converged, history).
     """
-    nact = npairs * (ncwo + 1)
+    nact = npairs * (ncwo + 1) + nsingle
     C = np.array(C0, dtype=np.float64)
     gamma = None if gamma0 is None else np.array(gamma0, dtype=np.float64)
 
@@ -97,16 +102,16 @@ def optimize(C0, gamma0, H, ints, npairs, ncwo, functional=pnof.PNOF7, kind="df"
         if fixed_n is not None:
             n = np.asarray(fixed_n, dtype=np.float64)
             Hpp, J, K = _jk_hpp(C, H, ints, nact, kind)
-            return gamma, n, pnof.energy_from_jk(n, Hpp, J, K, npairs, ncwo, functional)
+            return gamma, n, pnof.energy_from_jk(n, Hpp, J, K, npairs, ncwo, functional, nsingle)
         Hpp, J, K = _jk_hpp(C, H, ints, nact, kind)
-        gamma, E, _ = optimize_on(gamma, Hpp, J, K, npairs, ncwo, functional, on_kind)
-        return gamma, on_map(gamma, npairs, ncwo, on_kind), E
+        gamma, E, _ = optimize_on(gamma, Hpp, J, K, npairs, ncwo, functional, on_kind, nsingle=nsingle)
+        return gamma, on_map(gamma, npairs, ncwo, on_kind, nsingle), E
 
     # initial step
     gamma, n, _ = occupations(C, gamma)
-    E0, lam = _lagrangian(C, n, H, ints, npairs, ncwo, functional, kind)
+    E0, lam = _lagrangian(C, n, H, ints, npairs, ncwo, functional, kind, nsingle)
     C, diag, _ = pnof.orbital_step(lam, C)
-    E_prev, lam = _lagrangian(C, n, H, ints, npairs, ncwo, functional, kind)
+    E_prev, lam = _lagrangian(C, n, H, ints, npairs, ncwo, functional, kind, nsingle)
     history = [E0, E_prev]
     crit = {}
     mats, errs = [], []
@@ -114,7 +119,7 @@ def optimize(C0, gamma0, H, ints, npairs, ncwo, functional=pnof.PNOF7, kind="df"
     it = 0
     for it in range(1, maxit + 1):
         gamma, n, E_n = occupations(C, gamma)          # E[n^{j+1}, phi^j]
-        E_fixed_orb, lam = _lagrangian(C, n, H, ints, npairs, ncwo, functional, kind)
+        E_fixed_orb, lam = _lagrangian(C, n, H, ints, npairs, ncwo, functional, kind, nsingle)
         # matrix of Eq. Fockian: off-diagonal from lambda, diagonal from the previous step
         F = pnof.fockian_offdiag(lam)
         if zeta > 0:
@@ -130,7 +135,7 @@ def optimize(C0, gamma0, H, ints, npairs, ncwo, functional=pnof.PNOF7, kind="df"
                 F = C.T @ diis_extrapolate(mats, errs) @ C
         diag, U = np.linalg.eigh(F)
         C = C @ pnof.sign_fix(U)
-        E_new, lam_new = _lagrangian(C, n, H, ints, npairs, ncwo, functional, kind)
+        E_new, lam_new = _lagrangian(C, n, H, ints, npairs, ncwo, functional, kind, nsingle)
         history.append(E_new)
         crit = {"d_n": abs(E_n - E_prev), "d_phi": abs(E_new - E_fixed_orb), "d_E": abs(E_new - E_prev),
                 "max_asym": pnof.max_asym(lam_new)}
@@ -141,6 +146,6 @@ def optimize(C0, gamma0, H, ints, npairs, ncwo, functional=pnof.PNOF7, kind="df"
             break
         if crit["d_n"] < eps_n and crit["d_phi"] < eps_phi and crit["d_E"] < eps:
             break
-    _, lam = _lagrangian(C, n, H, ints, npairs, ncwo, functional, kind)
+    _, lam = _lagrangian(C, n, H, ints, npairs, ncwo, functional, kind, nsingle)
     return {"C": C, "gamma": gamma, "n": n, "E": E_prev, "max_asym": pnof.max_asym(lam), "iterations": it,
             "converged": converged, "history": history, "criteria": crit}

@@ -75,11 +75,11 @@ class BatchIO(ctypes.Structure):
 
 class Problem(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in
-                ("nbf", "naux", "npairs", "ncwo", "functional", "precision", "ints", "flags")]
+                ("nbf", "naux", "npairs", "ncwo", "functional", "precision", "ints", "flags", "nsingle")]
 
     @property
     def nact(self) -> int:
-        return self.npairs * (self.ncwo + 1)
+        return self.npairs * (self.ncwo + 1) + self.nsingle
 
 
 _lib = None
@@ -108,8 +108,8 @@ def lib():
             "pnof_workspace_size": ([P, PP, ctypes.POINTER(ctypes.c_size_t)], S),
             "pnof_set_workspace": ([P, P, ctypes.c_size_t], S),
             "pnof_set_pchunk": ([P, I], S),
-            "pnof_on_map": ([P, I, I, I, P, P, P], S),
-            "pnof_on_map_vjp": ([P, I, I, I, P, P, P], S),
+            "pnof_on_map": ([P, I, I, I, I, P, P, P], S),
+            "pnof_on_map_vjp": ([P, I, I, I, I, P, P, P], S),
             "pnof_jk": ([P, PP, P, P, P, P, P, P, P, I], S),
             "pnof_energy": ([P, PP, P, P, P, P, P], S),
             "pnof_fock": ([P, PP, P, P, P, P, P, P, P, I], S),
@@ -137,8 +137,9 @@ def lib():
     return _lib
 
 
-def problem(nbf, naux, npairs, ncwo, functional=PNOF7, precision=FP64, ints=INTS_DF_F64, flags=0) -> Problem:
-    return Problem(nbf, naux, npairs, ncwo, functional, precision, ints, flags)
+def problem(nbf, naux, npairs, ncwo, functional=PNOF7, precision=FP64, ints=INTS_DF_F64, flags=0,
+            nsingle=0) -> Problem:
+    return Problem(nbf, naux, npairs, ncwo, functional, precision, ints, flags, nsingle)
 
 
 # ----------------------------------------------------------------------------- marshalling
@@ -241,17 +242,17 @@ class Context:
     def _f64(self, *shape):
         return torch.empty(*shape, dtype=torch.float64, device=self.device)
 
-    def on_map(self, gamma, npairs, ncwo, kind=ON_SIGMOID, jacobian=False):
-        nact = npairs * (ncwo + 1)
+    def on_map(self, gamma, npairs, ncwo, kind=ON_SIGMOID, jacobian=False, nsingle=0):
+        nact = npairs * (ncwo + 1) + nsingle
         ngam = nact if kind == ON_SIGMOID else npairs * ncwo
         n = self._f64(nact)
         jac = self._f64(nact, ngam) if jacobian else None
-        pnof_on_map(self, kind, npairs, ncwo, gamma, n, jac)
+        pnof_on_map(self, kind, npairs, ncwo, gamma, n, jac, nsingle)
         return (n, jac) if jacobian else n
 
-    def on_map_vjp(self, gamma, dEdn, npairs, ncwo, kind=ON_SIGMOID):
+    def on_map_vjp(self, gamma, dEdn, npairs, ncwo, kind=ON_SIGMOID, nsingle=0):
         out = self._f64(gamma.numel())
-        pnof_on_map_vjp(self, kind, npairs, ncwo, gamma, dEdn, out)
+        pnof_on_map_vjp(self, kind, npairs, ncwo, gamma, dEdn, out, nsingle)
         return out
 
     def jk(self, prob, C, ints, q_idx=None):
@@ -354,22 +355,23 @@ def pnof_check_problem(prob: Problem) -> int:
     return lib().pnof_check_problem(ctypes.byref(prob))
 
 
-def pnof_on_map(ctx, kind, npairs, ncwo, gamma, n, dn_dgamma=None):
-    nact = npairs * (ncwo + 1)
+def pnof_on_map(ctx, kind, npairs, ncwo, gamma, n, dn_dgamma=None, nsingle=0):
+    nact = npairs * (ncwo + 1) + nsingle
     ngam = nact if kind == ON_SIGMOID else npairs * ncwo
     _check(gamma, ngam, torch.float64, ctx.device, "gamma")
     _check(n, nact, torch.float64, ctx.device, "n")
     _check(dn_dgamma, nact * ngam, torch.float64, ctx.device, "dn_dgamma", optional=True)
-    _raise(ctx, lib().pnof_on_map(ctx.handle, kind, npairs, ncwo, _ptr(gamma), _ptr(n), _ptr(dn_dgamma)))
+    _raise(ctx, lib().pnof_on_map(ctx.handle, kind, npairs, ncwo, nsingle, _ptr(gamma), _ptr(n), _ptr(dn_dgamma)))
 
 
-def pnof_on_map_vjp(ctx, kind, npairs, ncwo, gamma, dEdn, dEdgamma):
-    nact = npairs * (ncwo + 1)
+def pnof_on_map_vjp(ctx, kind, npairs, ncwo, gamma, dEdn, dEdgamma, nsingle=0):
+    nact = npairs * (ncwo + 1) + nsingle
     ngam = nact if kind == ON_SIGMOID else npairs * ncwo
     _check(gamma, ngam, torch.float64, ctx.device, "gamma")
     _check(dEdn, nact, torch.float64, ctx.device, "dEdn")
     _check(dEdgamma, ngam, torch.float64, ctx.device, "dEdgamma")
-    _raise(ctx, lib().pnof_on_map_vjp(ctx.handle, kind, npairs, ncwo, _ptr(gamma), _ptr(dEdn), _ptr(dEdgamma)))
+    _raise(ctx, lib().pnof_on_map_vjp(ctx.handle, kind, npairs, ncwo, nsingle, _ptr(gamma), _ptr(dEdn),
+                                      _ptr(dEdgamma)))
 
 
 def _q(ctx, prob, q_idx):
@@ -453,9 +455,9 @@ class PNOFEnergy(torch.autograd.Function):
 
     @staticmethod
     def forward(fctx, C, gamma, H, ints, prob, ctx, kind=ON_SIGMOID):
-        n = ctx.on_map(gamma, prob.npairs, prob.ncwo, kind)
+        n = ctx.on_map(gamma, prob.npairs, prob.ncwo, kind, nsingle=prob.nsingle)
         out = ctx.lagrangian(prob, C, n, H, ints, grads=True)
-        dEdg = ctx.on_map_vjp(gamma, out["dEdn"], prob.npairs, prob.ncwo, kind)
+        dEdg = ctx.on_map_vjp(gamma, out["dEdn"], prob.npairs, prob.ncwo, kind, nsingle=prob.nsingle)
         fctx.save_for_backward(out["dEdC"], dEdg)
         return out["E"].reshape(())
 
@@ -467,9 +469,9 @@ class PNOFEnergy(torch.autograd.Function):
 
 def energy_and_grad(ctx, prob, C, gamma, H, ints, kind=ON_SIGMOID):
     """One energy + gradient evaluation (forward of PNOFEnergy), returning all device outputs."""
-    n = ctx.on_map(gamma, prob.npairs, prob.ncwo, kind)
+    n = ctx.on_map(gamma, prob.npairs, prob.ncwo, kind, nsingle=prob.nsingle)
     out = ctx.lagrangian(prob, C, n, H, ints, grads=True)
-    out["dEdgamma"] = ctx.on_map_vjp(gamma, out["dEdn"], prob.npairs, prob.ncwo, kind)
+    out["dEdgamma"] = ctx.on_map_vjp(gamma, out["dEdn"], prob.npairs, prob.ncwo, kind, nsingle=prob.nsingle)
     out["n"] = n
     return out
 

@@ -99,7 +99,8 @@ pnof_status check_problem(pnof_ctx ctx, const pnof_problem* p) {
   if (!p) return fail(ctx, PNOF_E_ARG, "problem is NULL");
   if (p->nbf <= 0) return fail(ctx, PNOF_E_SHAPE, "nbf must be positive");
   if (p->npairs <= 0 || p->ncwo <= 0) return fail(ctx, PNOF_E_SHAPE, "npairs and ncwo must be positive");
-  const long long nact = (long long)p->npairs * (p->ncwo + 1);
+  if (p->nsingle < 0) return fail(ctx, PNOF_E_SHAPE, "nsingle must not be negative");
+  const long long nact = (long long)p->npairs * (p->ncwo + 1) + p->nsingle;
   if (nact > p->nbf) return fail(ctx, PNOF_E_SHAPE, "npairs*(ncwo+1) exceeds nbf");
   if (p->functional != PNOF5 && p->functional != PNOF7 && p->functional != PNOF7S)
     return fail(ctx, PNOF_E_ARG, "unknown functional");
@@ -120,7 +121,7 @@ pnof_status check_problem(pnof_ctx ctx, const pnof_problem* p) {
 
 // ------------------------------------------------------------------------ planning
 struct Plan {
-  int nbf, nact, naux, npairs, ncwo, functional, prec, ints;
+  int nbf, nact, naux, npairs, ncwo, nsingle, functional, prec, ints;
   int pc, ns2, ns3, xv, yv;
   int ldk, ldx, ldxx, ldw, nact32;
   bool split;   // bf16 family
@@ -130,7 +131,8 @@ struct Plan {
 Plan make_plan(const pnof_problem* p, const pnof_tuning& tu) {
   Plan pl{};
   pl.nbf = p->nbf;
-  pl.nact = p->npairs * (p->ncwo + 1);
+  pl.nact = p->npairs * (p->ncwo + 1) + p->nsingle;
+  pl.nsingle = p->nsingle;
   pl.naux = p->naux;
   pl.npairs = p->npairs;
   pl.ncwo = p->ncwo;
@@ -311,7 +313,7 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
   const bool want_e = r.need_e;
   const bool have_n = (n != nullptr);
 
-  if (have_n) DEV_CHECK(ctx, coeffs(s, nact, pl.npairs, pl.ncwo, pl.functional, n, b.alpha, b.beta, b.beta32));
+  if (have_n) DEV_CHECK(ctx, coeffs(s, nact, pl.npairs, pl.ncwo, pl.nsingle, pl.functional, n, b.alpha, b.beta, b.beta32));
   if (H) {
     // HC = H C_A ; Hpp = diag(C_A^T H C_A)
     DEV_CHECK(ctx, gemm_f64(s, nbf, nact, nbf, 1, 1.0, H, nbf, 1, 0, C, nbf, 1, 0, 0.0, b.HC, nact, 1, 0));
@@ -428,7 +430,7 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
     if (r.asym) DEV_CHECK(ctx, max_asym(s, nbf, r.lam, b.partials + 256, r.asym));
   }
   if (r.dEdC) DEV_CHECK(ctx, grad_c(s, nbf, nact, Y, r.dEdC));
-  if (r.dEdn) DEV_CHECK(ctx, grad_n(s, nact, pl.npairs, pl.ncwo, pl.functional, n, b.Hpp, J, K, r.dEdn));
+  if (r.dEdn) DEV_CHECK(ctx, grad_n(s, nact, pl.npairs, pl.ncwo, pl.nsingle, pl.functional, n, b.Hpp, J, K, r.dEdn));
   return PNOF_OK;
 }
 
@@ -476,7 +478,7 @@ struct DevBuf {
 // E(n(gamma)) and dE/dgamma at fixed H_pp, J, K, evaluated on the device (Section 3.1).
 struct OnObjective {
   pnof_ctx ctx;
-  int kind, npairs, ncwo, nact, nbf, functional, ngam;
+  int kind, npairs, ncwo, nsingle, nact, nbf, functional, ngam;
   const double *Hpp, *J, *K;
   double *gam, *n, *alpha, *beta, *partials, *E, *dEdn, *g;
   std::vector<double> host;
@@ -485,11 +487,11 @@ struct OnObjective {
   pnof_status eval(const std::vector<double>& x, double& f, std::vector<double>& grad) {
     hipStream_t s = ctx->stream;
     DEV_CHECK(ctx, hipMemcpyAsync(gam, x.data(), sizeof(double) * ngam, hipMemcpyHostToDevice, s));
-    DEV_CHECK(ctx, on_map(s, kind, npairs, ncwo, gam, n, nullptr));
-    DEV_CHECK(ctx, coeffs(s, nact, npairs, ncwo, functional, n, alpha, beta, nullptr));
+    DEV_CHECK(ctx, on_map(s, kind, npairs, ncwo, nsingle, gam, n, nullptr));
+    DEV_CHECK(ctx, coeffs(s, nact, npairs, ncwo, nsingle, functional, n, alpha, beta, nullptr));
     DEV_CHECK(ctx, energy(s, nbf, nact, n, Hpp, alpha, beta, J, K, nullptr, nullptr, nullptr, nullptr, 0, 0, partials, E));
-    DEV_CHECK(ctx, grad_n(s, nact, npairs, ncwo, functional, n, Hpp, J, K, dEdn));
-    DEV_CHECK(ctx, on_map_vjp(s, kind, npairs, ncwo, gam, dEdn, g));
+    DEV_CHECK(ctx, grad_n(s, nact, npairs, ncwo, nsingle, functional, n, Hpp, J, K, dEdn));
+    DEV_CHECK(ctx, on_map_vjp(s, kind, npairs, ncwo, nsingle, gam, dEdn, g));
     host.resize(ngam + 1);
     DEV_CHECK(ctx, hipMemcpyAsync(host.data(), E, sizeof(double), hipMemcpyDeviceToHost, s));
     DEV_CHECK(ctx, hipMemcpyAsync(host.data() + 1, g, sizeof(double) * ngam, hipMemcpyDeviceToHost, s));
@@ -508,7 +510,8 @@ pnof_status on_objective_init(pnof_ctx ctx, DevBuf& db, const pnof_problem* prob
   o.kind = kind;
   o.npairs = prob->npairs;
   o.ncwo = prob->ncwo;
-  o.nact = prob->npairs * (prob->ncwo + 1);
+  o.nsingle = prob->nsingle;
+  o.nact = prob->npairs * (prob->ncwo + 1) + prob->nsingle;
   o.nbf = prob->nbf;
   o.functional = prob->functional;
   o.ngam = kind == 0 ? o.nact : o.npairs * o.ncwo;
@@ -651,7 +654,7 @@ struct BatchGeom {
 BatchGeom batch_geom(const pnof_problem& p) {
   BatchGeom g{};
   g.nbf = p.nbf;
-  g.nact = p.npairs * (p.ncwo + 1);
+  g.nact = p.npairs * (p.ncwo + 1) + p.nsingle;
   g.naux = p.naux;
   g.ldk = (int)round_up(g.nbf, 32);
   g.nact32 = g.ldw = (int)round_up(g.nact, 32);
@@ -857,30 +860,32 @@ pnof_status pnof_get_plan(pnof_ctx ctx, const pnof_problem* prob, pnof_tuning* o
   return PNOF_OK;
 }
 
-pnof_status pnof_on_map(pnof_ctx ctx, int32_t kind, int32_t npairs, int32_t ncwo, const double* gamma, double* n,
-                        double* dn_dgamma) {
+pnof_status pnof_on_map(pnof_ctx ctx, int32_t kind, int32_t npairs, int32_t ncwo, int32_t nsingle,
+                        const double* gamma, double* n, double* dn_dgamma) {
   if (!ctx) return fail(nullptr, PNOF_E_ARG, "context is NULL");
   if (kind != 0 && kind != 1) return fail(ctx, PNOF_E_ARG, "unknown ON map kind");
   if (npairs <= 0 || ncwo <= 0) return fail(ctx, PNOF_E_SHAPE, "npairs and ncwo must be positive");
   pnof_status st = check_ptrs(ctx, {gamma, n}, "pnof_on_map");
   if (st != PNOF_OK) return st;
   if ((st = check_ctx(ctx)) != PNOF_OK) return st;
-  const long long nact = (long long)npairs * (ncwo + 1);
+  if (nsingle < 0) return fail(ctx, PNOF_E_SHAPE, "nsingle must not be negative");
+  const long long nact = (long long)npairs * (ncwo + 1) + nsingle;
   const long long ngam = kind == 0 ? nact : (long long)npairs * ncwo;
   if (dn_dgamma) DEV_CHECK(ctx, fill_f64(ctx->stream, dn_dgamma, nact * ngam, 0.0));
-  DEV_CHECK(ctx, on_map(ctx->stream, kind, npairs, ncwo, gamma, n, dn_dgamma));
+  DEV_CHECK(ctx, on_map(ctx->stream, kind, npairs, ncwo, nsingle, gamma, n, dn_dgamma));
   return PNOF_OK;
 }
 
-pnof_status pnof_on_map_vjp(pnof_ctx ctx, int32_t kind, int32_t npairs, int32_t ncwo, const double* gamma,
-                            const double* dEdn, double* dEdgamma) {
+pnof_status pnof_on_map_vjp(pnof_ctx ctx, int32_t kind, int32_t npairs, int32_t ncwo, int32_t nsingle,
+                            const double* gamma, const double* dEdn, double* dEdgamma) {
   if (!ctx) return fail(nullptr, PNOF_E_ARG, "context is NULL");
   if (kind != 0 && kind != 1) return fail(ctx, PNOF_E_ARG, "unknown ON map kind");
   if (npairs <= 0 || ncwo <= 0) return fail(ctx, PNOF_E_SHAPE, "npairs and ncwo must be positive");
   pnof_status st = check_ptrs(ctx, {gamma, dEdn, dEdgamma}, "pnof_on_map_vjp");
   if (st != PNOF_OK) return st;
   if ((st = check_ctx(ctx)) != PNOF_OK) return st;
-  DEV_CHECK(ctx, on_map_vjp(ctx->stream, kind, npairs, ncwo, gamma, dEdn, dEdgamma));
+  if (nsingle < 0) return fail(ctx, PNOF_E_SHAPE, "nsingle must not be negative");
+  DEV_CHECK(ctx, on_map_vjp(ctx->stream, kind, npairs, ncwo, nsingle, gamma, dEdn, dEdgamma));
   return PNOF_OK;
 }
 
@@ -997,7 +1002,7 @@ pnof_status pnof_nofmp2_terms(pnof_ctx ctx, const pnof_problem* prob, const doub
   if (st != PNOF_OK) return st;
   if ((st = check_problem(ctx, prob)) != PNOF_OK) return st;
   if ((st = check_ptrs(ctx, {C, n, H, ints, E_hf, E_sta}, "pnof_nofmp2_terms")) != PNOF_OK) return st;
-  const int nact = prob->npairs * (prob->ncwo + 1);
+  const int nact = prob->npairs * (prob->ncwo + 1) + prob->nsingle;
   DevBuf db(ctx->stream);
   double* J = db.get<double>((long long)nact * nact);
   double* K = db.get<double>((long long)nact * nact);
@@ -1009,7 +1014,8 @@ pnof_status pnof_nofmp2_terms(pnof_ctx ctx, const pnof_problem* prob, const doub
   r.K = K;
   r.Hpp = Hpp;
   if ((st = run_step(ctx, prob, C, nullptr, H, ints, r)) != PNOF_OK) return st;
-  DEV_CHECK(ctx, nofmp2_terms(ctx->stream, nact, prob->npairs, prob->ncwo, n, Hpp, J, K, partials, E_hf, E_sta));
+  DEV_CHECK(ctx, nofmp2_terms(ctx->stream, nact, prob->npairs, prob->ncwo, prob->nsingle, n, Hpp, J, K, partials, E_hf,
+                              E_sta));
   return PNOF_OK;
 }
 
@@ -1021,7 +1027,7 @@ pnof_status pnof_optimize_on(pnof_ctx ctx, const pnof_problem* prob, int32_t kin
   if ((st = check_problem(ctx, prob)) != PNOF_OK) return st;
   if (kind != 0 && kind != 1) return fail(ctx, PNOF_E_ARG, "kind must be 0 (sigmoid) or 1 (trigonometric)");
   if ((st = check_ptrs(ctx, {C, H, J, K, gamma, E}, "pnof_optimize_on")) != PNOF_OK) return st;
-  const int nbf = prob->nbf, nact = prob->npairs * (prob->ncwo + 1);
+  const int nbf = prob->nbf, nact = prob->npairs * (prob->ncwo + 1) + prob->nsingle;
   DevBuf db(ctx->stream);
   double* HC = db.get<double>((long long)nbf * nact);
   double* Hpp = db.get<double>(nact);
@@ -1054,7 +1060,7 @@ pnof_status pnof_optimize(pnof_ctx ctx, const pnof_problem* prob, const double* 
   if ((st = check_ptrs(ctx, {H, ints, C, n}, "pnof_optimize")) != PNOF_OK) return st;
   if (!op.fix_n && !gamma) return fail(ctx, PNOF_E_ARG, "gamma is required unless fix_n");
   if (op.on_kind != 0 && op.on_kind != 1) return fail(ctx, PNOF_E_ARG, "on_kind must be 0 or 1");
-  const int nbf = prob->nbf, nact = prob->npairs * (prob->ncwo + 1);
+  const int nbf = prob->nbf, nact = prob->npairs * (prob->ncwo + 1) + prob->nsingle;
   const long long nn = (long long)nbf * nbf, n2 = (long long)nact * nact;
   const int maxit = op.maxit > 0 ? op.maxit : 200;
   const int ndiis = op.ndiis > 1 ? op.ndiis : 0;
@@ -1112,7 +1118,7 @@ pnof_status pnof_optimize(pnof_ctx ctx, const pnof_problem* prob, const double* 
     pnof_status st2 = run_step(ctx, &pr, C, nullptr, H, ints, r);
     if (st2 != PNOF_OK) return st2;
     if (op.fix_n) {
-      DEV_CHECK(ctx, coeffs(s, nact, pr.npairs, pr.ncwo, pr.functional, n, o.alpha, o.beta, nullptr));
+      DEV_CHECK(ctx, coeffs(s, nact, pr.npairs, pr.ncwo, pr.nsingle, pr.functional, n, o.alpha, o.beta, nullptr));
       DEV_CHECK(ctx, energy(s, nbf, nact, n, Hpp, o.alpha, o.beta, J, K, nullptr, nullptr, nullptr, nullptr, 0, 0,
                             o.partials, o.E));
       DEV_CHECK(ctx, hipMemcpyAsync(host2, o.E, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1124,7 +1130,7 @@ pnof_status pnof_optimize(pnof_ctx ctx, const pnof_problem* prob, const double* 
     st2 = lbfgs(o, gam, op.on, En, it);
     if (st2 != PNOF_OK) return st2;
     DEV_CHECK(ctx, hipMemcpyAsync(gamma, gam.data(), sizeof(double) * o.ngam, hipMemcpyHostToDevice, s));
-    DEV_CHECK(ctx, on_map(s, op.on_kind, pr.npairs, pr.ncwo, gamma, n, nullptr));
+    DEV_CHECK(ctx, on_map(s, op.on_kind, pr.npairs, pr.ncwo, pr.nsingle, gamma, n, nullptr));
     return PNOF_OK;
   };
   // diagonalise S (overwritten by the eigenvectors), new diagonal, C <- C U
@@ -1245,7 +1251,7 @@ pnof_status pnof_batch_plan(pnof_ctx ctx, int32_t ninst, const pnof_problem* pro
       b->geo.push_back(g);
       BInst& d = b->inst[i];
       d = BInst{};
-      d.nbf = g.nbf; d.nact = g.nact; d.naux = g.naux; d.npairs = p.npairs; d.ncwo = p.ncwo;
+      d.nbf = g.nbf; d.nact = g.nact; d.naux = g.naux; d.npairs = p.npairs; d.ncwo = p.ncwo; d.nsingle = p.nsingle;
       d.functional = p.functional; d.terms = b->terms;
       d.ldk = g.ldk; d.ldw = g.ldw; d.nact32 = g.nact32; d.ns2 = g.ns2; d.ns3 = g.ns3;
       const long long n2 = (long long)g.nact * g.nact, ny = (long long)g.nbf * g.nact;

@@ -13,24 +13,26 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint16_t u16;
 
 // ---------------------------------------------------------------- orbital layout
-// Strong orbital of pair g is g; weak k of pair g is npairs + ncwo*(npairs-1-g) + k.
-__host__ __device__ inline int pair_of(int p, int npairs, int ncwo) {
-  if (p < npairs) return p;
-  int w = p - npairs;
-  int blk = w / ncwo;
+// Strong orbital of pair g is g; the nsingle singly occupied orbitals (Omega_I) follow, each its own
+// subspace; weak k of pair g is npairs + nsingle + ncwo*(npairs-1-g) + k.
+__host__ __device__ inline int pair_of(int p, int npairs, int ncwo, int nsingle) {
+  if (p < npairs + nsingle) return p;
+  const int blk = (p - npairs - nsingle) / ncwo;
   return (blk < npairs) ? (npairs - 1 - blk) : -1;
 }
-__host__ __device__ inline int weak_index(int g, int k, int npairs, int ncwo) {
-  return npairs + ncwo * (npairs - 1 - g) + k;
+__host__ __device__ inline bool is_single(int p, int npairs, int nsingle) { return p >= npairs && p < npairs + nsingle; }
+__host__ __device__ inline int weak_index(int g, int k, int npairs, int ncwo, int nsingle) {
+  return npairs + nsingle + ncwo * (npairs - 1 - g) + k;
 }
 
 // ---------------------------------------------------------------- PNOF coefficients
 // alpha_pq, beta_pq of E_2 = sum_pq alpha_pq J_pq + beta_pq K_pq (Eqs. Eg, Efg, Efg_s).
-__device__ inline void pnof_coeff(int p, int q, double np_, double nq, int npairs, int ncwo, int functional,
-                                  double& a, double& b) {
+// A singly occupied orbital has no intra-subspace term (beta_pp = 0).
+__device__ inline void pnof_coeff(int p, int q, double np_, double nq, int npairs, int ncwo, int nsingle,
+                                  int functional, double& a, double& b) {
   a = 0.0;
-  if (pair_of(p, npairs, ncwo) == pair_of(q, npairs, ncwo)) {
-    if (p == q) b = np_;
+  if (pair_of(p, npairs, ncwo, nsingle) == pair_of(q, npairs, ncwo, nsingle)) {
+    if (p == q) b = is_single(p, npairs, nsingle) ? 0.0 : np_;
     else {
       const double s = sqrt(np_ * nq);
       b = (p < npairs || q < npairs) ? -s : s;
@@ -45,8 +47,8 @@ __device__ inline void pnof_coeff(int p, int q, double np_, double nq, int npair
 
 // Term q != p of dE/dn_p at fixed J, K (derivative of Eqs. Eg, Efg); php = sqrt(n_p (1 - n_p)).
 __device__ inline double grad_n_term(int p, int q, double np_, double nq, double php, double jpq, double kpq,
-                                     int npairs, int ncwo, int functional) {
-  if (pair_of(q, npairs, ncwo) == pair_of(p, npairs, ncwo)) {
+                                     int npairs, int ncwo, int nsingle, int functional) {
+  if (pair_of(q, npairs, ncwo, nsingle) == pair_of(p, npairs, ncwo, nsingle)) {
     const double sg = (p < npairs || q < npairs) ? -1.0 : 1.0;
     return sg * sqrt(nq / np_) * kpq;
   }
@@ -202,7 +204,7 @@ hipError_t df_bf16_gemm3(hipStream_t s, int nbf, int nact, int np, int nsplit, i
 // One instance of a batch: sizes, the caller's inputs and outputs, and its slices of the batch
 // workspace.  Leading dimensions: ldk = ldx = round_up(nbf, 32), ldw = nact32 = round_up(nact, 32).
 struct BInst {
-  int nbf, nact, naux, npairs, ncwo, functional, terms;
+  int nbf, nact, naux, npairs, ncwo, nsingle, functional, terms;
   int ldk, ldw, nact32, ns2, ns3;
   const double* C;
   const double* n;
@@ -235,7 +237,7 @@ hipError_t batch_finish(hipStream_t s, int ninst, const BInst* tab, const BMax& 
 // ---------------------------------------------------------------- small kernels (k_small.hip)
 hipError_t fill_f64(hipStream_t s, double* p, long long n, double v);
 hipError_t fill_u16(hipStream_t s, u16* p, long long n, u16 v);
-hipError_t coeffs(hipStream_t s, int nact, int npairs, int ncwo, int functional, const double* n,
+hipError_t coeffs(hipStream_t s, int nact, int npairs, int ncwo, int nsingle, int functional, const double* n,
                   double* alpha, double* beta, float* beta32);
 hipError_t transpose_ca(hipStream_t s, int nbf, int nact, const double* C, double* Ct, int ldk);
 hipError_t split_ca(hipStream_t s, int nbf, int nact, int terms, const double* C, u16* Ct_hi,
@@ -260,18 +262,18 @@ hipError_t assemble_y(hipStream_t s, int nbf, int nact, const double* n, const d
 hipError_t grad_c(hipStream_t s, int nbf, int nact, const double* Y, double* dEdC);
 hipError_t zero_cols(hipStream_t s, int nbf, int col0, double* M);
 hipError_t max_asym(hipStream_t s, int nbf, const double* lam, double* partials, double* out);
-hipError_t grad_n(hipStream_t s, int nact, int npairs, int ncwo, int functional, const double* n,
+hipError_t grad_n(hipStream_t s, int nact, int npairs, int ncwo, int nsingle, int functional, const double* n,
                   const double* Hpp, const double* J, const double* K, double* dEdn);
-hipError_t on_map(hipStream_t s, int kind, int npairs, int ncwo, const double* gamma, double* n,
+hipError_t on_map(hipStream_t s, int kind, int npairs, int ncwo, int nsingle, const double* gamma, double* n,
                   double* jac);
-hipError_t on_map_vjp(hipStream_t s, int kind, int npairs, int ncwo, const double* gamma,
+hipError_t on_map_vjp(hipStream_t s, int kind, int npairs, int ncwo, int nsingle, const double* gamma,
                       const double* dEdn, double* dEdgamma);
 hipError_t build_s(hipStream_t s, int nbf, const double* lam, const double* diag_prev, double zeta,
                    double* S);
 hipError_t sign_fix_cols(hipStream_t s, int nbf, double* Ucm);
 hipError_t offdiag_copy(hipStream_t s, int nbf, const double* src, double* dst);
 // E_hf and E_sta (device scalars) from n, H_pp, J, K; partials: 256 doubles of scratch.
-hipError_t nofmp2_terms(hipStream_t s, int nact, int npairs, int ncwo, const double* n, const double* Hpp,
+hipError_t nofmp2_terms(hipStream_t s, int nact, int npairs, int ncwo, int nsingle, const double* n, const double* Hpp,
                         const double* J, const double* K, double* partials, double* E_hf, double* E_sta);
 hipError_t count_nonfinite(hipStream_t s, const void* p, long long n, int is_bf16, int* flag);
 // explicit four-index integrals (nbf <= 64)

@@ -53,7 +53,7 @@ __global__ void prep_k(const BInst* __restrict__ tab) {
   INST_STRIDE(i, n2) {
     const int p = (int)(i / nact), q = (int)(i % nact);
     double a, b;
-    pnof_coeff(p, q, d.n[p], d.n[q], d.npairs, d.ncwo, d.functional, a, b);
+    pnof_coeff(p, q, d.n[p], d.n[q], d.npairs, d.ncwo, d.nsingle, d.functional, a, b);
     d.alpha[i] = a;
     d.beta[i] = b;
     d.beta32[i] = (float)b;
@@ -209,10 +209,11 @@ __global__ void finish_k(const BInst* __restrict__ tab) {
     for (int q = lane; q < nact; q += 64) {
       if (q == p) continue;
       s += grad_n_term(p, q, np_, d.n[q], php, d.J[(long long)p * nact + q], d.K[(long long)p * nact + q], d.npairs,
-                       d.ncwo, d.functional);
+                       d.ncwo, d.nsingle, d.functional);
     }
     for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-    if (lane == 0) d.dEdn[p] = 2.0 * d.Hpp[p] + d.K[(long long)p * nact + p] + s;
+    if (lane == 0)
+      d.dEdn[p] = 2.0 * d.Hpp[p] + (is_single(p, d.npairs, d.nsingle) ? 0.0 : d.K[(long long)p * nact + p]) + s;
   }
 }
 

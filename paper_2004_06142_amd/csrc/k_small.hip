@@ -1,4 +1,6 @@
 // Element-wise, reduction and small-matrix kernels of the PNOF step (float64 throughout).
+#include <algorithm>
+
 #include "common.h"
 
 namespace pnof {
@@ -20,12 +22,12 @@ __global__ void fill_f64_k(double* p, long long n, double v) { GRID_STRIDE(i, n)
 __global__ void fill_u16_k(u16* p, long long n, u16 v) { GRID_STRIDE(i, n) p[i] = v; }
 
 // alpha, beta of E_2 = sum_pq alpha_pq J_pq + beta_pq K_pq (Eqs. Eg, Efg, Efg_s).
-__global__ void coeffs_k(int nact, int npairs, int ncwo, int functional, const double* __restrict__ n,
+__global__ void coeffs_k(int nact, int npairs, int ncwo, int nsingle, int functional, const double* __restrict__ n,
                          double* __restrict__ alpha, double* __restrict__ beta, float* __restrict__ beta32) {
   GRID_STRIDE(i, (long long)nact * nact) {
     const int p = (int)(i / nact), q = (int)(i % nact);
     double a, b;
-    pnof_coeff(p, q, n[p], n[q], npairs, ncwo, functional, a, b);
+    pnof_coeff(p, q, n[p], n[q], npairs, ncwo, nsingle, functional, a, b);
     alpha[i] = a;
     beta[i] = b;
     if (beta32) beta32[i] = (float)b;
@@ -163,27 +165,33 @@ __global__ void sum_partials_k(int nparts, const double* __restrict__ partials, 
 }
 
 // NOF-MP2 reference terms (Eqs. HFL, Esta): block partial sums of E_hf and E_sta over a fixed
-// range of the index space [0, npairs) + [0, nact^2); stage 2 adds the partials in order.
-__global__ void nofmp2_stage1_k(int nact, int npairs, int ncwo, const double* __restrict__ n,
+// range of the index space [0, nom) + [0, nom^2) + [0, nact^2), nom = npairs + nsingle (the
+// subspace-defining orbitals, weight A = 1 strong, 1/2 single); stage 2 adds the partials in order.
+__global__ void nofmp2_stage1_k(int nact, int npairs, int ncwo, int nsingle, const double* __restrict__ n,
                                 const double* __restrict__ Hpp, const double* __restrict__ J,
                                 const double* __restrict__ K, double* __restrict__ partials) {
   const long long n2 = (long long)nact * nact;
-  const long long total = npairs + (long long)npairs * npairs + n2;
+  const int nom = npairs + nsingle;
+  const long long total = nom + (long long)nom * nom + n2;
   const long long per = (total + gridDim.x - 1) / gridDim.x;
   const long long b0 = blockIdx.x * per, b1 = min(total, b0 + per);
   double hf = 0.0, sta = 0.0;
   for (long long i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
-    if (i < npairs) hf += 2.0 * Hpp[i];
-    else if (i < npairs + (long long)npairs * npairs) {
-      const long long k = i - npairs;
-      const int f = (int)(k / npairs), g = (int)(k % npairs);
-      hf += 2.0 * J[(long long)f * nact + g] - K[(long long)f * nact + g];
+    if (i < nom) {
+      const int g = (int)i;
+      // 2 A_g H_gg, and minus the self-Coulomb J_gg / 4 of a single orbital
+      hf += g < npairs ? 2.0 * Hpp[g] : Hpp[g] - 0.25 * J[(long long)g * nact + g];
+    } else if (i < nom + (long long)nom * nom) {
+      const long long k = i - nom;
+      const int f = (int)(k / nom), g = (int)(k % nom);
+      const double af = f < npairs ? 1.0 : 0.5, ag = g < npairs ? 1.0 : 0.5;
+      hf += af * ag * (2.0 * J[(long long)f * nact + g] - K[(long long)f * nact + g]);
     } else {
-      const long long k = i - npairs - (long long)npairs * npairs;
+      const long long k = i - nom - (long long)nom * nom;
       const int p = (int)(k / nact), q = (int)(k % nact);
       if (p == q) continue;
       const double np_ = n[p], nq = n[q];
-      if (pair_of(p, npairs, ncwo) == pair_of(q, npairs, ncwo)) {
+      if (pair_of(p, npairs, ncwo, nsingle) == pair_of(q, npairs, ncwo, nsingle)) {
         const double lp = 1.0 - fabs(1.0 - 2.0 * np_), lq = 1.0 - fabs(1.0 - 2.0 * nq);
         const double sg = (p < npairs || q < npairs) ? -1.0 : 1.0;
         sta += sqrt(lp * lq) * sg * sqrt(np_ * nq) * K[k];
@@ -270,7 +278,7 @@ __global__ void max_partials_k(int nparts, const double* __restrict__ partials, 
 }
 
 // dE/dn_p (derivative of Eqs. Eg, Efg at fixed J, K, H_pp): one wavefront per orbital.
-__global__ void grad_n_k(int nact, int npairs, int ncwo, int functional, const double* __restrict__ n,
+__global__ void grad_n_k(int nact, int npairs, int ncwo, int nsingle, int functional, const double* __restrict__ n,
                          const double* __restrict__ Hpp, const double* __restrict__ J,
                          const double* __restrict__ K, double* __restrict__ g) {
   const int p = blockIdx.x, lane = threadIdx.x;
@@ -280,31 +288,34 @@ __global__ void grad_n_k(int nact, int npairs, int ncwo, int functional, const d
   for (int q = lane; q < nact; q += 64) {
     if (q == p) continue;
     s += grad_n_term(p, q, np_, n[q], php, J[(long long)p * nact + q], K[(long long)p * nact + q], npairs, ncwo,
-                     functional);
+                     nsingle, functional);
   }
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-  if (lane == 0) g[p] = 2.0 * Hpp[p] + K[(long long)p * nact + p] + s;
+  // a singly occupied orbital has no K_pp term (beta_pp = 0); its n is fixed at 1/2
+  if (lane == 0) g[p] = 2.0 * Hpp[p] + (is_single(p, npairs, nsingle) ? 0.0 : K[(long long)p * nact + p]) + s;
 }
 
 __device__ inline double sigm(double x) { return 1.0 / (1.0 + exp(-x)); }
 
-// ON maps, one thread per pair (Section 3.1).
-__global__ void on_map_k(int kind, int npairs, int ncwo, const double* __restrict__ gamma,
+// ON maps, one thread per pair (Section 3.1); singly occupied orbitals get n = 1/2 (their rows of
+// the Jacobian stay zero).
+__global__ void on_map_k(int kind, int npairs, int ncwo, int nsingle, const double* __restrict__ gamma,
                          double* __restrict__ n, double* __restrict__ jac) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < nsingle) n[npairs + g] = 0.5;
   if (g >= npairs) return;
-  const int nact = npairs * (ncwo + 1);
+  const int nact = npairs * (ncwo + 1) + nsingle;
   const int ngam = kind == 0 ? nact : npairs * ncwo;
   if (kind == 0) {
     double S = sigm(gamma[g]);
-    for (int k = 0; k < ncwo; ++k) S += sigm(gamma[weak_index(g, k, npairs, ncwo)]);
+    for (int k = 0; k < ncwo; ++k) S += sigm(gamma[weak_index(g, k, npairs, ncwo, nsingle)]);
     for (int a = -1; a < ncwo; ++a) {
-      const int p = a < 0 ? g : weak_index(g, a, npairs, ncwo);
+      const int p = a < 0 ? g : weak_index(g, a, npairs, ncwo, nsingle);
       const double sp = sigm(gamma[p]);
       n[p] = sp / S;
       if (jac) {
         for (int b = -1; b < ncwo; ++b) {
-          const int r = b < 0 ? g : weak_index(g, b, npairs, ncwo);
+          const int r = b < 0 ? g : weak_index(g, b, npairs, ncwo, nsingle);
           const double sr = sigm(gamma[r]);
           const double dsr = sr * (1.0 - sr);
           jac[(long long)p * ngam + r] = ((p == r ? dsr : 0.0) * S - sp * dsr) / (S * S);
@@ -319,7 +330,7 @@ __global__ void on_map_k(int kind, int npairs, int ncwo, const double* __restric
     if (jac) jac[(long long)g * ngam + g] = -cg * sg;
     double prod = 1.0;
     for (int i = 0; i < ncwo; ++i) {
-      const int p = weak_index(g, i, npairs, ncwo);
+      const int p = weak_index(g, i, npairs, ncwo, nsingle);
       const bool last = (i == ncwo - 1);
       const double gi = last ? 0.0 : gamma[npairs + g * (ncwo - 1) + i];
       const double si2 = last ? 1.0 : sin(gi) * sin(gi);
@@ -344,22 +355,24 @@ __global__ void on_map_k(int kind, int npairs, int ncwo, const double* __restric
   }
 }
 
-// dE/dgamma = (dn/dgamma)^T dE/dn, pair by pair.
-__global__ void on_map_vjp_k(int kind, int npairs, int ncwo, const double* __restrict__ gamma,
+// dE/dgamma = (dn/dgamma)^T dE/dn, pair by pair (the sigmoid variables of singly occupied orbitals
+// do not enter: zero).
+__global__ void on_map_vjp_k(int kind, int npairs, int ncwo, int nsingle, const double* __restrict__ gamma,
                              const double* __restrict__ dEdn, double* __restrict__ out) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (kind == 0 && g < nsingle) out[npairs + g] = 0.0;
   if (g >= npairs) return;
   if (kind == 0) {
     double S = sigm(gamma[g]);
-    for (int k = 0; k < ncwo; ++k) S += sigm(gamma[weak_index(g, k, npairs, ncwo)]);
+    for (int k = 0; k < ncwo; ++k) S += sigm(gamma[weak_index(g, k, npairs, ncwo, nsingle)]);
     // dE/dgamma_r = s'_r / S * (dEdn_r - sum_p n_p dEdn_p)
     double avg = 0.0;
     for (int a = -1; a < ncwo; ++a) {
-      const int p = a < 0 ? g : weak_index(g, a, npairs, ncwo);
+      const int p = a < 0 ? g : weak_index(g, a, npairs, ncwo, nsingle);
       avg += sigm(gamma[p]) / S * dEdn[p];
     }
     for (int b = -1; b < ncwo; ++b) {
-      const int r = b < 0 ? g : weak_index(g, b, npairs, ncwo);
+      const int r = b < 0 ? g : weak_index(g, b, npairs, ncwo, nsingle);
       const double sr = sigm(gamma[r]);
       out[r] = sr * (1.0 - sr) / S * (dEdn[r] - avg);
     }
@@ -376,7 +389,7 @@ __global__ void on_map_vjp_k(int kind, int npairs, int ncwo, const double* __res
       const bool last = (i == ncwo - 1);
       const double si = last ? 0.0 : sin(gamma[base + i]);
       const double fi = last ? 1.0 : si * si;
-      acc_g += dh * prod * fi * dEdn[weak_index(g, i, npairs, ncwo)];
+      acc_g += dh * prod * fi * dEdn[weak_index(g, i, npairs, ncwo, nsingle)];
       if (!last) { const double ci = cos(gamma[base + i]); prod *= ci * ci; }
     }
     out[g] = acc_g;
@@ -397,7 +410,7 @@ __global__ void on_map_vjp_k(int kind, int npairs, int ncwo, const double* __res
           const double si = last ? 0.0 : sin(gamma[base + i]);
           d = other * (-2.0 * cj * sj) * (last ? 1.0 : si * si);  // d(c_j^2) * f_i
         }
-        sum += d * dEdn[weak_index(g, i, npairs, ncwo)];
+        sum += d * dEdn[weak_index(g, i, npairs, ncwo, nsingle)];
       }
       out[base + j] = sum;
     }
@@ -641,9 +654,10 @@ hipError_t fill_u16(hipStream_t s, u16* p, long long n, u16 v) {
   if (n <= 0) return hipSuccess;
   LAUNCH(fill_u16_k, grid1(n), dim3(NT), p, n, v);
 }
-hipError_t coeffs(hipStream_t s, int nact, int npairs, int ncwo, int functional, const double* n,
+hipError_t coeffs(hipStream_t s, int nact, int npairs, int ncwo, int nsingle, int functional, const double* n,
                   double* alpha, double* beta, float* beta32) {
-  LAUNCH(coeffs_k, grid1((long long)nact * nact), dim3(NT), nact, npairs, ncwo, functional, n, alpha, beta, beta32);
+  LAUNCH(coeffs_k, grid1((long long)nact * nact), dim3(NT), nact, npairs, ncwo, nsingle, functional, n, alpha, beta,
+         beta32);
 }
 hipError_t transpose_ca(hipStream_t s, int nbf, int nact, const double* C, double* Ct, int ldk) {
   LAUNCH(transpose_ca_k, grid1((long long)nbf * nact), dim3(NT), nbf, nact, C, Ct, ldk);
@@ -672,10 +686,11 @@ hipError_t add_diag_bf16(hipStream_t s, int nact, int np, const double* Dc, cons
   if (e != hipSuccess) return e;
   LAUNCH(add_diag_bf16_k, grid1((long long)np * nact), dim3(NT), nact, np, dbuf, Wh, Wl, ldw, pstride);
 }
-hipError_t nofmp2_terms(hipStream_t s, int nact, int npairs, int ncwo, const double* n, const double* Hpp,
-                        const double* J, const double* K, double* partials, double* E_hf, double* E_sta) {
+hipError_t nofmp2_terms(hipStream_t s, int nact, int npairs, int ncwo, int nsingle, const double* n,
+                        const double* Hpp, const double* J, const double* K, double* partials, double* E_hf,
+                        double* E_sta) {
   const int nb = 128;   // partials holds 2 * nb doubles
-  hipLaunchKernelGGL(nofmp2_stage1_k, dim3(nb), dim3(NT), 0, s, nact, npairs, ncwo, n, Hpp, J, K, partials);
+  hipLaunchKernelGGL(nofmp2_stage1_k, dim3(nb), dim3(NT), 0, s, nact, npairs, ncwo, nsingle, n, Hpp, J, K, partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   LAUNCH(sum2_partials_k, dim3(1), dim3(NT), nb, partials, E_hf, E_sta);
@@ -721,16 +736,18 @@ hipError_t max_asym(hipStream_t s, int nbf, const double* lam, double* partials,
   if (e != hipSuccess) return e;
   LAUNCH(max_partials_k, dim3(1), dim3(NT), nb, partials, out);
 }
-hipError_t grad_n(hipStream_t s, int nact, int npairs, int ncwo, int functional, const double* n,
+hipError_t grad_n(hipStream_t s, int nact, int npairs, int ncwo, int nsingle, int functional, const double* n,
                   const double* Hpp, const double* J, const double* K, double* dEdn) {
-  LAUNCH(grad_n_k, dim3(nact), dim3(64), nact, npairs, ncwo, functional, n, Hpp, J, K, dEdn);
+  LAUNCH(grad_n_k, dim3(nact), dim3(64), nact, npairs, ncwo, nsingle, functional, n, Hpp, J, K, dEdn);
 }
-hipError_t on_map(hipStream_t s, int kind, int npairs, int ncwo, const double* gamma, double* n, double* jac) {
-  LAUNCH(on_map_k, dim3(cdiv(npairs, 64)), dim3(64), kind, npairs, ncwo, gamma, n, jac);
+hipError_t on_map(hipStream_t s, int kind, int npairs, int ncwo, int nsingle, const double* gamma, double* n,
+                  double* jac) {
+  LAUNCH(on_map_k, dim3(cdiv(std::max(npairs, nsingle), 64)), dim3(64), kind, npairs, ncwo, nsingle, gamma, n, jac);
 }
-hipError_t on_map_vjp(hipStream_t s, int kind, int npairs, int ncwo, const double* gamma, const double* dEdn,
-                      double* out) {
-  LAUNCH(on_map_vjp_k, dim3(cdiv(npairs, 64)), dim3(64), kind, npairs, ncwo, gamma, dEdn, out);
+hipError_t on_map_vjp(hipStream_t s, int kind, int npairs, int ncwo, int nsingle, const double* gamma,
+                      const double* dEdn, double* out) {
+  LAUNCH(on_map_vjp_k, dim3(cdiv(std::max(npairs, nsingle), 64)), dim3(64), kind, npairs, ncwo, nsingle, gamma, dEdn,
+         out);
 }
 hipError_t build_s(hipStream_t s, int nbf, const double* lam, const double* dprev, double zeta, double* S) {
   LAUNCH(build_s_k, grid1((long long)nbf * nbf), dim3(NT), nbf, lam, dprev, zeta, S);
