@@ -1355,7 +1355,7 @@ pnof_status pnof_batch_bind(pnof_batch b, const pnof_batch_io* io) {
     g3[i] = G3Args{g.nbf, g.nact, g.naux, g.ns3, d.xth, d.xtl, g.ldk, d.wh, d.wl, g.ldw, d.Ypart, wd};
     off[i + 1] = off[i] + g1_items(g1[i], 128, true);
     off[(n + 1) + i + 1] = off[(n + 1) + i] + g2_items(g2[i]);
-    off[2 * (n + 1) + i + 1] = off[2 * (n + 1) + i] + g3_items(g3[i]);
+    off[2 * (n + 1) + i + 1] = off[2 * (n + 1) + i] + g3_items(g3[i], 128);
     f[i] = F64Gemm{g.nbf, g.nact, g.nbf, 1.0, d.H, g.nbf, 1, d.C, g.nbf, 1, 0.0, d.HC, g.nact, 1};
     f[n + i] = F64Gemm{g.naux, g.nact, g.nact, 1.0, d.D, g.nact, 1, d.alpha, g.nact, 1, 0.0, d.dbuf, g.nact, 1};
     f[2 * n + i] = F64Gemm{g.nact, g.nact, g.naux, 1.0, d.D, 1, g.nact, d.D, g.nact, 1, 0.0, d.J, g.nact, 1};

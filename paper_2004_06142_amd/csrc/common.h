@@ -182,7 +182,9 @@ __host__ __device__ inline int g2_items(const G2Args& a) {
   const int t = cdiv(a.nact, 128);
   return a.nsplit * t * (t + 1) / 2;
 }
-__host__ __device__ inline int g3_items(const G3Args& a) { return a.nsplit * cdiv(a.nbf, 128) * cdiv(a.nact, 128); }
+// g3m: the block tile along mu (128, or 256 for the wide variant); the launch grid and the kernel's
+// decoding of its block index must use the same value.
+__host__ __device__ inline int g3_items(const G3Args& a, int g3m) { return a.nsplit * cdiv(a.nbf, g3m) * cdiv(a.nact, 128); }
 
 // Grouped launches over the instances of a batch: tab[i] are the arguments of instance i (device
 // memory), off[i] the first work item of instance i (off[ninst] = total).  terms as above;

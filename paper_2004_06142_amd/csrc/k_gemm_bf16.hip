@@ -713,7 +713,7 @@ __global__ __launch_bounds__(256, 1) void gemm2_kernel(G2Args g) {
 }
 template <int TERMS, int G3M, int MINB, bool VEC>
 __global__ __launch_bounds__(256, MINB) void gemm3_kernel(G3Args g) {
-  const int w = xcd_item(g3_items(g));
+  const int w = xcd_item(g3_items(g, G3M));
   if (w < 0) return;
   gemm3_body<TERMS, G3M, VEC>(w, g);
 }
@@ -802,7 +802,7 @@ hipError_t df_bf16_gemm2(hipStream_t s, int nbf, int nact, int np, int nsplit, i
 
 template <int TERMS, int G3M, int MINB>
 static void launch_g3(hipStream_t s, const G3Args& g) {
-  const dim3 grid = xcd_grid((long long)g.nsplit * cdiv(g.nbf, G3M) * cdiv(g.nact, T2));
+  const dim3 grid = xcd_grid(g3_items(g, G3M));
   const bool vec = (g.ldx % 32 == 0) && (g.ldw % 32 == 0) && al16(g.xt_hi) && (!g.xt_lo || al16(g.xt_lo)) &&
                    al16(g.w_hi) && (!g.w_lo || al16(g.w_lo));
   if (vec) hipLaunchKernelGGL((gemm3_kernel<TERMS, G3M, MINB, true>), grid, dim3(256), 0, s, g);
