@@ -17,7 +17,8 @@ from typing import Optional
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "libpnof.so")
+# PNOF_LIBRARY selects another build of the same library (e.g. a debug or variant build)
+_LIB_PATH = os.environ.get("PNOF_LIBRARY") or os.path.join(_HERE, "libpnof.so")
 
 PNOF5, PNOF7, PNOF7S = 5, 7, 8
 FP64, BF16, BF16_SPLIT = 0, 2, 3

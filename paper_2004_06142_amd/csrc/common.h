@@ -72,6 +72,19 @@ __device__ __forceinline__ void split_f32(float x, u16& hi, u16& lo) {
   hi = f32_to_bf16_bits(x);
   lo = f32_to_bf16_bits(x - bf16_bits_to_f32(hi));
 }
+// Two floats to bf16 with the hardware round-to-nearest-even conversion (v_cvt_pk_bf16_f32):
+// packed pair, first value in the low half.
+__device__ __forceinline__ uint32_t cvt2_bf16(float a, float b) {
+  typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+  const bf2 v = {(__bf16)a, (__bf16)b};
+  return __builtin_bit_cast(uint32_t, v);
+}
+// hi/lo split of two floats (as split_f32), as packed pairs.
+__device__ __forceinline__ void split2_f32(float a, float b, uint32_t& hi, uint32_t& lo) {
+  hi = cvt2_bf16(a, b);
+  lo = cvt2_bf16(a - __uint_as_float(hi << 16), b - __uint_as_float(hi & 0xFFFF0000u));
+}
+
 __device__ __forceinline__ void split_f64(double x, u16& hi, u16& lo) {
   hi = f32_to_bf16_bits((float)x);
   lo = f32_to_bf16_bits((float)(x - (double)bf16_bits_to_f32(hi)));

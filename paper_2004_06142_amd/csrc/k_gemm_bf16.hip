@@ -567,53 +567,51 @@ __device__ __forceinline__ void gemm2_body(int w, const G2Args& g) {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int jn = 0; jn < 4; ++jn)
+      for (int jn = 0; jn < 4; ++jn) {
+        const int p0 = m0 + row_of<T2>(i, 0), q = n0 + col_of<T2>(jn);
+        float wv[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int p = m0 + row_of<T2>(i, j), q = n0 + col_of<T2>(jn);
           const float b = a[i][jn][j];
           kacc[i][jn][j] += b * b;
-          if (p < nact && q < nact) {
-            const float wv = b * bet[i][jn][j];
-            u16 h, l;
-            if (!LO) { h = f32_to_bf16_bits(wv); l = 0; }
-            else split_f32(wv, h, l);
-            Wh[(long long)p * ldw + q] = h;
-            if (LO) Wl[(long long)p * ldw + q] = l;
-            if (diag && p == q) g.Dc[(long long)P * nact + p] = (double)b;
-          }
+          wv[j] = b * bet[i][jn][j];
         }
-    if (!diag) {
-      // mirror W_qp = W_pq: the four components of acc[i][jn] are consecutive p of one q
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int jn = 0; jn < 4; ++jn) {
-          const int p = m0 + row_of<T2>(i, 0), q = n0 + col_of<T2>(jn);
-          if (q >= nact || p >= nact) continue;
-          u16 h[4], l[4];
+        uint32_t h01, h23, l01 = 0, l23 = 0;
+        if constexpr (LO) {
+          split2_f32(wv[0], wv[1], h01, l01);
+          split2_f32(wv[2], wv[3], h23, l23);
+        } else {
+          h01 = cvt2_bf16(wv[0], wv[1]);
+          h23 = cvt2_bf16(wv[2], wv[3]);
+        }
+        if (q < nact) {
+          const u16 hv[4] = {(u16)h01, (u16)(h01 >> 16), (u16)h23, (u16)(h23 >> 16)};
+          const u16 lv[4] = {(u16)l01, (u16)(l01 >> 16), (u16)l23, (u16)(l23 >> 16)};
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            const float wv = p + j < nact ? a[i][jn][j] * bet[i][jn][j] : 0.f;
-            if (!LO) { h[j] = f32_to_bf16_bits(wv); l[j] = 0; }
-            else split_f32(wv, h[j], l[j]);
+            const int p = p0 + j;
+            if (p < nact) {
+              Wh[(long long)p * ldw + q] = hv[j];
+              if (LO) Wl[(long long)p * ldw + q] = lv[j];
+              if (diag && p == q) g.Dc[(long long)P * nact + p] = (double)a[i][jn][j];
+            }
           }
-          // p % 4 == 0 and ldw % 4 == 0: the four entries W[q][p..p+3] (p + 3 < ldw) are one 8-byte word
-          const long long o = (long long)q * ldw + p;
-          if ((ldw & 3) == 0) {
-            *reinterpret_cast<uint2*>(Wh + o) = uint2{h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16)};
-            if (LO)
-              *reinterpret_cast<uint2*>(Wl + o) = uint2{l[0] | ((uint32_t)l[1] << 16), l[2] | ((uint32_t)l[3] << 16)};
-          } else {
+          if (!diag && p0 < nact) {
+            const long long o = (long long)q * ldw + p0;
+            if ((ldw & 3) == 0) {
+              *reinterpret_cast<uint2*>(Wh + o) = uint2{h01, h23};
+              if (LO) *reinterpret_cast<uint2*>(Wl + o) = uint2{l01, l23};
+            } else {
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-              if (p + j < nact) {
-                Wh[o + j] = h[j];
-                if (LO) Wl[o + j] = l[j];
-              }
+              for (int j = 0; j < 4; ++j)
+                if (p0 + j < nact) {
+                  Wh[o + j] = hv[j];
+                  if (LO) Wl[o + j] = lv[j];
+                }
+            }
           }
         }
-    }
+      }
   };
   if constexpr (VEC) {
     constexpr int S = ring_depth(T2, T2, LO, LO, 163840);
