@@ -84,8 +84,8 @@ def traffic(kname, prec, plan):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported in this build "
-              "(the aux-index sharding across GPUs is a design note, not code).", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(sharding the auxiliary index across GPUs is described, not implemented).", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
