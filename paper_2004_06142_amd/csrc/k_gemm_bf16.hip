@@ -202,48 +202,46 @@ __device__ __forceinline__ void mainloop(Stage<BM, BN, ALO, BLO>& sm, int nseg, 
   store(0);
   __syncthreads();
   if (RESET) zero(acc);
-  int seg = 0, kt = 0;
-  for (int it = 0; it < total; ++it) {
-    const int buf = it & 1;
-    const bool more = it + 1 < total;
-    if (more) load();
-    bf16x8 ah[MI], bh[NI];
+  int it = 0;
+  for (int seg = 0; seg < nseg; ++seg) {
+    for (int kt = 0; kt < KT; ++kt, ++it) {
+      const int buf = it & 1;
+      const bool more = it + 1 < total;
+      if (more) load();
+      bf16x8 ah[MI], bh[NI];
 #pragma unroll
-    for (int i = 0; i < MI; ++i) ah[i] = frag<BM>(sm.a[buf][0], ACOL, wm + 16 * i);
+      for (int i = 0; i < MI; ++i) ah[i] = frag<BM>(sm.a[buf][0], ACOL, wm + 16 * i);
 #pragma unroll
-    for (int j = 0; j < NI; ++j) bh[j] = frag<BN>(sm.b[buf][0], BCOL, wn + 16 * j);
-#pragma unroll
-    for (int i = 0; i < MI; ++i)
-#pragma unroll
-      for (int j = 0; j < NI; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-    if (BLO) {
-      bf16x8 bl[NI];
-#pragma unroll
-      for (int j = 0; j < NI; ++j) bl[j] = frag<BN>(sm.b[buf][BLO ? 1 : 0], BCOL, wn + 16 * j);
+      for (int j = 0; j < NI; ++j) bh[j] = frag<BN>(sm.b[buf][0], BCOL, wn + 16 * j);
 #pragma unroll
       for (int i = 0; i < MI; ++i)
 #pragma unroll
         for (int j = 0; j < NI; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-    }
-    if (ALO) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+      if (BLO) {
+        bf16x8 bl[NI];
 #pragma unroll
-      for (int i = 0; i < MI; ++i) {
-        const bf16x8 al = frag<BM>(sm.a[buf][ALO ? 1 : 0], ACOL, wm + 16 * i);
+        for (int j = 0; j < NI; ++j) bl[j] = frag<BN>(sm.b[buf][BLO ? 1 : 0], BCOL, wn + 16 * j);
 #pragma unroll
-        for (int j = 0; j < NI; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+        for (int i = 0; i < MI; ++i)
+#pragma unroll
+          for (int j = 0; j < NI; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
       }
+      if (ALO) {
+#pragma unroll
+        for (int i = 0; i < MI; ++i) {
+          const bf16x8 al = frag<BM>(sm.a[buf][ALO ? 1 : 0], ACOL, wm + 16 * i);
+#pragma unroll
+          for (int j = 0; j < NI; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+        }
+      }
+      if (more) store(buf ^ 1);
+      __syncthreads();
     }
-    if (more) store(buf ^ 1);
-    if (++kt == KT) {
-      epi(seg, acc);
-      if (RESET) zero(acc);
-      kt = 0;
-      ++seg;
-    }
-    __syncthreads();
+    epi(seg, acc);
+    if (RESET) zero(acc);
   }
 }
 
@@ -369,48 +367,49 @@ __device__ __forceinline__ void mainloop_dl(Ring<BM, BN, ALO, BLO, S>& sm, int n
   for (int t = 0; t < S - 1; ++t)
     if (t < total) issue(t);
   if (RESET) zero(acc);
-  int seg = 0, kt = 0, stage = 0;
-  for (int it = 0; it < total; ++it) {
-    if (it + S - 2 < total) __builtin_amdgcn_s_waitcnt(waitcnt_vm(L * (S - 2)));
-    else __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
-    __builtin_amdgcn_s_barrier();
-    if (it + S - 1 < total) issue((stage + S - 1) % S);
-    bf16x8 ah[MI], bh[NI];
+  // segments outside, k-tiles inside: the epilogue sits outside the inner loop, so the register
+  // allocator keeps the accumulators in place through the k-loop (an epilogue inside the k-loop made
+  // it shuttle them between AGPRs and VGPRs on every k-tile)
+  int stage = 0, it = 0;
+  for (int seg = 0; seg < nseg; ++seg) {
+    for (int kt = 0; kt < KT; ++kt, ++it) {
+      if (it + S - 2 < total) __builtin_amdgcn_s_waitcnt(waitcnt_vm(L * (S - 2)));
+      else __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+      __builtin_amdgcn_s_barrier();
+      if (it + S - 1 < total) issue((stage + S - 1) % S);
+      bf16x8 ah[MI], bh[NI];
 #pragma unroll
-    for (int i = 0; i < MI; ++i) ah[i] = dl_frag<BM, ACOL>(sm.a[stage][0], wm + 16 * i);
+      for (int i = 0; i < MI; ++i) ah[i] = dl_frag<BM, ACOL>(sm.a[stage][0], wm + 16 * i);
 #pragma unroll
-    for (int j = 0; j < NI; ++j) bh[j] = dl_frag<BN, BCOL>(sm.b[stage][0], wn + 16 * j);
-#pragma unroll
-    for (int i = 0; i < MI; ++i)
-#pragma unroll
-      for (int j = 0; j < NI; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-    if (BLO) {
-      bf16x8 bl[NI];
-#pragma unroll
-      for (int j = 0; j < NI; ++j) bl[j] = dl_frag<BN, BCOL>(sm.b[stage][BLO ? 1 : 0], wn + 16 * j);
+      for (int j = 0; j < NI; ++j) bh[j] = dl_frag<BN, BCOL>(sm.b[stage][0], wn + 16 * j);
 #pragma unroll
       for (int i = 0; i < MI; ++i)
 #pragma unroll
         for (int j = 0; j < NI; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-    }
-    if (ALO) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+      if (BLO) {
+        bf16x8 bl[NI];
 #pragma unroll
-      for (int i = 0; i < MI; ++i) {
-        const bf16x8 al = dl_frag<BM, ACOL>(sm.a[stage][ALO ? 1 : 0], wm + 16 * i);
+        for (int j = 0; j < NI; ++j) bl[j] = dl_frag<BN, BCOL>(sm.b[stage][BLO ? 1 : 0], wn + 16 * j);
 #pragma unroll
-        for (int j = 0; j < NI; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+        for (int i = 0; i < MI; ++i)
+#pragma unroll
+          for (int j = 0; j < NI; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
       }
+      if (ALO) {
+#pragma unroll
+        for (int i = 0; i < MI; ++i) {
+          const bf16x8 al = dl_frag<BM, ACOL>(sm.a[stage][ALO ? 1 : 0], wm + 16 * i);
+#pragma unroll
+          for (int j = 0; j < NI; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+        }
+      }
+      stage = (stage + 1 == S) ? 0 : stage + 1;
     }
-    if (++kt == KT) {
-      epi(seg, acc);
-      if (RESET) zero(acc);
-      kt = 0;
-      ++seg;
-    }
-    stage = (stage + 1 == S) ? 0 : stage + 1;
+    epi(seg, acc);
+    if (RESET) zero(acc);
   }
   __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
   __builtin_amdgcn_s_barrier();
@@ -471,30 +470,35 @@ __device__ __forceinline__ int find_instance(const int* __restrict__ off, int ni
 }
 
 // gemm1: XT_P[p][mu] = sum_nu Ct[p][nu] B_P[mu][nu], written as a hi/lo pair.  Tile 128 (p) x G1N (mu).
-// STACK: the n-tiles run over the stacked rows (P, mu) of all np rows of B.
+// A work item is one tile for G1SEG consecutive P (the operand pipeline runs on from one P to the
+// next while the finished tile is written).  STACK: the n-tiles run over the stacked rows (P, mu)
+// of all np rows of B, one P-row range per item.
+constexpr int G1SEG = 1;   // P per gemm1 work item
 template <int TERMS, bool BLO, int G1N, int MINB, bool VEC, bool STACK>
 __device__ __forceinline__ void gemm1_body(int w, const G1Args& g) {
   constexpr bool ALO = TERMS >= 2;
   constexpr int G1M = 128;
   const int nbf = g.nbf, nact = g.nact, ldx = g.ldx;
   const int tm_n = (nact + G1M - 1) / G1M;
-  int P = 0, m0, n0;
+  int P0 = 0, nseg = 1, m0, n0;
   if constexpr (STACK) {
     m0 = (w % tm_n) * G1M;
     n0 = (w / tm_n) * G1N;
   } else {
     const int tn_n = (nbf + G1N - 1) / G1N;
-    P = w / (tm_n * tn_n);
+    P0 = (w / (tm_n * tn_n)) * G1SEG;
+    nseg = min(G1SEG, g.np - P0);
     const int tile = w % (tm_n * tn_n);
     m0 = (tile / tn_n) * G1M;
     n0 = (tile % tn_n) * G1N;
   }
   const long long pstride = (long long)g.ws.nact32 * ldx;
-  u16* XTh = g.xt_hi + (STACK ? 0 : P * pstride);
-  u16* XTl = g.xt_lo ? g.xt_lo + (STACK ? 0 : P * pstride) : nullptr;
   const long long nrows = (long long)g.np * nbf;
   f32x4 acc[G1M / 32][G1N / 32];
-  auto epi = [&](int, f32x4(&a)[G1M / 32][G1N / 32]) {
+  auto epi = [&](int seg, f32x4(&a)[G1M / 32][G1N / 32]) {
+    const long long po = STACK ? 0 : (long long)(P0 + seg) * pstride;
+    u16* XTh = g.xt_hi + po;
+    u16* XTl = g.xt_lo ? g.xt_lo + po : nullptr;
 #pragma unroll
     for (int i = 0; i < G1M / 32; ++i)
 #pragma unroll
@@ -527,19 +531,19 @@ __device__ __forceinline__ void gemm1_body(int w, const G1Args& g) {
     constexpr int S = ring_depth(G1M, G1N, ALO, BLO, MINB == 2 ? 81920 : 163840);
     __shared__ Ring<G1M, G1N, ALO, BLO, S> sm;
     auto A = [&](int) { return DOpnd{g.ct_hi, g.ct_lo, g.ldk, g.ws.ct_bytes}; };
-    auto B = [&](int) {
-      const long long o = (long long)P * g.bstride;
+    auto B = [&](int seg) {
+      const long long o = (long long)(P0 + seg) * g.bstride;
       return DOpnd{g.b_hi + o, BLO ? g.b_lo + o : nullptr, g.ldb, g.b_bytes - 2 * o};
     };
-    mainloop_dl<G1M, G1N, ALO, BLO, S, false, false, true>(sm, 1, 0, nbf, m0, n0, A, B, acc, epi);
+    mainloop_dl<G1M, G1N, ALO, BLO, S, false, false, true>(sm, nseg, 0, nbf, m0, n0, A, B, acc, epi);
   } else {
     __shared__ Stage<G1M, G1N, ALO, BLO> sm;
     auto A = [&](int) { return Opnd{g.ct_hi, g.ct_lo, g.ldk, nact, nbf, false}; };
-    auto B = [&](int) {
-      const long long o = (long long)P * g.bstride;
+    auto B = [&](int seg) {
+      const long long o = (long long)(P0 + seg) * g.bstride;
       return Opnd{g.b_hi + o, BLO ? g.b_lo + o : nullptr, g.ldb, STACK ? (int)nrows : nbf, nbf, false};
     };
-    mainloop<G1M, G1N, ALO, BLO, false, false, true>(sm, 1, 0, nbf, m0, n0, A, B, acc, epi);
+    mainloop<G1M, G1N, ALO, BLO, false, false, true>(sm, nseg, 0, nbf, m0, n0, A, B, acc, epi);
   }
 }
 
@@ -673,7 +677,9 @@ __device__ __forceinline__ void gemm3_body(int w, const G3Args& g) {
   zero(acc);
   auto none = [&](int, f32x4(&)[G3M / 32][G3N / 32]) {};
   if constexpr (VEC) {
-    constexpr int S = ring_depth(G3M, G3N, LO, LO, 163840);
+    // the 128-row tile runs two blocks per compute unit (two-stage ring each): while one block waits
+    // on its fragment reads or barrier, the other keeps the matrix cores busy
+    constexpr int S = ring_depth(G3M, G3N, LO, LO, G3M == 128 ? 81920 : 163840);
     __shared__ Ring<G3M, G3N, LO, LO, S> sm;
     auto A = [&](int seg) {
       const long long off = (long long)(pb + seg) * g.ws.nact32 * ldx;
@@ -710,7 +716,7 @@ __device__ __forceinline__ void gemm3_body(int w, const G3Args& g) {
 
 template <int TERMS, bool BLO, int G1N, int MINB, bool VEC>
 __global__ __launch_bounds__(256, MINB) void gemm1_kernel(G1Args g) {
-  const int w = xcd_item(g1_items(g, G1N, false));
+  const int w = xcd_item(g1_items(g, G1N, false, G1SEG));
   if (w < 0) return;
   gemm1_body<TERMS, BLO, G1N, MINB, VEC, false>(w, g);
 }
@@ -747,7 +753,7 @@ __global__ __launch_bounds__(256, 1) void gemm2_grouped(const G2Args* __restrict
   gemm2_body<TERMS, true>(w - off[i], g);
 }
 template <int TERMS>
-__global__ __launch_bounds__(256, 1) void gemm3_grouped(const G3Args* __restrict__ tab, const int* __restrict__ off,
+__global__ __launch_bounds__(256, 2) void gemm3_grouped(const G3Args* __restrict__ tab, const int* __restrict__ off,
                                                         int ninst, int total) {
   const int w = xcd_item(total);
   if (w < 0) return;
@@ -763,7 +769,7 @@ inline dim3 xcd_grid(long long items) { return dim3((unsigned)(cdiv(items, NXCD)
 inline bool al16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 template <int TERMS, bool BLO, int G1N, int MINB>
 static void launch_g1(hipStream_t s, const G1Args& g) {
-  const dim3 grid = xcd_grid(g1_items(g, G1N, false));
+  const dim3 grid = xcd_grid(g1_items(g, G1N, false, G1SEG));
   // direct-to-LDS needs 16-byte aligned rows of the caller's B (nbf % 8 == 0)
   const bool vec = (g.ldb % 8 == 0) && (g.nbf % 8 == 0) && (g.bstride % 8 == 0) && al16(g.b_hi) &&
                    (!g.b_lo || al16(g.b_lo)) && al16(g.ct_hi) && (!g.ct_lo || al16(g.ct_lo)) && (g.ldk % 32 == 0) &&
@@ -828,7 +834,7 @@ hipError_t df_bf16_gemm3(hipStream_t s, int nbf, int nact, int np, int nsplit, i
     else launch_g3<1, 128, 1>(s, g);
   } else {
     if (wide) launch_g3<3, 256, 1>(s, g);
-    else launch_g3<3, 128, 1>(s, g);
+    else launch_g3<3, 128, 2>(s, g);
   }
   return hipGetLastError();
 }
