@@ -188,9 +188,8 @@ struct G3Args {   // Ypart[s] = sum_{P in s} X_P W_P
 };
 // Work items of one launch.  The stacked form of X treats the rows (P, mu) of np consecutive B_P
 // as one matrix (B_P rows padded to ldb, bstride == nbf * ldb), so short rows do not waste tiles.
-// gemm1 work items: one output tile for `segs` consecutive P (stacked form: one tile of the stacked rows)
-__host__ __device__ inline int g1_items(const G1Args& a, int g1n, bool stacked, int segs = 1) {
-  return cdiv(a.nact, 128) * (stacked ? cdiv((long long)a.np * a.nbf, g1n) : cdiv(a.np, segs) * cdiv(a.nbf, g1n));
+__host__ __device__ inline int g1_items(const G1Args& a, int g1n, bool stacked) {
+  return cdiv(a.nact, 128) * (stacked ? cdiv((long long)a.np * a.nbf, g1n) : a.np * cdiv(a.nbf, g1n));
 }
 __host__ __device__ inline int g2_items(const G2Args& a) {
   const int t = cdiv(a.nact, 128);

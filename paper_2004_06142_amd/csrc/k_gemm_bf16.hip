@@ -20,6 +20,8 @@
 //     k of one row when lane 4j+q fetched rows 4q..4q+3 of k-row j.
 // Blocks are numbered so that the eight XCDs each receive one contiguous range of work items:
 // items sharing an operand (same P, or same split of P) run on the same XCD and share its L2.
+#include <type_traits>
+
 #include "common.h"
 
 namespace pnof {
@@ -283,10 +285,11 @@ struct DOpnd {
   long long bytes;   // readable bytes from hi (and from lo) onwards
 };
 
-template <int D>
+template <int D, int NW = 4>
 __device__ __forceinline__ void dl_issue(u16* lds_slice, const u16* base, long long bytes, long long ld, const bool col,
                                          int r0, int k0) {
-  constexpr int PER_WAVE = D / 64;   // (D * BK / 8 chunks) / 64 lanes / 4 waves
+  constexpr int PER_WAVE = D / (16 * NW);   // (D * BK / 8 chunks) / 64 lanes / NW waves
+  static_assert(D % (16 * NW) == 0, "slice rows per wave");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(base, bytes);
 #pragma unroll
@@ -341,25 +344,26 @@ struct Ring {
 
 // Contraction over segments seg = 0..nseg-1 and k in [kb, ke) of each; ACOL / BCOL fix the storage
 // order of the operands at compile time.
-template <int BM, int BN, bool ALO, bool BLO, int S, bool ACOL, bool BCOL, bool RESET, typename FA, typename FB,
-          typename EPI>
+template <int BM, int BN, bool ALO, bool BLO, int S, bool ACOL, bool BCOL, bool RESET, int WGM = 2, int WGN = 2,
+          typename FA, typename FB, typename EPI>
 __device__ __forceinline__ void mainloop_dl(Ring<BM, BN, ALO, BLO, S>& sm, int nseg, int kb, int ke, int m0, int n0,
-                                            FA A, FB B, f32x4 (&acc)[BM / 32][BN / 32], EPI epi) {
-  constexpr int MI = BM / 32, NI = BN / 32;
-  constexpr int L = (ALO ? 2 : 1) * (BM / 64) + (BLO ? 2 : 1) * (BN / 64);   // loads per wave per tile
+                                            FA A, FB B, f32x4 (&acc)[BM / (16 * WGM)][BN / (16 * WGN)], EPI epi) {
+  constexpr int NW = WGM * WGN;   // waves in a WGM x WGN grid, each owning (BM / WGM) x (BN / WGN)
+  constexpr int MI = BM / (16 * WGM), NI = BN / (16 * WGN);
+  constexpr int L = (ALO ? 2 : 1) * (BM / (16 * NW)) + (BLO ? 2 : 1) * (BN / (16 * NW));   // loads per wave per tile
   static_assert(L * (S - 2) < 64, "vmcnt range");
   const int wave = threadIdx.x >> 6;
-  const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
+  const int wm = (wave / WGN) * (BM / WGM), wn = (wave % WGN) * (BN / WGN);
   const int KT = (ke - kb + BK - 1) / BK;
   const int total = nseg * KT;
   if (total <= 0) return;
   int lseg = 0, lk = kb;
   auto issue = [&](int stage) {
     const DOpnd a = A(lseg), b = B(lseg);
-    dl_issue<BM>(sm.a[stage][0], a.hi, a.bytes, a.ld, ACOL, m0, lk);
-    if (ALO) dl_issue<BM>(sm.a[stage][ALO ? 1 : 0], a.lo, a.bytes, a.ld, ACOL, m0, lk);
-    dl_issue<BN>(sm.b[stage][0], b.hi, b.bytes, b.ld, BCOL, n0, lk);
-    if (BLO) dl_issue<BN>(sm.b[stage][BLO ? 1 : 0], b.lo, b.bytes, b.ld, BCOL, n0, lk);
+    dl_issue<BM, NW>(sm.a[stage][0], a.hi, a.bytes, a.ld, ACOL, m0, lk);
+    if (ALO) dl_issue<BM, NW>(sm.a[stage][ALO ? 1 : 0], a.lo, a.bytes, a.ld, ACOL, m0, lk);
+    dl_issue<BN, NW>(sm.b[stage][0], b.hi, b.bytes, b.ld, BCOL, n0, lk);
+    if (BLO) dl_issue<BN, NW>(sm.b[stage][BLO ? 1 : 0], b.lo, b.bytes, b.ld, BCOL, n0, lk);
     lk += BK;
     if (lk >= ke) { lk = kb; ++lseg; }
   };
@@ -416,15 +420,15 @@ __device__ __forceinline__ void mainloop_dl(Ring<BM, BN, ALO, BLO, S>& sm, int n
 }
 
 // Output row / column of component j of acc[i][jn] relative to the block tile origin.
-template <int BM>
+template <int BM, int WGM = 2, int WGN = 2>
 __device__ __forceinline__ int row_of(int i, int j) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  return (wave >> 1) * (BM / 2) + i * 16 + 4 * (lane >> 4) + j;
+  return (wave / WGN) * (BM / WGM) + i * 16 + 4 * (lane >> 4) + j;
 }
-template <int BN>
+template <int BN, int WGM = 2, int WGN = 2>
 __device__ __forceinline__ int col_of(int jn) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  return (wave & 1) * (BN / 2) + jn * 16 + (lane & 15);
+  return (wave % WGN) * (BN / WGN) + jn * 16 + (lane & 15);
 }
 
 // Lower-triangle tile t of a tt x tt tiling, ordered by column (tiles sharing tn are consecutive,
@@ -469,36 +473,33 @@ __device__ __forceinline__ int find_instance(const int* __restrict__ off, int ni
   return lo;
 }
 
-// gemm1: XT_P[p][mu] = sum_nu Ct[p][nu] B_P[mu][nu], written as a hi/lo pair.  Tile 128 (p) x G1N (mu).
-// A work item is one tile for G1SEG consecutive P (the operand pipeline runs on from one P to the
-// next while the finished tile is written).  STACK: the n-tiles run over the stacked rows (P, mu)
-// of all np rows of B, one P-row range per item.
-constexpr int G1SEG = 1;   // P per gemm1 work item
+// gemm1: XT_P[p][mu] = sum_nu Ct[p][nu] B_P[mu][nu], written as a hi/lo pair.  Tile 128 (p) x G1N (mu),
+// one P per work item (items covering several P measured slower: the epilogue's stores then stall
+// the next P's operand waits, as the vector-memory counter retires loads and stores in order).
+// STACK: the n-tiles run over the stacked rows (P, mu) of all np rows of B.
 template <int TERMS, bool BLO, int G1N, int MINB, bool VEC, bool STACK>
 __device__ __forceinline__ void gemm1_body(int w, const G1Args& g) {
   constexpr bool ALO = TERMS >= 2;
   constexpr int G1M = 128;
   const int nbf = g.nbf, nact = g.nact, ldx = g.ldx;
   const int tm_n = (nact + G1M - 1) / G1M;
-  int P0 = 0, nseg = 1, m0, n0;
+  int P = 0, m0, n0;
   if constexpr (STACK) {
     m0 = (w % tm_n) * G1M;
     n0 = (w / tm_n) * G1N;
   } else {
     const int tn_n = (nbf + G1N - 1) / G1N;
-    P0 = (w / (tm_n * tn_n)) * G1SEG;
-    nseg = min(G1SEG, g.np - P0);
+    P = w / (tm_n * tn_n);
     const int tile = w % (tm_n * tn_n);
     m0 = (tile / tn_n) * G1M;
     n0 = (tile % tn_n) * G1N;
   }
   const long long pstride = (long long)g.ws.nact32 * ldx;
+  u16* XTh = g.xt_hi + (STACK ? 0 : P * pstride);
+  u16* XTl = g.xt_lo ? g.xt_lo + (STACK ? 0 : P * pstride) : nullptr;
   const long long nrows = (long long)g.np * nbf;
   f32x4 acc[G1M / 32][G1N / 32];
-  auto epi = [&](int seg, f32x4(&a)[G1M / 32][G1N / 32]) {
-    const long long po = STACK ? 0 : (long long)(P0 + seg) * pstride;
-    u16* XTh = g.xt_hi + po;
-    u16* XTl = g.xt_lo ? g.xt_lo + po : nullptr;
+  auto epi = [&](int, f32x4(&a)[G1M / 32][G1N / 32]) {
 #pragma unroll
     for (int i = 0; i < G1M / 32; ++i)
 #pragma unroll
@@ -531,28 +532,34 @@ __device__ __forceinline__ void gemm1_body(int w, const G1Args& g) {
     constexpr int S = ring_depth(G1M, G1N, ALO, BLO, MINB == 2 ? 81920 : 163840);
     __shared__ Ring<G1M, G1N, ALO, BLO, S> sm;
     auto A = [&](int) { return DOpnd{g.ct_hi, g.ct_lo, g.ldk, g.ws.ct_bytes}; };
-    auto B = [&](int seg) {
-      const long long o = (long long)(P0 + seg) * g.bstride;
+    auto B = [&](int) {
+      const long long o = (long long)P * g.bstride;
       return DOpnd{g.b_hi + o, BLO ? g.b_lo + o : nullptr, g.ldb, g.b_bytes - 2 * o};
     };
-    mainloop_dl<G1M, G1N, ALO, BLO, S, false, false, true>(sm, nseg, 0, nbf, m0, n0, A, B, acc, epi);
+    mainloop_dl<G1M, G1N, ALO, BLO, S, false, false, true>(sm, 1, 0, nbf, m0, n0, A, B, acc, epi);
   } else {
     __shared__ Stage<G1M, G1N, ALO, BLO> sm;
     auto A = [&](int) { return Opnd{g.ct_hi, g.ct_lo, g.ldk, nact, nbf, false}; };
-    auto B = [&](int seg) {
-      const long long o = (long long)(P0 + seg) * g.bstride;
+    auto B = [&](int) {
+      const long long o = (long long)P * g.bstride;
       return Opnd{g.b_hi + o, BLO ? g.b_lo + o : nullptr, g.ldb, STACK ? (int)nrows : nbf, nbf, false};
     };
-    mainloop<G1M, G1N, ALO, BLO, false, false, true>(sm, nseg, 0, nbf, m0, n0, A, B, acc, epi);
+    mainloop<G1M, G1N, ALO, BLO, false, false, true>(sm, 1, 0, nbf, m0, n0, A, B, acc, epi);
   }
 }
 
 // gemm2: b_P = Ct XT_P^T on lower 128-tiles; Kpart[s] += sum_{P in s} b^2 (lower triangle, summed
 // over the successive P-chunks of one call), D[P][p] = b_pp, W_P = b o beta as a hi/lo pair, written
 // in full (off-diagonal tiles store their mirror image as well).
+// waves along q of a gemm2 block (2 x g2_wgn grid)
+constexpr int g2_wgn(bool vec) { return vec ? 4 : 2; }
+
 template <int TERMS, bool VEC>
 __device__ __forceinline__ void gemm2_body(int w, const G2Args& g) {
   constexpr bool LO = TERMS >= 3;
+  // the direct-load form runs 8 waves (2 x 4, each 64 x 32): half the accumulators, beta and K sums
+  // per wave, so they stay in registers, and two waves per SIMD hide each other's epilogue latency
+  constexpr int WGN = g2_wgn(VEC), NI = T2 / (16 * WGN);
   const int nbf = g.nbf, nact = g.nact, np = g.np, nsplit = g.nsplit, ldw = g.ldw, ldx = g.ldx;
   const int tt = (nact + T2 - 1) / T2;
   const int ntri = tt * (tt + 1) / 2;
@@ -562,28 +569,28 @@ __device__ __forceinline__ void gemm2_body(int w, const G2Args& g) {
   const int m0 = tm * T2, n0 = tn * T2;
   const int pb = (int)((long long)np * s / nsplit), pe = (int)((long long)np * (s + 1) / nsplit);
   // beta of this lane's accumulator positions, kept in registers for the whole P-range
-  f32x4 bet[4][4];
+  f32x4 bet[4][NI];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int jn = 0; jn < 4; ++jn)
+    for (int jn = 0; jn < NI; ++jn)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int p = m0 + row_of<T2>(i, j), q = n0 + col_of<T2>(jn);
+        const int p = m0 + row_of<T2, 2, WGN>(i, j), q = n0 + col_of<T2, 2, WGN>(jn);
         bet[i][jn][j] = (p < nact && q < nact) ? g.beta32[(long long)p * nact + q] : 0.f;
       }
-  f32x4 kacc[4][4], acc[4][4];
+  f32x4 kacc[4][NI], acc[4][NI];
   zero(kacc);
   const bool diag = (tm == tn);
-  auto epi = [&](int seg, f32x4(&a)[4][4]) {
+  auto epi = [&](int seg, f32x4(&a)[4][NI]) {
     const int P = pb + seg;
     u16* Wh = g.w_hi + (long long)P * g.ws.nact32 * ldw;
     u16* Wl = LO ? g.w_lo + (long long)P * g.ws.nact32 * ldw : nullptr;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int jn = 0; jn < 4; ++jn) {
-        const int p0 = m0 + row_of<T2>(i, 0), q = n0 + col_of<T2>(jn);
+      for (int jn = 0; jn < NI; ++jn) {
+        const int p0 = m0 + row_of<T2, 2, WGN>(i, 0), q = n0 + col_of<T2, 2, WGN>(jn);
         float wv[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -636,7 +643,7 @@ __device__ __forceinline__ void gemm2_body(int w, const G2Args& g) {
       const long long off = (long long)(pb + seg) * g.ws.nact32 * ldx;
       return DOpnd{g.xt_hi + off, LO ? g.xt_lo + off : nullptr, ldx, g.ws.xt_bytes - 2 * off};
     };
-    mainloop_dl<T2, T2, LO, LO, S, false, false, true>(sm, pe - pb, 0, nbf, m0, n0, A, B, acc, epi);
+    mainloop_dl<T2, T2, LO, LO, S, false, false, true, 2, WGN>(sm, pe - pb, 0, nbf, m0, n0, A, B, acc, epi);
   } else {
     __shared__ Stage<T2, T2, LO, LO> sm;
     auto A = [&](int) { return Opnd{g.ct_hi, g.ct_lo, g.ldk, nact, nbf, false}; };
@@ -650,10 +657,10 @@ __device__ __forceinline__ void gemm2_body(int w, const G2Args& g) {
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int jn = 0; jn < 4; ++jn)
+    for (int jn = 0; jn < NI; ++jn)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int p = m0 + row_of<T2>(i, j), q = n0 + col_of<T2>(jn);
+        const int p = m0 + row_of<T2, 2, WGN>(i, j), q = n0 + col_of<T2, 2, WGN>(jn);
         if (p < nact && q <= p) Kp[(long long)p * nact + q] += (double)kacc[i][jn][j];
       }
 }
@@ -716,12 +723,12 @@ __device__ __forceinline__ void gemm3_body(int w, const G3Args& g) {
 
 template <int TERMS, bool BLO, int G1N, int MINB, bool VEC>
 __global__ __launch_bounds__(256, MINB) void gemm1_kernel(G1Args g) {
-  const int w = xcd_item(g1_items(g, G1N, false, G1SEG));
+  const int w = xcd_item(g1_items(g, G1N, false));
   if (w < 0) return;
   gemm1_body<TERMS, BLO, G1N, MINB, VEC, false>(w, g);
 }
 template <int TERMS, bool VEC>
-__global__ __launch_bounds__(256, 1) void gemm2_kernel(G2Args g) {
+__global__ __launch_bounds__(128 * g2_wgn(VEC), 1) void gemm2_kernel(G2Args g) {
   const int w = xcd_item(g2_items(g));
   if (w < 0) return;
   gemm2_body<TERMS, VEC>(w, g);
@@ -744,7 +751,7 @@ __global__ __launch_bounds__(256, 1) void gemm1_grouped(const G1Args* __restrict
   gemm1_body<TERMS, false, 128, 1, true, true>(w - off[i], g);
 }
 template <int TERMS>
-__global__ __launch_bounds__(256, 1) void gemm2_grouped(const G2Args* __restrict__ tab, const int* __restrict__ off,
+__global__ __launch_bounds__(128 * g2_wgn(true), 1) void gemm2_grouped(const G2Args* __restrict__ tab, const int* __restrict__ off,
                                                         int ninst, int total) {
   const int w = xcd_item(total);
   if (w < 0) return;
@@ -769,7 +776,7 @@ inline dim3 xcd_grid(long long items) { return dim3((unsigned)(cdiv(items, NXCD)
 inline bool al16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 template <int TERMS, bool BLO, int G1N, int MINB>
 static void launch_g1(hipStream_t s, const G1Args& g) {
-  const dim3 grid = xcd_grid(g1_items(g, G1N, false, G1SEG));
+  const dim3 grid = xcd_grid(g1_items(g, G1N, false));
   // direct-to-LDS needs 16-byte aligned rows of the caller's B (nbf % 8 == 0)
   const bool vec = (g.ldb % 8 == 0) && (g.nbf % 8 == 0) && (g.bstride % 8 == 0) && al16(g.b_hi) &&
                    (!g.b_lo || al16(g.b_lo)) && al16(g.ct_hi) && (!g.ct_lo || al16(g.ct_lo)) && (g.ldk % 32 == 0) &&
@@ -806,11 +813,11 @@ hipError_t df_bf16_gemm2(hipStream_t s, int nbf, int nact, int np, int nsplit, i
   const bool vec = (ldk % 32 == 0) && (ldx % 32 == 0) && al16(Ct.hi) && (!Ct.lo || al16(Ct.lo)) && al16(XT.hi) &&
                    (!XT.lo || al16(XT.lo));
   if (terms == 1) {
-    if (vec) hipLaunchKernelGGL((gemm2_kernel<1, true>), grid, dim3(256), 0, s, g);
-    else hipLaunchKernelGGL((gemm2_kernel<1, false>), grid, dim3(256), 0, s, g);
+    if (vec) hipLaunchKernelGGL((gemm2_kernel<1, true>), grid, dim3(128 * g2_wgn(true)), 0, s, g);
+    else hipLaunchKernelGGL((gemm2_kernel<1, false>), grid, dim3(128 * g2_wgn(false)), 0, s, g);
   } else {
-    if (vec) hipLaunchKernelGGL((gemm2_kernel<3, true>), grid, dim3(256), 0, s, g);
-    else hipLaunchKernelGGL((gemm2_kernel<3, false>), grid, dim3(256), 0, s, g);
+    if (vec) hipLaunchKernelGGL((gemm2_kernel<3, true>), grid, dim3(128 * g2_wgn(true)), 0, s, g);
+    else hipLaunchKernelGGL((gemm2_kernel<3, false>), grid, dim3(128 * g2_wgn(false)), 0, s, g);
   }
   return hipGetLastError();
 }
@@ -847,8 +854,9 @@ hipError_t df_bf16_gemm1_grouped(hipStream_t s, int ninst, int total, int terms,
 }
 hipError_t df_bf16_gemm2_grouped(hipStream_t s, int ninst, int total, int terms, const G2Args* tab, const int* off) {
   if (total <= 0) return hipSuccess;
-  if (terms == 1) hipLaunchKernelGGL((gemm2_grouped<1>), xcd_grid(total), dim3(256), 0, s, tab, off, ninst, total);
-  else hipLaunchKernelGGL((gemm2_grouped<3>), xcd_grid(total), dim3(256), 0, s, tab, off, ninst, total);
+  if (terms == 1)
+    hipLaunchKernelGGL((gemm2_grouped<1>), xcd_grid(total), dim3(128 * g2_wgn(true)), 0, s, tab, off, ninst, total);
+  else hipLaunchKernelGGL((gemm2_grouped<3>), xcd_grid(total), dim3(128 * g2_wgn(true)), 0, s, tab, off, ninst, total);
   return hipGetLastError();
 }
 hipError_t df_bf16_gemm3_grouped(hipStream_t s, int ninst, int total, int terms, const G3Args* tab, const int* off) {
