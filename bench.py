@@ -27,16 +27,16 @@ KSRC = os.path.join(ROOT, "paper_2004_06142_amd", "csrc")
 # factor a plain 1 GiB elementwise copy gives, and the SHA-256 of the kernel source they were taken on:
 # once the source changes the figure no longer applies and traffic is reported as null.
 TRAFFIC = {
-    # profiles/c5_df1200_hbm_traffic.md: C5, bf16 split, 128-row chunks
-    ("gemm2_kernel", 3): {"bytes": 2543166977 + 454880178,
-                          "plan": {"pchunk": 128, "nsplit_b": 9},
-                          "sha256": {"k_gemm_bf16.hip": "6083e05454aa697560cffeae88d9bb0985521046df8dc821542933632fd94645"}},
-    ("gemm3_kernel", 3): {"bytes": 10764047431 + 29086124,
-                          "plan": {"pchunk": 128, "nsplit_y": 5, "y_variant": 0},
-                          "sha256": {"k_gemm_bf16.hip": "6083e05454aa697560cffeae88d9bb0985521046df8dc821542933632fd94645"}},
-    ("gemm1_kernel", 3): {"bytes": 2401680835 + 742275833,
+    # profiles/c5_df1200_hbm_traffic.md: C5, bf16 split, 128-row chunks (read + written bytes per launch)
+    ("gemm1_kernel", 3): {"bytes": 2393830130 + 758834704,
                           "plan": {"pchunk": 128, "x_variant": 0},
-                          "sha256": {"k_gemm_bf16.hip": "6083e05454aa697560cffeae88d9bb0985521046df8dc821542933632fd94645"}},
+                          "sha256": {"k_gemm_bf16.hip": "86d5263a36cc4ab9b37b90314c32194e650c753d7fe31b76054161bbd6e820d5"}},
+    ("gemm2_kernel", 3): {"bytes": 2411292054 + 878367456,
+                          "plan": {"pchunk": 128, "nsplit_b": 9},
+                          "sha256": {"k_gemm_bf16.hip": "86d5263a36cc4ab9b37b90314c32194e650c753d7fe31b76054161bbd6e820d5"}},
+    ("gemm3_kernel", 3): {"bytes": 4056725651 + 29187417,
+                          "plan": {"pchunk": 128, "nsplit_y": 5, "y_variant": 0},
+                          "sha256": {"k_gemm_bf16.hip": "86d5263a36cc4ab9b37b90314c32194e650c753d7fe31b76054161bbd6e820d5"}},
 }
 GOLDEN_C5 = os.path.join(ROOT, "tests", "golden", "c5_df1200_expected.json")
 
