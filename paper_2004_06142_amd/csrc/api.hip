@@ -205,7 +205,7 @@ Bufs carve(const Plan& pl, char* base) {
   b.flag = a.take<int>(4);
   if (is_df(pl.ints)) {
     b.D = a.take<double>((long long)pl.naux * pl.nact);
-    b.dbuf = a.take<double>((long long)pl.pc * pl.nact);
+    b.dbuf = a.take<double>((long long)F64_KSPLIT_MAX * pl.pc * pl.nact);
     b.Kpart = a.take<double>((long long)pl.ns2 * n2);
     if (!pl.split) {
       b.Ct = a.take<double>((long long)pl.nact * pl.ldk);

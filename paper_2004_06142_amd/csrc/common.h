@@ -260,7 +260,14 @@ hipError_t split_ca(hipStream_t s, int nbf, int nact, int terms, const double* C
 hipError_t split_b(hipStream_t s, long long n, const double* B, u16* hi, u16* lo);
 hipError_t widen_bf16(hipStream_t s, long long n, const u16* src, double* dst);
 hipError_t hpp_from_hc(hipStream_t s, int nbf, int nact, const double* C, const double* HC, double* Hpp);
-// d = Dchunk alpha (float64 matrix cores) into dbuf (np x nact), then W_P[p][p] += d[P][p].
+// Split-K float64 product for few output tiles: ks (<= F64_KSPLIT_MAX) dense M x N partial slabs in
+// Cpart, summed by the caller in slab order.  gemm_f64_ksplit gives the split used for a shape.
+constexpr int F64_KSPLIT_MAX = 8;
+int gemm_f64_ksplit(int M, int N, int K);
+hipError_t gemm_f64_splitk(hipStream_t s, int M, int N, int K, int ks, const double* A, long long sam, long long sak,
+                           const double* B, long long sbk, long long sbn, double* Cpart);
+// d = Dchunk alpha (float64 matrix cores, split over k into the F64_KSPLIT_MAX * np * nact doubles of
+// dbuf), then W_P[p][p] += d[P][p].
 hipError_t add_diag_f64(hipStream_t s, int nact, int np, const double* Dchunk, const double* alpha,
                         double* dbuf, double* W, int ldw);
 hipError_t add_diag_bf16(hipStream_t s, int nact, int np, const double* Dchunk, const double* alpha,

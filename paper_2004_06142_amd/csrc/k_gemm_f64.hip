@@ -45,18 +45,19 @@ __device__ __forceinline__ void store_slab(double (*S)[TM + LPAD], const double 
   }
 }
 
-// acc[mi][ni] += A(m0.., :) B(:, n0..) over k in [0, K).
+// acc[mi][ni] += A(m0.., :) B(:, n0..) over k in [kb, ke).
 template <bool AM, bool BN>
 __device__ __forceinline__ void tile_f64(F64Smem& sm, const double* __restrict__ A, long long sam,
                                          long long sak, const double* __restrict__ B, long long sbk,
-                                         long long sbn, int M, int N, int K, int m0, int n0,
+                                         long long sbn, int M, int N, int kb, int ke, int m0, int n0,
                                          f64x4 (&acc)[2][2]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int K = ke;
   double ra[4], rb[4];
-  load_slab<AM>(A, sam, sak, M, K, m0, 0, ra);
-  load_slab<BN>(B, sbn, sbk, N, K, n0, 0, rb);
-  for (int k0 = 0; k0 < K; k0 += TK) {
+  load_slab<AM>(A, sam, sak, M, K, m0, kb, ra);
+  load_slab<BN>(B, sbn, sbk, N, K, n0, kb, rb);
+  for (int k0 = kb; k0 < ke; k0 += TK) {
     __syncthreads();
     store_slab<AM>(sm.a, ra);
     store_slab<BN>(sm.b, rb);
@@ -109,7 +110,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(int M, int N, int K, doub
   const long long b = blockIdx.y;
   f64x4 acc[2][2];
   zero_acc(acc);
-  tile_f64<AM, BN>(sm, A + b * sab, sam, sak, B + b * sbb, sbk, sbn, M, N, K, m0, n0, acc);
+  tile_f64<AM, BN>(sm, A + b * sab, sam, sak, B + b * sbb, sbk, sbn, M, N, 0, K, m0, n0, acc);
   double* Cb = C + b * scb;
 #pragma unroll
   for (int mi = 0; mi < 2; ++mi)
@@ -135,7 +136,7 @@ __global__ __launch_bounds__(256) void gemm_f64_grouped_kernel(const F64Gemm* __
   const int m0 = (blockIdx.x / tiles_n) * TM, n0 = (blockIdx.x % tiles_n) * TN;
   f64x4 acc[2][2];
   zero_acc(acc);
-  tile_f64<AM, BN>(sm, g.A, g.sam, g.sak, g.B, g.sbk, g.sbn, g.M, g.N, g.K, m0, n0, acc);
+  tile_f64<AM, BN>(sm, g.A, g.sam, g.sak, g.B, g.sbk, g.sbn, g.M, g.N, 0, g.K, m0, n0, acc);
 #pragma unroll
   for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
@@ -147,6 +148,34 @@ __global__ __launch_bounds__(256) void gemm_f64_grouped_kernel(const F64Gemm* __
           double* c = g.C + (long long)m * g.scm + (long long)n * g.scn;
           *c = g.alpha * acc[mi][ni][j] + (g.beta != 0.0 ? g.beta * *c : 0.0);
         }
+      }
+}
+
+// Split-K form for products with few output tiles: block (tile, s) sums k in the s-th of ks equal
+// ranges and writes its partial to slab s of Cpart (ks dense M x N slabs, row-major).  The caller
+// adds the slabs in slab order, so the result does not depend on the schedule.
+template <bool AM, bool BN>
+__global__ __launch_bounds__(256) void gemm_f64_splitk_kernel(int M, int N, int K, int ks, const double* __restrict__ A,
+                                                              long long sam, long long sak,
+                                                              const double* __restrict__ B, long long sbk,
+                                                              long long sbn, double* __restrict__ Cpart) {
+  __shared__ F64Smem sm;
+  const int tiles_n = (N + TN - 1) / TN;
+  const int tile = blockIdx.x / ks, sidx = blockIdx.x % ks;
+  const int m0 = (tile / tiles_n) * TM, n0 = (tile % tiles_n) * TN;
+  const int kb = (int)((long long)K * sidx / ks), ke = (int)((long long)K * (sidx + 1) / ks);
+  f64x4 acc[2][2];
+  zero_acc(acc);
+  tile_f64<AM, BN>(sm, A, sam, sak, B, sbk, sbn, M, N, kb, ke, m0, n0, acc);
+  double* Cs = Cpart + (long long)sidx * M * N;
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int m = m0 + acc_row(mi, j), n = n0 + acc_col(ni);
+        if (m < M && n < N) Cs[(long long)m * N + n] = acc[mi][ni][j];
       }
 }
 
@@ -170,7 +199,7 @@ __global__ __launch_bounds__(256) void df_gemm1_kernel(int nbf, int nact, const 
   f64x4 acc[2][2];
   zero_acc(acc);
   // A(m=p, k=nu) = Ct[p*ldk + nu] (k contiguous); B(k=nu, n=mu) = B_P[nu*nbf + mu] (n contiguous)
-  tile_f64<false, true>(sm, Ct, ldk, 1, Bc + P * nbf * nbf, nbf, 1, nact, nbf, nbf, m0, n0, acc);
+  tile_f64<false, true>(sm, Ct, ldk, 1, Bc + P * nbf * nbf, nbf, 1, nact, nbf, 0, nbf, m0, n0, acc);
   double* X = XT + P * (long long)nact * ldx;
 #pragma unroll
   for (int mi = 0; mi < 2; ++mi)
@@ -203,7 +232,7 @@ __global__ __launch_bounds__(256) void df_gemm2_kernel(int nbf, int nact, int np
     f64x4 acc[2][2];
     zero_acc(acc);
     // A(m=p, k=mu) = Ct[p*ldk + mu]; B(k=mu, n=q) = XT_P[q*ldx + mu] (k contiguous)
-    tile_f64<false, false>(sm, Ct, ldk, 1, XT + (long long)P * nact * ldx, 1, ldx, nact, nact, nbf,
+    tile_f64<false, false>(sm, Ct, ldk, 1, XT + (long long)P * nact * ldx, 1, ldx, nact, nact, 0, nbf,
                            m0, n0, acc);
     double* Wp = W + (long long)P * nact * ldw;
 #pragma unroll
@@ -250,7 +279,7 @@ __global__ __launch_bounds__(256) void df_gemm3_kernel(int nbf, int nact, int np
   for (int P = pb; P < pe; ++P) {
     // A(m=mu, k=r) = XT_P[r*ldx + mu] (m contiguous); B(k=r, n=q) = W_P[r*ldw + q] (n contiguous)
     tile_f64<true, true>(sm, XT + (long long)P * nact * ldx, 1, ldx, W + (long long)P * nact * ldw,
-                         ldw, 1, nbf, nact, nact, m0, n0, acc);
+                         ldw, 1, nbf, nact, 0, nact, m0, n0, acc);
   }
   double* Y = Ypart + (long long)s * nbf * nact;
 #pragma unroll
@@ -281,6 +310,31 @@ hipError_t gemm_f64(hipStream_t s, int M, int N, int K, int batch, double alpha,
     hipLaunchKernelGGL((gemm_f64_kernel<false, true>), grid, dim3(256), 0, s, M, N, K, alpha, A, sam, sak, sab, B, sbk, sbn, sbb, beta, C, scm, scn, scb);
   else
     hipLaunchKernelGGL((gemm_f64_kernel<false, false>), grid, dim3(256), 0, s, M, N, K, alpha, A, sam, sak, sab, B, sbk, sbn, sbb, beta, C, scm, scn, scb);
+  return hipGetLastError();
+}
+
+int gemm_f64_ksplit(int M, int N, int K) {
+  const int tiles = cdiv(M, TM) * cdiv(N, TN);
+  int ks = cdiv(512, tiles);                   // about two blocks per compute unit
+  ks = ks < F64_KSPLIT_MAX ? ks : F64_KSPLIT_MAX;
+  const int kmax = cdiv(K, 4 * TK);            // at least four k-slabs per block
+  return ks < kmax ? ks : (kmax > 0 ? kmax : 1);
+}
+
+hipError_t gemm_f64_splitk(hipStream_t s, int M, int N, int K, int ks, const double* A, long long sam, long long sak,
+                           const double* B, long long sbk, long long sbn, double* Cpart) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  if (ks < 1 || ks > F64_KSPLIT_MAX) return hipErrorInvalidValue;
+  const dim3 grid(cdiv(M, TM) * cdiv(N, TN) * ks);
+  const bool am = (sam == 1), bn = (sbn == 1);
+  if (am && bn)
+    hipLaunchKernelGGL((gemm_f64_splitk_kernel<true, true>), grid, dim3(256), 0, s, M, N, K, ks, A, sam, sak, B, sbk, sbn, Cpart);
+  else if (am)
+    hipLaunchKernelGGL((gemm_f64_splitk_kernel<true, false>), grid, dim3(256), 0, s, M, N, K, ks, A, sam, sak, B, sbk, sbn, Cpart);
+  else if (bn)
+    hipLaunchKernelGGL((gemm_f64_splitk_kernel<false, true>), grid, dim3(256), 0, s, M, N, K, ks, A, sam, sak, B, sbk, sbn, Cpart);
+  else
+    hipLaunchKernelGGL((gemm_f64_splitk_kernel<false, false>), grid, dim3(256), 0, s, M, N, K, ks, A, sam, sak, B, sbk, sbn, Cpart);
   return hipGetLastError();
 }
 

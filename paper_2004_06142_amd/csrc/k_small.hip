@@ -72,22 +72,33 @@ __global__ void hpp_k(int nbf, int nact, const double* __restrict__ C, const dou
   if (lane == 0) Hpp[p] = s;
 }
 
-// W_P[p][p] += d[P][p], with d = D alpha (d_Pp = sum_q D_Pq alpha_qp) computed beforehand.
-__global__ void add_diag_f64_k(int nact, int np, const double* __restrict__ d, double* __restrict__ W, int ldw) {
-  GRID_STRIDE(i, (long long)np * nact) {
+// W_P[p][p] += d[P][p], with d = D alpha (d_Pp = sum_q D_Pq alpha_qp) computed beforehand as ks
+// partial slabs over ranges of q, added here in slab order.
+__device__ __forceinline__ double sum_slabs(const double* __restrict__ d, int ks, long long slab, long long i) {
+  double v = 0.0;
+  for (int s = 0; s < ks; ++s) v += d[s * slab + i];
+  return v;
+}
+
+__global__ void add_diag_f64_k(int nact, int np, int ks, const double* __restrict__ d, double* __restrict__ W,
+                               int ldw) {
+  const long long slab = (long long)np * nact;
+  GRID_STRIDE(i, slab) {
     const long long P = i / nact;
     const int p = (int)(i % nact);
-    W[P * nact * ldw + (long long)p * ldw + p] += d[i];
+    W[P * nact * ldw + (long long)p * ldw + p] += sum_slabs(d, ks, slab, i);
   }
 }
 
-__global__ void add_diag_bf16_k(int nact, int np, const double* __restrict__ d, u16* __restrict__ Wh,
+__global__ void add_diag_bf16_k(int nact, int np, int ks, const double* __restrict__ d, u16* __restrict__ Wh,
                                 u16* __restrict__ Wl, int ldw, long long pstride) {
-  GRID_STRIDE(i, (long long)np * nact) {
+  const long long slab = (long long)np * nact;
+  GRID_STRIDE(i, slab) {
     const long long P = i / nact;
     const int p = (int)(i % nact);
     const long long o = P * pstride + (long long)p * ldw + p;
-    double w = (double)bf16_bits_to_f32(Wh[o]) + (Wl ? (double)bf16_bits_to_f32(Wl[o]) : 0.0) + d[i];
+    double w = (double)bf16_bits_to_f32(Wh[o]) + (Wl ? (double)bf16_bits_to_f32(Wl[o]) : 0.0) +
+               sum_slabs(d, ks, slab, i);
     u16 h, l;
     split_f64(w, h, l);
     Wh[o] = h;
@@ -675,16 +686,18 @@ hipError_t hpp_from_hc(hipStream_t s, int nbf, int nact, const double* C, const 
 hipError_t add_diag_f64(hipStream_t s, int nact, int np, const double* Dc, const double* alpha, double* dbuf,
                         double* W, int ldw) {
   if (np <= 0) return hipSuccess;
-  hipError_t e = gemm_f64(s, np, nact, nact, 1, 1.0, Dc, nact, 1, 0, alpha, nact, 1, 0, 0.0, dbuf, nact, 1, 0);
+  const int ks = gemm_f64_ksplit(np, nact, nact);
+  hipError_t e = gemm_f64_splitk(s, np, nact, nact, ks, Dc, nact, 1, alpha, nact, 1, dbuf);
   if (e != hipSuccess) return e;
-  LAUNCH(add_diag_f64_k, grid1((long long)np * nact), dim3(NT), nact, np, dbuf, W, ldw);
+  LAUNCH(add_diag_f64_k, grid1((long long)np * nact), dim3(NT), nact, np, ks, dbuf, W, ldw);
 }
 hipError_t add_diag_bf16(hipStream_t s, int nact, int np, const double* Dc, const double* alpha, double* dbuf,
                          u16* Wh, u16* Wl, int ldw, long long pstride) {
   if (np <= 0) return hipSuccess;
-  hipError_t e = gemm_f64(s, np, nact, nact, 1, 1.0, Dc, nact, 1, 0, alpha, nact, 1, 0, 0.0, dbuf, nact, 1, 0);
+  const int ks = gemm_f64_ksplit(np, nact, nact);
+  hipError_t e = gemm_f64_splitk(s, np, nact, nact, ks, Dc, nact, 1, alpha, nact, 1, dbuf);
   if (e != hipSuccess) return e;
-  LAUNCH(add_diag_bf16_k, grid1((long long)np * nact), dim3(NT), nact, np, dbuf, Wh, Wl, ldw, pstride);
+  LAUNCH(add_diag_bf16_k, grid1((long long)np * nact), dim3(NT), nact, np, ks, dbuf, Wh, Wl, ldw, pstride);
 }
 hipError_t nofmp2_terms(hipStream_t s, int nact, int npairs, int ncwo, int nsingle, const double* n,
                         const double* Hpp, const double* J, const double* K, double* partials, double* E_hf,
