@@ -343,14 +343,14 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
       const long long nct = (long long)pl.nact32 * pl.ldk, nxt = (long long)pl.pc * pl.nact32 * pl.ldx,
                       nw = (long long)pl.pc * pl.nact32 * pl.ldw;
       wd = WsDims{pl.nact32, 2 * nct, 2 * nxt, 2 * nw};
-      // the zero pads of the tiles are part of the contract of the contraction kernels
-      DEV_CHECK(ctx, fill_u16(s, b.cth, nct, 0));
-      DEV_CHECK(ctx, fill_u16(s, b.xth, nxt, 0));
-      DEV_CHECK(ctx, fill_u16(s, b.wh, nw, 0));
-      if (pl.terms > 1) {
-        DEV_CHECK(ctx, fill_u16(s, b.ctl, nct, 0));
-        DEV_CHECK(ctx, fill_u16(s, b.xtl, nxt, 0));
-        DEV_CHECK(ctx, fill_u16(s, b.wl, nw, 0));
+      // the zero pads of the tiles are part of the contract of the contraction kernels; the valid
+      // blocks (Ct: nact x nbf, XT_P: nact x nbf, W_P: nact x nact) are overwritten in full before
+      // they are read, so only the pads are cleared
+      const long long sx = (long long)pl.nact32 * pl.ldx, sw = (long long)pl.nact32 * pl.ldw;
+      for (int lo = 0; lo < (pl.terms > 1 ? 2 : 1); ++lo) {
+        DEV_CHECK(ctx, zero_pads_u16(s, lo ? b.ctl : b.cth, 1, nct, nact, pl.nact32, pl.ldk, nbf));
+        DEV_CHECK(ctx, zero_pads_u16(s, lo ? b.xtl : b.xth, pl.pc, sx, nact, pl.nact32, pl.ldx, nbf));
+        DEV_CHECK(ctx, zero_pads_u16(s, lo ? b.wl : b.wh, pl.pc, sw, nact, pl.nact32, pl.ldw, nact));
       }
       DEV_CHECK(ctx, split_ca(s, nbf, nact, pl.terms, C, b.cth, b.ctl, pl.ldk));
       corr_terms = pl.terms > 1 ? 2 : 1;

@@ -252,6 +252,9 @@ hipError_t batch_finish(hipStream_t s, int ninst, const BInst* tab, const BMax& 
 // ---------------------------------------------------------------- small kernels (k_small.hip)
 hipError_t fill_f64(hipStream_t s, double* p, long long n, double v);
 hipError_t fill_u16(hipStream_t s, u16* p, long long n, u16 v);
+// zero columns [cols, ld) of rows [0, rows) and rows [rows, rows_pad) of nslice slices
+hipError_t zero_pads_u16(hipStream_t s, u16* base, int nslice, long long sstride, int rows, int rows_pad, int ld,
+                         int cols);
 hipError_t coeffs(hipStream_t s, int nact, int npairs, int ncwo, int nsingle, int functional, const double* n,
                   double* alpha, double* beta, float* beta32);
 hipError_t transpose_ca(hipStream_t s, int nbf, int nact, const double* C, double* Ct, int ldk);

@@ -21,6 +21,25 @@ inline dim3 grid1(long long n, int per = NT) {
 __global__ void fill_f64_k(double* p, long long n, double v) { GRID_STRIDE(i, n) p[i] = v; }
 __global__ void fill_u16_k(u16* p, long long n, u16 v) { GRID_STRIDE(i, n) p[i] = v; }
 
+// Zero the pads of nslice row-major slices (slice stride sstride): columns [cols, ld) of rows
+// [0, rows), and rows [rows, rows_pad) in full.
+__global__ void zero_pads_u16_k(u16* __restrict__ base, int nslice, long long sstride, int rows, int rows_pad, int ld,
+                                int cols) {
+  const long long side = (long long)rows * (ld - cols), per = side + (long long)(rows_pad - rows) * ld;
+  GRID_STRIDE(i, (long long)nslice * per) {
+    const long long sl = i / per, j = i % per;
+    long long r, c;
+    if (j < side) {
+      r = j / (ld - cols);
+      c = cols + j % (ld - cols);
+    } else {
+      r = rows + (j - side) / ld;
+      c = (j - side) % ld;
+    }
+    base[sl * sstride + r * ld + c] = 0;
+  }
+}
+
 // alpha, beta of E_2 = sum_pq alpha_pq J_pq + beta_pq K_pq (Eqs. Eg, Efg, Efg_s).
 __global__ void coeffs_k(int nact, int npairs, int ncwo, int nsingle, int functional, const double* __restrict__ n,
                          double* __restrict__ alpha, double* __restrict__ beta, float* __restrict__ beta32) {
@@ -664,6 +683,14 @@ hipError_t fill_f64(hipStream_t s, double* p, long long n, double v) {
 hipError_t fill_u16(hipStream_t s, u16* p, long long n, u16 v) {
   if (n <= 0) return hipSuccess;
   LAUNCH(fill_u16_k, grid1(n), dim3(NT), p, n, v);
+}
+hipError_t zero_pads_u16(hipStream_t s, u16* base, int nslice, long long sstride, int rows, int rows_pad, int ld,
+                         int cols) {
+  if (nslice <= 0 || rows < 0 || rows_pad < rows || cols < 0 || ld < cols || sstride < (long long)rows_pad * ld)
+    return hipErrorInvalidValue;
+  const long long n = (long long)nslice * ((long long)rows * (ld - cols) + (long long)(rows_pad - rows) * ld);
+  if (n == 0) return hipSuccess;
+  LAUNCH(zero_pads_u16_k, grid1(n), dim3(NT), base, nslice, sstride, rows, rows_pad, ld, cols);
 }
 hipError_t coeffs(hipStream_t s, int nact, int npairs, int ncwo, int nsingle, int functional, const double* n,
                   double* alpha, double* beta, float* beta32) {
