@@ -111,8 +111,10 @@ pnof_status pnof_set_workspace(pnof_ctx ctx, void* dev, size_t bytes);
  *   pchunk     rows of B processed per pass;
  *   nsplit_b   P-groups of the b / K contraction (each group keeps its own K partial sums);
  *   nsplit_y   P-groups of the Y contraction (each group keeps its own Y partial sums);
- *   x_variant, y_variant  block-tile shape of the bf16 X and Y contractions: 0 = 128 x 128 (two
- *              blocks per compute unit), 1 = 128 x 256 / 256 x 128 (one block per compute unit).
+ *   x_variant, y_variant  block-tile shape of the bf16 X and Y contractions: 1 = 128 x 128 (two
+ *              blocks per compute unit), 2 = 128 x 256 / 256 x 128, 3 = 256 x 256 with 8 waves
+ *              (one block per compute unit).  Automatic: 3 when it pads the output no more than 128
+ *              tiles do and both extents reach 512, else 1.  The float64 path ignores them.
  * Results do not depend on them beyond floating-point rounding order.  pnof_get_plan returns the
  * values a call on `prob` would use. */
 typedef struct {

@@ -29,8 +29,13 @@ def _bucket(x: int) -> int:
     return int(2 ** e * (1 + math.floor(4 * (x / 2 ** e - 1)) / 4))
 
 
+# bumped whenever the meaning of a tuning field changes, so stale entries are not applied
+SCHEMA = 2
+
+
 def key(prob, arch: str) -> str:
-    return f"{arch}:p{prob.precision}:i{prob.ints}:nbf{_bucket(prob.nbf)}:nact{_bucket(prob.nact)}:naux{_bucket(prob.naux)}"
+    return (f"v{SCHEMA}:{arch}:p{prob.precision}:i{prob.ints}:nbf{_bucket(prob.nbf)}:nact{_bucket(prob.nact)}"
+            f":naux{_bucket(prob.naux)}")
 
 
 def _arch(device) -> str:
@@ -68,6 +73,14 @@ def _time(ctx: Context, prob, run, reps: int) -> dict:
     return {"wall": wall, **{k: v[0] / reps for k, v in st.items()}}
 
 
+def apply_cached(ctx: Context, prob) -> dict | None:
+    """Set the cached tuning of `prob` on `ctx` if the cache holds one (else leave the automatic plan);
+    returns the entry or None."""
+    ent = load_cache().get(key(prob, _arch(ctx.device)))
+    ctx.set_tuning(ent["tuning"] if ent else None)
+    return ent
+
+
 def tune(ctx: Context, prob, run, reps: int = 2, use_cache: bool = True, verbose: bool = False) -> dict:
     """Pick launch parameters for `prob`; `run()` performs one library call on that problem."""
     arch = _arch(ctx.device)
@@ -97,12 +110,23 @@ def tune(ctx: Context, prob, run, reps: int = 2, use_cache: bool = True, verbose
         if r["wall"] < cur["wall"]:
             best, cur = ctx.plan(prob), r
     ctx.set_tuning(Tuning(**best))
-    # per-stage parameters, each judged on its own stage time
-    for field, stage, cands in (("x_variant", "X", [0, 1]), ("y_variant", "Y", [0, 1]),
-                                ("nsplit_b", "b", [best["nsplit_b"] // 2, best["nsplit_b"] * 2]),
-                                ("nsplit_y", "Y", [best["nsplit_y"] // 2, best["nsplit_y"] * 2])):
+    # per-stage parameters, each judged on its own stage time; a Y tile variant is tried with the
+    # P-split count the planner picks for it (the right count scales with the variant's tile count)
+    for field, stage, cands in (("x_variant", "X", [1, 2, 3]), ("y_variant", "Y", [1, 2, 3])):
         for v in cands:
-            if v == best[field] or v < 0 or (field.startswith("nsplit") and (v < 1 or v > best["pchunk"])):
+            if v == best[field]:
+                continue
+            trial = dict(best, **{field: v})
+            if field == "y_variant":
+                ctx.set_tuning(Tuning(**dict(trial, nsplit_y=0)))
+                trial["nsplit_y"] = ctx.plan(prob)["nsplit_y"]
+            r = measure(trial)
+            if r[stage] < cur[stage] * 0.98:
+                best, cur = trial, r
+    for field, stage in (("nsplit_b", "b"), ("nsplit_y", "Y")):
+        b0 = best[field]
+        for v in (b0 // 2, b0 - 1, b0 + 1, b0 * 2):
+            if v == best[field] or v < 1 or v > best["pchunk"]:
                 continue
             r = measure(dict(best, **{field: v}))
             if r[stage] < cur[stage] * 0.98:

@@ -141,8 +141,6 @@ Plan make_plan(const pnof_problem* p, const pnof_tuning& tu) {
   pl.ints = p->ints;
   pl.split = (p->precision != PNOF_FP64);
   pl.terms = p->precision == PNOF_BF16_SPLIT ? 3 : 1;
-  pl.xv = pl.split ? (tu.x_variant == 1) : 0;
-  pl.yv = pl.split ? (tu.y_variant == 1) : 0;
   const int tile = pl.split ? 128 : 64;
   // workspace rows padded to multiples of 32 (zero pads): whole k-tiles never need masking
   pl.ldk = (int)round_up(pl.nbf, 32);
@@ -150,8 +148,21 @@ Plan make_plan(const pnof_problem* p, const pnof_tuning& tu) {
   pl.ldxx = (int)round_up(pl.nact, 32);
   pl.ldw = (int)round_up(pl.nact, 32);
   pl.nact32 = (int)round_up(pl.nact, 32);
-  if (!is_df(p->ints)) { pl.pc = pl.ns2 = pl.ns3 = 1; return pl; }
-  const long long t1 = (long long)cdiv(pl.nact, tile) * cdiv(pl.nbf, pl.xv ? 256 : tile);
+  if (!is_df(p->ints)) { pl.pc = pl.ns2 = pl.ns3 = 1; pl.xv = pl.yv = 1; return pl; }
+  // block tiles of the split contractions: the 256 x 256 tile (variant 3) halves the LDS and operand
+  // traffic per product, and is the automatic choice when it pads the output no more than the 128
+  // tiling does (within 5 %) and both extents reach 512
+  auto pick = [&](int req, int m, int n) {
+    if (!pl.split) return 1;
+    if (req > 0) return req;
+    const double a128 = (double)round_up(m, 128) * round_up(n, 128), a256 = (double)round_up(m, 256) * round_up(n, 256);
+    return (m >= 512 && n >= 512 && a256 <= 1.05 * a128) ? 3 : 1;
+  };
+  pl.xv = pick(tu.x_variant, pl.nact, pl.nbf);
+  pl.yv = pick(tu.y_variant, pl.nbf, pl.nact);
+  const int xm = pl.xv == 3 ? 256 : tile, xn = pl.xv >= 2 ? 256 : tile;
+  const int ym = pl.yv >= 2 ? 256 : tile, yn = pl.yv == 3 ? 256 : tile;
+  const long long t1 = (long long)cdiv(pl.nact, xm) * cdiv(pl.nbf, xn);
   // enough blocks per launch to fill the chip, and enough rows per chunk that the per-split K
   // partials (ns2 x nact^2, read-modified-written once per chunk) stay small next to X and W
   long long pc = tu.pchunk > 0 ? tu.pchunk : std::max(64LL, (4096 + t1 - 1) / t1);
@@ -167,8 +178,11 @@ Plan make_plan(const pnof_problem* p, const pnof_tuning& tu) {
   const long long ntri = (long long)tt * (tt + 1) / 2;
   pl.ns2 = tu.nsplit_b > 0 ? tu.nsplit_b : (int)std::max(1LL, (1024 + ntri - 1) / ntri);
   pl.ns2 = std::min(pl.ns2, pl.pc);
-  const long long t3 = (long long)cdiv(pl.nbf, pl.yv ? 256 : tile) * cdiv(pl.nact, tile);
-  pl.ns3 = tu.nsplit_y > 0 ? tu.nsplit_y : (int)std::max(1LL, (1024 + t3 - 1) / t3);
+  // Y: as many P-splits as fit the chip's resident blocks in one round (MI355X: 256 compute units;
+  // the 128 x 128 bf16 tile runs two blocks per unit); the float64 form takes about 1024 blocks
+  const long long t3 = (long long)cdiv(pl.nbf, ym) * cdiv(pl.nact, yn);
+  const long long auto3 = pl.split ? std::max(1LL, (pl.yv == 1 ? 512 : 256) / t3) : std::max(1LL, (1024 + t3 - 1) / t3);
+  pl.ns3 = tu.nsplit_y > 0 ? tu.nsplit_y : (int)auto3;
   pl.ns3 = std::min(pl.ns3, pl.pc);
   return pl;
 }
@@ -843,8 +857,8 @@ pnof_status pnof_set_tuning(pnof_ctx ctx, const pnof_tuning* t) {
     ctx->tune = pnof_tuning{0, 0, 0, 0, 0};
     return PNOF_OK;
   }
-  if (t->pchunk < 0 || t->nsplit_b < 0 || t->nsplit_y < 0 || t->x_variant < 0 || t->x_variant > 1 ||
-      t->y_variant < 0 || t->y_variant > 1)
+  if (t->pchunk < 0 || t->nsplit_b < 0 || t->nsplit_y < 0 || t->x_variant < 0 || t->x_variant > 3 ||
+      t->y_variant < 0 || t->y_variant > 3)
     return fail(ctx, PNOF_E_ARG, "tuning values out of range");
   ctx->tune = *t;
   return PNOF_OK;
@@ -1353,9 +1367,9 @@ pnof_status pnof_batch_bind(pnof_batch b, const pnof_batch_io* io) {
     g2[i] = G2Args{g.nbf, g.nact, g.naux, g.ns2, d.cth, d.ctl, g.ldk, d.xth, d.xtl, g.ldk, d.beta32, d.Kpart, d.D,
                    d.wh, d.wl, g.ldw, wd};
     g3[i] = G3Args{g.nbf, g.nact, g.naux, g.ns3, d.xth, d.xtl, g.ldk, d.wh, d.wl, g.ldw, d.Ypart, wd};
-    off[i + 1] = off[i] + g1_items(g1[i], 128, true);
+    off[i + 1] = off[i] + g1_items(g1[i], 128, 128, true);
     off[(n + 1) + i + 1] = off[(n + 1) + i] + g2_items(g2[i]);
-    off[2 * (n + 1) + i + 1] = off[2 * (n + 1) + i] + g3_items(g3[i], 128);
+    off[2 * (n + 1) + i + 1] = off[2 * (n + 1) + i] + g3_items(g3[i], 128, 128);
     f[i] = F64Gemm{g.nbf, g.nact, g.nbf, 1.0, d.H, g.nbf, 1, d.C, g.nbf, 1, 0.0, d.HC, g.nact, 1};
     f[n + i] = F64Gemm{g.naux, g.nact, g.nact, 1.0, d.D, g.nact, 1, d.alpha, g.nact, 1, 0.0, d.dbuf, g.nact, 1};
     f[2 * n + i] = F64Gemm{g.nact, g.nact, g.naux, 1.0, d.D, 1, g.nact, d.D, g.nact, 1, 0.0, d.J, g.nact, 1};

@@ -188,16 +188,19 @@ struct G3Args {   // Ypart[s] = sum_{P in s} X_P W_P
 };
 // Work items of one launch.  The stacked form of X treats the rows (P, mu) of np consecutive B_P
 // as one matrix (B_P rows padded to ldb, bstride == nbf * ldb), so short rows do not waste tiles.
-__host__ __device__ inline int g1_items(const G1Args& a, int g1n, bool stacked) {
-  return cdiv(a.nact, 128) * (stacked ? cdiv((long long)a.np * a.nbf, g1n) : a.np * cdiv(a.nbf, g1n));
+// g1m x g1n: the block tile along (p, mu); grid and kernel must use the same values.
+__host__ __device__ inline int g1_items(const G1Args& a, int g1m, int g1n, bool stacked) {
+  return cdiv(a.nact, g1m) * (stacked ? cdiv((long long)a.np * a.nbf, g1n) : a.np * cdiv(a.nbf, g1n));
 }
 __host__ __device__ inline int g2_items(const G2Args& a) {
   const int t = cdiv(a.nact, 128);
   return a.nsplit * t * (t + 1) / 2;
 }
-// g3m: the block tile along mu (128, or 256 for the wide variant); the launch grid and the kernel's
-// decoding of its block index must use the same value.
-__host__ __device__ inline int g3_items(const G3Args& a, int g3m) { return a.nsplit * cdiv(a.nbf, g3m) * cdiv(a.nact, 128); }
+// g3m x g3n: the block tile along (mu, q); the launch grid and the kernel's decoding of its block
+// index must use the same values.
+__host__ __device__ inline int g3_items(const G3Args& a, int g3m, int g3n) {
+  return a.nsplit * cdiv(a.nbf, g3m) * cdiv(a.nact, g3n);
+}
 
 // Grouped launches over the instances of a batch: tab[i] are the arguments of instance i (device
 // memory), off[i] the first work item of instance i (off[ninst] = total).  terms as above;

@@ -473,14 +473,15 @@ __device__ __forceinline__ int find_instance(const int* __restrict__ off, int ni
   return lo;
 }
 
-// gemm1: XT_P[p][mu] = sum_nu Ct[p][nu] B_P[mu][nu], written as a hi/lo pair.  Tile 128 (p) x G1N (mu),
-// one P per work item (items covering several P measured slower: the epilogue's stores then stall
-// the next P's operand waits, as the vector-memory counter retires loads and stores in order).
+// gemm1: XT_P[p][mu] = sum_nu Ct[p][nu] B_P[mu][nu], written as a hi/lo pair.  Tile G1M (p) x G1N (mu)
+// in a WGM x WGN wave grid, one P per work item (items covering several P measured slower: the
+// epilogue's stores then stall the next P's operand waits, as the vector-memory counter retires loads
+// and stores in order).
 // STACK: the n-tiles run over the stacked rows (P, mu) of all np rows of B.
-template <int TERMS, bool BLO, int G1N, int MINB, bool VEC, bool STACK>
+template <int TERMS, bool BLO, int G1M, int G1N, int WGM, int WGN, int MINB, bool VEC, bool STACK>
 __device__ __forceinline__ void gemm1_body(int w, const G1Args& g) {
   constexpr bool ALO = TERMS >= 2;
-  constexpr int G1M = 128;
+  constexpr int MI = G1M / (16 * WGM), NI = G1N / (16 * WGN);
   const int nbf = g.nbf, nact = g.nact, ldx = g.ldx;
   const int tm_n = (nact + G1M - 1) / G1M;
   int P = 0, m0, n0;
@@ -498,26 +499,26 @@ __device__ __forceinline__ void gemm1_body(int w, const G1Args& g) {
   u16* XTh = g.xt_hi + (STACK ? 0 : P * pstride);
   u16* XTl = g.xt_lo ? g.xt_lo + (STACK ? 0 : P * pstride) : nullptr;
   const long long nrows = (long long)g.np * nbf;
-  f32x4 acc[G1M / 32][G1N / 32];
-  auto epi = [&](int, f32x4(&a)[G1M / 32][G1N / 32]) {
+  f32x4 acc[MI][NI];
+  auto epi = [&](int, f32x4(&a)[MI][NI]) {
 #pragma unroll
-    for (int i = 0; i < G1M / 32; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
-      for (int jn = 0; jn < G1N / 32; ++jn) {
+      for (int jn = 0; jn < NI; ++jn) {
         long long xo;
         if constexpr (STACK) {
-          const int c = n0 + col_of<G1N>(jn);
+          const int c = n0 + col_of<G1N, WGM, WGN>(jn);
           if (c >= nrows) continue;
           const int Pc = c / nbf;
           xo = Pc * pstride + (c - Pc * nbf);
         } else {
-          const int mu = n0 + col_of<G1N>(jn);
+          const int mu = n0 + col_of<G1N, WGM, WGN>(jn);
           if (mu >= nbf) continue;
           xo = mu;
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int p = m0 + row_of<G1M>(i, j);
+          const int p = m0 + row_of<G1M, WGM, WGN>(i, j);
           if (p >= nact) continue;
           u16 h, l;
           if (TERMS == 1) { h = f32_to_bf16_bits(a[i][jn][j]); l = 0; }
@@ -536,8 +537,9 @@ __device__ __forceinline__ void gemm1_body(int w, const G1Args& g) {
       const long long o = (long long)P * g.bstride;
       return DOpnd{g.b_hi + o, BLO ? g.b_lo + o : nullptr, g.ldb, g.b_bytes - 2 * o};
     };
-    mainloop_dl<G1M, G1N, ALO, BLO, S, false, false, true>(sm, 1, 0, nbf, m0, n0, A, B, acc, epi);
+    mainloop_dl<G1M, G1N, ALO, BLO, S, false, false, true, WGM, WGN>(sm, 1, 0, nbf, m0, n0, A, B, acc, epi);
   } else {
+    static_assert(VEC || (WGM == 2 && WGN == 2), "register-staged path: 2 x 2 waves");
     __shared__ Stage<G1M, G1N, ALO, BLO> sm;
     auto A = [&](int) { return Opnd{g.ct_hi, g.ct_lo, g.ldk, nact, nbf, false}; };
     auto B = [&](int) {
@@ -668,11 +670,14 @@ __device__ __forceinline__ void gemm2_body(int w, const G2Args& g) {
 // gemm3: Ypart[s][mu][q] = sum_{P in s} sum_r XT_P[r][mu] W_P[q][r].  XT is read as a col operand,
 // W (stored in full) as a row operand; every block walks (P, r) in the same order, so blocks of one
 // split that share an operand panel read it at about the same time.
-// Tile G3M (mu) x 128 (q).
-template <int TERMS, int G3M, bool VEC>
+// Tile G3M (mu) x G3N (q), waves in a WGM x WGN grid.  Each wave's share of the tile sets how many
+// matrix-core products one byte read from LDS feeds: a 64 x 64 wave reads 16 KB per k-tile for 48
+// products, a 128 x 64 wave 24 KB for 96; LDS bandwidth (about 128 bytes per clock per compute unit)
+// is what limits the 64 x 64 form.
+template <int TERMS, int G3M, int G3N, int WGM, int WGN, int MINB, bool VEC>
 __device__ __forceinline__ void gemm3_body(int w, const G3Args& g) {
   constexpr bool LO = TERMS >= 3;
-  constexpr int G3N = T2;
+  constexpr int MI = G3M / (16 * WGM), NI = G3N / (16 * WGN);
   const int nbf = g.nbf, nact = g.nact, np = g.np, nsplit = g.nsplit, ldx = g.ldx, ldw = g.ldw;
   const int tm_n = (nbf + G3M - 1) / G3M, tn_n = (nact + G3N - 1) / G3N;
   const int s = w / (tm_n * tn_n);
@@ -680,13 +685,13 @@ __device__ __forceinline__ void gemm3_body(int w, const G3Args& g) {
   grouped_tile<4>(w % (tm_n * tn_n), tm_n, tn_n, tm, tn);
   const int m0 = tm * G3M, n0 = tn * G3N;
   const int pb = (int)((long long)np * s / nsplit), pe = (int)((long long)np * (s + 1) / nsplit);
-  f32x4 acc[G3M / 32][G3N / 32];
+  f32x4 acc[MI][NI];
   zero(acc);
-  auto none = [&](int, f32x4(&)[G3M / 32][G3N / 32]) {};
+  auto none = [&](int, f32x4(&)[MI][NI]) {};
   if constexpr (VEC) {
-    // the 128-row tile runs two blocks per compute unit (two-stage ring each): while one block waits
-    // on its fragment reads or barrier, the other keeps the matrix cores busy
-    constexpr int S = ring_depth(G3M, G3N, LO, LO, G3M == 128 ? 81920 : 163840);
+    // the 128 x 128 tile runs two blocks per compute unit (two-stage ring each): while one block
+    // waits on its fragment reads or barrier, the other keeps the matrix cores busy
+    constexpr int S = ring_depth(G3M, G3N, LO, LO, MINB == 2 ? 81920 : 163840);
     __shared__ Ring<G3M, G3N, LO, LO, S> sm;
     auto A = [&](int seg) {
       const long long off = (long long)(pb + seg) * g.ws.nact32 * ldx;
@@ -696,8 +701,9 @@ __device__ __forceinline__ void gemm3_body(int w, const G3Args& g) {
       const long long off = (long long)(pb + seg) * g.ws.nact32 * ldw;
       return DOpnd{g.w_hi + off, LO ? g.w_lo + off : nullptr, ldw, g.ws.w_bytes - 2 * off};
     };
-    mainloop_dl<G3M, G3N, LO, LO, S, true, false, false>(sm, pe - pb, 0, nact, m0, n0, A, B, acc, none);
+    mainloop_dl<G3M, G3N, LO, LO, S, true, false, false, WGM, WGN>(sm, pe - pb, 0, nact, m0, n0, A, B, acc, none);
   } else {
+    static_assert(VEC || (WGM == 2 && WGN == 2), "register-staged path: 2 x 2 waves");
     __shared__ Stage<G3M, G3N, LO, LO> sm;
     auto A = [&](int seg) {
       const long long off = (long long)(pb + seg) * g.ws.nact32 * ldx;
@@ -711,21 +717,21 @@ __device__ __forceinline__ void gemm3_body(int w, const G3Args& g) {
   }
   float* Y = g.Ypart + (long long)s * nbf * nact;
 #pragma unroll
-  for (int i = 0; i < G3M / 32; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
-    for (int jn = 0; jn < G3N / 32; ++jn)
+    for (int jn = 0; jn < NI; ++jn)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int m = m0 + row_of<G3M>(i, j), n = n0 + col_of<G3N>(jn);
+        const int m = m0 + row_of<G3M, WGM, WGN>(i, j), n = n0 + col_of<G3N, WGM, WGN>(jn);
         if (m < nbf && n < nact) Y[(long long)m * nact + n] = acc[i][jn][j];
       }
 }
 
-template <int TERMS, bool BLO, int G1N, int MINB, bool VEC>
-__global__ __launch_bounds__(256, MINB) void gemm1_kernel(G1Args g) {
-  const int w = xcd_item(g1_items(g, G1N, false));
+template <int TERMS, bool BLO, int G1M, int G1N, int WGM, int WGN, int MINB, bool VEC>
+__global__ __launch_bounds__(64 * WGM * WGN, MINB) void gemm1_kernel(G1Args g) {
+  const int w = xcd_item(g1_items(g, G1M, G1N, false));
   if (w < 0) return;
-  gemm1_body<TERMS, BLO, G1N, MINB, VEC, false>(w, g);
+  gemm1_body<TERMS, BLO, G1M, G1N, WGM, WGN, MINB, VEC, false>(w, g);
 }
 template <int TERMS, bool VEC>
 __global__ __launch_bounds__(128 * g2_wgn(VEC), 1) void gemm2_kernel(G2Args g) {
@@ -733,11 +739,11 @@ __global__ __launch_bounds__(128 * g2_wgn(VEC), 1) void gemm2_kernel(G2Args g) {
   if (w < 0) return;
   gemm2_body<TERMS, VEC>(w, g);
 }
-template <int TERMS, int G3M, int MINB, bool VEC>
-__global__ __launch_bounds__(256, MINB) void gemm3_kernel(G3Args g) {
-  const int w = xcd_item(g3_items(g, G3M));
+template <int TERMS, int G3M, int G3N, int WGM, int WGN, int MINB, bool VEC>
+__global__ __launch_bounds__(64 * WGM * WGN, MINB) void gemm3_kernel(G3Args g) {
+  const int w = xcd_item(g3_items(g, G3M, G3N));
   if (w < 0) return;
-  gemm3_body<TERMS, G3M, VEC>(w, g);
+  gemm3_body<TERMS, G3M, G3N, WGM, WGN, MINB, VEC>(w, g);
 }
 
 // Grouped forms: one launch over the work items of every instance of a batch.
@@ -748,7 +754,7 @@ __global__ __launch_bounds__(256, 1) void gemm1_grouped(const G1Args* __restrict
   if (w < 0) return;
   const int i = find_instance(off, ninst, w);
   const G1Args g = tab[i];
-  gemm1_body<TERMS, false, 128, 1, true, true>(w - off[i], g);
+  gemm1_body<TERMS, false, 128, 128, 2, 2, 1, true, true>(w - off[i], g);
 }
 template <int TERMS>
 __global__ __launch_bounds__(128 * g2_wgn(true), 1) void gemm2_grouped(const G2Args* __restrict__ tab, const int* __restrict__ off,
@@ -766,7 +772,7 @@ __global__ __launch_bounds__(256, 2) void gemm3_grouped(const G3Args* __restrict
   if (w < 0) return;
   const int i = find_instance(off, ninst, w);
   const G3Args g = tab[i];
-  gemm3_body<TERMS, 128, true>(w - off[i], g);
+  gemm3_body<TERMS, 128, 128, 2, 2, 2, true>(w - off[i], g);
 }
 
 inline dim3 xcd_grid(long long items) { return dim3((unsigned)(cdiv(items, NXCD) * NXCD)); }
@@ -774,15 +780,30 @@ inline dim3 xcd_grid(long long items) { return dim3((unsigned)(cdiv(items, NXCD)
 }  // namespace
 
 inline bool al16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
-template <int TERMS, bool BLO, int G1N, int MINB>
+template <int TERMS, bool BLO, int G1M, int G1N, int WGM, int WGN, int MINB>
 static void launch_g1(hipStream_t s, const G1Args& g) {
-  const dim3 grid = xcd_grid(g1_items(g, G1N, false));
+  const dim3 grid = xcd_grid(g1_items(g, G1M, G1N, false));
   // direct-to-LDS needs 16-byte aligned rows of the caller's B (nbf % 8 == 0)
   const bool vec = (g.ldb % 8 == 0) && (g.nbf % 8 == 0) && (g.bstride % 8 == 0) && al16(g.b_hi) &&
                    (!g.b_lo || al16(g.b_lo)) && al16(g.ct_hi) && (!g.ct_lo || al16(g.ct_lo)) && (g.ldk % 32 == 0) &&
                    (g.ldx % 32 == 0);
-  if (vec) hipLaunchKernelGGL((gemm1_kernel<TERMS, BLO, G1N, MINB, true>), grid, dim3(256), 0, s, g);
-  else hipLaunchKernelGGL((gemm1_kernel<TERMS, BLO, G1N, MINB, false>), grid, dim3(256), 0, s, g);
+  // operands without aligned rows take the register-staged 128 x 128 form whatever the variant
+  if (vec)
+    hipLaunchKernelGGL((gemm1_kernel<TERMS, BLO, G1M, G1N, WGM, WGN, MINB, true>), grid, dim3(64 * WGM * WGN), 0, s, g);
+  else
+    hipLaunchKernelGGL((gemm1_kernel<TERMS, BLO, 128, 128, 2, 2, 2, false>), xcd_grid(g1_items(g, 128, 128, false)),
+                       dim3(256), 0, s, g);
+}
+
+// variant (resolved by the planner): 1 = 128 x 128 (4 waves of 64 x 64, two blocks per CU),
+// 2 = 128 x 256 (4 waves of 64 x 128), 3 = 256 x 256 (8 waves of 128 x 64)
+template <int TERMS, bool BLO>
+static void launch_g1v(hipStream_t s, const G1Args& g, int variant) {
+  switch (variant) {
+    case 2: launch_g1<TERMS, BLO, 128, 256, 2, 2, 1>(s, g); break;
+    case 3: launch_g1<TERMS, BLO, 256, 256, 2, 4, 1>(s, g); break;
+    default: launch_g1<TERMS, BLO, 128, 128, 2, 2, 2>(s, g); break;
+  }
 }
 
 hipError_t df_bf16_gemm1(hipStream_t s, int nbf, int nact, int np, int terms, SplitPtr Ct, int ldk, SplitPtr Bp,
@@ -790,17 +811,9 @@ hipError_t df_bf16_gemm1(hipStream_t s, int nbf, int nact, int np, int terms, Sp
                          const WsDims& d) {
   if (np <= 0) return hipSuccess;
   const G1Args g{nbf, nact, np, Ct.hi, Ct.lo, ldk, Bp.hi, Bp.lo, bstride, ldb, b_bytes, XT_hi, XT_lo, ldx, d};
-  const bool wide = (variant == 1);
-  if (terms == 1) {
-    if (wide) launch_g1<1, false, 256, 1>(s, g);
-    else launch_g1<1, false, 128, 2>(s, g);
-  } else if (Bp.lo == nullptr) {
-    if (wide) launch_g1<2, false, 256, 1>(s, g);
-    else launch_g1<2, false, 128, 2>(s, g);
-  } else {
-    if (wide) launch_g1<3, true, 256, 1>(s, g);
-    else launch_g1<3, true, 128, 2>(s, g);
-  }
+  if (terms == 1) launch_g1v<1, false>(s, g, variant);
+  else if (Bp.lo == nullptr) launch_g1v<2, false>(s, g, variant);
+  else launch_g1v<3, true>(s, g, variant);
   return hipGetLastError();
 }
 
@@ -822,26 +835,36 @@ hipError_t df_bf16_gemm2(hipStream_t s, int nbf, int nact, int np, int nsplit, i
   return hipGetLastError();
 }
 
-template <int TERMS, int G3M, int MINB>
+template <int TERMS, int G3M, int G3N, int WGM, int WGN, int MINB>
 static void launch_g3(hipStream_t s, const G3Args& g) {
-  const dim3 grid = xcd_grid(g3_items(g, G3M));
+  const dim3 grid = xcd_grid(g3_items(g, G3M, G3N));
   const bool vec = (g.ldx % 32 == 0) && (g.ldw % 32 == 0) && al16(g.xt_hi) && (!g.xt_lo || al16(g.xt_lo)) &&
                    al16(g.w_hi) && (!g.w_lo || al16(g.w_lo));
-  if (vec) hipLaunchKernelGGL((gemm3_kernel<TERMS, G3M, MINB, true>), grid, dim3(256), 0, s, g);
-  else hipLaunchKernelGGL((gemm3_kernel<TERMS, G3M, MINB, false>), grid, dim3(256), 0, s, g);
+  // operands without aligned rows take the register-staged 128 x 128 form whatever the variant
+  if (vec) hipLaunchKernelGGL((gemm3_kernel<TERMS, G3M, G3N, WGM, WGN, MINB, true>), grid, dim3(64 * WGM * WGN), 0, s, g);
+  else
+    hipLaunchKernelGGL((gemm3_kernel<TERMS, 128, 128, 2, 2, 2, false>), xcd_grid(g3_items(g, 128, 128)), dim3(256), 0,
+                       s, g);
 }
 
 hipError_t df_bf16_gemm3(hipStream_t s, int nbf, int nact, int np, int nsplit, int terms, SplitPtr XT, int ldx,
                          SplitPtr W, int ldw, float* Ypart, int variant, const WsDims& d) {
   if (np <= 0) return hipSuccess;
   const G3Args g{nbf, nact, np, nsplit, XT.hi, XT.lo, ldx, W.hi, W.lo, ldw, Ypart, d};
-  const bool wide = (variant == 1);
+  // variant (resolved by the planner): 1 = 128 x 128 (4 waves of 64 x 64, two blocks per CU),
+  // 2 = 256 x 128 (4 waves of 128 x 64), 3 = 256 x 256 (8 waves of 128 x 64)
   if (terms == 1) {
-    if (wide) launch_g3<1, 256, 1>(s, g);
-    else launch_g3<1, 128, 1>(s, g);
+    switch (variant) {
+      case 2: launch_g3<1, 256, 128, 2, 2, 1>(s, g); break;
+      case 3: launch_g3<1, 256, 256, 2, 4, 1>(s, g); break;
+      default: launch_g3<1, 128, 128, 2, 2, 2>(s, g); break;
+    }
   } else {
-    if (wide) launch_g3<3, 256, 1>(s, g);
-    else launch_g3<3, 128, 2>(s, g);
+    switch (variant) {
+      case 2: launch_g3<3, 256, 128, 2, 2, 1>(s, g); break;
+      case 3: launch_g3<3, 256, 256, 2, 4, 1>(s, g); break;
+      default: launch_g3<3, 128, 128, 2, 2, 2>(s, g); break;
+    }
   }
   return hipGetLastError();
 }

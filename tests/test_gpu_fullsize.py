@@ -1,4 +1,6 @@
-"""Full-size parity on the configured workloads, in the launch configuration the benchmark times.
+"""Full-size parity on the configured workloads, in the launch configuration the benchmark times
+(the autotuner's cached launch parameters for the shape when the cache holds them, as the benchmark
+applies them; else the automatic plan).
 
 Expected values are the oracle's, stored by tests/golden/make_expected.py (FP64, streamed route,
 same seeded inputs).  B is generated on the device by the seeded filler (bit-identical to the host
@@ -14,6 +16,8 @@ import torch
 import synth
 
 P = pytest.importorskip("paper_2004_06142_amd")
+from paper_2004_06142_amd import autotune  # noqa: E402
+
 pytestmark = pytest.mark.gpu
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -56,6 +60,8 @@ def test_full_size_parity(ctx, name):
     res = {}
     for prec in (P.FP64, P.BF16_SPLIT):
         prob = P.problem(wl.nbf, wl.naux, wl.npairs, wl.ncwo, P.PNOF7, prec, kind)
+        ent = autotune.apply_cached(ctx, prob)
+        print(name, "prec", prec, "plan", ctx.plan(prob), "cached" if ent else "automatic")
         ctx.reserve(prob)
         n = ctx.on_map(gam, wl.npairs, wl.ncwo)
         out = ctx.lagrangian(prob, C, n, H, B, grads=True, jk=True)
@@ -73,6 +79,7 @@ def test_full_size_parity(ctx, name):
             "max_asym": abs(o["max_asym"][0] - ref["max_asym"]),
         }
         res[prec] = errs
+        ctx.set_tuning(None)
         print(name, "prec", prec, {k: f"{v:.2e}" for k, v in errs.items()})
     e64, emx = res[P.FP64], res[P.BF16_SPLIT]
     assert e64["E"] < 1e-8 and e64["lam"] < 1e-10 and e64["J"] < 1e-12 and e64["K"] < 1e-12
