@@ -27,16 +27,16 @@ KSRC = os.path.join(ROOT, "paper_2004_06142_amd", "csrc")
 # factor a plain 1 GiB elementwise copy gives, and the SHA-256 of the kernel source they were taken on:
 # once the source changes the figure no longer applies and traffic is reported as null.
 TRAFFIC = {
-    # profiles/c5_df1200_hbm_traffic.md: C5, bf16 split, 128-row chunks (read + written bytes per launch)
-    ("gemm1_kernel", 3): {"bytes": 2393830130 + 758834704,
-                          "plan": {"pchunk": 128, "x_variant": 0},
-                          "sha256": {"k_gemm_bf16.hip": "86d5263a36cc4ab9b37b90314c32194e650c753d7fe31b76054161bbd6e820d5"}},
-    ("gemm2_kernel", 3): {"bytes": 2411292054 + 878367456,
-                          "plan": {"pchunk": 128, "nsplit_b": 9},
-                          "sha256": {"k_gemm_bf16.hip": "86d5263a36cc4ab9b37b90314c32194e650c753d7fe31b76054161bbd6e820d5"}},
-    ("gemm3_kernel", 3): {"bytes": 4056725651 + 29187417,
-                          "plan": {"pchunk": 128, "nsplit_y": 5, "y_variant": 0},
-                          "sha256": {"k_gemm_bf16.hip": "86d5263a36cc4ab9b37b90314c32194e650c753d7fe31b76054161bbd6e820d5"}},
+    # profiles/c5_df1200_hbm_traffic.md: C5, bf16 split, 164-row chunks (read + written bytes per launch)
+    ("gemm1_kernel", 3): {"bytes": 1578956549 + 925472983,
+                          "plan": {"pchunk": 164, "x_variant": 3},
+                          "sha256": {"k_gemm_bf16.hip": "f913ca5d3cffdf3475185fb89843ba71174e5f5fb42a4604422b5f5cb0979431"}},
+    ("gemm2_kernel", 3): {"bytes": 3497199182 + 1133903226,
+                          "plan": {"pchunk": 164, "nsplit_b": 18},
+                          "sha256": {"k_gemm_bf16.hip": "f913ca5d3cffdf3475185fb89843ba71174e5f5fb42a4604422b5f5cb0979431"}},
+    ("gemm3_kernel", 3): {"bytes": 2746350622 + 232767068,
+                          "plan": {"pchunk": 164, "nsplit_y": 10, "y_variant": 3},
+                          "sha256": {"k_gemm_bf16.hip": "f913ca5d3cffdf3475185fb89843ba71174e5f5fb42a4604422b5f5cb0979431"}},
 }
 GOLDEN_C5 = os.path.join(ROOT, "tests", "golden", "c5_df1200_expected.json")
 
