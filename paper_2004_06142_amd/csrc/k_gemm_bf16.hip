@@ -344,8 +344,12 @@ struct Ring {
 
 // Contraction over segments seg = 0..nseg-1 and k in [kb, ke) of each; ACOL / BCOL fix the storage
 // order of the operands at compile time.
+// ILV: the k-tile's products run row block by row block (i-major), with the A fragments of block
+// i + 1 read while the products of block i issue, in an order pinned by scheduling groups: a wave
+// then waits only for its B fragments and first A block after the barrier, instead of for most of
+// the k-tile's fragment reads, and the LDS stays busy through the tile.
 template <int BM, int BN, bool ALO, bool BLO, int S, bool ACOL, bool BCOL, bool RESET, int WGM = 2, int WGN = 2,
-          typename FA, typename FB, typename EPI>
+          bool ILV = false, typename FA, typename FB, typename EPI>
 __device__ __forceinline__ void mainloop_dl(Ring<BM, BN, ALO, BLO, S>& sm, int nseg, int kb, int ke, int m0, int n0,
                                             FA A, FB B, f32x4 (&acc)[BM / (16 * WGM)][BN / (16 * WGN)], EPI epi) {
   constexpr int NW = WGM * WGN;   // waves in a WGM x WGN grid, each owning (BM / WGM) x (BN / WGN)
@@ -381,6 +385,44 @@ __device__ __forceinline__ void mainloop_dl(Ring<BM, BN, ALO, BLO, S>& sm, int n
       else __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
       __builtin_amdgcn_s_barrier();
       if (it + S - 1 < total) issue((stage + S - 1) % S);
+      if constexpr (ILV) {
+        // reads of one A block: 1 (row layout) or 2 (transposing) instructions per hi / lo part
+        constexpr int RA = (ACOL ? 2 : 1) * (ALO ? 2 : 1);
+        constexpr int RB = (BCOL ? 2 : 1) * (BLO ? 2 : 1) * NI;
+        constexpr int PR = NI * (1 + (BLO ? 1 : 0) + (ALO ? 1 : 0));   // products per A block
+        bf16x8 bh[NI], bl[NI], ah[2], al[2];
+#pragma unroll
+        for (int j = 0; j < NI; ++j) {
+          bh[j] = dl_frag<BN, BCOL>(sm.b[stage][0], wn + 16 * j);
+          if (BLO) bl[j] = dl_frag<BN, BCOL>(sm.b[stage][BLO ? 1 : 0], wn + 16 * j);
+        }
+        ah[0] = dl_frag<BM, ACOL>(sm.a[stage][0], wm);
+        if (ALO) al[0] = dl_frag<BM, ACOL>(sm.a[stage][ALO ? 1 : 0], wm);
+        __builtin_amdgcn_sched_group_barrier(0x100, RB + RA, 0);
+#pragma unroll
+        for (int i = 0; i < MI; ++i) {
+          const int c = i & 1, n = c ^ 1;
+          if (i + 1 < MI) {
+            ah[n] = dl_frag<BM, ACOL>(sm.a[stage][0], wm + 16 * (i + 1));
+            if (ALO) al[n] = dl_frag<BM, ACOL>(sm.a[stage][ALO ? 1 : 0], wm + 16 * (i + 1));
+            __builtin_amdgcn_sched_group_barrier(0x100, RA, 0);
+          }
+          // products in passes over j, so no two consecutive products share an accumulator
+#pragma unroll
+          for (int j = 0; j < NI; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[c], bh[j], acc[i][j], 0, 0, 0);
+          if (BLO) {
+#pragma unroll
+            for (int j = 0; j < NI; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[c], bl[j], acc[i][j], 0, 0, 0);
+          }
+          if (ALO) {
+#pragma unroll
+            for (int j = 0; j < NI; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[c], bh[j], acc[i][j], 0, 0, 0);
+          }
+          __builtin_amdgcn_sched_group_barrier(0x008, PR, 0);
+        }
+        stage = (stage + 1 == S) ? 0 : stage + 1;
+        continue;
+      }
       bf16x8 ah[MI], bh[NI];
 #pragma unroll
       for (int i = 0; i < MI; ++i) ah[i] = dl_frag<BM, ACOL>(sm.a[stage][0], wm + 16 * i);
@@ -537,7 +579,8 @@ __device__ __forceinline__ void gemm1_body(int w, const G1Args& g) {
       const long long o = (long long)P * g.bstride;
       return DOpnd{g.b_hi + o, BLO ? g.b_lo + o : nullptr, g.ldb, g.b_bytes - 2 * o};
     };
-    mainloop_dl<G1M, G1N, ALO, BLO, S, false, false, true, WGM, WGN>(sm, 1, 0, nbf, m0, n0, A, B, acc, epi);
+    mainloop_dl<G1M, G1N, ALO, BLO, S, false, false, true, WGM, WGN, (WGM * WGN == 8)>(sm, 1, 0, nbf, m0, n0, A, B, acc,
+                                                                                      epi);
   } else {
     static_assert(VEC || (WGM == 2 && WGN == 2), "register-staged path: 2 x 2 waves");
     __shared__ Stage<G1M, G1N, ALO, BLO> sm;
@@ -701,7 +744,8 @@ __device__ __forceinline__ void gemm3_body(int w, const G3Args& g) {
       const long long off = (long long)(pb + seg) * g.ws.nact32 * ldw;
       return DOpnd{g.w_hi + off, LO ? g.w_lo + off : nullptr, ldw, g.ws.w_bytes - 2 * off};
     };
-    mainloop_dl<G3M, G3N, LO, LO, S, true, false, false, WGM, WGN>(sm, pe - pb, 0, nact, m0, n0, A, B, acc, none);
+    mainloop_dl<G3M, G3N, LO, LO, S, true, false, false, WGM, WGN, (WGM * WGN == 8)>(sm, pe - pb, 0, nact, m0, n0, A, B,
+                                                                                      acc, none);
   } else {
     static_assert(VEC || (WGM == 2 && WGN == 2), "register-staged path: 2 x 2 waves");
     __shared__ Stage<G3M, G3N, LO, LO> sm;
