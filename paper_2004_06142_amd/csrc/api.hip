@@ -974,6 +974,44 @@ pnof_status pnof_lagrangian(pnof_ctx ctx, const pnof_problem* prob, const double
   return run_step(ctx, prob, C, n, H, ints, r);
 }
 
+namespace {
+// Symmetric float64 eigensolver: A (n x n, symmetric, row-major; destroyed) -> ascending eigenvalues
+// w and eigenvectors U (column-major).  The Householder reduction runs on the library's kernels
+// (k_eig.hip); rocSOLVER solves the tridiagonal problem (stedc) and applies the reflectors (ormtr).
+// Sizes outside [3, TRIDIAG_MAX_N] take rocSOLVER's dsyevd.  info (device) receives the solver's
+// status (0 = converged).
+struct EighWs {
+  double* Vh;    // n * n
+  double* p2;    // 2n
+  double* e;     // n
+  double* tau;   // n
+};
+EighWs take_eigh_ws(Arena& a, int n) {
+  EighWs w;
+  w.Vh = a.take<double>((long long)n * n);
+  w.p2 = a.take<double>(2LL * n);
+  w.e = a.take<double>(n);
+  w.tau = a.take<double>(n);
+  return w;
+}
+pnof_status eigh(pnof_ctx ctx, int n, double* A, double* w, double* U, const EighWs& ws, int* info) {
+  hipStream_t s = ctx->stream;
+  if (n < 3 || n > TRIDIAG_MAX_N) {
+    rocblas_status rs = rocsolver_dsyevd(ctx->blas, rocblas_evect_original, rocblas_fill_upper, n, A, n, w, ws.e, info);
+    if (rs != rocblas_status_success) return fail(ctx, PNOF_E_DEVICE, "rocsolver_dsyevd failed to launch");
+    DEV_CHECK(ctx, hipMemcpyAsync(U, A, sizeof(double) * n * n, hipMemcpyDeviceToDevice, s));
+    return PNOF_OK;
+  }
+  DEV_CHECK(ctx, tridiag_f64(s, n, A, ws.Vh, ws.p2, w, ws.e, ws.tau));
+  rocblas_status rs = rocsolver_dstedc(ctx->blas, rocblas_evect_tridiagonal, n, w, ws.e, U, n, info);
+  if (rs != rocblas_status_success) return fail(ctx, PNOF_E_DEVICE, "rocsolver_dstedc failed to launch");
+  rs = rocsolver_dormtr(ctx->blas, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none, n, n, ws.Vh, n,
+                        ws.tau, U, n);
+  if (rs != rocblas_status_success) return fail(ctx, PNOF_E_DEVICE, "rocsolver_dormtr failed to launch");
+  return PNOF_OK;
+}
+}  // namespace
+
 pnof_status pnof_orbital_step(pnof_ctx ctx, int32_t nbf, const double* lambda, const double* C,
                               const double* diag_prev, double zeta, double* C_new, double* eps, double* S_out) {
   if (!ctx) return fail(nullptr, PNOF_E_ARG, "context is NULL");
@@ -986,23 +1024,26 @@ pnof_status pnof_orbital_step(pnof_ctx ctx, int32_t nbf, const double* lambda, c
   const long long n2 = (long long)nbf * nbf;
   Arena probe(nullptr);
   probe.take<double>(n2);
-  probe.take<double>(nbf);
+  probe.take<double>(n2);
+  take_eigh_ws(probe, nbf);
   probe.take<int>(4);
   char* ws = nullptr;
   if ((st = get_ws(ctx, probe.off + 256, &ws)) != PNOF_OK) return st;
   Arena a(ws);
   double* A = a.take<double>(n2);
-  double* E = a.take<double>(nbf);
+  double* U = a.take<double>(n2);
+  const EighWs ew = take_eigh_ws(a, nbf);
   int* info = a.take<int>(4);
   hipStream_t s = ctx->stream;
   DEV_CHECK(ctx, build_s(s, nbf, lambda, diag_prev, zeta, A));
   if (S_out) DEV_CHECK(ctx, hipMemcpyAsync(S_out, A, n2 * sizeof(double), hipMemcpyDeviceToDevice, s));
-  rocblas_status rs = TIMED(ctx, PNOF_STAGE_EIG, rocsolver_dsyevd(ctx->blas, rocblas_evect_original,
-                                                                 rocblas_fill_upper, nbf, A, nbf, eps, E, info));
-  if (rs != rocblas_status_success) return fail(ctx, PNOF_E_DEVICE, "rocsolver_dsyevd failed to launch");
-  DEV_CHECK(ctx, sign_fix_cols(s, nbf, A));
-  // C_new[mu][j] = sum_i C[mu][i] U[i][j], U column-major: U[i][j] = A[j*nbf + i]
-  DEV_CHECK(ctx, gemm_f64(s, nbf, nbf, nbf, 1, 1.0, C, nbf, 1, 0, A, 1, nbf, 0, 0.0, C_new, nbf, 1, 0));
+  {
+    StageTimer t_(ctx, PNOF_STAGE_EIG);
+    if ((st = eigh(ctx, nbf, A, eps, U, ew, info)) != PNOF_OK) return st;
+  }
+  DEV_CHECK(ctx, sign_fix_cols(s, nbf, U));
+  // C_new[mu][j] = sum_i C[mu][i] U[i][j], U column-major: U[i][j] = U[j*nbf + i]
+  DEV_CHECK(ctx, gemm_f64(s, nbf, nbf, nbf, 1, 1.0, C, nbf, 1, 0, U, 1, nbf, 0, 0.0, C_new, nbf, 1, 0));
   DEV_CHECK(ctx, hipMemcpyAsync(ctx->host_info, info, sizeof(int), hipMemcpyDeviceToHost, s));
   DEV_CHECK(ctx, hipStreamSynchronize(s));
   if (*ctx->host_info != 0)
@@ -1085,7 +1126,12 @@ pnof_status pnof_optimize(pnof_ctx ctx, const pnof_problem* prob, const double* 
   double* Cn = db.get<double>(nn);
   double* T1 = db.get<double>(nn);
   double* diag = db.get<double>(nbf);
-  double* ework = db.get<double>(nbf);
+  double* Ueig = db.get<double>(nn);
+  EighWs ew;
+  ew.Vh = db.get<double>(nn);
+  ew.p2 = db.get<double>(2LL * nbf);
+  ew.e = db.get<double>(nbf);
+  ew.tau = db.get<double>(nbf);
   int* info = db.get<int>(4);
   double* J = db.get<double>(n2);
   double* K = db.get<double>(n2);
@@ -1149,11 +1195,10 @@ pnof_status pnof_optimize(pnof_ctx ctx, const pnof_problem* prob, const double* 
   };
   // diagonalise S (overwritten by the eigenvectors), new diagonal, C <- C U
   auto diagonalise = [&]() -> pnof_status {
-    rocblas_status rs = rocsolver_dsyevd(ctx->blas, rocblas_evect_original, rocblas_fill_upper, nbf, S, nbf, diag,
-                                         ework, info);
-    if (rs != rocblas_status_success) return fail(ctx, PNOF_E_DEVICE, "rocsolver_dsyevd failed to launch");
-    DEV_CHECK(ctx, sign_fix_cols(s, nbf, S));
-    DEV_CHECK(ctx, gemm_f64(s, nbf, nbf, nbf, 1, 1.0, C, nbf, 1, 0, S, 1, nbf, 0, 0.0, Cn, nbf, 1, 0));
+    pnof_status se = eigh(ctx, nbf, S, diag, Ueig, ew, info);
+    if (se != PNOF_OK) return se;
+    DEV_CHECK(ctx, sign_fix_cols(s, nbf, Ueig));
+    DEV_CHECK(ctx, gemm_f64(s, nbf, nbf, nbf, 1, 1.0, C, nbf, 1, 0, Ueig, 1, nbf, 0, 0.0, Cn, nbf, 1, 0));
     DEV_CHECK(ctx, hipMemcpyAsync(C, Cn, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
     int hinfo = 0;
     DEV_CHECK(ctx, hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, s));

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <string>
 
 namespace pnof {
@@ -299,6 +300,11 @@ hipError_t on_map_vjp(hipStream_t s, int kind, int npairs, int ncwo, int nsingle
 hipError_t build_s(hipStream_t s, int nbf, const double* lam, const double* diag_prev, double zeta,
                    double* S);
 hipError_t sign_fix_cols(hipStream_t s, int nbf, double* Ucm);
+// Householder reduction to tridiagonal form (k_eig.hip), one launch per column: A (n x n symmetric,
+// row-major) is overwritten; d (n), e (n - 1), tau (n - 1) and the reflectors as rows of Vh (n x n,
+// read column-major: the lower-storage layout of ormtr); p2: 2n doubles of scratch.
+constexpr int TRIDIAG_MAX_N = 2048;   // three float64 vectors of n in LDS
+hipError_t tridiag_f64(hipStream_t s, int n, double* A, double* Vh, double* p2, double* d, double* e, double* tau);
 hipError_t offdiag_copy(hipStream_t s, int nbf, const double* src, double* dst);
 // E_hf and E_sta (device scalars) from n, H_pp, J, K; partials: 256 doubles of scratch.
 hipError_t nofmp2_terms(hipStream_t s, int nact, int npairs, int ncwo, int nsingle, const double* n, const double* Hpp,

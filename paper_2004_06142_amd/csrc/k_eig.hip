@@ -1,0 +1,195 @@
+// Householder reduction of a symmetric float64 matrix to tridiagonal form, one kernel per column.
+//
+// The orbital step diagonalises an n x n symmetric matrix every iteration (n = 1200 at the largest
+// workload).  The reduction is a chain of n dependent steps, so its cost is per-step latency, not
+// bandwidth.  Each step here is a single launch: it applies the previous step's rank-2 update to
+// the rows it owns and, in the same pass over each row, accumulates that row's product with the new
+// Householder vector.  The update is never a separate kernel, and no step reads the matrix twice.
+//
+// Step k (0 <= k < n), with v_{k-1}, tau_{k-1} and p_{k-1} = tau_{k-1} A v_{k-1} from step k - 1:
+//   w_{k-1} = p_{k-1} - (tau_{k-1} / 2) (p_{k-1} . v_{k-1}) v_{k-1};
+//   c = row k of A with the pending update A -= v w^T + w v^T applied (A is symmetric, so row k is
+//       column k); d_k = c_k;
+//   Householder vector of c_{k+1..n-1}: v_k (v_k[k+1] = 1), tau_k, e_k = beta (LAPACK's dlarfg
+//       convention: beta = -sign(alpha) |c_{k+1..}|, tau = (beta - alpha) / beta; tau = 0 when the
+//       column below the subdiagonal is already zero);
+//   rows i > k: apply the pending update, store, p_k[i] = tau_k (row i . v_k).
+// Every block recomputes w_{k-1}, c and v_k identically (same data, same reduction order); block 0
+// stores v_k as row k of Vh, which read column-major is the lower-storage reflector layout that
+// LAPACK-style routines (ormtr) take: Q = H_0 H_1 ... H_{n-2}, H_k = I - tau_k v_k v_k^T, A = Q T Q^T.
+#include "common.h"
+
+namespace pnof {
+namespace {
+
+constexpr int TNT = 256;   // threads per block
+constexpr int TROWS = 4;   // rows of the trailing matrix per block (one per wavefront)
+constexpr int TPQ = 4;     // prologue elements per thread held in registers (loops cover the rest)
+constexpr int TPRE = 24;   // row elements per lane loaded before the prologue (loops cover the rest)
+
+__device__ double tblock_sum(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < TNT / 64; ++i) s += red[i];
+  return s;
+}
+
+__global__ __launch_bounds__(TNT) void trd_step_k(int n, int k, double* __restrict__ A, double* __restrict__ Vh,
+                                                  const double* __restrict__ pprev, double* __restrict__ pcur,
+                                                  double* __restrict__ d, double* __restrict__ e,
+                                                  double* __restrict__ tau) {
+  extern __shared__ double sh[];
+  const int m = n - k;          // active indices k .. n-1, stored from 0
+  double* vp = sh;              // v_{k-1}
+  double* wp = sh + m;          // p_{k-1}, then w_{k-1}
+  double* vk = sh + 2 * m;      // c, then v_k
+  __shared__ double red[TNT / 64];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  // this wavefront's row: its first TPRE * 64 elements are loaded before the prologue, so their
+  // latency overlaps the prologue's
+  const int irow = k + 1 + blockIdx.x * TROWS + wv;
+  const bool has_row = (irow < n) && (m >= 2);
+  double* __restrict__ row = A + (long long)(has_row ? irow : k) * n + k;
+  double a[TPRE];
+#pragma unroll
+  for (int c = 0; c < TPRE; ++c) {
+    const int jl = 1 + lane + 64 * c;
+    a[c] = (has_row && jl < m) ? row[jl] : 0.0;
+  }
+  // prologue: v_{k-1}, p_{k-1} and row k loaded together
+  const double* vprev = Vh + (long long)(k > 0 ? k - 1 : 0) * n + k;
+  const double* pp = pprev + k;
+  const double* rowk = A + (long long)k * n + k;
+  double rv[TPQ], rp[TPQ], rc[TPQ];
+#pragma unroll
+  for (int q = 0; q < TPQ; ++q) {
+    const int i = t + TNT * q;
+    const bool ok = i < m;
+    rv[q] = (ok && k > 0) ? vprev[i] : 0.0;
+    rp[q] = (ok && k > 0) ? pp[i] : 0.0;
+    rc[q] = ok ? rowk[i] : 0.0;
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < TPQ; ++q) {
+    const int i = t + TNT * q;
+    if (i < m) {
+      vp[i] = rv[q];
+      s += rv[q] * rp[q];
+    }
+  }
+  for (int i = t + TNT * TPQ; i < m; i += TNT) {
+    const double v = k > 0 ? vprev[i] : 0.0, p = k > 0 ? pp[i] : 0.0;
+    vp[i] = v;
+    wp[i] = p;
+    s += v * p;
+  }
+  s = tblock_sum(s, red);   // its syncs also publish vp and wp
+  const double half = k > 0 ? 0.5 * tau[k - 1] * s : 0.0;
+  const double v0 = vp[0], w0 = (k > 0 ? pp[0] : 0.0) - half * v0;
+  double sig = 0.0;
+#pragma unroll
+  for (int q = 0; q < TPQ; ++q) {
+    const int i = t + TNT * q;
+    if (i < m) {
+      const double w = rp[q] - half * rv[q];
+      wp[i] = w;
+      const double c = rc[q] - v0 * w - w0 * rv[q];
+      rc[q] = c;
+      vk[i] = c;
+      if (i >= 2) sig += c * c;
+    }
+  }
+  for (int i = t + TNT * TPQ; i < m; i += TNT) {
+    const double w = wp[i] - half * vp[i];
+    wp[i] = w;
+    const double c = rowk[i] - v0 * w - w0 * vp[i];
+    vk[i] = c;
+    if (i >= 2) sig += c * c;
+  }
+  sig = tblock_sum(sig, red);   // also publishes wp and vk
+  double tk = 0.0, beta = 0.0, scal = 0.0;
+  if (m >= 2) {
+    const double alpha = vk[1];
+    if (sig == 0.0) {
+      beta = alpha;
+    } else {
+      beta = -copysign(sqrt(alpha * alpha + sig), alpha);
+      tk = (beta - alpha) / beta;
+      scal = 1.0 / (alpha - beta);
+    }
+  }
+  const double dk = vk[0];
+  __syncthreads();   // every thread has read vk[0] and vk[1]
+#pragma unroll
+  for (int q = 0; q < TPQ; ++q) {
+    const int i = t + TNT * q;
+    if (i < m) vk[i] = (i == 0) ? 0.0 : (i == 1 ? 1.0 : rc[q] * scal);
+  }
+  for (int i = t + TNT * TPQ; i < m; i += TNT) vk[i] = (i == 0) ? 0.0 : (i == 1 ? 1.0 : vk[i] * scal);
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    double* vrow = Vh + (long long)k * n + k;
+    for (int i = t; i < m; i += TNT) vrow[i] = vk[i];
+    if (t == 0) {
+      d[k] = dk;
+      if (m >= 2) {
+        e[k] = beta;
+        tau[k] = tk;
+      }
+    }
+  }
+  if (!has_row) return;
+  const int il = irow - k;
+  const double vpi = vp[il], wpi = wp[il];
+  double acc = 0.0;
+#pragma unroll
+  for (int c = 0; c < TPRE; ++c) {
+    const int jl = 1 + lane + 64 * c;
+    if (jl < m) {
+      const double x = a[c] - vpi * wp[jl] - wpi * vp[jl];
+      row[jl] = x;
+      acc += x * vk[jl];
+    }
+  }
+  constexpr int CH = 8;
+  for (int j0 = 1 + 64 * TPRE; j0 < m; j0 += 64 * CH) {
+    double b[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int jl = j0 + lane + 64 * c;
+      b[c] = jl < m ? row[jl] : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int jl = j0 + lane + 64 * c;
+      if (jl < m) {
+        const double x = b[c] - vpi * wp[jl] - wpi * vp[jl];
+        row[jl] = x;
+        acc += x * vk[jl];
+      }
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (lane == 0) pcur[irow] = tk * acc;
+}
+
+}  // namespace
+
+hipError_t tridiag_f64(hipStream_t s, int n, double* A, double* Vh, double* p2, double* d, double* e, double* tau) {
+  if (n <= 0 || n > TRIDIAG_MAX_N) return hipErrorInvalidValue;
+  const size_t shm = 3 * (size_t)n * sizeof(double);
+  for (int k = 0; k < n; ++k) {
+    const int blocks = std::max(1, cdiv(n - k - 1, TROWS));
+    hipLaunchKernelGGL(trd_step_k, dim3(blocks), dim3(TNT), shm, s, n, k, A, Vh, p2 + ((k + 1) & 1) * (long long)n,
+                       p2 + (k & 1) * (long long)n, d, e, tau);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace pnof
