@@ -264,6 +264,37 @@ def test_orbital_step_symmetrised(ctx):
     assert np.max(np.abs(h(Cn)[:, iso] - Cr[:, iso])) < 1e-8
 
 
+# sizes around the eigensolver's internal limits: n < 3 and n > 2048 take the library solver,
+# 1024 < n and 1537 < n cross the register-held prologue and row chunks of the reduction kernel
+@pytest.mark.parametrize("nbf", [1, 2, 3, 5, 64, 1025, 1601, 2100])
+def test_orbital_step_sizes(ctx, nbf):
+    rng = np.random.default_rng(nbf)
+    lam = rng.standard_normal((nbf, nbf))
+    C, _ = np.linalg.qr(rng.standard_normal((nbf, nbf)))
+    Cn, eps = ctx.orbital_step(t(lam), t(C))
+    Cr, eps_r, Sr = pnof.orbital_step(lam, C)
+    _eig_compare(h(eps), eps_r, h(Cn), C, Sr)
+
+
+@pytest.mark.parametrize("kind", ["diagonal", "blocks"])
+def test_orbital_step_reflector_free_columns(ctx, kind):
+    """Columns already zero below the subdiagonal (tau = 0 in the reduction): a diagonal matrix, and
+    two decoupled blocks (one column of the first block has no coupling past the second row)."""
+    nbf = 70
+    rng = np.random.default_rng(5)
+    if kind == "diagonal":
+        lam = np.diag(np.linspace(-3.0, 4.0, nbf))
+    else:
+        lam = np.zeros((nbf, nbf))
+        a, b = rng.standard_normal((30, 30)), rng.standard_normal((40, 40))
+        lam[:30, :30] = a + a.T
+        lam[30:, 30:] = b + b.T
+    C, _ = np.linalg.qr(rng.standard_normal((nbf, nbf)))
+    Cn, eps = ctx.orbital_step(t(lam), t(C))
+    Cr, eps_r, Sr = pnof.orbital_step(lam, C)
+    _eig_compare(h(eps), eps_r, h(Cn), C, Sr)
+
+
 def test_orbital_step_fockian_zeta(ctx):
     inst = _case("orbF", 40, 60, 4, 3)
     n, ref = _ref(inst, pnof.PNOF7)
