@@ -28,15 +28,15 @@ KSRC = os.path.join(ROOT, "paper_2004_06142_amd", "csrc")
 # once the source changes the figure no longer applies and traffic is reported as null.
 TRAFFIC = {
     # profiles/c5_df1200_hbm_traffic.md: C5, bf16 split, 164-row chunks (read + written bytes per launch)
-    ("gemm1_kernel", 3): {"bytes": 1578956549 + 925472983,
+    ("gemm1_kernel", 3): {"bytes": 1605205416 + 925021926,
                           "plan": {"pchunk": 164, "x_variant": 3},
-                          "sha256": {"k_gemm_bf16.hip": "f913ca5d3cffdf3475185fb89843ba71174e5f5fb42a4604422b5f5cb0979431"}},
-    ("gemm2_kernel", 3): {"bytes": 3497199182 + 1133903226,
+                          "sha256": {"k_gemm_bf16.hip": "fa87ab5462fcc90db27209aab0d9d7a43dab7ec032cb23ed34f40d884ad5e71f"}},
+    ("gemm2_kernel", 3): {"bytes": 3493328017 + 1138433279,
                           "plan": {"pchunk": 164, "nsplit_b": 18},
-                          "sha256": {"k_gemm_bf16.hip": "f913ca5d3cffdf3475185fb89843ba71174e5f5fb42a4604422b5f5cb0979431"}},
-    ("gemm3_kernel", 3): {"bytes": 2746350622 + 232767068,
+                          "sha256": {"k_gemm_bf16.hip": "fa87ab5462fcc90db27209aab0d9d7a43dab7ec032cb23ed34f40d884ad5e71f"}},
+    ("gemm3_kernel", 3): {"bytes": 2767146960 + 241445775,
                           "plan": {"pchunk": 164, "nsplit_y": 10, "y_variant": 3},
-                          "sha256": {"k_gemm_bf16.hip": "f913ca5d3cffdf3475185fb89843ba71174e5f5fb42a4604422b5f5cb0979431"}},
+                          "sha256": {"k_gemm_bf16.hip": "fa87ab5462fcc90db27209aab0d9d7a43dab7ec032cb23ed34f40d884ad5e71f"}},
 }
 GOLDEN_C5 = os.path.join(ROOT, "tests", "golden", "c5_df1200_expected.json")
 
