@@ -791,14 +791,16 @@ __global__ __launch_bounds__(64 * WGM * WGN, MINB) void gemm3_kernel(G3Args g) {
 }
 
 // Grouped forms: one launch over the work items of every instance of a batch.
+// (two blocks per compute unit, as the single-problem 128 x 128 form: 8.6 -> 7.7 ms per 64-instance
+// PES batch)
 template <int TERMS>
-__global__ __launch_bounds__(256, 1) void gemm1_grouped(const G1Args* __restrict__ tab, const int* __restrict__ off,
+__global__ __launch_bounds__(256, 2) void gemm1_grouped(const G1Args* __restrict__ tab, const int* __restrict__ off,
                                                         int ninst, int total) {
   const int w = xcd_item(total);
   if (w < 0) return;
   const int i = find_instance(off, ninst, w);
   const G1Args g = tab[i];
-  gemm1_body<TERMS, false, 128, 128, 2, 2, 1, true, true>(w - off[i], g);
+  gemm1_body<TERMS, false, 128, 128, 2, 2, 2, true, true>(w - off[i], g);
 }
 template <int TERMS>
 __global__ __launch_bounds__(128 * g2_wgn(true), 1) void gemm2_grouped(const G2Args* __restrict__ tab, const int* __restrict__ off,
