@@ -213,7 +213,7 @@ def main():
     torch.cuda.empty_cache()
 
     if args.pes_reps > 0:
-        result["pes_batch"] = pes_batch(P, ctx, args.pes_reps)
+        result["pes_batch"] = pes_batch(P, ctx, args.pes_reps, tune=not args.no_tune)
         torch.cuda.empty_cache()
 
     if args.cpu_rows > 0:
@@ -224,7 +224,7 @@ def main():
 GOLDEN_PES = os.path.join(ROOT, "tests", "golden", "pes64_expected.json")
 
 
-def pes_batch(P, ctx, reps):
+def pes_batch(P, ctx, reps, tune=True):
     """The 64-instance PES scan (N_bf in [40, 300], bf16 split) as one graph-replayed batch."""
     import numpy as np
     import torch
@@ -243,6 +243,9 @@ def pes_batch(P, ctx, reps):
                     "B": sdev.make_b(inst.key, wl.nbf, wl.naux, dtype=torch.bfloat16, device=dev)})
     batch = P.Batch(ctx, probs)
     outs = batch.bind(ins)
+    if tune:
+        from paper_2004_06142_amd import autotune
+        autotune.tune_batch(batch)
     for _ in range(3):
         batch.run(graph=True)
     torch.cuda.synchronize()
@@ -260,6 +263,7 @@ def pes_batch(P, ctx, reps):
     res = {"instances": len(probs), "nbf_range": [min(p.nbf for p in probs), max(p.nbf for p in probs)],
            "ms_per_batch_p50": med, "ms_p90": float(np.percentile(times, 90)), "ms_p99": float(np.percentile(times, 99)),
            "instances_per_s": len(probs) / (med * 1e-3), "launches_per_batch": batch.info()["launches"],
+           "tiles_xby": list(batch.tiles()),
            "graph": True, "algorithmic_tflops": flops / (med * 1e-3) / 1e12,
            "note": "every instance completes with the batch's last grouped launch, so per-instance latency "
                    "equals the batch latency"}

@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define PNOF_ABI_VERSION 2
+#define PNOF_ABI_VERSION 3
 
 typedef struct pnof_ctx_s* pnof_ctx;
 
@@ -285,6 +285,13 @@ pnof_status pnof_batch_bind(pnof_batch batch, const pnof_batch_io* io);
 pnof_status pnof_batch_run(pnof_batch batch, int32_t use_graph);
 /* Device bytes held by the batch, and the number of launches one run enqueues. */
 pnof_status pnof_batch_info(pnof_batch batch, size_t* bytes, int32_t* launches);
+/* Tile widths along the active orbitals of the grouped X, b and Y contractions: 64 or 128, 0 for
+ * the automatic choice (64 when it cuts that stage's padded matrix-core work, summed over the
+ * instances, by a quarter or more).  May be called before or after pnof_batch_bind; it discards a
+ * captured graph.  Results do not depend on the widths beyond floating-point rounding order.
+ * pnof_batch_get_tiles writes the three widths in use.  (ABI version 3.) */
+pnof_status pnof_batch_set_tiles(pnof_batch batch, int32_t x_tile, int32_t b_tile, int32_t y_tile);
+pnof_status pnof_batch_get_tiles(pnof_batch batch, int32_t* tiles);
 void pnof_batch_destroy(pnof_batch batch);
 
 #ifdef __cplusplus

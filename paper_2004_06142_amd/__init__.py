@@ -34,7 +34,8 @@ EXPORTS = ["pnof_abi_version", "pnof_last_error", "pnof_check_problem", "pnof_cr
            "pnof_on_map_vjp", "pnof_jk", "pnof_energy", "pnof_fock", "pnof_lagrangian", "pnof_orbital_step",
            "pnof_profile_begin", "pnof_profile_end", "pnof_set_tuning", "pnof_get_plan", "pnof_optimize_on",
            "pnof_optimize", "pnof_nofmp2_terms", "pnof_batch_plan",
-           "pnof_batch_bind", "pnof_batch_run", "pnof_batch_info", "pnof_batch_destroy"]
+           "pnof_batch_bind", "pnof_batch_run", "pnof_batch_info", "pnof_batch_destroy", "pnof_batch_set_tiles",
+           "pnof_batch_get_tiles"]
 STAGES = ("X", "b", "Y", "eig")
 
 
@@ -129,6 +130,8 @@ def lib():
             "pnof_batch_run": ([P, I], S),
             "pnof_batch_info": ([P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_int32)], S),
             "pnof_batch_destroy": ([P], None),
+            "pnof_batch_set_tiles": ([P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32], S),
+            "pnof_batch_get_tiles": ([P, ctypes.POINTER(ctypes.c_int32)], S),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -501,6 +504,15 @@ class Batch:
         nb, nl = ctypes.c_size_t(), ctypes.c_int32()
         _raise(self.ctx, lib().pnof_batch_info(self.handle, ctypes.byref(nb), ctypes.byref(nl)))
         return {"bytes": nb.value, "launches": nl.value}
+
+    def set_tiles(self, x: int = 0, b: int = 0, y: int = 0):
+        """Tile widths (64 or 128; 0 = automatic) along the active orbitals of the grouped X, b, Y."""
+        _raise(self.ctx, lib().pnof_batch_set_tiles(self.handle, x, b, y))
+
+    def tiles(self) -> tuple:
+        out = (ctypes.c_int32 * 3)()
+        _raise(self.ctx, lib().pnof_batch_get_tiles(self.handle, out))
+        return tuple(out)
 
     def bind(self, inputs, grads: bool = True):
         if len(inputs) != len(self.problems):

@@ -141,6 +141,62 @@ def tune(ctx: Context, prob, run, reps: int = 2, use_cache: bool = True, verbose
     return entry
 
 
+def batch_key(batch, arch: str) -> str:
+    """Cache key of a batch: its precision and the sorted (nbf, nact, naux) of its instances."""
+    import hashlib
+    shapes = sorted((p.nbf, p.nact, p.naux) for p in batch.problems)
+    h = hashlib.sha1(repr(shapes).encode()).hexdigest()[:16]
+    return f"v{SCHEMA}:{arch}:batch:p{batch.problems[0].precision}:n{len(shapes)}:{h}"
+
+
+def tune_batch(batch, reps: int = 10, use_cache: bool = True, verbose: bool = False) -> dict:
+    """Pick the tile widths (64 or 128 along the active orbitals) of a bound batch's grouped X, b and Y
+    contractions by timing graph replays of the whole batch, one stage at a time from the automatic
+    choice; the entry is cached under the batch's shape signature."""
+    arch = _arch(batch.ctx.device)
+    k = batch_key(batch, arch)
+    cache = load_cache() if use_cache else {}
+    if k in cache:
+        batch.set_tiles(*cache[k]["tiles"])
+        return cache[k]
+
+    def measure(tiles):
+        batch.set_tiles(*tiles)
+        for _ in range(2):
+            batch.run(graph=True)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            batch.run(graph=True)
+            b.record()
+            b.synchronize()
+            ts.append(a.elapsed_time(b))
+        ts.sort()
+        ms = ts[len(ts) // 2]
+        if verbose:
+            print("  tune batch", tiles, round(ms, 3), flush=True)
+        return ms
+
+    batch.set_tiles(0, 0, 0)
+    best = list(batch.tiles())
+    cur = measure(best)
+    for stage in range(3):
+        trial = list(best)
+        trial[stage] = 64 if best[stage] == 128 else 128
+        ms = measure(trial)
+        if ms < cur * 0.99:
+            best, cur = trial, ms
+    batch.set_tiles(*best)
+    entry = {"tiles": best, "ms": cur, "arch": arch, "instances": len(batch.problems)}
+    if use_cache:
+        cache = load_cache()
+        cache[k] = entry
+        save_cache(cache)
+    return entry
+
+
 def main():
     """Tune one synthetic workload on device 0 and store the entry in the cache file."""
     import argparse

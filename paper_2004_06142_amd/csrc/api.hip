@@ -703,6 +703,8 @@ struct pnof_batch_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int launches = 13;
+  int req[3] = {0, 0, 0};             // requested tile widths along the active orbitals (0: automatic)
+  int tile[3] = {128, 128, 128};      // in use: X (rows p), b (square), Y (columns q)
 };
 
 namespace {
@@ -715,6 +717,47 @@ void batch_drop_graph(pnof_batch b) {
 }
 
 // The fixed launch sequence of one batch step.
+// Tile widths along the active orbitals for the grouped X, b and Y contractions.  Automatic: 64
+// when it cuts the padded matrix-core work of that stage, summed over the instances, by a quarter or
+// more (the 64-wide forms do less work per LDS byte, so a small saving does not pay).
+void batch_resolve_tiles(pnof_batch b) {
+  double w[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+  const int ts[2] = {128, 64};
+  for (const BatchGeom& g : b->geo)
+    for (int k = 0; k < 2; ++k) {
+      const double t = ts[k], na = (double)round_up(g.nact, ts[k]), tt = cdiv(g.nact, ts[k]);
+      w[0][k] += (double)g.naux * g.nbf * g.ldk * na;
+      w[1][k] += (double)g.naux * g.ldk * t * t * tt * (tt + 1) / 2;
+      w[2][k] += (double)g.naux * round_up(g.nbf, 128) * na * g.nact32;
+    }
+  for (int s = 0; s < 3; ++s) b->tile[s] = b->req[s] ? b->req[s] : (w[s][1] <= 0.75 * w[s][0] ? 64 : 128);
+}
+
+// Work-item offsets of the grouped launches for the tiles in use (the kernels decode with the same
+// widths), uploaded to the device.
+hipError_t batch_offsets(pnof_batch b, hipStream_t s) {
+  const int n = b->ninst;
+  std::vector<int> off(3 * (n + 1), 0);
+  for (int i = 0; i < n; ++i) {
+    const BatchGeom& g = b->geo[i];
+    G1Args g1{};
+    g1.nbf = g.nbf; g1.nact = g.nact; g1.np = g.naux;
+    G2Args g2{};
+    g2.nact = g.nact; g2.nsplit = g.ns2;
+    G3Args g3{};
+    g3.nbf = g.nbf; g3.nact = g.nact; g3.nsplit = g.ns3;
+    off[i + 1] = off[i] + g1_items(g1, b->tile[0], 128, true);
+    off[(n + 1) + i + 1] = off[(n + 1) + i] + g2_items(g2, b->tile[1]);
+    off[2 * (n + 1) + i + 1] = off[2 * (n + 1) + i] + g3_items(g3, 128, b->tile[2]);
+  }
+  b->tot1 = off[n];
+  b->tot2 = off[2 * (n + 1) - 1];
+  b->tot3 = off[3 * (n + 1) - 1];
+  hipError_t e = hipMemcpyAsync(b->d_off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(s);   // off goes out of scope
+}
+
 hipError_t batch_enqueue(pnof_batch b, hipStream_t s) {
   const int n = b->ninst;
   hipError_t e;
@@ -723,11 +766,11 @@ hipError_t batch_enqueue(pnof_batch b, hipStream_t s) {
   BSTEP(batch_prep(s, n, b->d_inst, b->mx));
   BSTEP(gemm_f64_grouped(s, n, b->maxM[0], b->maxN[0], false, true, b->d_f64));
   BSTEP(batch_hpp(s, n, b->d_inst, b->mx));
-  BSTEP(df_bf16_gemm1_grouped(s, n, b->tot1, b->terms, b->d_g1, b->d_off));
-  BSTEP(df_bf16_gemm2_grouped(s, n, b->tot2, b->terms, b->d_g2, b->d_off + (n + 1)));
+  BSTEP(df_bf16_gemm1_grouped(s, n, b->tot1, b->terms, b->tile[0], b->d_g1, b->d_off));
+  BSTEP(df_bf16_gemm2_grouped(s, n, b->tot2, b->terms, b->tile[1], b->d_g2, b->d_off + (n + 1)));
   BSTEP(gemm_f64_grouped(s, n, b->maxM[1], b->maxN[1], false, true, b->d_f64 + n));
   BSTEP(batch_add_diag(s, n, b->d_inst, b->mx));
-  BSTEP(df_bf16_gemm3_grouped(s, n, b->tot3, b->terms, b->d_g3, b->d_off + 2 * (n + 1)));
+  BSTEP(df_bf16_gemm3_grouped(s, n, b->tot3, b->terms, b->tile[2], b->d_g3, b->d_off + 2 * (n + 1)));
   BSTEP(batch_reduce(s, n, b->d_inst, b->mx));
   BSTEP(gemm_f64_grouped(s, n, b->maxM[2], b->maxN[2], true, true, b->d_f64 + 2 * n));
   BSTEP(batch_energy_y(s, n, b->d_inst, b->mx));
@@ -1379,7 +1422,30 @@ pnof_status pnof_batch_plan(pnof_ctx ctx, int32_t ninst, const pnof_problem* pro
     b->maxM[3] = std::max(b->maxM[3], g.nbf);  b->maxN[3] = std::max(b->maxN[3], g.nact);   // C^T Y
   }
   b->mx = mx;
+  batch_resolve_tiles(b);
   *out = b;
+  return PNOF_OK;
+}
+
+pnof_status pnof_batch_set_tiles(pnof_batch b, int32_t x_tile, int32_t b_tile, int32_t y_tile) {
+  if (!b) return fail(nullptr, PNOF_E_ARG, "batch is NULL");
+  pnof_ctx ctx = b->ctx;
+  pnof_status st = check_ctx(ctx);
+  if (st != PNOF_OK) return st;
+  const int v[3] = {x_tile, b_tile, y_tile};
+  for (int k = 0; k < 3; ++k)
+    if (v[k] != 0 && v[k] != 64 && v[k] != 128) return fail(ctx, PNOF_E_ARG, "tile widths are 0 (automatic), 64 or 128");
+  for (int k = 0; k < 3; ++k) b->req[k] = v[k];
+  batch_resolve_tiles(b);
+  batch_drop_graph(b);
+  if (b->bound) DEV_CHECK(ctx, batch_offsets(b, ctx->stream));
+  return PNOF_OK;
+}
+
+pnof_status pnof_batch_get_tiles(pnof_batch b, int32_t* tiles) {
+  if (!b) return fail(nullptr, PNOF_E_ARG, "batch is NULL");
+  if (!tiles) return fail(b->ctx, PNOF_E_ARG, "tiles is NULL");
+  for (int k = 0; k < 3; ++k) tiles[k] = b->tile[k];
   return PNOF_OK;
 }
 
@@ -1398,7 +1464,6 @@ pnof_status pnof_batch_bind(pnof_batch b, const pnof_batch_io* io) {
   std::vector<G2Args> g2(n);
   std::vector<G3Args> g3(n);
   std::vector<F64Gemm> f(4 * n);
-  std::vector<int> off(3 * (n + 1), 0);
   for (int i = 0; i < n; ++i) {
     BInst& d = b->inst[i];
     const BatchGeom& g = b->geo[i];
@@ -1412,23 +1477,17 @@ pnof_status pnof_batch_bind(pnof_batch b, const pnof_batch_io* io) {
     g2[i] = G2Args{g.nbf, g.nact, g.naux, g.ns2, d.cth, d.ctl, g.ldk, d.xth, d.xtl, g.ldk, d.beta32, d.Kpart, d.D,
                    d.wh, d.wl, g.ldw, wd};
     g3[i] = G3Args{g.nbf, g.nact, g.naux, g.ns3, d.xth, d.xtl, g.ldk, d.wh, d.wl, g.ldw, d.Ypart, wd};
-    off[i + 1] = off[i] + g1_items(g1[i], 128, 128, true);
-    off[(n + 1) + i + 1] = off[(n + 1) + i] + g2_items(g2[i]);
-    off[2 * (n + 1) + i + 1] = off[2 * (n + 1) + i] + g3_items(g3[i], 128, 128);
     f[i] = F64Gemm{g.nbf, g.nact, g.nbf, 1.0, d.H, g.nbf, 1, d.C, g.nbf, 1, 0.0, d.HC, g.nact, 1};
     f[n + i] = F64Gemm{g.naux, g.nact, g.nact, 1.0, d.D, g.nact, 1, d.alpha, g.nact, 1, 0.0, d.dbuf, g.nact, 1};
     f[2 * n + i] = F64Gemm{g.nact, g.nact, g.naux, 1.0, d.D, 1, g.nact, d.D, g.nact, 1, 0.0, d.J, g.nact, 1};
     f[3 * n + i] = F64Gemm{g.nbf, g.nact, g.nbf, 1.0, d.C, 1, g.nbf, d.Y, g.nact, 1, 0.0, d.lam, g.nbf, 1};
   }
-  b->tot1 = off[n];
-  b->tot2 = off[2 * (n + 1) - 1];
-  b->tot3 = off[3 * (n + 1) - 1];
   hipStream_t s = ctx->stream;
   DEV_CHECK(ctx, hipMemcpyAsync(b->d_inst, b->inst.data(), sizeof(BInst) * n, hipMemcpyHostToDevice, s));
   DEV_CHECK(ctx, hipMemcpyAsync(b->d_g1, g1.data(), sizeof(G1Args) * n, hipMemcpyHostToDevice, s));
   DEV_CHECK(ctx, hipMemcpyAsync(b->d_g2, g2.data(), sizeof(G2Args) * n, hipMemcpyHostToDevice, s));
   DEV_CHECK(ctx, hipMemcpyAsync(b->d_g3, g3.data(), sizeof(G3Args) * n, hipMemcpyHostToDevice, s));
-  DEV_CHECK(ctx, hipMemcpyAsync(b->d_off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice, s));
+  DEV_CHECK(ctx, batch_offsets(b, s));
   DEV_CHECK(ctx, hipMemcpyAsync(b->d_f64, f.data(), sizeof(F64Gemm) * f.size(), hipMemcpyHostToDevice, s));
   DEV_CHECK(ctx, batch_pack(s, n, b->d_inst, b->mx));
   // the host staging vectors go out of scope: wait for the copies

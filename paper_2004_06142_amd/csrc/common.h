@@ -193,8 +193,9 @@ struct G3Args {   // Ypart[s] = sum_{P in s} X_P W_P
 __host__ __device__ inline int g1_items(const G1Args& a, int g1m, int g1n, bool stacked) {
   return cdiv(a.nact, g1m) * (stacked ? cdiv((long long)a.np * a.nbf, g1n) : a.np * cdiv(a.nbf, g1n));
 }
-__host__ __device__ inline int g2_items(const G2Args& a) {
-  const int t = cdiv(a.nact, 128);
+// tt: the square tile of the b contraction (128; 64 for the grouped form of short active spaces)
+__host__ __device__ inline int g2_items(const G2Args& a, int tt) {
+  const int t = cdiv(a.nact, tt);
   return a.nsplit * t * (t + 1) / 2;
 }
 // g3m x g3n: the block tile along (mu, q); the launch grid and the kernel's decoding of its block
@@ -206,9 +207,14 @@ __host__ __device__ inline int g3_items(const G3Args& a, int g3m, int g3n) {
 // Grouped launches over the instances of a batch: tab[i] are the arguments of instance i (device
 // memory), off[i] the first work item of instance i (off[ninst] = total).  terms as above;
 // B must be bf16 (exact) with padded rows, and every leading dimension a multiple of 32.
-hipError_t df_bf16_gemm1_grouped(hipStream_t s, int ninst, int total, int terms, const G1Args* tab, const int* off);
-hipError_t df_bf16_gemm2_grouped(hipStream_t s, int ninst, int total, int terms, const G2Args* tab, const int* off);
-hipError_t df_bf16_gemm3_grouped(hipStream_t s, int ninst, int total, int terms, const G3Args* tab, const int* off);
+// tile: width of the tiles along the active orbitals, 128 or 64 (the work-item offsets must be counted
+// with the same width: g1_items(.., tile, 128, true), g2_items(.., tile), g3_items(.., 128, tile)).
+hipError_t df_bf16_gemm1_grouped(hipStream_t s, int ninst, int total, int terms, int tile, const G1Args* tab,
+                                 const int* off);
+hipError_t df_bf16_gemm2_grouped(hipStream_t s, int ninst, int total, int terms, int tile, const G2Args* tab,
+                                 const int* off);
+hipError_t df_bf16_gemm3_grouped(hipStream_t s, int ninst, int total, int terms, int tile, const G3Args* tab,
+                                 const int* off);
 
 hipError_t df_bf16_gemm1(hipStream_t s, int nbf, int nact, int np, int terms, SplitPtr Ct, int ldk, SplitPtr Bp,
                          long long bstride, int ldb, long long b_bytes, u16* XT_hi, u16* XT_lo, int ldx, int variant,

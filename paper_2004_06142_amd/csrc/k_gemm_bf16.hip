@@ -593,49 +593,51 @@ __device__ __forceinline__ void gemm1_body(int w, const G1Args& g) {
   }
 }
 
-// gemm2: b_P = Ct XT_P^T on lower 128-tiles; Kpart[s] += sum_{P in s} b^2 (lower triangle, summed
+// gemm2: b_P = Ct XT_P^T on lower-triangle tiles; Kpart[s] += sum_{P in s} b^2 (lower triangle, summed
 // over the successive P-chunks of one call), D[P][p] = b_pp, W_P = b o beta as a hi/lo pair, written
 // in full (off-diagonal tiles store their mirror image as well).
 // waves along q of a gemm2 block (2 x g2_wgn grid)
 constexpr int g2_wgn(bool vec) { return vec ? 4 : 2; }
 
-template <int TERMS, bool VEC>
+// TT: the square tile (128, or 64 for the short active spaces of batch instances, with 4 waves).
+template <int TERMS, bool VEC, int TT = T2>
 __device__ __forceinline__ void gemm2_body(int w, const G2Args& g) {
   constexpr bool LO = TERMS >= 3;
-  // the direct-load form runs 8 waves (2 x 4, each 64 x 32): half the accumulators, beta and K sums
-  // per wave, so they stay in registers, and two waves per SIMD hide each other's epilogue latency
-  constexpr int WGN = g2_wgn(VEC), NI = T2 / (16 * WGN);
+  // the direct-load form of the 128 tile runs 8 waves (2 x 4, each 64 x 32): half the accumulators,
+  // beta and K sums per wave, so they stay in registers, and two waves per SIMD hide each other's
+  // epilogue latency; the 64 tile runs 4 waves of 32 x 32
+  constexpr int WGN = g2_wgn(VEC && TT == 128), NI = TT / (16 * WGN), MI = TT / 32;
   const int nbf = g.nbf, nact = g.nact, np = g.np, nsplit = g.nsplit, ldw = g.ldw, ldx = g.ldx;
-  const int tt = (nact + T2 - 1) / T2;
+  const int tt = (nact + TT - 1) / TT;
   const int ntri = tt * (tt + 1) / 2;
   const int s = w / ntri;
   int tm, tn;
   tri_tile(w % ntri, tt, tm, tn);
-  const int m0 = tm * T2, n0 = tn * T2;
+  const int m0 = tm * TT, n0 = tn * TT;
   const int pb = (int)((long long)np * s / nsplit), pe = (int)((long long)np * (s + 1) / nsplit);
   // beta of this lane's accumulator positions, kept in registers for the whole P-range
-  f32x4 bet[4][NI];
+  f32x4 bet[MI][NI];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
     for (int jn = 0; jn < NI; ++jn)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int p = m0 + row_of<T2, 2, WGN>(i, j), q = n0 + col_of<T2, 2, WGN>(jn);
+        const int p = m0 + row_of<TT, 2, WGN>(i, j), q = n0 + col_of<TT, 2, WGN>(jn);
         bet[i][jn][j] = (p < nact && q < nact) ? g.beta32[(long long)p * nact + q] : 0.f;
       }
-  f32x4 kacc[4][NI], acc[4][NI];
+  f32x4 kacc[MI][NI], acc[MI][NI];
   zero(kacc);
   const bool diag = (tm == tn);
-  auto epi = [&](int seg, f32x4(&a)[4][NI]) {
+  auto epi = [&](int seg, f32x4(&a)[MI][NI]) {
     const int P = pb + seg;
     u16* Wh = g.w_hi + (long long)P * g.ws.nact32 * ldw;
     u16* Wl = LO ? g.w_lo + (long long)P * g.ws.nact32 * ldw : nullptr;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
       for (int jn = 0; jn < NI; ++jn) {
-        const int p0 = m0 + row_of<T2, 2, WGN>(i, 0), q = n0 + col_of<T2, 2, WGN>(jn);
+        const int p0 = m0 + row_of<TT, 2, WGN>(i, 0), q = n0 + col_of<TT, 2, WGN>(jn);
         float wv[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -681,31 +683,31 @@ __device__ __forceinline__ void gemm2_body(int w, const G2Args& g) {
       }
   };
   if constexpr (VEC) {
-    constexpr int S = ring_depth(T2, T2, LO, LO, 163840);
-    __shared__ Ring<T2, T2, LO, LO, S> sm;
+    constexpr int S = ring_depth(TT, TT, LO, LO, TT == 128 ? 163840 : 81920);
+    __shared__ Ring<TT, TT, LO, LO, S> sm;
     auto A = [&](int) { return DOpnd{g.ct_hi, g.ct_lo, g.ldk, g.ws.ct_bytes}; };
     auto B = [&](int seg) {
       const long long off = (long long)(pb + seg) * g.ws.nact32 * ldx;
       return DOpnd{g.xt_hi + off, LO ? g.xt_lo + off : nullptr, ldx, g.ws.xt_bytes - 2 * off};
     };
-    mainloop_dl<T2, T2, LO, LO, S, false, false, true, 2, WGN>(sm, pe - pb, 0, nbf, m0, n0, A, B, acc, epi);
+    mainloop_dl<TT, TT, LO, LO, S, false, false, true, 2, WGN>(sm, pe - pb, 0, nbf, m0, n0, A, B, acc, epi);
   } else {
-    __shared__ Stage<T2, T2, LO, LO> sm;
+    __shared__ Stage<TT, TT, LO, LO> sm;
     auto A = [&](int) { return Opnd{g.ct_hi, g.ct_lo, g.ldk, nact, nbf, false}; };
     auto B = [&](int seg) {
       const long long off = (long long)(pb + seg) * g.ws.nact32 * ldx;
       return Opnd{g.xt_hi + off, LO ? g.xt_lo + off : nullptr, ldx, nact, nbf, false};
     };
-    mainloop<T2, T2, LO, LO, false, false, true>(sm, pe - pb, 0, nbf, m0, n0, A, B, acc, epi);
+    mainloop<TT, TT, LO, LO, false, false, true>(sm, pe - pb, 0, nbf, m0, n0, A, B, acc, epi);
   }
   double* Kp = g.Kpart + (long long)s * nact * nact;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
     for (int jn = 0; jn < NI; ++jn)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int p = m0 + row_of<T2, 2, WGN>(i, j), q = n0 + col_of<T2, 2, WGN>(jn);
+        const int p = m0 + row_of<TT, 2, WGN>(i, j), q = n0 + col_of<TT, 2, WGN>(jn);
         if (p < nact && q <= p) Kp[(long long)p * nact + q] += (double)kacc[i][jn][j];
       }
 }
@@ -779,7 +781,7 @@ __global__ __launch_bounds__(64 * WGM * WGN, MINB) void gemm1_kernel(G1Args g) {
 }
 template <int TERMS, bool VEC>
 __global__ __launch_bounds__(128 * g2_wgn(VEC), 1) void gemm2_kernel(G2Args g) {
-  const int w = xcd_item(g2_items(g));
+  const int w = xcd_item(g2_items(g, T2));
   if (w < 0) return;
   gemm2_body<TERMS, VEC>(w, g);
 }
@@ -790,35 +792,37 @@ __global__ __launch_bounds__(64 * WGM * WGN, MINB) void gemm3_kernel(G3Args g) {
   gemm3_body<TERMS, G3M, G3N, WGM, WGN, MINB, VEC>(w, g);
 }
 
-// Grouped forms: one launch over the work items of every instance of a batch.
-// (two blocks per compute unit, as the single-problem 128 x 128 form: 8.6 -> 7.7 ms per 64-instance
-// PES batch)
-template <int TERMS>
+// Grouped forms: one launch over the work items of every instance of a batch.  The tile width along
+// the active orbitals is a template parameter (128, or 64 when the instances' active spaces are
+// short); the 64-wide forms run 4 waves and two blocks per compute unit.
+// (X at two blocks per compute unit, as the single-problem 128 x 128 form: 8.6 -> 7.7 ms per
+// 64-instance PES batch)
+template <int TERMS, int TM>
 __global__ __launch_bounds__(256, 2) void gemm1_grouped(const G1Args* __restrict__ tab, const int* __restrict__ off,
                                                         int ninst, int total) {
   const int w = xcd_item(total);
   if (w < 0) return;
   const int i = find_instance(off, ninst, w);
   const G1Args g = tab[i];
-  gemm1_body<TERMS, false, 128, 128, 2, 2, 2, true, true>(w - off[i], g);
+  gemm1_body<TERMS, false, TM, 128, 2, 2, 2, true, true>(w - off[i], g);
 }
-template <int TERMS>
-__global__ __launch_bounds__(128 * g2_wgn(true), 1) void gemm2_grouped(const G2Args* __restrict__ tab, const int* __restrict__ off,
-                                                        int ninst, int total) {
+template <int TERMS, int TT>
+__global__ __launch_bounds__(TT == 128 ? 128 * g2_wgn(true) : 256, TT == 128 ? 1 : 2) void gemm2_grouped(
+    const G2Args* __restrict__ tab, const int* __restrict__ off, int ninst, int total) {
   const int w = xcd_item(total);
   if (w < 0) return;
   const int i = find_instance(off, ninst, w);
   const G2Args g = tab[i];
-  gemm2_body<TERMS, true>(w - off[i], g);
+  gemm2_body<TERMS, true, TT>(w - off[i], g);
 }
-template <int TERMS>
+template <int TERMS, int TN>
 __global__ __launch_bounds__(256, 2) void gemm3_grouped(const G3Args* __restrict__ tab, const int* __restrict__ off,
                                                         int ninst, int total) {
   const int w = xcd_item(total);
   if (w < 0) return;
   const int i = find_instance(off, ninst, w);
   const G3Args g = tab[i];
-  gemm3_body<TERMS, 128, 128, 2, 2, 2, true>(w - off[i], g);
+  gemm3_body<TERMS, 128, TN, 2, 2, 2, true>(w - off[i], g);
 }
 
 inline dim3 xcd_grid(long long items) { return dim3((unsigned)(cdiv(items, NXCD) * NXCD)); }
@@ -868,7 +872,7 @@ hipError_t df_bf16_gemm2(hipStream_t s, int nbf, int nact, int np, int nsplit, i
                          u16* W_lo, int ldw, const WsDims& d) {
   if (np <= 0) return hipSuccess;
   const G2Args g{nbf, nact, np, nsplit, Ct.hi, Ct.lo, ldk, XT.hi, XT.lo, ldx, beta32, Kpart, Dchunk, W_hi, W_lo, ldw, d};
-  const dim3 grid = xcd_grid(g2_items(g));
+  const dim3 grid = xcd_grid(g2_items(g, T2));
   const bool vec = (ldk % 32 == 0) && (ldx % 32 == 0) && al16(Ct.hi) && (!Ct.lo || al16(Ct.lo)) && al16(XT.hi) &&
                    (!XT.lo || al16(XT.lo));
   if (terms == 1) {
@@ -915,23 +919,44 @@ hipError_t df_bf16_gemm3(hipStream_t s, int nbf, int nact, int np, int nsplit, i
   return hipGetLastError();
 }
 
-hipError_t df_bf16_gemm1_grouped(hipStream_t s, int ninst, int total, int terms, const G1Args* tab, const int* off) {
+hipError_t df_bf16_gemm1_grouped(hipStream_t s, int ninst, int total, int terms, int tile, const G1Args* tab,
+                                 const int* off) {
   if (total <= 0) return hipSuccess;
-  if (terms == 1) hipLaunchKernelGGL((gemm1_grouped<1>), xcd_grid(total), dim3(256), 0, s, tab, off, ninst, total);
-  else hipLaunchKernelGGL((gemm1_grouped<2>), xcd_grid(total), dim3(256), 0, s, tab, off, ninst, total);
+  const dim3 gr = xcd_grid(total);
+  if (tile == 64) {
+    if (terms == 1) hipLaunchKernelGGL((gemm1_grouped<1, 64>), gr, dim3(256), 0, s, tab, off, ninst, total);
+    else hipLaunchKernelGGL((gemm1_grouped<2, 64>), gr, dim3(256), 0, s, tab, off, ninst, total);
+  } else {
+    if (terms == 1) hipLaunchKernelGGL((gemm1_grouped<1, 128>), gr, dim3(256), 0, s, tab, off, ninst, total);
+    else hipLaunchKernelGGL((gemm1_grouped<2, 128>), gr, dim3(256), 0, s, tab, off, ninst, total);
+  }
   return hipGetLastError();
 }
-hipError_t df_bf16_gemm2_grouped(hipStream_t s, int ninst, int total, int terms, const G2Args* tab, const int* off) {
+hipError_t df_bf16_gemm2_grouped(hipStream_t s, int ninst, int total, int terms, int tile, const G2Args* tab,
+                                 const int* off) {
   if (total <= 0) return hipSuccess;
-  if (terms == 1)
-    hipLaunchKernelGGL((gemm2_grouped<1>), xcd_grid(total), dim3(128 * g2_wgn(true)), 0, s, tab, off, ninst, total);
-  else hipLaunchKernelGGL((gemm2_grouped<3>), xcd_grid(total), dim3(128 * g2_wgn(true)), 0, s, tab, off, ninst, total);
+  const dim3 gr = xcd_grid(total);
+  if (tile == 64) {
+    if (terms == 1) hipLaunchKernelGGL((gemm2_grouped<1, 64>), gr, dim3(256), 0, s, tab, off, ninst, total);
+    else hipLaunchKernelGGL((gemm2_grouped<3, 64>), gr, dim3(256), 0, s, tab, off, ninst, total);
+  } else {
+    const dim3 bl(128 * g2_wgn(true));
+    if (terms == 1) hipLaunchKernelGGL((gemm2_grouped<1, 128>), gr, bl, 0, s, tab, off, ninst, total);
+    else hipLaunchKernelGGL((gemm2_grouped<3, 128>), gr, bl, 0, s, tab, off, ninst, total);
+  }
   return hipGetLastError();
 }
-hipError_t df_bf16_gemm3_grouped(hipStream_t s, int ninst, int total, int terms, const G3Args* tab, const int* off) {
+hipError_t df_bf16_gemm3_grouped(hipStream_t s, int ninst, int total, int terms, int tile, const G3Args* tab,
+                                 const int* off) {
   if (total <= 0) return hipSuccess;
-  if (terms == 1) hipLaunchKernelGGL((gemm3_grouped<1>), xcd_grid(total), dim3(256), 0, s, tab, off, ninst, total);
-  else hipLaunchKernelGGL((gemm3_grouped<3>), xcd_grid(total), dim3(256), 0, s, tab, off, ninst, total);
+  const dim3 gr = xcd_grid(total);
+  if (tile == 64) {
+    if (terms == 1) hipLaunchKernelGGL((gemm3_grouped<1, 64>), gr, dim3(256), 0, s, tab, off, ninst, total);
+    else hipLaunchKernelGGL((gemm3_grouped<3, 64>), gr, dim3(256), 0, s, tab, off, ninst, total);
+  } else {
+    if (terms == 1) hipLaunchKernelGGL((gemm3_grouped<1, 128>), gr, dim3(256), 0, s, tab, off, ninst, total);
+    else hipLaunchKernelGGL((gemm3_grouped<3, 128>), gr, dim3(256), 0, s, tab, off, ninst, total);
+  }
   return hipGetLastError();
 }
 

@@ -162,7 +162,13 @@ def test_rebind_with_new_orbitals(ctx):
         assert abs(o["E"].item() - r["E"]) < _energy_tol(n, r, wl, pnof.PNOF7)
 
 
-def test_full_pes_scan_against_stored_oracle_values(ctx):
+# tile widths along the active orbitals of the grouped X, b, Y (None: the automatic choice); the
+# 64-wide forms cut the padding of the short active spaces (nact = 0.4 nbf in [16, 120])
+TILES = [None, (128, 128, 128), (64, 64, 64), (64, 128, 64), (128, 64, 128)]
+
+
+@pytest.mark.parametrize("tiles", TILES, ids=[str(t) for t in TILES])
+def test_full_pes_scan_against_stored_oracle_values(ctx, tiles):
     if not os.path.exists(GOLD):
         pytest.skip("pes64 expected values not generated")
     ref = json.load(open(GOLD))
@@ -172,6 +178,9 @@ def test_full_pes_scan_against_stored_oracle_values(ctx):
     batch = P.Batch(ctx, probs)
     ins = [_device_inputs(ctx, i) for i in insts]
     outs = batch.bind(ins)
+    if tiles is not None:
+        batch.set_tiles(*tiles)        # after bind: offsets recomputed, graph dropped
+        assert batch.tiles() == tiles
     batch.run(graph=True)
     torch.cuda.synchronize()
     worst = {"E": 0.0, "lam": 0.0, "dEdC": 0.0, "dEdn": 0.0}
@@ -190,7 +199,32 @@ def test_full_pes_scan_against_stored_oracle_values(ctx):
         assert abs(o["max_asym"].item() - r["max_asym"]) < 2e-5
         for k, v in (("E", dE), ("lam", el), ("dEdC", ec), ("dEdn", en)):
             worst[k] = max(worst[k], v)
-    print("pes64 worst errors", {k: f"{v:.2e}" for k, v in worst.items()})
+    print("pes64 worst errors", batch.tiles(), {k: f"{v:.2e}" for k, v in worst.items()})
+    batch.close()
+
+
+def test_batch_tile_tuner(ctx):
+    """The batch autotuner times the tile widths of a bound batch and leaves a valid choice in place;
+    results under every choice agree with the 128-wide reference to float32 summation order."""
+    from paper_2004_06142_amd import autotune
+    insts = synth.pes_scan(6, seed=11, with_b=False)
+    probs = [P.problem(i.wl.nbf, i.wl.naux, i.wl.npairs, i.wl.ncwo, P.PNOF7, P.BF16_SPLIT, P.INTS_DF_BF16)
+             for i in insts]
+    batch = P.Batch(ctx, probs)
+    outs = batch.bind([_device_inputs(ctx, i) for i in insts])
+    batch.set_tiles(128, 128, 128)
+    batch.run(graph=False)
+    torch.cuda.synchronize()
+    ref = [float(o["E"].item()) for o in outs]
+    ent = autotune.tune_batch(batch, reps=3, use_cache=False)
+    assert tuple(ent["tiles"]) == batch.tiles() and all(t in (64, 128) for t in ent["tiles"])
+    batch.run(graph=True)
+    torch.cuda.synchronize()
+    for o, e in zip(outs, ref):
+        assert abs(o["E"].item() - e) < 1e-7
+    with pytest.raises(P.PnofError, match="PNOF_E_ARG"):
+        batch.set_tiles(96, 0, 0)
+    batch.close()
 
 
 def test_batch_error_paths(ctx):
