@@ -28,15 +28,15 @@ KSRC = os.path.join(ROOT, "paper_2004_06142_amd", "csrc")
 # once the source changes the figure no longer applies and traffic is reported as null.
 TRAFFIC = {
     # profiles/c5_df1200_hbm_traffic.md: C5, bf16 split, 164-row chunks (read + written bytes per launch)
-    ("gemm1_kernel", 3): {"bytes": 1605205416 + 925021926,
+    ("gemm1_kernel", 3): {"bytes": 1593675954 + 925182301,
                           "plan": {"pchunk": 164, "x_variant": 3},
-                          "sha256": {"k_gemm_bf16.hip": "fa87ab5462fcc90db27209aab0d9d7a43dab7ec032cb23ed34f40d884ad5e71f"}},
-    ("gemm2_kernel", 3): {"bytes": 3493328017 + 1138433279,
+                          "sha256": {"k_gemm_bf16.hip": "93e384042bfef719761bc804c10593f04cb61e0cdc64d44db46345e525e50c8a"}},
+    ("gemm2_kernel", 3): {"bytes": 3506566865 + 1139885083,
                           "plan": {"pchunk": 164, "nsplit_b": 18},
-                          "sha256": {"k_gemm_bf16.hip": "fa87ab5462fcc90db27209aab0d9d7a43dab7ec032cb23ed34f40d884ad5e71f"}},
-    ("gemm3_kernel", 3): {"bytes": 2767146960 + 241445775,
+                          "sha256": {"k_gemm_bf16.hip": "93e384042bfef719761bc804c10593f04cb61e0cdc64d44db46345e525e50c8a"}},
+    ("gemm3_kernel", 3): {"bytes": 2751681556 + 241431699,
                           "plan": {"pchunk": 164, "nsplit_y": 10, "y_variant": 3},
-                          "sha256": {"k_gemm_bf16.hip": "fa87ab5462fcc90db27209aab0d9d7a43dab7ec032cb23ed34f40d884ad5e71f"}},
+                          "sha256": {"k_gemm_bf16.hip": "93e384042bfef719761bc804c10593f04cb61e0cdc64d44db46345e525e50c8a"}},
 }
 GOLDEN_C5 = os.path.join(ROOT, "tests", "golden", "c5_df1200_expected.json")
 
