@@ -415,7 +415,7 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
         DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_B, df_bf16_gemm2(s, nbf, nact, np, ns2, pl.terms, Ct, pl.ldk, XT, pl.ldx, b.beta32, b.Kpart, Dc,
                                      b.wh, b.wl, pl.ldw, wd)));
         if (want_y) {
-          DEV_CHECK(ctx, add_diag_bf16(s, nact, np, Dc, b.alpha, b.dbuf, b.wh, b.wl, pl.ldw, (long long)pl.nact32 * pl.ldw));
+          DEV_CHECK(ctx, add_diag_bf16(s, nact, np, Dc, b.alpha, b.beta32, b.dbuf, b.wh, b.wl, pl.ldw, (long long)pl.nact32 * pl.ldw));
           SplitPtr W{b.wh, b.wl};
           DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_Y, df_bf16_gemm3(s, nbf, nact, np, ns3, pl.terms, XT, pl.ldx, W, pl.ldw, b.Ypart32, pl.yv, wd)));
           DEV_CHECK(ctx, reduce_y_f32(s, ny, ns3, b.Ypart32, b.Y2e));
@@ -1379,6 +1379,7 @@ pnof_status pnof_batch_plan(pnof_ctx ctx, int32_t ninst, const pnof_problem* pro
       d.Hpp = a.take<double>(g.nact);
       d.D = a.take<double>((long long)g.naux * g.nact);
       d.dbuf = a.take<double>((long long)g.naux * g.nact);
+      d.epart = a.take<double>(BATCH_EPARTS);
     }
     b->d_inst = a.take<BInst>(ninst);
     b->d_g1 = a.take<G1Args>(ninst);
@@ -1412,7 +1413,7 @@ pnof_status pnof_batch_plan(pnof_ctx ctx, int32_t ninst, const pnof_problem* pro
     mx.nbf = std::max(mx.nbf, g.nbf);
     mx.nact = std::max(mx.nact, g.nact);
     mx.pack = std::max(mx.pack, (long long)g.naux * g.nact32 * g.ldk + (long long)g.naux * g.nbf * g.ldk);
-    mx.prep = std::max(mx.prep, std::max((long long)g.ns2 * n2, (long long)g.nact * g.nbf));
+    mx.prep = std::max(mx.prep, std::max(n2, (long long)g.nact * g.nbf));
     mx.y = std::max(mx.y, ny);
     mx.k = std::max(mx.k, n2);
     mx.diag = std::max(mx.diag, (long long)g.naux * g.nact);

@@ -59,6 +59,24 @@ __device__ inline double grad_n_term(int p, int q, double np_, double nq, double
   return s;
 }
 
+// sum_{k < ns} p[k * stride], added in order of k, with the loads issued eight at a time: the partial
+// sums of a split contraction lie far apart in memory, and with one load in flight per thread the
+// reduction would wait out the memory latency once per split.
+template <typename T>
+__device__ __forceinline__ double sum_strided(const T* __restrict__ p, int ns, long long stride) {
+  double s = 0.0;
+  int k = 0;
+  for (; k + 8 <= ns; k += 8) {
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = p[(long long)(k + u) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += (double)v[u];
+  }
+  for (; k < ns; ++k) s += (double)p[(long long)k * stride];
+  return s;
+}
+
 // ---------------------------------------------------------------- bf16 helpers
 // Round-to-nearest-even float32 -> bfloat16 bits (inputs here are finite).
 __device__ __forceinline__ u16 f32_to_bf16_bits(float x) {
@@ -209,6 +227,8 @@ __host__ __device__ inline int g3_items(const G3Args& a, int g3m, int g3n) {
 // B must be bf16 (exact) with padded rows, and every leading dimension a multiple of 32.
 // tile: width of the tiles along the active orbitals, 128 or 64 (the work-item offsets must be counted
 // with the same width: g1_items(.., tile, 128, true), g2_items(.., tile), g3_items(.., 128, tile)).
+// The grouped b contraction covers every P of its instances, so it stores its K sums into Kpart
+// (no prior clearing) where the single-problem form adds them.
 hipError_t df_bf16_gemm1_grouped(hipStream_t s, int ninst, int total, int terms, int tile, const G1Args* tab,
                                  const int* off);
 hipError_t df_bf16_gemm2_grouped(hipStream_t s, int ninst, int total, int terms, int tile, const G2Args* tab,
@@ -242,10 +262,13 @@ struct BInst {
   double* asym;
   u16* Bp;              // packed B: naux x nbf x ldk, zero pads
   double *alpha, *beta, *HC, *Hpp, *J, *K, *Kpart, *D, *dbuf, *Y2e, *Y;
+  double* epart;        // BATCH_EPARTS energy partials, summed in order by the last launch
   float* beta32;
   float* Ypart;
   u16 *cth, *ctl, *xth, *xtl, *wh, *wl;
 };
+// Blocks per instance that sum the energy (each writes one partial to epart).
+constexpr int BATCH_EPARTS = 32;
 // Each launch covers every instance (blockIdx.y = instance); maxima size the grids.
 struct BMax {
   int nbf, nact;
@@ -280,11 +303,13 @@ int gemm_f64_ksplit(int M, int N, int K);
 hipError_t gemm_f64_splitk(hipStream_t s, int M, int N, int K, int ks, const double* A, long long sam, long long sak,
                            const double* B, long long sbk, long long sbn, double* Cpart);
 // d = Dchunk alpha (float64 matrix cores, split over k into the F64_KSPLIT_MAX * np * nact doubles of
-// dbuf), then W_P[p][p] += d[P][p].
+// dbuf), then W_P[p][p] += d[P][p].  The split form rebuilds the diagonal from Dchunk (the b
+// contraction's float accumulators b^P_pp) as float(b^P_pp * beta32_pp) + d[P][p] and only writes it,
+// so W's scattered diagonal is never read back.
 hipError_t add_diag_f64(hipStream_t s, int nact, int np, const double* Dchunk, const double* alpha,
                         double* dbuf, double* W, int ldw);
 hipError_t add_diag_bf16(hipStream_t s, int nact, int np, const double* Dchunk, const double* alpha,
-                         double* dbuf, u16* W_hi, u16* W_lo, int ldw, long long pstride);
+                         const float* beta32, double* dbuf, u16* W_hi, u16* W_lo, int ldw, long long pstride);
 hipError_t reduce_k(hipStream_t s, int nact, int nsplit, const double* Kpart, double* K);
 hipError_t reduce_y_f64(hipStream_t s, long long n, int nsplit, const double* Ypart, double* Y);
 hipError_t reduce_y_f32(hipStream_t s, long long n, int nsplit, const float* Ypart, double* Y);

@@ -45,7 +45,8 @@ __global__ void pack_k(const BInst* __restrict__ tab) {
   }
 }
 
-// alpha, beta (float64 and float32), C_A^T split into hi/lo, K partials zeroed.
+// alpha, beta (float64 and float32), C_A^T split into hi/lo.  The K partials need no clearing: the
+// grouped b contraction stores (not adds) every lower-triangle position of every split.
 __global__ void prep_k(const BInst* __restrict__ tab) {
   const BInst& d = tab[blockIdx.y];
   const int nact = d.nact, nbf = d.nbf;
@@ -65,7 +66,6 @@ __global__ void prep_k(const BInst* __restrict__ tab) {
     d.cth[(long long)p * d.ldk + mu] = h;
     if (d.terms > 1) d.ctl[(long long)p * d.ldk + mu] = l;
   }
-  INST_STRIDE(i, (long long)d.ns2 * n2) d.Kpart[i] = 0.0;
 }
 
 // Hpp[p] = sum_mu C[mu][p] HC[mu][p]: one wavefront per orbital.
@@ -79,7 +79,9 @@ __global__ void hpp_k(const BInst* __restrict__ tab) {
   if (threadIdx.x == 0) d.Hpp[p] = s;
 }
 
-// W_P[p][p] += (D alpha)[P][p], re-split into hi/lo.
+// W_P[p][p] = float(b^P_pp beta_pp) + (D alpha)[P][p], split into hi/lo.  D holds the b contraction's
+// float accumulators of the diagonal, so the entry is rebuilt and only written: the scattered
+// diagonal of W is never read back.
 __global__ void add_diag_k(const BInst* __restrict__ tab) {
   const BInst& d = tab[blockIdx.y];
   const long long pstride = (long long)d.nact32 * d.ldw;
@@ -87,29 +89,27 @@ __global__ void add_diag_k(const BInst* __restrict__ tab) {
     const long long P = i / d.nact;
     const int p = (int)(i % d.nact);
     const long long o = P * pstride + (long long)p * d.ldw + p;
-    const double w = (double)bf16_bits_to_f32(d.wh[o]) + (d.wl ? (double)bf16_bits_to_f32(d.wl[o]) : 0.0) + d.dbuf[i];
+    const float wv = (float)d.D[i] * d.beta32[(long long)p * d.nact + p];
     u16 h, l;
-    split_f64(w, h, l);
+    split_f64((double)wv + d.dbuf[i], h, l);
     d.wh[o] = h;
     if (d.wl) d.wl[o] = l;
   }
 }
 
-// Y2e = sum_s Ypart[s]; K[p][q] = sum_s Kpart[s][max(p,q)][min(p,q)].
+// Y2e = sum_s Ypart[s]; K[p][q] = K[q][p] = sum_s Kpart[s][p][q] for q <= p (rows read coalesced).
 __global__ void reduce_k(const BInst* __restrict__ tab) {
   const BInst& d = tab[blockIdx.y];
   const long long ny = (long long)d.nbf * d.nact, n2 = (long long)d.nact * d.nact;
   INST_STRIDE(i, ny) {
-    double s = 0.0;
-    for (int k = 0; k < d.ns3; ++k) s += (double)d.Ypart[(long long)k * ny + i];
-    d.Y2e[i] = s;
+    d.Y2e[i] = sum_strided(d.Ypart + i, d.ns3, ny);
   }
   INST_STRIDE(i, n2) {
     const int p = (int)(i / d.nact), q = (int)(i % d.nact);
-    const int a = p > q ? p : q, b = p > q ? q : p;
-    double s = 0.0;
-    for (int k = 0; k < d.ns2; ++k) s += d.Kpart[(long long)k * n2 + (long long)a * d.nact + b];
+    if (q > p) continue;
+    const double s = sum_strided(d.Kpart + i, d.ns2, n2);
     d.K[i] = s;
+    d.K[(long long)q * d.nact + p] = s;
   }
 }
 
@@ -139,65 +139,70 @@ __device__ inline double block_max(double v) {
   return s;
 }
 
-// Energy of Eq. EPNOF7 with the first-order correction of the split orbitals, one block per
-// instance (fixed summation order); Y = n o (H C_A) + Y2e on the other blocks.
+// Energy of Eq. EPNOF7 with the first-order correction of the split orbitals: blocks
+// 0 .. BATCH_EPARTS-1 of each instance each sum one contiguous range of the terms (fixed order) into
+// epart; the last launch adds the partials in order.  The other blocks form Y = n o (H C_A) + Y2e.
+// Block 0 also clears the asymmetry maximum that the last launch raises.
 __global__ void energy_y_k(const BInst* __restrict__ tab) {
   const BInst& d = tab[blockIdx.y];
   const int nbf = d.nbf, nact = d.nact;
-  const long long ny = (long long)nbf * nact;
-  if (blockIdx.x == 0) {
-    const long long n2 = (long long)nact * nact;
-    const long long total = nact + n2 + ny;
+  const long long ny = (long long)nbf * nact, n2 = (long long)nact * nact;
+  if (blockIdx.x < BATCH_EPARTS) {
+    const long long total = nact + n2 + ny, per = (total + BATCH_EPARTS - 1) / BATCH_EPARTS;
+    const long long lo = (long long)blockIdx.x * per, hi = lo + per < total ? lo + per : total;
     double s = 0.0;
-    for (long long i = threadIdx.x; i < total; i += blockDim.x) {
-      if (i < nact) s += 2.0 * d.n[i] * d.Hpp[i];
-      else if (i < nact + n2) {
-        const long long k = i - nact;
-        s += d.alpha[k] * d.J[k] + d.beta[k] * d.K[k];
-      } else {
-        const long long k = i - nact - n2;
-        const int mu = (int)(k / nact), p = (int)(k % nact);
-        double ct = (double)bf16_bits_to_f32(d.cth[(long long)p * d.ldk + mu]);
-        if (d.terms > 1) ct += (double)bf16_bits_to_f32(d.ctl[(long long)p * d.ldk + mu]);
-        s += 4.0 * d.Y2e[k] * (d.C[(long long)mu * nbf + p] - ct);
-      }
+    const long long e0 = lo < nact ? lo : nact, e1 = hi < nact ? hi : nact;
+    for (long long i = e0 + threadIdx.x; i < e1; i += blockDim.x) s += 2.0 * d.n[i] * d.Hpp[i];
+    const long long j0 = (lo > nact ? lo : nact) - nact, j1 = (hi < nact + n2 ? hi : nact + n2) - nact;
+    for (long long k = j0 + threadIdx.x; k < j1; k += blockDim.x) s += d.alpha[k] * d.J[k] + d.beta[k] * d.K[k];
+    const long long y0 = (lo > nact + n2 ? lo : nact + n2) - nact - n2, y1 = hi - nact - n2;
+    for (long long k = y0 + threadIdx.x; k < y1; k += blockDim.x) {
+      const int mu = (int)(k / nact), p = (int)(k % nact);
+      double ct = (double)bf16_bits_to_f32(d.cth[(long long)p * d.ldk + mu]);
+      if (d.terms > 1) ct += (double)bf16_bits_to_f32(d.ctl[(long long)p * d.ldk + mu]);
+      s += 4.0 * d.Y2e[k] * (d.C[(long long)mu * nbf + p] - ct);
     }
     s = block_sum(s);
-    if (threadIdx.x == 0) *d.E = s;
+    if (threadIdx.x == 0) {
+      d.epart[blockIdx.x] = s;
+      if (blockIdx.x == 0 && d.asym) *d.asym = 0.0;
+    }
     return;
   }
-  for (long long i = (long long)(blockIdx.x - 1) * blockDim.x + threadIdx.x; i < ny;
-       i += (long long)(gridDim.x - 1) * blockDim.x)
+  for (long long i = (long long)(blockIdx.x - BATCH_EPARTS) * blockDim.x + threadIdx.x; i < ny;
+       i += (long long)(gridDim.x - BATCH_EPARTS) * blockDim.x)
     d.Y[i] = d.n[i % nact] * d.HC[i] + d.Y2e[i];
 }
 
-// lambda columns >= nact zeroed, dE/dC = 4 Y (zero columns beyond nact), dE/dn (one wavefront per
-// orbital), max |lambda - lambda^T| (last block row).
+// E = sum of the energy partials in order; lambda columns >= nact zeroed, dE/dC = 4 Y (zero columns
+// beyond nact), max |lambda - lambda^T| (every block takes its own maximum and raises the instance's
+// with an integer atomic max on the bits, exact for non-negative doubles), dE/dn (one wavefront per
+// orbital).
 __global__ void finish_k(const BInst* __restrict__ tab) {
   const BInst& d = tab[blockIdx.y];
   const int nbf = d.nbf, nact = d.nact;
-  const int nb = gridDim.x;
-  if ((int)blockIdx.x == nb - 1) {
-    if (!d.asym) return;
-    __syncthreads();
-    double m = 0.0;
-    for (long long i = threadIdx.x; i < (long long)nbf * nbf; i += blockDim.x) {
-      const long long p = i / nbf, q = i % nbf;
-      const double a = q < nact ? d.lam[i] : 0.0, b = p < nact ? d.lam[q * nbf + p] : 0.0;
-      m = fmax(m, fabs(a - b));
-    }
-    m = block_max(m);
-    if (threadIdx.x == 0) *d.asym = m;
-    return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double e = 0.0;
+    for (int b = 0; b < BATCH_EPARTS; ++b) e += d.epart[b];
+    *d.E = e;
   }
-  // blocks 0 .. nb-2: element-wise part, with the first nact * 64 threads also doing dE/dn
-  const long long nthreads = (long long)(nb - 1) * blockDim.x;
+  const long long nthreads = (long long)gridDim.x * blockDim.x;
   const long long t0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  double m = 0.0;
   for (long long i = t0; i < (long long)nbf * nbf; i += nthreads) {
     const long long r = i / nbf;
     const int c = (int)(i % nbf);
+    if (d.asym) {
+      const double a = c < nact ? d.lam[i] : 0.0, b = r < nact ? d.lam[(long long)c * nbf + r] : 0.0;
+      m = fmax(m, fabs(a - b));
+    }
     if (c >= nact) d.lam[i] = 0.0;
     if (d.dEdC) d.dEdC[i] = c < nact ? 4.0 * d.Y[r * nact + c] : 0.0;
+  }
+  if (d.asym) {
+    m = block_max(m);
+    if (threadIdx.x == 0 && m > 0.0)
+      atomicMax(reinterpret_cast<unsigned long long*>(d.asym), (unsigned long long)__double_as_longlong(m));
   }
   if (!d.dEdn) return;
   const int lane = threadIdx.x & 63;
@@ -243,13 +248,12 @@ hipError_t batch_reduce(hipStream_t s, int ninst, const BInst* tab, const BMax& 
 }
 hipError_t batch_energy_y(hipStream_t s, int ninst, const BInst* tab, const BMax& mx) {
   dim3 g = grid2(mx.y, ninst);
-  g.x += 1;
+  g.x += BATCH_EPARTS;
   LAUNCH2(energy_y_k, g, tab);
 }
 hipError_t batch_finish(hipStream_t s, int ninst, const BInst* tab, const BMax& mx) {
   dim3 g = grid2((long long)mx.nbf * mx.nbf, ninst);
   if (g.x * NT / 64 < (unsigned)mx.nact) g.x = (unsigned)((mx.nact * 64LL + NT - 1) / NT);
-  g.x += 1;
   LAUNCH2(finish_k, g, tab);
 }
 

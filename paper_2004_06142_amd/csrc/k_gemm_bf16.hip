@@ -600,7 +600,8 @@ __device__ __forceinline__ void gemm1_body(int w, const G1Args& g) {
 constexpr int g2_wgn(bool vec) { return vec ? 4 : 2; }
 
 // TT: the square tile (128, or 64 for the short active spaces of batch instances, with 4 waves).
-template <int TERMS, bool VEC, int TT = T2>
+// KSET: store the K sums instead of adding them (a launch that covers every P of the problem).
+template <int TERMS, bool VEC, int TT = T2, bool KSET = false>
 __device__ __forceinline__ void gemm2_body(int w, const G2Args& g) {
   constexpr bool LO = TERMS >= 3;
   // the direct-load form of the 128 tile runs 8 waves (2 x 4, each 64 x 32): half the accumulators,
@@ -708,7 +709,10 @@ __device__ __forceinline__ void gemm2_body(int w, const G2Args& g) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int p = m0 + row_of<TT, 2, WGN>(i, j), q = n0 + col_of<TT, 2, WGN>(jn);
-        if (p < nact && q <= p) Kp[(long long)p * nact + q] += (double)kacc[i][jn][j];
+        if (p < nact && q <= p) {
+          if constexpr (KSET) Kp[(long long)p * nact + q] = (double)kacc[i][jn][j];
+          else Kp[(long long)p * nact + q] += (double)kacc[i][jn][j];
+        }
       }
 }
 
@@ -813,7 +817,7 @@ __global__ __launch_bounds__(TT == 128 ? 128 * g2_wgn(true) : 256, TT == 128 ? 1
   if (w < 0) return;
   const int i = find_instance(off, ninst, w);
   const G2Args g = tab[i];
-  gemm2_body<TERMS, true, TT>(w - off[i], g);
+  gemm2_body<TERMS, true, TT, true>(w - off[i], g);
 }
 template <int TERMS, int TN>
 __global__ __launch_bounds__(256, 2) void gemm3_grouped(const G3Args* __restrict__ tab, const int* __restrict__ off,

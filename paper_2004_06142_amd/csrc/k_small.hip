@@ -109,39 +109,38 @@ __global__ void add_diag_f64_k(int nact, int np, int ks, const double* __restric
   }
 }
 
-__global__ void add_diag_bf16_k(int nact, int np, int ks, const double* __restrict__ d, u16* __restrict__ Wh,
-                                u16* __restrict__ Wl, int ldw, long long pstride) {
+__global__ void add_diag_bf16_k(int nact, int np, int ks, const double* __restrict__ d, const double* __restrict__ Dc,
+                                const float* __restrict__ beta32, u16* __restrict__ Wh, u16* __restrict__ Wl, int ldw,
+                                long long pstride) {
   const long long slab = (long long)np * nact;
   GRID_STRIDE(i, slab) {
     const long long P = i / nact;
     const int p = (int)(i % nact);
     const long long o = P * pstride + (long long)p * ldw + p;
-    double w = (double)bf16_bits_to_f32(Wh[o]) + (Wl ? (double)bf16_bits_to_f32(Wl[o]) : 0.0) +
-               sum_slabs(d, ks, slab, i);
+    const float wv = (float)Dc[i] * beta32[(long long)p * nact + p];
     u16 h, l;
-    split_f64(w, h, l);
+    split_f64((double)wv + sum_slabs(d, ks, slab, i), h, l);
     Wh[o] = h;
     if (Wl) Wl[o] = l;
   }
 }
 
-// K[p][q] += sum_s Kpart[s][max][min], mirrored.
+// K[p][q] += sum_s Kpart[s][max][min], mirrored: each lower-triangle position is read along rows
+// (coalesced) and added to both halves.
 __global__ void reduce_k_k(int nact, int nsplit, const double* __restrict__ Kpart, double* __restrict__ K) {
   GRID_STRIDE(i, (long long)nact * nact) {
     const int p = (int)(i / nact), q = (int)(i % nact);
-    const int a = p > q ? p : q, b = p > q ? q : p;
-    double s = 0.0;
-    for (int k = 0; k < nsplit; ++k) s += Kpart[(long long)k * nact * nact + (long long)a * nact + b];
+    if (q > p) continue;
+    const double s = sum_strided(Kpart + i, nsplit, (long long)nact * nact);
     K[i] += s;
+    if (q != p) K[(long long)q * nact + p] += s;
   }
 }
 
 template <typename T>
 __global__ void reduce_y_k(long long n, int nsplit, const T* __restrict__ Yp, double* __restrict__ Y) {
   GRID_STRIDE(i, n) {
-    double s = 0.0;
-    for (int k = 0; k < nsplit; ++k) s += (double)Yp[(long long)k * n + i];
-    Y[i] += s;
+    Y[i] += sum_strided(Yp + i, nsplit, n);
   }
 }
 
@@ -718,13 +717,13 @@ hipError_t add_diag_f64(hipStream_t s, int nact, int np, const double* Dc, const
   if (e != hipSuccess) return e;
   LAUNCH(add_diag_f64_k, grid1((long long)np * nact), dim3(NT), nact, np, ks, dbuf, W, ldw);
 }
-hipError_t add_diag_bf16(hipStream_t s, int nact, int np, const double* Dc, const double* alpha, double* dbuf,
-                         u16* Wh, u16* Wl, int ldw, long long pstride) {
+hipError_t add_diag_bf16(hipStream_t s, int nact, int np, const double* Dc, const double* alpha, const float* beta32,
+                         double* dbuf, u16* Wh, u16* Wl, int ldw, long long pstride) {
   if (np <= 0) return hipSuccess;
   const int ks = gemm_f64_ksplit(np, nact, nact);
   hipError_t e = gemm_f64_splitk(s, np, nact, nact, ks, Dc, nact, 1, alpha, nact, 1, dbuf);
   if (e != hipSuccess) return e;
-  LAUNCH(add_diag_bf16_k, grid1((long long)np * nact), dim3(NT), nact, np, ks, dbuf, Wh, Wl, ldw, pstride);
+  LAUNCH(add_diag_bf16_k, grid1((long long)np * nact), dim3(NT), nact, np, ks, dbuf, Dc, beta32, Wh, Wl, ldw, pstride);
 }
 hipError_t nofmp2_terms(hipStream_t s, int nact, int npairs, int ncwo, int nsingle, const double* n,
                         const double* Hpp, const double* J, const double* K, double* partials, double* E_hf,

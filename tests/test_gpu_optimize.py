@@ -113,20 +113,35 @@ def test_orbital_loop_matches_oracle_loop(ctx, ndiis, zeta):
 
 
 def test_orbital_loop_mixed_precision(ctx):
-    """The loop on the bf16-split contractions follows the float64 loop: after the same number of
-    iterations the energies agree within the mixed-precision energy bar, and the energy has gone
-    down from the guess by far more than that."""
+    """The loop on the bf16-split contractions follows the float64 loop.
+
+    Two separate claims.  (1) Accuracy of the contractions: at the orbitals and occupations where
+    the mixed loop stops, the mixed-precision energy agrees with the float64 energy within the
+    1e-6 Ha bar.  (2) Drift of the loop: each iteration steps along a gradient that carries the
+    mixed precision's error (about 1e-7 relative in dE/dC), and the orbital step (diagonalisation,
+    DIIS extrapolation) turns that into energy differences of about 1e-6 Ha per iteration, with
+    alternating sign (measured: at most 1.8e-6 in the first six iterations).  The energies after
+    six iterations therefore agree within 1e-5 Ha, and both lie far below the guess."""
     s = synth.make(synth.Workload("opt_mixed", 64, 256, 4, 3, "bf16"), 4)
     C0 = np.linalg.eigh(s.H)[1]
     B = t(s.B).to(torch.bfloat16)
     kw = dict(gamma=t(s.gamma), maxit=6, ndiis=4, delta=0.0)
-    r64 = ctx.optimize(P.problem(64, 256, 4, 3, P.PNOF7, P.FP64, P.INTS_DF_BF16), t(s.H), B, t(C0), **kw)
-    rmx = ctx.optimize(P.problem(64, 256, 4, 3, P.PNOF7, P.BF16_SPLIT, P.INTS_DF_BF16), t(s.H), B, t(C0), **kw)
+    p64 = P.problem(64, 256, 4, 3, P.PNOF7, P.FP64, P.INTS_DF_BF16)
+    pmx = P.problem(64, 256, 4, 3, P.PNOF7, P.BF16_SPLIT, P.INTS_DF_BF16)
+    r64 = ctx.optimize(p64, t(s.H), B, t(C0), **kw)
+    rmx = ctx.optimize(pmx, t(s.H), B, t(C0), **kw)
     print(f"mixed loop: E64 {r64['E']:.10f} Emx {rmx['E']:.10f}", flush=True)
     assert r64["iterations"] == rmx["iterations"] == 6
-    assert abs(rmx["E"] - r64["E"]) < 1e-6
+    # (1) both precisions at the mixed loop's final point
+    e64 = ctx.energy(p64, rmx["C"], rmx["n"], t(s.H), B).item()
+    emx = ctx.energy(pmx, rmx["C"], rmx["n"], t(s.H), B).item()
+    print(f"same orbitals: E64 {e64:.10f} Emx {emx:.10f}", flush=True)
+    assert abs(emx - e64) < 1e-6
+    assert abs(emx - rmx["E"]) < 1e-6
+    # (2) drift of the two loops
+    assert abs(rmx["E"] - r64["E"]) < 1e-5
     e0 = oopt.optimize(C0, s.gamma, s.H, s.B, 4, 3, maxit=0, delta=0.0)["history"][0]
-    assert r64["E"] < e0 - 1e-2
+    assert r64["E"] < e0 - 1e-2 and rmx["E"] < e0 - 1e-2
 
 
 def test_optimize_error_paths(ctx):
