@@ -182,9 +182,11 @@ pnof_status pnof_lagrangian(pnof_ctx ctx, const pnof_problem* prob, const double
  * signed so that its largest-magnitude entry (lowest index on ties) is positive;
  * C_new = C U.  lambda, C, C_new: nbf x nbf; eps: nbf; S_out (optional): the matrix diagonalised.
  * C_new must not alias C or lambda.  The Householder reduction to tridiagonal form runs on the
- * library's kernels (one launch per column); rocSOLVER solves the tridiagonal problem (dstedc) and
- * applies the reflectors (dormtr); nbf < 3 or nbf > 2048 use rocSOLVER's dsyevd.  Scratch: about
- * 3 nbf^2 doubles from the context's workspace (grown by the context if the lent one is smaller).
+ * library's kernels (one launch per column); rocSOLVER solves the tridiagonal problem (dstedc)
+ * while a second stream of the context (default priority, forked and joined with events) forms
+ * the product of the reflectors on the library's kernels; the eigenvectors are then that product
+ * times dstedc's.  nbf < 3 or nbf > 2048 use rocSOLVER's dsyevd.  Scratch: about 4 nbf^2 doubles
+ * from the context's workspace (grown by the context if the lent one is smaller).
  * PNOF_E_EIG if the tridiagonal solver does not converge. */
 pnof_status pnof_orbital_step(pnof_ctx ctx, int32_t nbf, const double* lambda, const double* C,
                               const double* diag_prev, double zeta, double* C_new, double* eps,

@@ -26,6 +26,10 @@ struct pnof_ctx_s {
   size_t own_bytes = 0;
   pnof_tuning tune{0, 0, 0, 0, 0};
   int* host_info = nullptr;  // pinned
+  // second stream (default priority) for work that overlaps the main stream's, forked and joined
+  // with events; created on first use
+  hipStream_t aux = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   // measurement: launches of the contraction kernels bracketed by events on the stream
   bool profiling = false;
   struct Ev { int stage; hipEvent_t a, b; };
@@ -829,6 +833,12 @@ void pnof_destroy(pnof_ctx ctx) {
     hipEventDestroy(e.b);
   }
   for (auto e : ctx->pool) hipEventDestroy(e);
+  if (ctx->aux) {
+    hipStreamSynchronize(ctx->aux);
+    hipStreamDestroy(ctx->aux);
+  }
+  if (ctx->fork_ev) hipEventDestroy(ctx->fork_ev);
+  if (ctx->join_ev) hipEventDestroy(ctx->join_ev);
   if (ctx->own_ws) hipFree(ctx->own_ws);
   if (ctx->host_info) hipHostFree(ctx->host_info);
   if (ctx->blas) rocblas_destroy_handle(ctx->blas);
@@ -1020,14 +1030,19 @@ pnof_status pnof_lagrangian(pnof_ctx ctx, const pnof_problem* prob, const double
 namespace {
 // Symmetric float64 eigensolver: A (n x n, symmetric, row-major; destroyed) -> ascending eigenvalues
 // w and eigenvectors U (column-major).  The Householder reduction runs on the library's kernels
-// (k_eig.hip); rocSOLVER solves the tridiagonal problem (stedc) and applies the reflectors (ormtr).
+// (k_eig.hip), A = Q T Q^T.  rocSOLVER solves the tridiagonal problem (stedc, eigenvectors Z into
+// A's storage) while the context's second stream forms Q = H_0 ... H_{n-2} explicitly (reflectors
+// applied to the identity in blocks, k_eig.hip form_q_f64); then U = Q Z.  The tridiagonal solver's many small
+// launches leave most of the chip idle, so forming Q there costs no time on the main stream.
 // Sizes outside [3, TRIDIAG_MAX_N] take rocSOLVER's dsyevd.  info (device) receives the solver's
 // status (0 = converged).
 struct EighWs {
-  double* Vh;    // n * n
-  double* p2;    // 2n
-  double* e;     // n
-  double* tau;   // n
+  double* Vh = nullptr;    // n * n
+  double* p2 = nullptr;    // 2n
+  double* e = nullptr;     // n
+  double* tau = nullptr;   // n
+  double* T = nullptr;     // ormtr_tblocks(n) * ORMTR_NB^2
+  double* Q = nullptr;     // n * n
 };
 EighWs take_eigh_ws(Arena& a, int n) {
   EighWs w;
@@ -1035,6 +1050,8 @@ EighWs take_eigh_ws(Arena& a, int n) {
   w.p2 = a.take<double>(2LL * n);
   w.e = a.take<double>(n);
   w.tau = a.take<double>(n);
+  w.T = a.take<double>((long long)ormtr_tblocks(std::max(n, 1)) * ORMTR_NB * ORMTR_NB);
+  w.Q = a.take<double>((long long)n * n);
   return w;
 }
 pnof_status eigh(pnof_ctx ctx, int n, double* A, double* w, double* U, const EighWs& ws, int* info) {
@@ -1045,12 +1062,24 @@ pnof_status eigh(pnof_ctx ctx, int n, double* A, double* w, double* U, const Eig
     DEV_CHECK(ctx, hipMemcpyAsync(U, A, sizeof(double) * n * n, hipMemcpyDeviceToDevice, s));
     return PNOF_OK;
   }
+  if (!ws.Vh || !ws.p2 || !ws.e || !ws.tau || !ws.T || !ws.Q)
+    return fail(ctx, PNOF_E_ARG, "eigensolver workspace missing");
+  if (!ctx->aux) {
+    DEV_CHECK(ctx, hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+    DEV_CHECK(ctx, hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming));
+    DEV_CHECK(ctx, hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming));
+  }
   DEV_CHECK(ctx, tridiag_f64(s, n, A, ws.Vh, ws.p2, w, ws.e, ws.tau));
-  rocblas_status rs = rocsolver_dstedc(ctx->blas, rocblas_evect_tridiagonal, n, w, ws.e, U, n, info);
+  DEV_CHECK(ctx, hipEventRecord(ctx->fork_ev, s));
+  DEV_CHECK(ctx, hipStreamWaitEvent(ctx->aux, ctx->fork_ev, 0));
+  DEV_CHECK(ctx, form_q_f64(ctx->aux, n, ws.Vh, ws.tau, ws.T, ws.Q));
+  DEV_CHECK(ctx, hipEventRecord(ctx->join_ev, ctx->aux));
+  double* Z = A;   // free after the reduction
+  rocblas_status rs = rocsolver_dstedc(ctx->blas, rocblas_evect_tridiagonal, n, w, ws.e, Z, n, info);
   if (rs != rocblas_status_success) return fail(ctx, PNOF_E_DEVICE, "rocsolver_dstedc failed to launch");
-  rs = rocsolver_dormtr(ctx->blas, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none, n, n, ws.Vh, n,
-                        ws.tau, U, n);
-  if (rs != rocblas_status_success) return fail(ctx, PNOF_E_DEVICE, "rocsolver_dormtr failed to launch");
+  DEV_CHECK(ctx, hipStreamWaitEvent(s, ctx->join_ev, 0));
+  // U = Q Z, all column-major
+  DEV_CHECK(ctx, gemm_f64(s, n, n, n, 1, 1.0, ws.Q, 1, n, 0, Z, 1, n, 0, 0.0, U, 1, n, 0));
   return PNOF_OK;
 }
 }  // namespace
@@ -1175,6 +1204,8 @@ pnof_status pnof_optimize(pnof_ctx ctx, const pnof_problem* prob, const double* 
   ew.p2 = db.get<double>(2LL * nbf);
   ew.e = db.get<double>(nbf);
   ew.tau = db.get<double>(nbf);
+  ew.T = db.get<double>((long long)ormtr_tblocks(nbf) * ORMTR_NB * ORMTR_NB);
+  ew.Q = db.get<double>(nn);
   int* info = db.get<int>(4);
   double* J = db.get<double>(n2);
   double* K = db.get<double>(n2);

@@ -179,7 +179,197 @@ __global__ __launch_bounds__(TNT) void trd_step_k(int n, int k, double* __restri
   if (lane == 0) pcur[irow] = tk * acc;
 }
 
+// ---------------------------------------------------------------- back-transformation
+// U = Q Z for the eigenvectors Z of the tridiagonal matrix (column-major n x n), Q = H_0 ... H_{n-2}.
+// The reflectors are taken in blocks of ONB: Q_b = H_{k0} ... H_{k0+nb-1} = I - V T V^T with V the
+// block's vectors as columns and T upper triangular (the compact WY form of a product of
+// reflectors, Schreiber and Van Loan 1989).  Columns of Z are independent, so each workgroup owns
+// OCW of them in LDS and applies Q_last, ..., Q_0 in turn; no step waits on another workgroup.
+constexpr int ONB = ORMTR_NB;                 // reflectors per block
+constexpr int OCW = 8;                        // eigenvector columns per workgroup
+constexpr int ORPT = TRIDIAG_MAX_N / TNT;     // rows per thread in the update
+
+// T of every block (one workgroup each): G[i][j] = v_i . v_j (i < j), then T[j][j] = tau_j and
+// T[0:j][j] = -tau_j T[0:j][0:j] G[0:j][j], stored full ONB x ONB with zeros outside the block.
+__global__ __launch_bounds__(TNT) void larft_k(int n, int nref, const double* __restrict__ Vh,
+                                               const double* __restrict__ tau, double* __restrict__ Tall) {
+  __shared__ double Vs[64][ONB + 1];
+  __shared__ double G[ONB][ONB + 1];
+  __shared__ double T[ONB][ONB + 1];
+  const int t = threadIdx.x, k0 = blockIdx.x * ONB, nb = min(ONB, nref - k0);
+  constexpr int NQ = ONB * ONB / TNT;
+  double g[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) g[q] = 0.0;
+  for (int r0 = k0 + 1; r0 < n; r0 += 64) {
+    __syncthreads();
+    for (int e = t; e < 64 * ONB; e += TNT) {
+      const int j = e / 64, rr = e % 64, r = r0 + rr, k = k0 + j;
+      Vs[rr][j] = (j < nb && r < n && r > k) ? (r == k + 1 ? 1.0 : Vh[(long long)k * n + r]) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int e = t + TNT * q, i = e / ONB, j = e % ONB;
+      if (i < j) {
+        double a = g[q];
+        for (int rr = 0; rr < 64; ++rr) a += Vs[rr][i] * Vs[rr][j];
+        g[q] = a;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int e = t + TNT * q;
+    G[e / ONB][e % ONB] = g[q];
+    T[e / ONB][e % ONB] = 0.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < nb; ++j) {
+    const double tj = tau[k0 + j];
+    if (t < j) {
+      double a = 0.0;
+      for (int l = t; l < j; ++l) a += T[t][l] * G[l][j];
+      T[t][j] = -tj * a;
+    } else if (t == j) {
+      T[j][j] = tj;
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < ONB * ONB; e += TNT) Tall[(long long)blockIdx.x * ONB * ONB + e] = T[e / ONB][e % ONB];
+}
+
+// Z <- Q Z on OCW columns per workgroup: for each block b, last to first, W1 = V^T Z (threads
+// (j, g) sum rows r = g mod 8, then the 8 partials are added in order), W2 = T W1, Z -= V W2.
+// ident: Z is the identity (Q itself is formed).  Column c of the identity is then left alone by
+// every reflector k >= c (its vector is zero on rows <= k), so a panel starts at the first block
+// that reaches its columns.  Loads of V are issued in batches (16 per thread in W1, 32 in the
+// update) so that their latency is paid once per batch.
+__global__ __launch_bounds__(TNT) void ormtr_k(int n, int nref, const double* __restrict__ Vh,
+                                               const double* __restrict__ Tall, double* __restrict__ Z, int ident) {
+  __shared__ double Zs[TRIDIAG_MAX_N * OCW];
+  __shared__ double Wp[8][ONB][OCW];
+  __shared__ double W1[ONB][OCW];
+  __shared__ double W2[ONB][OCW];
+  __shared__ double Ts[ONB][ONB];
+  const int t = threadIdx.x, c0 = blockIdx.x * OCW;
+  for (int e = t; e < n * OCW; e += TNT) {
+    const int c = e / n, r = e % n;
+    Zs[r * OCW + c] = c0 + c >= n ? 0.0 : ident ? (r == c0 + c ? 1.0 : 0.0) : Z[(long long)(c0 + c) * n + r];
+  }
+  const int nblk = (nref + ONB - 1) / ONB;
+  const int bstart = ident ? min(nblk - 1, max(0, c0 + OCW - 2) / ONB) : nblk - 1;
+  constexpr int U1 = 16, JG = 4;
+  for (int b = bstart; b >= 0; --b) {
+    const int k0 = b * ONB, nb = min(ONB, nref - k0);
+    for (int e = t; e < ONB * ONB; e += TNT) Ts[e / ONB][e % ONB] = Tall[(long long)b * ONB * ONB + e];
+    __syncthreads();   // Zs (panel load or previous block's update) and Ts visible
+    {
+      const int j = t >> 3, g = t & 7, k = k0 + j;
+      double acc[OCW];
+#pragma unroll
+      for (int c = 0; c < OCW; ++c) acc[c] = 0.0;
+      if (j < nb) {
+        const double* __restrict__ v = Vh + (long long)k * n;
+        for (int r0 = k + 1 + g; r0 < n; r0 += 8 * U1) {
+          double vv[U1];
+#pragma unroll
+          for (int u = 0; u < U1; ++u) {
+            const int r = r0 + 8 * u;
+            vv[u] = r < n ? (r == k + 1 ? 1.0 : v[r]) : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < U1; ++u) {
+            const int r = r0 + 8 * u;
+            if (r < n) {
+#pragma unroll
+              for (int c = 0; c < OCW; ++c) acc[c] += vv[u] * Zs[r * OCW + c];
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < OCW; ++c) Wp[g][j][c] = acc[c];
+    }
+    __syncthreads();
+    {
+      const int j = t >> 3, c = t & 7;
+      double a = 0.0;
+#pragma unroll
+      for (int g = 0; g < 8; ++g) a += Wp[g][j][c];
+      W1[j][c] = a;
+    }
+    __syncthreads();
+    {
+      const int i = t >> 3, c = t & 7;
+      double a = 0.0;
+      for (int l = i; l < nb; ++l) a += Ts[i][l] * W1[l][c];
+      W2[i][c] = a;   // zero for i >= nb
+    }
+    __syncthreads();
+    double z[ORPT][OCW];
+#pragma unroll
+    for (int q = 0; q < ORPT; ++q) {
+      const int r = k0 + 1 + t + TNT * q;
+#pragma unroll
+      for (int c = 0; c < OCW; ++c) z[q][c] = r < n ? Zs[r * OCW + c] : 0.0;
+    }
+    for (int j0 = 0; j0 < nb; j0 += JG) {
+      double vv[JG][ORPT];
+#pragma unroll
+      for (int jj = 0; jj < JG; ++jj) {
+        const int k = k0 + j0 + jj;
+#pragma unroll
+        for (int q = 0; q < ORPT; ++q) {
+          const int r = k0 + 1 + t + TNT * q;
+          vv[jj][q] = (j0 + jj < nb && r > k && r < n) ? (r == k + 1 ? 1.0 : Vh[(long long)k * n + r]) : 0.0;
+        }
+      }
+#pragma unroll
+      for (int jj = 0; jj < JG; ++jj) {
+        double w[OCW];
+#pragma unroll
+        for (int c = 0; c < OCW; ++c) w[c] = W2[min(j0 + jj, ONB - 1)][c];
+#pragma unroll
+        for (int q = 0; q < ORPT; ++q)
+#pragma unroll
+          for (int c = 0; c < OCW; ++c) z[q][c] -= vv[jj][q] * w[c];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < ORPT; ++q) {
+      const int r = k0 + 1 + t + TNT * q;
+      if (r < n) {
+#pragma unroll
+        for (int c = 0; c < OCW; ++c) Zs[r * OCW + c] = z[q][c];
+      }
+    }
+    __syncthreads();   // Wp, W1, W2 and Ts are rewritten by the next block
+  }
+  __syncthreads();
+  for (int e = t; e < n * OCW; e += TNT) {
+    const int c = e / n, r = e % n;
+    if (c0 + c < n) Z[(long long)(c0 + c) * n + r] = Zs[r * OCW + c];
+  }
+}
+
 }  // namespace
+
+hipError_t ormtr_f64(hipStream_t s, int n, const double* Vh, const double* tau, double* Tall, double* Z) {
+  if (n < 3 || n > TRIDIAG_MAX_N) return hipErrorInvalidValue;
+  const int nref = n - 1, nblk = cdiv(nref, ONB);
+  hipLaunchKernelGGL(larft_k, dim3(nblk), dim3(TNT), 0, s, n, nref, Vh, tau, Tall);
+  hipLaunchKernelGGL(ormtr_k, dim3(cdiv(n, OCW)), dim3(TNT), 0, s, n, nref, Vh, Tall, Z, 0);
+  return hipGetLastError();
+}
+
+hipError_t form_q_f64(hipStream_t s, int n, const double* Vh, const double* tau, double* Tall, double* Q) {
+  if (n < 3 || n > TRIDIAG_MAX_N) return hipErrorInvalidValue;
+  const int nref = n - 1, nblk = cdiv(nref, ONB);
+  hipLaunchKernelGGL(larft_k, dim3(nblk), dim3(TNT), 0, s, n, nref, Vh, tau, Tall);
+  hipLaunchKernelGGL(ormtr_k, dim3(cdiv(n, OCW)), dim3(TNT), 0, s, n, nref, Vh, Tall, Q, 1);
+  return hipGetLastError();
+}
 
 hipError_t tridiag_f64(hipStream_t s, int n, double* A, double* Vh, double* p2, double* d, double* e, double* tau) {
   if (n <= 0 || n > TRIDIAG_MAX_N) return hipErrorInvalidValue;
