@@ -179,6 +179,112 @@ __global__ __launch_bounds__(TNT) void trd_step_k(int n, int k, double* __restri
   if (lane == 0) pcur[irow] = tk * acc;
 }
 
+// ---------------------------------------------------------------- the last columns
+// Once n - k <= TAILM the trailing block fits in one workgroup's LDS: a single launch of TAILNT
+// threads finishes the reduction there (same Householder convention, the rank-2 update applied
+// eagerly), with block barriers in place of one launch per column.
+constexpr int TAILM = 128;
+constexpr int TAILNT = 1024;
+
+__device__ double tail_sum(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < TAILNT / 64; ++i) s += red[i];
+  return s;
+}
+
+__global__ __launch_bounds__(TAILNT) void trd_tail_k(int n, int k0, const double* __restrict__ A,
+                                                     double* __restrict__ Vh, const double* __restrict__ pprev,
+                                                     double* __restrict__ d, double* __restrict__ e,
+                                                     double* __restrict__ tau) {
+  constexpr int LD = TAILM + 1;
+  __shared__ double As[TAILM * LD];
+  __shared__ double vs[TAILM], ps[TAILM], ws[TAILM];
+  static_assert(TAILNT / 8 >= TAILM, "one group of 8 lanes per row");
+  __shared__ double red[TAILNT / 64];
+  const int t = threadIdx.x, m0 = n - k0;
+  for (int q = t; q < m0 * m0; q += TAILNT) {
+    const int i = q / m0, j = q % m0;
+    As[i * LD + j] = A[(long long)(k0 + i) * n + k0 + j];
+  }
+  if (k0 > 0) {
+    // the update pending from column k0 - 1: w = p - (tau/2)(p.v) v, A -= v w^T + w v^T
+    for (int i = t; i < m0; i += TAILNT) {
+      vs[i] = Vh[(long long)(k0 - 1) * n + k0 + i];
+      ps[i] = pprev[k0 + i];
+    }
+    __syncthreads();
+    double s = 0.0;
+    for (int i = t; i < m0; i += TAILNT) s += vs[i] * ps[i];
+    s = tail_sum(s, red);
+    const double half = 0.5 * tau[k0 - 1] * s;
+    for (int i = t; i < m0; i += TAILNT) ws[i] = ps[i] - half * vs[i];
+    __syncthreads();
+    for (int q = t; q < m0 * m0; q += TAILNT) {
+      const int i = q / m0, j = q % m0;
+      As[i * LD + j] = As[i * LD + j] - vs[i] * ws[j] - ws[i] * vs[j];
+    }
+  }
+  __syncthreads();
+  // rows of the trailing block go to groups of 8 lanes (TAILNT / 8 = TAILM groups): row i = 1 + grp,
+  // columns 1 + sub + 8u
+  const int grp = t >> 3, sub = t & 7;
+  for (int k = k0; k < n; ++k) {
+    const int l = k - k0, m = n - k;
+    const double* __restrict__ col = As + l * LD + l;   // row l from the diagonal on (= column l)
+    // every wavefront forms |c_{2..}|^2 itself from LDS (no barrier)
+    double sig = 0.0;
+    for (int i = 2 + (t & 63); i < m; i += 64) sig += col[i] * col[i];
+    for (int o = 32; o > 0; o >>= 1) sig += __shfl_xor(sig, o, 64);
+    const double dk = col[0], alpha = m >= 2 ? col[1] : 0.0;
+    double tk = 0.0, beta = alpha, scal = 0.0;
+    if (m >= 2 && sig != 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + sig), alpha);
+      tk = (beta - alpha) / beta;
+      scal = 1.0 / (alpha - beta);
+    }
+    for (int i = t; i < m; i += TAILNT) vs[i] = i == 0 ? 0.0 : (i == 1 ? 1.0 : col[i] * scal);
+    if (t == 0) {
+      d[k] = dk;
+      if (m >= 2) {
+        e[k] = beta;
+        tau[k] = tk;
+      }
+    }
+    __syncthreads();
+    for (int i = t; i < m; i += TAILNT) Vh[(long long)k * n + k + i] = vs[i];
+    // p_i = tau (A v)_i for the rows i >= 1 below k: 8 lanes per row, 3 shuffle levels
+    const int i = 1 + grp;
+    const bool has_row = i < m;
+    const double* __restrict__ row = As + (l + (has_row ? i : 0)) * LD + l;
+    double a = 0.0;
+    if (has_row)
+      for (int j = 1 + sub; j < m; j += 8) a += row[j] * vs[j];
+    a += __shfl_xor(a, 1, 64);
+    a += __shfl_xor(a, 2, 64);
+    a += __shfl_xor(a, 4, 64);
+    const double pi = tk * a, vi = has_row ? vs[i] : 0.0;
+    if (sub == 0) ps[i - 1] = has_row ? pi * vi : 0.0;
+    __syncthreads();
+    // p . v, formed by every wavefront from the staged products (same order in each)
+    double s2 = 0.0;
+    for (int r = t & 63; r < TAILM; r += 64) s2 += ps[r];
+    for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o, 64);
+    const double half = 0.5 * tk * s2, wi = pi - half * vi;
+    if (has_row && sub == 0) ws[i] = wi;
+    __syncthreads();
+    if (has_row) {
+      double* __restrict__ ar = As + (l + i) * LD + l;
+      for (int j = 1 + sub; j < m; j += 8) ar[j] = ar[j] - vi * ws[j] - wi * vs[j];
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------- back-transformation
 // U = Q Z for the eigenvectors Z of the tridiagonal matrix (column-major n x n), Q = H_0 ... H_{n-2}.
 // The reflectors are taken in blocks of ONB: Q_b = H_{k0} ... H_{k0+nb-1} = I - V T V^T with V the
@@ -374,11 +480,14 @@ hipError_t form_q_f64(hipStream_t s, int n, const double* Vh, const double* tau,
 hipError_t tridiag_f64(hipStream_t s, int n, double* A, double* Vh, double* p2, double* d, double* e, double* tau) {
   if (n <= 0 || n > TRIDIAG_MAX_N) return hipErrorInvalidValue;
   const size_t shm = 3 * (size_t)n * sizeof(double);
-  for (int k = 0; k < n; ++k) {
+  const int k0 = std::max(0, n - TAILM);   // columns k0 .. n-1: one workgroup, trailing block in LDS
+  for (int k = 0; k < k0; ++k) {
     const int blocks = std::max(1, cdiv(n - k - 1, TROWS));
     hipLaunchKernelGGL(trd_step_k, dim3(blocks), dim3(TNT), shm, s, n, k, A, Vh, p2 + ((k + 1) & 1) * (long long)n,
                        p2 + (k & 1) * (long long)n, d, e, tau);
   }
+  hipLaunchKernelGGL(trd_tail_k, dim3(1), dim3(TAILNT), 0, s, n, k0, A, Vh,
+                     p2 + ((k0 + 1) & 1) * (long long)n, d, e, tau);
   return hipGetLastError();
 }
 
