@@ -28,15 +28,15 @@ KSRC = os.path.join(ROOT, "paper_2004_06142_amd", "csrc")
 # once the source changes the figure no longer applies and traffic is reported as null.
 TRAFFIC = {
     # profiles/c5_df1200_hbm_traffic.md: C5, bf16 split, 164-row chunks (read + written bytes per launch)
-    ("gemm1_kernel", 3): {"bytes": 1593675954 + 925182301,
+    ("gemm1_kernel", 3): {"bytes": 1573919638 + 925192741,
                           "plan": {"pchunk": 164, "x_variant": 3},
-                          "sha256": {"k_gemm_bf16.hip": "93e384042bfef719761bc804c10593f04cb61e0cdc64d44db46345e525e50c8a"}},
-    ("gemm2_kernel", 3): {"bytes": 3506566865 + 1139885083,
+                          "sha256": {"k_gemm_bf16.hip": "5aac520fb45d7991fd5bfbcff7868df8d56b0626576d23d037cdd4c7e0106188"}},
+    ("gemm2_kernel", 3): {"bytes": 3502265100 + 1132423991,
                           "plan": {"pchunk": 164, "nsplit_b": 18},
-                          "sha256": {"k_gemm_bf16.hip": "93e384042bfef719761bc804c10593f04cb61e0cdc64d44db46345e525e50c8a"}},
-    ("gemm3_kernel", 3): {"bytes": 2751681556 + 241431699,
+                          "sha256": {"k_gemm_bf16.hip": "5aac520fb45d7991fd5bfbcff7868df8d56b0626576d23d037cdd4c7e0106188"}},
+    ("gemm3_kernel", 3): {"bytes": 2749738221 + 241434063,
                           "plan": {"pchunk": 164, "nsplit_y": 10, "y_variant": 3},
-                          "sha256": {"k_gemm_bf16.hip": "93e384042bfef719761bc804c10593f04cb61e0cdc64d44db46345e525e50c8a"}},
+                          "sha256": {"k_gemm_bf16.hip": "5aac520fb45d7991fd5bfbcff7868df8d56b0626576d23d037cdd4c7e0106188"}},
 }
 GOLDEN_C5 = os.path.join(ROOT, "tests", "golden", "c5_df1200_expected.json")
 
