@@ -336,13 +336,10 @@ hipError_t sign_fix_cols(hipStream_t s, int nbf, double* Ucm);
 // read column-major: the lower-storage layout of ormtr); p2: 2n doubles of scratch.
 constexpr int TRIDIAG_MAX_N = 2048;   // three float64 vectors of n in LDS
 hipError_t tridiag_f64(hipStream_t s, int n, double* A, double* Vh, double* p2, double* d, double* e, double* tau);
-// U = Q Z with Q = H_0 ... H_{n-2} the reflectors of tridiag_f64 (Vh, tau) and Z column-major n x n
-// (overwritten), reflectors applied in blocks of ORMTR_NB.  Tall: workspace of ormtr_tblocks(n)
-// * ORMTR_NB^2 doubles.  3 <= n <= TRIDIAG_MAX_N.
+// Q = H_0 ... H_{n-2} (column-major n x n) from the reflectors of tridiag_f64 (Vh, tau), applied in
+// blocks of ORMTR_NB.  Tall: workspace of ormtr_tblocks(n) * ORMTR_NB^2 doubles.  3 <= n <= TRIDIAG_MAX_N.
 constexpr int ORMTR_NB = 32;
 inline int ormtr_tblocks(int n) { return (n - 1 + ORMTR_NB - 1) / ORMTR_NB; }
-hipError_t ormtr_f64(hipStream_t s, int n, const double* Vh, const double* tau, double* Tall, double* Z);
-// Q = H_0 ... H_{n-2} itself (column-major n x n), same workspace.
 hipError_t form_q_f64(hipStream_t s, int n, const double* Vh, const double* tau, double* Tall, double* Q);
 hipError_t offdiag_copy(hipStream_t s, int nbf, const double* src, double* dst);
 // E_hf and E_sta (device scalars) from n, H_pp, J, K; partials: 256 doubles of scratch.

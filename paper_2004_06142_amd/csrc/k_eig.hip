@@ -286,11 +286,12 @@ __global__ __launch_bounds__(TAILNT) void trd_tail_k(int n, int k0, const double
 }
 
 // ---------------------------------------------------------------- back-transformation
-// U = Q Z for the eigenvectors Z of the tridiagonal matrix (column-major n x n), Q = H_0 ... H_{n-2}.
-// The reflectors are taken in blocks of ONB: Q_b = H_{k0} ... H_{k0+nb-1} = I - V T V^T with V the
-// block's vectors as columns and T upper triangular (the compact WY form of a product of
-// reflectors, Schreiber and Van Loan 1989).  Columns of Z are independent, so each workgroup owns
-// OCW of them in LDS and applies Q_last, ..., Q_0 in turn; no step waits on another workgroup.
+// Q = H_0 ... H_{n-2} formed explicitly (column-major n x n); the eigenvectors are then Q times
+// those of the tridiagonal matrix.  The reflectors are taken in blocks of ONB:
+// Q_b = H_{k0} ... H_{k0+nb-1} = I - V T V^T with V the block's vectors as columns and T upper
+// triangular (the compact WY form of a product of reflectors, Schreiber and Van Loan 1989).
+// Columns are independent, so each workgroup owns OCW of them in LDS and applies Q_last, ..., Q_0
+// to the identity in turn; no step waits on another workgroup.
 constexpr int ONB = ORMTR_NB;                 // reflectors per block
 constexpr int OCW = 8;                        // eigenvector columns per workgroup
 constexpr int ORPT = TRIDIAG_MAX_N / TNT;     // rows per thread in the update
@@ -345,14 +346,14 @@ __global__ __launch_bounds__(TNT) void larft_k(int n, int nref, const double* __
   for (int e = t; e < ONB * ONB; e += TNT) Tall[(long long)blockIdx.x * ONB * ONB + e] = T[e / ONB][e % ONB];
 }
 
-// Z <- Q Z on OCW columns per workgroup: for each block b, last to first, W1 = V^T Z (threads
-// (j, g) sum rows r = g mod 8, then the 8 partials are added in order), W2 = T W1, Z -= V W2.
-// ident: Z is the identity (Q itself is formed).  Column c of the identity is then left alone by
-// every reflector k >= c (its vector is zero on rows <= k), so a panel starts at the first block
-// that reaches its columns.  Loads of V are issued in batches (16 per thread in W1, 32 in the
-// update) so that their latency is paid once per batch.
+// Q = Q I on OCW columns per workgroup (Z starts as the identity panel): for each block b, last to
+// first, W1 = V^T Z (threads (j, g) sum rows r = g mod 8, then the 8 partials are added in order),
+// W2 = T W1, Z -= V W2.  Column c of the identity is left alone by every reflector k >= c (its
+// vector is zero on rows <= k), so a panel starts at the first block that reaches its columns.
+// Loads of V are issued in batches (16 per thread in W1, 32 in the update) so that their latency
+// is paid once per batch.
 __global__ __launch_bounds__(TNT) void ormtr_k(int n, int nref, const double* __restrict__ Vh,
-                                               const double* __restrict__ Tall, double* __restrict__ Z, int ident) {
+                                               const double* __restrict__ Tall, double* __restrict__ Z) {
   __shared__ double Zs[TRIDIAG_MAX_N * OCW];
   __shared__ double Wp[8][ONB][OCW];
   __shared__ double W1[ONB][OCW];
@@ -361,10 +362,10 @@ __global__ __launch_bounds__(TNT) void ormtr_k(int n, int nref, const double* __
   const int t = threadIdx.x, c0 = blockIdx.x * OCW;
   for (int e = t; e < n * OCW; e += TNT) {
     const int c = e / n, r = e % n;
-    Zs[r * OCW + c] = c0 + c >= n ? 0.0 : ident ? (r == c0 + c ? 1.0 : 0.0) : Z[(long long)(c0 + c) * n + r];
+    Zs[r * OCW + c] = (c0 + c < n && r == c0 + c) ? 1.0 : 0.0;
   }
   const int nblk = (nref + ONB - 1) / ONB;
-  const int bstart = ident ? min(nblk - 1, max(0, c0 + OCW - 2) / ONB) : nblk - 1;
+  const int bstart = min(nblk - 1, max(0, c0 + OCW - 2) / ONB);
   constexpr int U1 = 16, JG = 4;
   for (int b = bstart; b >= 0; --b) {
     const int k0 = b * ONB, nb = min(ONB, nref - k0);
@@ -461,19 +462,11 @@ __global__ __launch_bounds__(TNT) void ormtr_k(int n, int nref, const double* __
 
 }  // namespace
 
-hipError_t ormtr_f64(hipStream_t s, int n, const double* Vh, const double* tau, double* Tall, double* Z) {
-  if (n < 3 || n > TRIDIAG_MAX_N) return hipErrorInvalidValue;
-  const int nref = n - 1, nblk = cdiv(nref, ONB);
-  hipLaunchKernelGGL(larft_k, dim3(nblk), dim3(TNT), 0, s, n, nref, Vh, tau, Tall);
-  hipLaunchKernelGGL(ormtr_k, dim3(cdiv(n, OCW)), dim3(TNT), 0, s, n, nref, Vh, Tall, Z, 0);
-  return hipGetLastError();
-}
-
 hipError_t form_q_f64(hipStream_t s, int n, const double* Vh, const double* tau, double* Tall, double* Q) {
   if (n < 3 || n > TRIDIAG_MAX_N) return hipErrorInvalidValue;
   const int nref = n - 1, nblk = cdiv(nref, ONB);
   hipLaunchKernelGGL(larft_k, dim3(nblk), dim3(TNT), 0, s, n, nref, Vh, tau, Tall);
-  hipLaunchKernelGGL(ormtr_k, dim3(cdiv(n, OCW)), dim3(TNT), 0, s, n, nref, Vh, Tall, Q, 1);
+  hipLaunchKernelGGL(ormtr_k, dim3(cdiv(n, OCW)), dim3(TNT), 0, s, n, nref, Vh, Tall, Q);
   return hipGetLastError();
 }
 

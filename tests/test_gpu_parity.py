@@ -267,8 +267,9 @@ def test_orbital_step_symmetrised(ctx):
 # sizes around the eigensolver's internal limits: n < 3 and n > 2048 take the library solver,
 # 1024 < n and 1537 < n cross the register-held prologue and row chunks of the reduction kernel,
 # 33 and 200 end the back-transformation's blocks of 32 reflectors and panels of 8 columns part
-# way, 2048 fills its LDS panel and every row slot of its update
-@pytest.mark.parametrize("nbf", [1, 2, 3, 5, 33, 64, 200, 1025, 1601, 2048, 2100])
+# way, 2048 fills its LDS panel and every row slot of its update; 128 is reduced by the
+# single-workgroup tail alone, 129 and 130 hand it one and two columns' pending updates
+@pytest.mark.parametrize("nbf", [1, 2, 3, 5, 33, 64, 128, 129, 130, 200, 1025, 1601, 2048, 2100])
 def test_orbital_step_sizes(ctx, nbf):
     rng = np.random.default_rng(nbf)
     lam = rng.standard_normal((nbf, nbf))
