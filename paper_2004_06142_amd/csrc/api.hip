@@ -1064,11 +1064,9 @@ pnof_status eigh(pnof_ctx ctx, int n, double* A, double* w, double* U, const Eig
   }
   if (!ws.Vh || !ws.p2 || !ws.e || !ws.tau || !ws.T || !ws.Q)
     return fail(ctx, PNOF_E_ARG, "eigensolver workspace missing");
-  if (!ctx->aux) {
-    DEV_CHECK(ctx, hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
-    DEV_CHECK(ctx, hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming));
-    DEV_CHECK(ctx, hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming));
-  }
+  if (!ctx->aux) DEV_CHECK(ctx, hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+  if (!ctx->fork_ev) DEV_CHECK(ctx, hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming));
+  if (!ctx->join_ev) DEV_CHECK(ctx, hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming));
   DEV_CHECK(ctx, tridiag_f64(s, n, A, ws.Vh, ws.p2, w, ws.e, ws.tau));
   DEV_CHECK(ctx, hipEventRecord(ctx->fork_ev, s));
   DEV_CHECK(ctx, hipStreamWaitEvent(ctx->aux, ctx->fork_ev, 0));
@@ -1076,8 +1074,8 @@ pnof_status eigh(pnof_ctx ctx, int n, double* A, double* w, double* U, const Eig
   DEV_CHECK(ctx, hipEventRecord(ctx->join_ev, ctx->aux));
   double* Z = A;   // free after the reduction
   rocblas_status rs = rocsolver_dstedc(ctx->blas, rocblas_evect_tridiagonal, n, w, ws.e, Z, n, info);
+  DEV_CHECK(ctx, hipStreamWaitEvent(s, ctx->join_ev, 0));   // joined on every path: Q uses the workspace
   if (rs != rocblas_status_success) return fail(ctx, PNOF_E_DEVICE, "rocsolver_dstedc failed to launch");
-  DEV_CHECK(ctx, hipStreamWaitEvent(s, ctx->join_ev, 0));
   // U = Q Z, all column-major
   DEV_CHECK(ctx, gemm_f64(s, n, n, n, 1, 1.0, ws.Q, 1, n, 0, Z, 1, n, 0, 0.0, U, 1, n, 0));
   return PNOF_OK;
