@@ -22,13 +22,42 @@
 namespace pnof {
 namespace {
 
+// Sums over the lanes of a wavefront with DPP lane moves, which stay in the vector unit (a shuffle
+// goes through the LDS crossbar on every level).  Quad permutes (lane ^ 1, lane ^ 2) and the
+// half-row and row mirrors (lane i <-> 7 - i, 15 - i) leave every lane of a row of 16 with the row's
+// sum; two row broadcasts (lane 15 into rows 1 and 3, lane 31 into rows 2 and 3) then carry the row
+// sums into lane 63, which is read back.  All 64 lanes must be active.
+template <int CTRL, int ROWMASK = 0xf>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+// sum over each group of 8 lanes (lanes 8g .. 8g + 7), in every lane of the group
+__device__ __forceinline__ double group8_sum(double v) {
+  v += dpp_mov<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+  v += dpp_mov<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+  v += dpp_mov<0x141>(v);   // row_half_mirror
+  return v;
+}
+// sum over the 64 lanes, returned in every lane
+__device__ __forceinline__ double wave_sum(double v) {
+  v = group8_sum(v);
+  v += dpp_mov<0x140>(v);        // row_mirror
+  v += dpp_mov<0x142, 0xa>(v);   // row_bcast:15
+  v += dpp_mov<0x143, 0xc>(v);   // row_bcast:31
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
 constexpr int TNT = 256;   // threads per block
 constexpr int TROWS = 4;   // rows of the trailing matrix per block (one per wavefront)
 constexpr int TPQ = 4;     // prologue elements per thread held in registers (loops cover the rest)
 constexpr int TPRE = 24;   // row elements per lane loaded before the prologue (loops cover the rest)
 
 __device__ double tblock_sum(double v, double* red) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  v = wave_sum(v);
   const int w = threadIdx.x >> 6;
   __syncthreads();
   if ((threadIdx.x & 63) == 0) red[w] = v;
@@ -175,7 +204,7 @@ __global__ __launch_bounds__(TNT) void trd_step_k(int n, int k, double* __restri
       }
     }
   }
-  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  acc = wave_sum(acc);
   if (lane == 0) pcur[irow] = tk * acc;
 }
 
@@ -187,7 +216,7 @@ constexpr int TAILM = 128;
 constexpr int TAILNT = 1024;
 
 __device__ double tail_sum(double v, double* red) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  v = wave_sum(v);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
@@ -239,7 +268,7 @@ __global__ __launch_bounds__(TAILNT) void trd_tail_k(int n, int k0, const double
     // every wavefront forms |c_{2..}|^2 itself from LDS (no barrier)
     double sig = 0.0;
     for (int i = 2 + (t & 63); i < m; i += 64) sig += col[i] * col[i];
-    for (int o = 32; o > 0; o >>= 1) sig += __shfl_xor(sig, o, 64);
+    sig = wave_sum(sig);
     const double dk = col[0], alpha = m >= 2 ? col[1] : 0.0;
     double tk = 0.0, beta = alpha, scal = 0.0;
     if (m >= 2 && sig != 0.0) {
@@ -264,16 +293,14 @@ __global__ __launch_bounds__(TAILNT) void trd_tail_k(int n, int k0, const double
     double a = 0.0;
     if (has_row)
       for (int j = 1 + sub; j < m; j += 8) a += row[j] * vs[j];
-    a += __shfl_xor(a, 1, 64);
-    a += __shfl_xor(a, 2, 64);
-    a += __shfl_xor(a, 4, 64);
+    a = group8_sum(a);
     const double pi = tk * a, vi = has_row ? vs[i] : 0.0;
     if (sub == 0) ps[i - 1] = has_row ? pi * vi : 0.0;
     __syncthreads();
     // p . v, formed by every wavefront from the staged products (same order in each)
     double s2 = 0.0;
     for (int r = t & 63; r < TAILM; r += 64) s2 += ps[r];
-    for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o, 64);
+    s2 = wave_sum(s2);
     const double half = 0.5 * tk * s2, wi = pi - half * vi;
     if (has_row && sub == 0) ws[i] = wi;
     __syncthreads();
