@@ -110,6 +110,32 @@ def test_batch_equals_single_problem_path(ctx):
         assert torch.max(torch.abs(o["dEdC"] - ref["dEdC"])).item() < 1e-4
 
 
+def test_batch_tiny_instances(ctx):
+    """Instances far below one tile (N_bf 10..13, two active orbitals): fewer energy terms than the
+    32 blocks that sum them per instance, one partial lower-triangle tile, padded rows of B.  Each
+    against the single-problem entry point, on a graph replay and again on a second replay (the
+    asymmetry maximum is cleared and raised anew on every run)."""
+    insts = synth.pes_scan(4, seed=2004061427, nbf_range=(10, 13), ncwo=1, with_b=True)
+    probs = [P.problem(i.wl.nbf, i.wl.naux, i.wl.npairs, i.wl.ncwo, P.PNOF7, P.BF16_SPLIT, P.INTS_DF_BF16)
+             for i in insts]
+    assert all(i.wl.npairs * (i.wl.ncwo + 1) == 2 for i in insts)
+    batch = P.Batch(ctx, probs)
+    ins = [_device_inputs(ctx, i) for i in insts]
+    outs = batch.bind(ins)
+    for _ in range(2):
+        batch.run(graph=True)
+        torch.cuda.synchronize()
+        for prob, x, o in zip(probs, ins, outs):
+            ref = ctx.lagrangian(prob, x["C"], x["n"], x["H"], x["B"], grads=True)
+            torch.cuda.synchronize()
+            assert abs(o["E"].item() - ref["E"].item()) < 1e-6
+            assert torch.max(torch.abs(o["lam"] - ref["lam"])).item() < 2e-5
+            assert torch.max(torch.abs(o["dEdn"] - ref["dEdn"])).item() < 2e-5
+            assert torch.max(torch.abs(o["dEdC"] - ref["dEdC"])).item() < 1e-4
+            assert abs(o["max_asym"].item() - ref["max_asym"].item()) < 2e-5
+    batch.close()
+
+
 def test_graph_replays_match_eager(ctx):
     """Graph replays, with eager library work and synchronisations between them, reproduce the
     eager result bit for bit (the same kernels in the same order)."""
