@@ -61,7 +61,7 @@ typedef enum {
   PNOF_E_NOMEM = 4,        /* workspace allocation failed                               */
   PNOF_E_DEVICE = 5,       /* HIP launch or runtime error (possibly from an earlier call) */
   PNOF_E_NONFINITE = 6,    /* PNOF_CHECK_FINITE found a NaN / Inf in an input           */
-  PNOF_E_UNSUPPORTED = 7,  /* valid request that this build does not implement         */
+  PNOF_E_UNSUPPORTED = 7,  /* valid request that the library does not implement       */
   PNOF_E_EIG = 8           /* the eigensolver did not converge                          */
 } pnof_status;
 
