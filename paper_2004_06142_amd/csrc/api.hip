@@ -30,6 +30,7 @@ struct pnof_ctx_s {
   // with events; created on first use
   hipStream_t aux = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  hipEvent_t pipe_ev[4] = {nullptr, nullptr, nullptr, nullptr};   // chunk pipeline of the split path
   // measurement: launches of the contraction kernels bracketed by events on the stream
   bool profiling = false;
   struct Ev { int stage; hipEvent_t a, b; };
@@ -90,6 +91,16 @@ pnof_status rb_dgemm(pnof_ctx ctx, int M, int N, int K, double alpha, const doub
   const rocblas_status st = rocblas_dgemm(ctx->blas, ta, tb, M, N, K, &alpha, A, (int)lda, B, (int)ldb, &beta, C,
                                           (int)scn);
   if (st != rocblas_status_success) return fail(ctx, PNOF_E_DEVICE, "rocblas_dgemm failed");
+  return PNOF_OK;
+}
+
+// The context's second stream (default priority) and the events that fork and join it.
+pnof_status ensure_aux(pnof_ctx ctx) {
+  if (!ctx->aux) DEV_CHECK(ctx, hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+  if (!ctx->fork_ev) DEV_CHECK(ctx, hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming));
+  if (!ctx->join_ev) DEV_CHECK(ctx, hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming));
+  for (hipEvent_t& e : ctx->pipe_ev)
+    if (!e) DEV_CHECK(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
   return PNOF_OK;
 }
 
@@ -229,6 +240,7 @@ struct Bufs {
   u16 *cth, *ctl;       // split
   double *XT, *W, *Ypart64, *Bw;   // fp64 chunk
   u16 *xth, *xtl, *wh, *wl, *bh, *bl;  // split chunk
+  u16 *xth2, *xtl2;                    // split: XT of the next chunk (X runs one chunk ahead)
   float* Ypart32;
   double *Jr, *Kr;      // explicit integrals
   int* flag;
@@ -266,9 +278,11 @@ Bufs carve(const Plan& pl, char* base) {
       b.cth = a.take<u16>((long long)pl.nact32 * pl.ldk);
       b.ctl = a.take<u16>((long long)pl.nact32 * pl.ldk);
       b.xth = a.take<u16>((long long)pl.pc * pl.nact32 * pl.ldx);
+      b.xth2 = a.take<u16>((long long)pl.pc * pl.nact32 * pl.ldx);
       b.wh = a.take<u16>((long long)pl.pc * pl.nact32 * pl.ldw);
       if (pl.terms > 1) {
         b.xtl = a.take<u16>((long long)pl.pc * pl.nact32 * pl.ldx);
+        b.xtl2 = a.take<u16>((long long)pl.pc * pl.nact32 * pl.ldx);
         b.wl = a.take<u16>((long long)pl.pc * pl.nact32 * pl.ldw);
       }
       b.Ypart32 = a.take<float>((long long)pl.ns3 * ny);
@@ -399,17 +413,18 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
       for (int lo = 0; lo < (pl.terms > 1 ? 2 : 1); ++lo) {
         DEV_CHECK(ctx, zero_pads_u16(s, lo ? b.ctl : b.cth, 1, nct, nact, pl.nact32, pl.ldk, nbf));
         DEV_CHECK(ctx, zero_pads_u16(s, lo ? b.xtl : b.xth, pl.pc, sx, nact, pl.nact32, pl.ldx, nbf));
+        DEV_CHECK(ctx, zero_pads_u16(s, lo ? b.xtl2 : b.xth2, pl.pc, sx, nact, pl.nact32, pl.ldx, nbf));
         DEV_CHECK(ctx, zero_pads_u16(s, lo ? b.wl : b.wh, pl.pc, sw, nact, pl.nact32, pl.ldw, nact));
       }
       DEV_CHECK(ctx, split_ca(s, nbf, nact, pl.terms, C, b.cth, b.ctl, pl.ldk));
       corr_terms = pl.terms > 1 ? 2 : 1;
     }
     const long long bsz = (long long)nbf * nbf;
-    for (int p0 = 0; p0 < pl.naux; p0 += pl.pc) {
-      const int np = std::min(pl.pc, pl.naux - p0);
-      const int ns2 = std::min(pl.ns2, np), ns3 = std::min(pl.ns3, np);
-      double* Dc = b.D + (long long)p0 * nact;
-      if (!pl.split) {
+    if (!pl.split) {
+      for (int p0 = 0; p0 < pl.naux; p0 += pl.pc) {
+        const int np = std::min(pl.pc, pl.naux - p0);
+        const int ns2 = std::min(pl.ns2, np), ns3 = std::min(pl.ns3, np);
+        double* Dc = b.D + (long long)p0 * nact;
         const double* Bc;
         if (pl.ints == PNOF_INTS_DF_F64) Bc = static_cast<const double*>(ints) + p0 * bsz;
         else {
@@ -426,40 +441,85 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
         if (r.Jq || r.Kq || r.Fq)
           DEV_CHECK(ctx, df_ao_accum(s, nbf, nact, np, r.nq, r.q_idx, Bc, 0, Dc, b.alpha, b.beta, b.XT, nullptr, nullptr,
                                      pl.ldx, (long long)nact * pl.ldx, r.Jq, r.Kq, r.Fq));
-      } else {
+      }
+    } else {
+      // Chunk pipeline: X of chunk c + 1 runs between b and Y of chunk c (XT is double-buffered,
+      // chunk c in buffer c & 1), while the context's second stream forms chunk c's D alpha and W
+      // diagonal beside it; the Y partials of chunk c are reduced there beside b and X of the next
+      // chunks.  Events order the two streams: W's diagonal before Y(c); the reduction of Y(c - 1)
+      // before Y(c) overwrites the partials; the last reduction before Y2e is read.  W itself is
+      // single-buffered: Y(c) precedes b(c + 1) on the main stream.
+      const int nchunk = (int)cdiv(pl.naux, pl.pc);
+      SplitPtr Ct{b.cth, pl.terms > 1 ? b.ctl : nullptr};
+      u16* const xth_[2] = {b.xth, b.xth2};
+      u16* const xtl_[2] = {b.xtl, b.xtl2};
+      hipStream_t sa = nullptr;
+      hipEvent_t ev_b = nullptr, ev_d = nullptr, ev_y = nullptr, ev_r = nullptr;
+      if (want_y) {
+        RB_CHECK(ensure_aux(ctx));
+        sa = ctx->aux;
+        ev_b = ctx->pipe_ev[0];
+        ev_d = ctx->pipe_ev[1];
+        ev_y = ctx->pipe_ev[2];
+        ev_r = ctx->pipe_ev[3];
+      }
+      auto run_x = [&](int c) -> pnof_status {
+        const long long p0 = (long long)c * pl.pc;
+        const int np = (int)std::min<long long>(pl.pc, pl.naux - p0);
         SplitPtr Bp;
-        const void* Bsrc;
         long long b_bytes;
         if (pl.ints == PNOF_INTS_DF_BF16) {
           Bp.hi = static_cast<const u16*>(ints) + p0 * bsz;
           Bp.lo = nullptr;
-          Bsrc = Bp.hi;
           b_bytes = 2LL * (pl.naux - p0) * bsz;
         } else {
           b_bytes = 2LL * np * bsz;
-          const double* Bf = static_cast<const double*>(ints) + p0 * bsz;
-          DEV_CHECK(ctx, split_b(s, np * bsz, Bf, b.bh, b.bl));
+          DEV_CHECK(ctx, split_b(s, np * bsz, static_cast<const double*>(ints) + p0 * bsz, b.bh, b.bl));
           Bp.hi = b.bh;
           Bp.lo = pl.terms > 1 ? b.bl : nullptr;
-          Bsrc = Bf;
         }
-        SplitPtr Ct{b.cth, pl.terms > 1 ? b.ctl : nullptr};
-        DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_X, df_bf16_gemm1(s, nbf, nact, np, pl.terms, Ct, pl.ldk, Bp, bsz, nbf, b_bytes, b.xth,
-                                                               b.xtl, pl.ldx, pl.xv, wd)));
-        SplitPtr XT{b.xth, b.xtl};
-        DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_B, df_bf16_gemm2(s, nbf, nact, np, ns2, pl.terms, Ct, pl.ldk, XT, pl.ldx, b.beta32, b.Kpart, Dc,
-                                     b.wh, b.wl, pl.ldw, wd)));
+        DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_X, df_bf16_gemm1(s, nbf, nact, np, pl.terms, Ct, pl.ldk, Bp, bsz, nbf, b_bytes,
+                                                               xth_[c & 1], xtl_[c & 1], pl.ldx, pl.xv, wd)));
+        return PNOF_OK;
+      };
+      RB_CHECK(run_x(0));
+      for (int c = 0; c < nchunk; ++c) {
+        const int p0 = c * pl.pc;
+        const int np = std::min(pl.pc, pl.naux - p0);
+        const int ns2 = std::min(pl.ns2, np), ns3 = std::min(pl.ns3, np);
+        double* Dc = b.D + (long long)p0 * nact;
+        SplitPtr XT{xth_[c & 1], pl.terms > 1 ? xtl_[c & 1] : nullptr};
+        DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_B, df_bf16_gemm2(s, nbf, nact, np, ns2, pl.terms, Ct, pl.ldk, XT, pl.ldx,
+                                                               b.beta32, b.Kpart, Dc, b.wh, b.wl, pl.ldw, wd)));
         if (want_y) {
-          DEV_CHECK(ctx, add_diag_bf16(s, nact, np, Dc, b.alpha, b.beta32, b.dbuf, b.wh, b.wl, pl.ldw, (long long)pl.nact32 * pl.ldw));
-          SplitPtr W{b.wh, b.wl};
-          DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_Y, df_bf16_gemm3(s, nbf, nact, np, ns3, pl.terms, XT, pl.ldx, W, pl.ldw, b.Ypart32, pl.yv, wd)));
-          DEV_CHECK(ctx, reduce_y_f32(s, ny, ns3, b.Ypart32, b.Y2e));
+          DEV_CHECK(ctx, hipEventRecord(ev_b, s));
+          DEV_CHECK(ctx, hipStreamWaitEvent(sa, ev_b, 0));
+          DEV_CHECK(ctx, add_diag_bf16(sa, nact, np, Dc, b.alpha, b.beta32, b.dbuf, b.wh, b.wl, pl.ldw,
+                                       (long long)pl.nact32 * pl.ldw));
+          DEV_CHECK(ctx, hipEventRecord(ev_d, sa));
         }
-        if (r.Jq || r.Kq || r.Fq)
+        if (c + 1 < nchunk) RB_CHECK(run_x(c + 1));
+        if (want_y) {
+          DEV_CHECK(ctx, hipStreamWaitEvent(s, ev_d, 0));
+          if (c > 0) DEV_CHECK(ctx, hipStreamWaitEvent(s, ev_r, 0));
+          SplitPtr W{b.wh, b.wl};
+          DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_Y, df_bf16_gemm3(s, nbf, nact, np, ns3, pl.terms, XT, pl.ldx, W, pl.ldw,
+                                                                 b.Ypart32, pl.yv, wd)));
+          DEV_CHECK(ctx, hipEventRecord(ev_y, s));
+          DEV_CHECK(ctx, hipStreamWaitEvent(sa, ev_y, 0));
+          DEV_CHECK(ctx, reduce_y_f32(sa, ny, ns3, b.Ypart32, b.Y2e));
+          DEV_CHECK(ctx, hipEventRecord(ev_r, sa));
+        }
+        if (r.Jq || r.Kq || r.Fq) {
+          const void* Bsrc = pl.ints == PNOF_INTS_DF_BF16
+                                 ? static_cast<const void*>(static_cast<const u16*>(ints) + (long long)p0 * bsz)
+                                 : static_cast<const void*>(static_cast<const double*>(ints) + (long long)p0 * bsz);
           DEV_CHECK(ctx, df_ao_accum(s, nbf, nact, np, r.nq, r.q_idx, Bsrc, pl.ints == PNOF_INTS_DF_BF16, Dc, b.alpha,
-                                     b.beta, nullptr, b.xth, b.xtl, pl.ldx, (long long)pl.nact32 * pl.ldx, r.Jq, r.Kq,
+                                     b.beta, nullptr, XT.hi, XT.lo, pl.ldx, (long long)pl.nact32 * pl.ldx, r.Jq, r.Kq,
                                      r.Fq));
+        }
       }
+      if (want_y) DEV_CHECK(ctx, hipStreamWaitEvent(s, ev_r, 0));
     }
     DEV_CHECK(ctx, reduce_k(s, nact, pl.ns2, b.Kpart, K));
     // J = D^T D
@@ -870,6 +930,8 @@ void pnof_destroy(pnof_ctx ctx) {
   }
   if (ctx->fork_ev) hipEventDestroy(ctx->fork_ev);
   if (ctx->join_ev) hipEventDestroy(ctx->join_ev);
+  for (hipEvent_t e : ctx->pipe_ev)
+    if (e) hipEventDestroy(e);
   if (ctx->own_ws) hipFree(ctx->own_ws);
   if (ctx->host_info) hipHostFree(ctx->host_info);
   if (ctx->blas) rocblas_destroy_handle(ctx->blas);
@@ -1095,9 +1157,7 @@ pnof_status eigh(pnof_ctx ctx, int n, double* A, double* w, double* U, const Eig
   }
   if (!ws.Vh || !ws.p2 || !ws.e || !ws.tau || !ws.T || !ws.Q)
     return fail(ctx, PNOF_E_ARG, "eigensolver workspace missing");
-  if (!ctx->aux) DEV_CHECK(ctx, hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
-  if (!ctx->fork_ev) DEV_CHECK(ctx, hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming));
-  if (!ctx->join_ev) DEV_CHECK(ctx, hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming));
+  RB_CHECK(ensure_aux(ctx));
   DEV_CHECK(ctx, tridiag_f64(s, n, A, ws.Vh, ws.p2, w, ws.e, ws.tau));
   DEV_CHECK(ctx, hipEventRecord(ctx->fork_ev, s));
   DEV_CHECK(ctx, hipStreamWaitEvent(ctx->aux, ctx->fork_ev, 0));
