@@ -28,13 +28,13 @@ KSRC = os.path.join(ROOT, "paper_2004_06142_amd", "csrc")
 # once the source changes the figure no longer applies and traffic is reported as null.
 TRAFFIC = {
     # profiles/c5_df1200_hbm_traffic.md: C5, bf16 split, 164-row chunks (read + written bytes per launch)
-    ("gemm1_kernel", 3): {"bytes": 1573489151 + 925078710,
+    ("gemm1_kernel", 3): {"bytes": 1581566046 + 926101569,
                           "plan": {"pchunk": 164, "x_variant": 3},
                           "sha256": {"k_gemm_bf16.hip": "5aac520fb45d7991fd5bfbcff7868df8d56b0626576d23d037cdd4c7e0106188"}},
-    ("gemm2_kernel", 3): {"bytes": 3469759224 + 1137493355,
+    ("gemm2_kernel", 3): {"bytes": 3460111292 + 1144690217,
                           "plan": {"pchunk": 164, "nsplit_b": 18},
                           "sha256": {"k_gemm_bf16.hip": "5aac520fb45d7991fd5bfbcff7868df8d56b0626576d23d037cdd4c7e0106188"}},
-    ("gemm3_kernel", 3): {"bytes": 2747461623 + 241429317,
+    ("gemm3_kernel", 3): {"bytes": 2747214750 + 241432962,
                           "plan": {"pchunk": 164, "nsplit_y": 10, "y_variant": 3},
                           "sha256": {"k_gemm_bf16.hip": "5aac520fb45d7991fd5bfbcff7868df8d56b0626576d23d037cdd4c7e0106188"}},
 }
