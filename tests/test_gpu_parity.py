@@ -174,6 +174,40 @@ def test_pchunk_invariance(ctx, pc):
     assert abs(out["E"].item() - ref["E"]) < 1e-10
 
 
+@pytest.mark.parametrize("kind", [P.INTS_DF_F64, P.INTS_DF_BF16])
+@pytest.mark.parametrize("pc", [1, 7])
+def test_split_chunk_pipeline(ctx, kind, pc):
+    """The bf16-split path over many chunks of B rows: X runs one chunk ahead into the second XT
+    buffer while the context's second stream forms D alpha, W's diagonal and the Y reduction.  With
+    1 or 7 rows per chunk (45 and 7 chunks, the last one short) the results match the oracle and the
+    one-chunk run, the per-orbital AO matrices (which read XT chunk by chunk) included."""
+    inst = _case("chunks_split", 64, 45, 4, 3, "bf16")
+    n, ref = _ref(inst, pnof.PNOF7)
+    prob = P.problem(64, 45, 4, 3, P.PNOF7, P.BF16_SPLIT, kind)
+    B = _ints(inst, kind)
+    q = [0, 5, 9]
+    one = ctx.lagrangian(prob, t(inst.C), t(n), t(inst.H), B)
+    _, fq_one = ctx.fock(prob, t(inst.C), t(n), t(inst.H), B, q_idx=q)
+    ctx.set_pchunk(pc)
+    try:
+        out = ctx.lagrangian(prob, t(inst.C), t(n), t(inst.H), B)
+        _, fq = ctx.fock(prob, t(inst.C), t(n), t(inst.H), B, q_idx=q)
+    finally:
+        ctx.set_pchunk(0)
+    torch.cuda.synchronize()
+    assert abs(out["E"].item() - ref["E"]) < split_energy_tol("chunks_split", n, ref, 4, 3)
+    assert np.max(np.abs(h(out["lam"]) - ref["lam"])) < 2e-5
+    # the chunking regroups the float32 partial sums, so the two runs agree to the mixed-precision
+    # bars (a wrong buffer or an unordered stream would miss them by orders of magnitude)
+    assert abs(out["E"].item() - one["E"].item()) < 1e-6
+    for k in ("lam", "dEdC", "dEdn"):
+        assert torch.max(torch.abs(out[k] - one[k])).item() < 2e-5, k
+    F = pnof.fock_ao(inst.C, n, inst.H, inst.B, 4, 3, pnof.PNOF7)
+    for i, qq in enumerate(q):
+        assert np.max(np.abs(h(fq[i]) - F[qq])) < 1e-4
+        assert torch.max(torch.abs(fq[i] - fq_one[i])).item() < 1e-4
+
+
 def test_determinism(ctx):
     inst = _case("det", 150, 200, 10, 4, "bf16")
     n, _ = _ref(inst, pnof.PNOF7)
