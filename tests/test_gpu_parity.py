@@ -192,8 +192,15 @@ def test_split_chunk_pipeline(ctx, kind, pc):
     try:
         out = ctx.lagrangian(prob, t(inst.C), t(n), t(inst.H), B)
         _, fq = ctx.fock(prob, t(inst.C), t(n), t(inst.H), B, q_idx=q)
+        _, K, Jq, Kq = ctx.jk(prob, t(inst.C), B, q_idx=q)   # no Y: the chunk loop without the second stream
     finally:
         ctx.set_pchunk(0)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(h(K) - ref["K"])) < 2e-5
+    for i, qq in enumerate(q):
+        Jr, Kr = pnof.jk_ao_df(inst.B, inst.C, qq)
+        assert np.max(np.abs(h(Jq[i]) - Jr)) < 1e-4
+        assert np.max(np.abs(h(Kq[i]) - Kr)) < 1e-4
     torch.cuda.synchronize()
     assert abs(out["E"].item() - ref["E"]) < split_energy_tol("chunks_split", n, ref, 4, 3)
     assert np.max(np.abs(h(out["lam"]) - ref["lam"])) < 2e-5
