@@ -29,7 +29,12 @@
  *       PNOF_INTS_DF_BF16   the same B stored as bfloat16 (the stored values are exact inputs).
  *     B_P must be symmetric in (m, n).
  *   - Calls are asynchronous on the context's HIP stream; outputs are valid after that stream is
- *     synchronised.  Scalar outputs (E, max_asym) are device scalars.
+ *     synchronised.  Scalar outputs (E, max_asym) are device scalars.  Some steps also run on a
+ *     second stream owned by the context (default priority): the orbital step's product of
+ *     reflectors, and in the bf16-split density-fitted calls that form the Fock vectors the per-chunk
+ *     D alpha, W diagonal and Y reduction.  That stream waits on an event recorded on the context's
+ *     stream before its first use in a call, and the context's stream waits on its last event before
+ *     the call's remaining work, so stream order as seen by the caller is unchanged.
  *   - Errors: arguments, shapes and enums are validated on the host before anything is enqueued;
  *     on error nothing is launched and the call returns a status; pnof_last_error() gives the text.
  *     A failed launch or an earlier asynchronous device error is returned as PNOF_E_DEVICE.
