@@ -795,6 +795,8 @@ struct pnof_batch_s {
   int maxM[4] = {0, 0, 0, 0}, maxN[4] = {0, 0, 0, 0};
   bool bound = false;
   hipStream_t cap = nullptr;
+  hipStream_t side = nullptr;         // second stream of a step (default priority)
+  hipEvent_t ev[3] = {};              // fork at the start, fork after b, join before energy_y
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int launches = 13;
@@ -853,21 +855,31 @@ hipError_t batch_offsets(pnof_batch b, hipStream_t s) {
   return hipStreamSynchronize(s);   // off goes out of scope
 }
 
+// Two branches, forked and joined with events (in a captured graph they become parallel nodes):
+// H C_A and H_pp, which only the energy reads, run on the side stream beside prep, X and b; then
+// J = D^T D beside D alpha, W's diagonal, Y and the reduction.
 hipError_t batch_enqueue(pnof_batch b, hipStream_t s) {
   const int n = b->ninst;
+  hipStream_t s2 = b->side;
   hipError_t e;
 #define BSTEP(expr) \
   if ((e = (expr)) != hipSuccess) return e
+  BSTEP(hipEventRecord(b->ev[0], s));
+  BSTEP(hipStreamWaitEvent(s2, b->ev[0], 0));
+  BSTEP(gemm_f64_grouped(s2, n, b->maxM[0], b->maxN[0], false, true, b->d_f64));
+  BSTEP(batch_hpp(s2, n, b->d_inst, b->mx));
   BSTEP(batch_prep(s, n, b->d_inst, b->mx));
-  BSTEP(gemm_f64_grouped(s, n, b->maxM[0], b->maxN[0], false, true, b->d_f64));
-  BSTEP(batch_hpp(s, n, b->d_inst, b->mx));
   BSTEP(df_bf16_gemm1_grouped(s, n, b->tot1, b->terms, b->tile[0], b->d_g1, b->d_off));
   BSTEP(df_bf16_gemm2_grouped(s, n, b->tot2, b->terms, b->tile[1], b->d_g2, b->d_off + (n + 1)));
+  BSTEP(hipEventRecord(b->ev[1], s));
+  BSTEP(hipStreamWaitEvent(s2, b->ev[1], 0));
+  BSTEP(gemm_f64_grouped(s2, n, b->maxM[2], b->maxN[2], true, true, b->d_f64 + 2 * n));
+  BSTEP(hipEventRecord(b->ev[2], s2));
   BSTEP(gemm_f64_grouped(s, n, b->maxM[1], b->maxN[1], false, true, b->d_f64 + n));
   BSTEP(batch_add_diag(s, n, b->d_inst, b->mx));
   BSTEP(df_bf16_gemm3_grouped(s, n, b->tot3, b->terms, b->tile[2], b->d_g3, b->d_off + 2 * (n + 1)));
   BSTEP(batch_reduce(s, n, b->d_inst, b->mx));
-  BSTEP(gemm_f64_grouped(s, n, b->maxM[2], b->maxN[2], true, true, b->d_f64 + 2 * n));
+  BSTEP(hipStreamWaitEvent(s, b->ev[2], 0));
   BSTEP(batch_energy_y(s, n, b->d_inst, b->mx));
   BSTEP(gemm_f64_grouped(s, n, b->maxM[3], b->maxN[3], true, true, b->d_f64 + 3 * n));
   BSTEP(batch_finish(s, n, b->d_inst, b->mx));
@@ -1623,6 +1635,9 @@ pnof_status pnof_batch_run(pnof_batch b, int32_t use_graph) {
   pnof_status st = check_ctx(ctx);
   if (st != PNOF_OK) return st;
   if (!b->bound) return fail(ctx, PNOF_E_ARG, "pnof_batch_bind must be called before pnof_batch_run");
+  if (!b->side) DEV_CHECK(ctx, hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking));
+  for (hipEvent_t& ev : b->ev)
+    if (!ev) DEV_CHECK(ctx, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
   if (!use_graph) {
     DEV_CHECK(ctx, batch_enqueue(b, ctx->stream));
     return PNOF_OK;
@@ -1658,6 +1673,12 @@ void pnof_batch_destroy(pnof_batch b) {
   hipStreamSynchronize(b->ctx->stream);
   batch_drop_graph(b);
   if (b->cap) hipStreamDestroy(b->cap);
+  if (b->side) {
+    hipStreamSynchronize(b->side);
+    hipStreamDestroy(b->side);
+  }
+  for (hipEvent_t ev : b->ev)
+    if (ev) hipEventDestroy(ev);
   if (b->ws) hipFree(b->ws);
   delete b;
 }
