@@ -31,8 +31,9 @@
  *   - Calls are asynchronous on the context's HIP stream; outputs are valid after that stream is
  *     synchronised.  Scalar outputs (E, max_asym) are device scalars.  Some steps also run on a
  *     second stream owned by the context (default priority): the orbital step's product of
- *     reflectors, and in the bf16-split density-fitted calls that form the Fock vectors the per-chunk
- *     D alpha, W diagonal and Y reduction.  That stream waits on an event recorded on the context's
+ *     reflectors, and in the bf16 density-fitted calls the row bounds of each next chunk of B (split
+ *     mode) and, when the Fock vectors are formed, the per-chunk D alpha, W diagonal and Y
+ *     reduction.  That stream waits on an event recorded on the context's
  *     stream before its first use in a call, and the context's stream waits on its last event before
  *     the call's remaining work, so stream order as seen by the caller is unchanged.
  *   - Errors: arguments, shapes and enums are validated on the host before anything is enqueued;
@@ -74,12 +75,21 @@ typedef enum { PNOF5 = 5, PNOF7 = 7, PNOF7S = 8 } pnof_functional;
 
 /* Arithmetic of the three-index contractions (X = B C, b = C^T X, Y = sum_P X W):
  *   PNOF_FP64        float64 matrix cores;
+ *   PNOF_FP32        float32 matrix cores (v_mfma_f32_16x16x4f32): C, B, X and W rounded to float32,
+ *                    float32 accumulation within a P row and over the rows of one P-split of Y, K in
+ *                    float64, and the energy corrected to first order with 4 <Y_2e, C_A - float(C_A)>;
  *   PNOF_BF16        one bfloat16 pass per contraction, float32 accumulation (error study only);
- *   PNOF_BF16_SPLIT  C, X and W carried as bfloat16 hi + lo pairs (2, 3 and 3 products),
- *                    float32 accumulation, float64 sums over P, and the energy corrected to first
- *                    order with 4 <Y, C_A - (C_hi + C_lo)> in float64.
+ *   PNOF_BF16_SPLIT  16-bit matrix cores with float32 accumulation.  C_A is carried as a bf16 pair
+ *                    C~ = hi + lo (|C - C~| <= 2^-17 |C|); X = B C~ takes 2 bf16 products against a
+ *                    bf16 B.  X, W and C~ itself (for b) are carried as fp16 pairs of the value times
+ *                    a power of two (about 22 significant bits) fixed per chunk of P rows from bounds
+ *                    of |B| and |C|; b and Y take 3 fp16 products each (hi*hi, hi*lo, lo*hi).  A
+ *                    float64 B is carried as an fp16 pair too (X then takes 3 fp16 products).  K sums
+ *                    b^2 in float32 over the rows of one P-split of one chunk, then in float64; D, J,
+ *                    Y are summed over P in float64 per chunk.  The energy is corrected to first
+ *                    order with 4 <Y_2e, C_A - C~> in float64.
  * Energies, lambda, J = D^T D, the eigensolver and all reductions are float64 in every mode. */
-typedef enum { PNOF_FP64 = 0, PNOF_BF16 = 2, PNOF_BF16_SPLIT = 3 } pnof_precision;
+typedef enum { PNOF_FP64 = 0, PNOF_FP32 = 1, PNOF_BF16 = 2, PNOF_BF16_SPLIT = 3 } pnof_precision;
 
 typedef enum { PNOF_INTS_ERI4_F64 = 0, PNOF_INTS_DF_F64 = 1, PNOF_INTS_DF_BF16 = 2 } pnof_ints;
 

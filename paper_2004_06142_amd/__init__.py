@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.environ.get("PNOF_LIBRARY") or os.path.join(_HERE, "libpnof.so")
 
 PNOF5, PNOF7, PNOF7S = 5, 7, 8
-FP64, BF16, BF16_SPLIT = 0, 2, 3
+FP64, FP32, BF16, BF16_SPLIT = 0, 1, 2, 3
 INTS_ERI4_F64, INTS_DF_F64, INTS_DF_BF16 = 0, 1, 2
 CHECK_FINITE = 1
 ON_SIGMOID, ON_TRIG = 0, 1

@@ -30,7 +30,7 @@ struct pnof_ctx_s {
   // with events; created on first use
   hipStream_t aux = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
-  hipEvent_t pipe_ev[4] = {nullptr, nullptr, nullptr, nullptr};   // chunk pipeline of the split path
+  hipEvent_t pipe_ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};   // chunk pipeline of the split path
   // measurement: launches of the contraction kernels bracketed by events on the stream
   bool profiling = false;
   struct Ev { int stage; hipEvent_t a, b; };
@@ -104,6 +104,18 @@ pnof_status ensure_aux(pnof_ctx ctx) {
   return PNOF_OK;
 }
 
+// Joins the context's second stream into its stream when a scope that forked it ends (on every
+// return path, so that no work of the call is left running on the second stream).
+struct AuxJoin {
+  pnof_ctx ctx;
+  bool forked = false;
+  explicit AuxJoin(pnof_ctx c) : ctx(c) {}
+  ~AuxJoin() {
+    if (!forked) return;
+    if (hipEventRecord(ctx->join_ev, ctx->aux) == hipSuccess) hipStreamWaitEvent(ctx->stream, ctx->join_ev, 0);
+  }
+};
+
 #define RB_CHECK(expr)                    \
   do {                                    \
     const pnof_status st_ = (expr);       \
@@ -150,7 +162,8 @@ pnof_status check_problem(pnof_ctx ctx, const pnof_problem* p) {
   if (nact > p->nbf) return fail(ctx, PNOF_E_SHAPE, "npairs*(ncwo+1) exceeds nbf");
   if (p->functional != PNOF5 && p->functional != PNOF7 && p->functional != PNOF7S)
     return fail(ctx, PNOF_E_ARG, "unknown functional");
-  if (p->precision != PNOF_FP64 && p->precision != PNOF_BF16 && p->precision != PNOF_BF16_SPLIT)
+  if (p->precision != PNOF_FP64 && p->precision != PNOF_FP32 && p->precision != PNOF_BF16 &&
+      p->precision != PNOF_BF16_SPLIT)
     return fail(ctx, PNOF_E_ARG, "unknown precision");
   if (p->ints != PNOF_INTS_ERI4_F64 && !is_df(p->ints)) return fail(ctx, PNOF_E_ARG, "unknown integral kind");
   if (p->flags & ~PNOF_CHECK_FINITE) return fail(ctx, PNOF_E_ARG, "unknown flag bits");
@@ -171,6 +184,7 @@ struct Plan {
   int pc, ns2, ns3, xv, yv;
   int ldk, ldx, ldxx, ldw, nact32;
   bool split;   // bf16 family
+  bool f32;     // PNOF_FP32: the float64 path's kernels in float32
   int terms;    // 1 or 3
 };
 
@@ -185,7 +199,8 @@ Plan make_plan(const pnof_problem* p, const pnof_tuning& tu) {
   pl.functional = p->functional;
   pl.prec = p->precision;
   pl.ints = p->ints;
-  pl.split = (p->precision != PNOF_FP64);
+  pl.split = (p->precision == PNOF_BF16 || p->precision == PNOF_BF16_SPLIT);
+  pl.f32 = (p->precision == PNOF_FP32);
   pl.terms = p->precision == PNOF_BF16_SPLIT ? 3 : 1;
   const int tile = pl.split ? 128 : 64;
   // workspace rows padded to multiples of 32 (zero pads): whole k-tiles never need masking
@@ -214,8 +229,9 @@ Plan make_plan(const pnof_problem* p, const pnof_tuning& tu) {
   long long pc = tu.pchunk > 0 ? tu.pchunk : std::max(64LL, (4096 + t1 - 1) / t1);
   const long long per_p = pl.split ? (long long)(2LL * pl.nact32 * pl.ldx + 2LL * pl.nact32 * pl.ldw) * 2 +
                                          (p->ints == PNOF_INTS_DF_F64 ? 4LL * pl.nbf * pl.nbf : 0)
-                                   : (long long)(pl.nact * pl.ldx + pl.nact * pl.ldw) * 8 +
-                                         (p->ints == PNOF_INTS_DF_BF16 ? 8LL * pl.nbf * pl.nbf : 0);
+                                   : pl.f32 ? (long long)(pl.nact * pl.ldx + pl.nact * pl.ldw) * 4
+                                            : (long long)(pl.nact * pl.ldx + pl.nact * pl.ldw) * 8 +
+                                                  (p->ints == PNOF_INTS_DF_BF16 ? 8LL * pl.nbf * pl.nbf : 0);
   const long long cap = std::max(1LL, (2LL << 30) / std::max(1LL, per_p));
   if (tu.pchunk <= 0) pc = std::min(pc, cap);
   pc = std::min<long long>(pc, pl.naux);
@@ -237,8 +253,12 @@ struct Bufs {
   double *alpha, *beta, *HC, *Hpp, *J, *K, *Y2e, *Y, *D, *Kpart, *partials, *E, *dbuf;
   float* beta32;
   double* Ct;           // fp64
-  u16 *cth, *ctl;       // split
+  u16 *cth, *ctl;       // split: bf16 C_A^T (the compact pair in the split mode)
+  u16 *ch16, *cl16;     // split mode: fp16 pair of C~ sC
+  uint32_t* bnd;        // split mode: scale bounds (call-level words, then two per chunk)
+  float* colb;          // split mode: per-orbital bounds (4 nact)
   double *XT, *W, *Ypart64, *Bw;   // fp64 chunk
+  float *Ct32, *XT32, *W32;        // fp32 path
   u16 *xth, *xtl, *wh, *wl, *bh, *bl;  // split chunk
   u16 *xth2, *xtl2;                    // split: XT of the next chunk (X runs one chunk ahead)
   float* Ypart32;
@@ -268,7 +288,12 @@ Bufs carve(const Plan& pl, char* base) {
     b.D = a.take<double>((long long)pl.naux * pl.nact);
     b.dbuf = a.take<double>((long long)F64_KSPLIT_MAX * pl.pc * pl.nact);
     b.Kpart = a.take<double>((long long)pl.ns2 * n2);
-    if (!pl.split) {
+    if (pl.f32) {
+      b.Ct32 = a.take<float>((long long)pl.nact * pl.ldk);
+      b.XT32 = a.take<float>((long long)pl.pc * pl.nact * pl.ldx);
+      b.W32 = a.take<float>((long long)pl.pc * pl.nact * pl.ldw);
+      b.Ypart32 = a.take<float>((long long)pl.ns3 * ny);
+    } else if (!pl.split) {
       b.Ct = a.take<double>((long long)pl.nact * pl.ldk);
       b.XT = a.take<double>((long long)pl.pc * pl.nact * pl.ldx);
       b.W = a.take<double>((long long)pl.pc * pl.nact * pl.ldw);
@@ -277,6 +302,12 @@ Bufs carve(const Plan& pl, char* base) {
     } else {
       b.cth = a.take<u16>((long long)pl.nact32 * pl.ldk);
       b.ctl = a.take<u16>((long long)pl.nact32 * pl.ldk);
+      if (pl.terms > 1) {
+        b.ch16 = a.take<u16>((long long)pl.nact32 * pl.ldk);
+        b.cl16 = a.take<u16>((long long)pl.nact32 * pl.ldk);
+        b.bnd = a.take<uint32_t>(scl_words(cdiv(pl.naux, pl.pc)));
+        b.colb = a.take<float>(4LL * pl.nact);
+      }
       b.xth = a.take<u16>((long long)pl.pc * pl.nact32 * pl.ldx);
       b.xth2 = a.take<u16>((long long)pl.pc * pl.nact32 * pl.ldx);
       b.wh = a.take<u16>((long long)pl.pc * pl.nact32 * pl.ldw);
@@ -372,7 +403,8 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
   double* J = r.J ? r.J : b.J;
   double* K = r.K ? r.K : b.K;
   double* Y = r.Y ? r.Y : b.Y;
-  const bool want_y = r.need_y || (pl.split && r.need_e) || r.Fq;
+  // the split and float32 modes correct the energy with Y (first order in the rounding of C)
+  const bool want_y = r.need_y || ((pl.split || pl.f32) && r.need_e) || r.Fq;
   const bool want_e = r.need_e;
   const bool have_n = (n != nullptr);
 
@@ -401,7 +433,10 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
     DEV_CHECK(ctx, fill_f64(s, b.Kpart, (long long)pl.ns2 * n2, 0.0));
     if (want_y) DEV_CHECK(ctx, fill_f64(s, b.Y2e, ny, 0.0));
     WsDims wd{pl.nact32, 0, 0, 0};
-    if (!pl.split) DEV_CHECK(ctx, transpose_ca(s, nbf, nact, C, b.Ct, pl.ldk));
+    if (pl.f32) {
+      DEV_CHECK(ctx, transpose_ca_f32(s, nbf, nact, C, b.Ct32, pl.ldk));
+      corr_terms = 1;
+    } else if (!pl.split) DEV_CHECK(ctx, transpose_ca(s, nbf, nact, C, b.Ct, pl.ldk));
     else {
       const long long nct = (long long)pl.nact32 * pl.ldk, nxt = (long long)pl.pc * pl.nact32 * pl.ldx,
                       nw = (long long)pl.pc * pl.nact32 * pl.ldw;
@@ -412,15 +447,42 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
       const long long sx = (long long)pl.nact32 * pl.ldx, sw = (long long)pl.nact32 * pl.ldw;
       for (int lo = 0; lo < (pl.terms > 1 ? 2 : 1); ++lo) {
         DEV_CHECK(ctx, zero_pads_u16(s, lo ? b.ctl : b.cth, 1, nct, nact, pl.nact32, pl.ldk, nbf));
+        if (pl.terms > 1) DEV_CHECK(ctx, zero_pads_u16(s, lo ? b.cl16 : b.ch16, 1, nct, nact, pl.nact32, pl.ldk, nbf));
         DEV_CHECK(ctx, zero_pads_u16(s, lo ? b.xtl : b.xth, pl.pc, sx, nact, pl.nact32, pl.ldx, nbf));
         DEV_CHECK(ctx, zero_pads_u16(s, lo ? b.xtl2 : b.xth2, pl.pc, sx, nact, pl.nact32, pl.ldx, nbf));
         DEV_CHECK(ctx, zero_pads_u16(s, lo ? b.wl : b.wh, pl.pc, sw, nact, pl.nact32, pl.ldw, nact));
       }
-      DEV_CHECK(ctx, split_ca(s, nbf, nact, pl.terms, C, b.cth, b.ctl, pl.ldk));
+      // split mode: bounds that fix the power-of-two scales of the fp16 pairs (call-level words; the
+      // per-chunk words are cleared here and raised by the row bounds of each chunk of B)
+      if (pl.terms > 1)
+        DEV_CHECK(ctx, scale_bounds(s, nbf, nact, C, n, pl.npairs, pl.ncwo, pl.nsingle, pl.functional, b.colb, b.bnd,
+                                    2 * (int)cdiv(pl.naux, pl.pc)));
+      DEV_CHECK(ctx, split_ca(s, nbf, nact, pl.terms, C, b.cth, b.ctl, b.ch16, b.cl16, pl.ldk, b.bnd));
       corr_terms = pl.terms > 1 ? 2 : 1;
     }
     const long long bsz = (long long)nbf * nbf;
-    if (!pl.split) {
+    if (pl.f32) {
+      for (int p0 = 0; p0 < pl.naux; p0 += pl.pc) {
+        const int np = std::min(pl.pc, pl.naux - p0);
+        const int ns2 = std::min(pl.ns2, np), ns3 = std::min(pl.ns3, np);
+        double* Dc = b.D + (long long)p0 * nact;
+        const bool bb = pl.ints == PNOF_INTS_DF_BF16;
+        const void* Bc = bb ? static_cast<const void*>(static_cast<const u16*>(ints) + p0 * bsz)
+                            : static_cast<const void*>(static_cast<const double*>(ints) + p0 * bsz);
+        DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_X, df_f32_gemm1(s, nbf, nact, np, b.Ct32, pl.ldk, Bc, bb, b.XT32, pl.ldx)));
+        DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_B, df_f32_gemm2(s, nbf, nact, np, ns2, b.Ct32, pl.ldk, b.XT32, pl.ldx,
+                                                              b.beta32, b.Kpart, Dc, b.W32, pl.ldw)));
+        if (want_y) {
+          DEV_CHECK(ctx, add_diag_f32(s, nact, np, Dc, b.alpha, b.dbuf, b.W32, pl.ldw));
+          DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_Y, df_f32_gemm3(s, nbf, nact, np, ns3, b.XT32, pl.ldx, b.W32, pl.ldw,
+                                                                b.Ypart32)));
+          DEV_CHECK(ctx, reduce_y_f32(s, ny, ns3, b.Ypart32, b.Y2e));
+        }
+        if (r.Jq || r.Kq || r.Fq)
+          DEV_CHECK(ctx, df_ao_accum(s, nbf, nact, np, r.nq, r.q_idx, Bc, bb, Dc, b.alpha, b.beta, nullptr, b.XT32,
+                                     nullptr, nullptr, pl.ldx, (long long)nact * pl.ldx, r.Jq, r.Kq, r.Fq, nullptr, 0));
+      }
+    } else if (!pl.split) {
       for (int p0 = 0; p0 < pl.naux; p0 += pl.pc) {
         const int np = std::min(pl.pc, pl.naux - p0);
         const int ns2 = std::min(pl.ns2, np), ns3 = std::min(pl.ns3, np);
@@ -440,33 +502,43 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
         }
         if (r.Jq || r.Kq || r.Fq)
           DEV_CHECK(ctx, df_ao_accum(s, nbf, nact, np, r.nq, r.q_idx, Bc, 0, Dc, b.alpha, b.beta, b.XT, nullptr, nullptr,
-                                     pl.ldx, (long long)nact * pl.ldx, r.Jq, r.Kq, r.Fq));
+                                     nullptr, pl.ldx, (long long)nact * pl.ldx, r.Jq, r.Kq, r.Fq, nullptr, 0));
       }
     } else {
       // Chunk pipeline: X of chunk c + 1 runs between b and Y of chunk c (XT is double-buffered,
-      // chunk c in buffer c & 1), while the context's second stream forms chunk c's D alpha and W
-      // diagonal beside it; the Y partials of chunk c are reduced there beside b and X of the next
-      // chunks.  Events order the two streams: W's diagonal before Y(c); the reduction of Y(c - 1)
-      // before Y(c) overwrites the partials; the last reduction before Y2e is read.  W itself is
-      // single-buffered: Y(c) precedes b(c + 1) on the main stream.
+      // chunk c in buffer c & 1), while the context's second stream forms the row bounds of chunk
+      // c + 1's B beside b(c), chunk c's D alpha and W diagonal beside X(c + 1), and reduces the Y
+      // partials of chunk c beside b and X of the next chunks.  Events order the two streams: the
+      // row bounds of a chunk before its X; W's diagonal before Y(c); the reduction of Y(c - 1) before
+      // Y(c) overwrites the partials; the last reduction before Y2e is read.  W itself is
+      // single-buffered: Y(c) precedes b(c + 1) on the main stream.  Whatever path leaves this scope,
+      // the main stream waits for the second one.
       const int nchunk = (int)cdiv(pl.naux, pl.pc);
-      SplitPtr Ct{b.cth, pl.terms > 1 ? b.ctl : nullptr};
+      const bool split = pl.terms > 1;
+      SplitPtr Ct{b.cth, split ? b.ctl : nullptr};      // X from a bf16 B: compact bf16 pair
+      SplitPtr C16{split ? b.ch16 : b.cth, split ? b.cl16 : nullptr};   // b (and X from float64 B)
       u16* const xth_[2] = {b.xth, b.xth2};
       u16* const xtl_[2] = {b.xtl, b.xtl2};
-      hipStream_t sa = nullptr;
-      hipEvent_t ev_b = nullptr, ev_d = nullptr, ev_y = nullptr, ev_r = nullptr;
-      if (want_y) {
-        RB_CHECK(ensure_aux(ctx));
-        sa = ctx->aux;
-        ev_b = ctx->pipe_ev[0];
-        ev_d = ctx->pipe_ev[1];
-        ev_y = ctx->pipe_ev[2];
-        ev_r = ctx->pipe_ev[3];
-      }
+      RB_CHECK(ensure_aux(ctx));
+      AuxJoin join(ctx);
+      hipStream_t sa = ctx->aux;
+      hipEvent_t ev_b = ctx->pipe_ev[0], ev_d = ctx->pipe_ev[1], ev_y = ctx->pipe_ev[2], ev_r = ctx->pipe_ev[3],
+                 ev_x = ctx->pipe_ev[4], ev_pre = ctx->pipe_ev[5];
+      auto chunk_rows = [&](int c) { return (int)std::min<long long>(pl.pc, pl.naux - (long long)c * pl.pc); };
+      auto bounds = [&](hipStream_t st, int c) -> pnof_status {
+        const long long p0 = (long long)c * pl.pc;
+        const void* Bc = pl.ints == PNOF_INTS_DF_BF16
+                             ? static_cast<const void*>(static_cast<const u16*>(ints) + p0 * bsz)
+                             : static_cast<const void*>(static_cast<const double*>(ints) + p0 * bsz);
+        DEV_CHECK(ctx, b_bounds(st, Bc, pl.ints == PNOF_INTS_DF_F64, (long long)chunk_rows(c) * nbf, nbf, nbf,
+                                b.bnd + SCL_CALL + 2 * c));
+        return PNOF_OK;
+      };
       auto run_x = [&](int c) -> pnof_status {
         const long long p0 = (long long)c * pl.pc;
-        const int np = (int)std::min<long long>(pl.pc, pl.naux - p0);
+        const int np = chunk_rows(c);
         SplitPtr Bp;
+        SplitPtr A = Ct;
         long long b_bytes;
         if (pl.ints == PNOF_INTS_DF_BF16) {
           Bp.hi = static_cast<const u16*>(ints) + p0 * bsz;
@@ -474,37 +546,51 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
           b_bytes = 2LL * (pl.naux - p0) * bsz;
         } else {
           b_bytes = 2LL * np * bsz;
-          DEV_CHECK(ctx, split_b(s, np * bsz, static_cast<const double*>(ints) + p0 * bsz, b.bh, b.bl));
+          DEV_CHECK(ctx, split_b(s, np * bsz, static_cast<const double*>(ints) + p0 * bsz, b.bh, b.bl,
+                                 split ? b.bnd : nullptr, c));
           Bp.hi = b.bh;
-          Bp.lo = pl.terms > 1 ? b.bl : nullptr;
+          Bp.lo = split ? b.bl : nullptr;
+          if (split) A = C16;
         }
-        DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_X, df_bf16_gemm1(s, nbf, nact, np, pl.terms, Ct, pl.ldk, Bp, bsz, nbf, b_bytes,
-                                                               xth_[c & 1], xtl_[c & 1], pl.ldx, pl.xv, wd)));
+        DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_X, df_bf16_gemm1(s, nbf, nact, np, pl.terms, A, pl.ldk, Bp, bsz, nbf, b_bytes,
+                                                               xth_[c & 1], xtl_[c & 1], pl.ldx, pl.xv, wd, b.bnd, c)));
         return PNOF_OK;
       };
+      if (split) RB_CHECK(bounds(s, 0));
       RB_CHECK(run_x(0));
       for (int c = 0; c < nchunk; ++c) {
         const int p0 = c * pl.pc;
-        const int np = std::min(pl.pc, pl.naux - p0);
+        const int np = chunk_rows(c);
         const int ns2 = std::min(pl.ns2, np), ns3 = std::min(pl.ns3, np);
         double* Dc = b.D + (long long)p0 * nact;
-        SplitPtr XT{xth_[c & 1], pl.terms > 1 ? xtl_[c & 1] : nullptr};
-        DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_B, df_bf16_gemm2(s, nbf, nact, np, ns2, pl.terms, Ct, pl.ldk, XT, pl.ldx,
-                                                               b.beta32, b.Kpart, Dc, b.wh, b.wl, pl.ldw, wd)));
+        SplitPtr XT{xth_[c & 1], split ? xtl_[c & 1] : nullptr};
+        if (split && c + 1 < nchunk) {
+          DEV_CHECK(ctx, hipEventRecord(ev_x, s));
+          DEV_CHECK(ctx, hipStreamWaitEvent(sa, ev_x, 0));
+          join.forked = true;
+          RB_CHECK(bounds(sa, c + 1));
+          DEV_CHECK(ctx, hipEventRecord(ev_pre, sa));
+        }
+        DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_B, df_bf16_gemm2(s, nbf, nact, np, ns2, pl.terms, C16, pl.ldk, XT, pl.ldx,
+                                                               b.beta32, b.Kpart, Dc, b.wh, b.wl, pl.ldw, wd, b.bnd, c)));
         if (want_y) {
           DEV_CHECK(ctx, hipEventRecord(ev_b, s));
           DEV_CHECK(ctx, hipStreamWaitEvent(sa, ev_b, 0));
+          join.forked = true;
           DEV_CHECK(ctx, add_diag_bf16(sa, nact, np, Dc, b.alpha, b.beta32, b.dbuf, b.wh, b.wl, pl.ldw,
-                                       (long long)pl.nact32 * pl.ldw));
+                                       (long long)pl.nact32 * pl.ldw, b.bnd, c));
           DEV_CHECK(ctx, hipEventRecord(ev_d, sa));
         }
-        if (c + 1 < nchunk) RB_CHECK(run_x(c + 1));
+        if (c + 1 < nchunk) {
+          if (split) DEV_CHECK(ctx, hipStreamWaitEvent(s, ev_pre, 0));
+          RB_CHECK(run_x(c + 1));
+        }
         if (want_y) {
           DEV_CHECK(ctx, hipStreamWaitEvent(s, ev_d, 0));
           if (c > 0) DEV_CHECK(ctx, hipStreamWaitEvent(s, ev_r, 0));
           SplitPtr W{b.wh, b.wl};
           DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_Y, df_bf16_gemm3(s, nbf, nact, np, ns3, pl.terms, XT, pl.ldx, W, pl.ldw,
-                                                                 b.Ypart32, pl.yv, wd)));
+                                                                 b.Ypart32, pl.yv, wd, b.bnd, c)));
           DEV_CHECK(ctx, hipEventRecord(ev_y, s));
           DEV_CHECK(ctx, hipStreamWaitEvent(sa, ev_y, 0));
           DEV_CHECK(ctx, reduce_y_f32(sa, ny, ns3, b.Ypart32, b.Y2e));
@@ -515,8 +601,8 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
                                  ? static_cast<const void*>(static_cast<const u16*>(ints) + (long long)p0 * bsz)
                                  : static_cast<const void*>(static_cast<const double*>(ints) + (long long)p0 * bsz);
           DEV_CHECK(ctx, df_ao_accum(s, nbf, nact, np, r.nq, r.q_idx, Bsrc, pl.ints == PNOF_INTS_DF_BF16, Dc, b.alpha,
-                                     b.beta, nullptr, XT.hi, XT.lo, pl.ldx, (long long)pl.nact32 * pl.ldx, r.Jq, r.Kq,
-                                     r.Fq));
+                                     b.beta, nullptr, nullptr, XT.hi, XT.lo, pl.ldx, (long long)pl.nact32 * pl.ldx, r.Jq,
+                                     r.Kq, r.Fq, b.bnd, c));
         }
       }
       if (want_y) DEV_CHECK(ctx, hipStreamWaitEvent(s, ev_r, 0));
@@ -529,8 +615,8 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
 
   if (want_e) {
     double* E = r.E ? r.E : b.E;
-    DEV_CHECK(ctx, energy(s, nbf, nact, n, b.Hpp, b.alpha, b.beta, J, K, b.Y2e, C, b.cth, b.ctl, pl.ldk, corr_terms,
-                          b.partials, E));
+    DEV_CHECK(ctx, energy(s, nbf, nact, n, b.Hpp, b.alpha, b.beta, J, K, b.Y2e, C, b.cth, b.ctl, b.Ct32, pl.ldk,
+                          corr_terms, b.partials, E));
   }
   if (want_y) DEV_CHECK(ctx, assemble_y(s, nbf, nact, n, b.HC, b.Y2e, Y));
   if (r.lam) {
@@ -598,7 +684,8 @@ struct OnObjective {
     DEV_CHECK(ctx, hipMemcpyAsync(gam, x.data(), sizeof(double) * ngam, hipMemcpyHostToDevice, s));
     DEV_CHECK(ctx, on_map(s, kind, npairs, ncwo, nsingle, gam, n, nullptr));
     DEV_CHECK(ctx, coeffs(s, nact, npairs, ncwo, nsingle, functional, n, alpha, beta, nullptr));
-    DEV_CHECK(ctx, energy(s, nbf, nact, n, Hpp, alpha, beta, J, K, nullptr, nullptr, nullptr, nullptr, 0, 0, partials, E));
+    DEV_CHECK(ctx, energy(s, nbf, nact, n, Hpp, alpha, beta, J, K, nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0,
+                          partials, E));
     DEV_CHECK(ctx, grad_n(s, nact, npairs, ncwo, nsingle, functional, n, Hpp, J, K, dEdn));
     DEV_CHECK(ctx, on_map_vjp(s, kind, npairs, ncwo, nsingle, gam, dEdn, g));
     host.resize(ngam + 1);
@@ -868,6 +955,7 @@ hipError_t batch_enqueue(pnof_batch b, hipStream_t s) {
   BSTEP(hipStreamWaitEvent(s2, b->ev[0], 0));
   BSTEP(gemm_f64_grouped(s2, n, b->maxM[0], b->maxN[0], false, true, b->d_f64));
   BSTEP(batch_hpp(s2, n, b->d_inst, b->mx));
+  if (b->terms > 1) BSTEP(batch_bounds(s, n, b->d_inst, b->mx));
   BSTEP(batch_prep(s, n, b->d_inst, b->mx));
   BSTEP(df_bf16_gemm1_grouped(s, n, b->tot1, b->terms, b->tile[0], b->d_g1, b->d_off));
   BSTEP(df_bf16_gemm2_grouped(s, n, b->tot2, b->terms, b->tile[1], b->d_g2, b->d_off + (n + 1)));
@@ -1354,8 +1442,8 @@ pnof_status pnof_optimize(pnof_ctx ctx, const pnof_problem* prob, const double* 
     if (st2 != PNOF_OK) return st2;
     if (op.fix_n) {
       DEV_CHECK(ctx, coeffs(s, nact, pr.npairs, pr.ncwo, pr.nsingle, pr.functional, n, o.alpha, o.beta, nullptr));
-      DEV_CHECK(ctx, energy(s, nbf, nact, n, Hpp, o.alpha, o.beta, J, K, nullptr, nullptr, nullptr, nullptr, 0, 0,
-                            o.partials, o.E));
+      DEV_CHECK(ctx, energy(s, nbf, nact, n, Hpp, o.alpha, o.beta, J, K, nullptr, nullptr, nullptr, nullptr, nullptr,
+                            0, 0, o.partials, o.E));
       DEV_CHECK(ctx, hipMemcpyAsync(host2, o.E, sizeof(double), hipMemcpyDeviceToHost, s));
       DEV_CHECK(ctx, hipStreamSynchronize(s));
       En = host2[0];
@@ -1473,6 +1561,7 @@ pnof_status pnof_batch_plan(pnof_ctx ctx, int32_t ninst, const pnof_problem* pro
   b->ctx = ctx;
   b->ninst = ninst;
   b->terms = prec == PNOF_BF16_SPLIT ? 3 : 1;
+  b->launches = b->terms > 1 ? 15 : 13;   // the split mode adds the two launches of the scale bounds
   b->probs.assign(probs, probs + ninst);
   b->inst.resize(ninst);
   // carve (measure, then allocate and carve again)
@@ -1495,8 +1584,12 @@ pnof_status pnof_batch_plan(pnof_ctx ctx, int32_t ninst, const pnof_problem* pro
       d.wh = a.take<u16>((long long)g.naux * g.nact32 * g.ldw);
       if (b->terms > 1) {
         d.ctl = a.take<u16>((long long)g.nact32 * g.ldk);
+        d.ch16 = a.take<u16>((long long)g.nact32 * g.ldk);
+        d.cl16 = a.take<u16>((long long)g.nact32 * g.ldk);
         d.xtl = a.take<u16>((long long)g.naux * g.nact32 * g.ldk);
         d.wl = a.take<u16>((long long)g.naux * g.nact32 * g.ldw);
+        d.bnd = a.take<uint32_t>(SCL_CALL + 2);
+        d.colb = a.take<float>(4LL * g.nact);
       }
       d.alpha = a.take<double>(n2);
       d.beta = a.take<double>(n2);
@@ -1549,6 +1642,7 @@ pnof_status pnof_batch_plan(pnof_ctx ctx, int32_t ninst, const pnof_problem* pro
     mx.y = std::max(mx.y, ny);
     mx.k = std::max(mx.k, n2);
     mx.diag = std::max(mx.diag, (long long)g.naux * g.nact);
+    mx.rows = std::max(mx.rows, (long long)g.naux * g.nbf);
     b->maxM[0] = std::max(b->maxM[0], g.nbf);  b->maxN[0] = std::max(b->maxN[0], g.nact);   // H C_A
     b->maxM[1] = std::max(b->maxM[1], g.naux); b->maxN[1] = std::max(b->maxN[1], g.nact);   // D alpha
     b->maxM[2] = std::max(b->maxM[2], g.nact); b->maxN[2] = std::max(b->maxN[2], g.nact);   // D^T D
@@ -1605,11 +1699,15 @@ pnof_status pnof_batch_bind(pnof_batch b, const pnof_batch_io* io) {
     const long long nct = (long long)g.nact32 * g.ldk, nxt = (long long)g.naux * g.nact32 * g.ldk,
                     nw = (long long)g.naux * g.nact32 * g.ldw;
     const WsDims wd{g.nact32, 2 * nct, 2 * nxt, 2 * nw};
+    // X: the compact bf16 pair of C (or one bf16 value) times B; b: the fp16 pair of C~ sC in the
+    // split mode; the scales of each instance come from its bound words (one chunk: all of B)
     g1[i] = G1Args{g.nbf, g.nact, g.naux, d.cth, d.ctl, g.ldk, d.Bp, nullptr, (long long)g.nbf * g.ldk, g.ldk,
-                   2LL * g.naux * g.nbf * g.ldk, d.xth, d.xtl, g.ldk, wd};
-    g2[i] = G2Args{g.nbf, g.nact, g.naux, g.ns2, d.cth, d.ctl, g.ldk, d.xth, d.xtl, g.ldk, d.beta32, d.Kpart, d.D,
-                   d.wh, d.wl, g.ldw, wd};
-    g3[i] = G3Args{g.nbf, g.nact, g.naux, g.ns3, d.xth, d.xtl, g.ldk, d.wh, d.wl, g.ldw, d.Ypart, wd};
+                   2LL * g.naux * g.nbf * g.ldk, d.xth, d.xtl, g.ldk, wd, d.bnd, 0};
+    const u16* c2h = b->terms > 1 ? d.ch16 : d.cth;
+    const u16* c2l = b->terms > 1 ? d.cl16 : nullptr;
+    g2[i] = G2Args{g.nbf, g.nact, g.naux, g.ns2, c2h, c2l, g.ldk, d.xth, d.xtl, g.ldk, d.beta32, d.Kpart, d.D,
+                   d.wh, d.wl, g.ldw, wd, d.bnd, 0};
+    g3[i] = G3Args{g.nbf, g.nact, g.naux, g.ns3, d.xth, d.xtl, g.ldk, d.wh, d.wl, g.ldw, d.Ypart, wd, d.bnd, 0};
     f[i] = F64Gemm{g.nbf, g.nact, g.nbf, 1.0, d.H, g.nbf, 1, d.C, g.nbf, 1, 0.0, d.HC, g.nact, 1};
     f[n + i] = F64Gemm{g.naux, g.nact, g.nact, 1.0, d.D, g.nact, 1, d.alpha, g.nact, 1, 0.0, d.dbuf, g.nact, 1};
     f[2 * n + i] = F64Gemm{g.nact, g.nact, g.naux, 1.0, d.D, 1, g.nact, d.D, g.nact, 1, 0.0, d.J, g.nact, 1};
@@ -1623,6 +1721,7 @@ pnof_status pnof_batch_bind(pnof_batch b, const pnof_batch_io* io) {
   DEV_CHECK(ctx, batch_offsets(b, s));
   DEV_CHECK(ctx, hipMemcpyAsync(b->d_f64, f.data(), sizeof(F64Gemm) * f.size(), hipMemcpyHostToDevice, s));
   DEV_CHECK(ctx, batch_pack(s, n, b->d_inst, b->mx));
+  if (b->terms > 1) DEV_CHECK(ctx, batch_b_bounds(s, n, b->d_inst, b->mx));
   // the host staging vectors go out of scope: wait for the copies
   DEV_CHECK(ctx, hipStreamSynchronize(s));
   b->bound = true;

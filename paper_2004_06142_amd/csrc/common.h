@@ -109,6 +109,97 @@ __device__ __forceinline__ void split_f64(double x, u16& hi, u16& lo) {
   lo = f32_to_bf16_bits((float)(x - (double)bf16_bits_to_f32(hi)));
 }
 
+// Compact bf16 pair of an orbital coefficient: hi = bf16(x), lo = bf16(x - hi), except that a lo
+// below 2^(e - 14) (2^e <= |hi| < 2^(e+1)) is rounded once more to the grid 2^(e - 21), where it
+// needs at most 8 bits.  hi + lo then spans at most 22 bits: it is exact in float32, and after a
+// power-of-two scaling it splits exactly into an fp16 pair (11 + 11 bits) while the scaled value
+// stays above 2^-3 (|C~| >= 2^-14 max|C| with the scale sC), so the b contraction's fp16 operand is
+// the same C~ as X's bf16 one; smaller entries differ by at most 2^-37 max|C|.
+// |x - hi - lo| <= 2^-17 |x|.
+__device__ __forceinline__ void split_compact(double x, u16& hi, u16& lo) {
+  hi = f32_to_bf16_bits((float)x);
+  const double h = (double)bf16_bits_to_f32(hi);
+  lo = f32_to_bf16_bits((float)(x - h));
+  const double l = (double)bf16_bits_to_f32(lo);
+  if (h == 0.0 || l == 0.0) return;
+  const int e = ilogb(h);
+  if (ilogb(l) >= e - 14) return;
+  const double q = ldexp(1.0, e - 21);
+  lo = (u16)(__float_as_uint((float)(rint(l / q) * q)) >> 16);
+}
+
+// ---------------------------------------------------------------- fp16 pairs with a power-of-two scale
+// In the split mode the operands of the b and Y contractions (and of X when B is float64) are carried
+// as fp16 hi + lo pairs of the value times a power of two s: hi = fp16(x s), lo = fp16(x s - hi),
+// |x s - hi - lo| <= 2^-22 |x s| while x s stays in fp16's normal range (absolute error at most 2^-25
+// below it).  s is chosen from a bound of |x| so that |x s| <= 2^14.
+__device__ __forceinline__ u16 f32_to_f16_bits(float x) {
+  const _Float16 h = (_Float16)x;
+  return __builtin_bit_cast(u16, h);
+}
+__device__ __forceinline__ float f16_bits_to_f32(u16 b) { return (float)__builtin_bit_cast(_Float16, b); }
+__device__ __forceinline__ void split_f16(float xs, u16& hi, u16& lo) {
+  hi = f32_to_f16_bits(xs);
+  lo = f32_to_f16_bits(xs - f16_bits_to_f32(hi));
+}
+// Two values at once, as packed pairs (first value in the low half).
+__device__ __forceinline__ void split2_f16(float a, float b, uint32_t& hi, uint32_t& lo) {
+  const u16 ha = f32_to_f16_bits(a), hb = f32_to_f16_bits(b);
+  const u16 la = f32_to_f16_bits(a - f16_bits_to_f32(ha)), lb = f32_to_f16_bits(b - f16_bits_to_f32(hb));
+  hi = (uint32_t)ha | ((uint32_t)hb << 16);
+  lo = (uint32_t)la | ((uint32_t)lb << 16);
+}
+
+// Exponent e with bound < 2^e (0 for a zero or non-finite bound), clamped to [-60, 60].
+__host__ __device__ inline int bound_exp(float bound) {
+  if (!(bound > 0.0f) || !(bound < 3.0e38f)) return 0;
+  int e;
+  frexpf(bound, &e);
+  return e > 60 ? 60 : (e < -60 ? -60 : e);
+}
+
+// Bounds that fix the scales of one problem (or one batch instance) and of one P-chunk of it, kept as
+// the bits of non-negative floats (so an integer atomic max is a float max):
+//   call-level  [0] max |C_pq| over active columns, [1] max column 1-norm of C_A,
+//               [2] max |beta| + max row 1-norm of alpha;
+//   per chunk c [SCL_CALL + 2c] max row 1-norm sum_nu |B_P mu nu| over the chunk's rows,
+//               [SCL_CALL + 2c + 1] max |B| over the chunk (float64 B only).
+constexpr int SCL_CALL = 4;
+inline long long scl_words(long long nchunk) { return SCL_CALL + 2 * nchunk; }
+
+// Multipliers of the split mode for one chunk, all powers of two (exact in float32):
+//   sC    Chat = C~ sC (the fp16 pair of the b contraction, and of X when B is float64);
+//   sB    Bhat = B sB (float64 B only);
+//   xmul  X accumulator -> Xhat = X sX (1 * sX for bf16 B; sX / (sC sB) for float64 B);
+//   invB  b accumulator (Chat^T Xhat) -> b;
+//   sW    What = W sW;  wmul = invB sW (b accumulator times beta -> What);
+//   invY  Y accumulator (Xhat^T What) -> Y;  invX = 1 / sX.
+// |X_P mu q| <= sum_nu |B_P mu nu| |C~_nu q| <= rownorm(B) max|C~|; |b_pq| <= ||c~_p||_1 max|X|;
+// |W_pq| <= max|b| (max|beta| + max_p sum_r |alpha_pr|) (the diagonal adds d = D alpha).  The 1 %
+// margins cover the float32 rounding of the bounds and |C~| <= |C| (1 + 2^-16).
+struct Scales {
+  float sC, sB, xmul, invB, sW, wmul, invY, invX;
+};
+__device__ __forceinline__ Scales chunk_scales(const uint32_t* __restrict__ bnd, int chunk, bool f64b) {
+  const int ec = bound_exp(__uint_as_float(bnd[0]) * 1.01f), ec1 = bound_exp(__uint_as_float(bnd[1]) * 1.01f),
+            eab = bound_exp(__uint_as_float(bnd[2]) * 1.01f);
+  const int ebn = bound_exp(__uint_as_float(bnd[SCL_CALL + 2 * chunk]) * 1.01f);
+  const int ebm = f64b ? bound_exp(__uint_as_float(bnd[SCL_CALL + 2 * chunk + 1]) * 1.01f) : 0;
+  const int kC = 13 - ec, kB = f64b ? 13 - ebm : 0;
+  const int kX = 14 - (ebn + ec);                // |X| < 2^(ebn + ec)
+  const int kW = 14 - (ec1 + ebn + ec + eab);    // |W| < 2^(ec1 + ebn + ec + eab)
+  Scales s;
+  s.sC = ldexpf(1.0f, kC);
+  s.sB = ldexpf(1.0f, kB);
+  s.xmul = ldexpf(1.0f, f64b ? kX - kC - kB : kX);
+  s.invB = ldexpf(1.0f, -kC - kX);
+  s.sW = ldexpf(1.0f, kW);
+  s.wmul = ldexpf(1.0f, kW - kC - kX);
+  s.invY = ldexpf(1.0f, -kX - kW);
+  s.invX = ldexpf(1.0f, -kX);
+  return s;
+}
+
 __host__ __device__ inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
 __host__ __device__ inline long long round_up(long long a, long long b) { return (a + b - 1) / b * b; }
 
@@ -148,6 +239,15 @@ hipError_t df_f64_gemm2(hipStream_t s, int nbf, int nact, int np, int nsplit, co
                         double* Dchunk, double* W, int ldw);
 hipError_t df_f64_gemm3(hipStream_t s, int nbf, int nact, int np, int nsplit, const double* XT,
                         int ldx, const double* W, int ldw, double* Ypart);
+// Float32 forms (PNOF_FP32): float operands and accumulation, float64 K sums and D; gemm1 reads B as
+// stored (bf16 when b_is_bf16, else float64) and rounds it to float.
+hipError_t df_f32_gemm1(hipStream_t s, int nbf, int nact, int np, const float* Ct, int ldk, const void* Bchunk,
+                        int b_is_bf16, float* XT, int ldx);
+hipError_t df_f32_gemm2(hipStream_t s, int nbf, int nact, int np, int nsplit, const float* Ct, int ldk,
+                        const float* XT, int ldx, const float* beta32, double* Kpart, double* Dchunk, float* W,
+                        int ldw);
+hipError_t df_f32_gemm3(hipStream_t s, int nbf, int nact, int np, int nsplit, const float* XT, int ldx,
+                        const float* W, int ldw, float* Ypart);
 
 // ---------------------------------------------------------------- bf16 split GEMMs (k_gemm_bf16.hip)
 // terms: 1 = hi*hi; 3 = hi*hi + hi*lo + lo*hi.  variant: 0 = 128 x 128 block tiles (two blocks per
@@ -177,6 +277,8 @@ struct G1Args {   // XT_P[p][mu] = sum_nu Ct[p][nu] B_P[mu][nu]
   u16* xt_lo;
   int ldx;
   WsDims ws;
+  const uint32_t* bnd;   // split mode: the bounds that fix the scales (see chunk_scales)
+  int chunk;
 };
 struct G2Args {   // b_P = Ct XT_P^T; K partials, D, W
   int nbf, nact, np, nsplit;
@@ -193,6 +295,8 @@ struct G2Args {   // b_P = Ct XT_P^T; K partials, D, W
   u16* w_lo;
   int ldw;
   WsDims ws;
+  const uint32_t* bnd;
+  int chunk;
 };
 struct G3Args {   // Ypart[s] = sum_{P in s} X_P W_P
   int nbf, nact, np, nsplit;
@@ -204,6 +308,8 @@ struct G3Args {   // Ypart[s] = sum_{P in s} X_P W_P
   int ldw;
   float* Ypart;
   WsDims ws;
+  const uint32_t* bnd;
+  int chunk;
 };
 // Work items of one launch.  The stacked form of X treats the rows (P, mu) of np consecutive B_P
 // as one matrix (B_P rows padded to ldb, bstride == nbf * ldb), so short rows do not waste tiles.
@@ -236,14 +342,19 @@ hipError_t df_bf16_gemm2_grouped(hipStream_t s, int ninst, int total, int terms,
 hipError_t df_bf16_gemm3_grouped(hipStream_t s, int ninst, int total, int terms, int tile, const G3Args* tab,
                                  const int* off);
 
+// Split mode (terms > 1): bnd / chunk give the scales of the chunk (chunk_scales); the X output, the
+// b operands Ct (fp16 pair of C~ sC) and XT, W and the Y operands are fp16 pairs; X from a float64 B
+// takes Ct and B as fp16 pairs (terms 3), from a bf16 B the compact bf16 pair of C (terms 2).
 hipError_t df_bf16_gemm1(hipStream_t s, int nbf, int nact, int np, int terms, SplitPtr Ct, int ldk, SplitPtr Bp,
                          long long bstride, int ldb, long long b_bytes, u16* XT_hi, u16* XT_lo, int ldx, int variant,
-                         const WsDims& d);
+                         const WsDims& d, const uint32_t* bnd, int chunk);
 hipError_t df_bf16_gemm2(hipStream_t s, int nbf, int nact, int np, int nsplit, int terms,
                          SplitPtr Ct, int ldk, SplitPtr XT, int ldx, const float* beta32,
-                         double* Kpart, double* Dchunk, u16* W_hi, u16* W_lo, int ldw, const WsDims& d);
+                         double* Kpart, double* Dchunk, u16* W_hi, u16* W_lo, int ldw, const WsDims& d,
+                         const uint32_t* bnd, int chunk);
 hipError_t df_bf16_gemm3(hipStream_t s, int nbf, int nact, int np, int nsplit, int terms, SplitPtr XT,
-                         int ldx, SplitPtr W, int ldw, float* Ypart, int variant, const WsDims& d);
+                         int ldx, SplitPtr W, int ldw, float* Ypart, int variant, const WsDims& d,
+                         const uint32_t* bnd, int chunk);
 
 // ---------------------------------------------------------------- batches (k_batch.hip)
 // One instance of a batch: sizes, the caller's inputs and outputs, and its slices of the batch
@@ -266,16 +377,21 @@ struct BInst {
   float* beta32;
   float* Ypart;
   u16 *cth, *ctl, *xth, *xtl, *wh, *wl;
+  u16 *ch16, *cl16;     // split mode: fp16 pair of C~ sC (the b contraction's operand)
+  uint32_t* bnd;        // split mode: scale bounds (SCL_CALL call-level words, then the words of B)
+  float* colb;          // split mode: per-orbital bounds (4 nact)
 };
 // Blocks per instance that sum the energy (each writes one partial to epart).
 constexpr int BATCH_EPARTS = 32;
 // Each launch covers every instance (blockIdx.y = instance); maxima size the grids.
 struct BMax {
   int nbf, nact;
-  long long pack, zero, prep, y, k, diag;
+  long long pack, zero, prep, y, k, diag, rows;
 };
 hipError_t batch_pack(hipStream_t s, int ninst, const BInst* tab, const BMax& mx);   // B -> Bp, zero workspace
-hipError_t batch_prep(hipStream_t s, int ninst, const BInst* tab, const BMax& mx);   // coeffs, split C_A, zero K partials
+hipError_t batch_b_bounds(hipStream_t s, int ninst, const BInst* tab, const BMax& mx);   // row bounds of B (at bind)
+hipError_t batch_bounds(hipStream_t s, int ninst, const BInst* tab, const BMax& mx);     // call-level scale bounds
+hipError_t batch_prep(hipStream_t s, int ninst, const BInst* tab, const BMax& mx);   // coeffs, split C_A
 hipError_t batch_hpp(hipStream_t s, int ninst, const BInst* tab, const BMax& mx);
 hipError_t batch_add_diag(hipStream_t s, int ninst, const BInst* tab, const BMax& mx);
 hipError_t batch_reduce(hipStream_t s, int ninst, const BInst* tab, const BMax& mx);  // Y2e, K
@@ -291,9 +407,22 @@ hipError_t zero_pads_u16(hipStream_t s, u16* base, int nslice, long long sstride
 hipError_t coeffs(hipStream_t s, int nact, int npairs, int ncwo, int nsingle, int functional, const double* n,
                   double* alpha, double* beta, float* beta32);
 hipError_t transpose_ca(hipStream_t s, int nbf, int nact, const double* C, double* Ct, int ldk);
+hipError_t transpose_ca_f32(hipStream_t s, int nbf, int nact, const double* C, float* Ct, int ldk);
+// float32 W: d = Dchunk alpha as in add_diag_f64, then W_P[p][p] += d[P][p].
+hipError_t add_diag_f32(hipStream_t s, int nact, int np, const double* Dchunk, const double* alpha, double* dbuf,
+                        float* W, int ldw);
+// C_A^T as bf16 (terms 1) or, in the split mode, the compact bf16 pair (hi, lo) plus the fp16 pair
+// (h16, l16) of the same value times sC (bnd: call-level words already formed).
 hipError_t split_ca(hipStream_t s, int nbf, int nact, int terms, const double* C, u16* Ct_hi,
-                    u16* Ct_lo, int ldk);
-hipError_t split_b(hipStream_t s, long long n, const double* B, u16* hi, u16* lo);
+                    u16* Ct_lo, u16* Ct_h16, u16* Ct_l16, int ldk, const uint32_t* bnd);
+// float64 B rows of one chunk as the fp16 pair of B sB.
+hipError_t split_b(hipStream_t s, long long n, const double* B, u16* hi, u16* lo, const uint32_t* bnd, int chunk);
+// Call-level scale bounds from C_A and n (col: 4 nact floats of scratch) into bnd[0..SCL_CALL), and
+// the nclear per-chunk words after them cleared.
+hipError_t scale_bounds(hipStream_t s, int nbf, int nact, const double* C, const double* n, int npairs, int ncwo,
+                        int nsingle, int functional, float* col, uint32_t* bnd, int nclear);
+// Largest row 1-norm and largest |B| of nrows rows (ncols used of ld) raised into slot[0], slot[1].
+hipError_t b_bounds(hipStream_t s, const void* B, int is_f64, long long nrows, int ncols, long long ld, uint32_t* slot);
 hipError_t widen_bf16(hipStream_t s, long long n, const u16* src, double* dst);
 hipError_t hpp_from_hc(hipStream_t s, int nbf, int nact, const double* C, const double* HC, double* Hpp);
 // Split-K float64 product for few output tiles: ks (<= F64_KSPLIT_MAX) dense M x N partial slabs in
@@ -309,13 +438,14 @@ hipError_t gemm_f64_splitk(hipStream_t s, int M, int N, int K, int ks, const dou
 hipError_t add_diag_f64(hipStream_t s, int nact, int np, const double* Dchunk, const double* alpha,
                         double* dbuf, double* W, int ldw);
 hipError_t add_diag_bf16(hipStream_t s, int nact, int np, const double* Dchunk, const double* alpha,
-                         const float* beta32, double* dbuf, u16* W_hi, u16* W_lo, int ldw, long long pstride);
+                         const float* beta32, double* dbuf, u16* W_hi, u16* W_lo, int ldw, long long pstride,
+                         const uint32_t* bnd, int chunk);
 hipError_t reduce_k(hipStream_t s, int nact, int nsplit, const double* Kpart, double* K);
 hipError_t reduce_y_f64(hipStream_t s, long long n, int nsplit, const double* Ypart, double* Y);
 hipError_t reduce_y_f32(hipStream_t s, long long n, int nsplit, const float* Ypart, double* Y);
 hipError_t energy(hipStream_t s, int nbf, int nact, const double* n, const double* Hpp,
                   const double* alpha, const double* beta, const double* J, const double* K,
-                  const double* Y2e, const double* C, const u16* Ct_hi, const u16* Ct_lo, int ldk,
+                  const double* Y2e, const double* C, const u16* Ct_hi, const u16* Ct_lo, const float* Ct32, int ldk,
                   int corr_terms, double* partials, double* E);
 hipError_t assemble_y(hipStream_t s, int nbf, int nact, const double* n, const double* HC,
                       const double* Y2e, double* Y);
@@ -362,8 +492,9 @@ hipError_t eri_fock_ao(hipStream_t s, int nbf, int nact, int nq, const int32_t* 
 // density-fitted per-orbital AO matrices, accumulated one P-chunk at a time
 hipError_t df_ao_accum(hipStream_t s, int nbf, int nact, int np, int nq, const int32_t* q_idx,
                        const void* Bchunk, int b_is_bf16, const double* Dchunk,
-                       const double* alpha, const double* beta, const double* XT, const u16* XT_hi,
-                       const u16* XT_lo, int ldx, long long xps, double* Jq, double* Kq, double* Fq);
+                       const double* alpha, const double* beta, const double* XT, const float* XT32, const u16* XT_hi,
+                       const u16* XT_lo, int ldx, long long xps, double* Jq, double* Kq, double* Fq,
+                       const uint32_t* bnd, int chunk);
 hipError_t fock_ao_h(hipStream_t s, int nbf, int nq, const int32_t* q_idx, const double* n,
                      const double* H, double* Fq);
 

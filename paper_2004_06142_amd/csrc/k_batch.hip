@@ -34,7 +34,12 @@ __global__ void pack_k(const BInst* __restrict__ tab) {
   INST_STRIDE(i, nct) {
     d.cth[i] = 0;
     if (d.ctl) d.ctl[i] = 0;
+    if (d.ch16) {
+      d.ch16[i] = 0;
+      d.cl16[i] = 0;
+    }
   }
+  if (d.bnd && blockIdx.x == 0 && threadIdx.x < SCL_CALL + 2) d.bnd[threadIdx.x] = 0u;
   INST_STRIDE(i, nxt) {
     d.xth[i] = 0;
     if (d.xtl) d.xtl[i] = 0;
@@ -45,8 +50,94 @@ __global__ void pack_k(const BInst* __restrict__ tab) {
   }
 }
 
-// alpha, beta (float64 and float32), C_A^T split into hi/lo.  The K partials need no clearing: the
-// grouped b contraction stores (not adds) every lower-triangle position of every split.
+// Row bounds of each instance's packed B (zero pads add nothing): the largest row 1-norm into
+// bnd[SCL_CALL] with an integer atomic max on the bits (one wavefront per row).
+__global__ void b_bounds_k(const BInst* __restrict__ tab) {
+  const BInst& d = tab[blockIdx.y];
+  if (!d.bnd) return;
+  __shared__ float red[NT / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const long long nrows = (long long)d.naux * d.nbf;
+  float rmax = 0.f;
+  for (long long r = (long long)blockIdx.x * (NT / 64) + w; r < nrows; r += (long long)gridDim.x * (NT / 64)) {
+    const u16* row = d.Bp + r * d.ldk;
+    float s = 0.f;
+    for (int c = 8 * lane; c < d.ldk; c += 512) {
+      const uint4 v = *reinterpret_cast<const uint4*>(row + c);
+      const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) s += fabsf(__uint_as_float(wd[k] << 16)) + fabsf(__uint_as_float(wd[k] & 0xFFFF0000u));
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    rmax = fmaxf(rmax, __shfl(s, 0, 64));
+  }
+  if (lane == 0) red[w] = rmax;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < NT / 64; ++k) red[0] = fmaxf(red[0], red[k]);
+    if (red[0] > 0.f) atomicMax(d.bnd + SCL_CALL, __float_as_uint(red[0]));
+  }
+}
+
+// Call-level scale bounds, stage 1: one wavefront per active orbital q of each instance,
+// colb[4q..4q+3] = sum_mu |C_mu q|, max_mu |C_mu q|, sum_r |alpha_qr|, max_r |beta_qr|.
+__global__ void col_bounds_k(const BInst* __restrict__ tab) {
+  const BInst& d = tab[blockIdx.y];
+  if (!d.bnd) return;
+  const int lane = threadIdx.x & 63;
+  const int q = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+  if (q >= d.nact) return;
+  double s1 = 0.0, cm = 0.0, sa = 0.0, bm = 0.0;
+  for (int mu = lane; mu < d.nbf; mu += 64) {
+    const double c = fabs(d.C[(long long)mu * d.nbf + q]);
+    s1 += c;
+    cm = fmax(cm, c);
+  }
+  for (int r = lane; r < d.nact; r += 64) {
+    double a, b;
+    pnof_coeff(q, r, d.n[q], d.n[r], d.npairs, d.ncwo, d.nsingle, d.functional, a, b);
+    sa += fabs(a);
+    bm = fmax(bm, fabs(b));
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    s1 += __shfl_down(s1, off, 64);
+    sa += __shfl_down(sa, off, 64);
+    cm = fmax(cm, __shfl_down(cm, off, 64));
+    bm = fmax(bm, __shfl_down(bm, off, 64));
+  }
+  if (lane == 0) {
+    d.colb[4 * q + 0] = (float)s1;
+    d.colb[4 * q + 1] = (float)cm;
+    d.colb[4 * q + 2] = (float)sa;
+    d.colb[4 * q + 3] = (float)bm;
+  }
+}
+
+// Stage 2, one block per instance: the call-level words bnd[0..3).
+__global__ void bounds_reduce_k(const BInst* __restrict__ tab) {
+  const BInst& d = tab[blockIdx.y];
+  if (!d.bnd) return;
+  __shared__ float red[4][NT / 64];
+  float v[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int q = threadIdx.x; q < d.nact; q += blockDim.x)
+    for (int k = 0; k < 4; ++k) v[k] = fmaxf(v[k], d.colb[4 * q + k]);
+  for (int off = 32; off > 0; off >>= 1)
+    for (int k = 0; k < 4; ++k) v[k] = fmaxf(v[k], __shfl_down(v[k], off, 64));
+  if ((threadIdx.x & 63) == 0)
+    for (int k = 0; k < 4; ++k) red[k][threadIdx.x >> 6] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < 4; ++k)
+      for (int w = 1; w < NT / 64; ++w) red[k][0] = fmaxf(red[k][0], red[k][w]);
+    d.bnd[0] = __float_as_uint(red[1][0]);
+    d.bnd[1] = __float_as_uint(red[0][0]);
+    d.bnd[2] = __float_as_uint(red[3][0] + red[2][0]);
+  }
+}
+
+// alpha, beta (float64 and float32), C_A^T as bf16 (terms 1) or, in the split mode, the compact bf16
+// pair and the fp16 pair of the same value times sC.  The K partials need no clearing: the grouped b
+// contraction stores (not adds) every lower-triangle position of every split.
 __global__ void prep_k(const BInst* __restrict__ tab) {
   const BInst& d = tab[blockIdx.y];
   const int nact = d.nact, nbf = d.nbf;
@@ -59,12 +150,23 @@ __global__ void prep_k(const BInst* __restrict__ tab) {
     d.beta[i] = b;
     d.beta32[i] = (float)b;
   }
+  const float sC = d.terms > 1 ? chunk_scales(d.bnd, 0, false).sC : 1.0f;
   INST_STRIDE(i, (long long)nact * nbf) {
     const int p = (int)(i / nbf), mu = (int)(i % nbf);
+    const long long o = (long long)p * d.ldk + mu;
+    const double x = d.C[(long long)mu * nbf + p];
+    if (d.terms == 1) {
+      d.cth[o] = f32_to_bf16_bits((float)x);
+      continue;
+    }
     u16 h, l;
-    split_f64(d.C[(long long)mu * nbf + p], h, l);
-    d.cth[(long long)p * d.ldk + mu] = h;
-    if (d.terms > 1) d.ctl[(long long)p * d.ldk + mu] = l;
+    split_compact(x, h, l);
+    d.cth[o] = h;
+    d.ctl[o] = l;
+    u16 a, b;
+    split_f16((bf16_bits_to_f32(h) + bf16_bits_to_f32(l)) * sC, a, b);
+    d.ch16[o] = a;
+    d.cl16[o] = b;
   }
 }
 
@@ -79,21 +181,27 @@ __global__ void hpp_k(const BInst* __restrict__ tab) {
   if (threadIdx.x == 0) d.Hpp[p] = s;
 }
 
-// W_P[p][p] = float(b^P_pp beta_pp) + (D alpha)[P][p], split into hi/lo.  D holds the b contraction's
-// float accumulators of the diagonal, so the entry is rebuilt and only written: the scattered
-// diagonal of W is never read back.
+// W_P[p][p] = float(b^P_pp beta_pp) + (D alpha)[P][p], as the fp16 pair of W sW (split mode) or one
+// bf16 value.  D holds the b contraction's diagonal, so the entry is rebuilt and only written: the
+// scattered diagonal of W is never read back.
 __global__ void add_diag_k(const BInst* __restrict__ tab) {
   const BInst& d = tab[blockIdx.y];
   const long long pstride = (long long)d.nact32 * d.ldw;
+  const float sW = d.wl ? chunk_scales(d.bnd, 0, false).sW : 1.0f;
   INST_STRIDE(i, (long long)d.naux * d.nact) {
     const long long P = i / d.nact;
     const int p = (int)(i % d.nact);
     const long long o = P * pstride + (long long)p * d.ldw + p;
     const float wv = (float)d.D[i] * d.beta32[(long long)p * d.nact + p];
-    u16 h, l;
-    split_f64((double)wv + d.dbuf[i], h, l);
-    d.wh[o] = h;
-    if (d.wl) d.wl[o] = l;
+    const double w = (double)wv + d.dbuf[i];
+    if (d.wl) {
+      u16 h, l;
+      split_f16((float)(w * (double)sW), h, l);
+      d.wh[o] = h;
+      d.wl[o] = l;
+    } else {
+      d.wh[o] = f32_to_bf16_bits((float)w);
+    }
   }
 }
 
@@ -232,6 +340,15 @@ __global__ void finish_k(const BInst* __restrict__ tab) {
 
 hipError_t batch_pack(hipStream_t s, int ninst, const BInst* tab, const BMax& mx) {
   LAUNCH2(pack_k, grid2(mx.pack, ninst, 8192), tab);
+}
+hipError_t batch_b_bounds(hipStream_t s, int ninst, const BInst* tab, const BMax& mx) {
+  LAUNCH2(b_bounds_k, grid2(mx.rows, ninst, 1024), tab);
+}
+hipError_t batch_bounds(hipStream_t s, int ninst, const BInst* tab, const BMax& mx) {
+  hipLaunchKernelGGL(col_bounds_k, dim3((unsigned)cdiv(mx.nact, NT / 64), (unsigned)ninst), dim3(NT), 0, s, tab);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  LAUNCH2(bounds_reduce_k, dim3(1, (unsigned)ninst), tab);
 }
 hipError_t batch_prep(hipStream_t s, int ninst, const BInst* tab, const BMax& mx) {
   LAUNCH2(prep_k, grid2(mx.prep, ninst), tab);

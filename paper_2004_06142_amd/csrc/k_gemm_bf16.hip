@@ -1,14 +1,17 @@
-// bfloat16 matrix-core (v_mfma_f32_16x16x32_bf16) contractions with float32 accumulation.
+// 16-bit matrix-core (v_mfma_f32_16x16x32_bf16 / _f16) contractions with float32 accumulation.
 //
-// Operands may be carried as a hi + lo pair of bf16 values (x ~= hi + lo to about 16 significant
-// bits); the accumulator then receives
-//   terms = 1: hi*hi
-//   terms = 2: Ahi*Bhi + Alo*Bhi                  (B exact in bf16)
+// Operands may be carried as a hi + lo pair of 16-bit values; the accumulator then receives
+//   terms = 1: hi*hi                              (bf16, one pass)
+//   terms = 2: Ahi*Bhi + Alo*Bhi                  (B exact in bf16: X from a bf16 B)
 //   terms = 3: Ahi*Bhi + Ahi*Blo + Alo*Bhi        (the lo*lo product is below float32 rounding)
+// In the split mode the pairs of the b and Y contractions (and of X when B is float64) are fp16
+// pairs of the value times a power of two (11 + 11 significant bits; the scales are fixed per P-chunk
+// from bounds, see chunk_scales), multiplied by the fp16 matrix-core instruction; X from a bf16 B
+// multiplies the compact bf16 pair of C by B and writes fp16 pairs.
 //
 // Block tiles BM x BN x 32 (128 x 256 for X, 128 x 128 for the symmetric b, 256 x 128 for Y),
 // 256 threads = 4 waves (2 x 2), each wave owning (BM/2) x (BN/2) in 16 x 16 MFMA blocks.  Operand
-// k-tiles go global -> registers (one tile ahead) -> LDS (two buffers), one barrier per k-tile.  MFMA lane layout (16x16x32 bf16): lane l supplies row l%16 and the eight k
+// k-tiles go global -> registers (one tile ahead) -> LDS (two buffers), one barrier per k-tile.  MFMA lane layout (16x16x32): lane l supplies row l%16 and the eight k
 // values 8*(l/16)..+7 of each operand; result element (4*(l/16)+j, l%16) is component j.
 //
 // Operand storage in global memory:
@@ -34,6 +37,16 @@ constexpr int T2 = 128;             // tile of the symmetric nact x nact product
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef short v4s __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+// One 16 x 16 x 32 product; fragments hold raw 16-bit patterns (bf16 or fp16 by F16).
+template <bool F16>
+__device__ __forceinline__ f32x4 mma(bf16x8 a, bf16x8 b, f32x4 c) {
+  if constexpr (F16)
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
 
 struct Opnd {
   const u16* hi;
@@ -171,7 +184,8 @@ __device__ __forceinline__ void zero(f32x4 (&acc)[MI][NI]) {
 // BM x BN block tile; 4 waves in 2 x 2, each owning (BM/2) x (BN/2).  acc is reset at the start of
 // each segment when RESET; epi(seg, acc) runs at the end of each.  A(seg, k0) / B(seg, k0) give
 // the operand descriptors of a k-tile (the storage order may change from one k-tile to the next).
-template <int BM, int BN, bool ALO, bool BLO, bool ACOL, bool BCOL, bool RESET, typename FA, typename FB, typename EPI>
+template <int BM, int BN, bool ALO, bool BLO, bool ACOL, bool BCOL, bool RESET, bool F16, typename FA, typename FB,
+          typename EPI>
 __device__ __forceinline__ void mainloop(Stage<BM, BN, ALO, BLO>& sm, int nseg, int kb, int ke, int m0, int n0, FA A,
                                          FB B, f32x4 (&acc)[BM / 32][BN / 32], EPI epi) {
   constexpr int MI = BM / 32, NI = BN / 32;
@@ -219,7 +233,7 @@ __device__ __forceinline__ void mainloop(Stage<BM, BN, ALO, BLO>& sm, int nseg, 
       for (int i = 0; i < MI; ++i)
 #pragma unroll
         for (int j = 0; j < NI; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = mma<F16>(ah[i], bh[j], acc[i][j]);
       if (BLO) {
         bf16x8 bl[NI];
 #pragma unroll
@@ -228,7 +242,7 @@ __device__ __forceinline__ void mainloop(Stage<BM, BN, ALO, BLO>& sm, int nseg, 
         for (int i = 0; i < MI; ++i)
 #pragma unroll
           for (int j = 0; j < NI; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = mma<F16>(ah[i], bl[j], acc[i][j]);
       }
       if (ALO) {
 #pragma unroll
@@ -236,7 +250,7 @@ __device__ __forceinline__ void mainloop(Stage<BM, BN, ALO, BLO>& sm, int nseg, 
           const bf16x8 al = frag<BM>(sm.a[buf][ALO ? 1 : 0], ACOL, wm + 16 * i);
 #pragma unroll
           for (int j = 0; j < NI; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = mma<F16>(al, bh[j], acc[i][j]);
         }
       }
       if (more) store(buf ^ 1);
@@ -348,8 +362,8 @@ struct Ring {
 // i + 1 read while the products of block i issue, in an order pinned by scheduling groups: a wave
 // then waits only for its B fragments and first A block after the barrier, instead of for most of
 // the k-tile's fragment reads, and the LDS stays busy through the tile.
-template <int BM, int BN, bool ALO, bool BLO, int S, bool ACOL, bool BCOL, bool RESET, int WGM = 2, int WGN = 2,
-          bool ILV = false, typename FA, typename FB, typename EPI>
+template <int BM, int BN, bool ALO, bool BLO, int S, bool ACOL, bool BCOL, bool RESET, bool F16, int WGM = 2,
+          int WGN = 2, bool ILV = false, typename FA, typename FB, typename EPI>
 __device__ __forceinline__ void mainloop_dl(Ring<BM, BN, ALO, BLO, S>& sm, int nseg, int kb, int ke, int m0, int n0,
                                             FA A, FB B, f32x4 (&acc)[BM / (16 * WGM)][BN / (16 * WGN)], EPI epi) {
   constexpr int NW = WGM * WGN;   // waves in a WGM x WGN grid, each owning (BM / WGM) x (BN / WGN)
@@ -409,14 +423,14 @@ __device__ __forceinline__ void mainloop_dl(Ring<BM, BN, ALO, BLO, S>& sm, int n
           }
           // products in passes over j, so no two consecutive products share an accumulator
 #pragma unroll
-          for (int j = 0; j < NI; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[c], bh[j], acc[i][j], 0, 0, 0);
+          for (int j = 0; j < NI; ++j) acc[i][j] = mma<F16>(ah[c], bh[j], acc[i][j]);
           if (BLO) {
 #pragma unroll
-            for (int j = 0; j < NI; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[c], bl[j], acc[i][j], 0, 0, 0);
+            for (int j = 0; j < NI; ++j) acc[i][j] = mma<F16>(ah[c], bl[j], acc[i][j]);
           }
           if (ALO) {
 #pragma unroll
-            for (int j = 0; j < NI; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[c], bh[j], acc[i][j], 0, 0, 0);
+            for (int j = 0; j < NI; ++j) acc[i][j] = mma<F16>(al[c], bh[j], acc[i][j]);
           }
           __builtin_amdgcn_sched_group_barrier(0x008, PR, 0);
         }
@@ -432,7 +446,7 @@ __device__ __forceinline__ void mainloop_dl(Ring<BM, BN, ALO, BLO, S>& sm, int n
       for (int i = 0; i < MI; ++i)
 #pragma unroll
         for (int j = 0; j < NI; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = mma<F16>(ah[i], bh[j], acc[i][j]);
       if (BLO) {
         bf16x8 bl[NI];
 #pragma unroll
@@ -441,7 +455,7 @@ __device__ __forceinline__ void mainloop_dl(Ring<BM, BN, ALO, BLO, S>& sm, int n
         for (int i = 0; i < MI; ++i)
 #pragma unroll
           for (int j = 0; j < NI; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = mma<F16>(ah[i], bl[j], acc[i][j]);
       }
       if (ALO) {
 #pragma unroll
@@ -449,7 +463,7 @@ __device__ __forceinline__ void mainloop_dl(Ring<BM, BN, ALO, BLO, S>& sm, int n
           const bf16x8 al = dl_frag<BM, ACOL>(sm.a[stage][ALO ? 1 : 0], wm + 16 * i);
 #pragma unroll
           for (int j = 0; j < NI; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = mma<F16>(al, bh[j], acc[i][j]);
         }
       }
       stage = (stage + 1 == S) ? 0 : stage + 1;
@@ -541,6 +555,8 @@ __device__ __forceinline__ void gemm1_body(int w, const G1Args& g) {
   u16* XTh = g.xt_hi + (STACK ? 0 : P * pstride);
   u16* XTl = g.xt_lo ? g.xt_lo + (STACK ? 0 : P * pstride) : nullptr;
   const long long nrows = (long long)g.np * nbf;
+  // split mode: X is written as the fp16 pair of X sX
+  const float xmul = TERMS >= 2 ? chunk_scales(g.bnd, g.chunk, TERMS == 3).xmul : 1.0f;
   f32x4 acc[MI][NI];
   auto epi = [&](int, f32x4(&a)[MI][NI]) {
 #pragma unroll
@@ -564,7 +580,7 @@ __device__ __forceinline__ void gemm1_body(int w, const G1Args& g) {
           if (p >= nact) continue;
           u16 h, l;
           if (TERMS == 1) { h = f32_to_bf16_bits(a[i][jn][j]); l = 0; }
-          else split_f32(a[i][jn][j], h, l);
+          else split_f16(a[i][jn][j] * xmul, h, l);
           XTh[(long long)p * ldx + xo] = h;
           if (XTl) XTl[(long long)p * ldx + xo] = l;
         }
@@ -579,7 +595,8 @@ __device__ __forceinline__ void gemm1_body(int w, const G1Args& g) {
       const long long o = (long long)P * g.bstride;
       return DOpnd{g.b_hi + o, BLO ? g.b_lo + o : nullptr, g.ldb, g.b_bytes - 2 * o};
     };
-    mainloop_dl<G1M, G1N, ALO, BLO, S, false, false, true, WGM, WGN, (WGM * WGN == 8)>(sm, 1, 0, nbf, m0, n0, A, B, acc,
+    mainloop_dl<G1M, G1N, ALO, BLO, S, false, false, true, (TERMS == 3), WGM, WGN, (WGM * WGN == 8)>(sm, 1, 0, nbf, m0, n0,
+                                                                                                     A, B, acc,
                                                                                       epi);
   } else {
     static_assert(VEC || (WGM == 2 && WGN == 2), "register-staged path: 2 x 2 waves");
@@ -589,7 +606,7 @@ __device__ __forceinline__ void gemm1_body(int w, const G1Args& g) {
       const long long o = (long long)P * g.bstride;
       return Opnd{g.b_hi + o, BLO ? g.b_lo + o : nullptr, g.ldb, STACK ? (int)nrows : nbf, nbf, false};
     };
-    mainloop<G1M, G1N, ALO, BLO, false, false, true>(sm, 1, 0, nbf, m0, n0, A, B, acc, epi);
+    mainloop<G1M, G1N, ALO, BLO, false, false, true, (TERMS == 3)>(sm, 1, 0, nbf, m0, n0, A, B, acc, epi);
   }
 }
 
@@ -616,7 +633,15 @@ __device__ __forceinline__ void gemm2_body(int w, const G2Args& g) {
   tri_tile(w % ntri, tt, tm, tn);
   const int m0 = tm * TT, n0 = tn * TT;
   const int pb = (int)((long long)np * s / nsplit), pe = (int)((long long)np * (s + 1) / nsplit);
-  // beta of this lane's accumulator positions, kept in registers for the whole P-range
+  // split mode: the accumulator holds b sC sX; W is written as the fp16 pair of W sW
+  float invB = 1.0f, wmul = 1.0f;
+  if constexpr (LO) {
+    const Scales sc = chunk_scales(g.bnd, g.chunk, false);
+    invB = sc.invB;
+    wmul = sc.wmul;
+  }
+  // beta (times the W scale) of this lane's accumulator positions, kept in registers for the whole
+  // P-range
   f32x4 bet[MI][NI];
 #pragma unroll
   for (int i = 0; i < MI; ++i)
@@ -625,7 +650,7 @@ __device__ __forceinline__ void gemm2_body(int w, const G2Args& g) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int p = m0 + row_of<TT, 2, WGN>(i, j), q = n0 + col_of<TT, 2, WGN>(jn);
-        bet[i][jn][j] = (p < nact && q < nact) ? g.beta32[(long long)p * nact + q] : 0.f;
+        bet[i][jn][j] = (p < nact && q < nact) ? g.beta32[(long long)p * nact + q] * wmul : 0.f;
       }
   f32x4 kacc[MI][NI], acc[MI][NI];
   zero(kacc);
@@ -642,14 +667,14 @@ __device__ __forceinline__ void gemm2_body(int w, const G2Args& g) {
         float wv[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const float b = a[i][jn][j];
+          const float b = a[i][jn][j] * invB;
           kacc[i][jn][j] += b * b;
-          wv[j] = b * bet[i][jn][j];
+          wv[j] = a[i][jn][j] * bet[i][jn][j];
         }
         uint32_t h01, h23, l01 = 0, l23 = 0;
         if constexpr (LO) {
-          split2_f32(wv[0], wv[1], h01, l01);
-          split2_f32(wv[2], wv[3], h23, l23);
+          split2_f16(wv[0], wv[1], h01, l01);
+          split2_f16(wv[2], wv[3], h23, l23);
         } else {
           h01 = cvt2_bf16(wv[0], wv[1]);
           h23 = cvt2_bf16(wv[2], wv[3]);
@@ -663,7 +688,7 @@ __device__ __forceinline__ void gemm2_body(int w, const G2Args& g) {
             if (p < nact) {
               Wh[(long long)p * ldw + q] = hv[j];
               if (LO) Wl[(long long)p * ldw + q] = lv[j];
-              if (diag && p == q) g.Dc[(long long)P * nact + p] = (double)a[i][jn][j];
+              if (diag && p == q) g.Dc[(long long)P * nact + p] = (double)(a[i][jn][j] * invB);
             }
           }
           if (!diag && p0 < nact) {
@@ -691,7 +716,7 @@ __device__ __forceinline__ void gemm2_body(int w, const G2Args& g) {
       const long long off = (long long)(pb + seg) * g.ws.nact32 * ldx;
       return DOpnd{g.xt_hi + off, LO ? g.xt_lo + off : nullptr, ldx, g.ws.xt_bytes - 2 * off};
     };
-    mainloop_dl<TT, TT, LO, LO, S, false, false, true, 2, WGN>(sm, pe - pb, 0, nbf, m0, n0, A, B, acc, epi);
+    mainloop_dl<TT, TT, LO, LO, S, false, false, true, LO, 2, WGN>(sm, pe - pb, 0, nbf, m0, n0, A, B, acc, epi);
   } else {
     __shared__ Stage<TT, TT, LO, LO> sm;
     auto A = [&](int) { return Opnd{g.ct_hi, g.ct_lo, g.ldk, nact, nbf, false}; };
@@ -699,7 +724,7 @@ __device__ __forceinline__ void gemm2_body(int w, const G2Args& g) {
       const long long off = (long long)(pb + seg) * g.ws.nact32 * ldx;
       return Opnd{g.xt_hi + off, LO ? g.xt_lo + off : nullptr, ldx, nact, nbf, false};
     };
-    mainloop<TT, TT, LO, LO, false, false, true>(sm, pe - pb, 0, nbf, m0, n0, A, B, acc, epi);
+    mainloop<TT, TT, LO, LO, false, false, true, LO>(sm, pe - pb, 0, nbf, m0, n0, A, B, acc, epi);
   }
   double* Kp = g.Kpart + (long long)s * nact * nact;
 #pragma unroll
@@ -750,7 +775,7 @@ __device__ __forceinline__ void gemm3_body(int w, const G3Args& g) {
       const long long off = (long long)(pb + seg) * g.ws.nact32 * ldw;
       return DOpnd{g.w_hi + off, LO ? g.w_lo + off : nullptr, ldw, g.ws.w_bytes - 2 * off};
     };
-    mainloop_dl<G3M, G3N, LO, LO, S, true, false, false, WGM, WGN, (WGM * WGN == 8)>(sm, pe - pb, 0, nact, m0, n0, A, B,
+    mainloop_dl<G3M, G3N, LO, LO, S, true, false, false, LO, WGM, WGN, (WGM * WGN == 8)>(sm, pe - pb, 0, nact, m0, n0, A, B,
                                                                                       acc, none);
   } else {
     static_assert(VEC || (WGM == 2 && WGN == 2), "register-staged path: 2 x 2 waves");
@@ -763,9 +788,10 @@ __device__ __forceinline__ void gemm3_body(int w, const G3Args& g) {
       const long long off = (long long)(pb + seg) * g.ws.nact32 * ldw;
       return Opnd{g.w_hi + off, LO ? g.w_lo + off : nullptr, ldw, nact, nact, false};
     };
-    mainloop<G3M, G3N, LO, LO, true, false, false>(sm, pe - pb, 0, nact, m0, n0, A, B, acc, none);
+    mainloop<G3M, G3N, LO, LO, true, false, false, LO>(sm, pe - pb, 0, nact, m0, n0, A, B, acc, none);
   }
   float* Y = g.Ypart + (long long)s * nbf * nact;
+  const float invY = LO ? chunk_scales(g.bnd, g.chunk, false).invY : 1.0f;   // acc = Y sX sW
 #pragma unroll
   for (int i = 0; i < MI; ++i)
 #pragma unroll
@@ -773,7 +799,7 @@ __device__ __forceinline__ void gemm3_body(int w, const G3Args& g) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int m = m0 + row_of<G3M, WGM, WGN>(i, j), n = n0 + col_of<G3N, WGM, WGN>(jn);
-        if (m < nbf && n < nact) Y[(long long)m * nact + n] = acc[i][jn][j];
+        if (m < nbf && n < nact) Y[(long long)m * nact + n] = acc[i][jn][j] * invY;
       }
 }
 
@@ -862,9 +888,9 @@ static void launch_g1v(hipStream_t s, const G1Args& g, int variant) {
 
 hipError_t df_bf16_gemm1(hipStream_t s, int nbf, int nact, int np, int terms, SplitPtr Ct, int ldk, SplitPtr Bp,
                          long long bstride, int ldb, long long b_bytes, u16* XT_hi, u16* XT_lo, int ldx, int variant,
-                         const WsDims& d) {
+                         const WsDims& d, const uint32_t* bnd, int chunk) {
   if (np <= 0) return hipSuccess;
-  const G1Args g{nbf, nact, np, Ct.hi, Ct.lo, ldk, Bp.hi, Bp.lo, bstride, ldb, b_bytes, XT_hi, XT_lo, ldx, d};
+  const G1Args g{nbf, nact, np, Ct.hi, Ct.lo, ldk, Bp.hi, Bp.lo, bstride, ldb, b_bytes, XT_hi, XT_lo, ldx, d, bnd, chunk};
   if (terms == 1) launch_g1v<1, false>(s, g, variant);
   else if (Bp.lo == nullptr) launch_g1v<2, false>(s, g, variant);
   else launch_g1v<3, true>(s, g, variant);
@@ -873,9 +899,10 @@ hipError_t df_bf16_gemm1(hipStream_t s, int nbf, int nact, int np, int terms, Sp
 
 hipError_t df_bf16_gemm2(hipStream_t s, int nbf, int nact, int np, int nsplit, int terms, SplitPtr Ct, int ldk,
                          SplitPtr XT, int ldx, const float* beta32, double* Kpart, double* Dchunk, u16* W_hi,
-                         u16* W_lo, int ldw, const WsDims& d) {
+                         u16* W_lo, int ldw, const WsDims& d, const uint32_t* bnd, int chunk) {
   if (np <= 0) return hipSuccess;
-  const G2Args g{nbf, nact, np, nsplit, Ct.hi, Ct.lo, ldk, XT.hi, XT.lo, ldx, beta32, Kpart, Dchunk, W_hi, W_lo, ldw, d};
+  const G2Args g{nbf,   nact,  np,     nsplit, Ct.hi, Ct.lo, ldk, XT.hi, XT.lo, ldx, beta32,
+                 Kpart, Dchunk, W_hi, W_lo,   ldw,   d,     bnd, chunk};
   const dim3 grid = xcd_grid(g2_items(g, T2));
   const bool vec = (ldk % 32 == 0) && (ldx % 32 == 0) && al16(Ct.hi) && (!Ct.lo || al16(Ct.lo)) && al16(XT.hi) &&
                    (!XT.lo || al16(XT.lo));
@@ -902,9 +929,10 @@ static void launch_g3(hipStream_t s, const G3Args& g) {
 }
 
 hipError_t df_bf16_gemm3(hipStream_t s, int nbf, int nact, int np, int nsplit, int terms, SplitPtr XT, int ldx,
-                         SplitPtr W, int ldw, float* Ypart, int variant, const WsDims& d) {
+                         SplitPtr W, int ldw, float* Ypart, int variant, const WsDims& d, const uint32_t* bnd,
+                         int chunk) {
   if (np <= 0) return hipSuccess;
-  const G3Args g{nbf, nact, np, nsplit, XT.hi, XT.lo, ldx, W.hi, W.lo, ldw, Ypart, d};
+  const G3Args g{nbf, nact, np, nsplit, XT.hi, XT.lo, ldx, W.hi, W.lo, ldw, Ypart, d, bnd, chunk};
   // variant (resolved by the planner): 1 = 128 x 128 (4 waves of 64 x 64, two blocks per CU),
   // 2 = 256 x 128 (4 waves of 128 x 64), 3 = 256 x 256 (8 waves of 128 x 64)
   if (terms == 1) {

@@ -59,24 +59,170 @@ __global__ void transpose_ca_k(int nbf, int nact, const double* __restrict__ C, 
     Ct[(long long)p * ldk + mu] = C[(long long)mu * nbf + p];
   }
 }
-
-__global__ void split_ca_k(int nbf, int nact, int terms, const double* __restrict__ C, u16* __restrict__ hi,
-                           u16* __restrict__ lo, int ldk) {
+__global__ void transpose_ca_f32_k(int nbf, int nact, const double* __restrict__ C, float* __restrict__ Ct, int ldk) {
   GRID_STRIDE(i, (long long)nact * nbf) {
     const int p = (int)(i / nbf), mu = (int)(i % nbf);
-    u16 h, l;
-    split_f64(C[(long long)mu * nbf + p], h, l);
-    hi[(long long)p * ldk + mu] = h;
-    if (terms > 1) lo[(long long)p * ldk + mu] = l;
+    Ct[(long long)p * ldk + mu] = (float)C[(long long)mu * nbf + p];
   }
 }
 
-__global__ void split_b_k(long long n, const double* __restrict__ B, u16* __restrict__ hi, u16* __restrict__ lo) {
+// C_A^T as bf16: one value (terms 1), or the compact bf16 pair C~ = hi + lo of X's contraction plus
+// the exact fp16 pair of C~ sC for the b contraction (and X from a float64 B).
+__global__ void split_ca_k(int nbf, int nact, int terms, const double* __restrict__ C, u16* __restrict__ hi,
+                           u16* __restrict__ lo, u16* __restrict__ h16, u16* __restrict__ l16, int ldk,
+                           const uint32_t* __restrict__ bnd) {
+  const float sC = terms > 1 ? chunk_scales(bnd, 0, false).sC : 1.0f;
+  GRID_STRIDE(i, (long long)nact * nbf) {
+    const int p = (int)(i / nbf), mu = (int)(i % nbf);
+    const long long o = (long long)p * ldk + mu;
+    const double x = C[(long long)mu * nbf + p];
+    if (terms == 1) {
+      hi[o] = f32_to_bf16_bits((float)x);
+      continue;
+    }
+    u16 h, l;
+    split_compact(x, h, l);
+    hi[o] = h;
+    lo[o] = l;
+    // hi + lo spans at most 22 bits: exact in float32, and its fp16 pair is exact (split_compact)
+    const float xs = (bf16_bits_to_f32(h) + bf16_bits_to_f32(l)) * sC;
+    u16 a, b;
+    split_f16(xs, a, b);
+    h16[o] = a;
+    l16[o] = b;
+  }
+}
+
+// float64 B as the fp16 pair of B sB (sB of the chunk), or as one bf16 value when bnd is null.
+__global__ void split_b_k(long long n, const double* __restrict__ B, u16* __restrict__ hi, u16* __restrict__ lo,
+                          const uint32_t* __restrict__ bnd, int chunk) {
+  if (!bnd) {
+    GRID_STRIDE(i, n) hi[i] = f32_to_bf16_bits((float)B[i]);
+    return;
+  }
+  const float sB = chunk_scales(bnd, chunk, true).sB;
   GRID_STRIDE(i, n) {
     u16 h, l;
-    split_f64(B[i], h, l);
+    const double xs = B[i] * (double)sB;
+    h = f32_to_f16_bits((float)xs);
+    l = f32_to_f16_bits((float)(xs - (double)f16_bits_to_f32(h)));
     hi[i] = h;
     lo[i] = l;
+  }
+}
+
+// Scale bounds, stage 1: one wavefront per active orbital q writes col[4q..4q+3] = sum_mu |C_mu q|,
+// max_mu |C_mu q|, sum_r |alpha_qr|, max_r |beta_qr| (alpha, beta of Eqs. Eg, Efg from n; zero when
+// n is absent).
+__global__ void col_bounds_k(int nbf, int nact, const double* __restrict__ C, const double* __restrict__ n,
+                             int npairs, int ncwo, int nsingle, int functional, float* __restrict__ col) {
+  const int lane = threadIdx.x & 63;
+  const int q = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (q >= nact) return;
+  double s1 = 0.0, cm = 0.0, sa = 0.0, bm = 0.0;
+  for (int mu = lane; mu < nbf; mu += 64) {
+    const double c = fabs(C[(long long)mu * nbf + q]);
+    s1 += c;
+    cm = fmax(cm, c);
+  }
+  if (n) {
+    for (int r = lane; r < nact; r += 64) {
+      double a, b;
+      pnof_coeff(q, r, n[q], n[r], npairs, ncwo, nsingle, functional, a, b);
+      sa += fabs(a);
+      bm = fmax(bm, fabs(b));
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    s1 += __shfl_down(s1, off, 64);
+    sa += __shfl_down(sa, off, 64);
+    cm = fmax(cm, __shfl_down(cm, off, 64));
+    bm = fmax(bm, __shfl_down(bm, off, 64));
+  }
+  if (lane == 0) {
+    col[4 * q + 0] = (float)s1;
+    col[4 * q + 1] = (float)cm;
+    col[4 * q + 2] = (float)sa;
+    col[4 * q + 3] = (float)bm;
+  }
+}
+
+// Scale bounds, stage 2 (one block): the call-level words of bnd, and the per-chunk words cleared.
+__global__ void bounds_reduce_k(int nact, const float* __restrict__ col, uint32_t* __restrict__ bnd, int nclear) {
+  __shared__ float red[4][NT / 64];
+  float v[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int q = threadIdx.x; q < nact; q += blockDim.x)
+    for (int k = 0; k < 4; ++k) v[k] = fmaxf(v[k], col[4 * q + k]);
+  for (int off = 32; off > 0; off >>= 1)
+    for (int k = 0; k < 4; ++k) v[k] = fmaxf(v[k], __shfl_down(v[k], off, 64));
+  if ((threadIdx.x & 63) == 0)
+    for (int k = 0; k < 4; ++k) red[k][threadIdx.x >> 6] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < 4; ++k)
+      for (int w = 1; w < NT / 64; ++w) red[k][0] = fmaxf(red[k][0], red[k][w]);
+    bnd[0] = __float_as_uint(red[1][0]);                 // max |C|
+    bnd[1] = __float_as_uint(red[0][0]);                 // max column 1-norm
+    bnd[2] = __float_as_uint(red[3][0] + red[2][0]);     // max |beta| + max row 1-norm of alpha
+    bnd[3] = 0u;
+  }
+  for (int i = threadIdx.x; i < nclear; i += blockDim.x) bnd[SCL_CALL + i] = 0u;
+}
+
+// Row bounds of a block of B rows (nrows rows of ncols elements, leading dimension ld): the largest
+// row 1-norm and the largest |B|, raised into slot[0], slot[1] with integer atomic maxima on the bits
+// of the non-negative floats.  One wavefront per row (grid-stride over rows).
+template <bool F64, bool VEC>
+__global__ void b_bounds_k(const void* __restrict__ B, long long nrows, int ncols, long long ld,
+                           uint32_t* __restrict__ slot) {
+  __shared__ float red[2][NT / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  float rmax = 0.f, amax = 0.f;
+  for (long long r = (long long)blockIdx.x * (NT / 64) + w; r < nrows; r += (long long)gridDim.x * (NT / 64)) {
+    float s = 0.f;
+    if constexpr (F64) {
+      const double* row = static_cast<const double*>(B) + r * ld;
+      for (int c = lane; c < ncols; c += 64) {
+        const float a = (float)fabs(row[c]);
+        s += a;
+        amax = fmaxf(amax, a);
+      }
+    } else if constexpr (VEC) {
+      const u16* row = static_cast<const u16*>(B) + r * ld;
+      for (int c = 8 * lane; c < ncols; c += 512) {
+        const uint4 v = *reinterpret_cast<const uint4*>(row + c);
+        const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const float a = fabsf(__uint_as_float(wd[k] << 16)), b = fabsf(__uint_as_float(wd[k] & 0xFFFF0000u));
+          s += a + b;
+          amax = fmaxf(amax, fmaxf(a, b));
+        }
+      }
+    } else {
+      const u16* row = static_cast<const u16*>(B) + r * ld;
+      for (int c = lane; c < ncols; c += 64) {
+        const float a = fabsf(bf16_bits_to_f32(row[c]));
+        s += a;
+        amax = fmaxf(amax, a);
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    rmax = fmaxf(rmax, __shfl(s, 0, 64));
+  }
+  for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_down(amax, off, 64));
+  if (lane == 0) {
+    red[0][w] = rmax;
+    red[1][w] = amax;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < NT / 64; ++k) {
+      red[0][0] = fmaxf(red[0][0], red[0][k]);
+      red[1][0] = fmaxf(red[1][0], red[1][k]);
+    }
+    if (red[0][0] > 0.f) atomicMax(slot, __float_as_uint(red[0][0]));
+    if (red[1][0] > 0.f) atomicMax(slot + 1, __float_as_uint(red[1][0]));
   }
 }
 
@@ -109,19 +255,35 @@ __global__ void add_diag_f64_k(int nact, int np, int ks, const double* __restric
   }
 }
 
+__global__ void add_diag_f32_k(int nact, int np, int ks, const double* __restrict__ d, float* __restrict__ W, int ldw) {
+  const long long slab = (long long)np * nact;
+  GRID_STRIDE(i, slab) {
+    const long long P = i / nact;
+    const int p = (int)(i % nact);
+    float* w = W + P * nact * ldw + (long long)p * ldw + p;
+    *w = (float)((double)*w + sum_slabs(d, ks, slab, i));
+  }
+}
+
 __global__ void add_diag_bf16_k(int nact, int np, int ks, const double* __restrict__ d, const double* __restrict__ Dc,
                                 const float* __restrict__ beta32, u16* __restrict__ Wh, u16* __restrict__ Wl, int ldw,
-                                long long pstride) {
+                                long long pstride, const uint32_t* __restrict__ bnd, int chunk) {
   const long long slab = (long long)np * nact;
+  const float sW = Wl ? chunk_scales(bnd, chunk, false).sW : 1.0f;
   GRID_STRIDE(i, slab) {
     const long long P = i / nact;
     const int p = (int)(i % nact);
     const long long o = P * pstride + (long long)p * ldw + p;
     const float wv = (float)Dc[i] * beta32[(long long)p * nact + p];
-    u16 h, l;
-    split_f64((double)wv + sum_slabs(d, ks, slab, i), h, l);
-    Wh[o] = h;
-    if (Wl) Wl[o] = l;
+    const double w = (double)wv + sum_slabs(d, ks, slab, i);
+    if (Wl) {   // split mode: the fp16 pair of W sW
+      u16 h, l;
+      split_f16((float)(w * (double)sW), h, l);
+      Wh[o] = h;
+      Wl[o] = l;
+    } else {
+      Wh[o] = f32_to_bf16_bits((float)w);
+    }
   }
 }
 
@@ -163,8 +325,9 @@ __global__ void energy_stage1_k(int nbf, int nact, const double* __restrict__ n,
                                 const double* __restrict__ alpha, const double* __restrict__ beta,
                                 const double* __restrict__ J, const double* __restrict__ K,
                                 const double* __restrict__ Y2e, const double* __restrict__ C,
-                                const u16* __restrict__ cth, const u16* __restrict__ ctl, int ldk,
-                                int corr_terms, double* __restrict__ partials) {
+                                const u16* __restrict__ cth, const u16* __restrict__ ctl,
+                                const float* __restrict__ ct32, int ldk, int corr_terms,
+                                double* __restrict__ partials) {
   const long long n2 = (long long)nact * nact;
   const long long ncorr = corr_terms > 0 ? (long long)nbf * nact : 0;
   const long long total = nact + n2 + ncorr;
@@ -177,8 +340,12 @@ __global__ void energy_stage1_k(int nbf, int nact, const double* __restrict__ n,
     else {
       const long long k = i - nact - n2;
       const int mu = (int)(k / nact), p = (int)(k % nact);
-      double ct = (double)bf16_bits_to_f32(cth[(long long)p * ldk + mu]);
-      if (corr_terms > 1) ct += (double)bf16_bits_to_f32(ctl[(long long)p * ldk + mu]);
+      double ct;
+      if (ct32) ct = (double)ct32[(long long)p * ldk + mu];
+      else {
+        ct = (double)bf16_bits_to_f32(cth[(long long)p * ldk + mu]);
+        if (corr_terms > 1) ct += (double)bf16_bits_to_f32(ctl[(long long)p * ldk + mu]);
+      }
       s += 4.0 * Y2e[k] * (C[(long long)mu * nbf + p] - ct);
     }
   }
@@ -621,20 +788,24 @@ __global__ void fock_ao_h_k(int nbf, int nq, const int32_t* __restrict__ q_idx, 
 
 // Per-orbital AO matrices from one P-chunk:  J^q += sum_P D_Pq B_P,  K^q += sum_P x_Pq x_Pq^T,
 // F^q += sum_P [d_Pq B_P + sum_r beta_qr x_Pr x_Pr^T]  with x_Pr[mu] = XT[P][r][mu].
-__device__ inline double xt_val(const double* XT, const u16* xh, const u16* xl, long long o) {
+// XT is float64, one bf16 value (terms 1), or the fp16 pair of X sX (split mode; invX = 1 / sX).
+__device__ inline double xt_val(const double* XT, const float* XT32, const u16* xh, const u16* xl, double invX,
+                                long long o) {
   if (XT) return XT[o];
-  double v = (double)bf16_bits_to_f32(xh[o]);
-  if (xl) v += (double)bf16_bits_to_f32(xl[o]);
-  return v;
+  if (XT32) return (double)XT32[o];
+  if (!xl) return (double)bf16_bits_to_f32(xh[o]);
+  return ((double)f16_bits_to_f32(xh[o]) + (double)f16_bits_to_f32(xl[o])) * invX;
 }
 
 __global__ void df_ao_accum_k(int nbf, int nact, int np, int nq, const int32_t* __restrict__ q_idx,
                               const void* __restrict__ Bc, int b_bf16, const double* __restrict__ Dc,
                               const double* __restrict__ alpha, const double* __restrict__ beta,
-                              const double* __restrict__ XT, const u16* __restrict__ xh,
+                              const double* __restrict__ XT, const float* __restrict__ XT32, const u16* __restrict__ xh,
                               const u16* __restrict__ xl, int ldx, long long xps, double* __restrict__ Jq,
-                              double* __restrict__ Kq, double* __restrict__ Fq) {
+                              double* __restrict__ Kq, double* __restrict__ Fq, const uint32_t* __restrict__ bnd,
+                              int chunk) {
   const long long n2 = (long long)nbf * nbf;
+  const double invX = xl ? (double)chunk_scales(bnd, chunk, false).invX : 1.0;
   GRID_STRIDE(i, (long long)nq * n2) {
     const int k = (int)(i / n2);
     const long long e = i % n2;
@@ -648,15 +819,15 @@ __global__ void df_ao_accum_k(int nbf, int nact, int np, int nq, const int32_t* 
       const double* Dp = Dc + (long long)P * nact;
       const long long xo = (long long)P * xps;
       sj += Dp[q] * b;
-      const double xm = xt_val(XT, xh, xl, xo + (long long)q * ldx + m);
-      const double xn = xt_val(XT, xh, xl, xo + (long long)q * ldx + nn);
+      const double xm = xt_val(XT, XT32, xh, xl, invX, xo + (long long)q * ldx + m);
+      const double xn = xt_val(XT, XT32, xh, xl, invX, xo + (long long)q * ldx + nn);
       sk += xm * xn;
       if (Fq) {
         double d = 0.0, kk = 0.0;
         for (int r = 0; r < nact; ++r) {
           d += alpha[(long long)q * nact + r] * Dp[r];
-          kk += beta[(long long)q * nact + r] * xt_val(XT, xh, xl, xo + (long long)r * ldx + m) *
-                xt_val(XT, xh, xl, xo + (long long)r * ldx + nn);
+          kk += beta[(long long)q * nact + r] * xt_val(XT, XT32, xh, xl, invX, xo + (long long)r * ldx + m) *
+                xt_val(XT, XT32, xh, xl, invX, xo + (long long)r * ldx + nn);
         }
         sf += d * b + kk;
       }
@@ -699,12 +870,40 @@ hipError_t coeffs(hipStream_t s, int nact, int npairs, int ncwo, int nsingle, in
 hipError_t transpose_ca(hipStream_t s, int nbf, int nact, const double* C, double* Ct, int ldk) {
   LAUNCH(transpose_ca_k, grid1((long long)nbf * nact), dim3(NT), nbf, nact, C, Ct, ldk);
 }
-hipError_t split_ca(hipStream_t s, int nbf, int nact, int terms, const double* C, u16* hi, u16* lo, int ldk) {
-  LAUNCH(split_ca_k, grid1((long long)nbf * nact), dim3(NT), nbf, nact, terms, C, hi, lo, ldk);
+hipError_t transpose_ca_f32(hipStream_t s, int nbf, int nact, const double* C, float* Ct, int ldk) {
+  LAUNCH(transpose_ca_f32_k, grid1((long long)nbf * nact), dim3(NT), nbf, nact, C, Ct, ldk);
 }
-hipError_t split_b(hipStream_t s, long long n, const double* B, u16* hi, u16* lo) {
+hipError_t add_diag_f32(hipStream_t s, int nact, int np, const double* Dc, const double* alpha, double* dbuf, float* W,
+                        int ldw) {
+  if (np <= 0) return hipSuccess;
+  const int ks = gemm_f64_ksplit(np, nact, nact);
+  hipError_t e = gemm_f64_splitk(s, np, nact, nact, ks, Dc, nact, 1, alpha, nact, 1, dbuf);
+  if (e != hipSuccess) return e;
+  LAUNCH(add_diag_f32_k, grid1((long long)np * nact), dim3(NT), nact, np, ks, dbuf, W, ldw);
+}
+hipError_t split_ca(hipStream_t s, int nbf, int nact, int terms, const double* C, u16* hi, u16* lo, u16* h16,
+                    u16* l16, int ldk, const uint32_t* bnd) {
+  LAUNCH(split_ca_k, grid1((long long)nbf * nact), dim3(NT), nbf, nact, terms, C, hi, lo, h16, l16, ldk, bnd);
+}
+hipError_t split_b(hipStream_t s, long long n, const double* B, u16* hi, u16* lo, const uint32_t* bnd, int chunk) {
   if (n <= 0) return hipSuccess;
-  LAUNCH(split_b_k, grid1(n), dim3(NT), n, B, hi, lo);
+  LAUNCH(split_b_k, grid1(n), dim3(NT), n, B, hi, lo, bnd, chunk);
+}
+hipError_t scale_bounds(hipStream_t s, int nbf, int nact, const double* C, const double* n, int npairs, int ncwo,
+                        int nsingle, int functional, float* col, uint32_t* bnd, int nclear) {
+  hipLaunchKernelGGL(col_bounds_k, dim3((unsigned)cdiv(nact, NT / 64)), dim3(NT), 0, s, nbf, nact, C, n, npairs, ncwo,
+                     nsingle, functional, col);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  LAUNCH(bounds_reduce_k, dim3(1), dim3(NT), nact, col, bnd, nclear);
+}
+hipError_t b_bounds(hipStream_t s, const void* B, int is_f64, long long nrows, int ncols, long long ld, uint32_t* slot) {
+  if (nrows <= 0) return hipSuccess;
+  const dim3 g((unsigned)std::min<long long>(cdiv(nrows, NT / 64), 2048));
+  const bool vec = !is_f64 && (ld % 8 == 0) && ((reinterpret_cast<uintptr_t>(B) & 15) == 0);
+  if (is_f64) LAUNCH((b_bounds_k<true, false>), g, dim3(NT), B, nrows, ncols, ld, slot);
+  if (vec) LAUNCH((b_bounds_k<false, true>), g, dim3(NT), B, nrows, ncols, ld, slot);
+  LAUNCH((b_bounds_k<false, false>), g, dim3(NT), B, nrows, ncols, ld, slot);
 }
 hipError_t hpp_from_hc(hipStream_t s, int nbf, int nact, const double* C, const double* HC, double* Hpp) {
   LAUNCH(hpp_k, dim3(nact), dim3(64), nbf, nact, C, HC, Hpp);
@@ -718,12 +917,13 @@ hipError_t add_diag_f64(hipStream_t s, int nact, int np, const double* Dc, const
   LAUNCH(add_diag_f64_k, grid1((long long)np * nact), dim3(NT), nact, np, ks, dbuf, W, ldw);
 }
 hipError_t add_diag_bf16(hipStream_t s, int nact, int np, const double* Dc, const double* alpha, const float* beta32,
-                         double* dbuf, u16* Wh, u16* Wl, int ldw, long long pstride) {
+                         double* dbuf, u16* Wh, u16* Wl, int ldw, long long pstride, const uint32_t* bnd, int chunk) {
   if (np <= 0) return hipSuccess;
   const int ks = gemm_f64_ksplit(np, nact, nact);
   hipError_t e = gemm_f64_splitk(s, np, nact, nact, ks, Dc, nact, 1, alpha, nact, 1, dbuf);
   if (e != hipSuccess) return e;
-  LAUNCH(add_diag_bf16_k, grid1((long long)np * nact), dim3(NT), nact, np, ks, dbuf, Dc, beta32, Wh, Wl, ldw, pstride);
+  LAUNCH(add_diag_bf16_k, grid1((long long)np * nact), dim3(NT), nact, np, ks, dbuf, Dc, beta32, Wh, Wl, ldw, pstride,
+         bnd, chunk);
 }
 hipError_t nofmp2_terms(hipStream_t s, int nact, int npairs, int ncwo, int nsingle, const double* n,
                         const double* Hpp, const double* J, const double* K, double* partials, double* E_hf,
@@ -748,11 +948,11 @@ hipError_t reduce_y_f32(hipStream_t s, long long n, int nsplit, const float* Yp,
 }
 hipError_t energy(hipStream_t s, int nbf, int nact, const double* n, const double* Hpp,
                   const double* alpha, const double* beta, const double* J, const double* K,
-                  const double* Y2e, const double* C, const u16* cth, const u16* ctl, int ldk,
+                  const double* Y2e, const double* C, const u16* cth, const u16* ctl, const float* ct32, int ldk,
                   int corr_terms, double* partials, double* E) {
   const int nb = 256;
   hipLaunchKernelGGL(energy_stage1_k, dim3(nb), dim3(NT), 0, s, nbf, nact, n, Hpp, alpha, beta, J, K, Y2e,
-                     C, cth, ctl, ldk, corr_terms, partials);
+                     C, cth, ctl, ct32, ldk, corr_terms, partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   LAUNCH(sum_partials_k, dim3(1), dim3(NT), nb, partials, E);
@@ -821,11 +1021,11 @@ hipError_t eri_fock_ao(hipStream_t s, int nbf, int nact, int nq, const int32_t* 
 }
 hipError_t df_ao_accum(hipStream_t s, int nbf, int nact, int np, int nq, const int32_t* q_idx,
                        const void* Bchunk, int b_is_bf16, const double* Dchunk, const double* alpha,
-                       const double* beta, const double* XT, const u16* XT_hi, const u16* XT_lo, int ldx,
-                       long long xps, double* Jq, double* Kq, double* Fq) {
+                       const double* beta, const double* XT, const float* XT32, const u16* XT_hi, const u16* XT_lo,
+                       int ldx, long long xps, double* Jq, double* Kq, double* Fq, const uint32_t* bnd, int chunk) {
   if (nq <= 0 || np <= 0) return hipSuccess;
   LAUNCH(df_ao_accum_k, grid1((long long)nq * nbf * nbf), dim3(NT), nbf, nact, np, nq, q_idx, Bchunk,
-         b_is_bf16, Dchunk, alpha, beta, XT, XT_hi, XT_lo, ldx, xps, Jq, Kq, Fq);
+         b_is_bf16, Dchunk, alpha, beta, XT, XT32, XT_hi, XT_lo, ldx, xps, Jq, Kq, Fq, bnd, chunk);
 }
 hipError_t fock_ao_h(hipStream_t s, int nbf, int nq, const int32_t* q_idx, const double* n, const double* H,
                      double* Fq) {

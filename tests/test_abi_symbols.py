@@ -63,7 +63,9 @@ def _check(lib, **kw):
     ({"npairs": 11}, 2),                       # 11 * 4 > 40
     ({"ncwo": 0}, 2),
     ({"functional": 6}, 1),
-    ({"precision": 1}, 1),
+    ({"precision": P.FP32}, 0),
+    ({"precision": P.FP32, "ints": P.INTS_DF_BF16}, 0),
+    ({"precision": 4}, 1),
     ({"ints": 9}, 1),
     ({"flags": 4}, 1),
     ({"naux": 0}, 2),                          # density fitting needs naux > 0
@@ -71,6 +73,7 @@ def _check(lib, **kw):
     ({"ints": P.INTS_ERI4_F64, "naux": 8}, 2),
     ({"ints": P.INTS_ERI4_F64, "naux": 0, "nbf": 65, "npairs": 4}, 2),
     ({"ints": P.INTS_ERI4_F64, "naux": 0, "precision": P.BF16_SPLIT}, 3),
+    ({"ints": P.INTS_ERI4_F64, "naux": 0, "precision": P.FP32}, 3),
 ])
 def test_check_problem(lib, kw, status):
     st, msg = _check(lib, **kw)

@@ -57,9 +57,7 @@ def test_lagrangian_with_singles_matches_oracle(ctx, func, prec, bdt):
         assert np.max(np.abs(out["dEdn"].cpu().numpy() - r["dEdn"])) < 1e-9
         assert np.max(np.abs(out["dEdC"].cpu().numpy() - r["dEdC"])) < 1e-9
     else:
-        alpha, beta = pnof.coefficients(n, npairs, ncwo, func, ns)
-        T = np.sqrt(np.sum((alpha * r["J"]) ** 2) + np.sum((beta * r["K"]) ** 2))
-        assert abs(E - r["E"]) < max(1e-6, 2.0 ** -17 * T)
+        assert abs(E - r["E"]) < 1e-6
         assert np.max(np.abs(out["lam"].cpu().numpy() - r["lam"])) < 2e-5
         assert np.max(np.abs(out["dEdC"].cpu().numpy() - r["dEdC"])) < 1e-4
 
@@ -137,8 +135,6 @@ def test_batch_with_singles(ctx):
     batch.run(graph=True)
     torch.cuda.synchronize()
     for o, (r, n, npairs, ncwo, ns) in zip(outs, refs):
-        alpha, beta = pnof.coefficients(n, npairs, ncwo, P.PNOF7, ns)
-        T = np.sqrt(np.sum((alpha * r["J"]) ** 2) + np.sum((beta * r["K"]) ** 2))
-        assert abs(o["E"].item() - r["E"]) < max(1e-6, 2.0 ** -17 * T)
+        assert abs(o["E"].item() - r["E"]) < 1e-6
         assert np.max(np.abs(o["lam"].cpu().numpy() - r["lam"])) < 2e-5
         assert np.max(np.abs(o["dEdn"].cpu().numpy() - r["dEdn"])) < 2e-5

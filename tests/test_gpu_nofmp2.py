@@ -1,7 +1,9 @@
 """NOF-MP2 reference terms (pnof_nofmp2_terms, Eqs. HFL and Esta) through the C ABI against the
-oracle.  Float64: 1e-10 Ha.  bf16 split: these sums of J and K carry no first-order correction
-for the split orbitals (unlike the energy), so the bound is the split's unit roundoff times the
-root-sum-square of their terms, 2^-17 sqrt(sum (2J - K)^2 + K^2), or 1e-6 Ha if larger."""
+oracle.  Float64: 1e-10 Ha.  bf16 split: E_hf and E_sta are plain sums of J and K, which carry the
+2^-17 rounding of the split orbitals C~ to first order (the energy removes that term with its
+first-order correction 4 <Y, C - C~>; these sums have no Fock vectors of their own to do the same),
+so the bound is 2^-17 times the root-sum-square of their terms, sqrt(sum (2J - K)^2 + K^2), or
+1e-6 Ha if larger."""
 import numpy as np
 import pytest
 import torch
@@ -45,6 +47,7 @@ def test_nofmp2_terms_match_oracle(ctx, name, prec, kind, tol):
     if tol is None:
         g = wl.npairs
         tol = max(1e-6, 2.0 ** -17 * np.sqrt(np.sum((2 * J[:g, :g] - K[:g, :g]) ** 2) + np.sum(K ** 2)))
+    print(f"{name} prec={prec}: dE_hf={abs(e_hf.item() - r_hf):.2e} dE_sta={abs(e_sta.item() - r_sta):.2e} tol={tol:.1e}")
     assert abs(e_hf.item() - r_hf) < tol
     assert abs(e_sta.item() - r_sta) < tol
 
