@@ -21,7 +21,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"bf16": 2.5e15, "f64": 78.6e12}
+PEAK = {"bf16": 2.5e15, "f64": 78.6e12, "f32": 157.3e12}   # dense matrix-core peaks (bf16 = fp16)
 KSRC = os.path.join(ROOT, "paper_2004_06142_amd", "csrc")
 # HBM bytes per launch from the FETCH_SIZE and WRITE_SIZE counter runs (profiles/), each scaled by the
 # factor a plain 1 GiB elementwise copy gives, and the SHA-256 of the kernel source they were taken on:
@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c5_df1200")
-    ap.add_argument("--precision", default="bf16split", choices=["bf16split", "fp64", "bf16"])
+    ap.add_argument("--precision", default="bf16split", choices=["bf16split", "fp64", "fp32", "bf16"])
     ap.add_argument("--fp64-steps", type=int, default=1, help="steps of the float64 path for the speedup (0: skip)")
     ap.add_argument("--cpu-rows", type=int, default=1024, help="rows of B in the oracle's timed sample (0: skip)")
     ap.add_argument("--pchunk", type=int, default=0)
@@ -56,6 +56,9 @@ def parse():
                     help="timed replays of the 64-instance PES-scan batch (0: skip that measurement)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a plain device-to-device copy of this many MiB (reference for traffic counters)")
+    ap.add_argument("--cpu-protocol", action="store_true",
+                    help="instead of the benchmark: the host DGEMM rate and the float64 oracle timed on the host "
+                         "cores (all threads and one thread) at C2 and C3, and over every row of B at C5")
     return ap.parse_args()
 
 
@@ -95,6 +98,9 @@ def main():
     import synth.device as sdev
 
     dev = torch.device("cuda", 0)
+    if args.cpu_protocol:
+        print(json.dumps(cpu_protocol()), flush=True)
+        return
     if args.copy_calibration:
         # one elementwise kernel that reads and writes exactly MIB MiB each (calibrates the HBM counters)
         src = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device=dev)
@@ -105,7 +111,7 @@ def main():
         del src, dst
     wl = synth.WORKLOADS[args.workload]
     inst = synth.workload(args.workload, with_b=False)
-    prec = {"bf16split": P.BF16_SPLIT, "fp64": P.FP64, "bf16": P.BF16}[args.precision]
+    prec = {"bf16split": P.BF16_SPLIT, "fp64": P.FP64, "fp32": P.FP32, "bf16": P.BF16}[args.precision]
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     C0, H, gamma = t(inst.C), t(inst.H), t(inst.gamma)
     bdt = torch.bfloat16 if wl.b_dtype == "bf16" else torch.float64
@@ -150,7 +156,7 @@ def main():
     print(f"[bench] {ms:.1f} ms/step, E = {E:.10f}, stages {prof}", file=sys.stderr, flush=True)
 
     # dominant contraction kernel and its roofline
-    dtype_key = "f64" if prec == P.FP64 else "bf16"
+    dtype_key = {P.FP64: "f64", P.FP32: "f32"}.get(prec, "bf16")
     stage = max(("X", "b", "Y"), key=lambda s: prof[s][0])
     st_ms, st_n = prof[stage]
     flops = stage_flops(wl, stage) * args.steps
@@ -168,7 +174,8 @@ def main():
         "metric": "PNOF7 energy+grad iterations/sec", "value": args.steps / dt, "unit": "iters/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": {"bf16split": "bf16x3+f32acc+f64", "fp64": "f64", "bf16": "bf16+f32acc"}[args.precision],
+        "dtype": {"bf16split": "bf16+f16 (f32 acc, f64 sums)", "fp64": "f64", "fp32": "f32",
+                  "bf16": "bf16 (f32 acc)"}[args.precision],
         "data": "synthetic",
         "config": {"workload": wl.name, "nbf": wl.nbf, "naux": wl.naux, "npairs": wl.npairs, "ncwo": wl.ncwo,
                    "nact": wl.nact, "functional": "PNOF7", "B": wl.b_dtype, "seed": synth.seed_of(wl.name)},
@@ -310,6 +317,88 @@ def cpu_baseline(wl, inst, rows):
             "sample": f"streamed FP64 oracle over {rows} of {wl.naux} B rows ({t_rows:.1f} s), per-row cost scaled "
                       f"to all rows, plus its fixed part ({t_fixed:.1f} s) and orbital step ({t_orb:.1f} s)",
             "seconds_per_iter_est": s_iter}
+
+
+def cpu_protocol():
+    """The float64 oracle on the host cores: DGEMM rate, then one energy + lambda + gradient step (+ the
+    orbital step's eigensolver) per configuration, timed with every OpenBLAS thread and with one.  B
+    is drawn before the clock starts (at C5 on the device, 96 rows at a time, widened to float64 and
+    copied to the host; only the oracle's work on each chunk is timed, every row of B is used)."""
+    import numpy as np
+    import torch
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    import synth
+    import synth.device as sdev
+    from oracle import pnof, stream
+
+    nthr = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("internal_api") == "openblas"] or [1])
+    res = {"host_threads": nthr, "cpu_count": os.cpu_count()}
+
+    def dgemm_rate(n=4096, reps=3):
+        a = np.random.default_rng(0).standard_normal((n, n))
+        b = a.T.copy()
+        a @ b
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            a @ b
+            ts.append(time.perf_counter() - t0)
+        return 2.0 * n ** 3 / min(ts) / 1e9
+
+    res["dgemm_gflops"] = dgemm_rate()
+    with threadpool_limits(1, user_api="blas"):
+        res["dgemm_gflops_1thread"] = dgemm_rate(2048)
+
+    def step(inst, n, B, naux):
+        t0 = time.perf_counter()
+        r = stream.lagrangian(inst.C, n, inst.H, B, inst.wl.npairs, inst.wl.ncwo, pnof.PNOF7, naux=naux)
+        pnof.orbital_step(r["lam"], inst.C)
+        return time.perf_counter() - t0
+
+    for name, reps in (("c2_df200", 5), ("c3_df500", 1)):
+        inst = synth.workload(name, with_b=False)
+        w = inst.wl
+        bdt = torch.bfloat16 if w.b_dtype == "bf16" else torch.float64
+        B = sdev.make_b(inst.key, w.nbf, w.naux, dtype=bdt, device=torch.device("cuda", 0)).to(torch.float64).cpu().numpy()
+        n = pnof.on_sigmoid(inst.gamma, w.npairs, w.ncwo)
+        ent = {"seconds_all_threads": float(np.median([step(inst, n, B, None) for _ in range(reps)]))}
+        with threadpool_limits(1, user_api="blas"):
+            ent["seconds_1thread"] = step(inst, n, B, None)
+        del B
+        ent["runs"] = reps
+        res[name] = ent
+        del inst
+        print(f"[cpu] {name}: {ent}", file=sys.stderr, flush=True)
+
+    wl = synth.WORKLOADS["c5_df1200"]
+    inst = synth.workload("c5_df1200", with_b=False)
+    n = pnof.on_sigmoid(inst.gamma, wl.npairs, wl.ncwo)
+    rows = 96
+    dev = torch.device("cuda", 0)
+    buf = torch.empty((rows, wl.nbf, wl.nbf), dtype=torch.bfloat16, device=dev)
+    gen = [0.0]
+
+    def chunk(p0, p1):
+        # drawing the rows and moving them to the host is not the oracle's work: its time is subtracted
+        t0 = time.perf_counter()
+        sdev.fill_b(buf[:p1 - p0], inst.key, wl.nbf, wl.naux, p0)
+        host = buf[:p1 - p0].to(torch.float64).cpu().numpy()
+        gen[0] += time.perf_counter() - t0
+        return host
+
+    t0 = time.perf_counter()
+    r = stream.lagrangian(inst.C, n, inst.H, chunk, wl.npairs, wl.ncwo, pnof.PNOF7, naux=wl.naux, pchunk=rows)
+    t_wall = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    pnof.orbital_step(r["lam"], inst.C)
+    t_orb = time.perf_counter() - t1
+    t_total = t_wall - gen[0]
+    res["c5_df1200"] = {"seconds_lagrangian": t_total, "seconds_orbital_step": t_orb,
+                        "seconds_per_iter": t_total + t_orb, "rows": wl.naux, "chunk_rows": rows,
+                        "seconds_drawing_rows": gen[0]}
+    print(f"[cpu] c5_df1200: {res['c5_df1200']}", file=sys.stderr, flush=True)
+    return res
 
 
 if __name__ == "__main__":

@@ -31,9 +31,8 @@
  *   - Calls are asynchronous on the context's HIP stream; outputs are valid after that stream is
  *     synchronised.  Scalar outputs (E, max_asym) are device scalars.  Some steps also run on a
  *     second stream owned by the context (default priority): the orbital step's product of
- *     reflectors, and in the bf16 density-fitted calls the row bounds of each next chunk of B (split
- *     mode) and, when the Fock vectors are formed, the per-chunk D alpha, W diagonal and Y
- *     reduction.  That stream waits on an event recorded on the context's
+ *     reflectors, and in the bf16-split density-fitted calls that form the Fock vectors the per-chunk
+ *     D alpha, W diagonal and Y reduction.  That stream waits on an event recorded on the context's
  *     stream before its first use in a call, and the context's stream waits on its last event before
  *     the call's remaining work, so stream order as seen by the caller is unchanged.
  *   - Errors: arguments, shapes and enums are validated on the host before anything is enqueued;

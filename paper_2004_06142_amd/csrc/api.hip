@@ -30,7 +30,7 @@ struct pnof_ctx_s {
   // with events; created on first use
   hipStream_t aux = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
-  hipEvent_t pipe_ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};   // chunk pipeline of the split path
+  hipEvent_t pipe_ev[4] = {nullptr, nullptr, nullptr, nullptr};   // chunk pipeline of the split path
   // measurement: launches of the contraction kernels bracketed by events on the stream
   bool profiling = false;
   struct Ev { int stage; hipEvent_t a, b; };
@@ -378,15 +378,44 @@ struct Req {
   int nq = 0;
   bool need_y = false;   // Fock vectors (and everything built from them)
   bool need_e = false;
+  // a workspace given by the call (the pchunk is lowered until the plan fits; nothing is allocated),
+  // the library's own float64 GEMM instead of rocBLAS, and every step on the context's stream
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool own_gemm = false;
+  bool one_stream = false;
 };
+
+// Float64 product C = A B with the strided views of gemm_f64, on rocBLAS or the library's kernel.
+pnof_status dprod(pnof_ctx ctx, bool own, int M, int N, int K, const double* A, long long sam, long long sak,
+                  const double* B, long long sbk, long long sbn, double* C, long long scm, long long scn) {
+  if (!own) return rb_dgemm(ctx, M, N, K, 1.0, A, sam, sak, B, sbk, sbn, 0.0, C, scm, scn);
+  DEV_CHECK(ctx, gemm_f64(ctx->stream, M, N, K, 1, 1.0, A, sam, sak, 0, B, sbk, sbn, 0, 0.0, C, scm, scn, 0));
+  return PNOF_OK;
+}
 
 pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, const double* n,
                      const double* H, const void* ints, Req& r) {
-  const Plan pl = make_plan(prob, ctx->tune);
+  Plan pl = make_plan(prob, ctx->tune);
   Bufs b = carve(pl, nullptr);
   char* ws = nullptr;
-  pnof_status st = get_ws(ctx, b.bytes, &ws);
-  if (st != PNOF_OK) return st;
+  pnof_status st = PNOF_OK;
+  if (r.ws) {
+    // fit the caller's region: fewer rows of B per chunk until the plan's workspace fits
+    pnof_tuning tu = ctx->tune;
+    while (b.bytes > r.ws_bytes && pl.pc > 1) {
+      tu.pchunk = std::max(1, pl.pc / 2);
+      pl = make_plan(prob, tu);
+      b = carve(pl, nullptr);
+    }
+    if (b.bytes > r.ws_bytes)
+      return fail(ctx, PNOF_E_UNSUPPORTED,
+                  "the problem needs " + std::to_string(b.bytes) + " bytes of workspace, more than the " +
+                      std::to_string(r.ws_bytes) + " available");
+    ws = r.ws;
+  } else if ((st = get_ws(ctx, b.bytes, &ws)) != PNOF_OK) {
+    return st;
+  }
   b = carve(pl, ws);
   hipStream_t s = ctx->stream;
   const int nbf = pl.nbf, nact = pl.nact;
@@ -411,7 +440,7 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
   if (have_n) DEV_CHECK(ctx, coeffs(s, nact, pl.npairs, pl.ncwo, pl.nsingle, pl.functional, n, b.alpha, b.beta, b.beta32));
   if (H) {
     // HC = H C_A ; Hpp = diag(C_A^T H C_A)
-    RB_CHECK(rb_dgemm(ctx, nbf, nact, nbf, 1.0, H, nbf, 1, C, nbf, 1, 0.0, b.HC, nact, 1));
+    RB_CHECK(dprod(ctx, r.own_gemm, nbf, nact, nbf, H, nbf, 1, C, nbf, 1, b.HC, nact, 1));
     DEV_CHECK(ctx, hpp_from_hc(s, nbf, nact, C, b.HC, b.Hpp));
     if (r.Hpp) DEV_CHECK(ctx, hipMemcpyAsync(r.Hpp, b.Hpp, sizeof(double) * nact, hipMemcpyDeviceToDevice, s));
   }
@@ -506,11 +535,10 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
       }
     } else {
       // Chunk pipeline: X of chunk c + 1 runs between b and Y of chunk c (XT is double-buffered,
-      // chunk c in buffer c & 1), while the context's second stream forms the row bounds of chunk
-      // c + 1's B beside b(c), chunk c's D alpha and W diagonal beside X(c + 1), and reduces the Y
-      // partials of chunk c beside b and X of the next chunks.  Events order the two streams: the
-      // row bounds of a chunk before its X; W's diagonal before Y(c); the reduction of Y(c - 1) before
-      // Y(c) overwrites the partials; the last reduction before Y2e is read.  W itself is
+      // chunk c in buffer c & 1), while the context's second stream forms chunk c's D alpha and W
+      // diagonal beside X(c + 1), and reduces the Y partials of chunk c beside b and X of the next
+      // chunks.  Events order the two streams: W's diagonal before Y(c); the reduction of Y(c - 1)
+      // before Y(c) overwrites the partials; the last reduction before Y2e is read.  W itself is
       // single-buffered: Y(c) precedes b(c + 1) on the main stream.  Whatever path leaves this scope,
       // the main stream waits for the second one.
       const int nchunk = (int)cdiv(pl.naux, pl.pc);
@@ -519,21 +547,18 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
       SplitPtr C16{split ? b.ch16 : b.cth, split ? b.cl16 : nullptr};   // b (and X from float64 B)
       u16* const xth_[2] = {b.xth, b.xth2};
       u16* const xtl_[2] = {b.xtl, b.xtl2};
-      RB_CHECK(ensure_aux(ctx));
+      // one_stream: the second stream's work runs in order on the context's stream
+      const bool two = !r.one_stream;
+      if (two) RB_CHECK(ensure_aux(ctx));
       AuxJoin join(ctx);
-      hipStream_t sa = ctx->aux;
-      hipEvent_t ev_b = ctx->pipe_ev[0], ev_d = ctx->pipe_ev[1], ev_y = ctx->pipe_ev[2], ev_r = ctx->pipe_ev[3],
-                 ev_x = ctx->pipe_ev[4], ev_pre = ctx->pipe_ev[5];
+      hipStream_t sa = two ? ctx->aux : s;
+      hipEvent_t ev_b = ctx->pipe_ev[0], ev_d = ctx->pipe_ev[1], ev_y = ctx->pipe_ev[2], ev_r = ctx->pipe_ev[3];
       auto chunk_rows = [&](int c) { return (int)std::min<long long>(pl.pc, pl.naux - (long long)c * pl.pc); };
-      auto bounds = [&](hipStream_t st, int c) -> pnof_status {
-        const long long p0 = (long long)c * pl.pc;
-        const void* Bc = pl.ints == PNOF_INTS_DF_BF16
-                             ? static_cast<const void*>(static_cast<const u16*>(ints) + p0 * bsz)
-                             : static_cast<const void*>(static_cast<const double*>(ints) + p0 * bsz);
-        DEV_CHECK(ctx, b_bounds(st, Bc, pl.ints == PNOF_INTS_DF_F64, (long long)chunk_rows(c) * nbf, nbf, nbf,
-                                b.bnd + SCL_CALL + 2 * c));
-        return PNOF_OK;
-      };
+      // row bounds of every chunk of B in one pass before the first X (beside the contractions it
+      // would take their compute units: measured slower)
+      if (split)
+        DEV_CHECK(ctx, b_bounds(s, ints, pl.ints == PNOF_INTS_DF_F64, (long long)pl.naux * nbf, nbf, nbf,
+                                (long long)pl.pc * nbf, b.bnd + SCL_CALL));
       auto run_x = [&](int c) -> pnof_status {
         const long long p0 = (long long)c * pl.pc;
         const int np = chunk_rows(c);
@@ -556,7 +581,6 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
                                                                xth_[c & 1], xtl_[c & 1], pl.ldx, pl.xv, wd, b.bnd, c)));
         return PNOF_OK;
       };
-      if (split) RB_CHECK(bounds(s, 0));
       RB_CHECK(run_x(0));
       for (int c = 0; c < nchunk; ++c) {
         const int p0 = c * pl.pc;
@@ -564,37 +588,33 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
         const int ns2 = std::min(pl.ns2, np), ns3 = std::min(pl.ns3, np);
         double* Dc = b.D + (long long)p0 * nact;
         SplitPtr XT{xth_[c & 1], split ? xtl_[c & 1] : nullptr};
-        if (split && c + 1 < nchunk) {
-          DEV_CHECK(ctx, hipEventRecord(ev_x, s));
-          DEV_CHECK(ctx, hipStreamWaitEvent(sa, ev_x, 0));
-          join.forked = true;
-          RB_CHECK(bounds(sa, c + 1));
-          DEV_CHECK(ctx, hipEventRecord(ev_pre, sa));
-        }
         DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_B, df_bf16_gemm2(s, nbf, nact, np, ns2, pl.terms, C16, pl.ldk, XT, pl.ldx,
                                                                b.beta32, b.Kpart, Dc, b.wh, b.wl, pl.ldw, wd, b.bnd, c)));
         if (want_y) {
-          DEV_CHECK(ctx, hipEventRecord(ev_b, s));
-          DEV_CHECK(ctx, hipStreamWaitEvent(sa, ev_b, 0));
-          join.forked = true;
+          if (two) {
+            DEV_CHECK(ctx, hipEventRecord(ev_b, s));
+            DEV_CHECK(ctx, hipStreamWaitEvent(sa, ev_b, 0));
+            join.forked = true;
+          }
           DEV_CHECK(ctx, add_diag_bf16(sa, nact, np, Dc, b.alpha, b.beta32, b.dbuf, b.wh, b.wl, pl.ldw,
                                        (long long)pl.nact32 * pl.ldw, b.bnd, c));
-          DEV_CHECK(ctx, hipEventRecord(ev_d, sa));
+          if (two) DEV_CHECK(ctx, hipEventRecord(ev_d, sa));
         }
-        if (c + 1 < nchunk) {
-          if (split) DEV_CHECK(ctx, hipStreamWaitEvent(s, ev_pre, 0));
-          RB_CHECK(run_x(c + 1));
-        }
+        if (c + 1 < nchunk) RB_CHECK(run_x(c + 1));
         if (want_y) {
-          DEV_CHECK(ctx, hipStreamWaitEvent(s, ev_d, 0));
-          if (c > 0) DEV_CHECK(ctx, hipStreamWaitEvent(s, ev_r, 0));
+          if (two) {
+            DEV_CHECK(ctx, hipStreamWaitEvent(s, ev_d, 0));
+            if (c > 0) DEV_CHECK(ctx, hipStreamWaitEvent(s, ev_r, 0));
+          }
           SplitPtr W{b.wh, b.wl};
           DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_Y, df_bf16_gemm3(s, nbf, nact, np, ns3, pl.terms, XT, pl.ldx, W, pl.ldw,
                                                                  b.Ypart32, pl.yv, wd, b.bnd, c)));
-          DEV_CHECK(ctx, hipEventRecord(ev_y, s));
-          DEV_CHECK(ctx, hipStreamWaitEvent(sa, ev_y, 0));
+          if (two) {
+            DEV_CHECK(ctx, hipEventRecord(ev_y, s));
+            DEV_CHECK(ctx, hipStreamWaitEvent(sa, ev_y, 0));
+          }
           DEV_CHECK(ctx, reduce_y_f32(sa, ny, ns3, b.Ypart32, b.Y2e));
-          DEV_CHECK(ctx, hipEventRecord(ev_r, sa));
+          if (two) DEV_CHECK(ctx, hipEventRecord(ev_r, sa));
         }
         if (r.Jq || r.Kq || r.Fq) {
           const void* Bsrc = pl.ints == PNOF_INTS_DF_BF16
@@ -605,7 +625,7 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
                                      r.Kq, r.Fq, b.bnd, c));
         }
       }
-      if (want_y) DEV_CHECK(ctx, hipStreamWaitEvent(s, ev_r, 0));
+      if (want_y && two) DEV_CHECK(ctx, hipStreamWaitEvent(s, ev_r, 0));
     }
     DEV_CHECK(ctx, reduce_k(s, nact, pl.ns2, b.Kpart, K));
     // J = D^T D
@@ -620,7 +640,7 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
   }
   if (want_y) DEV_CHECK(ctx, assemble_y(s, nbf, nact, n, b.HC, b.Y2e, Y));
   if (r.lam) {
-    RB_CHECK(rb_dgemm(ctx, nbf, nact, nbf, 1.0, C, 1, nbf, Y, nact, 1, 0.0, r.lam, nbf, 1));
+    RB_CHECK(dprod(ctx, r.own_gemm, nbf, nact, nbf, C, 1, nbf, Y, nact, 1, r.lam, nbf, 1));
     DEV_CHECK(ctx, zero_cols(s, nbf, nact, r.lam));
     if (r.asym) DEV_CHECK(ctx, max_asym(s, nbf, r.lam, b.partials + 256, r.asym));
   }

@@ -142,12 +142,16 @@ __device__ __forceinline__ void split_f16(float xs, u16& hi, u16& lo) {
   hi = f32_to_f16_bits(xs);
   lo = f32_to_f16_bits(xs - f16_bits_to_f32(hi));
 }
-// Two values at once, as packed pairs (first value in the low half).
+// Two values at once, as packed pairs (first value in the low half): two packed conversions
+// (v_cvt_pk_f16_f32), two widenings and two subtractions.
 __device__ __forceinline__ void split2_f16(float a, float b, uint32_t& hi, uint32_t& lo) {
-  const u16 ha = f32_to_f16_bits(a), hb = f32_to_f16_bits(b);
-  const u16 la = f32_to_f16_bits(a - f16_bits_to_f32(ha)), lb = f32_to_f16_bits(b - f16_bits_to_f32(hb));
-  hi = (uint32_t)ha | ((uint32_t)hb << 16);
-  lo = (uint32_t)la | ((uint32_t)lb << 16);
+  typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  const f2 x = {a, b};
+  const h2 h = __builtin_convertvector(x, h2);
+  const h2 l = __builtin_convertvector(x - __builtin_convertvector(h, f2), h2);
+  hi = __builtin_bit_cast(uint32_t, h);
+  lo = __builtin_bit_cast(uint32_t, l);
 }
 
 // Exponent e with bound < 2^e (0 for a zero or non-finite bound), clamped to [-60, 60].
@@ -421,8 +425,10 @@ hipError_t split_b(hipStream_t s, long long n, const double* B, u16* hi, u16* lo
 // the nclear per-chunk words after them cleared.
 hipError_t scale_bounds(hipStream_t s, int nbf, int nact, const double* C, const double* n, int npairs, int ncwo,
                         int nsingle, int functional, float* col, uint32_t* bnd, int nclear);
-// Largest row 1-norm and largest |B| of nrows rows (ncols used of ld) raised into slot[0], slot[1].
-hipError_t b_bounds(hipStream_t s, const void* B, int is_f64, long long nrows, int ncols, long long ld, uint32_t* slot);
+// Per chunk of rows_per_chunk rows of B (nrows rows, ncols used of ld): the largest row 1-norm and the
+// largest |B|, raised into slot[2c], slot[2c + 1] (the words must start at zero).
+hipError_t b_bounds(hipStream_t s, const void* B, int is_f64, long long nrows, int ncols, long long ld,
+                    long long rows_per_chunk, uint32_t* slot);
 hipError_t widen_bf16(hipStream_t s, long long n, const u16* src, double* dst);
 hipError_t hpp_from_hc(hipStream_t s, int nbf, int nact, const double* C, const double* HC, double* Hpp);
 // Split-K float64 product for few output tiles: ks (<= F64_KSPLIT_MAX) dense M x N partial slabs in

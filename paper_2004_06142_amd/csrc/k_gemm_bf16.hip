@@ -743,7 +743,9 @@ __device__ __forceinline__ void gemm2_body(int w, const G2Args& g) {
 
 // gemm3: Ypart[s][mu][q] = sum_{P in s} sum_r XT_P[r][mu] W_P[q][r].  XT is read as a col operand,
 // W (stored in full) as a row operand; every block walks (P, r) in the same order, so blocks of one
-// split that share an operand panel read it at about the same time.
+// split that share an operand panel read it at about the same time.  Split mode: 3 fp16 products
+// (2 products, dropping X_lo W_hi at about 2^-12 relative, left lambda 2.2e-5 from the exact values on
+// a 77-function edge shape).
 // Tile G3M (mu) x G3N (q), waves in a WGM x WGN grid.  Each wave's share of the tile sets how many
 // matrix-core products one byte read from LDS feeds: a 64 x 64 wave reads 16 KB per k-tile for 48
 // products, a 128 x 64 wave 24 KB for 96; LDS bandwidth (about 128 bytes per clock per compute unit)
@@ -775,8 +777,8 @@ __device__ __forceinline__ void gemm3_body(int w, const G3Args& g) {
       const long long off = (long long)(pb + seg) * g.ws.nact32 * ldw;
       return DOpnd{g.w_hi + off, LO ? g.w_lo + off : nullptr, ldw, g.ws.w_bytes - 2 * off};
     };
-    mainloop_dl<G3M, G3N, LO, LO, S, true, false, false, LO, WGM, WGN, (WGM * WGN == 8)>(sm, pe - pb, 0, nact, m0, n0, A, B,
-                                                                                      acc, none);
+    mainloop_dl<G3M, G3N, LO, LO, S, true, false, false, LO, WGM, WGN, (WGM * WGN == 8)>(sm, pe - pb, 0, nact, m0, n0,
+                                                                                       A, B, acc, none);
   } else {
     static_assert(VEC || (WGM == 2 && WGN == 2), "register-staged path: 2 x 2 waves");
     __shared__ Stage<G3M, G3N, LO, LO> sm;

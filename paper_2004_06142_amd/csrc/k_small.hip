@@ -169,23 +169,41 @@ __global__ void bounds_reduce_k(int nact, const float* __restrict__ col, uint32_
   for (int i = threadIdx.x; i < nclear; i += blockDim.x) bnd[SCL_CALL + i] = 0u;
 }
 
-// Row bounds of a block of B rows (nrows rows of ncols elements, leading dimension ld): the largest
-// row 1-norm and the largest |B|, raised into slot[0], slot[1] with integer atomic maxima on the bits
-// of the non-negative floats.  One wavefront per row (grid-stride over rows).
+// Row bounds of B (nrows rows of ncols elements, leading dimension ld): for every chunk of
+// rows_per_chunk consecutive rows, the largest row 1-norm and the largest |B|, raised into
+// slot[2c], slot[2c + 1] with integer atomic maxima on the bits of the non-negative floats.  One
+// wavefront per row; each wavefront walks a contiguous range of rows and raises a chunk's words when
+// it leaves that chunk.
 template <bool F64, bool VEC>
 __global__ void b_bounds_k(const void* __restrict__ B, long long nrows, int ncols, long long ld,
-                           uint32_t* __restrict__ slot) {
-  __shared__ float red[2][NT / 64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+                           long long rows_per_chunk, uint32_t* __restrict__ slot) {
+  const int lane = threadIdx.x & 63;
+  const long long nw = (long long)gridDim.x * (blockDim.x >> 6);
+  const long long w = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const long long per = (nrows + nw - 1) / nw;
+  const long long r0 = w * per, r1 = r0 + per < nrows ? r0 + per : nrows;
   float rmax = 0.f, amax = 0.f;
-  for (long long r = (long long)blockIdx.x * (NT / 64) + w; r < nrows; r += (long long)gridDim.x * (NT / 64)) {
-    float s = 0.f;
+  long long cur = r0 < r1 ? r0 / rows_per_chunk : -1;
+  auto flush = [&]() {
+    if (lane == 0 && cur >= 0) {
+      if (rmax > 0.f) atomicMax(slot + 2 * cur, __float_as_uint(rmax));
+      if (amax > 0.f) atomicMax(slot + 2 * cur + 1, __float_as_uint(amax));
+    }
+    rmax = 0.f;
+    amax = 0.f;
+  };
+  for (long long r = r0; r < r1; ++r) {
+    if (r / rows_per_chunk != cur) {
+      flush();
+      cur = r / rows_per_chunk;
+    }
+    float s = 0.f, a = 0.f;
     if constexpr (F64) {
       const double* row = static_cast<const double*>(B) + r * ld;
       for (int c = lane; c < ncols; c += 64) {
-        const float a = (float)fabs(row[c]);
-        s += a;
-        amax = fmaxf(amax, a);
+        const float v = (float)fabs(row[c]);
+        s += v;
+        a = fmaxf(a, v);
       }
     } else if constexpr (VEC) {
       const u16* row = static_cast<const u16*>(B) + r * ld;
@@ -194,36 +212,27 @@ __global__ void b_bounds_k(const void* __restrict__ B, long long nrows, int ncol
         const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          const float a = fabsf(__uint_as_float(wd[k] << 16)), b = fabsf(__uint_as_float(wd[k] & 0xFFFF0000u));
-          s += a + b;
-          amax = fmaxf(amax, fmaxf(a, b));
+          const float x = fabsf(__uint_as_float(wd[k] << 16)), y = fabsf(__uint_as_float(wd[k] & 0xFFFF0000u));
+          s += x + y;
+          a = fmaxf(a, fmaxf(x, y));
         }
       }
     } else {
       const u16* row = static_cast<const u16*>(B) + r * ld;
       for (int c = lane; c < ncols; c += 64) {
-        const float a = fabsf(bf16_bits_to_f32(row[c]));
-        s += a;
-        amax = fmaxf(amax, a);
+        const float v = fabsf(bf16_bits_to_f32(row[c]));
+        s += v;
+        a = fmaxf(a, v);
       }
     }
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-    rmax = fmaxf(rmax, __shfl(s, 0, 64));
-  }
-  for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_down(amax, off, 64));
-  if (lane == 0) {
-    red[0][w] = rmax;
-    red[1][w] = amax;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int k = 1; k < NT / 64; ++k) {
-      red[0][0] = fmaxf(red[0][0], red[0][k]);
-      red[1][0] = fmaxf(red[1][0], red[1][k]);
+    for (int off = 32; off > 0; off >>= 1) {
+      s += __shfl_down(s, off, 64);
+      a = fmaxf(a, __shfl_down(a, off, 64));
     }
-    if (red[0][0] > 0.f) atomicMax(slot, __float_as_uint(red[0][0]));
-    if (red[1][0] > 0.f) atomicMax(slot + 1, __float_as_uint(red[1][0]));
+    rmax = fmaxf(rmax, __shfl(s, 0, 64));
+    amax = fmaxf(amax, __shfl(a, 0, 64));
   }
+  flush();
 }
 
 // Hpp[p] = sum_mu C[mu][p] HC[mu][p]: one wavefront per orbital, fixed reduction order.
@@ -897,13 +906,14 @@ hipError_t scale_bounds(hipStream_t s, int nbf, int nact, const double* C, const
   if (e != hipSuccess) return e;
   LAUNCH(bounds_reduce_k, dim3(1), dim3(NT), nact, col, bnd, nclear);
 }
-hipError_t b_bounds(hipStream_t s, const void* B, int is_f64, long long nrows, int ncols, long long ld, uint32_t* slot) {
+hipError_t b_bounds(hipStream_t s, const void* B, int is_f64, long long nrows, int ncols, long long ld,
+                    long long rows_per_chunk, uint32_t* slot) {
   if (nrows <= 0) return hipSuccess;
-  const dim3 g((unsigned)std::min<long long>(cdiv(nrows, NT / 64), 2048));
+  const dim3 g((unsigned)std::min<long long>(cdiv(nrows, NT / 64), 4096));
   const bool vec = !is_f64 && (ld % 8 == 0) && ((reinterpret_cast<uintptr_t>(B) & 15) == 0);
-  if (is_f64) LAUNCH((b_bounds_k<true, false>), g, dim3(NT), B, nrows, ncols, ld, slot);
-  if (vec) LAUNCH((b_bounds_k<false, true>), g, dim3(NT), B, nrows, ncols, ld, slot);
-  LAUNCH((b_bounds_k<false, false>), g, dim3(NT), B, nrows, ncols, ld, slot);
+  if (is_f64) LAUNCH((b_bounds_k<true, false>), g, dim3(NT), B, nrows, ncols, ld, rows_per_chunk, slot);
+  if (vec) LAUNCH((b_bounds_k<false, true>), g, dim3(NT), B, nrows, ncols, ld, rows_per_chunk, slot);
+  LAUNCH((b_bounds_k<false, false>), g, dim3(NT), B, nrows, ncols, ld, rows_per_chunk, slot);
 }
 hipError_t hpp_from_hc(hipStream_t s, int nbf, int nact, const double* C, const double* HC, double* Hpp) {
   LAUNCH(hpp_k, dim3(nact), dim3(64), nbf, nact, C, HC, Hpp);

@@ -1,10 +1,15 @@
 """Write the oracle's expected values for the full-size workloads (runs on the CPU only).
 
 Usage: python tests/golden/make_expected.py c5_df1200 [c3_df500] [pes64] ...
+       python tests/golden/make_expected.py --arrays c3_df500 [c5_df1200]
 Calls only ``oracle`` (FP64, streamed route) on inputs from ``synth``; B rows are regenerated
 chunk by chunk from the counter-based stream, in worker processes, so that no full float64 copy of B
 ever exists.  Output: tests/golden/<workload>_expected.json with the energy, the orbital-step
 eigenvalues and sampled entries of J, K, lambda, dE/dC and dE/dn (indices stored with the values).
+With --arrays: tests/golden/<workload>_arrays.npz instead, holding whole arrays -- at c3_df500 every
+element of J, K, the active columns of lambda and dE/dC, dE/dn and the orbital energies; at
+c5_df1200 the diagonals of J and K, LINES whole rows and whole active columns of lambda and dE/dC
+(indices stored), dE/dn and the orbital energies.
 """
 from __future__ import annotations
 
@@ -30,7 +35,8 @@ def _rows(args):
     return p0, synth.b_chunk(key, nbf, naux, p0, p1, dt)
 
 
-def expected(name: str, workers: int = 6) -> dict:
+def oracle_run(name: str, workers: int = 6):
+    """The streamed oracle's Lagrangian step and orbital energies on a named workload."""
     inst = synth.workload(name, with_b=False)
     wl = inst.wl
     n = pnof.on_sigmoid(inst.gamma, wl.npairs, wl.ncwo)
@@ -53,6 +59,30 @@ def expected(name: str, workers: int = 6) -> dict:
         r = stream.lagrangian(inst.C, n, inst.H, chunk, wl.npairs, wl.ncwo, pnof.PNOF7, naux=wl.naux,
                               pchunk=CHUNK)
     _, eps, _ = pnof.orbital_step(r["lam"], inst.C)
+    return inst, wl, r, eps, time.time() - t0
+
+
+LINES = 4
+
+
+def arrays(name: str) -> dict:
+    inst, wl, r, eps, sec = oracle_run(name)
+    na = wl.nact
+    if name == "c3_df500":
+        return {"J": r["J"], "K": r["K"], "lam": r["lam"][:, :na], "dEdC": r["dEdC"][:, :na], "dEdn": r["dEdn"],
+                "eps": eps, "E": np.array([r["E"]]), "seconds": np.array([sec])}
+    rng = np.random.default_rng(23)
+    rows = np.sort(rng.choice(wl.nbf, LINES, replace=False))
+    cols = np.sort(rng.choice(na, LINES, replace=False))
+    return {"Jdiag": np.diag(r["J"]).copy(), "Kdiag": np.diag(r["K"]).copy(), "rows": rows, "cols": cols,
+            "lam_rows": r["lam"][rows, :na], "lam_cols": r["lam"][:, cols], "dEdC_rows": r["dEdC"][rows, :na],
+            "dEdC_cols": r["dEdC"][:, cols], "dEdn": r["dEdn"], "eps": eps, "E": np.array([r["E"]]),
+            "seconds": np.array([sec])}
+
+
+def expected(name: str, workers: int = 6) -> dict:
+    inst, wl, r, eps, sec = oracle_run(name, workers)
+    t0 = time.time() - sec
     rng = np.random.default_rng(17)
     pq = rng.integers(0, wl.nact, size=(64, 2))
     lam_pq = np.stack([rng.integers(0, wl.nbf, 64), rng.integers(0, wl.nact, 64)], axis=1)
@@ -107,6 +137,13 @@ def expected_pes(ninst: int = 64) -> dict:
 
 
 if __name__ == "__main__":
+    if sys.argv[1] == "--arrays":
+        for name in sys.argv[2:]:
+            out = arrays(name)
+            path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{name}_arrays.npz")
+            np.savez_compressed(path, **out)
+            print(f"wrote {path} ({out['seconds'][0]:.0f} s)")
+        sys.exit(0)
     for name in sys.argv[1:]:
         out = expected_pes() if name == "pes64" else expected(name)
         path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{name}_expected.json")

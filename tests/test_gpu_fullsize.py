@@ -3,8 +3,12 @@
 applies them; else the automatic plan).
 
 Expected values are the oracle's, stored by tests/golden/make_expected.py (FP64, streamed route,
-same seeded inputs).  B is generated on the device by the seeded filler (bit-identical to the host
-generator, see test_gpu_synth.py).  Energies: <= 1e-8 Ha (float64 path), <= 1e-6 Ha (bf16 split).
+same seeded inputs): sampled entries in <name>_expected.json, and whole arrays in <name>_arrays.npz
+-- at C3 every element of J, K, lambda, dE/dC (active columns), dE/dn and the orbital energies; at
+C5 the diagonals of J and K, four whole rows and four whole active columns of lambda and dE/dC, all
+of dE/dn and the orbital energies.  B is generated on the device by the seeded filler
+(bit-identical to the host generator, see test_gpu_synth.py).  Energies: <= 1e-8 Ha (float64
+path), <= 1e-6 Ha (bf16 split).
 """
 import json
 import os
@@ -53,9 +57,35 @@ def _sampled(out, ref, key, getter):
     return np.max(np.abs(got - np.array(ref[key]["val"])))
 
 
+def _arrays(name):
+    path = os.path.join(GOLD, f"{name}_arrays.npz")
+    return dict(np.load(path)) if os.path.exists(path) else None
+
+
+def _array_errors(o, eps, arr, nact):
+    """Max abs error over every stored element (whole matrices at C3, whole lines at C5)."""
+    if "J" in arr:
+        return {"J_all": np.max(np.abs(o["J"] - arr["J"])), "K_all": np.max(np.abs(o["K"] - arr["K"])),
+                "lam_all": np.max(np.abs(o["lam"][:, :nact] - arr["lam"])),
+                "lam_zero": np.max(np.abs(o["lam"][:, nact:])) if o["lam"].shape[1] > nact else 0.0,
+                "dEdC_all": np.max(np.abs(o["dEdC"][:, :nact] - arr["dEdC"])),
+                "dEdn_all": np.max(np.abs(o["dEdn"][:nact] - arr["dEdn"])),
+                "eps_all": np.max(np.abs(eps - arr["eps"]))}
+    rows, cols = arr["rows"], arr["cols"]
+    return {"Jdiag": np.max(np.abs(np.diag(o["J"]) - arr["Jdiag"])),
+            "Kdiag": np.max(np.abs(np.diag(o["K"]) - arr["Kdiag"])),
+            "lam_lines": max(np.max(np.abs(o["lam"][rows, :nact] - arr["lam_rows"])),
+                             np.max(np.abs(o["lam"][:, cols] - arr["lam_cols"]))),
+            "dEdC_lines": max(np.max(np.abs(o["dEdC"][rows, :nact] - arr["dEdC_rows"])),
+                              np.max(np.abs(o["dEdC"][:, cols] - arr["dEdC_cols"]))),
+            "dEdn_all": np.max(np.abs(o["dEdn"][:nact] - arr["dEdn"])),
+            "eps_all": np.max(np.abs(eps - arr["eps"]))}
+
+
 @pytest.mark.parametrize("name", ["c3_df500", "c5_df1200"])
 def test_full_size_parity(ctx, name):
     ref = _load(name)
+    arr = _arrays(name)
     inst, wl, C, H, gam, B, kind = _inputs(name)
     res = {}
     for prec in (P.FP64, P.BF16_SPLIT):
@@ -78,6 +108,8 @@ def test_full_size_parity(ctx, name):
             "eps": float(np.max(np.abs(eps.cpu().numpy() - np.array(ref["eps"])))),
             "max_asym": abs(o["max_asym"][0] - ref["max_asym"]),
         }
+        if arr is not None:
+            errs.update(_array_errors(o, eps.cpu().numpy(), arr, wl.nact))
         res[prec] = errs
         ctx.set_tuning(None)
         print(name, "prec", prec, {k: f"{v:.2e}" for k, v in errs.items()})
@@ -86,6 +118,17 @@ def test_full_size_parity(ctx, name):
     assert e64["dEdC"] < 1e-9 and e64["dEdn"] < 1e-9 and e64["eps"] < 1e-9
     assert emx["E"] < 1e-6 and emx["lam"] < 2e-5 and emx["J"] < 2e-5 and emx["K"] < 2e-5
     assert emx["eps"] < 2e-5 and emx["dEdC"] < 1e-4
+    if arr is not None:
+        lim64 = {"J_all": 1e-12, "K_all": 1e-12, "lam_all": 1e-10, "lam_zero": 0.0, "dEdC_all": 1e-9,
+                 "dEdn_all": 1e-9, "eps_all": 1e-9, "Jdiag": 1e-12, "Kdiag": 1e-12, "lam_lines": 1e-10,
+                 "dEdC_lines": 1e-9}
+        limmx = {"J_all": 2e-5, "K_all": 2e-5, "lam_all": 2e-5, "lam_zero": 0.0, "dEdC_all": 1e-4,
+                 "dEdn_all": 1e-4, "eps_all": 2e-5, "Jdiag": 2e-5, "Kdiag": 2e-5, "lam_lines": 2e-5,
+                 "dEdC_lines": 1e-4}
+        for k in lim64:
+            if k in e64:
+                assert e64[k] <= lim64[k], (k, e64[k])
+                assert emx[k] <= limmx[k], (k, emx[k])
 
 
 def test_finite_difference_gradients_c3(ctx):

@@ -184,3 +184,22 @@ def test_fockian_offdiagonals_and_zeta_scaling():
     Cn, eps, S = pnof.orbital_step(lam, np.eye(6), diag_prev=diag, zeta=zeta)
     assert np.all(np.diag(S) == diag)
     assert np.max(np.abs(S - S.T)) == 0.0
+
+
+def test_scale_zeta_hand_worked_values():
+    """zeta scaling of Section 3.2 (each off-diagonal element divided by ten while its magnitude
+    exceeds zeta) on a fixed matrix, against values worked out by hand for zeta = 0.05:
+    0.7 -> 0.07 -> 0.007 (two divisions), 12.5 -> 0.0125 (three), -0.0501 -> -0.00501 (one, sign
+    kept), 0.05 stays (the test is strict: |F| > zeta), -0.004 and 0.0032 stay, the diagonal stays."""
+    F = np.array([[9.0, 0.7, -0.004, 12.5],
+                  [0.7, 8.0, 0.05, -0.0501],
+                  [-0.004, 0.05, 7.0, 3.2e-3],
+                  [12.5, -0.0501, 3.2e-3, 6.0]])
+    want = np.array([[9.0, 0.007, -0.004, 0.0125],
+                     [0.007, 8.0, 0.05, -0.00501],
+                     [-0.004, 0.05, 7.0, 0.0032],
+                     [0.0125, -0.00501, 0.0032, 6.0]])
+    got = pnof.scale_zeta(F, 0.05)
+    assert np.allclose(got, want, rtol=1e-14, atol=0.0)
+    assert np.array_equal(np.diag(got), np.diag(F))
+    assert got[1, 2] == 0.05   # the boundary value itself is not divided
