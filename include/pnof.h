@@ -188,6 +188,22 @@ pnof_status pnof_lagrangian(pnof_ctx ctx, const pnof_problem* prob, const double
                             double* E, double* dEdC, double* dEdn, double* max_asym, double* J,
                             double* K);
 
+/* ---- without device allocation -------------------------------------------------------------- */
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): pnof_lagrangian with the same arguments and results, its
+ * workspace taken from a static device array of PNOF_STATIC_SCRATCH_BYTES on each GPU (held until
+ * the process ends; pnof_create takes its address on the context's device).  Nothing is allocated:
+ * no hipMalloc / hipFree, no rocBLAS (the float64 products run on the library's own GEMM), no second
+ * stream (every step runs in order on the context's stream).  The rows of B per chunk are lowered
+ * until the workspace fits the array; a problem that does not fit even with one row per chunk
+ * returns PNOF_E_UNSUPPORTED, naming the bytes it needs.  All calls on one GPU share the array,
+ * which keeps the last call's contents (each call clears what must start at zero): calls that
+ * overlap on one GPU, from any context or stream, race. */
+#define PNOF_STATIC_SCRATCH_BYTES (64u << 20)
+pnof_status pnof_lagrangian_noalloc(pnof_ctx ctx, const pnof_problem* prob, const double* C, const double* n,
+                                    const double* H, const void* ints, double* lambda, double* E, double* dEdC,
+                                    double* dEdn, double* max_asym, double* J, double* K);
+
 /* ---- orbital step (Eq. Fockian; Section 3.4) ------------------------------------------------ */
 /* diag_prev == NULL: S = (lambda + lambda^T)/2.  Otherwise S_pq = lambda_qp - lambda_pq for p < q
  * (mirrored; the orientation of Eq. Fockian for which the first-order energy change of Eq. ene1

@@ -116,6 +116,7 @@ def lib():
             "pnof_energy": ([P, PP, P, P, P, P, P], S),
             "pnof_fock": ([P, PP, P, P, P, P, P, P, P, I], S),
             "pnof_lagrangian": ([P, PP, P, P, P, P, P, P, P, P, P, P, P], S),
+            "pnof_lagrangian_noalloc": ([P, PP, P, P, P, P, P, P, P, P, P, P, P], S),
             "pnof_orbital_step": ([P, I, P, P, P, D, P, P, P], S),
             "pnof_set_tuning": ([P, ctypes.POINTER(Tuning)], S),
             "pnof_get_plan": ([P, PP, ctypes.POINTER(Tuning)], S),

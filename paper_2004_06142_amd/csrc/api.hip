@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -14,6 +15,17 @@
 #include "pnof.h"
 
 using namespace pnof;
+
+// Workspace of pnof_lagrangian_noalloc: one static array per GPU, held until the process ends.  In
+// host code `scratch` is only a stand-in for the symbol; its device address on each GPU comes from
+// hipGetSymbolAddress (taken once per device by pnof_create) and only that address is used.
+static __device__ __align__(256) char scratch[PNOF_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+}  // namespace
 
 struct pnof_ctx_s {
   int device = 0;
@@ -1026,6 +1038,22 @@ pnof_status pnof_create(pnof_ctx* out, int device, void* hip_stream) {
     return fail(nullptr, PNOF_E_DEVICE, "rocblas_create_handle failed");
   }
   rocblas_set_stream(c->blas, c->stream);
+  {
+    // device address of the static workspace of pnof_lagrangian_noalloc on this device
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (device < kMaxDevices && !g_scratch[device]) {
+      void* p = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !p) {
+        hipGetLastError();
+        rocblas_destroy_handle(c->blas);
+        delete c;
+        return fail(nullptr, PNOF_E_DEVICE, std::string("hipGetSymbolAddress of the static workspace: ") +
+                                                hipGetErrorString(e));
+      }
+      g_scratch[device] = p;
+    }
+  }
   if (hipHostMalloc(reinterpret_cast<void**>(&c->host_info), sizeof(int) * 4, hipHostMallocDefault) != hipSuccess) {
     rocblas_destroy_handle(c->blas);
     delete c;
@@ -1237,6 +1265,37 @@ pnof_status pnof_lagrangian(pnof_ctx ctx, const pnof_problem* prob, const double
   r.K = K;
   r.need_y = true;
   r.need_e = true;
+  return run_step(ctx, prob, C, n, H, ints, r);
+}
+
+pnof_status pnof_lagrangian_noalloc(pnof_ctx ctx, const pnof_problem* prob, const double* C, const double* n,
+                                    const double* H, const void* ints, double* lambda, double* E, double* dEdC,
+                                    double* dEdn, double* max_asym_out, double* J, double* K) {
+  if (!ctx) return fail(nullptr, PNOF_E_ARG, "context is NULL");
+  pnof_status st = check_problem(ctx, prob);
+  if (st != PNOF_OK) return st;
+  if ((st = check_ptrs(ctx, {C, n, H, ints, lambda, E}, "pnof_lagrangian_noalloc")) != PNOF_OK) return st;
+  if ((st = check_ctx(ctx)) != PNOF_OK) return st;
+  void* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (ctx->device < kMaxDevices) ws = g_scratch[ctx->device];
+  }
+  if (!ws) return fail(ctx, PNOF_E_DEVICE, "the static workspace of this device was not set up");
+  Req r;
+  r.lam = lambda;
+  r.E = E;
+  r.dEdC = dEdC;
+  r.dEdn = dEdn;
+  r.asym = max_asym_out;
+  r.J = J;
+  r.K = K;
+  r.need_y = true;
+  r.need_e = true;
+  r.ws = static_cast<char*>(ws);
+  r.ws_bytes = PNOF_STATIC_SCRATCH_BYTES;
+  r.own_gemm = true;
+  r.one_stream = true;
   return run_step(ctx, prob, C, n, H, ints, r);
 }
 
