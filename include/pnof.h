@@ -54,7 +54,7 @@
 extern "C" {
 #endif
 
-#define PNOF_ABI_VERSION 3
+#define PNOF_ABI_VERSION 4
 
 typedef struct pnof_ctx_s* pnof_ctx;
 
@@ -282,24 +282,40 @@ pnof_status pnof_optimize(pnof_ctx ctx, const pnof_problem* prob, const double* 
                           pnof_opt_result* result);
 
 /* ---- batches of independent problems (a potential-energy-surface scan) ---------------------- */
-/* A batch runs the Lagrangian step (as pnof_lagrangian: E, lambda, optional dE/dC, dE/dn and
- * max asymmetry) for ninst independent problems of different sizes in one fixed sequence of
- * grouped launches: every launch covers all instances, so small instances share the chip instead of
- * each leaving it mostly idle.  Restrictions: every problem uses PNOF_INTS_DF_BF16 and the same
- * precision (PNOF_BF16_SPLIT or PNOF_BF16), flags == 0, and each instance's packed B and tile
- * buffers stay below 2 GiB (roughly nbf <= 600 at naux = 4 nbf); the functional may differ.
+/* A batch runs the Lagrangian step (as pnof_lagrangian: E, lambda, optional dE/dC, dE/dn, max
+ * asymmetry, and dE/dgamma through the ON map) for ninst independent problems of different sizes.
+ * Two forms of one step:
+ *   - a fixed sequence of grouped launches: every launch covers all instances, so small instances
+ *     share the chip instead of each leaving it mostly idle (pnof_batch_info gives the count);
+ *   - PNOF_BATCH_PERSISTENT: one persistent launch (after a launch that clears its scheduling
+ *     state).  Its blocks claim work items of each instance's current phase -- the next phase of an
+ *     instance opens when every item of the previous one is complete -- in instance order, so an
+ *     instance completes as soon as its own work does; each instance's completion time is recorded
+ *     on the device clock (pnof_batch_times).  The X and Y tile widths in use apply; b runs 64-wide.
+ *     A block that finds nothing to claim polls; once the batch's stall time
+ *     (pnof_batch_set_stall) passes with no work item completed anywhere, it raises a stall flag and
+ *     every block exits (pnof_batch_times then reports PNOF_E_DEVICE).  Split precision only.
+ * Restrictions: every problem uses PNOF_INTS_DF_BF16 and the same precision (PNOF_BF16_SPLIT or
+ * PNOF_BF16), flags == 0, and each instance's packed B and tile buffers stay below 2 GiB (roughly
+ * nbf <= 600 at naux = 4 nbf); the functional may differ.
  *
  * pnof_batch_plan: validates the problems and allocates the batch's device workspace (owned by the
  *   batch, freed by pnof_batch_destroy; the only allocation of a batch).  Uses the context's device
  *   and stream; the context must outlive the batch.
  * pnof_batch_bind: io[i] gives instance i's device buffers (the pnof_lagrangian conventions:
- *   C, H, lambda, dEdC nbf x nbf; n, dEdn nbf; E and max_asym one double each).  Binding copies
- *   every instance's B into the batch's padded layout (rows padded to a multiple of 32) and
- *   clears the tile workspace, on the context stream; later runs read that copy, so bind again
- *   after B changes.  C, n and H are read by every run at the bound addresses.
- * pnof_batch_run: enqueues one step of every instance on the context stream.  use_graph != 0
- *   captures the sequence into a HIP graph on its first use (on a private stream) and replays it
- *   afterwards; rebinding discards the graph.  Runs on one batch must not overlap. */
+ *   C, H, lambda, dEdC nbf x nbf; n, dEdn nbf; E and max_asym one double each; gamma and dEdgamma
+ *   the variables of ON map on_kind, see pnof_on_map -- dEdgamma needs dEdn).  Binding copies every
+ *   instance's B into the batch's padded layout (rows padded to a multiple of 32) and clears the
+ *   tile workspace, on the context stream; later runs read that copy, so bind again after B
+ *   changes.  C, n, H and gamma are read by every run at the bound addresses.
+ * pnof_batch_run: enqueues one step of every instance on the context stream; flags:
+ *   PNOF_BATCH_GRAPH captures the launches into a HIP graph on first use (on a private stream) and
+ *   replays it afterwards (rebinding discards the graph); PNOF_BATCH_PERSISTENT selects the
+ *   persistent form.  Runs on one batch must not overlap.
+ * pnof_batch_times: after a persistent run, synchronises the context stream and writes each
+ *   instance's completion time in microseconds after the run's start (us: ninst host doubles).
+ *   (ABI version 4: gamma, dEdgamma, on_kind; run flags; completion times; stall time.) */
+enum { PNOF_BATCH_GRAPH = 1, PNOF_BATCH_PERSISTENT = 2 };
 typedef struct pnof_batch_s* pnof_batch;
 typedef struct {
   const double* C;
@@ -311,10 +327,17 @@ typedef struct {
   double* dEdC;         /* optional */
   double* dEdn;         /* optional (entries >= nact untouched) */
   double* max_asym;     /* optional: one device double */
+  const double* gamma;  /* optional: ON-map variables of n (for dEdgamma) */
+  double* dEdgamma;     /* optional: needs gamma and dEdn */
+  int32_t on_kind;      /* ON map of gamma: 0 sigmoid, 1 trigonometric */
 } pnof_batch_io;
 pnof_status pnof_batch_plan(pnof_ctx ctx, int32_t ninst, const pnof_problem* probs, pnof_batch* out);
 pnof_status pnof_batch_bind(pnof_batch batch, const pnof_batch_io* io);
-pnof_status pnof_batch_run(pnof_batch batch, int32_t use_graph);
+pnof_status pnof_batch_run(pnof_batch batch, int32_t flags);
+pnof_status pnof_batch_times(pnof_batch batch, double* us);
+/* Time (device clock, microseconds) a persistent run may pass with no work item completed anywhere
+ * before its blocks give up (0: the default, one second; at most 1e9). */
+pnof_status pnof_batch_set_stall(pnof_batch batch, double microseconds);
 /* Device bytes held by the batch, and the number of launches one run enqueues. */
 pnof_status pnof_batch_info(pnof_batch batch, size_t* bytes, int32_t* launches);
 /* Tile widths along the active orbitals of the grouped X, b and Y contractions: 64 or 128, 0 for

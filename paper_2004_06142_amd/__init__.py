@@ -12,6 +12,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
 from typing import Optional
 
 import torch
@@ -25,6 +26,7 @@ FP64, FP32, BF16, BF16_SPLIT = 0, 1, 2, 3
 INTS_ERI4_F64, INTS_DF_F64, INTS_DF_BF16 = 0, 1, 2
 CHECK_FINITE = 1
 ON_SIGMOID, ON_TRIG = 0, 1
+BATCH_GRAPH, BATCH_PERSISTENT = 1, 2
 
 STATUS = {0: "PNOF_OK", 1: "PNOF_E_ARG", 2: "PNOF_E_SHAPE", 3: "PNOF_E_DTYPE", 4: "PNOF_E_NOMEM",
           5: "PNOF_E_DEVICE", 6: "PNOF_E_NONFINITE", 7: "PNOF_E_UNSUPPORTED", 8: "PNOF_E_EIG"}
@@ -35,7 +37,7 @@ EXPORTS = ["pnof_abi_version", "pnof_last_error", "pnof_check_problem", "pnof_cr
            "pnof_profile_begin", "pnof_profile_end", "pnof_set_tuning", "pnof_get_plan", "pnof_optimize_on",
            "pnof_optimize", "pnof_nofmp2_terms", "pnof_batch_plan",
            "pnof_batch_bind", "pnof_batch_run", "pnof_batch_info", "pnof_batch_destroy", "pnof_batch_set_tiles",
-           "pnof_batch_get_tiles"]
+           "pnof_batch_get_tiles", "pnof_batch_times", "pnof_batch_set_stall"]
 STAGES = ("X", "b", "Y", "eig")
 
 
@@ -72,7 +74,8 @@ class OptResult(ctypes.Structure):
 
 
 class BatchIO(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_void_p) for n in ("C", "n", "H", "ints", "lambda_", "E", "dEdC", "dEdn", "max_asym")]
+    _fields_ = [(n, ctypes.c_void_p) for n in ("C", "n", "H", "ints", "lambda_", "E", "dEdC", "dEdn", "max_asym",
+                                                "gamma", "dEdgamma")] + [("on_kind", ctypes.c_int32)]
 
 
 class Problem(ctypes.Structure):
@@ -133,6 +136,8 @@ def lib():
             "pnof_batch_destroy": ([P], None),
             "pnof_batch_set_tiles": ([P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32], S),
             "pnof_batch_get_tiles": ([P, ctypes.POINTER(ctypes.c_int32)], S),
+            "pnof_batch_times": ([P, ctypes.POINTER(ctypes.c_double)], S),
+            "pnof_batch_set_stall": ([P, ctypes.c_double], S),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -201,7 +206,11 @@ class Context:
             lib().pnof_destroy(self.handle)
             self.handle = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # at interpreter shutdown the HIP runtime may already be tearing down: the process's end
+        # releases the device resources instead
+        if _finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -483,12 +492,15 @@ def energy_and_grad(ctx, prob, C, gamma, H, ints, kind=ON_SIGMOID):
 
 # ----------------------------------------------------------------------------- batches
 class Batch:
-    """A batch of independent problems run by one fixed sequence of grouped launches.
+    """A batch of independent problems, run as one fixed sequence of grouped launches or as one
+    persistent launch.
 
     ``problems``: list of Problem (DF_BF16, one precision).  ``bind(inputs)`` takes, per instance, a
-    dict with device tensors C, n, H, B (and optionally dEdC / dEdn / max_asym flags via
-    ``grads=True``) and allocates the outputs; ``run(graph=True)`` enqueues one step of every
-    instance (captured into a HIP graph on the first call) and returns the output dicts.
+    dict with device tensors C, n, H, B and optionally gamma (with ``on_kind``, for dE/dgamma), and
+    allocates the outputs (dEdC / dEdn / max_asym / dEdgamma with ``grads=True``).  ``run(graph,
+    persistent)`` enqueues one step of every instance (with ``graph``, captured into a HIP graph on
+    the first call) and returns the output dicts; after a persistent run ``times()`` gives each
+    instance's completion time in microseconds after the run's start.
     """
 
     def __init__(self, ctx: Context, problems):
@@ -531,31 +543,57 @@ class Batch:
             _ints_check(prob, x["B"], d)
             o = {"E": torch.zeros(1, dtype=torch.float64, device=d),
                  "lam": torch.zeros(nbf, nbf, dtype=torch.float64, device=d)}
+            gam = x.get("gamma")
+            kind = int(x.get("on_kind", ON_SIGMOID))
+            if gam is not None and kind in (ON_SIGMOID, ON_TRIG):   # the library rejects other kinds
+                ngam = prob.nact if kind == ON_SIGMOID else prob.npairs * prob.ncwo
+                _check(gam, ngam, torch.float64, d, f"gamma[{i}]")
             if grads:
                 o["dEdC"] = torch.zeros(nbf, nbf, dtype=torch.float64, device=d)
                 o["dEdn"] = torch.zeros(prob.nact, dtype=torch.float64, device=d)
                 o["max_asym"] = torch.zeros(1, dtype=torch.float64, device=d)
+                if gam is not None:
+                    o["dEdgamma"] = torch.zeros(gam.numel(), dtype=torch.float64, device=d)
             io = ios[i]
             io.C, io.n, io.H, io.ints = (x["C"].data_ptr(), x["n"].data_ptr(), x["H"].data_ptr(), x["B"].data_ptr())
             io.lambda_, io.E = o["lam"].data_ptr(), o["E"].data_ptr()
             io.dEdC = o["dEdC"].data_ptr() if grads else None
             io.dEdn = o["dEdn"].data_ptr() if grads else None
             io.max_asym = o["max_asym"].data_ptr() if grads else None
+            io.gamma = gam.data_ptr() if gam is not None else None
+            io.dEdgamma = o["dEdgamma"].data_ptr() if "dEdgamma" in o else None
+            io.on_kind = kind
             outs.append(o)
         _raise(self.ctx, lib().pnof_batch_bind(self.handle, ios))
         self.inputs, self.outputs = list(inputs), outs   # keep the bound tensors alive
         return outs
 
-    def run(self, graph: bool = True):
-        _raise(self.ctx, lib().pnof_batch_run(self.handle, 1 if graph else 0))
+    def run(self, graph: bool = True, persistent: bool = False):
+        flags = (BATCH_GRAPH if graph else 0) | (BATCH_PERSISTENT if persistent else 0)
+        _raise(self.ctx, lib().pnof_batch_run(self.handle, flags))
         return self.outputs
+
+    def times(self):
+        """Completion time of each instance in the last persistent run (microseconds after its
+        start); synchronises the context stream."""
+        out = (ctypes.c_double * len(self.problems))()
+        _raise(self.ctx, lib().pnof_batch_times(self.handle, out))
+        return list(out)
+
+    def set_stall(self, microseconds: float = 0.0):
+        """Time with no progress anywhere before a persistent run's blocks give up (0: one second)."""
+        _raise(self.ctx, lib().pnof_batch_set_stall(self.handle, float(microseconds)))
 
     def close(self):
         if getattr(self, "handle", None):
             lib().pnof_batch_destroy(self.handle)
             self.handle = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # at interpreter shutdown the HIP runtime may already be tearing down: the process's end
+        # releases the device resources instead
+        if _finalizing():
+            return
         try:
             self.close()
         except Exception:

@@ -921,6 +921,15 @@ struct pnof_batch_s {
   int launches = 13;
   int req[3] = {0, 0, 0};             // requested tile widths along the active orbitals (0: automatic)
   int tile[3] = {128, 128, 128};      // in use: X (rows p), b (square), Y (columns q)
+  // persistent kernel: scheduling state (batch workspace), its graph, the last run's mode
+  PSched ps{};
+  int* d_cnt = nullptr;
+  hipGraph_t pgraph = nullptr;
+  hipGraphExec_t pexec = nullptr;
+  int pblocks = 512;                  // two blocks per compute unit
+  double stall_us = 1e6;              // no progress for this long: a persistent run gives up
+  int last_flags = -1;
+  double clock_khz = 0.0;             // device wall clock
 };
 
 namespace {
@@ -928,8 +937,12 @@ namespace {
 void batch_drop_graph(pnof_batch b) {
   if (b->exec) hipGraphExecDestroy(b->exec);
   if (b->graph) hipGraphDestroy(b->graph);
+  if (b->pexec) hipGraphExecDestroy(b->pexec);
+  if (b->pgraph) hipGraphDestroy(b->pgraph);
   b->exec = nullptr;
   b->graph = nullptr;
+  b->pexec = nullptr;
+  b->pgraph = nullptr;
 }
 
 // The fixed launch sequence of one batch step.
@@ -969,9 +982,23 @@ hipError_t batch_offsets(pnof_batch b, hipStream_t s) {
   b->tot1 = off[n];
   b->tot2 = off[2 * (n + 1) - 1];
   b->tot3 = off[3 * (n + 1) - 1];
+  // work items per phase of the persistent kernel (X and Y at the widths in use, b 64-wide)
+  std::vector<int> cnt((size_t)n * PH_N);
+  for (int i = 0; i < n; ++i) {
+    const BatchGeom& g = b->geo[i];
+    G1Args g1{};
+    g1.nbf = g.nbf; g1.nact = g.nact; g1.np = g.naux;
+    G2Args g2{};
+    g2.nact = g.nact; g2.nsplit = g.ns2;
+    G3Args g3{};
+    g3.nbf = g.nbf; g3.nact = g.nact; g3.nsplit = g.ns3;
+    persist_counts(b->inst[i], g1, g2, g3, b->tile[0], b->tile[2], cnt.data() + (size_t)i * PH_N);
+  }
   hipError_t e = hipMemcpyAsync(b->d_off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return e;
-  return hipStreamSynchronize(s);   // off goes out of scope
+  e = hipMemcpyAsync(b->d_cnt, cnt.data(), sizeof(int) * cnt.size(), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(s);   // off and cnt go out of scope
 }
 
 // Two branches, forked and joined with events (in a captured graph they become parallel nodes):
@@ -1003,8 +1030,24 @@ hipError_t batch_enqueue(pnof_batch b, hipStream_t s) {
   BSTEP(batch_energy_y(s, n, b->d_inst, b->mx));
   BSTEP(gemm_f64_grouped(s, n, b->maxM[3], b->maxN[3], true, true, b->d_f64 + 3 * n));
   BSTEP(batch_finish(s, n, b->d_inst, b->mx));
+  BSTEP(batch_vjp(s, n, b->d_inst, b->mx));
 #undef BSTEP
   return hipSuccess;
+}
+
+// The persistent form: one launch clears the scheduling state, one runs every step of every instance.
+hipError_t batch_enqueue_persistent(pnof_batch b, hipStream_t s) {
+  PArgs a{};
+  a.ninst = b->ninst;
+  a.terms = b->terms;
+  a.inst = b->d_inst;
+  a.g1 = b->d_g1;
+  a.g2 = b->d_g2;
+  a.g3 = b->d_g3;
+  a.f64 = b->d_f64;
+  a.sc = b->ps;
+  a.sc.stall_ticks = (unsigned long long)(b->stall_us * b->clock_khz * 1e-3) + 1;
+  return batch_persist(s, a, b->ninst * PH_N, b->tile[0], b->tile[2], b->pblocks);
 }
 
 pnof_status batch_fail(pnof_batch b, pnof_status st, const std::string& msg) { return fail(b ? b->ctx : nullptr, st, msg); }
@@ -1636,11 +1679,18 @@ pnof_status pnof_batch_plan(pnof_ctx ctx, int32_t ninst, const pnof_problem* pro
     if (probs[i].precision != prec) return fail(ctx, PNOF_E_ARG, "all instances of a batch share one precision");
     if (probs[i].flags != 0) return fail(ctx, PNOF_E_UNSUPPORTED, "batches take no flags");
   }
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx->device) != hipSuccess || khz <= 0) {
+    hipGetLastError();
+    return fail(ctx, PNOF_E_DEVICE, "the device wall-clock rate is unavailable");
+  }
   pnof_batch b = new pnof_batch_s();
   b->ctx = ctx;
   b->ninst = ninst;
+  b->clock_khz = (double)khz;
   b->terms = prec == PNOF_BF16_SPLIT ? 3 : 1;
-  b->launches = b->terms > 1 ? 15 : 13;   // the split mode adds the two launches of the scale bounds
+  // the split mode adds the two launches of the scale bounds; the last one forms dE/dgamma
+  b->launches = b->terms > 1 ? 16 : 14;
   b->probs.assign(probs, probs + ninst);
   b->inst.resize(ninst);
   // carve (measure, then allocate and carve again)
@@ -1691,6 +1741,14 @@ pnof_status pnof_batch_plan(pnof_ctx ctx, int32_t ninst, const pnof_problem* pro
     b->d_g3 = a.take<G3Args>(ninst);
     b->d_off = a.take<int>(3LL * (ninst + 1));
     b->d_f64 = a.take<F64Gemm>(4LL * ninst);
+    b->d_cnt = a.take<int>((long long)ninst * PH_N);
+    b->ps.cnt = b->d_cnt;
+    b->ps.claim = a.take<int>((long long)ninst * PH_N);
+    b->ps.done = a.take<int>((long long)ninst * PH_N);
+    b->ps.phase = a.take<int>(ninst);
+    b->ps.t_end = a.take<unsigned long long>(ninst);
+    b->ps.t_start = a.take<unsigned long long>(1);
+    b->ps.prog = a.take<int>(4);
     return a.off + 256;
   };
   for (int i = 0; i < ninst; ++i) {
@@ -1765,6 +1823,12 @@ pnof_status pnof_batch_bind(pnof_batch b, const pnof_batch_io* io) {
   for (int i = 0; i < n; ++i)
     if (!io[i].C || !io[i].n || !io[i].H || !io[i].ints || !io[i].lambda || !io[i].E)
       return fail(ctx, PNOF_E_ARG, "instance " + std::to_string(i) + ": C, n, H, ints, lambda and E are required");
+  for (int i = 0; i < n; ++i) {
+    if (io[i].dEdgamma && (!io[i].gamma || !io[i].dEdn))
+      return fail(ctx, PNOF_E_ARG, "instance " + std::to_string(i) + ": dEdgamma needs gamma and dEdn");
+    if (io[i].gamma && io[i].on_kind != 0 && io[i].on_kind != 1)
+      return fail(ctx, PNOF_E_ARG, "instance " + std::to_string(i) + ": on_kind is 0 (sigmoid) or 1 (trigonometric)");
+  }
   batch_drop_graph(b);
   std::vector<G1Args> g1(n);
   std::vector<G2Args> g2(n);
@@ -1775,6 +1839,7 @@ pnof_status pnof_batch_bind(pnof_batch b, const pnof_batch_io* io) {
     const BatchGeom& g = b->geo[i];
     d.C = io[i].C; d.n = io[i].n; d.H = io[i].H; d.B = static_cast<const u16*>(io[i].ints);
     d.lam = io[i].lambda; d.E = io[i].E; d.dEdC = io[i].dEdC; d.dEdn = io[i].dEdn; d.asym = io[i].max_asym;
+    d.gamma = io[i].gamma; d.dEdgamma = io[i].dEdgamma; d.on_kind = io[i].on_kind;
     const long long nct = (long long)g.nact32 * g.ldk, nxt = (long long)g.naux * g.nact32 * g.ldk,
                     nw = (long long)g.naux * g.nact32 * g.ldw;
     const WsDims wd{g.nact32, 2 * nct, 2 * nxt, 2 * nw};
@@ -1807,23 +1872,32 @@ pnof_status pnof_batch_bind(pnof_batch b, const pnof_batch_io* io) {
   return PNOF_OK;
 }
 
-pnof_status pnof_batch_run(pnof_batch b, int32_t use_graph) {
+pnof_status pnof_batch_run(pnof_batch b, int32_t flags) {
   if (!b) return fail(nullptr, PNOF_E_ARG, "batch is NULL");
   pnof_ctx ctx = b->ctx;
   pnof_status st = check_ctx(ctx);
   if (st != PNOF_OK) return st;
   if (!b->bound) return fail(ctx, PNOF_E_ARG, "pnof_batch_bind must be called before pnof_batch_run");
-  if (!b->side) DEV_CHECK(ctx, hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking));
-  for (hipEvent_t& ev : b->ev)
-    if (!ev) DEV_CHECK(ctx, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  if (flags & ~(PNOF_BATCH_GRAPH | PNOF_BATCH_PERSISTENT)) return fail(ctx, PNOF_E_ARG, "unknown batch run flags");
+  const bool persistent = (flags & PNOF_BATCH_PERSISTENT) != 0, use_graph = (flags & PNOF_BATCH_GRAPH) != 0;
+  if (persistent && b->terms != 3)
+    return fail(ctx, PNOF_E_UNSUPPORTED, "the persistent batch kernel runs the split precision (PNOF_BF16_SPLIT)");
+  if (!persistent) {
+    if (!b->side) DEV_CHECK(ctx, hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking));
+    for (hipEvent_t& ev : b->ev)
+      if (!ev) DEV_CHECK(ctx, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  }
+  b->last_flags = flags;
   if (!use_graph) {
-    DEV_CHECK(ctx, batch_enqueue(b, ctx->stream));
+    DEV_CHECK(ctx, persistent ? batch_enqueue_persistent(b, ctx->stream) : batch_enqueue(b, ctx->stream));
     return PNOF_OK;
   }
-  if (!b->exec) {
+  hipGraph_t& graph = persistent ? b->pgraph : b->graph;
+  hipGraphExec_t& exec = persistent ? b->pexec : b->exec;
+  if (!exec) {
     if (!b->cap) DEV_CHECK(ctx, hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
     DEV_CHECK(ctx, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-    hipError_t e = batch_enqueue(b, b->cap);
+    hipError_t e = persistent ? batch_enqueue_persistent(b, b->cap) : batch_enqueue(b, b->cap);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(b->cap, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -1831,10 +1905,40 @@ pnof_status pnof_batch_run(pnof_batch b, int32_t use_graph) {
       hipGetLastError();
       return fail(ctx, PNOF_E_DEVICE, std::string("graph capture failed: ") + hipGetErrorString(e != hipSuccess ? e : e2));
     }
-    b->graph = g;
-    DEV_CHECK(ctx, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    graph = g;
+    DEV_CHECK(ctx, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
   }
-  DEV_CHECK(ctx, hipGraphLaunch(b->exec, ctx->stream));
+  DEV_CHECK(ctx, hipGraphLaunch(exec, ctx->stream));
+  return PNOF_OK;
+}
+
+pnof_status pnof_batch_times(pnof_batch b, double* us) {
+  if (!b) return fail(nullptr, PNOF_E_ARG, "batch is NULL");
+  pnof_ctx ctx = b->ctx;
+  pnof_status st = check_ctx(ctx);
+  if (st != PNOF_OK) return st;
+  if (!us) return fail(ctx, PNOF_E_ARG, "us is NULL");
+  if (b->last_flags < 0 || !(b->last_flags & PNOF_BATCH_PERSISTENT))
+    return fail(ctx, PNOF_E_UNSUPPORTED, "completion times are recorded by persistent runs only");
+  const int n = b->ninst;
+  std::vector<unsigned long long> t(n + 1);
+  int prog[4] = {0, 0, 0, 0};
+  DEV_CHECK(ctx, hipMemcpyAsync(t.data(), b->ps.t_end, sizeof(unsigned long long) * n, hipMemcpyDeviceToHost, ctx->stream));
+  DEV_CHECK(ctx, hipMemcpyAsync(t.data() + n, b->ps.t_start, sizeof(unsigned long long), hipMemcpyDeviceToHost, ctx->stream));
+  DEV_CHECK(ctx, hipMemcpyAsync(prog, b->ps.prog, sizeof(int) * 4, hipMemcpyDeviceToHost, ctx->stream));
+  DEV_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+  if (prog[2] != 0 || prog[1] != n)
+    return fail(ctx, PNOF_E_DEVICE, "the persistent batch run stalled (" + std::to_string(prog[1]) + " of " +
+                                        std::to_string(n) + " instances completed); its outputs are incomplete");
+  for (int i = 0; i < n; ++i) us[i] = (double)(t[i] - t[n]) * 1e3 / b->clock_khz;
+  return PNOF_OK;
+}
+
+pnof_status pnof_batch_set_stall(pnof_batch b, double microseconds) {
+  if (!b) return fail(nullptr, PNOF_E_ARG, "batch is NULL");
+  if (!(microseconds >= 0.0) || microseconds > 1e9) return fail(b->ctx, PNOF_E_ARG, "microseconds must be in [0, 1e9]");
+  b->stall_us = microseconds > 0.0 ? microseconds : 1e6;
+  batch_drop_graph(b);
   return PNOF_OK;
 }
 

@@ -59,6 +59,73 @@ __device__ inline double grad_n_term(int p, int q, double np_, double nq, double
   return s;
 }
 
+// ---------------------------------------------------------------- ON maps (Section 3.1)
+__device__ inline double sigm(double x) { return 1.0 / (1.0 + exp(-x)); }
+
+// Adjoint of the ON map for subspace g (pair g < npairs, or a singly occupied orbital): the entries
+// out[r] = sum_p dEdn[p] dn_p/dgamma_r of the gamma variables of that subspace.  kind 0: sigmoid map
+// normalised per pair (one gamma per active orbital); kind 1: trigonometric map (Eqs. soo, woo).
+__device__ inline void on_map_vjp_subspace(int kind, int npairs, int ncwo, int nsingle, const double* __restrict__ gamma,
+                                           const double* __restrict__ dEdn, double* __restrict__ out, int g) {
+  if (g >= npairs) {   // a singly occupied orbital: n = 1/2 whatever its gamma (sigmoid map; none in the other)
+    if (kind == 0 && g < npairs + nsingle) out[g] = 0.0;
+    return;
+  }
+  if (kind == 0) {
+    double S = sigm(gamma[g]);
+    for (int k = 0; k < ncwo; ++k) S += sigm(gamma[weak_index(g, k, npairs, ncwo, nsingle)]);
+    // dE/dgamma_r = s'_r / S * (dEdn_r - sum_p n_p dEdn_p)
+    double avg = 0.0;
+    for (int a = -1; a < ncwo; ++a) {
+      const int p = a < 0 ? g : weak_index(g, a, npairs, ncwo, nsingle);
+      avg += sigm(gamma[p]) / S * dEdn[p];
+    }
+    for (int b = -1; b < ncwo; ++b) {
+      const int r = b < 0 ? g : weak_index(g, b, npairs, ncwo, nsingle);
+      const double sr = sigm(gamma[r]);
+      out[r] = sr * (1.0 - sr) / S * (dEdn[r] - avg);
+    }
+  } else {
+    // n_i = h * prod_{k<i} c_k^2 * f_i, f_i = s_i^2 (f = 1 for the last weak orbital),
+    // c_k = cos(gamma_k), s_k = sin(gamma_k) of the pair's weak variables; h = sin^2(gamma_g)/2.
+    const double gs = gamma[g];
+    const double cg = cos(gs), sg = sin(gs);
+    const double h = 0.5 * sg * sg, dh = sg * cg;
+    const int base = npairs + g * (ncwo - 1);
+    double acc_g = -cg * sg * dEdn[g];
+    double prod = 1.0;
+    for (int i = 0; i < ncwo; ++i) {
+      const bool last = (i == ncwo - 1);
+      const double si = last ? 0.0 : sin(gamma[base + i]);
+      const double fi = last ? 1.0 : si * si;
+      acc_g += dh * prod * fi * dEdn[weak_index(g, i, npairs, ncwo, nsingle)];
+      if (!last) { const double ci = cos(gamma[base + i]); prod *= ci * ci; }
+    }
+    out[g] = acc_g;
+    for (int j = 0; j < ncwo - 1; ++j) {
+      const double cj = cos(gamma[base + j]), sj = sin(gamma[base + j]);
+      double sum = 0.0;
+      for (int i = j; i < ncwo; ++i) {
+        const bool last = (i == ncwo - 1);
+        double other = h;                           // prod over k < i, k != j of c_k^2
+        for (int k = 0; k < i; ++k) {
+          if (k == j) continue;
+          const double ck = cos(gamma[base + k]);
+          other *= ck * ck;
+        }
+        double d;
+        if (i == j) d = other * 2.0 * sj * cj;      // d(s_j^2)
+        else {
+          const double si = last ? 0.0 : sin(gamma[base + i]);
+          d = other * (-2.0 * cj * sj) * (last ? 1.0 : si * si);  // d(c_j^2) * f_i
+        }
+        sum += d * dEdn[weak_index(g, i, npairs, ncwo, nsingle)];
+      }
+      out[base + j] = sum;
+    }
+  }
+}
+
 // sum_{k < ns} p[k * stride], added in order of k, with the loads issued eight at a time: the partial
 // sums of a split contraction lie far apart in memory, and with one load in flight per thread the
 // reduction would wait out the memory latency once per split.
@@ -384,6 +451,9 @@ struct BInst {
   u16 *ch16, *cl16;     // split mode: fp16 pair of C~ sC (the b contraction's operand)
   uint32_t* bnd;        // split mode: scale bounds (SCL_CALL call-level words, then the words of B)
   float* colb;          // split mode: per-orbital bounds (4 nact)
+  const double* gamma;  // optional: ON-map variables (on_kind), for dE/dgamma
+  double* dEdgamma;     // optional output
+  int on_kind;
 };
 // Blocks per instance that sum the energy (each writes one partial to epart).
 constexpr int BATCH_EPARTS = 32;
@@ -401,6 +471,51 @@ hipError_t batch_add_diag(hipStream_t s, int ninst, const BInst* tab, const BMax
 hipError_t batch_reduce(hipStream_t s, int ninst, const BInst* tab, const BMax& mx);  // Y2e, K
 hipError_t batch_energy_y(hipStream_t s, int ninst, const BInst* tab, const BMax& mx);
 hipError_t batch_finish(hipStream_t s, int ninst, const BInst* tab, const BMax& mx);  // lambda cols, dE/dC, dE/dn, asym
+hipError_t batch_vjp(hipStream_t s, int ninst, const BInst* tab, const BMax& mx);     // dE/dgamma (instances with gamma)
+
+// ---------------------------------------------------------------- persistent batch kernel (k_gemm_bf16.hip)
+// One launch runs every step of every instance: blocks claim work items of an instance's current
+// phase (all items of the previous phase complete), in instance order.  Phases of one instance:
+enum {
+  PH_PREP = 0,   // scale bounds, alpha/beta, C split (one item)
+  PH_X,          // X tiles, then the float64 tiles of H C_A
+  PH_B,          // b tiles (64-wide), then H_pp (one item)
+  PH_DJ,         // float64 tiles of D alpha, then of J = D^T D
+  PH_DIAG,       // W diagonal
+  PH_Y,          // Y tiles
+  PH_RED,        // Y2e and K reductions
+  PH_EY,         // BATCH_EPARTS energy partials, then Y = n o (H C_A) + Y2e
+  PH_LAM,        // float64 tiles of lambda = C^T Y
+  PH_FIN,        // E, lambda columns, dE/dC, asymmetry, dE/dn
+  PH_VJP,        // dE/dgamma; the instance's completion time
+  PH_N
+};
+constexpr int PERSIST_PARTS = 8;   // items of the element-wise phases (W diagonal, reductions, Y, finish)
+constexpr int PERSIST_XG = 4;      // X tiles per work item (consecutive tiles share their rows of B)
+// Scheduling state (device memory, cleared by batch_persist before each run).
+struct PSched {
+  const int* cnt;                 // [ninst][PH_N] items of each phase
+  int* claim;                     // [ninst][PH_N] items handed out
+  int* done;                      // [ninst][PH_N] items completed
+  int* phase;                     // [ninst] first phase not complete
+  unsigned long long* t_end;      // [ninst] device wall clock when the instance completed
+  unsigned long long* t_start;    // device wall clock when the run started
+  int* prog;                      // [0] items completed, [1] instances completed, [2] stalled
+  unsigned long long stall_ticks; // device-clock ticks with no progress anywhere before a block gives up
+};
+struct PArgs {
+  int ninst, terms;
+  const BInst* inst;
+  const G1Args* g1;
+  const G2Args* g2;
+  const G3Args* g3;
+  const F64Gemm* f64;             // [4][ninst]: H C_A, D alpha, D^T D, C^T Y
+  PSched sc;
+};
+// Items of instance i in each phase for X / Y tile widths tx, ty (the b contraction runs 64-wide).
+void persist_counts(const BInst& d, const G1Args& g1, const G2Args& g2, const G3Args& g3, int tx, int ty, int* cnt);
+// Clears the scheduling state, stamps the start and runs the persistent kernel (grid: blocks).
+hipError_t batch_persist(hipStream_t s, const PArgs& a, int ninst_state_words, int tx, int ty, int blocks);
 
 // ---------------------------------------------------------------- small kernels (k_small.hip)
 hipError_t fill_f64(hipStream_t s, double* p, long long n, double v);

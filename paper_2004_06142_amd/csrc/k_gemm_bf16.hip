@@ -25,7 +25,9 @@
 // items sharing an operand (same P, or same split of P) run on the same XCD and share its L2.
 #include <type_traits>
 
+#include "batch_dev.h"
 #include "common.h"
+#include "f64_tile.h"
 
 namespace pnof {
 namespace {
@@ -356,6 +358,18 @@ struct Ring {
   u16 b[S][BLO ? 2 : 1][BN * BK];
 };
 
+// The ring of a contraction body: the caller's (EXT: e.g. one union shared by the bodies of a
+// persistent kernel, ext pointing into LDS) or the body's own static LDS.
+template <typename RT, bool EXT>
+__device__ __forceinline__ RT& ring_of(void* ext) {
+  if constexpr (EXT) {
+    return *reinterpret_cast<RT*>(ext);
+  } else {
+    __shared__ RT sm;
+    return sm;
+  }
+}
+
 // Contraction over segments seg = 0..nseg-1 and k in [kb, ke) of each; ACOL / BCOL fix the storage
 // order of the operands at compile time.
 // ILV: the k-tile's products run row block by row block (i-major), with the A fragments of block
@@ -534,8 +548,11 @@ __device__ __forceinline__ int find_instance(const int* __restrict__ off, int ni
 // epilogue's stores then stall the next P's operand waits, as the vector-memory counter retires loads
 // and stores in order).
 // STACK: the n-tiles run over the stacked rows (P, mu) of all np rows of B.
-template <int TERMS, bool BLO, int G1M, int G1N, int WGM, int WGN, int MINB, bool VEC, bool STACK>
-__device__ __forceinline__ void gemm1_body(int w, const G1Args& g) {
+// EXT / ext: the ring is the caller's (see ring_of); BUDGET: LDS bytes for the ring (0: the whole
+// unit's LDS shared by MINB blocks).
+template <int TERMS, bool BLO, int G1M, int G1N, int WGM, int WGN, int MINB, bool VEC, bool STACK, bool EXT = false,
+          int BUDGET = 0>
+__device__ __forceinline__ void gemm1_body(int w, const G1Args& g, void* ext = nullptr) {
   constexpr bool ALO = TERMS >= 2;
   constexpr int MI = G1M / (16 * WGM), NI = G1N / (16 * WGN);
   const int nbf = g.nbf, nact = g.nact, ldx = g.ldx;
@@ -588,8 +605,8 @@ __device__ __forceinline__ void gemm1_body(int w, const G1Args& g) {
   };
   if constexpr (VEC) {
     // the LDS of one compute unit is shared by MINB blocks
-    constexpr int S = ring_depth(G1M, G1N, ALO, BLO, MINB == 2 ? 81920 : 163840);
-    __shared__ Ring<G1M, G1N, ALO, BLO, S> sm;
+    constexpr int S = ring_depth(G1M, G1N, ALO, BLO, BUDGET > 0 ? BUDGET : (MINB == 2 ? 81920 : 163840));
+    auto& sm = ring_of<Ring<G1M, G1N, ALO, BLO, S>, EXT>(ext);
     auto A = [&](int) { return DOpnd{g.ct_hi, g.ct_lo, g.ldk, g.ws.ct_bytes}; };
     auto B = [&](int) {
       const long long o = (long long)P * g.bstride;
@@ -618,8 +635,8 @@ constexpr int g2_wgn(bool vec) { return vec ? 4 : 2; }
 
 // TT: the square tile (128, or 64 for the short active spaces of batch instances, with 4 waves).
 // KSET: store the K sums instead of adding them (a launch that covers every P of the problem).
-template <int TERMS, bool VEC, int TT = T2, bool KSET = false>
-__device__ __forceinline__ void gemm2_body(int w, const G2Args& g) {
+template <int TERMS, bool VEC, int TT = T2, bool KSET = false, bool EXT = false, int BUDGET = 0>
+__device__ __forceinline__ void gemm2_body(int w, const G2Args& g, void* ext = nullptr) {
   constexpr bool LO = TERMS >= 3;
   // the direct-load form of the 128 tile runs 8 waves (2 x 4, each 64 x 32): half the accumulators,
   // beta and K sums per wave, so they stay in registers, and two waves per SIMD hide each other's
@@ -709,8 +726,8 @@ __device__ __forceinline__ void gemm2_body(int w, const G2Args& g) {
       }
   };
   if constexpr (VEC) {
-    constexpr int S = ring_depth(TT, TT, LO, LO, TT == 128 ? 163840 : 81920);
-    __shared__ Ring<TT, TT, LO, LO, S> sm;
+    constexpr int S = ring_depth(TT, TT, LO, LO, BUDGET > 0 ? BUDGET : (TT == 128 ? 163840 : 81920));
+    auto& sm = ring_of<Ring<TT, TT, LO, LO, S>, EXT>(ext);
     auto A = [&](int) { return DOpnd{g.ct_hi, g.ct_lo, g.ldk, g.ws.ct_bytes}; };
     auto B = [&](int seg) {
       const long long off = (long long)(pb + seg) * g.ws.nact32 * ldx;
@@ -750,8 +767,8 @@ __device__ __forceinline__ void gemm2_body(int w, const G2Args& g) {
 // matrix-core products one byte read from LDS feeds: a 64 x 64 wave reads 16 KB per k-tile for 48
 // products, a 128 x 64 wave 24 KB for 96; LDS bandwidth (about 128 bytes per clock per compute unit)
 // is what limits the 64 x 64 form.
-template <int TERMS, int G3M, int G3N, int WGM, int WGN, int MINB, bool VEC>
-__device__ __forceinline__ void gemm3_body(int w, const G3Args& g) {
+template <int TERMS, int G3M, int G3N, int WGM, int WGN, int MINB, bool VEC, bool EXT = false, int BUDGET = 0>
+__device__ __forceinline__ void gemm3_body(int w, const G3Args& g, void* ext = nullptr) {
   constexpr bool LO = TERMS >= 3;
   constexpr int MI = G3M / (16 * WGM), NI = G3N / (16 * WGN);
   const int nbf = g.nbf, nact = g.nact, np = g.np, nsplit = g.nsplit, ldx = g.ldx, ldw = g.ldw;
@@ -767,8 +784,8 @@ __device__ __forceinline__ void gemm3_body(int w, const G3Args& g) {
   if constexpr (VEC) {
     // the 128 x 128 tile runs two blocks per compute unit (two-stage ring each): while one block
     // waits on its fragment reads or barrier, the other keeps the matrix cores busy
-    constexpr int S = ring_depth(G3M, G3N, LO, LO, MINB == 2 ? 81920 : 163840);
-    __shared__ Ring<G3M, G3N, LO, LO, S> sm;
+    constexpr int S = ring_depth(G3M, G3N, LO, LO, BUDGET > 0 ? BUDGET : (MINB == 2 ? 81920 : 163840));
+    auto& sm = ring_of<Ring<G3M, G3N, LO, LO, S>, EXT>(ext);
     auto A = [&](int seg) {
       const long long off = (long long)(pb + seg) * g.ws.nact32 * ldx;
       return DOpnd{g.xt_hi + off, LO ? g.xt_lo + off : nullptr, ldx, g.ws.xt_bytes - 2 * off};
@@ -855,6 +872,244 @@ __global__ __launch_bounds__(256, 2) void gemm3_grouped(const G3Args* __restrict
   const int i = find_instance(off, ninst, w);
   const G3Args g = tab[i];
   gemm3_body<TERMS, 128, TN, 2, 2, 2, true>(w - off[i], g);
+}
+
+// ------------------------------------------------------------------------------------------
+// Persistent batch kernel.  Every block loops: claim a work item of the first instance (in index
+// order) whose current phase still has unclaimed items -- every item of the phases before it being
+// complete, a claimed item never waits -- run it, publish it.  The block that completes a phase's
+// last item moves the instance to the next phase; the instance's last phase stamps its completion
+// time.  A block that finds nothing to claim polls; once stall_ticks of the device clock pass with
+// no item completed anywhere it raises the stall flag and exits, and the others exit on seeing the
+// flag, so every block ends whatever happens.  Releases and acquires are device-scope fences (the
+// instances' items run on every XCD).
+constexpr int PBUDGET = 79872;   // LDS of the largest ring; with the small arrays, two blocks per unit
+
+template <int TX, int TY>
+union PersistLds {
+  Ring<TX, 128, true, false, ring_depth(TX, 128, true, false, PBUDGET)> x;
+  Ring<64, 64, true, true, ring_depth(64, 64, true, true, PBUDGET)> b;
+  Ring<128, TY, true, true, ring_depth(128, TY, true, true, PBUDGET)> y;
+  f64t::F64Smem f;
+};
+
+__device__ __forceinline__ int ld_dev(const int* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+__device__ __forceinline__ int ld_uni(const int* p) { return __builtin_amdgcn_readfirstlane(ld_dev(p)); }
+
+// The prep item (one block): the call-level scale bounds reduced in LDS (the grouped launches take
+// two launches and a global array for them; the words are the same), then alpha, beta and C's split.
+__device__ inline void persist_prep(const BInst& d) {
+  __shared__ uint32_t m[4];
+  if (threadIdx.x < 4) m[threadIdx.x] = 0u;
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  for (int q = threadIdx.x >> 6; q < d.nact; q += blockDim.x >> 6) {
+    double s1 = 0.0, cm = 0.0, sa = 0.0, bm = 0.0;
+    for (int mu = lane; mu < d.nbf; mu += 64) {
+      const double c = fabs(d.C[(long long)mu * d.nbf + q]);
+      s1 += c;
+      cm = fmax(cm, c);
+    }
+    for (int r = lane; r < d.nact; r += 64) {
+      double a, b;
+      pnof_coeff(q, r, d.n[q], d.n[r], d.npairs, d.ncwo, d.nsingle, d.functional, a, b);
+      sa += fabs(a);
+      bm = fmax(bm, fabs(b));
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      s1 += __shfl_down(s1, off, 64);
+      sa += __shfl_down(sa, off, 64);
+      cm = fmax(cm, __shfl_down(cm, off, 64));
+      bm = fmax(bm, __shfl_down(bm, off, 64));
+    }
+    if (lane == 0) {
+      atomicMax(&m[0], __float_as_uint((float)s1));
+      atomicMax(&m[1], __float_as_uint((float)cm));
+      atomicMax(&m[2], __float_as_uint((float)sa));
+      atomicMax(&m[3], __float_as_uint((float)bm));
+    }
+  }
+  __syncthreads();
+  const uint32_t w0 = m[1], w1 = m[0], w2 = __float_as_uint(__uint_as_float(m[3]) + __uint_as_float(m[2]));
+  if (threadIdx.x == 0) {
+    d.bnd[0] = w0;
+    d.bnd[1] = w1;
+    d.bnd[2] = w2;
+  }
+  // sC exactly as chunk_scales forms it from bnd[0]
+  bdev::prep(d, 0, 1, ldexpf(1.0f, 13 - bound_exp(__uint_as_float(w0) * 1.01f)));
+}
+
+template <int TX, int TY>
+__device__ __forceinline__ void persist_item(const PArgs& a, int i, int ph, int idx, void* lds) {
+  const BInst& d = a.inst[i];
+  f64t::F64Smem& fs = *reinterpret_cast<f64t::F64Smem*>(lds);
+  const int n = a.ninst;
+  switch (ph) {
+    case PH_PREP:
+      persist_prep(d);
+      break;
+    case PH_X: {
+      const G1Args g = a.g1[i];
+      const int nt = g1_items(g, TX, 128, true), nx = cdiv(nt, PERSIST_XG);
+      if (idx < nx) {
+        const int t0 = idx * PERSIST_XG, t1 = t0 + PERSIST_XG < nt ? t0 + PERSIST_XG : nt;
+        for (int t = t0; t < t1; ++t) {
+          if (t > t0) __syncthreads();   // the ring of the tile before is free again
+          gemm1_body<2, false, TX, 128, 2, 2, 2, true, true, true, PBUDGET>(t, g, lds);
+        }
+      } else {
+        f64t::grouped_tile<false, true>(a.f64[i], idx - nx, fs);                           // H C_A
+      }
+      break;
+    }
+    case PH_B: {
+      const G2Args g = a.g2[i];
+      const int nb = g2_items(g, 64);
+      if (idx < nb) gemm2_body<3, true, 64, true, true, PBUDGET>(idx, g, lds);
+      else bdev::hpp(d, 0, 1);
+      break;
+    }
+    case PH_DJ: {
+      const int nd = f64t::grouped_tiles(d.naux, d.nact);
+      if (idx < nd) f64t::grouped_tile<false, true>(a.f64[n + i], idx, fs);                // D alpha
+      else f64t::grouped_tile<true, true>(a.f64[2 * n + i], idx - nd, fs);                // J = D^T D
+      break;
+    }
+    case PH_DIAG:
+      bdev::add_diag(d, idx, PERSIST_PARTS);
+      break;
+    case PH_Y: {
+      const G3Args g = a.g3[i];
+      gemm3_body<3, 128, TY, 2, 2, 2, true, true, PBUDGET>(idx, g, lds);
+      break;
+    }
+    case PH_RED:
+      bdev::reduce(d, idx, PERSIST_PARTS);
+      break;
+    case PH_EY:
+      if (idx < BATCH_EPARTS) bdev::energy_part(d, idx);
+      else bdev::y_assemble(d, idx - BATCH_EPARTS, PERSIST_PARTS);
+      break;
+    case PH_LAM:
+      f64t::grouped_tile<true, true>(a.f64[3 * n + i], idx, fs);                          // lambda = C^T Y
+      break;
+    case PH_FIN:
+      bdev::finish(d, idx, PERSIST_PARTS);
+      break;
+    default:
+      bdev::vjp(d, 0, 1);
+      break;
+  }
+}
+
+// The scheduling runs in wavefront 0 as a whole; the other wavefronts wait at the barrier.  Lane l
+// of wavefront 0 looks at instance base + l, a ballot picks the first instance with unclaimed items
+// of its open phase, and lane 0 alone performs the atomics (every value the lanes branch on is
+// uniform).  Publishing an item and claiming the next form a single region of wavefront 0 at the top
+// of the loop, so that no code path of the loop distinguishes lanes of one wavefront around a
+// barrier: were the two separate lane-0 regions on either side of the loop's back edge, the compiler
+// may join them into one and leave lanes 1..63 cycling through the barriers without lane 0.
+// Memory ordering: a block's wavefronts wait for their own stores before the barrier that ends an
+// item; wavefront 0 then writes the XCD's L2 back (device-scope release) before counting the item
+// done, and invalidates its caches (device-scope acquire) after claiming, before the barrier that
+// starts the next item.
+template <int TX, int TY>
+__global__ __launch_bounds__(256, 2) void batch_persist_k(PArgs a) {
+  __shared__ PersistLds<TX, TY> u;
+  __shared__ int s_it[3];
+  const PSched& sc = a.sc;
+  const int lane = threadIdx.x;   // in wavefront 0
+  const bool lead = threadIdx.x == 0;
+  int last = -1;   // state word (instance * PH_N + phase) of the item this block completed last
+  for (;;) {
+    if (threadIdx.x < 64) {
+      if (last >= 0) {   // publish it
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (lead) {
+          const int dn = atomicAdd(sc.done + last, 1) + 1;
+          if (dn == sc.cnt[last]) {
+            const int i = last / PH_N, ph = last % PH_N;
+            if (ph + 1 == PH_N) sc.t_end[i] = wall_clock64();
+            __threadfence();
+            atomicExch(sc.phase + i, ph + 1);
+            if (ph + 1 == PH_N) atomicAdd(sc.prog + 1, 1);
+          }
+          atomicAdd(sc.prog, 1);
+        }
+      }
+      int inst = -1, ph = 0, idx = 0;
+      int seen = ld_uni(sc.prog);
+      unsigned long long t_seen = wall_clock64();
+      for (;;) {
+        if (ld_uni(sc.prog + 1) >= a.ninst || ld_uni(sc.prog + 2) != 0) break;
+        for (int base = 0; base < a.ninst && inst < 0; base += 64) {
+          const int i = base + lane;
+          int p = PH_N, k = 0, cnt = 0;
+          bool open = false;
+          if (i < a.ninst) {
+            p = ld_dev(sc.phase + i);
+            if (p < PH_N) {
+              k = i * PH_N + p;
+              cnt = sc.cnt[k];
+              open = ld_dev(sc.claim + k) < cnt;
+            }
+          }
+          unsigned long long m = __ballot(open);
+          while (m) {
+            const int l = __ffsll((long long)m) - 1;
+            const int kk = __builtin_amdgcn_readlane(k, l), cc = __builtin_amdgcn_readlane(cnt, l);
+            int c = 0;
+            if (lead) c = atomicAdd(sc.claim + kk, 1);
+            c = __builtin_amdgcn_readlane(c, 0);
+            if (c < cc) {
+              inst = base + l;
+              ph = __builtin_amdgcn_readlane(p, l);
+              idx = c;
+              break;
+            }
+            m &= m - 1;   // that phase ran out meanwhile: the next instance
+          }
+        }
+        if (inst >= 0) break;
+        __builtin_amdgcn_s_sleep(8);
+        const int now = ld_uni(sc.prog);
+        const unsigned long long t = wall_clock64();
+        if (now != seen) {
+          seen = now;
+          t_seen = t;
+        } else if (t - t_seen > sc.stall_ticks) {
+          if (lead) atomicExch(sc.prog + 2, 1);
+          break;
+        }
+      }
+      if (inst >= 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      if (lead) {
+        s_it[0] = inst;
+        s_it[1] = ph;
+        s_it[2] = idx;
+      }
+    }
+    __syncthreads();
+    const int inst = __builtin_amdgcn_readfirstlane(s_it[0]), ph = __builtin_amdgcn_readfirstlane(s_it[1]),
+              idx = __builtin_amdgcn_readfirstlane(s_it[2]);
+    if (inst < 0) return;
+    persist_item<TX, TY>(a, inst, ph, idx, &u);
+    __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));   // this wavefront's stores have reached L2
+    __syncthreads();
+    last = inst * PH_N + ph;
+  }
+}
+
+// Clears the scheduling state of a run and stamps its start.
+__global__ void persist_reset_k(PSched sc, int nwords_inst, int ninst) {
+  for (int i = threadIdx.x; i < nwords_inst; i += blockDim.x) {
+    sc.claim[i] = 0;
+    sc.done[i] = 0;
+  }
+  for (int i = threadIdx.x; i < ninst; i += blockDim.x) sc.phase[i] = 0;
+  if (threadIdx.x < 3) sc.prog[threadIdx.x] = 0;
+  if (threadIdx.x == 0) *sc.t_start = wall_clock64();
 }
 
 inline dim3 xcd_grid(long long items) { return dim3((unsigned)(cdiv(items, NXCD) * NXCD)); }
@@ -991,6 +1246,35 @@ hipError_t df_bf16_gemm3_grouped(hipStream_t s, int ninst, int total, int terms,
     if (terms == 1) hipLaunchKernelGGL((gemm3_grouped<1, 128>), gr, dim3(256), 0, s, tab, off, ninst, total);
     else hipLaunchKernelGGL((gemm3_grouped<3, 128>), gr, dim3(256), 0, s, tab, off, ninst, total);
   }
+  return hipGetLastError();
+}
+
+}  // namespace pnof
+
+namespace pnof {
+
+void persist_counts(const BInst& d, const G1Args& g1, const G2Args& g2, const G3Args& g3, int tx, int ty, int* cnt) {
+  cnt[PH_PREP] = 1;
+  cnt[PH_X] = cdiv(g1_items(g1, tx, 128, true), PERSIST_XG) + f64t::grouped_tiles(d.nbf, d.nact);
+  cnt[PH_B] = g2_items(g2, 64) + 1;
+  cnt[PH_DJ] = f64t::grouped_tiles(d.naux, d.nact) + f64t::grouped_tiles(d.nact, d.nact);
+  cnt[PH_DIAG] = PERSIST_PARTS;
+  cnt[PH_Y] = g3_items(g3, 128, ty);
+  cnt[PH_RED] = PERSIST_PARTS;
+  cnt[PH_EY] = BATCH_EPARTS + PERSIST_PARTS;
+  cnt[PH_LAM] = f64t::grouped_tiles(d.nbf, d.nact);
+  cnt[PH_FIN] = PERSIST_PARTS;
+  cnt[PH_VJP] = 1;
+}
+
+hipError_t batch_persist(hipStream_t s, const PArgs& a, int ninst_state_words, int tx, int ty, int blocks) {
+  hipLaunchKernelGGL(persist_reset_k, dim3(1), dim3(256), 0, s, a.sc, ninst_state_words, a.ninst);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (tx == 64 && ty == 64) hipLaunchKernelGGL((batch_persist_k<64, 64>), dim3(blocks), dim3(256), 0, s, a);
+  else if (tx == 64) hipLaunchKernelGGL((batch_persist_k<64, 128>), dim3(blocks), dim3(256), 0, s, a);
+  else if (ty == 64) hipLaunchKernelGGL((batch_persist_k<128, 64>), dim3(blocks), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((batch_persist_k<128, 128>), dim3(blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

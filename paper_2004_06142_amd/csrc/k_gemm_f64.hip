@@ -7,94 +7,12 @@
 // sits in component j of lane l).  Register prefetch of the next k-slab overlaps global loads
 // with the matrix-core work.
 #include "common.h"
+#include "f64_tile.h"
 
 namespace pnof {
 namespace {
 
-constexpr int TM = 64, TN = 64, TK = 16, LPAD = 2;
-
-struct F64Smem {
-  double a[TK][TM + LPAD];
-  double b[TK][TN + LPAD];
-};
-
-// Strided view helper: element (r, k) of an operand, with r the output-side index.
-template <bool RCONTIG>
-__device__ __forceinline__ void load_slab(const double* __restrict__ P, long long sr, long long sk,
-                                          int R, int K, int r0, int k0, double (&reg)[4]) {
-  const int t = threadIdx.x;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    int r, k;
-    if (RCONTIG) { r = t & 63; k = (t >> 6) + 4 * i; }
-    else         { r = t >> 2; k = ((t & 3) << 2) + i; }
-    const int gr = r0 + r, gk = k0 + k;
-    reg[i] = (gr < R && gk < K) ? P[(long long)gr * sr + (long long)gk * sk] : 0.0;
-  }
-}
-
-template <bool RCONTIG>
-__device__ __forceinline__ void store_slab(double (*S)[TM + LPAD], const double (&reg)[4]) {
-  const int t = threadIdx.x;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    int r, k;
-    if (RCONTIG) { r = t & 63; k = (t >> 6) + 4 * i; }
-    else         { r = t >> 2; k = ((t & 3) << 2) + i; }
-    S[k][r] = reg[i];
-  }
-}
-
-// acc[mi][ni] += A(m0.., :) B(:, n0..) over k in [kb, ke).
-template <bool AM, bool BN>
-__device__ __forceinline__ void tile_f64(F64Smem& sm, const double* __restrict__ A, long long sam,
-                                         long long sak, const double* __restrict__ B, long long sbk,
-                                         long long sbn, int M, int N, int kb, int ke, int m0, int n0,
-                                         f64x4 (&acc)[2][2]) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  const int K = ke;
-  double ra[4], rb[4];
-  load_slab<AM>(A, sam, sak, M, K, m0, kb, ra);
-  load_slab<BN>(B, sbn, sbk, N, K, n0, kb, rb);
-  for (int k0 = kb; k0 < ke; k0 += TK) {
-    __syncthreads();
-    store_slab<AM>(sm.a, ra);
-    store_slab<BN>(sm.b, rb);
-    __syncthreads();
-    if (k0 + TK < K) {
-      load_slab<AM>(A, sam, sak, M, K, m0, k0 + TK, ra);
-      load_slab<BN>(B, sbn, sbk, N, K, n0, k0 + TK, rb);
-    }
-#pragma unroll
-    for (int kk = 0; kk < TK; kk += 4) {
-      const int kr = kk + (lane >> 4);
-      double a0 = sm.a[kr][wm + (lane & 15)], a1 = sm.a[kr][wm + 16 + (lane & 15)];
-      double b0 = sm.b[kr][wn + (lane & 15)], b1 = sm.b[kr][wn + 16 + (lane & 15)];
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
-    }
-  }
-}
-
-__device__ __forceinline__ void zero_acc(f64x4 (&acc)[2][2]) {
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
-}
-
-// Row / column of component j of acc[mi][ni] relative to the block tile origin.
-__device__ __forceinline__ int acc_row(int mi, int j) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  return (wave >> 1) * 32 + mi * 16 + (lane >> 4) + 4 * j;
-}
-__device__ __forceinline__ int acc_col(int ni) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  return (wave & 1) * 32 + ni * 16 + (lane & 15);
-}
+using namespace f64t;
 
 template <bool AM, bool BN>
 __global__ __launch_bounds__(256) void gemm_f64_kernel(int M, int N, int K, double alpha,
@@ -130,25 +48,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(int M, int N, int K, doub
 template <bool AM, bool BN>
 __global__ __launch_bounds__(256) void gemm_f64_grouped_kernel(const F64Gemm* __restrict__ tab) {
   __shared__ F64Smem sm;
-  const F64Gemm g = tab[blockIdx.y];
-  const int tiles_n = (g.N + TN - 1) / TN;
-  if ((int)blockIdx.x >= tiles_n * ((g.M + TM - 1) / TM)) return;
-  const int m0 = (blockIdx.x / tiles_n) * TM, n0 = (blockIdx.x % tiles_n) * TN;
-  f64x4 acc[2][2];
-  zero_acc(acc);
-  tile_f64<AM, BN>(sm, g.A, g.sam, g.sak, g.B, g.sbk, g.sbn, g.M, g.N, 0, g.K, m0, n0, acc);
-#pragma unroll
-  for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-    for (int ni = 0; ni < 2; ++ni)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int m = m0 + acc_row(mi, j), n = n0 + acc_col(ni);
-        if (m < g.M && n < g.N) {
-          double* c = g.C + (long long)m * g.scm + (long long)n * g.scn;
-          *c = g.alpha * acc[mi][ni][j] + (g.beta != 0.0 ? g.beta * *c : 0.0);
-        }
-      }
+  grouped_tile<AM, BN>(tab[blockIdx.y], blockIdx.x, sm);
 }
 
 // Split-K form for products with few output tiles: block (tile, s) sums k in the s-th of ks equal

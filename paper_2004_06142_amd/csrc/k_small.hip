@@ -500,7 +500,6 @@ __global__ void grad_n_k(int nact, int npairs, int ncwo, int nsingle, int functi
   if (lane == 0) g[p] = 2.0 * Hpp[p] + (is_single(p, npairs, nsingle) ? 0.0 : K[(long long)p * nact + p]) + s;
 }
 
-__device__ inline double sigm(double x) { return 1.0 / (1.0 + exp(-x)); }
 
 // ON maps, one thread per pair (Section 3.1); singly occupied orbitals get n = 1/2 (their rows of
 // the Jacobian stay zero).
@@ -565,61 +564,7 @@ __global__ void on_map_k(int kind, int npairs, int ncwo, int nsingle, const doub
 __global__ void on_map_vjp_k(int kind, int npairs, int ncwo, int nsingle, const double* __restrict__ gamma,
                              const double* __restrict__ dEdn, double* __restrict__ out) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (kind == 0 && g < nsingle) out[npairs + g] = 0.0;
-  if (g >= npairs) return;
-  if (kind == 0) {
-    double S = sigm(gamma[g]);
-    for (int k = 0; k < ncwo; ++k) S += sigm(gamma[weak_index(g, k, npairs, ncwo, nsingle)]);
-    // dE/dgamma_r = s'_r / S * (dEdn_r - sum_p n_p dEdn_p)
-    double avg = 0.0;
-    for (int a = -1; a < ncwo; ++a) {
-      const int p = a < 0 ? g : weak_index(g, a, npairs, ncwo, nsingle);
-      avg += sigm(gamma[p]) / S * dEdn[p];
-    }
-    for (int b = -1; b < ncwo; ++b) {
-      const int r = b < 0 ? g : weak_index(g, b, npairs, ncwo, nsingle);
-      const double sr = sigm(gamma[r]);
-      out[r] = sr * (1.0 - sr) / S * (dEdn[r] - avg);
-    }
-  } else {
-    // n_i = h * prod_{k<i} c_k^2 * f_i, f_i = s_i^2 (f = 1 for the last weak orbital),
-    // c_k = cos(gamma_k), s_k = sin(gamma_k) of the pair's weak variables; h = sin^2(gamma_g)/2.
-    const double gs = gamma[g];
-    const double cg = cos(gs), sg = sin(gs);
-    const double h = 0.5 * sg * sg, dh = sg * cg;
-    const int base = npairs + g * (ncwo - 1);
-    double acc_g = -cg * sg * dEdn[g];
-    double prod = 1.0;
-    for (int i = 0; i < ncwo; ++i) {
-      const bool last = (i == ncwo - 1);
-      const double si = last ? 0.0 : sin(gamma[base + i]);
-      const double fi = last ? 1.0 : si * si;
-      acc_g += dh * prod * fi * dEdn[weak_index(g, i, npairs, ncwo, nsingle)];
-      if (!last) { const double ci = cos(gamma[base + i]); prod *= ci * ci; }
-    }
-    out[g] = acc_g;
-    for (int j = 0; j < ncwo - 1; ++j) {
-      const double cj = cos(gamma[base + j]), sj = sin(gamma[base + j]);
-      double sum = 0.0;
-      for (int i = j; i < ncwo; ++i) {
-        const bool last = (i == ncwo - 1);
-        double other = h;                           // prod over k < i, k != j of c_k^2
-        for (int k = 0; k < i; ++k) {
-          if (k == j) continue;
-          const double ck = cos(gamma[base + k]);
-          other *= ck * ck;
-        }
-        double d;
-        if (i == j) d = other * 2.0 * sj * cj;      // d(s_j^2)
-        else {
-          const double si = last ? 0.0 : sin(gamma[base + i]);
-          d = other * (-2.0 * cj * sj) * (last ? 1.0 : si * si);  // d(c_j^2) * f_i
-        }
-        sum += d * dEdn[weak_index(g, i, npairs, ncwo, nsingle)];
-      }
-      out[base + j] = sum;
-    }
-  }
+  if (g < npairs + nsingle) on_map_vjp_subspace(kind, npairs, ncwo, nsingle, gamma, dEdn, out, g);
 }
 
 // dst = src with a zero diagonal (the error vector of the DIIS extrapolation).
@@ -995,8 +940,7 @@ hipError_t on_map(hipStream_t s, int kind, int npairs, int ncwo, int nsingle, co
 }
 hipError_t on_map_vjp(hipStream_t s, int kind, int npairs, int ncwo, int nsingle, const double* gamma,
                       const double* dEdn, double* out) {
-  LAUNCH(on_map_vjp_k, dim3(cdiv(std::max(npairs, nsingle), 64)), dim3(64), kind, npairs, ncwo, nsingle, gamma, dEdn,
-         out);
+  LAUNCH(on_map_vjp_k, dim3(cdiv(npairs + nsingle, 64)), dim3(64), kind, npairs, ncwo, nsingle, gamma, dEdn, out);
 }
 hipError_t build_s(hipStream_t s, int nbf, const double* lam, const double* dprev, double zeta, double* S) {
   LAUNCH(build_s_k, grid1((long long)nbf * nbf), dim3(NT), nbf, lam, dprev, zeta, S);

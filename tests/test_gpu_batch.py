@@ -258,4 +258,4 @@ def test_batch_error_paths(ctx):
     b = P.Batch(ctx, [good])
     with pytest.raises(P.PnofError, match="PNOF_E_ARG"):
         b.run()
-    assert b.info()["launches"] == 15   # 13 + the two launches of the split mode's scale bounds
+    assert b.info()["launches"] == 16   # 14 (the last forms dE/dgamma) + the two of the split mode's scale bounds
