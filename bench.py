@@ -408,6 +408,8 @@ def cpu_protocol():
         sdev.fill_b(buf[:p1 - p0], inst.key, wl.nbf, wl.naux, p0)
         host = buf[:p1 - p0].to(torch.float64).cpu().numpy()
         gen[0] += time.perf_counter() - t0
+        if p0 % (8 * rows) == 0:
+            print(f"[cpu] c5_df1200 rows {p0}..{p1} of {wl.naux}", file=sys.stderr, flush=True)
         return host
 
     t0 = time.perf_counter()

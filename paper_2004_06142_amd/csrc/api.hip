@@ -924,6 +924,8 @@ struct pnof_batch_s {
   // persistent kernel: scheduling state (batch workspace), its graph, the last run's mode
   PSched ps{};
   int* d_cnt = nullptr;
+  int* d_order = nullptr;             // instances grouped by die (see batch_offsets)
+  int* d_xoff = nullptr;
   hipGraph_t pgraph = nullptr;
   hipGraphExec_t pexec = nullptr;
   int pblocks = 512;                  // two blocks per compute unit
@@ -994,9 +996,36 @@ hipError_t batch_offsets(pnof_batch b, hipStream_t s) {
     g3.nbf = g.nbf; g3.nact = g.nact; g3.nsplit = g.ns3;
     persist_counts(b->inst[i], g1, g2, g3, b->tile[0], b->tile[2], cnt.data() + (size_t)i * PH_N);
   }
+  // the persistent kernel runs each instance on one die: longest-first assignment of the instances'
+  // contraction work to the least loaded die, each die's instances in index order
+  std::vector<double> work(n);
+  for (int i = 0; i < n; ++i) {
+    const BatchGeom& g = b->geo[i];
+    work[i] = 2.0 * g.naux * g.nbf * g.nact * (g.nbf + 2.0 * g.nact);
+  }
+  std::vector<int> byw(n);
+  for (int i = 0; i < n; ++i) byw[i] = i;
+  std::stable_sort(byw.begin(), byw.end(), [&](int x, int y) { return work[x] > work[y]; });
+  std::vector<std::vector<int>> die(PERSIST_NXCD);
+  std::vector<double> load(PERSIST_NXCD, 0.0);
+  for (int i : byw) {
+    const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    die[x].push_back(i);
+    load[x] += work[i];
+  }
+  std::vector<int> order, xoff(PERSIST_NXCD + 1, 0);
+  for (int x = 0; x < PERSIST_NXCD; ++x) {
+    std::sort(die[x].begin(), die[x].end());
+    order.insert(order.end(), die[x].begin(), die[x].end());
+    xoff[x + 1] = (int)order.size();
+  }
   hipError_t e = hipMemcpyAsync(b->d_off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return e;
   e = hipMemcpyAsync(b->d_cnt, cnt.data(), sizeof(int) * cnt.size(), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(b->d_order, order.data(), sizeof(int) * n, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(b->d_xoff, xoff.data(), sizeof(int) * xoff.size(), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return e;
   return hipStreamSynchronize(s);   // off and cnt go out of scope
 }
@@ -1749,6 +1778,10 @@ pnof_status pnof_batch_plan(pnof_ctx ctx, int32_t ninst, const pnof_problem* pro
     b->ps.t_end = a.take<unsigned long long>(ninst);
     b->ps.t_start = a.take<unsigned long long>(1);
     b->ps.prog = a.take<int>(4);
+    b->d_order = a.take<int>(ninst);
+    b->d_xoff = a.take<int>(PERSIST_NXCD + 1);
+    b->ps.order = b->d_order;
+    b->ps.xoff = b->d_xoff;
     return a.off + 256;
   };
   for (int i = 0; i < ninst; ++i) {

@@ -881,8 +881,7 @@ __global__ __launch_bounds__(256, 2) void gemm3_grouped(const G3Args* __restrict
 // last item moves the instance to the next phase; the instance's last phase stamps its completion
 // time.  A block that finds nothing to claim polls; once stall_ticks of the device clock pass with
 // no item completed anywhere it raises the stall flag and exits, and the others exit on seeing the
-// flag, so every block ends whatever happens.  Releases and acquires are device-scope fences (the
-// instances' items run on every XCD).
+// flag, so every block ends whatever happens.
 constexpr int PBUDGET = 79872;   // LDS of the largest ring; with the small arrays, two blocks per unit
 
 template <int TX, int TY>
@@ -1003,51 +1002,55 @@ __device__ __forceinline__ void persist_item(const PArgs& a, int i, int ph, int 
   }
 }
 
+// Every instance runs on one die: a block reads the id of the die it runs on from the hardware and
+// claims items of that die's instances only.  All of an instance's intermediate data then stays in
+// one L2, so a block makes its item's stores visible by waiting for them to reach L2 (before the
+// barrier that ends the item) and sees the other blocks' stores after invalidating its compute
+// unit's L1 (after claiming); no L2 write-back or invalidation is needed.  The scheduling words are
+// touched with device-scope atomics and coherent loads only.
 // The scheduling runs in wavefront 0 as a whole; the other wavefronts wait at the barrier.  Lane l
-// of wavefront 0 looks at instance base + l, a ballot picks the first instance with unclaimed items
-// of its open phase, and lane 0 alone performs the atomics (every value the lanes branch on is
-// uniform).  Publishing an item and claiming the next form a single region of wavefront 0 at the top
-// of the loop, so that no code path of the loop distinguishes lanes of one wavefront around a
-// barrier: were the two separate lane-0 regions on either side of the loop's back edge, the compiler
-// may join them into one and leave lanes 1..63 cycling through the barriers without lane 0.
-// Memory ordering: a block's wavefronts wait for their own stores before the barrier that ends an
-// item; wavefront 0 then writes the XCD's L2 back (device-scope release) before counting the item
-// done, and invalidates its caches (device-scope acquire) after claiming, before the barrier that
-// starts the next item.
+// of wavefront 0 looks at the die's instance base + l, a ballot picks the first one with unclaimed
+// items of its open phase, and lane 0 alone performs the atomics (every value the lanes branch on
+// is uniform).  Publishing an item and claiming the next form a single region of wavefront 0 at
+// the top of the loop, so that no code path of the loop distinguishes lanes of one wavefront around
+// a barrier: were the two separate lane-0 regions on either side of the loop's back edge, the
+// compiler may join them into one and leave lanes 1..63 cycling through the barriers without lane 0.
+__device__ __forceinline__ int die_id() { return (int)__builtin_amdgcn_s_getreg((3 << 11) | 20); }   // XCC_ID[3:0]
+__device__ __forceinline__ void l1_invalidate() { asm volatile("buffer_inv sc0" ::: "memory"); }
+
 template <int TX, int TY>
 __global__ __launch_bounds__(256, 2) void batch_persist_k(PArgs a) {
   __shared__ PersistLds<TX, TY> u;
   __shared__ int s_it[3];
   const PSched& sc = a.sc;
+  const int die = die_id();
+  if (die >= PERSIST_NXCD) return;   // not a die the instances were spread over: nothing to claim
+  const int lo = __builtin_amdgcn_readfirstlane(sc.xoff[die]), hi = __builtin_amdgcn_readfirstlane(sc.xoff[die + 1]);
   const int lane = threadIdx.x;   // in wavefront 0
   const bool lead = threadIdx.x == 0;
   int last = -1;   // state word (instance * PH_N + phase) of the item this block completed last
   for (;;) {
     if (threadIdx.x < 64) {
-      if (last >= 0) {   // publish it
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        if (lead) {
-          const int dn = atomicAdd(sc.done + last, 1) + 1;
-          if (dn == sc.cnt[last]) {
-            const int i = last / PH_N, ph = last % PH_N;
-            if (ph + 1 == PH_N) sc.t_end[i] = wall_clock64();
-            __threadfence();
-            atomicExch(sc.phase + i, ph + 1);
-            if (ph + 1 == PH_N) atomicAdd(sc.prog + 1, 1);
-          }
-          atomicAdd(sc.prog, 1);
+      if (last >= 0 && lead) {   // publish it
+        const int dn = atomicAdd(sc.done + last, 1) + 1;
+        if (dn == sc.cnt[last]) {
+          const int i = last / PH_N, ph = last % PH_N;
+          if (ph + 1 == PH_N) __hip_atomic_store(sc.t_end + i, wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          atomicExch(sc.phase + i, ph + 1);
+          if (ph + 1 == PH_N) atomicAdd(sc.prog + 1, 1);
         }
+        atomicAdd(sc.prog, 1);
       }
       int inst = -1, ph = 0, idx = 0;
       int seen = ld_uni(sc.prog);
       unsigned long long t_seen = wall_clock64();
       for (;;) {
         if (ld_uni(sc.prog + 1) >= a.ninst || ld_uni(sc.prog + 2) != 0) break;
-        for (int base = 0; base < a.ninst && inst < 0; base += 64) {
-          const int i = base + lane;
-          int p = PH_N, k = 0, cnt = 0;
+        for (int base = lo; base < hi && inst < 0; base += 64) {
+          int i = -1, p = PH_N, k = 0, cnt = 0;
           bool open = false;
-          if (i < a.ninst) {
+          if (base + lane < hi) {
+            i = sc.order[base + lane];
             p = ld_dev(sc.phase + i);
             if (p < PH_N) {
               k = i * PH_N + p;
@@ -1063,7 +1066,7 @@ __global__ __launch_bounds__(256, 2) void batch_persist_k(PArgs a) {
             if (lead) c = atomicAdd(sc.claim + kk, 1);
             c = __builtin_amdgcn_readlane(c, 0);
             if (c < cc) {
-              inst = base + l;
+              inst = __builtin_amdgcn_readlane(i, l);
               ph = __builtin_amdgcn_readlane(p, l);
               idx = c;
               break;
@@ -1083,7 +1086,7 @@ __global__ __launch_bounds__(256, 2) void batch_persist_k(PArgs a) {
           break;
         }
       }
-      if (inst >= 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      if (inst >= 0) l1_invalidate();
       if (lead) {
         s_it[0] = inst;
         s_it[1] = ph;
