@@ -81,31 +81,6 @@ struct Arena {
   }
 };
 
-// C(m,n) = alpha sum_k A(m,k) B(k,n) + beta C(m,n) with the strided views of gemm_f64 (A(m,k) =
-// A[m*sam + k*sak], ...; one stride of each operand is 1), on rocBLAS's dgemm.  Used for the square
-// float64 products of the step (N^3 at N = 1200: 67-80 us against 124-130 us for gemm_f64; the
-// tall D^T D stays on gemm_f64, which is faster there).  rocBLAS is column-major: a row-major C is
-// formed as C^T = B^T A^T.
-pnof_status rb_dgemm(pnof_ctx ctx, int M, int N, int K, double alpha, const double* A, long long sam, long long sak,
-                     const double* B, long long sbk, long long sbn, double beta, double* C, long long scm,
-                     long long scn) {
-  if (scn == 1 && scm != 1) {   // row-major C: transposed problem
-    std::swap(M, N);
-    std::swap(A, B);
-    const long long a_m = sbn, a_k = sbk, b_k = sak, b_n = sam;
-    sam = a_m; sak = a_k; sbk = b_k; sbn = b_n;
-    std::swap(scm, scn);
-  }
-  const rocblas_operation ta = sam == 1 ? rocblas_operation_none : rocblas_operation_transpose;
-  const rocblas_operation tb = sbk == 1 ? rocblas_operation_none : rocblas_operation_transpose;
-  const long long lda = sam == 1 ? sak : sam, ldb = sbk == 1 ? sbn : sbk;
-  rocblas_set_pointer_mode(ctx->blas, rocblas_pointer_mode_host);
-  const rocblas_status st = rocblas_dgemm(ctx->blas, ta, tb, M, N, K, &alpha, A, (int)lda, B, (int)ldb, &beta, C,
-                                          (int)scn);
-  if (st != rocblas_status_success) return fail(ctx, PNOF_E_DEVICE, "rocblas_dgemm failed");
-  return PNOF_OK;
-}
-
 // The context's second stream (default priority) and the events that fork and join it.
 pnof_status ensure_aux(pnof_ctx ctx) {
   if (!ctx->aux) DEV_CHECK(ctx, hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
@@ -391,17 +366,16 @@ struct Req {
   bool need_y = false;   // Fock vectors (and everything built from them)
   bool need_e = false;
   // a workspace given by the call (the pchunk is lowered until the plan fits; nothing is allocated),
-  // the library's own float64 GEMM instead of rocBLAS, and every step on the context's stream
+  // and every step on the context's stream
   char* ws = nullptr;
   size_t ws_bytes = 0;
-  bool own_gemm = false;
   bool one_stream = false;
 };
 
-// Float64 product C = A B with the strided views of gemm_f64, on rocBLAS or the library's kernel.
-pnof_status dprod(pnof_ctx ctx, bool own, int M, int N, int K, const double* A, long long sam, long long sak,
-                  const double* B, long long sbk, long long sbn, double* C, long long scm, long long scn) {
-  if (!own) return rb_dgemm(ctx, M, N, K, 1.0, A, sam, sak, B, sbk, sbn, 0.0, C, scm, scn);
+// Float64 product C = A B with the strided views of gemm_f64 (A(m,k) = A[m*sam + k*sak], ...; one
+// stride of each operand is 1), on the context stream.
+pnof_status dprod(pnof_ctx ctx, int M, int N, int K, const double* A, long long sam, long long sak, const double* B,
+                  long long sbk, long long sbn, double* C, long long scm, long long scn) {
   DEV_CHECK(ctx, gemm_f64(ctx->stream, M, N, K, 1, 1.0, A, sam, sak, 0, B, sbk, sbn, 0, 0.0, C, scm, scn, 0));
   return PNOF_OK;
 }
@@ -452,7 +426,7 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
   if (have_n) DEV_CHECK(ctx, coeffs(s, nact, pl.npairs, pl.ncwo, pl.nsingle, pl.functional, n, b.alpha, b.beta, b.beta32));
   if (H) {
     // HC = H C_A ; Hpp = diag(C_A^T H C_A)
-    RB_CHECK(dprod(ctx, r.own_gemm, nbf, nact, nbf, H, nbf, 1, C, nbf, 1, b.HC, nact, 1));
+    RB_CHECK(dprod(ctx, nbf, nact, nbf, H, nbf, 1, C, nbf, 1, b.HC, nact, 1));
     DEV_CHECK(ctx, hpp_from_hc(s, nbf, nact, C, b.HC, b.Hpp));
     if (r.Hpp) DEV_CHECK(ctx, hipMemcpyAsync(r.Hpp, b.Hpp, sizeof(double) * nact, hipMemcpyDeviceToDevice, s));
   }
@@ -652,7 +626,7 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
   }
   if (want_y) DEV_CHECK(ctx, assemble_y(s, nbf, nact, n, b.HC, b.Y2e, Y));
   if (r.lam) {
-    RB_CHECK(dprod(ctx, r.own_gemm, nbf, nact, nbf, C, 1, nbf, Y, nact, 1, r.lam, nbf, 1));
+    RB_CHECK(dprod(ctx, nbf, nact, nbf, C, 1, nbf, Y, nact, 1, r.lam, nbf, 1));
     DEV_CHECK(ctx, zero_cols(s, nbf, nact, r.lam));
     if (r.asym) DEV_CHECK(ctx, max_asym(s, nbf, r.lam, b.partials + 256, r.asym));
   }
@@ -1366,7 +1340,6 @@ pnof_status pnof_lagrangian_noalloc(pnof_ctx ctx, const pnof_problem* prob, cons
   r.need_e = true;
   r.ws = static_cast<char*>(ws);
   r.ws_bytes = PNOF_STATIC_SCRATCH_BYTES;
-  r.own_gemm = true;
   r.one_stream = true;
   return run_step(ctx, prob, C, n, H, ints, r);
 }
@@ -1419,7 +1392,7 @@ pnof_status eigh(pnof_ctx ctx, int n, double* A, double* w, double* U, const Eig
   DEV_CHECK(ctx, hipStreamWaitEvent(s, ctx->join_ev, 0));   // joined on every path: Q uses the workspace
   if (rs != rocblas_status_success) return fail(ctx, PNOF_E_DEVICE, "rocsolver_dstedc failed to launch");
   // U = Q Z, all column-major
-  RB_CHECK(rb_dgemm(ctx, n, n, n, 1.0, ws.Q, 1, n, Z, 1, n, 0.0, U, 1, n));
+  RB_CHECK(dprod(ctx, n, n, n, ws.Q, 1, n, Z, 1, n, U, 1, n));
   return PNOF_OK;
 }
 }  // namespace
@@ -1455,7 +1428,7 @@ pnof_status pnof_orbital_step(pnof_ctx ctx, int32_t nbf, const double* lambda, c
   }
   DEV_CHECK(ctx, sign_fix_cols(s, nbf, U));
   // C_new[mu][j] = sum_i C[mu][i] U[i][j], U column-major: U[i][j] = U[j*nbf + i]
-  RB_CHECK(rb_dgemm(ctx, nbf, nbf, nbf, 1.0, C, nbf, 1, U, 1, nbf, 0.0, C_new, nbf, 1));
+  RB_CHECK(dprod(ctx, nbf, nbf, nbf, C, nbf, 1, U, 1, nbf, C_new, nbf, 1));
   DEV_CHECK(ctx, hipMemcpyAsync(ctx->host_info, info, sizeof(int), hipMemcpyDeviceToHost, s));
   DEV_CHECK(ctx, hipStreamSynchronize(s));
   if (*ctx->host_info != 0)
