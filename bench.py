@@ -28,15 +28,15 @@ KSRC = os.path.join(ROOT, "paper_2004_06142_amd", "csrc")
 # once the source changes the figure no longer applies and traffic is reported as null.
 TRAFFIC = {
     # profiles/c5_df1200_hbm_traffic.md: C5, bf16 split, 164-row chunks (read + written bytes per launch)
-    ("gemm1_kernel", 3): {"bytes": 1581566046 + 926101569,
+    ("gemm1_kernel", 3): {"bytes": 1664531384 + 925359060,
                           "plan": {"pchunk": 164, "x_variant": 3},
-                          "sha256": {"k_gemm_bf16.hip": "5aac520fb45d7991fd5bfbcff7868df8d56b0626576d23d037cdd4c7e0106188"}},
-    ("gemm2_kernel", 3): {"bytes": 3460111292 + 1144690217,
+                          "sha256": {"k_gemm_bf16.hip": "ae9c434c75ac9058141ece77248fe915d6eb348c8704695632be58c8ffb38a05"}},
+    ("gemm2_kernel", 3): {"bytes": 3407027309 + 1143925456,
                           "plan": {"pchunk": 164, "nsplit_b": 18},
-                          "sha256": {"k_gemm_bf16.hip": "5aac520fb45d7991fd5bfbcff7868df8d56b0626576d23d037cdd4c7e0106188"}},
-    ("gemm3_kernel", 3): {"bytes": 2747214750 + 241432962,
+                          "sha256": {"k_gemm_bf16.hip": "ae9c434c75ac9058141ece77248fe915d6eb348c8704695632be58c8ffb38a05"}},
+    ("gemm3_kernel", 3): {"bytes": 2749325195 + 241435180,
                           "plan": {"pchunk": 164, "nsplit_y": 10, "y_variant": 3},
-                          "sha256": {"k_gemm_bf16.hip": "5aac520fb45d7991fd5bfbcff7868df8d56b0626576d23d037cdd4c7e0106188"}},
+                          "sha256": {"k_gemm_bf16.hip": "ae9c434c75ac9058141ece77248fe915d6eb348c8704695632be58c8ffb38a05"}},
 }
 GOLDEN_C5 = os.path.join(ROOT, "tests", "golden", "c5_df1200_expected.json")
 

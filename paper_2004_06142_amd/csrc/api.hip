@@ -48,6 +48,11 @@ struct pnof_ctx_s {
   struct Ev { int stage; hipEvent_t a, b; };
   std::vector<Ev> evs;
   std::vector<hipEvent_t> pool;
+  // buffers of the driver calls (occupation and orbital optimisation, NOF-MP2 terms), kept from one
+  // call to the next and grown on demand, so that repeated calls allocate nothing
+  struct Slot { void* p; size_t bytes; };
+  std::vector<Slot> slots;
+  size_t slot_top = 0;
 };
 
 namespace {
@@ -653,26 +658,36 @@ pnof_status check_q(pnof_ctx ctx, const void* a, const int32_t* q_idx, int32_t n
 namespace {
 
 // ------------------------------------------------------------------------ optimisation drivers
-// Device buffers owned by one driver call (freed after the stream has drained).
+// Device buffers of one driver call, taken from the context's driver slots in call order (nested
+// calls take the slots above their caller's); a slot is reallocated only when a call needs more than
+// it holds (after the stream has drained), otherwise reused as is.
 struct DevBuf {
-  hipStream_t s;
-  std::vector<void*> ptrs;
+  pnof_ctx ctx;
+  size_t base;
   bool ok = true;
-  explicit DevBuf(hipStream_t st) : s(st) {}
-  ~DevBuf() {
-    hipStreamSynchronize(s);
-    for (void* p : ptrs) hipFree(p);
-  }
+  explicit DevBuf(pnof_ctx c) : ctx(c), base(c->slot_top) {}
+  ~DevBuf() { ctx->slot_top = base; }
   template <typename T>
   T* get(long long n) {
-    void* p = nullptr;
-    if (hipMalloc(&p, sizeof(T) * (size_t)std::max(1LL, n)) != hipSuccess) {
-      hipGetLastError();
-      ok = false;
-      return nullptr;
+    const size_t bytes = sizeof(T) * (size_t)std::max(1LL, n);
+    const size_t i = ctx->slot_top++;
+    if (i == ctx->slots.size()) ctx->slots.push_back({nullptr, 0});
+    pnof_ctx_s::Slot& sl = ctx->slots[i];
+    if (sl.bytes < bytes) {
+      if (sl.p) {
+        hipStreamSynchronize(ctx->stream);
+        hipFree(sl.p);
+        sl.p = nullptr;
+        sl.bytes = 0;
+      }
+      if (hipMalloc(&sl.p, bytes) != hipSuccess) {
+        hipGetLastError();
+        ok = false;
+        return nullptr;
+      }
+      sl.bytes = bytes;
     }
-    ptrs.push_back(p);
-    return static_cast<T*>(p);
+    return static_cast<T*>(sl.p);
   }
 };
 
@@ -1118,6 +1133,8 @@ void pnof_destroy(pnof_ctx ctx) {
     hipEventDestroy(e.b);
   }
   for (auto e : ctx->pool) hipEventDestroy(e);
+  for (auto& sl : ctx->slots)
+    if (sl.p) hipFree(sl.p);
   if (ctx->aux) {
     hipStreamSynchronize(ctx->aux);
     hipStreamDestroy(ctx->aux);
@@ -1443,7 +1460,7 @@ pnof_status pnof_nofmp2_terms(pnof_ctx ctx, const pnof_problem* prob, const doub
   if ((st = check_problem(ctx, prob)) != PNOF_OK) return st;
   if ((st = check_ptrs(ctx, {C, n, H, ints, E_hf, E_sta}, "pnof_nofmp2_terms")) != PNOF_OK) return st;
   const int nact = prob->npairs * (prob->ncwo + 1) + prob->nsingle;
-  DevBuf db(ctx->stream);
+  DevBuf db(ctx);
   double* J = db.get<double>((long long)nact * nact);
   double* K = db.get<double>((long long)nact * nact);
   double* Hpp = db.get<double>(nact);
@@ -1468,7 +1485,7 @@ pnof_status pnof_optimize_on(pnof_ctx ctx, const pnof_problem* prob, int32_t kin
   if (kind != 0 && kind != 1) return fail(ctx, PNOF_E_ARG, "kind must be 0 (sigmoid) or 1 (trigonometric)");
   if ((st = check_ptrs(ctx, {C, H, J, K, gamma, E}, "pnof_optimize_on")) != PNOF_OK) return st;
   const int nbf = prob->nbf, nact = prob->npairs * (prob->ncwo + 1) + prob->nsingle;
-  DevBuf db(ctx->stream);
+  DevBuf db(ctx);
   double* HC = db.get<double>((long long)nbf * nact);
   double* Hpp = db.get<double>(nact);
   if (!db.ok) return fail(ctx, PNOF_E_NOMEM, "allocation failed");
@@ -1505,7 +1522,7 @@ pnof_status pnof_optimize(pnof_ctx ctx, const pnof_problem* prob, const double* 
   const int maxit = op.maxit > 0 ? op.maxit : 200;
   const int ndiis = op.ndiis > 1 ? op.ndiis : 0;
   hipStream_t s = ctx->stream;
-  DevBuf db(s);
+  DevBuf db(ctx);
   double* lam = db.get<double>(nn);
   double* S = db.get<double>(nn);
   double* Cn = db.get<double>(nn);

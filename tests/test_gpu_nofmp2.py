@@ -62,3 +62,22 @@ def test_nofmp2_hartree_fock_limit(ctx):
     E = ctx.energy(prob, t(inst.C), t(n), t(inst.H), t(inst.ERI))
     assert e_sta.item() == 0.0
     assert abs(e_hf.item() - E.item()) < 1e-10
+
+
+def test_repeated_driver_calls_allocate_nothing(ctx):
+    """The driver calls keep their device buffers in the context: after a first call, repeating it
+    (and the occupation optimiser) leaves the device's free memory unchanged."""
+    inst = synth.workload("c2_df200")
+    wl = inst.wl
+    n = pnof.on_sigmoid(inst.gamma, wl.npairs, wl.ncwo)
+    prob = P.problem(wl.nbf, wl.naux, wl.npairs, wl.ncwo, P.PNOF7, P.FP64, P.INTS_DF_F64)
+    C, nn, H, B = t(inst.C), t(n), t(inst.H), t(inst.B)
+    first = ctx.nofmp2_terms(prob, C, nn, H, B)
+    again = ctx.nofmp2_terms(prob, C, nn, H, B)   # torch's pool now holds the outputs' blocks too
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info(DEV)[0]
+    for _ in range(3):
+        again = ctx.nofmp2_terms(prob, C, nn, H, B)
+        torch.cuda.synchronize()
+        assert again[0].item() == first[0].item() and again[1].item() == first[1].item()
+    assert torch.cuda.mem_get_info(DEV)[0] == free0
