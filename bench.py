@@ -28,15 +28,15 @@ KSRC = os.path.join(ROOT, "paper_2004_06142_amd", "csrc")
 # once the source changes the figure no longer applies and traffic is reported as null.
 TRAFFIC = {
     # profiles/c5_df1200_hbm_traffic.md: C5, bf16 split, 164-row chunks (read + written bytes per launch)
-    ("gemm1_kernel", 3): {"bytes": 1664531384 + 925359060,
+    ("gemm1_kernel", 3): {"bytes": 1646564985 + 925567310,
                           "plan": {"pchunk": 164, "x_variant": 3},
-                          "sha256": {"k_gemm_bf16.hip": "ae9c434c75ac9058141ece77248fe915d6eb348c8704695632be58c8ffb38a05"}},
-    ("gemm2_kernel", 3): {"bytes": 3407027309 + 1143925456,
+                          "sha256": {"k_gemm_bf16.hip": "d44953359122915f1a197e463bd6d738b5814b491fd6ae9caba2da3333dde385"}},
+    ("gemm2_kernel", 3): {"bytes": 3541124563 + 1157092221,
                           "plan": {"pchunk": 164, "nsplit_b": 18},
-                          "sha256": {"k_gemm_bf16.hip": "ae9c434c75ac9058141ece77248fe915d6eb348c8704695632be58c8ffb38a05"}},
-    ("gemm3_kernel", 3): {"bytes": 2749325195 + 241435180,
+                          "sha256": {"k_gemm_bf16.hip": "d44953359122915f1a197e463bd6d738b5814b491fd6ae9caba2da3333dde385"}},
+    ("gemm3_kernel", 3): {"bytes": 2755097622 + 241426708,
                           "plan": {"pchunk": 164, "nsplit_y": 10, "y_variant": 3},
-                          "sha256": {"k_gemm_bf16.hip": "ae9c434c75ac9058141ece77248fe915d6eb348c8704695632be58c8ffb38a05"}},
+                          "sha256": {"k_gemm_bf16.hip": "d44953359122915f1a197e463bd6d738b5814b491fd6ae9caba2da3333dde385"}},
 }
 GOLDEN_C5 = os.path.join(ROOT, "tests", "golden", "c5_df1200_expected.json")
 

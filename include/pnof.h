@@ -292,9 +292,12 @@ pnof_status pnof_optimize(pnof_ctx ctx, const pnof_problem* prob, const double* 
  *     instance opens when every item of the previous one is complete -- in instance order, so an
  *     instance completes as soon as its own work does; each instance's completion time is recorded
  *     on the device clock (pnof_batch_times).  The X and Y tile widths in use apply; b runs 64-wide.
- *     A block that finds nothing to claim polls; once the batch's stall time
- *     (pnof_batch_set_stall) passes with no work item completed anywhere, it raises a stall flag and
- *     every block exits (pnof_batch_times then reports PNOF_E_DEVICE).  Split precision only.
+ *     Each instance runs on one accelerator die (one L2): instances are spread over the device's
+ *     dies by their work on the host, and a block serves the die it runs on.  A block that finds
+ *     nothing to claim polls; once the batch's stall time (pnof_batch_set_stall) passes with no
+ *     work item completed anywhere, it raises a stall flag and every block exits
+ *     (pnof_batch_times then reports PNOF_E_DEVICE; so it does if the device's die ids do not map
+ *     one to one onto its die count).  Split precision only.
  * Restrictions: every problem uses PNOF_INTS_DF_BF16 and the same precision (PNOF_BF16_SPLIT or
  * PNOF_BF16), flags == 0, and each instance's packed B and tile buffers stay below 2 GiB (roughly
  * nbf <= 600 at naux = 4 nbf); the functional may differ.

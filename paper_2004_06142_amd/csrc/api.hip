@@ -995,15 +995,16 @@ hipError_t batch_offsets(pnof_batch b, hipStream_t s) {
   std::vector<int> byw(n);
   for (int i = 0; i < n; ++i) byw[i] = i;
   std::stable_sort(byw.begin(), byw.end(), [&](int x, int y) { return work[x] > work[y]; });
-  std::vector<std::vector<int>> die(PERSIST_NXCD);
-  std::vector<double> load(PERSIST_NXCD, 0.0);
+  const int nd = b->ps.ndie;
+  std::vector<std::vector<int>> die(nd);
+  std::vector<double> load(nd, 0.0);
   for (int i : byw) {
     const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
     die[x].push_back(i);
     load[x] += work[i];
   }
-  std::vector<int> order, xoff(PERSIST_NXCD + 1, 0);
-  for (int x = 0; x < PERSIST_NXCD; ++x) {
+  std::vector<int> order, xoff(nd + 1, 0);
+  for (int x = 0; x < nd; ++x) {
     std::sort(die[x].begin(), die[x].end());
     order.insert(order.end(), die[x].begin(), die[x].end());
     xoff[x + 1] = (int)order.size();
@@ -1698,15 +1699,21 @@ pnof_status pnof_batch_plan(pnof_ctx ctx, int32_t ninst, const pnof_problem* pro
     if (probs[i].precision != prec) return fail(ctx, PNOF_E_ARG, "all instances of a batch share one precision");
     if (probs[i].flags != 0) return fail(ctx, PNOF_E_UNSUPPORTED, "batches take no flags");
   }
-  int khz = 0;
+  int khz = 0, nxcc = 0;
   if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx->device) != hipSuccess || khz <= 0) {
     hipGetLastError();
     return fail(ctx, PNOF_E_DEVICE, "the device wall-clock rate is unavailable");
   }
+  if (hipDeviceGetAttribute(&nxcc, hipDeviceAttributeNumberOfXccs, ctx->device) != hipSuccess || nxcc <= 0) {
+    hipGetLastError();
+    nxcc = 1;   // one group: every instance on whichever die runs the first block
+  }
+  nxcc = std::min(nxcc, PERSIST_MAX_DIES);
   pnof_batch b = new pnof_batch_s();
   b->ctx = ctx;
   b->ninst = ninst;
   b->clock_khz = (double)khz;
+  b->ps.ndie = nxcc;
   b->terms = prec == PNOF_BF16_SPLIT ? 3 : 1;
   // the split mode adds the two launches of the scale bounds; the last one forms dE/dgamma
   b->launches = b->terms > 1 ? 16 : 14;
@@ -1769,9 +1776,10 @@ pnof_status pnof_batch_plan(pnof_ctx ctx, int32_t ninst, const pnof_problem* pro
     b->ps.t_start = a.take<unsigned long long>(1);
     b->ps.prog = a.take<int>(4);
     b->d_order = a.take<int>(ninst);
-    b->d_xoff = a.take<int>(PERSIST_NXCD + 1);
+    b->d_xoff = a.take<int>(PERSIST_MAX_DIES + 1);
     b->ps.order = b->d_order;
     b->ps.xoff = b->d_xoff;
+    b->ps.die_of = a.take<int>(PERSIST_MAX_DIES);
     return a.off + 256;
   };
   for (int i = 0; i < ninst; ++i) {
@@ -1950,6 +1958,9 @@ pnof_status pnof_batch_times(pnof_batch b, double* us) {
   DEV_CHECK(ctx, hipMemcpyAsync(t.data() + n, b->ps.t_start, sizeof(unsigned long long), hipMemcpyDeviceToHost, ctx->stream));
   DEV_CHECK(ctx, hipMemcpyAsync(prog, b->ps.prog, sizeof(int) * 4, hipMemcpyDeviceToHost, ctx->stream));
   DEV_CHECK(ctx, hipStreamSynchronize(ctx->stream));
+  if (prog[2] == 2)
+    return fail(ctx, PNOF_E_DEVICE, "the persistent batch run stopped: the device's die ids do not map one to one onto "
+                                    "its XCC count; its outputs are incomplete (use the grouped form)");
   if (prog[2] != 0 || prog[1] != n)
     return fail(ctx, PNOF_E_DEVICE, "the persistent batch run stalled (" + std::to_string(prog[1]) + " of " +
                                         std::to_string(n) + " instances completed); its outputs are incomplete");

@@ -492,7 +492,7 @@ enum {
 };
 constexpr int PERSIST_PARTS = 8;   // items of the element-wise phases (W diagonal, reductions, Y, finish)
 constexpr int PERSIST_XG = 4;      // X tiles per work item (consecutive tiles share their rows of B)
-constexpr int PERSIST_NXCD = 8;    // accelerator complex dies (one L2 each); an instance runs on one
+constexpr int PERSIST_MAX_DIES = 16;   // accelerator complex dies (one L2 each) a device may have
 // Scheduling state (device memory, cleared by batch_persist before each run).
 struct PSched {
   const int* cnt;                 // [ninst][PH_N] items of each phase
@@ -503,7 +503,9 @@ struct PSched {
   unsigned long long* t_start;    // device wall clock when the run started
   int* prog;                      // [0] items completed, [1] instances completed, [2] stalled
   const int* order;               // instances grouped by the die that runs them, each group ascending
-  const int* xoff;                // [PERSIST_NXCD + 1]: group x is order[xoff[x] .. xoff[x + 1])
+  const int* xoff;                // [ndie + 1]: group x is order[xoff[x] .. xoff[x + 1])
+  int* die_of;                    // [ndie]: the hardware die id that took group x (-1 before)
+  int ndie;                       // the device's dies; a block of die id d serves group d % ndie
   unsigned long long stall_ticks; // device-clock ticks with no progress anywhere before a block gives up
 };
 struct PArgs {

@@ -1003,7 +1003,9 @@ __device__ __forceinline__ void persist_item(const PArgs& a, int i, int ph, int 
 }
 
 // Every instance runs on one die: a block reads the id of the die it runs on from the hardware and
-// claims items of that die's instances only.  All of an instance's intermediate data then stays in
+// claims items of that die's group of instances only (group = id modulo the device's die count;
+// the first block of a group records its die id, and a block of another die mapping to the same
+// group stops the run with the error flag rather than share an L2-resident instance).  All of an instance's intermediate data then stays in
 // one L2, so a block makes its item's stores visible by waiting for them to reach L2 (before the
 // barrier that ends the item) and sees the other blocks' stores after invalidating its compute
 // unit's L1 (after claiming); no L2 write-back or invalidation is needed.  The scheduling words are
@@ -1023,9 +1025,15 @@ __global__ __launch_bounds__(256, 2) void batch_persist_k(PArgs a) {
   __shared__ PersistLds<TX, TY> u;
   __shared__ int s_it[3];
   const PSched& sc = a.sc;
-  const int die = die_id();
-  if (die >= PERSIST_NXCD) return;   // not a die the instances were spread over: nothing to claim
-  const int lo = __builtin_amdgcn_readfirstlane(sc.xoff[die]), hi = __builtin_amdgcn_readfirstlane(sc.xoff[die + 1]);
+  const int die = die_id(), grp = die % sc.ndie;
+  if (threadIdx.x == 0) {
+    const int prev = atomicCAS(sc.die_of + grp, -1, die);
+    s_it[0] = (prev == -1 || prev == die) ? 0 : 1;
+    if (s_it[0]) atomicExch(sc.prog + 2, 2);   // two dies in one group: stop every block
+  }
+  __syncthreads();
+  if (s_it[0]) return;
+  const int lo = __builtin_amdgcn_readfirstlane(sc.xoff[grp]), hi = __builtin_amdgcn_readfirstlane(sc.xoff[grp + 1]);
   const int lane = threadIdx.x;   // in wavefront 0
   const bool lead = threadIdx.x == 0;
   int last = -1;   // state word (instance * PH_N + phase) of the item this block completed last
@@ -1111,6 +1119,7 @@ __global__ void persist_reset_k(PSched sc, int nwords_inst, int ninst) {
     sc.done[i] = 0;
   }
   for (int i = threadIdx.x; i < ninst; i += blockDim.x) sc.phase[i] = 0;
+  for (int i = threadIdx.x; i < sc.ndie; i += blockDim.x) sc.die_of[i] = -1;
   if (threadIdx.x < 3) sc.prog[threadIdx.x] = 0;
   if (threadIdx.x == 0) *sc.t_start = wall_clock64();
 }
