@@ -44,7 +44,7 @@ GOLDEN_C5 = os.path.join(ROOT, "tests", "golden", "c5_df1200_expected.json")
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c5_df1200")
     ap.add_argument("--precision", default="bf16split", choices=["bf16split", "fp64", "fp32", "bf16"])
@@ -140,17 +140,22 @@ def main():
         torch.cuda.synchronize()
         if profile:
             ctx.profile_begin()
+        # HIP events around each step on the library's stream, for the median and p5 / p95
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
         t0 = time.perf_counter()
-        for _ in range(steps):
+        evs[0].record(ctx.stream)
+        for i in range(steps):
             out, _ = step(prob, C0)
+            evs[i + 1].record(ctx.stream)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         prof = ctx.profile_end() if profile else None
-        return out, dt, prof
+        per = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(steps)])
+        return out, dt, prof, per
 
     prob = P.problem(wl.nbf, wl.naux, wl.npairs, wl.ncwo, P.PNOF7, prec, kind)
     print(f"[bench] workload {wl.name}: warmup {args.warmup}, timing {args.steps} steps", file=sys.stderr, flush=True)
-    out, dt, prof = run(prob, args.warmup, args.steps, True)
+    out, dt, prof, per = run(prob, args.warmup, args.steps, True)
     ms = 1e3 * dt / args.steps
     E = out["E"].item()
     print(f"[bench] {ms:.1f} ms/step, E = {E:.10f}, stages {prof}", file=sys.stderr, flush=True)
@@ -180,6 +185,8 @@ def main():
         "config": {"workload": wl.name, "nbf": wl.nbf, "naux": wl.naux, "npairs": wl.npairs, "ncwo": wl.ncwo,
                    "nact": wl.nact, "functional": "PNOF7", "B": wl.b_dtype, "seed": synth.seed_of(wl.name)},
         "energy_Ha": E, "stages": stages, "roofline": roofline, "launch": ctx.plan(prob),
+        "step_ms": {"median": float(np.median(per)), "p5": float(np.percentile(per, 5)),
+                    "p95": float(np.percentile(per, 95)), "steps": int(len(per))},
     }
     if os.path.exists(GOLDEN_C5) and wl.name == "c5_df1200":
         ref = json.load(open(GOLDEN_C5))
@@ -211,7 +218,7 @@ def main():
     if args.fp64_steps > 0 and prec != P.FP64:
         p64 = P.problem(wl.nbf, wl.naux, wl.npairs, wl.ncwo, P.PNOF7, P.FP64, kind)
         print("[bench] float64 path for the speedup", file=sys.stderr, flush=True)
-        o64, dt64, prof64 = run(p64, 0, args.fp64_steps, True)
+        o64, dt64, prof64, _ = run(p64, 0, args.fp64_steps, True)
         result["fp64_path"] = {"ms_per_step": 1e3 * dt64 / args.fp64_steps, "energy_Ha": o64["E"].item(),
                                "speedup_of_mixed": (dt64 / args.fp64_steps) / (dt / args.steps),
                                "abs_dE_mixed_vs_fp64": abs(E - o64["E"].item()),
@@ -283,12 +290,12 @@ def pes_batch(P, ctx, reps, tune=True):
     seq["note"] = "every instance completes with the batch's last grouped launch: per-instance latency = batch latency"
     pms, done = timed(True)
     per = summary(pms, 2)
-    # per-instance completion (device clock, from the run's start), median over the timed runs
-    inst_us = np.median(done, axis=0)
-    per["instance_latency_ms"] = {"p50": float(np.percentile(inst_us, 50)) * 1e-3,
-                                  "p90": float(np.percentile(inst_us, 90)) * 1e-3,
-                                  "p99": float(np.percentile(inst_us, 99)) * 1e-3,
-                                  "max": float(inst_us.max()) * 1e-3}
+    # per-instance completion times (device clock, from the run's start) over all instances x timed runs
+    samples = np.asarray(done).ravel()
+    per["instance_latency_ms"] = {"p50": float(np.percentile(samples, 50)) * 1e-3,
+                                  "p90": float(np.percentile(samples, 90)) * 1e-3,
+                                  "p99": float(np.percentile(samples, 99)) * 1e-3,
+                                  "max": float(samples.max()) * 1e-3, "samples": int(samples.size)}
     best = "persistent" if per["ms_per_batch_p50"] < seq["ms_per_batch_p50"] else "launch_sequence"
     head = per if best == "persistent" else seq
     res = {"instances": len(probs), "nbf_range": [min(p.nbf for p in probs), max(p.nbf for p in probs)],
@@ -344,7 +351,8 @@ def cpu_baseline(wl, inst, rows):
 
 def cpu_protocol():
     """The float64 oracle on the host cores: DGEMM rate, then one energy + lambda + gradient step (+ the
-    orbital step's eigensolver) per configuration, timed with every OpenBLAS thread and with one.  B
+    orbital step's eigensolver at C1, C2, C3 and C5) per configuration, timed with every OpenBLAS
+    thread, with 8 and with one (C5: every thread).  B
     is drawn before the clock starts (at C5 on the device, 96 rows at a time, widened to float64 and
     copied to the host; only the oracle's work on each chunk is timed, every row of B is used)."""
     import numpy as np
@@ -370,8 +378,27 @@ def cpu_protocol():
         return 2.0 * n ** 3 / min(ts) / 1e9
 
     res["dgemm_gflops"] = dgemm_rate()
+    with threadpool_limits(8, user_api="blas"):
+        res["dgemm_gflops_8threads"] = dgemm_rate()
     with threadpool_limits(1, user_api="blas"):
         res["dgemm_gflops_1thread"] = dgemm_rate(2048)
+
+    # C1: the explicit-integral path (generalised Fock matrix from the 24^4 tensor, energy, lambda,
+    # orbital step), median of 5
+    inst = synth.workload("c1_eri24")
+    w = inst.wl
+    n = pnof.on_sigmoid(inst.gamma, w.npairs, w.ncwo)
+
+    def c1():
+        t0 = time.perf_counter()
+        F = pnof.fock_ao(inst.C, n, inst.H, inst.ERI, w.npairs, w.ncwo, pnof.PNOF7, kind="eri")
+        pnof.energy(inst.C, n, inst.H, inst.ERI, w.npairs, w.ncwo, pnof.PNOF7, kind="eri")
+        pnof.orbital_step(pnof.lagrangian(inst.C, F), inst.C)
+        return time.perf_counter() - t0
+
+    res["c1_eri24"] = {"seconds_all_threads": float(np.median([c1() for _ in range(5)])), "runs": 5}
+    with threadpool_limits(1, user_api="blas"):
+        res["c1_eri24"]["seconds_1thread"] = float(np.median([c1() for _ in range(5)]))
 
     def step(inst, n, B, naux):
         t0 = time.perf_counter()
@@ -379,13 +406,15 @@ def cpu_protocol():
         pnof.orbital_step(r["lam"], inst.C)
         return time.perf_counter() - t0
 
-    for name, reps in (("c2_df200", 5), ("c3_df500", 1)):
+    for name, reps in (("c2_df200", 5), ("c3_df500", 3)):
         inst = synth.workload(name, with_b=False)
         w = inst.wl
         bdt = torch.bfloat16 if w.b_dtype == "bf16" else torch.float64
         B = sdev.make_b(inst.key, w.nbf, w.naux, dtype=bdt, device=torch.device("cuda", 0)).to(torch.float64).cpu().numpy()
         n = pnof.on_sigmoid(inst.gamma, w.npairs, w.ncwo)
         ent = {"seconds_all_threads": float(np.median([step(inst, n, B, None) for _ in range(reps)]))}
+        with threadpool_limits(8, user_api="blas"):
+            ent["seconds_8threads"] = float(np.median([step(inst, n, B, None) for _ in range(reps)]))
         with threadpool_limits(1, user_api="blas"):
             ent["seconds_1thread"] = step(inst, n, B, None)
         del B
@@ -393,6 +422,21 @@ def cpu_protocol():
         res[name] = ent
         del inst
         print(f"[cpu] {name}: {ent}", file=sys.stderr, flush=True)
+
+    # C4: the 64-instance PES scan, one Lagrangian + gradient per instance (B drawn before each clock)
+    c4 = {"seconds_all_threads": 0.0, "seconds_8threads": 0.0, "seconds_1thread": 0.0, "instances": 64}
+    for inst in synth.pes_scan(64, with_b=False):
+        w = inst.wl
+        B = synth.b_chunk(inst.key, w.nbf, w.naux, 0, w.naux, w.b_dtype).astype(np.float64)
+        n = pnof.on_sigmoid(inst.gamma, w.npairs, w.ncwo)
+        for key, lim in (("seconds_all_threads", None), ("seconds_8threads", 8), ("seconds_1thread", 1)):
+            with threadpool_limits(lim, user_api="blas"):
+                t0 = time.perf_counter()
+                stream.lagrangian(inst.C, n, inst.H, B, w.npairs, w.ncwo, pnof.PNOF7)
+                c4[key] += time.perf_counter() - t0
+        del B
+    res["c4_pes64"] = c4
+    print(f"[cpu] c4_pes64: {c4}", file=sys.stderr, flush=True)
 
     wl = synth.WORKLOADS["c5_df1200"]
     inst = synth.workload("c5_df1200", with_b=False)

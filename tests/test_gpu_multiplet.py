@@ -127,14 +127,23 @@ def test_batch_with_singles(ctx):
         n = pnof.on_sigmoid(gamma, npairs, ncwo, ns)
         probs.append(P.problem(nbf, 4 * nbf, npairs, ncwo, P.PNOF7, P.BF16_SPLIT, P.INTS_DF_BF16, nsingle=ns))
         B = sdev.make_b(inst.key, nbf, 4 * nbf, dtype=torch.bfloat16, device=DEV)
-        ins.append({"C": t(inst.C), "H": t(inst.H), "n": t(n), "B": B})
-        refs.append((stream.lagrangian(inst.C, n, inst.H, inst.B, npairs, ncwo, P.PNOF7, nsingle=ns), n, npairs,
-                     ncwo, ns))
+        ins.append({"C": t(inst.C), "H": t(inst.H), "n": t(n), "B": B, "gamma": t(gamma)})
+        r = stream.lagrangian(inst.C, n, inst.H, inst.B, npairs, ncwo, P.PNOF7, nsingle=ns)
+        r["dEdgamma"] = pnof.on_sigmoid_jac(gamma, npairs, ncwo, ns).T @ r["dEdn"]
+        refs.append((r, n, npairs, ncwo, ns))
     batch = P.Batch(ctx, probs)
     outs = batch.bind(ins)
-    batch.run(graph=True)
-    torch.cuda.synchronize()
-    for o, (r, n, npairs, ncwo, ns) in zip(outs, refs):
-        assert abs(o["E"].item() - r["E"]) < 1e-6
-        assert np.max(np.abs(o["lam"].cpu().numpy() - r["lam"])) < 2e-5
-        assert np.max(np.abs(o["dEdn"].cpu().numpy() - r["dEdn"])) < 2e-5
+    # the grouped launch sequence and the persistent form (dE/dgamma through the ON map with singles)
+    for persistent in (False, True):
+        for o in outs:
+            for v in o.values():
+                v.fill_(float("nan"))
+        batch.run(graph=True, persistent=persistent)
+        torch.cuda.synchronize()
+        if persistent:
+            assert len(batch.times()) == len(probs)
+        for o, (r, n, npairs, ncwo, ns) in zip(outs, refs):
+            assert abs(o["E"].item() - r["E"]) < 1e-6, persistent
+            assert np.max(np.abs(o["lam"].cpu().numpy() - r["lam"])) < 2e-5
+            assert np.max(np.abs(o["dEdn"].cpu().numpy() - r["dEdn"])) < 2e-5
+            assert np.max(np.abs(o["dEdgamma"].cpu().numpy() - r["dEdgamma"])) < 5e-5
