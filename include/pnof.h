@@ -341,6 +341,11 @@ pnof_status pnof_batch_times(pnof_batch batch, double* us);
 /* Time (device clock, microseconds) a persistent run may pass with no work item completed anywhere
  * before its blocks give up (0: the default, one second; at most 1e9). */
 pnof_status pnof_batch_set_stall(pnof_batch batch, double microseconds);
+/* Number of die groups the persistent form spreads the instances over (0: the device's XCC count,
+ * the default; at most 16).  A block on die d serves group d mod dies; a count under which two dies
+ * of the device share a group makes persistent runs stop early (pnof_batch_times reports
+ * PNOF_E_DEVICE).  For testing and for partitioned devices whose count the runtime misreports. */
+pnof_status pnof_batch_set_dies(pnof_batch batch, int32_t dies);
 /* Device bytes held by the batch, and the number of launches one run enqueues. */
 pnof_status pnof_batch_info(pnof_batch batch, size_t* bytes, int32_t* launches);
 /* Tile widths along the active orbitals of the grouped X, b and Y contractions: 64 or 128, 0 for

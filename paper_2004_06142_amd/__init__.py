@@ -37,7 +37,7 @@ EXPORTS = ["pnof_abi_version", "pnof_last_error", "pnof_check_problem", "pnof_cr
            "pnof_profile_begin", "pnof_profile_end", "pnof_set_tuning", "pnof_get_plan", "pnof_optimize_on",
            "pnof_optimize", "pnof_nofmp2_terms", "pnof_batch_plan",
            "pnof_batch_bind", "pnof_batch_run", "pnof_batch_info", "pnof_batch_destroy", "pnof_batch_set_tiles",
-           "pnof_batch_get_tiles", "pnof_batch_times", "pnof_batch_set_stall"]
+           "pnof_batch_get_tiles", "pnof_batch_times", "pnof_batch_set_stall", "pnof_batch_set_dies"]
 STAGES = ("X", "b", "Y", "eig")
 
 
@@ -138,6 +138,7 @@ def lib():
             "pnof_batch_get_tiles": ([P, ctypes.POINTER(ctypes.c_int32)], S),
             "pnof_batch_times": ([P, ctypes.POINTER(ctypes.c_double)], S),
             "pnof_batch_set_stall": ([P, ctypes.c_double], S),
+            "pnof_batch_set_dies": ([P, I], S),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -579,6 +580,10 @@ class Batch:
         out = (ctypes.c_double * len(self.problems))()
         _raise(self.ctx, lib().pnof_batch_times(self.handle, out))
         return list(out)
+
+    def set_dies(self, dies: int = 0):
+        """Die groups of the persistent form (0: the device's XCC count)."""
+        _raise(self.ctx, lib().pnof_batch_set_dies(self.handle, int(dies)))
 
     def set_stall(self, microseconds: float = 0.0):
         """Time with no progress anywhere before a persistent run's blocks give up (0: one second)."""

@@ -919,6 +919,7 @@ struct pnof_batch_s {
   hipGraphExec_t pexec = nullptr;
   int pblocks = 512;                  // two blocks per compute unit
   double stall_us = 1e6;              // no progress for this long: a persistent run gives up
+  int dev_dies = 1;                   // the device's XCC count
   int last_flags = -1;
   double clock_khz = 0.0;             // device wall clock
 };
@@ -1713,7 +1714,7 @@ pnof_status pnof_batch_plan(pnof_ctx ctx, int32_t ninst, const pnof_problem* pro
   b->ctx = ctx;
   b->ninst = ninst;
   b->clock_khz = (double)khz;
-  b->ps.ndie = nxcc;
+  b->ps.ndie = b->dev_dies = nxcc;
   b->terms = prec == PNOF_BF16_SPLIT ? 3 : 1;
   // the split mode adds the two launches of the scale bounds; the last one forms dE/dgamma
   b->launches = b->terms > 1 ? 16 : 14;
@@ -1965,6 +1966,16 @@ pnof_status pnof_batch_times(pnof_batch b, double* us) {
     return fail(ctx, PNOF_E_DEVICE, "the persistent batch run stalled (" + std::to_string(prog[1]) + " of " +
                                         std::to_string(n) + " instances completed); its outputs are incomplete");
   for (int i = 0; i < n; ++i) us[i] = (double)(t[i] - t[n]) * 1e3 / b->clock_khz;
+  return PNOF_OK;
+}
+
+pnof_status pnof_batch_set_dies(pnof_batch b, int32_t dies) {
+  if (!b) return fail(nullptr, PNOF_E_ARG, "batch is NULL");
+  if (dies < 0 || dies > PERSIST_MAX_DIES)
+    return fail(b->ctx, PNOF_E_ARG, "dies must be in [0, " + std::to_string(PERSIST_MAX_DIES) + "]");
+  b->ps.ndie = dies > 0 ? dies : b->dev_dies;
+  batch_drop_graph(b);
+  if (b->bound) DEV_CHECK(b->ctx, batch_offsets(b, b->ctx->stream));
   return PNOF_OK;
 }
 

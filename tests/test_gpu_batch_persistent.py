@@ -236,6 +236,40 @@ def test_persistent_stall_flag_ends_every_block(ctx):
     batch.close()
 
 
+def test_persistent_die_groups(ctx):
+    """Instances spread over fewer groups than the device has dies: two dies land in one group, and
+    the run stops early (every block exits) with the error reported, rather than letting two L2s
+    share an instance; at the device's own count, and at every count that maps its dies one to one,
+    the results are those of the grouped launches."""
+    insts = synth.pes_scan(10, seed=2004061432, nbf_range=(40, 160), with_b=False)
+    probs = [P.problem(i.wl.nbf, i.wl.naux, i.wl.npairs, i.wl.ncwo, P.PNOF7, P.BF16_SPLIT, P.INTS_DF_BF16)
+             for i in insts]
+    batch = P.Batch(ctx, probs)
+    outs = batch.bind([_inputs(ctx, i, P.ON_SIGMOID) for i in insts])
+    batch.run(graph=False)
+    torch.cuda.synchronize()
+    ref = [{k: v.clone() for k, v in o.items()} for o in outs]
+    ndev = torch.cuda.get_device_properties(0).multi_processor_count // 32   # 32 CUs per die
+    if ndev >= 2:
+        batch.set_dies(ndev // 2)
+        batch.run(graph=False, persistent=True)
+        with pytest.raises(P.PnofError, match="PNOF_E_DEVICE"):
+            batch.times()
+    for dies in (0, ndev):
+        batch.set_dies(dies)
+        for o in outs:
+            for v in o.values():
+                v.fill_(float("nan"))
+        batch.run(graph=True, persistent=True)
+        assert len(batch.times()) == len(insts)
+        for o, r in zip(outs, ref):
+            for k in r:
+                assert torch.equal(o[k], r[k]), (dies, k)
+    with pytest.raises(P.PnofError, match="PNOF_E_ARG"):
+        batch.set_dies(17)
+    batch.close()
+
+
 def test_persistent_error_paths(ctx):
     good = P.problem(64, 256, 6, 3, P.PNOF7, P.BF16_SPLIT, P.INTS_DF_BF16)
     b = P.Batch(ctx, [P.problem(64, 256, 6, 3, P.PNOF7, P.BF16, P.INTS_DF_BF16)])
