@@ -1366,12 +1366,11 @@ pnof_status pnof_lagrangian_noalloc(pnof_ctx ctx, const pnof_problem* prob, cons
 namespace {
 // Symmetric float64 eigensolver: A (n x n, symmetric, row-major; destroyed) -> ascending eigenvalues
 // w and eigenvectors U (column-major).  The Householder reduction runs on the library's kernels
-// (k_eig.hip), A = Q T Q^T.  rocSOLVER solves the tridiagonal problem (stedc, eigenvectors Z into
-// A's storage) while the context's second stream forms Q = H_0 ... H_{n-2} explicitly (reflectors
-// applied to the identity in blocks, k_eig.hip form_q_f64); then U = Q Z.  The tridiagonal solver's many small
-// launches leave most of the chip idle, so forming Q there costs no time on the main stream.
-// Sizes outside [3, TRIDIAG_MAX_N] take rocSOLVER's dsyevd.  info (device) receives the solver's
-// status (0 = converged).
+// (k_eig.hip), A = Q T Q^T.  The library's divide-and-conquer solver (k_tridiag.hip) solves the
+// tridiagonal problem, eigenvectors Z into A's storage, while the context's second stream forms
+// Q = H_0 ... H_{n-2} explicitly (reflectors applied to the identity in blocks, k_eig.hip
+// form_q_f64); then U = Q Z.  Sizes outside [3, TRIDIAG_MAX_N] take rocSOLVER's dsyevd.  info
+// (device) receives the solver's status (0 = converged).
 struct EighWs {
   double* Vh = nullptr;    // n * n
   double* p2 = nullptr;    // 2n
@@ -1379,6 +1378,7 @@ struct EighWs {
   double* tau = nullptr;   // n
   double* T = nullptr;     // ormtr_tblocks(n) * ORMTR_NB^2
   double* Q = nullptr;     // n * n
+  double* dc = nullptr;    // tridiag_dc_ws_doubles(n): the tridiagonal eigensolver's workspace
 };
 EighWs take_eigh_ws(Arena& a, int n) {
   EighWs w;
@@ -1388,6 +1388,7 @@ EighWs take_eigh_ws(Arena& a, int n) {
   w.tau = a.take<double>(n);
   w.T = a.take<double>((long long)ormtr_tblocks(std::max(n, 1)) * ORMTR_NB * ORMTR_NB);
   w.Q = a.take<double>((long long)n * n);
+  w.dc = a.take<double>(tridiag_dc_ws_doubles(std::max(n, 1)));
   return w;
 }
 pnof_status eigh(pnof_ctx ctx, int n, double* A, double* w, double* U, const EighWs& ws, int* info) {
@@ -1398,7 +1399,7 @@ pnof_status eigh(pnof_ctx ctx, int n, double* A, double* w, double* U, const Eig
     DEV_CHECK(ctx, hipMemcpyAsync(U, A, sizeof(double) * n * n, hipMemcpyDeviceToDevice, s));
     return PNOF_OK;
   }
-  if (!ws.Vh || !ws.p2 || !ws.e || !ws.tau || !ws.T || !ws.Q)
+  if (!ws.Vh || !ws.p2 || !ws.e || !ws.tau || !ws.T || !ws.Q || !ws.dc)
     return fail(ctx, PNOF_E_ARG, "eigensolver workspace missing");
   RB_CHECK(ensure_aux(ctx));
   DEV_CHECK(ctx, tridiag_f64(s, n, A, ws.Vh, ws.p2, w, ws.e, ws.tau));
@@ -1407,9 +1408,9 @@ pnof_status eigh(pnof_ctx ctx, int n, double* A, double* w, double* U, const Eig
   DEV_CHECK(ctx, form_q_f64(ctx->aux, n, ws.Vh, ws.tau, ws.T, ws.Q));
   DEV_CHECK(ctx, hipEventRecord(ctx->join_ev, ctx->aux));
   double* Z = A;   // free after the reduction
-  rocblas_status rs = rocsolver_dstedc(ctx->blas, rocblas_evect_tridiagonal, n, w, ws.e, Z, n, info);
+  const hipError_t de = tridiag_eig_dc(s, n, w, ws.e, Z, ws.dc, info);
   DEV_CHECK(ctx, hipStreamWaitEvent(s, ctx->join_ev, 0));   // joined on every path: Q uses the workspace
-  if (rs != rocblas_status_success) return fail(ctx, PNOF_E_DEVICE, "rocsolver_dstedc failed to launch");
+  DEV_CHECK(ctx, de);
   // U = Q Z, all column-major
   RB_CHECK(dprod(ctx, n, n, n, ws.Q, 1, n, Z, 1, n, U, 1, n));
   return PNOF_OK;
@@ -1538,6 +1539,7 @@ pnof_status pnof_optimize(pnof_ctx ctx, const pnof_problem* prob, const double* 
   ew.tau = db.get<double>(nbf);
   ew.T = db.get<double>((long long)ormtr_tblocks(nbf) * ORMTR_NB * ORMTR_NB);
   ew.Q = db.get<double>(nn);
+  ew.dc = db.get<double>(tridiag_dc_ws_doubles(nbf));
   int* info = db.get<int>(4);
   double* J = db.get<double>(n2);
   double* K = db.get<double>(n2);

@@ -278,6 +278,12 @@ __host__ __device__ inline long long round_up(long long a, long long b) { return
 // C[b] = alpha * A[b] B[b] + beta * C[b] with strided views
 //   A(m,k) = A[b*sab + m*sam + k*sak], B(k,n) = B[b*sbb + k*sbk + n*sbn], C(m,n) = C[b*scb + m*scm + n*scn]
 // Exactly one of sam/sak and one of sbk/sbn must be 1.
+// Eigenvalues (ascending, overwriting d) and eigenvectors (Z, n x n column-major) of the symmetric
+// tridiagonal matrix with diagonal d and off-diagonal e (n - 1 entries), by divide and conquer;
+// ws holds tridiag_dc_ws_doubles(n) doubles; info (device) is set nonzero if a secular equation
+// did not converge.  1 <= n <= TRIDIAG_MAX_N.
+long long tridiag_dc_ws_doubles(int n);
+hipError_t tridiag_eig_dc(hipStream_t s, int n, double* d, const double* e, double* Z, double* ws, int* info);
 hipError_t gemm_f64(hipStream_t s, int M, int N, int K, int batch, double alpha, const double* A,
                     long long sam, long long sak, long long sab, const double* B, long long sbk,
                     long long sbn, long long sbb, double beta, double* C, long long scm, long long scn,

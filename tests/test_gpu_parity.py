@@ -359,6 +359,46 @@ def test_orbital_step_reflector_free_columns(ctx, kind):
     _eig_compare(h(eps), eps_r, h(Cn), C, Sr)
 
 
+def _hard_spectrum(kind, rng):
+    """Symmetric inputs whose tridiagonal forms stress the divide-and-conquer merges: tridiagonal ones
+    reach the tridiagonal solver unchanged (every reflector of the reduction is the identity)."""
+    if kind == "wilkinson":         # W+ 201: pairs of eigenvalues equal to many digits
+        n = 201
+        return np.diag(np.abs(np.arange(n) - 100.0)) + np.diag(np.ones(n - 1), 1) + np.diag(np.ones(n - 1), -1)
+    if kind == "glued":             # ten W+ 21 blocks glued by 1e-8: clusters of ten near-equal values
+        blk = np.abs(np.arange(21) - 10.0)
+        d = np.tile(blk, 10)
+        e = np.concatenate([np.concatenate([np.ones(20), [1e-8]]) for _ in range(10)])[:-1]
+        return np.diag(d) + np.diag(e, 1) + np.diag(e, -1)
+    if kind == "split":             # exact zero couplings: merges with nothing to solve
+        n = 260
+        d = rng.standard_normal(n)
+        e = rng.standard_normal(n - 1)
+        e[::37] = 0.0
+        return np.diag(d) + np.diag(e, 1) + np.diag(e, -1)
+    n = 300
+    if kind == "clusters":          # ten eigenvalues, each thirty times
+        w = np.repeat(rng.standard_normal(10), 30)
+    elif kind == "near":            # clusters spread over 1e-12
+        w = np.repeat(rng.standard_normal(30), 10) + 1e-12 * rng.standard_normal(n)
+    else:                           # graded: magnitudes from 1e-12 to 1, both signs
+        w = 10.0 ** rng.uniform(-12, 0, n) * rng.choice([-1.0, 1.0], n)
+    V, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    return (V * w[None, :]) @ V.T
+
+
+@pytest.mark.parametrize("kind", ["wilkinson", "glued", "split", "clusters", "near", "graded"])
+def test_orbital_step_hard_spectra(ctx, kind):
+    rng = np.random.default_rng(11)
+    lam = _hard_spectrum(kind, rng)
+    nbf = lam.shape[0]
+    C, _ = np.linalg.qr(rng.standard_normal((nbf, nbf)))
+    Cn, eps = ctx.orbital_step(t(lam), t(C))
+    Cr, eps_r, Sr = pnof.orbital_step(lam, C)
+    _eig_compare(h(eps), eps_r, h(Cn), C, Sr)
+    assert np.all(np.diff(h(eps)) >= 0)
+
+
 def test_orbital_step_fockian_zeta(ctx):
     inst = _case("orbF", 40, 60, 4, 3)
     n, ref = _ref(inst, pnof.PNOF7)
