@@ -1376,7 +1376,7 @@ struct EighWs {
   double* p2 = nullptr;    // 2n
   double* e = nullptr;     // n
   double* tau = nullptr;   // n
-  double* T = nullptr;     // ormtr_tblocks(n) * ORMTR_NB^2
+  double* T = nullptr;     // form_q_ws_doubles(n): Q's formation
   double* Q = nullptr;     // n * n
   double* dc = nullptr;    // tridiag_dc_ws_doubles(n): the tridiagonal eigensolver's workspace
 };
@@ -1386,7 +1386,7 @@ EighWs take_eigh_ws(Arena& a, int n) {
   w.p2 = a.take<double>(2LL * n);
   w.e = a.take<double>(n);
   w.tau = a.take<double>(n);
-  w.T = a.take<double>((long long)ormtr_tblocks(std::max(n, 1)) * ORMTR_NB * ORMTR_NB);
+  w.T = a.take<double>(form_q_ws_doubles(std::max(n, 3)));
   w.Q = a.take<double>((long long)n * n);
   w.dc = a.take<double>(tridiag_dc_ws_doubles(std::max(n, 1)));
   return w;
@@ -1537,7 +1537,7 @@ pnof_status pnof_optimize(pnof_ctx ctx, const pnof_problem* prob, const double* 
   ew.p2 = db.get<double>(2LL * nbf);
   ew.e = db.get<double>(nbf);
   ew.tau = db.get<double>(nbf);
-  ew.T = db.get<double>((long long)ormtr_tblocks(nbf) * ORMTR_NB * ORMTR_NB);
+  ew.T = db.get<double>(form_q_ws_doubles(std::max(nbf, 3)));
   ew.Q = db.get<double>(nn);
   ew.dc = db.get<double>(tridiag_dc_ws_doubles(nbf));
   int* info = db.get<int>(4);

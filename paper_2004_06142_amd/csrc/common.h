@@ -599,10 +599,12 @@ hipError_t sign_fix_cols(hipStream_t s, int nbf, double* Ucm);
 constexpr int TRIDIAG_MAX_N = 2048;   // three float64 vectors of n in LDS
 hipError_t tridiag_f64(hipStream_t s, int n, double* A, double* Vh, double* p2, double* d, double* e, double* tau);
 // Q = H_0 ... H_{n-2} (column-major n x n) from the reflectors of tridiag_f64 (Vh, tau), applied in
-// blocks of ORMTR_NB.  Tall: workspace of ormtr_tblocks(n) * ORMTR_NB^2 doubles.  3 <= n <= TRIDIAG_MAX_N.
-constexpr int ORMTR_NB = 32;
-inline int ormtr_tblocks(int n) { return (n - 1 + ORMTR_NB - 1) / ORMTR_NB; }
-hipError_t form_q_f64(hipStream_t s, int n, const double* Vh, const double* tau, double* Tall, double* Q);
+// blocks of QNB as float64 GEMMs.  ws: form_q_ws_doubles(n) doubles.  3 <= n <= TRIDIAG_MAX_N.
+constexpr int QNB = 128;
+constexpr int FORMQ_KS = 8;   // k-splits of Q's skinny products
+inline int formq_blocks(int n) { return (n - 1 + QNB - 1) / QNB; }
+long long form_q_ws_doubles(int n);
+hipError_t form_q_f64(hipStream_t s, int n, const double* Vh, const double* tau, double* ws, double* Q);
 hipError_t offdiag_copy(hipStream_t s, int nbf, const double* src, double* dst);
 // E_hf and E_sta (device scalars) from n, H_pp, J, K; partials: 256 doubles of scratch.
 hipError_t nofmp2_terms(hipStream_t s, int nact, int npairs, int ncwo, int nsingle, const double* n, const double* Hpp,

@@ -314,186 +314,140 @@ __global__ __launch_bounds__(TAILNT) void trd_tail_k(int n, int k0, const double
 
 // ---------------------------------------------------------------- back-transformation
 // Q = H_0 ... H_{n-2} formed explicitly (column-major n x n); the eigenvectors are then Q times
-// those of the tridiagonal matrix.  The reflectors are taken in blocks of ONB:
-// Q_b = H_{k0} ... H_{k0+nb-1} = I - V T V^T with V the block's vectors as columns and T upper
-// triangular (the compact WY form of a product of reflectors, Schreiber and Van Loan 1989).
-// Columns are independent, so each workgroup owns OCW of them in LDS and applies Q_last, ..., Q_0
-// to the identity in turn; no step waits on another workgroup.
-constexpr int ONB = ORMTR_NB;                 // reflectors per block
-constexpr int OCW = 8;                        // eigenvector columns per workgroup
-constexpr int ORPT = TRIDIAG_MAX_N / TNT;     // rows per thread in the update
+// those of the tridiagonal matrix.  The reflectors are taken in blocks of QNB:
+// Q_b = H_{k0} ... H_{k0+QNB-1} = I - V T V^T with V the block's vectors as columns and T upper
+// triangular (the compact WY form of a product of reflectors, Schreiber and Van Loan 1989).  Q is
+// built from the identity by applying Q_last, ..., Q_0 in turn, each as three float64 GEMMs on the
+// trailing part [k0 + 1, n) x [k0 + 1, n) (columns at or before k0 are still unit columns there, and
+// rows at or before k0 are untouched by the block).
 
-// T of every block (one workgroup each): G[i][j] = v_i . v_j (i < j), then T[j][j] = tau_j and
-// T[0:j][j] = -tau_j T[0:j][0:j] G[0:j][j], stored full ONB x ONB with zeros outside the block.
-__global__ __launch_bounds__(TNT) void larft_k(int n, int nref, const double* __restrict__ Vh,
-                                               const double* __restrict__ tau, double* __restrict__ Tall) {
-  __shared__ double Vs[64][ONB + 1];
-  __shared__ double G[ONB][ONB + 1];
-  __shared__ double T[ONB][ONB + 1];
-  const int t = threadIdx.x, k0 = blockIdx.x * ONB, nb = min(ONB, nref - k0);
-  constexpr int NQ = ONB * ONB / TNT;
-  double g[NQ];
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) g[q] = 0.0;
-  for (int r0 = k0 + 1; r0 < n; r0 += 64) {
-    __syncthreads();
-    for (int e = t; e < 64 * ONB; e += TNT) {
-      const int j = e / 64, rr = e % 64, r = r0 + rr, k = k0 + j;
-      Vs[rr][j] = (j < nb && r < n && r > k) ? (r == k + 1 ? 1.0 : Vh[(long long)k * n + r]) : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int e = t + TNT * q, i = e / ONB, j = e % ONB;
-      if (i < j) {
-        double a = g[q];
-        for (int rr = 0; rr < 64; ++rr) a += Vs[rr][i] * Vs[rr][j];
-        g[q] = a;
-      }
-    }
+// V as explicit columns (zero above the unit entry, zero past the last reflector), and Q = I.
+__global__ __launch_bounds__(256) void formq_init_k(int n, int nref, int ncol, const double* __restrict__ Vh,
+                                                    double* __restrict__ Vc, double* __restrict__ Q) {
+  const long long tot = (long long)n * ncol, i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i < tot) {
+    const int c = (int)(i / n), r = (int)(i % n);
+    Vc[i] = (c < nref && r > c) ? (r == c + 1 ? 1.0 : Vh[(long long)c * n + r]) : 0.0;
   }
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    const int e = t + TNT * q;
-    G[e / ONB][e % ONB] = g[q];
-    T[e / ONB][e % ONB] = 0.0;
-  }
-  __syncthreads();
-  for (int j = 0; j < nb; ++j) {
-    const double tj = tau[k0 + j];
-    if (t < j) {
-      double a = 0.0;
-      for (int l = t; l < j; ++l) a += T[t][l] * G[l][j];
-      T[t][j] = -tj * a;
-    } else if (t == j) {
-      T[j][j] = tj;
-    }
-    __syncthreads();
-  }
-  for (int e = t; e < ONB * ONB; e += TNT) Tall[(long long)blockIdx.x * ONB * ONB + e] = T[e / ONB][e % ONB];
+  if (i < (long long)n * n) Q[i] = (i / n == i % n) ? 1.0 : 0.0;
 }
 
-// Q = Q I on OCW columns per workgroup (Z starts as the identity panel): for each block b, last to
-// first, W1 = V^T Z (threads (j, g) sum rows r = g mod 8, then the 8 partials are added in order),
-// W2 = T W1, Z -= V W2.  Column c of the identity is left alone by every reflector k >= c (its
-// vector is zero on rows <= k), so a panel starts at the first block that reaches its columns.
-// Loads of V are issued in batches (16 per thread in W1, 32 in the update) so that their latency
-// is paid once per batch.
-__global__ __launch_bounds__(TNT) void ormtr_k(int n, int nref, const double* __restrict__ Vh,
-                                               const double* __restrict__ Tall, double* __restrict__ Z) {
-  __shared__ double Zs[TRIDIAG_MAX_N * OCW];
-  __shared__ double Wp[8][ONB][OCW];
-  __shared__ double W1[ONB][OCW];
-  __shared__ double W2[ONB][OCW];
-  __shared__ double Ts[ONB][ONB];
-  const int t = threadIdx.x, c0 = blockIdx.x * OCW;
-  for (int e = t; e < n * OCW; e += TNT) {
-    const int c = e / n, r = e % n;
-    Zs[r * OCW + c] = (c0 + c < n && r == c0 + c) ? 1.0 : 0.0;
+// T of every block (one workgroup each) from the block's Gram matrix G = V^T V (row-major QNB x QNB).
+// Within a run of 32 reflectors, column j follows from the earlier ones: T[j][j] = tau_j,
+// T[0:j][j] = -tau_j T[0:j][0:j] G[0:j][j] (one wavefront per run, in parallel).  Adjacent triangles
+// then merge as T = [[T1, -T1 G12 T2], [0, T2]] (the product of two compact WY factors), 32 + 32 and
+// then 64 + 64; the scratch X = G12 T2 lives in T's empty lower triangle.  Zero past the block's last
+// reflector.
+__device__ __forceinline__ void formq_merge(double (*T)[QNB + 1], const double* __restrict__ G, int off, int h, int t0,
+                                            int nt) {
+  // X[i][c] = sum_{l <= c} G[off + i][off + h + l] T[off + h + l][off + h + c], stored at T[off + h + i][off + c]
+  for (int e = t0; e < h * h; e += nt) {
+    const int i = e / h, c = e % h;
+    double a = 0.0;
+    for (int l = 0; l <= c; ++l) a += G[(off + i) * QNB + off + h + l] * T[off + h + l][off + h + c];
+    T[off + h + i][off + c] = a;
   }
-  const int nblk = (nref + ONB - 1) / ONB;
-  const int bstart = min(nblk - 1, max(0, c0 + OCW - 2) / ONB);
-  constexpr int U1 = 16, JG = 4;
-  for (int b = bstart; b >= 0; --b) {
-    const int k0 = b * ONB, nb = min(ONB, nref - k0);
-    for (int e = t; e < ONB * ONB; e += TNT) Ts[e / ONB][e % ONB] = Tall[(long long)b * ONB * ONB + e];
-    __syncthreads();   // Zs (panel load or previous block's update) and Ts visible
-    {
-      const int j = t >> 3, g = t & 7, k = k0 + j;
-      double acc[OCW];
-#pragma unroll
-      for (int c = 0; c < OCW; ++c) acc[c] = 0.0;
-      if (j < nb) {
-        const double* __restrict__ v = Vh + (long long)k * n;
-        for (int r0 = k + 1 + g; r0 < n; r0 += 8 * U1) {
-          double vv[U1];
-#pragma unroll
-          for (int u = 0; u < U1; ++u) {
-            const int r = r0 + 8 * u;
-            vv[u] = r < n ? (r == k + 1 ? 1.0 : v[r]) : 0.0;
-          }
-#pragma unroll
-          for (int u = 0; u < U1; ++u) {
-            const int r = r0 + 8 * u;
-            if (r < n) {
-#pragma unroll
-              for (int c = 0; c < OCW; ++c) acc[c] += vv[u] * Zs[r * OCW + c];
-            }
-          }
-        }
+}
+__device__ __forceinline__ void formq_merge2(double (*T)[QNB + 1], int off, int h, int t0, int nt) {
+  // T[off + i][off + h + c] = -sum_{l >= i} T[off + i][off + l] X[l][c]
+  for (int e = t0; e < h * h; e += nt) {
+    const int i = e / h, c = e % h;
+    double a = 0.0;
+    for (int l = i; l < h; ++l) a += T[off + i][off + l] * T[off + h + l][off + c];
+    T[off + i][off + h + c] = -a;
+  }
+}
+
+__global__ __launch_bounds__(TNT) void formq_t_k(int nref, const double* __restrict__ tau, const double* __restrict__ Gall,
+                                                 double* __restrict__ Tall) {
+  __shared__ double T[QNB][QNB + 1];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int k0 = blockIdx.x * QNB, nb = min(QNB, nref - k0);
+  const double* G = Gall + (long long)blockIdx.x * QNB * QNB;
+  for (int e = t; e < QNB * QNB; e += TNT) T[e / QNB][e % QNB] = 0.0;
+  __syncthreads();
+  const int c0 = 32 * wv;
+  for (int jj = 0; jj < 32; ++jj) {
+    const int j = c0 + jj;
+    if (j < nb) {
+      if (lane < jj) {
+        double a = 0.0;
+        for (int l = lane; l < jj; ++l) a += T[c0 + lane][c0 + l] * G[(c0 + l) * QNB + j];
+        T[c0 + lane][j] = -tau[k0 + j] * a;
+      } else if (lane == jj) {
+        T[j][j] = tau[k0 + j];
       }
-#pragma unroll
-      for (int c = 0; c < OCW; ++c) Wp[g][j][c] = acc[c];
     }
     __syncthreads();
-    {
-      const int j = t >> 3, c = t & 7;
-      double a = 0.0;
-#pragma unroll
-      for (int g = 0; g < 8; ++g) a += Wp[g][j][c];
-      W1[j][c] = a;
-    }
-    __syncthreads();
-    {
-      const int i = t >> 3, c = t & 7;
-      double a = 0.0;
-      for (int l = i; l < nb; ++l) a += Ts[i][l] * W1[l][c];
-      W2[i][c] = a;   // zero for i >= nb
-    }
-    __syncthreads();
-    double z[ORPT][OCW];
-#pragma unroll
-    for (int q = 0; q < ORPT; ++q) {
-      const int r = k0 + 1 + t + TNT * q;
-#pragma unroll
-      for (int c = 0; c < OCW; ++c) z[q][c] = r < n ? Zs[r * OCW + c] : 0.0;
-    }
-    for (int j0 = 0; j0 < nb; j0 += JG) {
-      double vv[JG][ORPT];
-#pragma unroll
-      for (int jj = 0; jj < JG; ++jj) {
-        const int k = k0 + j0 + jj;
-#pragma unroll
-        for (int q = 0; q < ORPT; ++q) {
-          const int r = k0 + 1 + t + TNT * q;
-          vv[jj][q] = (j0 + jj < nb && r > k && r < n) ? (r == k + 1 ? 1.0 : Vh[(long long)k * n + r]) : 0.0;
-        }
-      }
-#pragma unroll
-      for (int jj = 0; jj < JG; ++jj) {
-        double w[OCW];
-#pragma unroll
-        for (int c = 0; c < OCW; ++c) w[c] = W2[min(j0 + jj, ONB - 1)][c];
-#pragma unroll
-        for (int q = 0; q < ORPT; ++q)
-#pragma unroll
-          for (int c = 0; c < OCW; ++c) z[q][c] -= vv[jj][q] * w[c];
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < ORPT; ++q) {
-      const int r = k0 + 1 + t + TNT * q;
-      if (r < n) {
-#pragma unroll
-        for (int c = 0; c < OCW; ++c) Zs[r * OCW + c] = z[q][c];
-      }
-    }
-    __syncthreads();   // Wp, W1, W2 and Ts are rewritten by the next block
+  }
+  // 32 + 32 (two merges at once, half the block each), then 64 + 64
+  formq_merge(T, G, (t >> 7) * 64, 32, t & 127, 128);
+  __syncthreads();
+  formq_merge2(T, (t >> 7) * 64, 32, t & 127, 128);
+  __syncthreads();
+  for (int e = t; e < 2 * 32 * 32; e += TNT) {   // clear the scratch
+    const int q = e >> 10, i = (e >> 5) & 31, c = e & 31;
+    T[q * 64 + 32 + i][q * 64 + c] = 0.0;
   }
   __syncthreads();
-  for (int e = t; e < n * OCW; e += TNT) {
-    const int c = e / n, r = e % n;
-    if (c0 + c < n) Z[(long long)(c0 + c) * n + r] = Zs[r * OCW + c];
+  formq_merge(T, G, 0, 64, t, TNT);
+  __syncthreads();
+  formq_merge2(T, 0, 64, t, TNT);
+  __syncthreads();
+  double* Tb = Tall + (long long)blockIdx.x * QNB * QNB;
+  for (int e = t; e < QNB * QNB; e += TNT) {
+    const int i = e / QNB, c = e % QNB;
+    Tb[e] = c >= i ? T[i][c] : 0.0;
   }
+}
+
+// W1 (QNB x mb, ld n) = the sum of the ks split-K slabs (each QNB x mb, dense).
+__global__ __launch_bounds__(256) void formq_sum_k(int mb, int n, int ks, const double* __restrict__ part,
+                                                   double* __restrict__ W1) {
+  const long long tot = (long long)QNB * mb, e = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= tot) return;
+  double a = 0.0;
+  for (int s = 0; s < ks; ++s) a += part[s * tot + e];
+  W1[(e / mb) * n + e % mb] = a;
 }
 
 }  // namespace
 
-hipError_t form_q_f64(hipStream_t s, int n, const double* Vh, const double* tau, double* Tall, double* Q) {
+long long form_q_ws_doubles(int n) {
+  const long long nb = formq_blocks(n);
+  return nb * QNB * n + 2 * nb * QNB * QNB + (2LL + FORMQ_KS) * QNB * n + 64;
+}
+
+hipError_t form_q_f64(hipStream_t s, int n, const double* Vh, const double* tau, double* ws, double* Q) {
   if (n < 3 || n > TRIDIAG_MAX_N) return hipErrorInvalidValue;
-  const int nref = n - 1, nblk = cdiv(nref, ONB);
-  hipLaunchKernelGGL(larft_k, dim3(nblk), dim3(TNT), 0, s, n, nref, Vh, tau, Tall);
-  hipLaunchKernelGGL(ormtr_k, dim3(cdiv(n, OCW)), dim3(TNT), 0, s, n, nref, Vh, Tall, Q);
+  const int nref = n - 1, nb = formq_blocks(n), ncol = nb * QNB;
+  double* Vc = ws;                                  // n x ncol, column-major
+  double* G = Vc + (long long)n * ncol;             // nb x QNB x QNB
+  double* T = G + (long long)nb * QNB * QNB;        // nb x QNB x QNB
+  double* W1 = T + (long long)nb * QNB * QNB;       // QNB x n, row-major (ld n)
+  double* W2 = W1 + (long long)QNB * n;             // QNB x n
+  double* part = W2 + (long long)QNB * n;           // FORMQ_KS slabs of QNB x mb
+  const long long tot = (long long)n * std::max(ncol, n);
+  hipLaunchKernelGGL(formq_init_k, dim3((unsigned)cdiv(tot, 256)), dim3(256), 0, s, n, nref, ncol, Vh, Vc, Q);
+  // G_b = V_b^T V_b
+  hipError_t e = gemm_f64(s, QNB, QNB, n, nb, 1.0, Vc, n, 1, (long long)QNB * n, Vc, 1, n, (long long)QNB * n, 0.0,
+                          G, QNB, 1, (long long)QNB * QNB);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(formq_t_k, dim3(nb), dim3(TNT), 0, s, nref, tau, G, T);
+  for (int b = nb - 1; b >= 0; --b) {
+    const int k0 = b * QNB, mb = n - k0 - 1;
+    const double* Vb = Vc + (long long)k0 * n + k0 + 1;   // V_b(r, i) = Vb[i * n + r], rows k0 + 1 ..
+    double* Zb = Q + (long long)(k0 + 1) * n + k0 + 1;    // Z(r, c) = Zb[c * n + r]
+    // W1 = V_b^T Z, W2 = T_b W1, Z -= V_b W2
+    // the first product has few output tiles (QNB x mb) and a long k: split over k, slabs summed
+    const int ks = std::min(FORMQ_KS, std::max(1, mb / 128));
+    if ((e = gemm_f64_splitk(s, QNB, mb, mb, ks, Vb, n, 1, Zb, 1, n, part)) != hipSuccess) return e;
+    hipLaunchKernelGGL(formq_sum_k, dim3((unsigned)cdiv((long long)QNB * mb, 256)), dim3(256), 0, s, mb, n, ks, part, W1);
+    if ((e = gemm_f64(s, QNB, mb, QNB, 1, 1.0, T + (long long)b * QNB * QNB, QNB, 1, 0, W1, n, 1, 0, 0.0, W2, n, 1, 0)) !=
+        hipSuccess)
+      return e;
+    if ((e = gemm_f64(s, mb, mb, QNB, 1, -1.0, Vb, 1, n, 0, W2, n, 1, 0, 1.0, Zb, 1, n, 0)) != hipSuccess) return e;
+  }
   return hipGetLastError();
 }
 

@@ -11,7 +11,7 @@
 // coupling b = e[cut - 1] is taken out as a rank-one term: both adjacent diagonal entries lose |b|,
 // and the parent is blockdiag(T1, T2) + |b| v v^T with v = e_last(T1) + sign(b) e_first(T2).
 //
-// Leaves: one workgroup each, cyclic Jacobi (round-robin pairs, the matrix in LDS).
+// Leaves: one wavefront each, cyclic Jacobi (round-robin pairs, the matrix in LDS).
 // Merge of two children with eigen-decompositions T1 = Q1 D1 Q1^T, T2 = Q2 D2 Q2^T, per level, for
 // all parents of the level at once (kernels in launch order):
 //   deflate  z = [last row of Q1, sign(b) first row of Q2] / sqrt 2, rho = 2 |b|; the children's
@@ -19,7 +19,10 @@
 //            are, and a neighbour pair whose rotation zeroing one z entry perturbs the matrix by
 //            less than tol is rotated (the rotated entry leaves); tol = 8 eps max(|d|, |z|).  The
 //            rotations form chains (each continues with the surviving entry), replayed later on
-//            the eigenvector columns.  The k survivors keep strictly increasing d.
+//            the eigenvector columns.  The k survivors keep strictly increasing d.  Only the
+//            rotations are sequential: the z test, and the rotation test of every neighbour pair
+//            on the values before any rotation, run in parallel; a chain is walked serially from
+//            each pair that passes (a pair after a chain's end sees unrotated values again).
 //   secular  root i of 1/rho + sum_j z_j^2 / (d_j - x) = 0 in (d_i, d_i+1) (the last one in
 //            (d_k-1, d_k-1 + rho |z|^2]), one wavefront per root, stored as an offset tau from
 //            the nearer pole so that every d_j - x is formed without cancellation.  Iteration:
@@ -38,16 +41,17 @@
 //   gemm     the survivors' eigenvectors: first child's rows = compact[rows of T1, first two
 //            groups] U[first two groups, :], second child's rows likewise with the last two groups,
 //            so the zero blocks of blockdiag(Q1, Q2) are never multiplied.
-// Eigenvalues and vectors ping-pong between the caller's (w, Z) and a workspace pair by level
-// parity, so that the last merge writes the caller's arrays.
+// Launches per level: deflate | secular | rank + zhat | vec + gather + chain | gemm.  Eigenvalues and
+// vectors ping-pong between the caller's (w, Z) and a workspace pair by level parity, so that the
+// last merge writes the caller's arrays.
 #include "common.h"
 #include "f64_tile.h"
 
 namespace pnof {
 namespace {
 
-constexpr int DC_LEAF = 48;                 // rows of a leaf at most (Jacobi in one workgroup)
-constexpr int DC_LP = DC_LEAF + 2;          // leaf LDS row pitch (one padding row for odd sizes)
+constexpr int DC_LEAF = 16;                 // rows of a leaf at most (Jacobi in one wavefront)
+constexpr int DC_LP = DC_LEAF + 1;          // leaf LDS row pitch
 constexpr int DMAX = TRIDIAG_MAX_N;
 constexpr int SQ = DMAX / 64;               // entries per lane of a wavefront over one parent
 constexpr double UEPS = 1.1102230246251565e-16;   // unit roundoff 2^-53
@@ -134,19 +138,20 @@ __global__ __launch_bounds__(1024) void dc_prep_k(DcWs w, const double* __restri
   }
 }
 
-// One leaf per workgroup: cyclic Jacobi with round-robin pairs (every round rotates m/2 disjoint
+// One leaf per wavefront: cyclic Jacobi with round-robin pairs (every round rotates m/2 disjoint
 // pairs at once), until a sweep rotates nothing.  A pair is left alone when its off-diagonal entry
-// is below eps sqrt(|a_pp a_qq|) or 1e-3 eps of the leaf's largest entry.
-__global__ __launch_bounds__(256) void dc_leaf_k(DcWs w) {
+// is below eps sqrt(|a_pp a_qq|) or 1e-3 eps of the leaf's largest entry.  Odd sizes add a zero
+// row and column whose pair never rotates.
+__global__ __launch_bounds__(64) void dc_leaf_k(DcWs w) {
   const int n = w.n, T = w.T, tid = threadIdx.x;
   const int o = seg_lo(n, T, blockIdx.x), m = seg_lo(n, T, blockIdx.x + 1) - o;
   const int mp = m + (m & 1), np = mp / 2;
-  __shared__ double A[DC_LEAF + 1][DC_LP], V[DC_LEAF + 1][DC_LP];
-  __shared__ double pc[DC_LEAF / 2 + 1], ps[DC_LEAF / 2 + 1], pt[DC_LEAF / 2 + 1];
-  __shared__ int pp[DC_LEAF / 2 + 1], pq[DC_LEAF / 2 + 1], prot[DC_LEAF / 2 + 1];
+  __shared__ double A[DC_LEAF][DC_LP], V[DC_LEAF][DC_LP];
+  __shared__ double pc[DC_LEAF / 2], ps[DC_LEAF / 2], pt[DC_LEAF / 2];
+  __shared__ int pp[DC_LEAF / 2], pq[DC_LEAF / 2], prot[DC_LEAF / 2];
   __shared__ int any;
-  __shared__ double anrm;
-  for (int x = tid; x < mp * mp; x += 256) {
+  double mx = 0.0;
+  for (int x = tid; x < mp * mp; x += 64) {
     const int r = x / mp, c = x % mp;
     double a = 0.0;
     if (r < m && c < m) {
@@ -156,17 +161,11 @@ __global__ __launch_bounds__(256) void dc_leaf_k(DcWs w) {
     }
     A[r][c] = a;
     V[r][c] = r == c ? 1.0 : 0.0;
+    mx = fmax(mx, fabs(a));
   }
+  const double athr = 1e-3 * UEPS * wmax(mx);
   __syncthreads();
-  if (tid < 64) {
-    double v = 0.0;
-    for (int x = tid; x < m * m; x += 64) v = fmax(v, fabs(A[x / m][x % m]));
-    v = wmax(v);
-    if (tid == 0) anrm = v;
-  }
-  __syncthreads();
-  const double athr = 1e-3 * UEPS * anrm;
-  for (int sweep = 0; sweep < 40 && mp > 1; ++sweep) {
+  for (int sweep = 0; sweep < 40; ++sweep) {
     if (tid == 0) any = 0;
     __syncthreads();
     for (int r = 0; r < mp - 1; ++r) {
@@ -175,7 +174,7 @@ __global__ __launch_bounds__(256) void dc_leaf_k(DcWs w) {
         if (tid == 0) { p = r; q = mp - 1; }
         else { p = (r + tid) % (mp - 1); q = (r - tid + mp - 1) % (mp - 1); }
         if (p > q) { const int x = p; p = q; q = x; }
-        double c = 1.0, s = 0.0, tt = 0.0;
+        double c = 1.0, sn = 0.0, tt = 0.0;
         int rot = 0;
         if (q < m) {
           const double apq = A[p][q], app = A[p][p], aqq = A[q][q];
@@ -183,22 +182,22 @@ __global__ __launch_bounds__(256) void dc_leaf_k(DcWs w) {
             const double th = (aqq - app) / (2.0 * apq);
             tt = fabs(th) > 1e150 ? 0.5 / th : copysign(1.0, th) / (fabs(th) + sqrt(1.0 + th * th));
             c = 1.0 / sqrt(1.0 + tt * tt);
-            s = tt * c;
+            sn = tt * c;
             rot = 1;
           }
         }
-        pp[tid] = p; pq[tid] = q; pc[tid] = c; ps[tid] = s; pt[tid] = tt; prot[tid] = rot;
+        pp[tid] = p; pq[tid] = q; pc[tid] = c; ps[tid] = sn; pt[tid] = tt; prot[tid] = rot;
         if (rot) any = 1;
       }
       __syncthreads();
       // A <- J^T A J on 2 x 2 blocks (pair P1 <= P2, mirrored), V <- V J
       const int nblk = np * (np + 1) / 2;
-      for (int b = tid; b < nblk; b += 256) {
-        int P1 = 0, rem = b;
+      for (int bk = tid; bk < nblk; bk += 64) {
+        int P1 = 0, rem = bk;
         while (rem >= np - P1) { rem -= np - P1; ++P1; }
         const int P2 = P1 + rem;
-        const int p1 = pp[P1], q1 = pq[P1], p2 = pp[P2], q2 = pq[P2];
         if (!prot[P1] && !prot[P2]) continue;
+        const int p1 = pp[P1], q1 = pq[P1], p2 = pp[P2], q2 = pq[P2];
         if (P1 == P2) {
           const double apq = A[p1][q1];
           A[p1][p1] -= pt[P1] * apq;
@@ -218,13 +217,13 @@ __global__ __launch_bounds__(256) void dc_leaf_k(DcWs w) {
         A[q1][p2] = n10; A[p2][q1] = n10;
         A[q1][q2] = n11; A[q2][q1] = n11;
       }
-      for (int x = tid; x < mp * np; x += 256) {
+      for (int x = tid; x < mp * np; x += 64) {
         const int row = x / np, P = x % np;
         if (!prot[P]) continue;
         const int p = pp[P], q = pq[P];
-        const double c = pc[P], s = ps[P], vp = V[row][p], vq = V[row][q];
-        V[row][p] = c * vp - s * vq;
-        V[row][q] = s * vp + c * vq;
+        const double c = pc[P], sn = ps[P], vp = V[row][p], vq = V[row][q];
+        V[row][p] = c * vp - sn * vq;
+        V[row][q] = sn * vp + c * vq;
       }
       __syncthreads();
     }
@@ -235,7 +234,7 @@ __global__ __launch_bounds__(256) void dc_leaf_k(DcWs w) {
   // ascending order (ties by index), written at the leaf's block of the level-T buffers
   const int ob = T & 1;
   const double sc = T == 0 ? w.scale[0] : 1.0;
-  for (int i = tid; i < m; i += 256) {
+  for (int i = tid; i < m; i += 64) {
     const double v = A[i][i];
     int rk = 0;
     for (int y = 0; y < m; ++y) {
@@ -248,8 +247,41 @@ __global__ __launch_bounds__(256) void dc_leaf_k(DcWs w) {
   }
 }
 
-// Deflation, one workgroup per parent; the scan over the merged list is serial (thread 0), the rest
-// is spread over the block.
+// Exclusive prefix over the 256 threads of a block of each thread's count v; total in `total`.
+__device__ __forceinline__ int block_scan(int v, int* sh, int& total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) sh[wv] = x;
+  __syncthreads();
+  int base = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int c = sh[i];
+    base += i < wv ? c : 0;
+    tot += c;
+  }
+  __syncthreads();
+  total = tot;
+  return base + x - v;
+}
+
+// Rotation of the neighbour pair (pj, s) of the merged list that zeroes z[pj], and whether the
+// matrix it leaves out, |(d_s - d_pj) C S|, is within tol.
+__device__ __forceinline__ bool pair_rot(double zp, double zs, double dp, double ds, double tol, double& C, double& S,
+                                         double& tau) {
+  tau = hypot(zs, zp);
+  C = zs / tau;
+  S = -zp / tau;
+  return fabs((ds - dp) * C * S) <= tol;
+}
+
+// Deflation, one workgroup per parent.  Each thread owns 8 consecutive places of the merged list
+// (TRIDIAG_MAX_N = 256 x 8); compactions go through block prefix sums.
 __global__ __launch_bounds__(256) void dc_deflate_k(DcWs w, int t) {
   const int n = w.n, tid = threadIdx.x, j0 = blockIdx.x;
   const int o = seg_lo(n, t, j0), m = seg_lo(n, t, j0 + 1) - o;
@@ -259,13 +291,17 @@ __global__ __launch_bounds__(256) void dc_deflate_k(DcWs w, int t) {
   const double* Z = w.zbuf[in];
   const double b = w.es[o + m1 - 1];
   const double rho = 2.0 * fabs(b), sg = b < 0.0 ? -1.0 : 1.0;
-  // by position in the merged ascending list
+  // by place in the merged ascending list
   __shared__ double sd[DMAX], sz[DMAX];
-  __shared__ short ssrc[DMAX], snd[DMAX], sdf[DMAX];
-  __shared__ unsigned char smask[DMAX], sinch[DMAX];
+  __shared__ short ssrc[DMAX];   // local source column
+  __shared__ short sl[DMAX];     // survivors of the z test, in order
+  __shared__ short sx[DMAX];     // flagged pairs, then the final survivors
+  __shared__ short sdf[DMAX];    // deflated places
+  __shared__ unsigned char smask[DMAX];   // rows touched: 1 first child, 2 second
+  __shared__ unsigned char sflg[DMAX];    // 1 z-deflated, 2 rotated out, 4 in a chain
   __shared__ double red[8];
-  __shared__ int cnt[256][3];
-  __shared__ int tot[5];
+  __shared__ int sh[4];
+  __shared__ int snc;
   double md = 0.0, mz = 0.0;
   for (int j = tid; j < m; j += 256) {
     const double dj = din[j];
@@ -285,7 +321,6 @@ __global__ __launch_bounds__(256) void dc_deflate_k(DcWs w, int t) {
     sz[rk] = zj;
     ssrc[rk] = (short)j;
     smask[rk] = j < m1 ? 1 : 2;
-    sinch[rk] = 0;
     md = fmax(md, fabs(dj));
     mz = fmax(mz, fabs(zj));
   }
@@ -295,94 +330,112 @@ __global__ __launch_bounds__(256) void dc_deflate_k(DcWs w, int t) {
   __syncthreads();
   const double tol = 8.0 * UEPS * fmax(fmax(fmax(red[0], red[1]), fmax(red[2], red[3])),
                                        fmax(fmax(red[4], red[5]), fmax(red[6], red[7])));
+  const int e0 = tid * 8, e1 = min(m, e0 + 8);
+  // z test; survivors compacted in order
+  int cnt = 0;
+  for (int x = e0; x < e1; ++x) {
+    const bool dz = rho * fabs(sz[x]) <= tol;
+    sflg[x] = dz ? 1 : 0;
+    cnt += !dz;
+  }
+  int ns;
+  int pos = block_scan(cnt, sh, ns);
+  for (int x = e0; x < e1; ++x)
+    if (!sflg[x]) sl[pos++] = (short)x;
+  __syncthreads();
+  // neighbour pairs of survivors that rotate on unrotated values
+  cnt = 0;
+  unsigned pf = 0;
+  for (int q = e0; q < min(ns - 1, e0 + 8); ++q) {
+    double C, S, tau;
+    const int a = sl[q], c = sl[q + 1];
+    if (pair_rot(sz[a], sz[c], sd[a], sd[c], tol, C, S, tau)) { pf |= 1u << (q - e0); ++cnt; }
+  }
+  int nfl;
+  pos = block_scan(cnt, sh, nfl);
+  for (int q = e0; q < min(ns - 1, e0 + 8); ++q)
+    if (pf >> (q - e0) & 1) sx[pos++] = (short)q;
+  __syncthreads();
+  // rotation chains, walked serially from each flagged pair not yet consumed
   if (tid == 0) {
-    int k = 0, nd = 0, nc = 0, cpos = 0, pj = -1;
-    bool open = false;
+    int nc = 0, cpos = 0, next = 0;
     int* cm = w.cm + o;
     double* rc = w.rc + o;
     double* rs = w.rs + o;
-    for (int s = 0; s < m; ++s) {
-      if (rho * fabs(sz[s]) <= tol) { sdf[nd++] = (short)s; continue; }
-      if (pj < 0) { pj = s; continue; }
-      const double zp = sz[pj], zs = sz[s];
-      const double tau = hypot(zs, zp);
-      const double C = zs / tau, S = -zp / tau;
-      if (fabs((sd[s] - sd[pj]) * C * S) <= tol) {
+    for (int f = 0; f < nfl; ++f) {
+      int q = sx[f];
+      if (q < next) continue;
+      int pj = sl[q];
+      bool open = false;
+      while (q + 1 < ns) {
+        const int x = sl[q + 1];
+        double C, S, tau;
+        if (!pair_rot(sz[pj], sz[x], sd[pj], sd[x], tol, C, S, tau)) break;
         if (!open) {
           w.chs[o + nc] = cpos;
           cm[cpos++] = ssrc[pj];
-          sinch[pj] = 1;
+          sflg[pj] |= 4;
           open = true;
         }
         rc[cpos - 1] = C;
         rs[cpos - 1] = S;
-        cm[cpos++] = ssrc[s];
-        sinch[s] = 1;
-        sz[s] = tau;
+        cm[cpos++] = ssrc[x];
+        sflg[x] |= 4;
+        sz[x] = tau;
         sz[pj] = 0.0;
-        const double dp = sd[pj], dn = sd[s];
+        const double dp = sd[pj], dn = sd[x];
         sd[pj] = dp * C * C + dn * S * S;
-        sd[s] = dp * S * S + dn * C * C;
-        smask[s] |= smask[pj];
-        sdf[nd++] = (short)pj;
-        pj = s;
-      } else {
-        if (open) { w.chl[o + nc] = cpos - 1 - w.chs[o + nc]; ++nc; open = false; }
-        snd[k++] = (short)pj;
-        pj = s;
+        sd[x] = dp * S * S + dn * C * C;
+        smask[x] |= smask[pj];
+        sflg[pj] |= 2;
+        pj = x;
+        ++q;
       }
-    }
-    if (pj >= 0) {
       if (open) { w.chl[o + nc] = cpos - 1 - w.chs[o + nc]; ++nc; }
-      snd[k++] = (short)pj;
+      next = q + 1;
     }
-    tot[0] = k;
-    tot[1] = nd;
-    tot[2] = nc;
+    snc = nc;
   }
   __syncthreads();
-  const int k = tot[0], nd = tot[1];
-  // survivors: groups by the rows they touch, compact positions in group order
-  const int per = (k + 255) / 256, i0 = tid * per, i1 = min(k, i0 + per);
+  // final survivors in order, with their groups; deflated places in order
   int c1 = 0, c3 = 0, c2 = 0;
-  for (int i = i0; i < i1; ++i) {
-    const int g = smask[snd[i]];
+  cnt = 0;
+  for (int q = e0; q < min(ns, e0 + 8); ++q) {
+    const int x = sl[q];
+    if (sflg[x] & 2) continue;
+    ++cnt;
+    const int g = smask[x];
     c1 += g == 1; c3 += g == 3; c2 += g == 2;
   }
-  cnt[tid][0] = c1; cnt[tid][1] = c3; cnt[tid][2] = c2;
-  __syncthreads();
-  if (tid == 0) {
-    int a1 = 0, a3 = 0, a2 = 0;
-    for (int x = 0; x < 256; ++x) {
-      const int v1 = cnt[x][0], v3 = cnt[x][1], v2 = cnt[x][2];
-      cnt[x][0] = a1; cnt[x][1] = a3; cnt[x][2] = a2;
-      a1 += v1; a3 += v3; a2 += v2;
+  int k, n1, n12, n3, nd;
+  pos = block_scan(cnt, sh, k);
+  int b1 = block_scan(c1, sh, n1), b3 = block_scan(c3, sh, n12), b2 = block_scan(c2, sh, n3);
+  for (int q = e0; q < min(ns, e0 + 8); ++q) {
+    const int x = sl[q];
+    if (sflg[x] & 2) continue;
+    const int g = smask[x];
+    const int cp = g == 1 ? b1++ : (g == 3 ? n1 + b3++ : n1 + n12 + b2++);
+    w.dl[o + pos] = sd[x];
+    w.zl[o + pos] = sz[x];
+    w.qpos[o + pos] = cp;
+    w.dest[o + ssrc[x]] = cp;
+    ++pos;
+  }
+  cnt = 0;
+  for (int x = e0; x < e1; ++x) cnt += (sflg[x] & 3) != 0;
+  pos = block_scan(cnt, sh, nd);
+  for (int x = e0; x < e1; ++x)
+    if (sflg[x] & 3) {
+      w.val[o + k + pos] = sd[x];
+      w.dest[o + ssrc[x]] = -1 - pos;
+      ++pos;
     }
-    tot[3] = a1;
-    tot[4] = a3;
+  for (int x = e0; x < e1; ++x) w.inch[o + ssrc[x]] = (sflg[x] & 4) ? 1 : 0;
+  if (tid == 0) {
     DcPar P;
-    P.k = k; P.n1 = a1; P.n12 = a3; P.n3 = a2; P.ndef = nd; P.nchain = tot[2]; P.rho = rho;
+    P.k = k; P.n1 = n1; P.n12 = n12; P.n3 = n3; P.ndef = nd; P.nchain = snc; P.rho = rho;
     w.par[j0] = P;
   }
-  __syncthreads();
-  {
-    const int n1 = tot[3], n12 = tot[4];
-    int b1 = cnt[tid][0], b3 = cnt[tid][1], b2 = cnt[tid][2];
-    for (int i = i0; i < i1; ++i) {
-      const int s = snd[i], g = smask[s];
-      const int pos = g == 1 ? b1++ : (g == 3 ? n1 + b3++ : n1 + n12 + b2++);
-      w.dl[o + i] = sd[s];
-      w.zl[o + i] = sz[s];
-      w.qpos[o + i] = pos;
-      w.dest[o + ssrc[s]] = pos;
-    }
-  }
-  for (int q = tid; q < nd; q += 256) {
-    const int s = sdf[q];
-    w.val[o + k + q] = sd[s];
-    w.dest[o + ssrc[s]] = -1 - q;
-  }
-  for (int s = tid; s < m; s += 256) w.inch[o + ssrc[s]] = sinch[s];
 }
 
 // Root i of the secular equation of its parent, one wavefront per root.
@@ -431,8 +484,8 @@ __global__ __launch_bounds__(256) void dc_secular_k(DcWs w, int t) {
     for (int q = 0; q < SQ; ++q) {
       const int j = lane + 64 * q;
       if (j < k) {
-        const double del = (dj[q] - dorg) - tau;
-        const double t1 = z2[q] / del, t2 = t1 / del;
+        const double rd = 1.0 / ((dj[q] - dorg) - tau);
+        const double t1 = z2[q] * rd, t2 = t1 * rd;
         if (j <= i) { psi += t1; dpsi += t2; }
         else { phi += t1; dphi += t2; }
         sab += fabs(t1);
@@ -483,29 +536,36 @@ __global__ __launch_bounds__(256) void dc_secular_k(DcWs w, int t) {
   }
 }
 
-// Place of every eigenvalue of a parent in its ascending output (ties by index).
-__global__ __launch_bounds__(256) void dc_rank_k(DcWs w, int t, int tiles) {
-  const int n = w.n, par = blockIdx.x / tiles, tile = blockIdx.x % tiles;
+// Place of every eigenvalue of a parent in its ascending output (ties by index); block (parent,
+// 64 values), the four wavefronts counting over quarters of the parent.
+__device__ __forceinline__ void rank_blk(const DcWs& w, int t, int par, int tile) {
+  const int n = w.n, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int o = seg_lo(n, t, par), m = seg_lo(n, t, par + 1) - o;
-  if (tile * 256 >= m) return;
+  if (tile * 64 >= m) return;
   __shared__ double sv[DMAX];
-  for (int x = threadIdx.x; x < m; x += 256) sv[x] = w.val[o + x];
+  __shared__ int part[4][64];
+  for (int x = tid; x < m; x += 256) sv[x] = w.val[o + x];
   __syncthreads();
-  const int x = tile * 256 + threadIdx.x;
-  if (x >= m) return;
-  const double v = sv[x];
+  const int x = tile * 64 + lane;
+  const double v = x < m ? sv[x] : 0.0;
+  const int y0 = (m * wv) >> 2, y1 = (m * (wv + 1)) >> 2;
   int r = 0;
-  for (int y = 0; y < m; ++y) {
+  for (int y = y0; y < y1; ++y) {
     const double u = sv[y];
     r += (u < v) || (u == v && y < x);
   }
-  w.rank[o + x] = r;
-  w.dbuf[t & 1][o + r] = t == 0 ? v * w.scale[0] : v;
+  part[wv][lane] = r;
+  __syncthreads();
+  if (wv == 0 && x < m) {
+    r = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
+    w.rank[o + x] = r;
+    w.dbuf[t & 1][o + r] = t == 0 ? v * w.scale[0] : v;
+  }
 }
 
-// Recomputed weight of survivor j, one wavefront per survivor.
-__global__ __launch_bounds__(256) void dc_zhat_k(DcWs w, int t) {
-  const int gw = (int)((blockIdx.x * 256u + threadIdx.x) >> 6), lane = threadIdx.x & 63;
+// Recomputed weight of survivor j (global wavefront index gw), one wavefront per survivor.
+__device__ __forceinline__ void zhat_wave(const DcWs& w, int t, int gw) {
+  const int lane = threadIdx.x & 63;
   if (gw >= w.n) return;
   const int par = parent_of(w.n, t, gw), o = seg_lo(w.n, t, par);
   const DcPar P = w.par[par];
@@ -525,9 +585,8 @@ __global__ __launch_bounds__(256) void dc_zhat_k(DcWs w, int t) {
 
 // Eigenvector i of diag(d) + rho zhat zhat^T, one wavefront per root, into column i of the
 // parent's block of Mm, rows in the compact order.
-__global__ __launch_bounds__(256) void dc_vec_k(DcWs w, int t) {
-  const int n = w.n;
-  const int gw = (int)((blockIdx.x * 256u + threadIdx.x) >> 6), lane = threadIdx.x & 63;
+__device__ __forceinline__ void vec_wave(const DcWs& w, int t, int gw) {
+  const int n = w.n, lane = threadIdx.x & 63;
   if (gw >= n) return;
   const int par = parent_of(n, t, gw), o = seg_lo(n, t, par);
   const DcPar P = w.par[par];
@@ -546,50 +605,48 @@ __global__ __launch_bounds__(256) void dc_vec_k(DcWs w, int t) {
   for (int j = lane; j < k; j += 64) col[w.qpos[o + j]] = zh[j] / ((dl[j] - dorg) - ti) * inv;
 }
 
+// Destination column of local source j of a parent: its compact place (survivors) or its output
+// place (deflated).
+__device__ __forceinline__ double* dest_col(const DcWs& w, int t, int o, int k, int j) {
+  const int dst = w.dest[o + j];
+  return dst >= 0 ? w.Qc + (long long)(o + dst) * w.n + o
+                  : w.zbuf[t & 1] + (long long)(o + w.rank[o + k - 1 - dst]) * w.n + o;
+}
+
 // Columns of blockdiag(Q1, Q2) that no rotation touches; block (parent, 64 rows, 32 columns).
-__global__ __launch_bounds__(256) void dc_gather_k(DcWs w, int t, int rt, int ct) {
+__device__ __forceinline__ void gather_blk(const DcWs& w, int t, int bx, int rt, int ct) {
   const int n = w.n;
-  int bx = blockIdx.x;
   const int tc = bx % ct;
   bx /= ct;
   const int tr = bx % rt, par = bx / rt;
   const int o = seg_lo(n, t, par), m = seg_lo(n, t, par + 1) - o;
   const int m1 = seg_lo(n, t + 1, 2 * par + 1) - o;
   const int r = tr * 64 + (threadIdx.x & 63);
-  if (tr * 64 >= m || tc * 32 >= m || r >= m) return;
+  if (tc * 32 >= m || r >= m) return;
   const int k = w.par[par].k;
   const double* Zin = w.zbuf[(t + 1) & 1];
-  double* Zout = w.zbuf[t & 1];
   for (int c = threadIdx.x >> 6; c < 32; c += 4) {
     const int j = tc * 32 + c;
     if (j >= m) break;
     if (w.inch[o + j]) continue;
-    const int dst = w.dest[o + j];
-    double* col = dst >= 0 ? w.Qc + (long long)(o + dst) * n + o : Zout + (long long)(o + w.rank[o + k - 1 - dst]) * n + o;
     const bool inblk = j < m1 ? r < m1 : r >= m1;
-    col[r] = inblk ? Zin[(long long)(o + j) * n + o + r] : 0.0;
+    dest_col(w, t, o, k, j)[r] = inblk ? Zin[(long long)(o + j) * n + o + r] : 0.0;
   }
 }
 
 // Rotation chains replayed on their columns, one thread per row; block (parent, 64 rows), the four
 // wavefronts taking every fourth chain.
-__global__ __launch_bounds__(256) void dc_chain_k(DcWs w, int t, int rt) {
-  const int n = w.n, par = blockIdx.x / rt, tr = blockIdx.x % rt;
+__device__ __forceinline__ void chain_blk(const DcWs& w, int t, int bx, int rt) {
+  const int n = w.n, par = bx / rt, tr = bx % rt;
   const int o = seg_lo(n, t, par), m = seg_lo(n, t, par + 1) - o;
   const int m1 = seg_lo(n, t + 1, 2 * par + 1) - o;
   const DcPar P = w.par[par];
   const int r = tr * 64 + (threadIdx.x & 63);
   if (P.nchain == 0 || r >= m) return;
   const double* Zin = w.zbuf[(t + 1) & 1];
-  double* Zout = w.zbuf[t & 1];
   auto val = [&](int j) {
     const bool inblk = j < m1 ? r < m1 : r >= m1;
     return inblk ? Zin[(long long)(o + j) * n + o + r] : 0.0;
-  };
-  auto put = [&](int j, double v) {
-    const int dst = w.dest[o + j];
-    double* col = dst >= 0 ? w.Qc + (long long)(o + dst) * n + o : Zout + (long long)(o + w.rank[o + P.k - 1 - dst]) * n + o;
-    col[r] = v;
   };
   for (int c = threadIdx.x >> 6; c < P.nchain; c += 4) {
     const int s0 = w.chs[o + c], L = w.chl[o + c];
@@ -597,11 +654,27 @@ __global__ __launch_bounds__(256) void dc_chain_k(DcWs w, int t, int rt) {
     for (int l = 0; l < L; ++l) {
       const double y = val(w.cm[o + s0 + l + 1]);
       const double C = w.rc[o + s0 + l], S = w.rs[o + s0 + l];
-      put(w.cm[o + s0 + l], C * x + S * y);
+      dest_col(w, t, o, P.k, w.cm[o + s0 + l])[r] = C * x + S * y;
       x = C * y - S * x;
     }
-    put(w.cm[o + s0 + L], x);
+    dest_col(w, t, o, P.k, w.cm[o + s0 + L])[r] = x;
   }
+}
+
+// After the roots: ranks (blocks [0, nrank)) and recomputed weights (the rest).
+__global__ __launch_bounds__(256) void dc_post1_k(DcWs w, int t, int tiles, int nrank) {
+  const int bx = blockIdx.x;
+  if (bx < nrank) rank_blk(w, t, bx / tiles, bx % tiles);
+  else zhat_wave(w, t, (int)(((bx - nrank) * 256u + threadIdx.x) >> 6));
+}
+
+// After the weights and ranks: eigenvectors of the rank-one updates (blocks [0, nvec)), untouched
+// columns (the next ngat), rotation chains (the rest).
+__global__ __launch_bounds__(256) void dc_post2_k(DcWs w, int t, int nvec, int ngat, int rt, int ct) {
+  const int bx = blockIdx.x;
+  if (bx < nvec) vec_wave(w, t, (int)((bx * 256u + threadIdx.x) >> 6));
+  else if (bx < nvec + ngat) gather_blk(w, t, bx - nvec, rt, ct);
+  else chain_blk(w, t, bx - nvec - ngat, rt);
 }
 
 // The survivors' eigenvectors: block (parent, child half, 64 rows, 32 roots); each root's column
@@ -679,19 +752,16 @@ hipError_t tridiag_eig_dc(hipStream_t s, int n, double* d, const double* e, doub
   w.par = reinterpret_cast<DcPar*>(take(4LL * n));
   w.info = info;
   hipLaunchKernelGGL(dc_prep_k, dim3(1), dim3(1024), 0, s, w, d, e);
-  hipLaunchKernelGGL(dc_leaf_k, dim3(1u << w.T), dim3(256), 0, s, w);
-  const unsigned waves = (unsigned)cdiv_i(n * 64, 256);
+  hipLaunchKernelGGL(dc_leaf_k, dim3(1u << w.T), dim3(64), 0, s, w);
+  const int waves = cdiv_i(n * 64, 256);
   for (int t = w.T - 1; t >= 0; --t) {
     const int np = 1 << t, mmax = cdiv_i(n, np), mcmax = cdiv_i(n, 2 * np);
     hipLaunchKernelGGL(dc_deflate_k, dim3(np), dim3(256), 0, s, w, t);
     hipLaunchKernelGGL(dc_secular_k, dim3(waves), dim3(256), 0, s, w, t);
-    const int rtl = cdiv_i(mmax, 256);
-    hipLaunchKernelGGL(dc_rank_k, dim3(np * rtl), dim3(256), 0, s, w, t, rtl);
-    hipLaunchKernelGGL(dc_zhat_k, dim3(waves), dim3(256), 0, s, w, t);
-    hipLaunchKernelGGL(dc_vec_k, dim3(waves), dim3(256), 0, s, w, t);
-    const int rt = cdiv_i(mmax, 64), ct = cdiv_i(mmax, 32);
-    hipLaunchKernelGGL(dc_gather_k, dim3(np * rt * ct), dim3(256), 0, s, w, t, rt, ct);
-    hipLaunchKernelGGL(dc_chain_k, dim3(np * rt), dim3(256), 0, s, w, t, rt);
+    const int tiles = cdiv_i(mmax, 64), nrank = np * tiles;
+    hipLaunchKernelGGL(dc_post1_k, dim3(nrank + waves), dim3(256), 0, s, w, t, tiles, nrank);
+    const int rt = cdiv_i(mmax, 64), ct = cdiv_i(mmax, 32), ngat = np * rt * ct;
+    hipLaunchKernelGGL(dc_post2_k, dim3(waves + ngat + np * rt), dim3(256), 0, s, w, t, waves, ngat, rt, ct);
     const int tm_n = cdiv_i(mcmax, f64t::wide::BM), tn_n = cdiv_i(mmax, f64t::wide::BNT);
     hipLaunchKernelGGL(dc_gemm_k, dim3(np * 2 * tm_n * tn_n), dim3(256), 0, s, w, t, tm_n, tn_n);
   }
