@@ -278,7 +278,7 @@ Bufs carve(const Plan& pl, char* base) {
   b.flag = a.take<int>(4);
   if (is_df(pl.ints)) {
     b.D = a.take<double>((long long)pl.naux * pl.nact);
-    b.dbuf = a.take<double>((long long)F64_KSPLIT_MAX * pl.pc * pl.nact);
+    b.dbuf = a.take<double>((long long)pl.pc * pl.nact);
     b.Kpart = a.take<double>((long long)pl.ns2 * n2);
     if (pl.f32) {
       b.Ct32 = a.take<float>((long long)pl.nact * pl.ldk);
@@ -427,6 +427,7 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
   const bool want_y = r.need_y || ((pl.split || pl.f32) && r.need_e) || r.Fq;
   const bool want_e = r.need_e;
   const bool have_n = (n != nullptr);
+  const OccLayout occ{n, pl.npairs, pl.ncwo, pl.nsingle};
 
   if (have_n) DEV_CHECK(ctx, coeffs(s, nact, pl.npairs, pl.ncwo, pl.nsingle, pl.functional, n, b.alpha, b.beta, b.beta32));
   if (H) {
@@ -493,7 +494,7 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
         DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_B, df_f32_gemm2(s, nbf, nact, np, ns2, b.Ct32, pl.ldk, b.XT32, pl.ldx,
                                                               b.beta32, b.Kpart, Dc, b.W32, pl.ldw)));
         if (want_y) {
-          DEV_CHECK(ctx, add_diag_f32(s, nact, np, Dc, b.alpha, b.dbuf, b.W32, pl.ldw));
+          DEV_CHECK(ctx, add_diag_f32(s, nact, np, Dc, occ, b.dbuf, b.W32, pl.ldw));
           DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_Y, df_f32_gemm3(s, nbf, nact, np, ns3, b.XT32, pl.ldx, b.W32, pl.ldw,
                                                                 b.Ypart32)));
           DEV_CHECK(ctx, reduce_y_f32(s, ny, ns3, b.Ypart32, b.Y2e));
@@ -516,7 +517,7 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
         DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_X, df_f64_gemm1(s, nbf, nact, np, b.Ct, pl.ldk, Bc, b.XT, pl.ldx)));
         DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_B, df_f64_gemm2(s, nbf, nact, np, ns2, b.Ct, pl.ldk, b.XT, pl.ldx, b.beta, b.Kpart, Dc, b.W, pl.ldw)));
         if (want_y) {
-          DEV_CHECK(ctx, add_diag_f64(s, nact, np, Dc, b.alpha, b.dbuf, b.W, pl.ldw));
+          DEV_CHECK(ctx, add_diag_f64(s, nact, np, Dc, occ, b.dbuf, b.W, pl.ldw));
           DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_Y, df_f64_gemm3(s, nbf, nact, np, ns3, b.XT, pl.ldx, b.W, pl.ldw, b.Ypart64)));
           DEV_CHECK(ctx, reduce_y_f64(s, ny, ns3, b.Ypart64, b.Y2e));
         }
@@ -587,7 +588,7 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
             DEV_CHECK(ctx, hipStreamWaitEvent(sa, ev_b, 0));
             join.forked = true;
           }
-          DEV_CHECK(ctx, add_diag_bf16(sa, nact, np, Dc, b.alpha, b.beta32, b.dbuf, b.wh, b.wl, pl.ldw,
+          DEV_CHECK(ctx, add_diag_bf16(sa, nact, np, Dc, occ, b.beta32, b.dbuf, b.wh, b.wl, pl.ldw,
                                        (long long)pl.nact32 * pl.ldw, b.bnd, c));
           if (two) DEV_CHECK(ctx, hipEventRecord(ev_d, sa));
         }

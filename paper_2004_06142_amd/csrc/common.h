@@ -538,8 +538,13 @@ hipError_t coeffs(hipStream_t s, int nact, int npairs, int ncwo, int nsingle, in
                   double* alpha, double* beta, float* beta32);
 hipError_t transpose_ca(hipStream_t s, int nbf, int nact, const double* C, double* Ct, int ldk);
 hipError_t transpose_ca_f32(hipStream_t s, int nbf, int nact, const double* C, float* Ct, int ldk);
+// The occupations and the subspace layout (the structure of the Coulomb coefficients alpha).
+struct OccLayout {
+  const double* n;
+  int npairs, ncwo, nsingle;
+};
 // float32 W: d = Dchunk alpha as in add_diag_f64, then W_P[p][p] += d[P][p].
-hipError_t add_diag_f32(hipStream_t s, int nact, int np, const double* Dchunk, const double* alpha, double* dbuf,
+hipError_t add_diag_f32(hipStream_t s, int nact, int np, const double* Dchunk, const OccLayout& oc, double* dbuf,
                         float* W, int ldw);
 // C_A^T as bf16 (terms 1) or, in the split mode, the compact bf16 pair (hi, lo) plus the fp16 pair
 // (h16, l16) of the same value times sC (bnd: call-level words already formed).
@@ -563,13 +568,13 @@ constexpr int F64_KSPLIT_MAX = 8;
 int gemm_f64_ksplit(int M, int N, int K);
 hipError_t gemm_f64_splitk(hipStream_t s, int M, int N, int K, int ks, const double* A, long long sam, long long sak,
                            const double* B, long long sbk, long long sbn, double* Cpart);
-// d = Dchunk alpha (float64 matrix cores, split over k into the F64_KSPLIT_MAX * np * nact doubles of
-// dbuf), then W_P[p][p] += d[P][p].  The split form rebuilds the diagonal from Dchunk (the b
-// contraction's float accumulators b^P_pp) as float(b^P_pp * beta32_pp) + d[P][p] and only writes it,
-// so W's scattered diagonal is never read back.
-hipError_t add_diag_f64(hipStream_t s, int nact, int np, const double* Dchunk, const double* alpha,
+// d = Dchunk alpha (np x nact into dbuf), formed from the structure of alpha (2 n_p n_q between
+// subspaces, 0 within one) in O(np nact), then W_P[p][p] += d[P][p].  The split form rebuilds the
+// diagonal from Dchunk (the b contraction's float accumulators b^P_pp) as float(b^P_pp * beta32_pp) +
+// d[P][p] and only writes it, so W's scattered diagonal is never read back.
+hipError_t add_diag_f64(hipStream_t s, int nact, int np, const double* Dchunk, const OccLayout& oc,
                         double* dbuf, double* W, int ldw);
-hipError_t add_diag_bf16(hipStream_t s, int nact, int np, const double* Dchunk, const double* alpha,
+hipError_t add_diag_bf16(hipStream_t s, int nact, int np, const double* Dchunk, const OccLayout& oc,
                          const float* beta32, double* dbuf, u16* W_hi, u16* W_lo, int ldw, long long pstride,
                          const uint32_t* bnd, int chunk);
 hipError_t reduce_k(hipStream_t s, int nact, int nsplit, const double* Kpart, double* K);

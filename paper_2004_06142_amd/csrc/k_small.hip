@@ -254,6 +254,41 @@ __device__ __forceinline__ double sum_slabs(const double* __restrict__ d, int ks
   return v;
 }
 
+// d[P][q] = sum_p D[P][p] alpha_pq.  The Coulomb coefficients are alpha_pq = 2 n_p n_q between
+// different subspaces and 0 within one (Eqs. Eg, Efg), so d = 2 n_q (s_P - S_P,g(q)) with
+// s_P = sum_p n_p D[P][p] and S_P,g the same sum over q's own subspace (a strong orbital and its weak
+// ones, or one singly occupied orbital): O(nact) per row instead of a product with alpha.  One
+// workgroup per row P; the row sum is reduced in a fixed order.
+__global__ void d_alpha_k(int nact, int npairs, int ncwo, int nsingle, const double* __restrict__ n,
+                          const double* __restrict__ Dc, double* __restrict__ d) {
+  const int P = blockIdx.x, tid = threadIdx.x;
+  const double* Dr = Dc + (long long)P * nact;
+  __shared__ double red[NT / 64];
+  double v = 0.0;
+  for (int p = tid; p < nact; p += NT) v += n[p] * Dr[p];
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  double sP = 0.0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) sP += red[w];
+  for (int q = tid; q < nact; q += NT) {
+    const int g = pair_of(q, npairs, ncwo, nsingle);
+    double Sg;
+    if (g < npairs) {
+      Sg = n[g] * Dr[g];
+      for (int k = 0; k < ncwo; ++k) {
+        const int w = weak_index(g, k, npairs, ncwo, nsingle);
+        Sg += n[w] * Dr[w];
+      }
+    } else {
+      Sg = n[q] * Dr[q];
+    }
+    d[(long long)P * nact + q] = 2.0 * n[q] * (sP - Sg);
+  }
+}
+
 __global__ void add_diag_f64_k(int nact, int np, int ks, const double* __restrict__ d, double* __restrict__ W,
                                int ldw) {
   const long long slab = (long long)np * nact;
@@ -827,13 +862,11 @@ hipError_t transpose_ca(hipStream_t s, int nbf, int nact, const double* C, doubl
 hipError_t transpose_ca_f32(hipStream_t s, int nbf, int nact, const double* C, float* Ct, int ldk) {
   LAUNCH(transpose_ca_f32_k, grid1((long long)nbf * nact), dim3(NT), nbf, nact, C, Ct, ldk);
 }
-hipError_t add_diag_f32(hipStream_t s, int nact, int np, const double* Dc, const double* alpha, double* dbuf, float* W,
+hipError_t add_diag_f32(hipStream_t s, int nact, int np, const double* Dc, const OccLayout& oc, double* dbuf, float* W,
                         int ldw) {
   if (np <= 0) return hipSuccess;
-  const int ks = gemm_f64_ksplit(np, nact, nact);
-  hipError_t e = gemm_f64_splitk(s, np, nact, nact, ks, Dc, nact, 1, alpha, nact, 1, dbuf);
-  if (e != hipSuccess) return e;
-  LAUNCH(add_diag_f32_k, grid1((long long)np * nact), dim3(NT), nact, np, ks, dbuf, W, ldw);
+  hipLaunchKernelGGL(d_alpha_k, dim3(np), dim3(NT), 0, s, nact, oc.npairs, oc.ncwo, oc.nsingle, oc.n, Dc, dbuf);
+  LAUNCH(add_diag_f32_k, grid1((long long)np * nact), dim3(NT), nact, np, 1, dbuf, W, ldw);
 }
 hipError_t split_ca(hipStream_t s, int nbf, int nact, int terms, const double* C, u16* hi, u16* lo, u16* h16,
                     u16* l16, int ldk, const uint32_t* bnd) {
@@ -863,21 +896,17 @@ hipError_t b_bounds(hipStream_t s, const void* B, int is_f64, long long nrows, i
 hipError_t hpp_from_hc(hipStream_t s, int nbf, int nact, const double* C, const double* HC, double* Hpp) {
   LAUNCH(hpp_k, dim3(nact), dim3(64), nbf, nact, C, HC, Hpp);
 }
-hipError_t add_diag_f64(hipStream_t s, int nact, int np, const double* Dc, const double* alpha, double* dbuf,
+hipError_t add_diag_f64(hipStream_t s, int nact, int np, const double* Dc, const OccLayout& oc, double* dbuf,
                         double* W, int ldw) {
   if (np <= 0) return hipSuccess;
-  const int ks = gemm_f64_ksplit(np, nact, nact);
-  hipError_t e = gemm_f64_splitk(s, np, nact, nact, ks, Dc, nact, 1, alpha, nact, 1, dbuf);
-  if (e != hipSuccess) return e;
-  LAUNCH(add_diag_f64_k, grid1((long long)np * nact), dim3(NT), nact, np, ks, dbuf, W, ldw);
+  hipLaunchKernelGGL(d_alpha_k, dim3(np), dim3(NT), 0, s, nact, oc.npairs, oc.ncwo, oc.nsingle, oc.n, Dc, dbuf);
+  LAUNCH(add_diag_f64_k, grid1((long long)np * nact), dim3(NT), nact, np, 1, dbuf, W, ldw);
 }
-hipError_t add_diag_bf16(hipStream_t s, int nact, int np, const double* Dc, const double* alpha, const float* beta32,
+hipError_t add_diag_bf16(hipStream_t s, int nact, int np, const double* Dc, const OccLayout& oc, const float* beta32,
                          double* dbuf, u16* Wh, u16* Wl, int ldw, long long pstride, const uint32_t* bnd, int chunk) {
   if (np <= 0) return hipSuccess;
-  const int ks = gemm_f64_ksplit(np, nact, nact);
-  hipError_t e = gemm_f64_splitk(s, np, nact, nact, ks, Dc, nact, 1, alpha, nact, 1, dbuf);
-  if (e != hipSuccess) return e;
-  LAUNCH(add_diag_bf16_k, grid1((long long)np * nact), dim3(NT), nact, np, ks, dbuf, Dc, beta32, Wh, Wl, ldw, pstride,
+  hipLaunchKernelGGL(d_alpha_k, dim3(np), dim3(NT), 0, s, nact, oc.npairs, oc.ncwo, oc.nsingle, oc.n, Dc, dbuf);
+  LAUNCH(add_diag_bf16_k, grid1((long long)np * nact), dim3(NT), nact, np, 1, dbuf, Dc, beta32, Wh, Wl, ldw, pstride,
          bnd, chunk);
 }
 hipError_t nofmp2_terms(hipStream_t s, int nact, int npairs, int ncwo, int nsingle, const double* n,
