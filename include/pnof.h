@@ -212,12 +212,12 @@ pnof_status pnof_lagrangian_noalloc(pnof_ctx ctx, const pnof_problem* prob, cons
  * signed so that its largest-magnitude entry (lowest index on ties) is positive;
  * C_new = C U.  lambda, C, C_new: nbf x nbf; eps: nbf; S_out (optional): the matrix diagonalised.
  * C_new must not alias C or lambda.  The Householder reduction to tridiagonal form runs on the
- * library's kernels (one launch per column); rocSOLVER solves the tridiagonal problem (dstedc)
- * while a second stream of the context (default priority, forked and joined with events) forms
- * the product of the reflectors on the library's kernels; the eigenvectors are then that product
- * times dstedc's.  nbf < 3 or nbf > 2048 use rocSOLVER's dsyevd.  Scratch: about 4 nbf^2 doubles
- * from the context's workspace (grown by the context if the lent one is smaller).
- * PNOF_E_EIG if the tridiagonal solver does not converge. */
+ * library's kernels (one launch per column); the library's divide-and-conquer solver solves the
+ * tridiagonal problem while a second stream of the context (default priority, forked and joined
+ * with events) forms the product of the reflectors in blocks of 128; the eigenvectors are then that
+ * product times the tridiagonal solver's.  nbf < 3 or nbf > 2048 use rocSOLVER's dsyevd.  Scratch:
+ * about 9 nbf^2 doubles from the context's workspace (grown by the context if the lent one is
+ * smaller).  PNOF_E_EIG if a secular equation of the tridiagonal solver does not converge. */
 pnof_status pnof_orbital_step(pnof_ctx ctx, int32_t nbf, const double* lambda, const double* C,
                               const double* diag_prev, double zeta, double* C_new, double* eps,
                               double* S_out);
