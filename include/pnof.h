@@ -138,6 +138,16 @@ pnof_status pnof_set_tuning(pnof_ctx ctx, const pnof_tuning* tuning);   /* NULL:
 pnof_status pnof_get_plan(pnof_ctx ctx, const pnof_problem* prob, pnof_tuning* out);
 /* Shorthand for setting only pnof_tuning.pchunk. */
 pnof_status pnof_set_pchunk(pnof_ctx ctx, int32_t pchunk);
+/* Bind the integrals of repeated calls (Section 3.4: they stay fixed through an orbital
+ * optimisation).  In the bf16 split mode every call otherwise reads all of B once more before its
+ * contractions, for the row bounds of each chunk of P rows that fix the fp16 pairs' power-of-two
+ * scales; pnof_bind_integrals makes that pass once, for `prob` under the current launch plan, and
+ * keeps the bounds in the context.  A later call whose problem has the same nbf, naux and integral
+ * kind, whose plan has the same pchunk and whose `ints` is the same device pointer reuses them; any
+ * other call computes its own as before.  The caller must not change the bound integrals: after a
+ * change, bind again (or unbind).  prob == NULL or ints == NULL unbinds.  Other precisions: nothing
+ * to keep (PNOF_OK).  Allocates a few bytes per chunk once; later calls allocate nothing. */
+pnof_status pnof_bind_integrals(pnof_ctx ctx, const pnof_problem* prob, const void* ints);
 
 /* Measurement: between pnof_profile_begin and pnof_profile_end every launch of the three-index
  * contraction kernels (and of the eigensolver) is bracketed by HIP events recorded on the context

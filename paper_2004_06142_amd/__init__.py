@@ -37,7 +37,8 @@ EXPORTS = ["pnof_abi_version", "pnof_last_error", "pnof_check_problem", "pnof_cr
            "pnof_profile_begin", "pnof_profile_end", "pnof_set_tuning", "pnof_get_plan", "pnof_optimize_on",
            "pnof_optimize", "pnof_nofmp2_terms", "pnof_batch_plan",
            "pnof_batch_bind", "pnof_batch_run", "pnof_batch_info", "pnof_batch_destroy", "pnof_batch_set_tiles",
-           "pnof_batch_get_tiles", "pnof_batch_times", "pnof_batch_set_stall", "pnof_batch_set_dies"]
+           "pnof_batch_get_tiles", "pnof_batch_times", "pnof_batch_set_stall", "pnof_batch_set_dies",
+           "pnof_bind_integrals"]
 STAGES = ("X", "b", "Y", "eig")
 
 
@@ -113,6 +114,7 @@ def lib():
             "pnof_workspace_size": ([P, PP, ctypes.POINTER(ctypes.c_size_t)], S),
             "pnof_set_workspace": ([P, P, ctypes.c_size_t], S),
             "pnof_set_pchunk": ([P, I], S),
+            "pnof_bind_integrals": ([P, PP, P], S),
             "pnof_on_map": ([P, I, I, I, I, P, P, P], S),
             "pnof_on_map_vjp": ([P, I, I, I, I, P, P, P], S),
             "pnof_jk": ([P, PP, P, P, P, P, P, P, P, I], S),
@@ -242,6 +244,15 @@ class Context:
 
     def set_pchunk(self, pc: int):
         _raise(self, lib().pnof_set_pchunk(self.handle, pc))
+
+    def bind_integrals(self, prob: Optional[Problem] = None, ints: Optional[torch.Tensor] = None):
+        """Keep the split mode's row bounds of `ints` for later calls on the same integrals
+        (pnof_bind_integrals); no arguments unbind.  The bound tensor must not change while bound."""
+        if prob is None or ints is None:
+            _raise(self, lib().pnof_bind_integrals(self.handle, None, None))
+            return
+        _ints_check(prob, ints, self.device)
+        _raise(self, lib().pnof_bind_integrals(self.handle, ctypes.byref(prob), _ptr(ints)))
 
     def reserve(self, prob: Problem):
         """Allocate the workspace for `prob` as a torch tensor and lend it to the library."""

@@ -53,6 +53,14 @@ struct pnof_ctx_s {
   struct Slot { void* p; size_t bytes; };
   std::vector<Slot> slots;
   size_t slot_top = 0;
+  // integrals bound by pnof_bind_integrals: their per-chunk row bounds (split mode) and the key they
+  // were computed under
+  struct Bound {
+    const void* ints = nullptr;
+    int nbf = 0, naux = 0, kind = 0, pc = 0;
+    uint32_t* words = nullptr;   // 2 per chunk (device)
+    size_t nwords = 0, cap = 0;
+  } bound;
 };
 
 namespace {
@@ -548,9 +556,15 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
       auto chunk_rows = [&](int c) { return (int)std::min<long long>(pl.pc, pl.naux - (long long)c * pl.pc); };
       // row bounds of every chunk of B in one pass before the first X (beside the contractions it
       // would take their compute units: measured slower)
-      if (split)
-        DEV_CHECK(ctx, b_bounds(s, ints, pl.ints == PNOF_INTS_DF_F64, (long long)pl.naux * nbf, nbf, nbf,
-                                (long long)pl.pc * nbf, b.bnd + SCL_CALL));
+      if (split) {
+        const auto& bd = ctx->bound;
+        if (bd.ints && bd.ints == ints && bd.nbf == nbf && bd.naux == pl.naux && bd.kind == pl.ints && bd.pc == pl.pc)
+          DEV_CHECK(ctx, hipMemcpyAsync(b.bnd + SCL_CALL, bd.words, bd.nwords * sizeof(uint32_t),
+                                        hipMemcpyDeviceToDevice, s));   // bound integrals: kept bounds
+        else
+          DEV_CHECK(ctx, b_bounds(s, ints, pl.ints == PNOF_INTS_DF_F64, (long long)pl.naux * nbf, nbf, nbf,
+                                  (long long)pl.pc * nbf, b.bnd + SCL_CALL));
+      }
       auto run_x = [&](int c) -> pnof_status {
         const long long p0 = (long long)c * pl.pc;
         const int np = chunk_rows(c);
@@ -1147,6 +1161,7 @@ void pnof_destroy(pnof_ctx ctx) {
   for (hipEvent_t e : ctx->pipe_ev)
     if (e) hipEventDestroy(e);
   if (ctx->own_ws) hipFree(ctx->own_ws);
+  if (ctx->bound.words) hipFree(ctx->bound.words);
   if (ctx->host_info) hipHostFree(ctx->host_info);
   if (ctx->blas) rocblas_destroy_handle(ctx->blas);
   delete ctx;
@@ -1221,6 +1236,38 @@ pnof_status pnof_set_tuning(pnof_ctx ctx, const pnof_tuning* t) {
       t->y_variant < 0 || t->y_variant > 3)
     return fail(ctx, PNOF_E_ARG, "tuning values out of range");
   ctx->tune = *t;
+  return PNOF_OK;
+}
+
+pnof_status pnof_bind_integrals(pnof_ctx ctx, const pnof_problem* prob, const void* ints) {
+  if (!ctx) return fail(nullptr, PNOF_E_ARG, "context is NULL");
+  auto& bd = ctx->bound;
+  bd.ints = nullptr;
+  if (!prob || !ints) return PNOF_OK;
+  pnof_status st = check_problem(ctx, prob);
+  if (st != PNOF_OK) return st;
+  if ((st = check_ptrs(ctx, {ints}, "pnof_bind_integrals")) != PNOF_OK) return st;
+  if ((st = check_ctx(ctx)) != PNOF_OK) return st;
+  const Plan pl = make_plan(prob, ctx->tune);
+  if (!is_df(pl.ints) || pl.terms <= 1) return PNOF_OK;
+  const size_t nw = 2 * (size_t)cdiv(pl.naux, pl.pc);
+  if (nw > bd.cap) {
+    if (bd.words) DEV_CHECK(ctx, hipFree(bd.words));
+    bd.words = nullptr;
+    bd.cap = 0;
+    DEV_CHECK(ctx, hipMalloc(&bd.words, nw * sizeof(uint32_t)));
+    bd.cap = nw;
+  }
+  hipStream_t s = ctx->stream;
+  DEV_CHECK(ctx, hipMemsetAsync(bd.words, 0, nw * sizeof(uint32_t), s));   // the bounds are raised from zero
+  DEV_CHECK(ctx, b_bounds(s, ints, pl.ints == PNOF_INTS_DF_F64, (long long)pl.naux * pl.nbf, pl.nbf, pl.nbf,
+                          (long long)pl.pc * pl.nbf, bd.words));
+  bd.ints = ints;
+  bd.nbf = pl.nbf;
+  bd.naux = pl.naux;
+  bd.kind = pl.ints;
+  bd.pc = pl.pc;
+  bd.nwords = nw;
   return PNOF_OK;
 }
 

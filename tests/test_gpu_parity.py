@@ -467,3 +467,45 @@ def test_error_paths(ctx):
     assert e.value.status == 1
     # the context still works after errors
     assert np.isfinite(ctx.energy(P.problem(30, 20, 2, 2), t(inst.C), t(n), t(inst.H), t(inst.B)).item())
+
+
+# ------------------------------------------------------------------------------ bound integrals
+@pytest.mark.parametrize("bdt", ["bf16", "f64"])
+def test_bound_integrals(ctx, bdt):
+    """pnof_bind_integrals keeps the split mode's row bounds of B: a call on the bound integrals
+    matches an unbound call bit for bit (the kept bounds are the ones the call computes); after
+    rebinding to other integrals the calls follow them, calls on integrals other than the bound ones
+    compute their own bounds, and another pchunk than at binding does too."""
+    inst = _case("bound", 130, 300, 13, 4, bdt)
+    kind = P.INTS_DF_F64 if bdt == "f64" else P.INTS_DF_BF16
+    n, _ = _ref(inst, pnof.PNOF7)
+    prob = P.problem(130, 300, 13, 4, P.PNOF7, P.BF16_SPLIT, kind)
+    C, H, nn = t(inst.C), t(inst.H), t(n)
+    B = _ints(inst, kind)
+    B2 = B * 0.5    # exact in either format
+
+    def run(ints):
+        o = ctx.lagrangian(prob, C, nn, H, ints, jk=True)
+        return [h(o[k]) for k in ("E", "lam", "J", "K", "dEdC")]
+
+    def same(a, b):
+        return all(np.array_equal(x, y) for x, y in zip(a, b))
+
+    try:
+        ctx.bind_integrals()
+        free1, free2 = run(B), run(B2)
+        ctx.bind_integrals(prob, B)
+        assert same(run(B), free1)
+        assert same(run(B2), free2)          # not the bound integrals: own bounds
+        ctx.bind_integrals(prob, B2)
+        assert same(run(B2), free2)
+        assert not same(free1, free2)
+        ctx.set_pchunk(100)                  # another chunking than at binding: own bounds
+        bound_other = run(B2)
+        ctx.bind_integrals()
+        assert same(bound_other, run(B2))
+        ctx.bind_integrals(prob, B2)         # bound at this chunking
+        assert same(run(B2), bound_other)
+    finally:
+        ctx.bind_integrals()
+        ctx.set_tuning(None)
