@@ -547,6 +547,11 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
       SplitPtr C16{split ? b.ch16 : b.cth, split ? b.cl16 : nullptr};   // b (and X from float64 B)
       u16* const xth_[2] = {b.xth, b.xth2};
       u16* const xtl_[2] = {b.xtl, b.xtl2};
+      // W stored once per 128 x 128 block pair (b writes the lower triangle below its diagonal
+      // tiles, Y reads each block in the orientation that holds it): needs Y's direct-load path
+      auto a16 = [](const void* p) { return p == nullptr || (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+      const bool wsym = pl.ldx % 32 == 0 && pl.ldw % 32 == 0 && a16(b.xth) && a16(b.xth2) && a16(b.xtl) &&
+                        a16(b.xtl2) && a16(b.wh) && a16(b.wl);
       // one_stream: the second stream's work runs in order on the context's stream
       const bool two = !r.one_stream;
       if (two) RB_CHECK(ensure_aux(ctx));
@@ -595,7 +600,8 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
         double* Dc = b.D + (long long)p0 * nact;
         SplitPtr XT{xth_[c & 1], split ? xtl_[c & 1] : nullptr};
         DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_B, df_bf16_gemm2(s, nbf, nact, np, ns2, pl.terms, C16, pl.ldk, XT, pl.ldx,
-                                                               b.beta32, b.Kpart, Dc, b.wh, b.wl, pl.ldw, wd, b.bnd, c)));
+                                                               b.beta32, b.Kpart, Dc, b.wh, b.wl, pl.ldw, wd, b.bnd, c,
+                                                               wsym)));
         if (want_y) {
           if (two) {
             DEV_CHECK(ctx, hipEventRecord(ev_b, s));
@@ -614,7 +620,7 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
           }
           SplitPtr W{b.wh, b.wl};
           DEV_CHECK(ctx, TIMED(ctx, PNOF_STAGE_Y, df_bf16_gemm3(s, nbf, nact, np, ns3, pl.terms, XT, pl.ldx, W, pl.ldw,
-                                                                 b.Ypart32, pl.yv, wd, b.bnd, c)));
+                                                                 b.Ypart32, pl.yv, wd, b.bnd, c, wsym)));
           if (two) {
             DEV_CHECK(ctx, hipEventRecord(ev_y, s));
             DEV_CHECK(ctx, hipStreamWaitEvent(sa, ev_y, 0));

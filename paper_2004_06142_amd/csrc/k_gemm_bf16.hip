@@ -376,10 +376,15 @@ __device__ __forceinline__ RT& ring_of(void* ext) {
 // i + 1 read while the products of block i issue, in an order pinned by scheduling groups: a wave
 // then waits only for its B fragments and first A block after the barrier, instead of for most of
 // the k-tile's fragment reads, and the LDS stays busy through the tile.
+// BSYM: the B operand is W as gemm2 writes it with lower_only, read per 128-wide part of the tile:
+// block (q-block, k-block) of 128 x 128 is read row-wise (W[q][k]) when k-block <= q-block and
+// column-wise (W[k][q], its transpose) otherwise; each part of the stage is laid out for its view.
 template <int BM, int BN, bool ALO, bool BLO, int S, bool ACOL, bool BCOL, bool RESET, bool F16, int WGM = 2,
-          int WGN = 2, bool ILV = false, typename FA, typename FB, typename EPI>
+          int WGN = 2, bool ILV = false, bool BSYM = false, typename FA, typename FB, typename EPI>
 __device__ __forceinline__ void mainloop_dl(Ring<BM, BN, ALO, BLO, S>& sm, int nseg, int kb, int ke, int m0, int n0,
                                             FA A, FB B, f32x4 (&acc)[BM / (16 * WGM)][BN / (16 * WGN)], EPI epi) {
+  constexpr int SH = 128;         // BSYM: width of one part of the B tile (the b tile of W)
+  static_assert(!BSYM || (BN % SH == 0 && !BCOL && (BN / WGN) <= SH), "BSYM: parts of 128, one per wave");
   constexpr int NW = WGM * WGN;   // waves in a WGM x WGN grid, each owning (BM / WGM) x (BN / WGN)
   constexpr int MI = BM / (16 * WGM), NI = BN / (16 * WGN);
   constexpr int L = (ALO ? 2 : 1) * (BM / (16 * NW)) + (BLO ? 2 : 1) * (BN / (16 * NW));   // loads per wave per tile
@@ -394,8 +399,17 @@ __device__ __forceinline__ void mainloop_dl(Ring<BM, BN, ALO, BLO, S>& sm, int n
     const DOpnd a = A(lseg), b = B(lseg);
     dl_issue<BM, NW>(sm.a[stage][0], a.hi, a.bytes, a.ld, ACOL, m0, lk);
     if (ALO) dl_issue<BM, NW>(sm.a[stage][ALO ? 1 : 0], a.lo, a.bytes, a.ld, ACOL, m0, lk);
-    dl_issue<BN, NW>(sm.b[stage][0], b.hi, b.bytes, b.ld, BCOL, n0, lk);
-    if (BLO) dl_issue<BN, NW>(sm.b[stage][BLO ? 1 : 0], b.lo, b.bytes, b.ld, BCOL, n0, lk);
+    if constexpr (BSYM) {
+#pragma unroll
+      for (int h = 0; h < BN / SH; ++h) {
+        const bool col = lk / SH > (n0 + SH * h) / SH;
+        dl_issue<SH, NW>(sm.b[stage][0] + h * SH * BK, b.hi, b.bytes, b.ld, col, n0 + SH * h, lk);
+        if (BLO) dl_issue<SH, NW>(sm.b[stage][BLO ? 1 : 0] + h * SH * BK, b.lo, b.bytes, b.ld, col, n0 + SH * h, lk);
+      }
+    } else {
+      dl_issue<BN, NW>(sm.b[stage][0], b.hi, b.bytes, b.ld, BCOL, n0, lk);
+      if (BLO) dl_issue<BN, NW>(sm.b[stage][BLO ? 1 : 0], b.lo, b.bytes, b.ld, BCOL, n0, lk);
+    }
     lk += BK;
     if (lk >= ke) { lk = kb; ++lseg; }
   };
@@ -406,56 +420,61 @@ __device__ __forceinline__ void mainloop_dl(Ring<BM, BN, ALO, BLO, S>& sm, int n
   // segments outside, k-tiles inside: the epilogue sits outside the inner loop, so the register
   // allocator keeps the accumulators in place through the k-loop (an epilogue inside the k-loop made
   // it shuttle them between AGPRs and VGPRs on every k-tile)
+  // B fragment at wave column c (0 .. BN / WGN) of the stage; bv: the part is read column-wise
+  // (BSYM; the wave's columns lie in one part)
+  auto bfrag = [&](auto bv, const u16* base, int c) -> bf16x8 {
+    if constexpr (BSYM) {
+      return dl_frag<SH, decltype(bv)::value>(base + (wn / SH) * SH * BK, wn % SH + c);
+    } else {
+      return dl_frag<BN, BCOL>(base, wn + c);
+    }
+  };
   int stage = 0, it = 0;
-  for (int seg = 0; seg < nseg; ++seg) {
-    for (int kt = 0; kt < KT; ++kt, ++it) {
-      if (it + S - 2 < total) __builtin_amdgcn_s_waitcnt(waitcnt_vm(L * (S - 2)));
-      else __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
-      __builtin_amdgcn_s_barrier();
-      if (it + S - 1 < total) issue((stage + S - 1) % S);
-      if constexpr (ILV) {
-        // reads of one A block: 1 (row layout) or 2 (transposing) instructions per hi / lo part
-        constexpr int RA = (ACOL ? 2 : 1) * (ALO ? 2 : 1);
-        constexpr int RB = (BCOL ? 2 : 1) * (BLO ? 2 : 1) * NI;
-        constexpr int PR = NI * (1 + (BLO ? 1 : 0) + (ALO ? 1 : 0));   // products per A block
-        bf16x8 bh[NI], bl[NI], ah[2], al[2];
+  // one k-tile's products from stage `stage`; bv as for bfrag (a compile-time view, so that each
+  // form is straight-line code with its own read counts in the scheduling groups)
+  auto ktile = [&](auto bv) {
+    constexpr bool BC = BSYM ? decltype(bv)::value : BCOL;   // B read with transposing reads
+    if constexpr (ILV) {
+      // reads of one A block: 1 (row layout) or 2 (transposing) instructions per hi / lo part
+      constexpr int RA = (ACOL ? 2 : 1) * (ALO ? 2 : 1);
+      constexpr int RB = (BC ? 2 : 1) * (BLO ? 2 : 1) * NI;
+      constexpr int PR = NI * (1 + (BLO ? 1 : 0) + (ALO ? 1 : 0));   // products per A block
+      bf16x8 bh[NI], bl[NI], ah[2], al[2];
 #pragma unroll
-        for (int j = 0; j < NI; ++j) {
-          bh[j] = dl_frag<BN, BCOL>(sm.b[stage][0], wn + 16 * j);
-          if (BLO) bl[j] = dl_frag<BN, BCOL>(sm.b[stage][BLO ? 1 : 0], wn + 16 * j);
-        }
-        ah[0] = dl_frag<BM, ACOL>(sm.a[stage][0], wm);
-        if (ALO) al[0] = dl_frag<BM, ACOL>(sm.a[stage][ALO ? 1 : 0], wm);
-        __builtin_amdgcn_sched_group_barrier(0x100, RB + RA, 0);
-#pragma unroll
-        for (int i = 0; i < MI; ++i) {
-          const int c = i & 1, n = c ^ 1;
-          if (i + 1 < MI) {
-            ah[n] = dl_frag<BM, ACOL>(sm.a[stage][0], wm + 16 * (i + 1));
-            if (ALO) al[n] = dl_frag<BM, ACOL>(sm.a[stage][ALO ? 1 : 0], wm + 16 * (i + 1));
-            __builtin_amdgcn_sched_group_barrier(0x100, RA, 0);
-          }
-          // products in passes over j, so no two consecutive products share an accumulator
-#pragma unroll
-          for (int j = 0; j < NI; ++j) acc[i][j] = mma<F16>(ah[c], bh[j], acc[i][j]);
-          if (BLO) {
-#pragma unroll
-            for (int j = 0; j < NI; ++j) acc[i][j] = mma<F16>(ah[c], bl[j], acc[i][j]);
-          }
-          if (ALO) {
-#pragma unroll
-            for (int j = 0; j < NI; ++j) acc[i][j] = mma<F16>(al[c], bh[j], acc[i][j]);
-          }
-          __builtin_amdgcn_sched_group_barrier(0x008, PR, 0);
-        }
-        stage = (stage + 1 == S) ? 0 : stage + 1;
-        continue;
+      for (int j = 0; j < NI; ++j) {
+        bh[j] = bfrag(bv, sm.b[stage][0], 16 * j);
+        if (BLO) bl[j] = bfrag(bv, sm.b[stage][BLO ? 1 : 0], 16 * j);
       }
+      ah[0] = dl_frag<BM, ACOL>(sm.a[stage][0], wm);
+      if (ALO) al[0] = dl_frag<BM, ACOL>(sm.a[stage][ALO ? 1 : 0], wm);
+      __builtin_amdgcn_sched_group_barrier(0x100, RB + RA, 0);
+#pragma unroll
+      for (int i = 0; i < MI; ++i) {
+        const int c = i & 1, n = c ^ 1;
+        if (i + 1 < MI) {
+          ah[n] = dl_frag<BM, ACOL>(sm.a[stage][0], wm + 16 * (i + 1));
+          if (ALO) al[n] = dl_frag<BM, ACOL>(sm.a[stage][ALO ? 1 : 0], wm + 16 * (i + 1));
+          __builtin_amdgcn_sched_group_barrier(0x100, RA, 0);
+        }
+        // products in passes over j, so no two consecutive products share an accumulator
+#pragma unroll
+        for (int j = 0; j < NI; ++j) acc[i][j] = mma<F16>(ah[c], bh[j], acc[i][j]);
+        if (BLO) {
+#pragma unroll
+          for (int j = 0; j < NI; ++j) acc[i][j] = mma<F16>(ah[c], bl[j], acc[i][j]);
+        }
+        if (ALO) {
+#pragma unroll
+          for (int j = 0; j < NI; ++j) acc[i][j] = mma<F16>(al[c], bh[j], acc[i][j]);
+        }
+        __builtin_amdgcn_sched_group_barrier(0x008, PR, 0);
+      }
+    } else {
       bf16x8 ah[MI], bh[NI];
 #pragma unroll
       for (int i = 0; i < MI; ++i) ah[i] = dl_frag<BM, ACOL>(sm.a[stage][0], wm + 16 * i);
 #pragma unroll
-      for (int j = 0; j < NI; ++j) bh[j] = dl_frag<BN, BCOL>(sm.b[stage][0], wn + 16 * j);
+      for (int j = 0; j < NI; ++j) bh[j] = bfrag(bv, sm.b[stage][0], 16 * j);
 #pragma unroll
       for (int i = 0; i < MI; ++i)
 #pragma unroll
@@ -464,7 +483,7 @@ __device__ __forceinline__ void mainloop_dl(Ring<BM, BN, ALO, BLO, S>& sm, int n
       if (BLO) {
         bf16x8 bl[NI];
 #pragma unroll
-        for (int j = 0; j < NI; ++j) bl[j] = dl_frag<BN, BCOL>(sm.b[stage][BLO ? 1 : 0], wn + 16 * j);
+        for (int j = 0; j < NI; ++j) bl[j] = bfrag(bv, sm.b[stage][BLO ? 1 : 0], 16 * j);
 #pragma unroll
         for (int i = 0; i < MI; ++i)
 #pragma unroll
@@ -479,6 +498,21 @@ __device__ __forceinline__ void mainloop_dl(Ring<BM, BN, ALO, BLO, S>& sm, int n
           for (int j = 0; j < NI; ++j)
             acc[i][j] = mma<F16>(al, bh[j], acc[i][j]);
         }
+      }
+    }
+  };
+  for (int seg = 0; seg < nseg; ++seg) {
+    for (int kt = 0; kt < KT; ++kt, ++it) {
+      if (it + S - 2 < total) __builtin_amdgcn_s_waitcnt(waitcnt_vm(L * (S - 2)));
+      else __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+      __builtin_amdgcn_s_barrier();
+      if (it + S - 1 < total) issue((stage + S - 1) % S);
+      if constexpr (BSYM) {
+        // this wave's part is read column-wise when the k-tile's 128-block lies past the part's
+        if ((kb + kt * BK) / SH > (n0 + wn) / SH) ktile(std::true_type{});
+        else ktile(std::false_type{});
+      } else {
+        ktile(std::false_type{});
       }
       stage = (stage + 1 == S) ? 0 : stage + 1;
     }
@@ -708,7 +742,7 @@ __device__ __forceinline__ void gemm2_body(int w, const G2Args& g, void* ext = n
               if (diag && p == q) g.Dc[(long long)P * nact + p] = (double)(a[i][jn][j] * invB);
             }
           }
-          if (!diag && p0 < nact) {
+          if (!diag && p0 < nact && !g.lower_only) {
             const long long o = (long long)q * ldw + p0;
             if ((ldw & 3) == 0) {
               *reinterpret_cast<uint2*>(Wh + o) = uint2{h01, h23};
@@ -767,7 +801,8 @@ __device__ __forceinline__ void gemm2_body(int w, const G2Args& g, void* ext = n
 // matrix-core products one byte read from LDS feeds: a 64 x 64 wave reads 16 KB per k-tile for 48
 // products, a 128 x 64 wave 24 KB for 96; LDS bandwidth (about 128 bytes per clock per compute unit)
 // is what limits the 64 x 64 form.
-template <int TERMS, int G3M, int G3N, int WGM, int WGN, int MINB, bool VEC, bool EXT = false, int BUDGET = 0>
+template <int TERMS, int G3M, int G3N, int WGM, int WGN, int MINB, bool VEC, bool EXT = false, int BUDGET = 0,
+          bool WSYM = false>
 __device__ __forceinline__ void gemm3_body(int w, const G3Args& g, void* ext = nullptr) {
   constexpr bool LO = TERMS >= 3;
   constexpr int MI = G3M / (16 * WGM), NI = G3N / (16 * WGN);
@@ -794,10 +829,11 @@ __device__ __forceinline__ void gemm3_body(int w, const G3Args& g, void* ext = n
       const long long off = (long long)(pb + seg) * g.ws.nact32 * ldw;
       return DOpnd{g.w_hi + off, LO ? g.w_lo + off : nullptr, ldw, g.ws.w_bytes - 2 * off};
     };
-    mainloop_dl<G3M, G3N, LO, LO, S, true, false, false, LO, WGM, WGN, (WGM * WGN == 8)>(sm, pe - pb, 0, nact, m0, n0,
-                                                                                       A, B, acc, none);
+    mainloop_dl<G3M, G3N, LO, LO, S, true, false, false, LO, WGM, WGN, (WGM * WGN == 8), WSYM>(sm, pe - pb, 0, nact,
+                                                                                             m0, n0, A, B, acc, none);
   } else {
     static_assert(VEC || (WGM == 2 && WGN == 2), "register-staged path: 2 x 2 waves");
+    static_assert(!WSYM, "the symmetric W layout is read on the direct-load path only");
     __shared__ Stage<G3M, G3N, LO, LO> sm;
     auto A = [&](int seg) {
       const long long off = (long long)(pb + seg) * g.ws.nact32 * ldx;
@@ -834,11 +870,11 @@ __global__ __launch_bounds__(128 * g2_wgn(VEC), 1) void gemm2_kernel(G2Args g) {
   if (w < 0) return;
   gemm2_body<TERMS, VEC>(w, g);
 }
-template <int TERMS, int G3M, int G3N, int WGM, int WGN, int MINB, bool VEC>
+template <int TERMS, int G3M, int G3N, int WGM, int WGN, int MINB, bool VEC, bool WSYM = false>
 __global__ __launch_bounds__(64 * WGM * WGN, MINB) void gemm3_kernel(G3Args g) {
   const int w = xcd_item(g3_items(g, G3M, G3N));
   if (w < 0) return;
-  gemm3_body<TERMS, G3M, G3N, WGM, WGN, MINB, VEC>(w, g);
+  gemm3_body<TERMS, G3M, G3N, WGM, WGN, MINB, VEC, false, 0, WSYM>(w, g);
 }
 
 // Grouped forms: one launch over the work items of every instance of a batch.  The tile width along
@@ -1168,10 +1204,10 @@ hipError_t df_bf16_gemm1(hipStream_t s, int nbf, int nact, int np, int terms, Sp
 
 hipError_t df_bf16_gemm2(hipStream_t s, int nbf, int nact, int np, int nsplit, int terms, SplitPtr Ct, int ldk,
                          SplitPtr XT, int ldx, const float* beta32, double* Kpart, double* Dchunk, u16* W_hi,
-                         u16* W_lo, int ldw, const WsDims& d, const uint32_t* bnd, int chunk) {
+                         u16* W_lo, int ldw, const WsDims& d, const uint32_t* bnd, int chunk, bool wsym) {
   if (np <= 0) return hipSuccess;
   const G2Args g{nbf,   nact,  np,     nsplit, Ct.hi, Ct.lo, ldk, XT.hi, XT.lo, ldx, beta32,
-                 Kpart, Dchunk, W_hi, W_lo,   ldw,   d,     bnd, chunk};
+                 Kpart, Dchunk, W_hi, W_lo,   ldw,   d,     bnd, chunk, wsym ? 1 : 0};
   const dim3 grid = xcd_grid(g2_items(g, T2));
   const bool vec = (ldk % 32 == 0) && (ldx % 32 == 0) && al16(Ct.hi) && (!Ct.lo || al16(Ct.lo)) && al16(XT.hi) &&
                    (!XT.lo || al16(XT.lo));
@@ -1185,13 +1221,20 @@ hipError_t df_bf16_gemm2(hipStream_t s, int nbf, int nact, int np, int nsplit, i
   return hipGetLastError();
 }
 
+static bool g3_vec(const G3Args& g) {
+  return (g.ldx % 32 == 0) && (g.ldw % 32 == 0) && al16(g.xt_hi) && (!g.xt_lo || al16(g.xt_lo)) && al16(g.w_hi) &&
+         (!g.w_lo || al16(g.w_lo));
+}
+
 template <int TERMS, int G3M, int G3N, int WGM, int WGN, int MINB>
 static void launch_g3(hipStream_t s, const G3Args& g) {
   const dim3 grid = xcd_grid(g3_items(g, G3M, G3N));
-  const bool vec = (g.ldx % 32 == 0) && (g.ldw % 32 == 0) && al16(g.xt_hi) && (!g.xt_lo || al16(g.xt_lo)) &&
-                   al16(g.w_hi) && (!g.w_lo || al16(g.w_lo));
+  const bool vec = g3_vec(g);
   // operands without aligned rows take the register-staged 128 x 128 form whatever the variant
-  if (vec) hipLaunchKernelGGL((gemm3_kernel<TERMS, G3M, G3N, WGM, WGN, MINB, true>), grid, dim3(64 * WGM * WGN), 0, s, g);
+  if (vec && g.wsym)
+    hipLaunchKernelGGL((gemm3_kernel<TERMS, G3M, G3N, WGM, WGN, MINB, true, true>), grid, dim3(64 * WGM * WGN), 0, s, g);
+  else if (vec)
+    hipLaunchKernelGGL((gemm3_kernel<TERMS, G3M, G3N, WGM, WGN, MINB, true>), grid, dim3(64 * WGM * WGN), 0, s, g);
   else
     hipLaunchKernelGGL((gemm3_kernel<TERMS, 128, 128, 2, 2, 2, false>), xcd_grid(g3_items(g, 128, 128)), dim3(256), 0,
                        s, g);
@@ -1199,9 +1242,10 @@ static void launch_g3(hipStream_t s, const G3Args& g) {
 
 hipError_t df_bf16_gemm3(hipStream_t s, int nbf, int nact, int np, int nsplit, int terms, SplitPtr XT, int ldx,
                          SplitPtr W, int ldw, float* Ypart, int variant, const WsDims& d, const uint32_t* bnd,
-                         int chunk) {
+                         int chunk, bool wsym) {
   if (np <= 0) return hipSuccess;
-  const G3Args g{nbf, nact, np, nsplit, XT.hi, XT.lo, ldx, W.hi, W.lo, ldw, Ypart, d, bnd, chunk};
+  const G3Args g{nbf, nact, np, nsplit, XT.hi, XT.lo, ldx, W.hi, W.lo, ldw, Ypart, d, bnd, chunk, wsym ? 1 : 0};
+  if (wsym && !g3_vec(g)) return hipErrorInvalidValue;   // the symmetric layout needs the direct-load path
   // variant (resolved by the planner): 1 = 128 x 128 (4 waves of 64 x 64, two blocks per CU),
   // 2 = 256 x 128 (4 waves of 128 x 64), 3 = 256 x 256 (8 waves of 128 x 64)
   if (terms == 1) {
