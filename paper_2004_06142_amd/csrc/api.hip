@@ -547,8 +547,9 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
       SplitPtr C16{split ? b.ch16 : b.cth, split ? b.cl16 : nullptr};   // b (and X from float64 B)
       u16* const xth_[2] = {b.xth, b.xth2};
       u16* const xtl_[2] = {b.xtl, b.xtl2};
-      // W stored once per 128 x 128 block pair (b writes the lower triangle below its diagonal
-      // tiles, Y reads each block in the orientation that holds it): needs Y's direct-load path
+      // W stored once per 128 x 128 block pair (b writes only the transposed image of its tiles, the
+      // blocks on and above the diagonal; Y reads each block in the orientation that holds it): needs
+      // Y's direct-load path
       auto a16 = [](const void* p) { return p == nullptr || (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
       const bool wsym = pl.ldx % 32 == 0 && pl.ldw % 32 == 0 && a16(b.xth) && a16(b.xth2) && a16(b.xtl) &&
                         a16(b.xtl2) && a16(b.wh) && a16(b.wl);

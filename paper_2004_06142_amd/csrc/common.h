@@ -374,9 +374,10 @@ struct G2Args {   // b_P = Ct XT_P^T; K partials, D, W
   WsDims ws;
   const uint32_t* bnd;
   int chunk;
-  // W stored once per 128 x 128 block pair: whole diagonal tiles, and below them only the lower
-  // triangle (the upper is the transpose, W_P being symmetric); gemm3 with wsym reads it that way
-  int lower_only = 0;
+  // W stored once per 128 x 128 block pair, W_P being symmetric: each tile (on or below the
+  // diagonal) writes only its transposed image W[q][p], so W holds the blocks on and above the
+  // diagonal; gemm3 with wsym reads it that way
+  int wsym = 0;
 };
 struct G3Args {   // Ypart[s] = sum_{P in s} X_P W_P
   int nbf, nact, np, nsplit;
@@ -390,7 +391,7 @@ struct G3Args {   // Ypart[s] = sum_{P in s} X_P W_P
   WsDims ws;
   const uint32_t* bnd;
   int chunk;
-  int wsym = 0;   // W as gemm2 writes it with lower_only (see G2Args)
+  int wsym = 0;   // W as gemm2 writes it with wsym (see G2Args)
 };
 // Work items of one launch.  The stacked form of X treats the rows (P, mu) of np consecutive B_P
 // as one matrix (B_P rows padded to ldb, bstride == nbf * ldb), so short rows do not waste tiles.
@@ -429,9 +430,9 @@ hipError_t df_bf16_gemm3_grouped(hipStream_t s, int ninst, int total, int terms,
 hipError_t df_bf16_gemm1(hipStream_t s, int nbf, int nact, int np, int terms, SplitPtr Ct, int ldk, SplitPtr Bp,
                          long long bstride, int ldb, long long b_bytes, u16* XT_hi, u16* XT_lo, int ldx, int variant,
                          const WsDims& d, const uint32_t* bnd, int chunk);
-// wsym: W is written below the diagonal 128 x 128 tiles only in its lower triangle (gemm2), and Y
-// reads each 128 x 128 block of W in the orientation that holds it (gemm3); split mode, 128 x 128 b
-// tiles, Y variants on the direct-load path only.
+// wsym: W is written only as the transposed image of b's tiles, i.e. its 128 x 128 blocks on and
+// above the diagonal (gemm2), and Y reads each block of W in the orientation that holds it (gemm3);
+// split mode, 128 x 128 b tiles, Y on the direct-load path only.
 hipError_t df_bf16_gemm2(hipStream_t s, int nbf, int nact, int np, int nsplit, int terms,
                          SplitPtr Ct, int ldk, SplitPtr XT, int ldx, const float* beta32,
                          double* Kpart, double* Dchunk, u16* W_hi, u16* W_lo, int ldw, const WsDims& d,

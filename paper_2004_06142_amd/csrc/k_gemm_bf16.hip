@@ -376,9 +376,10 @@ __device__ __forceinline__ RT& ring_of(void* ext) {
 // i + 1 read while the products of block i issue, in an order pinned by scheduling groups: a wave
 // then waits only for its B fragments and first A block after the barrier, instead of for most of
 // the k-tile's fragment reads, and the LDS stays busy through the tile.
-// BSYM: the B operand is W as gemm2 writes it with lower_only, read per 128-wide part of the tile:
-// block (q-block, k-block) of 128 x 128 is read row-wise (W[q][k]) when k-block <= q-block and
-// column-wise (W[k][q], its transpose) otherwise; each part of the stage is laid out for its view.
+// BSYM: the B operand is W as gemm2 writes it with wsym (the 128 x 128 blocks on and above the
+// diagonal), read per 128-wide part of the tile: block (q-block, k-block) is read row-wise (W[q][k])
+// when k-block >= q-block and column-wise (W[k][q], its transpose) otherwise; each part of the stage
+// is laid out for its view.
 template <int BM, int BN, bool ALO, bool BLO, int S, bool ACOL, bool BCOL, bool RESET, bool F16, int WGM = 2,
           int WGN = 2, bool ILV = false, bool BSYM = false, typename FA, typename FB, typename EPI>
 __device__ __forceinline__ void mainloop_dl(Ring<BM, BN, ALO, BLO, S>& sm, int nseg, int kb, int ke, int m0, int n0,
@@ -402,7 +403,7 @@ __device__ __forceinline__ void mainloop_dl(Ring<BM, BN, ALO, BLO, S>& sm, int n
     if constexpr (BSYM) {
 #pragma unroll
       for (int h = 0; h < BN / SH; ++h) {
-        const bool col = lk / SH > (n0 + SH * h) / SH;
+        const bool col = lk / SH < (n0 + SH * h) / SH;
         dl_issue<SH, NW>(sm.b[stage][0] + h * SH * BK, b.hi, b.bytes, b.ld, col, n0 + SH * h, lk);
         if (BLO) dl_issue<SH, NW>(sm.b[stage][BLO ? 1 : 0] + h * SH * BK, b.lo, b.bytes, b.ld, col, n0 + SH * h, lk);
       }
@@ -508,8 +509,8 @@ __device__ __forceinline__ void mainloop_dl(Ring<BM, BN, ALO, BLO, S>& sm, int n
       __builtin_amdgcn_s_barrier();
       if (it + S - 1 < total) issue((stage + S - 1) % S);
       if constexpr (BSYM) {
-        // this wave's part is read column-wise when the k-tile's 128-block lies past the part's
-        if ((kb + kt * BK) / SH > (n0 + wn) / SH) ktile(std::true_type{});
+        // this wave's part is read column-wise when the k-tile's 128-block lies before the part's
+        if ((kb + kt * BK) / SH < (n0 + wn) / SH) ktile(std::true_type{});
         else ktile(std::false_type{});
       } else {
         ktile(std::false_type{});
@@ -730,7 +731,20 @@ __device__ __forceinline__ void gemm2_body(int w, const G2Args& g, void* ext = n
           h01 = cvt2_bf16(wv[0], wv[1]);
           h23 = cvt2_bf16(wv[2], wv[3]);
         }
-        if (q < nact) {
+        if (q < nact && g.wsym) {
+          // the transposed image only: W[q][p0 .. p0 + 3] in one 8-byte store (the padding columns
+          // past nact receive zeros), covering the blocks on and above the diagonal
+          if (p0 < nact) {
+            const long long o = (long long)q * ldw + p0;
+            *reinterpret_cast<uint2*>(Wh + o) = uint2{h01, h23};
+            if (LO) *reinterpret_cast<uint2*>(Wl + o) = uint2{l01, l23};
+          }
+          if (diag) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              if (p0 + j == q) g.Dc[(long long)P * nact + q] = (double)(a[i][jn][j] * invB);
+          }
+        } else if (q < nact) {
           const u16 hv[4] = {(u16)h01, (u16)(h01 >> 16), (u16)h23, (u16)(h23 >> 16)};
           const u16 lv[4] = {(u16)l01, (u16)(l01 >> 16), (u16)l23, (u16)(l23 >> 16)};
 #pragma unroll
@@ -742,7 +756,7 @@ __device__ __forceinline__ void gemm2_body(int w, const G2Args& g, void* ext = n
               if (diag && p == q) g.Dc[(long long)P * nact + p] = (double)(a[i][jn][j] * invB);
             }
           }
-          if (!diag && p0 < nact && !g.lower_only) {
+          if (!diag && p0 < nact) {
             const long long o = (long long)q * ldw + p0;
             if ((ldw & 3) == 0) {
               *reinterpret_cast<uint2*>(Wh + o) = uint2{h01, h23};
