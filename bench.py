@@ -28,15 +28,15 @@ KSRC = os.path.join(ROOT, "paper_2004_06142_amd", "csrc")
 # once the source changes the figure no longer applies and traffic is reported as null.
 TRAFFIC = {
     # profiles/c5_df1200_hbm_traffic.md: C5, bf16 split, 164-row chunks (read + written bytes per launch)
-    ("gemm1_kernel", 3): {"bytes": 1646564985 + 925567310,
+    ("gemm1_kernel", 3): {"bytes": 1616331062 + 926146614,
                           "plan": {"pchunk": 164, "x_variant": 3},
-                          "sha256": {"k_gemm_bf16.hip": "d44953359122915f1a197e463bd6d738b5814b491fd6ae9caba2da3333dde385"}},
-    ("gemm2_kernel", 3): {"bytes": 3541124563 + 1157092221,
+                          "sha256": {"k_gemm_bf16.hip": "f7cfd8b044dd4d8209dc58f678428b587955388859fa47962b130730de081c0c"}},
+    ("gemm2_kernel", 3): {"bytes": 4146286647 + 639393009,
                           "plan": {"pchunk": 164, "nsplit_b": 18},
-                          "sha256": {"k_gemm_bf16.hip": "d44953359122915f1a197e463bd6d738b5814b491fd6ae9caba2da3333dde385"}},
-    ("gemm3_kernel", 3): {"bytes": 2755097622 + 241426708,
+                          "sha256": {"k_gemm_bf16.hip": "f7cfd8b044dd4d8209dc58f678428b587955388859fa47962b130730de081c0c"}},
+    ("gemm3_kernel", 3): {"bytes": 2586050632 + 57679787,
                           "plan": {"pchunk": 164, "nsplit_y": 10, "y_variant": 3},
-                          "sha256": {"k_gemm_bf16.hip": "d44953359122915f1a197e463bd6d738b5814b491fd6ae9caba2da3333dde385"}},
+                          "sha256": {"k_gemm_bf16.hip": "f7cfd8b044dd4d8209dc58f678428b587955388859fa47962b130730de081c0c"}},
 }
 GOLDEN_C5 = os.path.join(ROOT, "tests", "golden", "c5_df1200_expected.json")
 

@@ -62,6 +62,28 @@ def test_lagrangian_with_singles_matches_oracle(ctx, func, prec, bdt):
         assert np.max(np.abs(out["dEdC"].cpu().numpy() - r["dEdC"])) < 1e-4
 
 
+@pytest.mark.parametrize("func,npairs,ns", [(P.PNOF7, 43, 5), (P.PNOF5, 43, 5), (P.PNOF7S, 44, 0), (P.PNOF7, 44, 0)])
+def test_large_active_space_split_mode(ctx, func, npairs, ns):
+    """Active spaces past 512 orbitals in the bf16 split mode: the symmetric W (the transposed image
+    of b's lower-triangle tiles) and Y's block-wise reads over many 128-blocks; nact = 521 and 528
+    leave ragged tails of 128 and 256, and singles give one-orbital subspaces (beta_pp = 0)."""
+    nbf, naux, ncwo = 560, 240, 11
+    inst, gamma, nact = _case(nbf, naux, npairs, ncwo, ns, "bf16", seed=43)
+    assert nact >= 512 and nact % 128 != 0
+    n = pnof.on_sigmoid(gamma, npairs, ncwo, ns)
+    prob = P.problem(nbf, naux, npairs, ncwo, func, P.BF16_SPLIT, P.INTS_DF_BF16, nsingle=ns)
+    out = ctx.lagrangian(prob, t(inst.C), t(n), t(inst.H), t(inst.B).to(torch.bfloat16), grads=True, jk=True)
+    r = stream.lagrangian(inst.C, n, inst.H, inst.B, npairs, ncwo, func, nsingle=ns)
+    o = {k: v.cpu().numpy() for k, v in out.items()}
+    jk_tol = max(2e-5, 2.0 ** -14 * max(np.max(np.abs(r["J"])), np.max(np.abs(r["K"]))))
+    errs = {"E": abs(o["E"][0] - r["E"]), "lam": np.max(np.abs(o["lam"] - r["lam"])),
+            "dEdC": np.max(np.abs(o["dEdC"] - r["dEdC"])), "J": np.max(np.abs(o["J"] - r["J"])),
+            "K": np.max(np.abs(o["K"] - r["K"])), "dEdn": np.max(np.abs(o["dEdn"][:nact] - r["dEdn"]))}
+    print(func, nact, {k: f"{v:.2e}" for k, v in errs.items()})
+    assert errs["E"] < 1e-6 and errs["lam"] < 2e-5 and errs["dEdC"] < 1e-4
+    assert errs["J"] < jk_tol and errs["K"] < jk_tol and errs["dEdn"] < 1e-4
+
+
 @pytest.mark.parametrize("kind", [P.ON_SIGMOID, P.ON_TRIG])
 def test_on_map_and_adjoint_with_singles(ctx, kind):
     npairs, ncwo, ns = 3, 2, 2
