@@ -56,6 +56,8 @@ constexpr int TROWS = 4;   // rows of the trailing matrix per block (one per wav
 constexpr int TPQ = 4;     // prologue elements per thread held in registers (loops cover the rest)
 constexpr int TPRE = 24;   // row elements per lane loaded before the prologue (loops cover the rest)
 
+__host__ __device__ inline int trd_group_base(int k) { return ((k + 1) / TROWS) & ~7; }
+
 __device__ double tblock_sum(double v, double* red) {
   v = wave_sum(v);
   const int w = threadIdx.x >> 6;
@@ -81,8 +83,11 @@ __global__ __launch_bounds__(TNT) void trd_step_k(int n, int k, double* __restri
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   // this wavefront's row: its first TPRE * 64 elements are loaded before the prologue, so their
   // latency overlaps the prologue's
-  const int irow = k + 1 + blockIdx.x * TROWS + wv;
-  const bool has_row = (irow < n) && (m >= 2);
+  // row group g = irow / TROWS goes to block g - gb, with gb a multiple of 8: workgroups are dealt to
+  // the 8 XCDs round-robin, so each row stays on one XCD (and its L2) from step to step
+  const int gb = trd_group_base(k);
+  const int irow = (gb + (int)blockIdx.x) * TROWS + wv;
+  const bool has_row = (irow > k) && (irow < n) && (m >= 2);
   double* __restrict__ row = A + (long long)(has_row ? irow : k) * n + k;
   double a[TPRE];
 #pragma unroll
@@ -456,7 +461,7 @@ hipError_t tridiag_f64(hipStream_t s, int n, double* A, double* Vh, double* p2, 
   const size_t shm = 3 * (size_t)n * sizeof(double);
   const int k0 = std::max(0, n - TAILM);   // columns k0 .. n-1: one workgroup, trailing block in LDS
   for (int k = 0; k < k0; ++k) {
-    const int blocks = std::max(1, cdiv(n - k - 1, TROWS));
+    const int blocks = std::max(1, (n - 1) / TROWS - trd_group_base(k) + 1);
     hipLaunchKernelGGL(trd_step_k, dim3(blocks), dim3(TNT), shm, s, n, k, A, Vh, p2 + ((k + 1) & 1) * (long long)n,
                        p2 + (k & 1) * (long long)n, d, e, tau);
   }
