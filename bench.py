@@ -30,13 +30,13 @@ TRAFFIC = {
     # profiles/c5_df1200_hbm_traffic.md: C5, bf16 split, 164-row chunks (read + written bytes per launch)
     ("gemm1_kernel", 3): {"bytes": 1616331062 + 926146614,
                           "plan": {"pchunk": 164, "x_variant": 3},
-                          "sha256": {"k_gemm_bf16.hip": "f7cfd8b044dd4d8209dc58f678428b587955388859fa47962b130730de081c0c"}},
+                          "sha256": {"k_gemm_bf16.hip": "739a0e927a9a5740758dc869d19722c729b4c658e67bcb213bd4cf4448b56ae8"}},
     ("gemm2_kernel", 3): {"bytes": 4146286647 + 639393009,
                           "plan": {"pchunk": 164, "nsplit_b": 18},
-                          "sha256": {"k_gemm_bf16.hip": "f7cfd8b044dd4d8209dc58f678428b587955388859fa47962b130730de081c0c"}},
+                          "sha256": {"k_gemm_bf16.hip": "739a0e927a9a5740758dc869d19722c729b4c658e67bcb213bd4cf4448b56ae8"}},
     ("gemm3_kernel", 3): {"bytes": 2586050632 + 57679787,
                           "plan": {"pchunk": 164, "nsplit_y": 10, "y_variant": 3},
-                          "sha256": {"k_gemm_bf16.hip": "f7cfd8b044dd4d8209dc58f678428b587955388859fa47962b130730de081c0c"}},
+                          "sha256": {"k_gemm_bf16.hip": "739a0e927a9a5740758dc869d19722c729b4c658e67bcb213bd4cf4448b56ae8"}},
 }
 GOLDEN_C5 = os.path.join(ROOT, "tests", "golden", "c5_df1200_expected.json")
 

@@ -471,8 +471,8 @@ pnof_status run_step(pnof_ctx ctx, const pnof_problem* prob, const double* C, co
                       nw = (long long)pl.pc * pl.nact32 * pl.ldw;
       wd = WsDims{pl.nact32, 2 * nct, 2 * nxt, 2 * nw};
       // the zero pads of the tiles are part of the contract of the contraction kernels; the valid
-      // blocks (Ct: nact x nbf, XT_P: nact x nbf, W_P: nact x nact) are overwritten in full before
-      // they are read, so only the pads are cleared
+      // blocks (Ct: nact x nbf, XT_P: nact x nbf, W_P: the part of nact x nact that Y reads) are
+      // overwritten before they are read, so only the pads are cleared
       const long long sx = (long long)pl.nact32 * pl.ldx, sw = (long long)pl.nact32 * pl.ldw;
       for (int lo = 0; lo < (pl.terms > 1 ? 2 : 1); ++lo) {
         DEV_CHECK(ctx, zero_pads_u16(s, lo ? b.ctl : b.cth, 1, nct, nact, pl.nact32, pl.ldk, nbf));

@@ -663,8 +663,10 @@ __device__ __forceinline__ void gemm1_body(int w, const G1Args& g, void* ext = n
 }
 
 // gemm2: b_P = Ct XT_P^T on lower-triangle tiles; Kpart[s] += sum_{P in s} b^2 (lower triangle, summed
-// over the successive P-chunks of one call), D[P][p] = b_pp, W_P = b o beta as a hi/lo pair, written
-// in full (off-diagonal tiles store their mirror image as well).
+// over the successive P-chunks of one call), D[P][p] = b_pp, W_P = b o beta as a hi/lo pair.  W is
+// written in full (off-diagonal tiles store their mirror image as well), or with wsym only as the
+// transposed image of each tile: the 128 x 128 blocks on and above the diagonal, which gemm3 with
+// wsym reads.
 // waves along q of a gemm2 block (2 x g2_wgn grid)
 constexpr int g2_wgn(bool vec) { return vec ? 4 : 2; }
 
@@ -807,7 +809,8 @@ __device__ __forceinline__ void gemm2_body(int w, const G2Args& g, void* ext = n
 }
 
 // gemm3: Ypart[s][mu][q] = sum_{P in s} sum_r XT_P[r][mu] W_P[q][r].  XT is read as a col operand,
-// W (stored in full) as a row operand; every block walks (P, r) in the same order, so blocks of one
+// W as a row operand (with wsym, each 128-wide block from the orientation gemm2 stored it in: rows
+// on and above the diagonal, columns below); every block walks (P, r) in the same order, so blocks of one
 // split that share an operand panel read it at about the same time.  Split mode: 3 fp16 products
 // (2 products, dropping X_lo W_hi at about 2^-12 relative, left lambda 2.2e-5 from the exact values on
 // a 77-function edge shape).
