@@ -327,9 +327,10 @@ def test_orbital_step_symmetrised(ctx):
 
 # sizes around the eigensolver's internal limits: n < 3 and n > 2048 take the library solver,
 # 1024 < n and 1537 < n cross the register-held prologue and row chunks of the reduction kernel,
-# 33 and 200 end the back-transformation's blocks of 32 reflectors and panels of 8 columns part
-# way, 2048 fills its LDS panel and every row slot of its update; 128 is reduced by the
-# single-workgroup tail alone, 129 and 130 hand it one and two columns' pending updates
+# 2048 fills its three LDS vectors; 128 is reduced by the single-workgroup tail alone, 129 and 130
+# hand it one and two columns' pending updates; Q is formed in blocks of 128 reflectors, which 129
+# fills exactly and 130, 200, 1025 and 1601 end part way; the divide-and-conquer solver splits down
+# to leaves of at most 16 rows, so 5 is one leaf and 33 merges uneven halves
 @pytest.mark.parametrize("nbf", [1, 2, 3, 5, 33, 64, 128, 129, 130, 200, 1025, 1601, 2048, 2100])
 def test_orbital_step_sizes(ctx, nbf):
     rng = np.random.default_rng(nbf)
