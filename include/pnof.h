@@ -84,8 +84,8 @@ typedef enum { PNOF5 = 5, PNOF7 = 7, PNOF7S = 8 } pnof_functional;
  *                    a power of two (about 22 significant bits) fixed per chunk of P rows from bounds
  *                    of |B| and |C|; b and Y take 3 fp16 products each (hi*hi, hi*lo, lo*hi).  A
  *                    float64 B is carried as an fp16 pair too (X then takes 3 fp16 products).  K sums
- *                    b^2 in float32 over the rows of one P-split of one chunk, then in float64; D, J,
- *                    Y are summed over P in float64 per chunk.  The energy is corrected to first
+ *                    b^2 and Y its products in float32 over the rows of one P-split of one chunk,
+ *                    then in float64; D and J = D^T D are float64.  The energy is corrected to first
  *                    order with 4 <Y_2e, C_A - C~> in float64.
  * Energies, lambda, J = D^T D, the eigensolver and all reductions are float64 in every mode. */
 typedef enum { PNOF_FP64 = 0, PNOF_FP32 = 1, PNOF_BF16 = 2, PNOF_BF16_SPLIT = 3 } pnof_precision;
