@@ -38,7 +38,7 @@ def _case(nbf, naux, npairs, ncwo, nsingle, dtype="f64", seed=41):
 
 
 @pytest.mark.parametrize("func", [P.PNOF7, P.PNOF5, P.PNOF7S])
-@pytest.mark.parametrize("prec,bdt", [(P.FP64, "f64"), (P.BF16_SPLIT, "bf16")])
+@pytest.mark.parametrize("prec,bdt", [(P.FP64, "f64"), (P.FP32, "f64"), (P.BF16_SPLIT, "bf16")])
 def test_lagrangian_with_singles_matches_oracle(ctx, func, prec, bdt):
     npairs, ncwo, ns = 4, 3, 3
     inst, gamma, nact = _case(72, 288, npairs, ncwo, ns, bdt)
@@ -62,16 +62,19 @@ def test_lagrangian_with_singles_matches_oracle(ctx, func, prec, bdt):
         assert np.max(np.abs(out["dEdC"].cpu().numpy() - r["dEdC"])) < 1e-4
 
 
-@pytest.mark.parametrize("func,npairs,ns", [(P.PNOF7, 43, 5), (P.PNOF5, 43, 5), (P.PNOF7S, 44, 0), (P.PNOF7, 44, 0)])
-def test_large_active_space_split_mode(ctx, func, npairs, ns):
+@pytest.mark.parametrize("func,npairs,ns,prec", [(P.PNOF7, 43, 5, P.BF16_SPLIT), (P.PNOF5, 43, 5, P.BF16_SPLIT),
+                                                  (P.PNOF7S, 44, 0, P.BF16_SPLIT), (P.PNOF7, 44, 0, P.BF16_SPLIT),
+                                                  (P.PNOF7, 43, 5, P.FP32)])
+def test_large_active_space_split_mode(ctx, func, npairs, ns, prec):
     """Active spaces past 512 orbitals in the bf16 split mode: the symmetric W (the transposed image
     of b's lower-triangle tiles) and Y's block-wise reads over many 128-blocks; nact = 521 and 528
-    leave ragged tails of 128 and 256, and singles give one-orbital subspaces (beta_pp = 0)."""
+    leave ragged tails of 128 and 256, and singles give one-orbital subspaces (beta_pp = 0).  The
+    float32 mode on the same shape, at the same tolerances."""
     nbf, naux, ncwo = 560, 240, 11
     inst, gamma, nact = _case(nbf, naux, npairs, ncwo, ns, "bf16", seed=43)
     assert nact >= 512 and nact % 128 != 0
     n = pnof.on_sigmoid(gamma, npairs, ncwo, ns)
-    prob = P.problem(nbf, naux, npairs, ncwo, func, P.BF16_SPLIT, P.INTS_DF_BF16, nsingle=ns)
+    prob = P.problem(nbf, naux, npairs, ncwo, func, prec, P.INTS_DF_BF16, nsingle=ns)
     out = ctx.lagrangian(prob, t(inst.C), t(n), t(inst.H), t(inst.B).to(torch.bfloat16), grads=True, jk=True)
     r = stream.lagrangian(inst.C, n, inst.H, inst.B, npairs, ncwo, func, nsingle=ns)
     o = {k: v.cpu().numpy() for k, v in out.items()}
